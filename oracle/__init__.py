@@ -1,0 +1,266 @@
+"""FP64 CPU oracle for ray tracing through uniaxial-dielectric cylindrical cloaks.
+
+TEST INFRASTRUCTURE. This package is the independent reference that the GPU
+library is checked against (Halimeh & Wegener, Sects. 2-4). Only the test
+suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py``
+import it; the product package never does. It shares no code with the GPU
+library: the C source ``cloak_oracle.c`` is compiled with gcc, loaded here
+with ctypes, and fed plain numpy arrays.
+
+Descriptions are plain dicts (the same keys the GPU binding accepts):
+  cloak:  r1, r2, z0, z1, axis (0 radial Eq. (14), 1 azimuthal Eq. (15)), inner_mirror
+  opts:   scheme (0 RK4, 1 DP45), h, rtol, atol, hmax, r_out, max_steps, max_bounces
+  camera: eye, look, up, fov_deg, w, h, spp, seed
+  room:   lo, hi, tile, rgb (6 faces x 2 parities x 3)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cloak_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libcloak_oracle.so")
+_lib = None
+
+c_double_p = ctypes.POINTER(ctypes.c_double)
+c_int32_p = ctypes.POINTER(ctypes.c_int32)
+c_int64_p = ctypes.POINTER(ctypes.c_int64)
+c_uint8_p = ctypes.POINTER(ctypes.c_uint8)
+
+
+def build() -> str:
+    """Compile the oracle with gcc (FP64, -O2, OpenMP, no SIMD intrinsics)."""
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-shared", "-fPIC", "-Wall",
+           "-o", _LIB_PATH, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return _LIB_PATH
+
+
+class _Cloak(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("z0", ctypes.c_double), ("z1", ctypes.c_double),
+                ("axis", ctypes.c_int32), ("inner_mirror", ctypes.c_int32)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int32), ("max_bounces", ctypes.c_int32),
+                ("h", ctypes.c_double), ("rtol", ctypes.c_double),
+                ("atol", ctypes.c_double), ("hmax", ctypes.c_double),
+                ("r_out", ctypes.c_double), ("max_steps", ctypes.c_int64)]
+
+
+class _Camera(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_double * 3), ("look", ctypes.c_double * 3),
+                ("up", ctypes.c_double * 3), ("fov_deg", ctypes.c_double),
+                ("w", ctypes.c_int32), ("h", ctypes.c_int32), ("spp", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class _Room(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("tile", ctypes.c_double), ("rgb", ctypes.c_float * 36)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        L.orc_trace.argtypes = [ctypes.POINTER(_Cloak), ctypes.POINTER(_Opts), ctypes.c_int32,
+                                ctypes.c_int64, c_double_p, c_double_p, c_double_p, c_int32_p,
+                                c_double_p, c_int64_p]
+        L.orc_render_samples.argtypes = [ctypes.POINTER(_Cloak), ctypes.POINTER(_Opts),
+                                         ctypes.POINTER(_Room), ctypes.POINTER(_Camera),
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                         c_int64_p, c_uint8_p, c_double_p, c_int32_p]
+        L.orc_eps_cyl.argtypes = [ctypes.POINTER(_Cloak), ctypes.c_double, c_double_p]
+        L.orc_metric.argtypes = [ctypes.POINTER(_Cloak), c_double_p, c_double_p]
+        L.orc_metric_det_form.argtypes = [ctypes.POINTER(_Cloak), c_double_p, c_double_p]
+        L.orc_rhs.argtypes = [ctypes.POINTER(_Cloak), ctypes.c_int32, c_double_p, c_double_p]
+        L.orc_rhs_eq8_isotropic.argtypes = [ctypes.POINTER(_Cloak), c_double_p, c_double_p]
+        L.orc_refract_in.argtypes = [ctypes.c_double, ctypes.c_double, c_double_p, c_double_p,
+                                     c_double_p, ctypes.c_int32, c_double_p, c_double_p]
+        L.orc_refract_in.restype = ctypes.c_int32
+        L.orc_refract_out.argtypes = [ctypes.c_double, ctypes.c_double, c_double_p, c_double_p,
+                                      c_double_p, ctypes.c_int32, c_double_p]
+        L.orc_refract_out.restype = ctypes.c_int32
+        L.orc_camera_ray.argtypes = [ctypes.POINTER(_Camera), ctypes.c_int32, ctypes.c_int64,
+                                     c_double_p, c_double_p]
+        L.orc_room_code.argtypes = [ctypes.POINTER(_Room), c_double_p, c_double_p, c_double_p]
+        L.orc_room_code.restype = ctypes.c_int32
+        L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_splitmix64.restype = ctypes.c_uint64
+        L.orc_test_oscillator.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, c_double_p, c_int64_p]
+        L.orc_test_oscillator.restype = ctypes.c_double
+        L.orc_num_threads.restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _ptr(a, t=c_double_p):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+def _cloak(d):
+    if d is None:
+        return None
+    return _Cloak(float(d["r1"]), float(d["r2"]), float(d.get("z0", -np.inf)),
+                  float(d.get("z1", np.inf)), int(d["axis"]), int(d.get("inner_mirror", 1)))
+
+
+def _opts(d):
+    return _Opts(int(d.get("scheme", 0)), int(d.get("max_bounces", 4)), float(d.get("h", 1e-3)),
+                 float(d.get("rtol", 1e-8)), float(d.get("atol", 1e-8)),
+                 float(d.get("hmax", 0.5)), float(d.get("r_out", 3.0)),
+                 int(d.get("max_steps", 1_000_000)))
+
+
+def _camera(d):
+    c = _Camera()
+    for k in ("eye", "look", "up"):
+        getattr(c, k)[:] = [float(v) for v in d[k]]
+    c.fov_deg = float(d["fov_deg"])
+    c.w, c.h, c.spp = int(d["w"]), int(d["h"]), int(d.get("spp", 1))
+    c.seed = int(d.get("seed", 0)) & ((1 << 64) - 1)
+    return c
+
+
+def _room(d):
+    r = _Room()
+    r.lo[:] = [float(v) for v in d["lo"]]
+    r.hi[:] = [float(v) for v in d["hi"]]
+    r.tile = float(d["tile"])
+    r.rgb[:] = [float(v) for v in np.asarray(d["rgb"], dtype=np.float32).reshape(-1)]
+    return r
+
+
+def trace(cloak, opts, branch, rays6):
+    """Trace vacuum rays (SoA array 6 x n: origin, direction) through the cloak.
+
+    Returns a dict with out (6 x n: point on r = r_out, unit direction), opl,
+    status, hres (|H-1| at the last interface) and nsteps (step attempts).
+    """
+    rays6 = np.ascontiguousarray(rays6, dtype=np.float64)
+    n = rays6.shape[1]
+    out = np.empty((6, n))
+    opl = np.empty(n)
+    st = np.empty(n, dtype=np.int32)
+    hr = np.empty(n)
+    ns = np.empty(n, dtype=np.int64)
+    c, o = _cloak(cloak), _opts(opts)
+    lib().orc_trace(ctypes.byref(c), ctypes.byref(o), int(branch), n, _ptr(rays6), _ptr(out),
+                    _ptr(opl), _ptr(st, c_int32_p), _ptr(hr), _ptr(ns, c_int64_p))
+    return {"out": out, "opl": opl, "status": st, "hres": hr, "nsteps": ns}
+
+
+def render_samples(cloak, opts, room, camera, cam_index, branch, ids):
+    """Codes (face*2+parity, 12 = black), records (7 x n) and status of samples."""
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    n = ids.shape[0]
+    code = np.empty(n, dtype=np.uint8)
+    rec = np.empty((7, n))
+    st = np.empty(n, dtype=np.int32)
+    c = _cloak(cloak)
+    o, rm, cm = _opts(opts), _room(room), _camera(camera)
+    lib().orc_render_samples(ctypes.byref(c) if c is not None else None, ctypes.byref(o),
+                             ctypes.byref(rm), ctypes.byref(cm), int(cam_index), int(branch), n,
+                             _ptr(ids, c_int64_p), _ptr(code, c_uint8_p), _ptr(rec),
+                             _ptr(st, c_int32_p))
+    return {"code": code, "rec": rec, "status": st}
+
+
+def render_pixels(cloak, opts, room, camera, cam_index, branch, pixels):
+    """Mean RGB (float64, n x 3) of the given pixels over their samples."""
+    pixels = np.asarray(pixels, dtype=np.int64)
+    spp = int(camera.get("spp", 1))
+    ids = (pixels[:, None] * spp + np.arange(spp)[None, :]).reshape(-1)
+    r = render_samples(cloak, opts, room, camera, cam_index, branch, ids)
+    table = np.zeros((13, 3))
+    table[:12] = np.asarray(room["rgb"], dtype=np.float32).reshape(12, 3)
+    col = table[r["code"]].reshape(len(pixels), spp, 3).mean(axis=1)
+    return col, r
+
+
+def eps_cyl(cloak, r):
+    out = np.empty(3)
+    c = _cloak(cloak)
+    lib().orc_eps_cyl(ctypes.byref(c), float(r), _ptr(out))
+    return out
+
+
+def metric(cloak, x, det_form=False):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    M = np.empty(9)
+    c = _cloak(cloak)
+    f = lib().orc_metric_det_form if det_form else lib().orc_metric
+    f(ctypes.byref(c), _ptr(x), _ptr(M))
+    return M.reshape(3, 3)
+
+
+def rhs(cloak, branch, y, eq8_isotropic=False):
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    dy = np.empty(6)
+    c = _cloak(cloak)
+    if eq8_isotropic:
+        lib().orc_rhs_eq8_isotropic(ctypes.byref(c), _ptr(y), _ptr(dy))
+    else:
+        lib().orc_rhs(ctypes.byref(c), int(branch), _ptr(y), _ptr(dy))
+    return dy
+
+
+def refract_in(eps_o, eps_e, chat, nhat, kin, branch):
+    """Entry refraction (Sect. 3). Returns (status, k, v); status 1 = evanescent."""
+    chat, nhat, kin = (np.ascontiguousarray(a, dtype=np.float64) for a in (chat, nhat, kin))
+    k = np.empty(3)
+    v = np.empty(3)
+    st = lib().orc_refract_in(float(eps_o), float(eps_e), _ptr(chat), _ptr(nhat), _ptr(kin),
+                              int(branch), _ptr(k), _ptr(v))
+    return st, k, v
+
+
+def refract_out(eps_o, eps_e, chat, nhat, v_in, branch):
+    """Exit refraction into vacuum. Returns (status, d_out); status 1 = TIR."""
+    chat, nhat, v_in = (np.ascontiguousarray(a, dtype=np.float64) for a in (chat, nhat, v_in))
+    d = np.empty(3)
+    st = lib().orc_refract_out(float(eps_o), float(eps_e), _ptr(chat), _ptr(nhat), _ptr(v_in),
+                               int(branch), _ptr(d))
+    return st, d
+
+
+def camera_ray(camera, cam_index, sample_id):
+    o = np.empty(3)
+    d = np.empty(3)
+    cm = _camera(camera)
+    lib().orc_camera_ray(ctypes.byref(cm), int(cam_index), int(sample_id), _ptr(o), _ptr(d))
+    return o, d
+
+
+def room_code(room, o, d):
+    o = np.ascontiguousarray(o, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    s = np.empty(1)
+    rm = _room(room)
+    code = lib().orc_room_code(ctypes.byref(rm), _ptr(o), _ptr(d), _ptr(s))
+    return int(code), float(s[0])
+
+
+def splitmix64(seed, n):
+    return int(lib().orc_splitmix64(int(seed) & ((1 << 64) - 1), int(n) & ((1 << 64) - 1)))
+
+
+def test_oscillator(scheme, h, rtol, T):
+    y = np.empty(6)
+    ns = np.empty(1, dtype=np.int64)
+    e = lib().orc_test_oscillator(int(scheme), float(h), float(rtol), float(T), _ptr(y),
+                                  _ptr(ns, c_int64_p))
+    return float(e), y, int(ns[0])
+
+
+def num_threads():
+    return int(lib().orc_num_threads())

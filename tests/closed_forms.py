@@ -1,0 +1,214 @@
+"""Closed forms and quadratures that pin the oracle (no code shared with it).
+
+Everything here is derived by hand from the paper's equations, independently
+of the oracle's Cartesian formulation:
+
+* For the uniaxial cloaks of Eq. (14) and Eq. (15), the auxiliary matrix of
+  Eq. (7) is diagonal in the cylindrical frame: the components across the
+  optic axis are eps_e and the one along it is eps_o (extraordinary ray), or
+  n_o^2 times the identity (ordinary ray, Eq. (2) is Eq. (8) with M = n_o^2 I).
+* Eq. (8) is the Euler-Lagrange equation of L = v^T M v / 2 (Fermat's
+  principle, Sect. 2); in cylindrical coordinates this gives the reduced
+  right-hand side below, and the conserved p_theta = r m_theta v_theta,
+  p_z = m_z v_z and H = v^T M v = 1.
+* Extraordinary in-plane rays of both cloaks, and azimuthal-cloak
+  extraordinary rays in 3-D, see a flat metric in the coordinates
+  rho = sqrt(kappa) (r - a), zeta = sqrt(kappa) z: straight lines at unit
+  speed (the design of Sect. 4 keeps the ideal cloak's index distribution
+  for in-plane polarized light).
+* Radial-cloak ordinary rays: constant index n_o = sqrt(kappa) (Sect. 4),
+  straight lines, Snell refraction, specular inner mirror.
+* Radial-cloak extraordinary and azimuthal-cloak ordinary rays in 3-D:
+  integrable, exit angle and height by one-dimensional quadrature.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy import integrate, optimize
+
+RADIAL, AZIMUTHAL = 0, 1
+ORDINARY, EXTRAORDINARY = 0, 1
+
+
+def kappa(a, b):
+    return (b / (b - a)) ** 2
+
+
+def cyl_metric(axis, branch, r, a=1.0, b=2.0):
+    """(m_r, m_theta, m_z) and their r-derivatives."""
+    k = kappa(a, b)
+    s = ((r - a) / r) ** 2
+    sp = 2.0 * a * (r - a) / r ** 3
+    if branch == EXTRAORDINARY:
+        if axis == RADIAL:   # c = r_hat: eps_e = k s along r, eps_o = k across
+            return (k, k * s, k * s), (0.0, k * sp, k * sp)
+        return (k, k * s, k), (0.0, k * sp, 0.0)   # c = theta_hat
+    if axis == RADIAL:
+        return (k, k, k), (0.0, 0.0, 0.0)
+    return (k * s, k * s, k * s), (k * sp, k * sp, k * sp)
+
+
+def reduced_rhs(axis, branch, y, a=1.0, b=2.0):
+    """Euler-Lagrange equations of L = (m_r rdot^2 + m_theta r^2 thetadot^2 +
+    m_z zdot^2)/2, written back in Cartesian components."""
+    x, yy, z, vx, vy, vz = y
+    r = math.hypot(x, yy)
+    rh = (x / r, yy / r)
+    th = (-yy / r, x / r)
+    vr = vx * rh[0] + vy * rh[1]
+    vt = vx * th[0] + vy * th[1]
+    m, dm = cyl_metric(axis, branch, r, a, b)
+    ar = (-dm[0] * vr ** 2 + dm[1] * vt ** 2 + dm[2] * vz ** 2
+          - 2.0 * (m[0] - m[1]) * vt ** 2 / r) / (2.0 * m[0])
+    at = -(dm[1] / m[1]) * vr * vt
+    az = -(dm[2] / m[2]) * vr * vz
+    return np.array([vx, vy, vz, ar * rh[0] + at * th[0], ar * rh[1] + at * th[1], az])
+
+
+def side_entry(o, d, b=2.0):
+    """Vacuum leg to the outer cylinder: entry distance, point, local frame and
+    the incident direction's components (k_n, k_theta, k_z) there."""
+    A = d[0] ** 2 + d[1] ** 2
+    B = o[0] * d[0] + o[1] * d[1]
+    C = o[0] ** 2 + o[1] ** 2 - b * b
+    s = (-B - math.sqrt(B * B - A * C)) / A
+    p = o + s * d
+    r = math.hypot(p[0], p[1])
+    rh = np.array([p[0] / r, p[1] / r, 0.0])
+    th = np.array([-p[1] / r, p[0] / r, 0.0])
+    return s, p, rh, th, (d @ rh, d @ th, d[2])
+
+
+def frame_at(p):
+    r = math.hypot(p[0], p[1])
+    return np.array([p[0] / r, p[1] / r, 0.0]), np.array([-p[1] / r, p[0] / r, 0.0])
+
+
+def exit_direction(p, kt, kz):
+    """Vacuum direction leaving r = b at p with conserved tangential k."""
+    rh, th = frame_at(p)
+    kn = math.sqrt(max(0.0, 1.0 - kt * kt - kz * kz))
+    return kn * rh + kt * th + kz * np.array([0.0, 0.0, 1.0])
+
+
+def cf2_azimuthal_e(o, d, a=1.0, b=2.0):
+    """Azimuthal cloak, extraordinary ray, infinite cylinder: straight line in
+    (rho cos theta, rho sin theta, sqrt(kappa) z) at unit speed; rho(b) = b."""
+    k = kappa(a, b)
+    sk = math.sqrt(k)
+    s_in, p, rh, th, (kn, kt, kz) = side_entry(o, d, b)
+    q = math.sqrt(k - k * kt * kt - kz * kz)  # normal wave-vector component inside
+    X0 = np.array([p[0], p[1], sk * p[2]])
+    V = -(q / sk) * rh + kt * th + np.array([0.0, 0.0, kz / sk])
+    Vxy = V[:2]
+    s = -2.0 * (X0[:2] @ Vxy) / (Vxy @ Vxy)
+    X1 = X0 + s * V
+    pe = np.array([X1[0], X1[1], X1[2] / sk])
+    return pe, exit_direction(pe, kt, kz), s_in + s
+
+
+def cf3_radial_o(o, d, a=1.0, b=2.0):
+    """Radial cloak, ordinary ray: Snell at r = b with n = sqrt(kappa),
+    straight line, specular reflection at the metal cylinder r = a."""
+    k = kappa(a, b)
+    s_in, p, rh, th, (kn, kt, kz) = side_entry(o, d, b)
+    kvec = kt * th + np.array([0.0, 0.0, kz]) - math.sqrt(k - kt * kt - kz * kz) * rh
+    v = kvec / k
+    x = p.copy()
+    t = 0.0
+    A = v[0] ** 2 + v[1] ** 2
+    B = x[0] * v[0] + x[1] * v[1]
+    C = x[0] ** 2 + x[1] ** 2 - a * a
+    disc = B * B - A * C
+    if disc >= 0.0:
+        tm = (-B - math.sqrt(disc)) / A
+        if tm > 0.0:
+            x = x + tm * v
+            t += tm
+            n = np.array([x[0], x[1], 0.0]) / math.hypot(x[0], x[1])
+            v = v - 2.0 * (v @ n) * n
+    B = x[0] * v[0] + x[1] * v[1]
+    C = x[0] ** 2 + x[1] ** 2 - b * b
+    tb = (-B + math.sqrt(B * B - A * C)) / A
+    x = x + tb * v
+    t += tb
+    rh1, th1 = frame_at(x)
+    kout = k * v
+    return x, exit_direction(x, kout @ th1, kout[2]), s_in + t
+
+
+def cf4_quadrature(axis, branch, o, d, a=1.0, b=2.0):
+    """Integrable 3-D cases (radial extraordinary, azimuthal ordinary): the
+    exit angle, height and optical path by quadrature between the turning
+    point and r = b, with r = r_min + (b - r_min) u^2."""
+    k = kappa(a, b)
+    s_in, p, rh, th, (kn, kt, kz) = side_entry(o, d, b)
+    # entry velocity at r = b where k s(b) = 1: p_theta = b k_theta, p_z = k_z
+    pth, pz = b * kt, kz
+
+    def F(r):
+        m, _ = cyl_metric(axis, branch, r, a, b)
+        return 1.0 - pth * pth / (r * r * m[1]) - pz * pz / m[2]
+
+    rmin = optimize.brentq(F, a * (1.0 + 1e-15) + 1e-15, b, xtol=1e-16, rtol=1e-15, maxiter=500)
+
+    def parts(u):
+        r = rmin + (b - rmin) * u * u
+        m, _ = cyl_metric(axis, branch, r, a, b)
+        rdot = math.sqrt(max(F(r), 0.0) / m[0])
+        jac = 2.0 * (b - rmin) * u
+        return r, m, rdot, jac
+
+    def f_theta(u):
+        r, m, rdot, jac = parts(u)
+        return pth / (r * r * m[1]) * jac / rdot if u > 0 else _limit(f_theta)
+
+    def f_z(u):
+        r, m, rdot, jac = parts(u)
+        return (pz / m[2]) * jac / rdot if u > 0 else _limit(f_z)
+
+    def f_t(u):
+        r, m, rdot, jac = parts(u)
+        return jac / rdot if u > 0 else _limit(f_t)
+
+    def _limit(f):
+        return f(1e-9)
+
+    opt = dict(epsabs=1e-14, epsrel=1e-13, limit=200)
+    dth = 2.0 * integrate.quad(f_theta, 0.0, 1.0, **opt)[0]
+    dz = 2.0 * integrate.quad(f_z, 0.0, 1.0, **opt)[0]
+    T = 2.0 * integrate.quad(f_t, 0.0, 1.0, **opt)[0]
+    th0 = math.atan2(p[1], p[0])
+    pe = np.array([b * math.cos(th0 + dth), b * math.sin(th0 + dth), p[2] + dz])
+    return pe, exit_direction(pe, kt, kz), s_in + T
+
+
+def aimed_rays(n, seed, r_start=3.0, b=2.0, min_tangential=0.25, elev=True, min_ktheta=0.0):
+    """Vacuum rays from r = r_start that hit the side of the infinite cylinder
+    with tangential wave-vector (k_theta, k_z) of norm >= min_tangential
+    (away from the singular set p_theta = p_z = 0) and |k_theta| >= min_ktheta
+    (azimuthal-cloak extraordinary rays: only p_theta keeps them off r = a).
+    SoA (6, n)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        phi = rng.uniform(0, 2 * math.pi)
+        o = np.array([r_start * math.cos(phi), r_start * math.sin(phi), rng.uniform(-1, 1)])
+        target = np.array([rng.uniform(-b, b), rng.uniform(-b, b), rng.uniform(-1, 1)])
+        if not elev:
+            o[2] = 0.0
+            target[2] = 0.0
+        dd = target - o
+        dd /= np.linalg.norm(dd)
+        A = dd[0] ** 2 + dd[1] ** 2
+        B = o[0] * dd[0] + o[1] * dd[1]
+        C = o[0] ** 2 + o[1] ** 2 - b * b
+        if B * B - A * C <= 0:
+            continue
+        s, p, rh, th, (kn, kt, kz) = side_entry(o, dd, b)
+        if math.hypot(kt, kz) < min_tangential or abs(kn) < 0.05 or abs(kt) < min_ktheta:
+            continue
+        out.append(np.concatenate([o, dd]))
+    return np.array(out).T.copy()

@@ -1,0 +1,489 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these compare the oracle with itself: each expected value comes from
+a number printed in the paper (tests/golden), a closed form derived by hand
+(tests/closed_forms.py), a textbook law, a quadrature, or an invariant.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1209_6038_amd import workloads as W
+from tests import closed_forms as CF
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+E, O = CF.EXTRAORDINARY, CF.ORDINARY
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------
+# material, Eq. (1), (7), (14), (15)
+# --------------------------------------------------------------------------
+def test_paper_radial_ordinary_index_is_two():
+    """Sect. 4: with a = 5 cm, b = 10 cm the radial cloak's n_o is 2."""
+    g = _gold("paper_values.json")
+    a, b = g["inner_radius_a_cm"]["value"], g["outer_radius_b_cm"]["value"]
+    c = {"r1": a, "r2": b, "axis": 0}
+    for r in np.linspace(a * 1.01, b, 7):
+        eps = oracle.eps_cyl(c, r)
+        # radial cloak: eps_theta = eps_z is the ordinary (degenerate) value
+        assert math.sqrt(eps[1]) == pytest.approx(g["radial_cloak_ordinary_index"]["value"], abs=1e-15)
+        assert eps[1] == eps[2]
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_eq7_two_forms_agree(axis):
+    """Eq. (7): |eps| eps^-1 / n_o^2 = n_o^2 n_e^2 eps^-1 (needs |eps| = n_o^4 n_e^2,
+    which holds only with eps_o the doubly degenerate principal value)."""
+    c = W.cloak(axis)
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        r = rng.uniform(1.001, 2.0)
+        th = rng.uniform(0, 2 * math.pi)
+        x = np.array([r * math.cos(th), r * math.sin(th), rng.uniform(-3, 3)])
+        M1 = oracle.metric(c, x)
+        M2 = oracle.metric(c, x, det_form=True)
+        np.testing.assert_allclose(M1, M2, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_metric_eigenstructure(axis):
+    """M has eigenvalue eps_o along the optic axis (r_hat for Eq. (14), theta_hat
+    for Eq. (15)) and eps_e across it."""
+    c = W.cloak(axis)
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        r = rng.uniform(1.001, 2.0)
+        th = rng.uniform(0, 2 * math.pi)
+        x = np.array([r * math.cos(th), r * math.sin(th), 0.3])
+        M = oracle.metric(c, x)
+        m, _ = CF.cyl_metric(axis, E, r)
+        rh = np.array([math.cos(th), math.sin(th), 0.0])
+        tt = np.array([-math.sin(th), math.cos(th), 0.0])
+        zz = np.array([0.0, 0.0, 1.0])
+        np.testing.assert_allclose(M, M.T, atol=1e-14)
+        for vec, lam in ((rh, m[0]), (tt, m[1]), (zz, m[2])):
+            np.testing.assert_allclose(M @ vec, lam * vec, rtol=1e-12, atol=1e-13)
+
+
+def test_material_at_outer_radius_is_index_matched_component():
+    """Derived from Eq. (14)/(15): ((b-a)/b)^2 (b/(b-a))^2 = 1 at r = b."""
+    for axis in (0, 1):
+        eps = oracle.eps_cyl(W.cloak(axis), 2.0)
+        assert eps[0] == pytest.approx(1.0, abs=1e-15)
+
+
+# --------------------------------------------------------------------------
+# ray equations, Eq. (2) and Eq. (8)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("branch", [0, 1])
+def test_rhs_matches_cylindrical_euler_lagrange(axis, branch):
+    """The oracle's Cartesian Eq. (8) (dual-number grad M) and Eq. (2) agree with
+    the Euler-Lagrange equations of L = v^T M v / 2 in cylindrical coordinates."""
+    c = W.cloak(axis)
+    rng = np.random.default_rng(3 + 10 * axis + branch)
+    for _ in range(50):
+        r = rng.uniform(1.0005, 2.0)
+        th = rng.uniform(0, 2 * math.pi)
+        y = np.array([r * math.cos(th), r * math.sin(th), rng.uniform(-2, 2),
+                      *rng.normal(size=3)])
+        got = oracle.rhs(c, branch, y)
+        want = CF.reduced_rhs(axis, branch, y)
+        scale = np.abs(want).max() + 1.0
+        np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-12 * scale)
+
+
+def test_eq8_with_isotropic_metric_is_eq2():
+    """Sect. 2: Eq. (8) has the same form as Eq. (2); with M = n_o^2 I it is Eq. (2)."""
+    c = W.cloak(1)  # azimuthal cloak: n_o varies with r
+    rng = np.random.default_rng(4)
+    for _ in range(30):
+        r = rng.uniform(1.001, 2.0)
+        th = rng.uniform(0, 2 * math.pi)
+        y = np.array([r * math.cos(th), r * math.sin(th), 0.7, *rng.normal(size=3)])
+        np.testing.assert_allclose(oracle.rhs(c, O, y, eq8_isotropic=True), oracle.rhs(c, O, y),
+                                   rtol=1e-12, atol=1e-12)
+
+
+def test_radial_ordinary_rhs_is_zero():
+    """Sect. 4: constant n_o in the radial cloak, so Eq. (2) has a zero right side."""
+    c = W.cloak(0)
+    rng = np.random.default_rng(5)
+    for _ in range(10):
+        y = np.array([1.3, -0.4, 0.2, *rng.normal(size=3)])
+        np.testing.assert_allclose(oracle.rhs(c, O, y)[3:], 0.0, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Sect. 3: refraction, Eqs. (6), (9)-(11)
+# --------------------------------------------------------------------------
+def _random_interface(rng):
+    n = rng.normal(size=3)
+    n /= np.linalg.norm(n)
+    kin = rng.normal(size=3)
+    kin -= 1.5 * abs(kin @ n) * n + (kin @ n) * n  # make it point into the surface
+    kin /= np.linalg.norm(kin)
+    assert kin @ n < 0
+    return n, kin
+
+
+def test_isotropic_refraction_is_snell():
+    rng = np.random.default_rng(6)
+    for _ in range(50):
+        n, kin = _random_interface(rng)
+        eps = rng.uniform(1.2, 5.0)
+        c = rng.normal(size=3)
+        c /= np.linalg.norm(c)
+        for branch in (0, 1):
+            st, k, v = oracle.refract_in(eps, eps, c, n, kin, branch)
+            assert st == 0
+            sin_i = np.linalg.norm(np.cross(kin, n))
+            sin_t = np.linalg.norm(np.cross(k / np.linalg.norm(k), n))
+            assert sin_i == pytest.approx(math.sqrt(eps) * sin_t, abs=1e-12)
+            assert np.linalg.norm(k) == pytest.approx(math.sqrt(eps), rel=1e-13)
+            # plane of incidence and direction into the medium
+            assert abs(np.cross(kin, n) @ k) < 1e-12
+            assert k @ n < 0
+            np.testing.assert_allclose(v, k / eps, atol=1e-13)
+
+
+def test_extraordinary_refraction_satisfies_fresnel_and_phase_matching():
+    """For any optic axis: tangential k continuous (Eq. (11)), the refracted k on
+    the extraordinary index surface k_par^2/n_o^2 + k_perp^2/n_e^2 = 1 (the
+    textbook index ellipsoid behind Eq. (9)), k.v = 1 and v^T M v = 1 (Eq. (6))."""
+    rng = np.random.default_rng(7)
+    for _ in range(100):
+        n, kin = _random_interface(rng)
+        c = rng.normal(size=3)
+        c /= np.linalg.norm(c)
+        eo, ee = rng.uniform(0.3, 5.0, size=2)
+        st, k, v = oracle.refract_in(eo, ee, c, n, kin, 1)
+        if st:
+            continue
+        kt_in = kin - (kin @ n) * n
+        np.testing.assert_allclose(k - (k @ n) * n, kt_in, atol=1e-12)
+        kpar = k @ c
+        kperp2 = k @ k - kpar ** 2
+        assert kpar ** 2 / eo + kperp2 / ee == pytest.approx(1.0, abs=1e-11)
+        assert k @ n < 0
+        assert k @ v == pytest.approx(1.0, abs=1e-11)
+        M = ee * (np.eye(3) - np.outer(c, c)) + eo * np.outer(c, c)
+        assert v @ M @ v == pytest.approx(1.0, abs=1e-11)
+
+
+def test_radial_axis_polarization_angle():
+    """Sect. 3 after Eq. (10): optic axis along the normal gives
+    phi_e = pi/2 - varphi_e, i.e. n(varphi_e)^2 = n_o^2 n_e^2 /
+    (n_o^2 sin^2 varphi_e + n_e^2 cos^2 varphi_e) for the refracted wave."""
+    g = _gold("paper_values.json")["polarization_angle_radial_axis"]
+    rng = np.random.default_rng(8)
+    for _ in range(40):
+        n, kin = _random_interface(rng)
+        eo, ee = rng.uniform(0.5, 4.0, size=2)
+        st, k, v = oracle.refract_in(eo, ee, n, n, kin, 1)
+        if st:
+            # no real root: the tangential k exceeds the index at grazing
+            # refraction, where phi_e = 0 and Eq. (9) gives n = n_e
+            assert np.linalg.norm(np.cross(kin, n)) > math.sqrt(ee) - 1e-12
+            continue
+        kn = np.linalg.norm(k)
+        vphi = math.atan2(np.linalg.norm(k - (k @ n) * n), -(k @ n))
+        phi_e = g["phi_e_plus_varphi_e"] - vphi
+        want = math.sqrt(eo * ee / (eo * math.cos(phi_e) ** 2 + ee * math.sin(phi_e) ** 2))
+        assert kn == pytest.approx(want, rel=1e-12)
+
+
+def test_closed_form_entry_velocities_at_outer_radius():
+    """Derived at r = b (kappa s(b) = 1): azimuthal-cloak ordinary rays enter
+    undeviated; radial-cloak extraordinary rays enter with
+    v = k_t + (cos(phi_i) / sqrt(kappa)) n_in."""
+    rng = np.random.default_rng(9)
+    k = CF.kappa(1.0, 2.0)
+    for _ in range(30):
+        th = rng.uniform(0, 2 * math.pi)
+        n = np.array([math.cos(th), math.sin(th), 0.0])
+        _, kin = _random_interface(rng)
+        kin = kin - 2 * max(0.0, kin @ n) * n
+        if kin @ n > -0.05:
+            continue
+        # azimuthal cloak at r = b: eps_o = kappa s = 1, eps_e = kappa, c = theta_hat
+        c_az = np.array([-math.sin(th), math.cos(th), 0.0])
+        st, kk, v = oracle.refract_in(1.0, k, c_az, n, kin, 0)
+        np.testing.assert_allclose(v, kin, atol=1e-13)
+        # radial cloak at r = b: eps_o = kappa, eps_e = kappa s = 1, c = r_hat
+        st, kk, v = oracle.refract_in(k, 1.0, n, n, kin, 1)
+        cos_i = -(kin @ n)
+        np.testing.assert_allclose(v, kin + cos_i * n - cos_i / math.sqrt(k) * n, atol=1e-12)
+
+
+def test_refraction_time_reversal():
+    """Reversing the refracted ray velocity and refracting it out returns the
+    reversed incident direction (Eq. (11) read both ways)."""
+    rng = np.random.default_rng(10)
+    for _ in range(60):
+        n, kin = _random_interface(rng)
+        c = rng.normal(size=3)
+        c /= np.linalg.norm(c)
+        eo, ee = rng.uniform(1.0, 5.0, size=2)
+        for branch in (0, 1):
+            st, k, v = oracle.refract_in(eo, ee, c, n, kin, branch)
+            st2, d = oracle.refract_out(eo, ee, c, n, -v, branch)
+            assert st == 0 and st2 == 0
+            np.testing.assert_allclose(d, -kin, atol=1e-11)
+
+
+def test_evanescent_conditions():
+    """No transmitted ordinary wave when sin(phi_i) > n_o (possible for n_o < 1
+    near the inner radius of the azimuthal cloak); total internal reflection
+    when the tangential k inside exceeds 1."""
+    n = np.array([0.0, 0.0, 1.0])
+    kin = np.array([math.sin(1.2), 0.0, -math.cos(1.2)])
+    st, _, _ = oracle.refract_in(0.5, 4.0, np.array([1.0, 0, 0]), n, kin, 0)
+    assert st == 1  # sin(1.2) = 0.93 > sqrt(0.5)
+    st, _, _ = oracle.refract_in(0.9, 4.0, np.array([1.0, 0, 0]), n, kin, 0)
+    assert st == 0
+    st, _ = oracle.refract_out(4.0, 4.0, np.array([1.0, 0, 0]), n,
+                               np.array([0.4, 0.0, 0.1]), 0)
+    assert st == 1  # |k_t| = 4 * 0.4 > 1
+
+
+# --------------------------------------------------------------------------
+# integrators
+# --------------------------------------------------------------------------
+def test_rk4_is_fourth_order():
+    e1 = oracle.test_oscillator(0, 0.1, 0.0, 10.0)[0]
+    e2 = oracle.test_oscillator(0, 0.05, 0.0, 10.0)[0]
+    assert 14.0 < e1 / e2 < 18.0
+
+
+def test_dp45_fifth_order_propagation():
+    e1 = oracle.test_oscillator(2, 0.2, 0.0, 10.0)[0]
+    e2 = oracle.test_oscillator(2, 0.1, 0.0, 10.0)[0]
+    assert 26.0 < e1 / e2 < 38.0
+
+
+def test_dp45_error_tracks_tolerance():
+    errs, steps = [], []
+    for tol in (1e-6, 1e-8, 1e-10):
+        e, _, ns = oracle.test_oscillator(1, 0.01, tol, 10.0)
+        errs.append(e)
+        steps.append(ns)
+        assert e < 100 * tol
+    assert errs[0] > errs[1] > errs[2]
+    assert steps[0] < steps[1] < steps[2]
+    # step count grows like tol^(-1/5)
+    assert 1.8 < steps[2] / steps[1] < 3.5
+
+
+# --------------------------------------------------------------------------
+# tracing: exact results the paper's design fixes
+# --------------------------------------------------------------------------
+def _exact_inplane(rays):
+    o, d = rays[:3], rays[3:]
+    p = o[0] * (-d[1]) + o[1] * d[0]
+    s = 2.0 * np.sqrt(9.0 - p ** 2)
+    return o + s * d, d, s, p
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("scheme", ["rk4", "dp45"])
+def test_inplane_extraordinary_rays_are_cloaked_exactly(axis, scheme):
+    """Sect. 4 (design of Eqs. (14)/(15)): in-plane rays with in-plane
+    polarization are cloaked exactly and keep the vacuum time of flight."""
+    rays = W.inplane_bundle(48, 2)
+    opts = W.opts_rk4() if scheme == "rk4" else W.opts_dp45()
+    r = oracle.trace(W.cloak(axis), opts, E, rays)
+    pe, de, s, p = _exact_inplane(rays)
+    hit = np.abs(p) < 2.0
+    assert (r["status"][hit] == 0).all() and (r["status"][~hit] == 1).all()
+    res = np.abs(p) >= 0.3
+    tol = 3e-9 if scheme == "rk4" else 1e-6
+    assert np.linalg.norm(r["out"][:3] - pe, axis=0)[res].max() < tol
+    assert np.linalg.norm(r["out"][3:] - de, axis=0)[res].max() < tol
+    assert np.abs(r["opl"] - s)[res].max() < tol
+    if scheme == "rk4":
+        assert np.nanmax(r["hres"][res]) < 1e-10
+
+
+def test_azimuthal_extraordinary_3d_is_a_virtual_straight_line():
+    rays = CF.aimed_rays(24, 11, min_ktheta=0.2)
+    r = oracle.trace(W.cloak(1), W.opts_rk4(r_out=2.0), E, rays)
+    for i in range(rays.shape[1]):
+        pe, de, opl = CF.cf2_azimuthal_e(rays[:3, i], rays[3:, i])
+        np.testing.assert_allclose(r["out"][:3, i], pe, atol=2e-8)
+        np.testing.assert_allclose(r["out"][3:, i], de, atol=2e-8)
+        assert r["opl"][i] == pytest.approx(opl, abs=2e-8)
+
+
+def test_radial_ordinary_3d_is_a_lens_with_mirror():
+    """Sect. 4: straight ordinary rays, refracted like a cylindrical lens, and
+    specularly reflected at the metal cylinder."""
+    rays = CF.aimed_rays(24, 12)
+    r = oracle.trace(W.cloak(0), W.opts_rk4(r_out=2.0), O, rays)
+    for i in range(rays.shape[1]):
+        pe, de, opl = CF.cf3_radial_o(rays[:3, i], rays[3:, i])
+        np.testing.assert_allclose(r["out"][:3, i], pe, atol=1e-10)
+        np.testing.assert_allclose(r["out"][3:, i], de, atol=1e-10)
+        assert r["opl"][i] == pytest.approx(opl, abs=1e-10)
+
+
+@pytest.mark.parametrize("axis,branch", [(0, 1), (1, 0)])
+def test_integrable_3d_cases_match_quadrature(axis, branch):
+    rays = CF.aimed_rays(12, 13 + axis)
+    r = oracle.trace(W.cloak(axis), W.opts_rk4(r_out=2.0), branch, rays)
+    for i in range(rays.shape[1]):
+        pe, de, opl = CF.cf4_quadrature(axis, branch, rays[:3, i], rays[3:, i])
+        np.testing.assert_allclose(r["out"][:3, i], pe, atol=1e-7)
+        np.testing.assert_allclose(r["out"][3:, i], de, atol=1e-7)
+        assert r["opl"][i] == pytest.approx(opl, abs=1e-7)
+        assert r["hres"][i] < 1e-9
+
+
+def test_which_rays_reach_the_metal_cylinder():
+    """Sect. 4: in the radial cloak all ordinary rays reach the inner metal
+    cylinder and no extraordinary ray does; in the azimuthal cloak no ray does.
+    With an absorbing core, the rays that reach it are the absorbed ones."""
+    rays = CF.aimed_rays(32, 14, min_tangential=0.1)
+    for axis, branch, want_absorbed in ((0, 0, True), (0, 1, False), (1, 0, False), (1, 1, False)):
+        c = W.cloak(axis, inner_mirror=0)
+        r = oracle.trace(c, W.opts_rk4(r_out=2.0), branch, rays)
+        assert ((r["status"] == 2).all() if want_absorbed else (r["status"] == 0).all())
+
+
+def test_ordinary_rays_do_not_cloak():
+    """Sect. 2: ordinary rays do not lead to cloaking."""
+    rays = W.inplane_bundle(32, 1)
+    pe, de, s, p = _exact_inplane(rays)
+    for axis in (0, 1):
+        r = oracle.trace(W.cloak(axis), W.opts_rk4(), O, rays)
+        hit = np.abs(p) < 1.9
+        assert np.linalg.norm(r["out"][3:] - de, axis=0)[hit].max() > 0.1
+
+
+@pytest.mark.parametrize("axis,branch", [(0, 1), (1, 1), (1, 0), (0, 0)])
+def test_time_reversal(axis, branch):
+    rays = CF.aimed_rays(12, 15)
+    op = W.opts_rk4()
+    r = oracle.trace(W.cloak(axis), op, branch, rays)
+    back = np.concatenate([r["out"][:3], -r["out"][3:]])
+    r2 = oracle.trace(W.cloak(axis), op, branch, back)
+    np.testing.assert_allclose(r2["out"][:3], rays[:3], atol=1e-8)
+    np.testing.assert_allclose(r2["out"][3:], -rays[3:], atol=1e-8)
+    np.testing.assert_allclose(r2["opl"], r["opl"], atol=1e-8)
+
+
+def test_rotation_equivariance():
+    rays = CF.aimed_rays(8, 16)
+    ang = 0.7391
+    R = np.array([[math.cos(ang), -math.sin(ang), 0], [math.sin(ang), math.cos(ang), 0], [0, 0, 1]])
+    rot = np.concatenate([R @ rays[:3], R @ rays[3:]])
+    for axis in (0, 1):
+        a = oracle.trace(W.cloak(axis), W.opts_rk4(), E, rays)
+        b = oracle.trace(W.cloak(axis), W.opts_rk4(), E, rot)
+        np.testing.assert_allclose(b["out"][:3], R @ a["out"][:3], atol=1e-9)
+        np.testing.assert_allclose(b["out"][3:], R @ a["out"][3:], atol=1e-9)
+
+
+def test_scale_invariance():
+    """The paper's 5 cm / 10 cm cloak and the unit cloak give the same rays
+    scaled by 5 (Eqs. (14)/(15) depend on r/a and b/a only)."""
+    lam = _gold("paper_values.json")["inner_radius_a_cm"]["value"]
+    rays = CF.aimed_rays(8, 17)
+    big = np.concatenate([lam * rays[:3], rays[3:]])
+    for axis in (0, 1):
+        c1 = W.cloak(axis)
+        c2 = dict(c1, r1=lam * c1["r1"], r2=lam * c1["r2"])
+        a = oracle.trace(c1, W.opts_rk4(), E, rays)
+        b = oracle.trace(c2, W.opts_rk4(h=lam * 1e-3, r_out=lam * 3.0), E, big)
+        np.testing.assert_allclose(b["out"][:3], lam * a["out"][:3], atol=1e-9 * lam)
+        np.testing.assert_allclose(b["out"][3:], a["out"][3:], atol=1e-9)
+        np.testing.assert_allclose(b["opl"], lam * a["opl"], atol=1e-9 * lam)
+
+
+def test_invalid_and_missing_rays():
+    c = W.cloak(0, height=4.0)
+    # columns: origin inside the cloak body, NaN origin, ray passing by,
+    # zero direction, ray through the cloak
+    rays = np.array([[0.5, np.nan, 5.0, 5.0, 5.0],
+                     [0.0, 0.0, 5.0, 5.0, 0.3],
+                     [1.0, 1.0, 1.0, 1.0, 1.0],
+                     [1.0, 1.0, 0.0, 0.0, -1.0],
+                     [0.0, 0.0, 1.0, 0.0, 0.0],
+                     [0.0, 0.0, 0.0, 0.0, 0.0]])
+    r = oracle.trace(c, W.opts_dp45(), E, rays)
+    assert list(r["status"]) == [6, 6, 1, 6, 0]
+    # a passing ray is reported where it leaves r = r_out, unchanged
+    np.testing.assert_allclose(r["out"][3:, 2], [0, 1, 0], atol=0)
+
+
+def test_top_disk_of_metal_cylinder_reflects():
+    c = W.cloak(1, height=4.0)
+    rays = np.array([[0.3], [0.2], [8.0], [0.0], [0.0], [-1.0]])
+    r = oracle.trace(c, W.opts_dp45(r_out=3.0), E, rays)
+    assert r["status"][0] == 7
+    np.testing.assert_allclose(r["out"][3:, 0], [0, 0, 1.0], atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# camera, room, shading
+# --------------------------------------------------------------------------
+def test_splitmix64_published_value():
+    g = _gold("splitmix64.json")
+    assert oracle.splitmix64(g["seed"], g["n"]) == int(g["value_hex"], 16)
+
+
+def test_camera_centre_and_corner():
+    cam = W.orbit_camera(0.3, 20.0, 3, 3)
+    o, d = oracle.camera_ray(cam, 0, 4)  # centre pixel of a 3x3 image
+    f = np.array(cam["look"]) - np.array(cam["eye"])
+    np.testing.assert_allclose(d, f / np.linalg.norm(f), atol=1e-15)
+    o, d0 = oracle.camera_ray(cam, 0, 0)  # top-left pixel centre
+    t = math.tan(math.radians(30.0)) * 2.0 / 3.0
+    ang = math.acos(d0 @ d)
+    assert ang == pytest.approx(math.atan(math.hypot(t, t)), abs=1e-14)
+    assert d0[2] > d[2]  # row 0 is at the top
+
+
+def test_room_codes_by_hand():
+    room = W.room()
+    c = np.array([0.0, 0.0, 5.0])
+    # +x wall at (10, 0, 5): floor(0) + floor(10) = 10 -> parity 0, face 1
+    assert oracle.room_code(room, c, np.array([1.0, 0, 0]))[0] == 2
+    # floor at (0, 0, 0): face 4, parity 0
+    code, s = oracle.room_code(room, c, np.array([0, 0, -1.0]))
+    assert code == 8 and s == pytest.approx(5.0)
+    # +x wall at (10, 0.7, 5.2): floor(1.4) + floor(10.4) = 11 -> odd
+    d = np.array([10.0, 0.7, 0.2])
+    d /= np.linalg.norm(d)
+    assert oracle.room_code(room, c, d)[0] == 3
+    # -y wall at (-1.2, -10, 7.6): floor(-2.4) + floor(15.2) = -3 + 15 -> even
+    d = np.array([-1.2, -10.0, 2.6])
+    d /= np.linalg.norm(d)
+    assert oracle.room_code(room, c, d)[0] == 4
+
+
+def test_elevation0_centre_row_is_cloaked_for_extraordinary_light():
+    """Sect. 4: the cloaks are exact for rays in the cross-section plane with
+    in-plane polarization, so the camera's centre row at elevation 0 shows the
+    empty room (up to tile-edge pixels)."""
+    n = 65
+    cam = W.orbit_camera(0.0, 0.0, n, n)
+    room = W.room()
+    row = np.arange(n) + (n // 2) * n
+    empty, _ = oracle.render_pixels(None, W.opts_dp45(), room, cam, 0, E, row)
+    for axis in (0, 1):
+        c = W.cloak(axis, height=4.0)
+        col, r = oracle.render_pixels(c, W.opts_rk4(), room, cam, 0, E, row)
+        assert (r["status"] == 0).sum() > 10
+        assert (np.abs(col - empty).max(axis=1) > 0).sum() <= 1
+        col_o, _ = oracle.render_pixels(c, W.opts_rk4(), room, cam, 0, O, row)
+        assert (np.abs(col_o - empty).max(axis=1) > 0).sum() > 5
