@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Benchmark of the cloak ray tracer on one MI355X.
+
+Workload (one step): the photorealistic-render workload -- radial and
+azimuthal uniaxial cloaks (R1 = 1, R2 = 2, height 4) in the checkerboard room
+[-10,10]^2 x [0,10] (0.5 tiles), pinhole camera at distance 8 from (0,0,2),
+60 deg field of view, elevations 0/15/30/45 deg, 1024 x 1024 pixels,
+ordinary and extraordinary branch traced separately, Dormand-Prince 5(4) at
+tolerance 1e-8. One step = rt_render of both cloaks (16.8 M camera rays).
+
+Metric: Mrays/s traced through the cloak = rays that enter the cloak material
+per second of step time (all camera rays per second are reported too).
+
+Prints one JSON line. --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64 (256 CUs x 2.4 GHz x 128 flop/clk)
+PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 with packed instructions
+
+# Algorithmic flops (FMA = 2; add, mul, div, sqrt, rcp = 1) of one evaluation
+# of dv/dt (Eq. (8), reduced cylindrical form) per branch kind
+# (radial-o, radial-e, azimuthal-o, azimuthal-e).
+ACCEL_FLOPS = {0: 0, 1: 41, 2: 37, 3: 37}
+# One Dormand-Prince 5(4) attempt on the 6-component state: stage inputs
+# (20 non-zero a_sj per component, 2 flops each, + 2 per stage) 312, embedded
+# error 78, scaled RMS norm 42, controller 5.
+DP45_COMBINE_FLOPS = 312 + 78 + 42 + 5
+DP45_STAGES = 6
+# RK4: stage inputs 3 x 6 FMA + 3, final combination 6 x 8.
+RK4_COMBINE_FLOPS = 75 + 48
+RK4_STAGES = 4
+
+
+def attempt_flops(kind: int, scheme: int) -> int:
+    if scheme == 1:
+        return DP45_COMBINE_FLOPS + DP45_STAGES * ACCEL_FLOPS[kind]
+    return RK4_COMBINE_FLOPS + RK4_STAGES * ACCEL_FLOPS[kind]
+
+
+def cpu_baseline(opts, cams, stride, entered_only=True):
+    """Time the oracle on every `stride`-th pixel of every image."""
+    import numpy as np
+
+    import oracle
+    from paper_1209_6038_amd import workloads as W
+    room = W.room()
+    n_entered = 0
+    n_rays = 0
+    t0 = time.perf_counter()
+    for axis in (0, 1):
+        c = W.cloak(axis, height=W.HEIGHT)
+        for k, cam in enumerate(cams):
+            ids = np.arange(0, cam["w"] * cam["h"], stride, dtype=np.int64)
+            for branch in (0, 1):
+                r = oracle.render_samples(c, opts, room, cam, k, branch, ids)
+                n_entered += int(np.isin(r["status"], (0, 2, 3, 4, 5)).sum())
+                n_rays += len(ids)
+    dt = time.perf_counter() - t0
+    return {"value": n_entered / dt / 1e6, "unit": "Mrays/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"every {stride}th pixel of the 16 images ({n_rays} camera rays, "
+                      f"{n_entered} entering the cloak), FP64 C oracle with OpenMP, {dt:.1f} s",
+            "all_rays_per_s": n_rays / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--res", type=int, default=1024)
+    ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed")
+    ap.add_argument("--refill", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--cpu-stride", type=int, default=31)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it "
+              "(see DESIGN.md for how the path would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1209_6038_amd import build as B
+    from paper_1209_6038_amd import rt
+    from paper_1209_6038_amd import workloads as W
+
+    if not os.path.exists(rt.LIB_PATH):
+        B.build()
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    cams = W.render_views(res=args.res)
+    opts = W.render_opts(precision=args.precision, refill_period=args.refill, block=args.block)
+    cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
+    room = W.room()
+    outs = [torch.empty((len(cams), 2, args.res, args.res, 3), dtype=torch.float32, device=dev)
+            for _ in cloaks]
+
+    def step():
+        for cl, out in zip(cloaks, outs):
+            rt.render(cl, opts, room, cams, 3, out=out)
+
+    # untimed counting pass: entering rays and integrator step attempts
+    entered = 0
+    flops = 0
+    for ci, cl in enumerate(cloaks):
+        _, aux = rt.render(cl, opts, room, cams, 3, aux=True)
+        torch.cuda.synchronize()
+        st = aux["status"].cpu().numpy()
+        ns = aux["nsteps"].cpu().numpy().astype(np.int64)
+        entered += int(np.isin(st, (0, 2, 3, 4, 5)).sum())
+        for pi, pol in enumerate((0, 1)):
+            kind = ci * 2 + pol
+            flops += int(ns[:, pi].sum()) * attempt_flops(kind, opts["scheme"])
+        del aux
+    camera_rays = 2 * len(cams) * 2 * args.res * args.res
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    rt.profile_enable(True)
+    rt.profile_read()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    transit_ms, launches = rt.profile_read()
+    rt.profile_enable(False)
+
+    launches_per_step = launches / args.steps
+    avg_launch_ms = transit_ms / max(launches, 1)
+    flops_per_launch = flops / launches_per_step
+    achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    peak = PEAK_FP64_TFLOPS if args.precision == 0 else PEAK_FP32_TFLOPS
+    value = entered / (ms * 1e-3) / 1e6
+    rec = {
+        "metric": "Mrays/s traced through cloak at <=1e-6 exit error",
+        "value": round(value, 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "3-D render: radial + azimuthal uniaxial cloaks (R1=1, R2=2, "
+                               "height 4), checkerboard room 20x20x10, 4 elevations x 1024^2 px, "
+                               "ordinary + extraordinary, DP45 tol 1e-8",
+                   "camera_rays_per_step": camera_rays,
+                   "rays_entering_cloak_per_step": entered,
+                   "all_camera_rays_per_s_M": round(camera_rays / (ms * 1e-3) / 1e6, 3),
+                   "precision": "fp64" if args.precision == 0 else "mixed",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "k_transit (integrator)",
+                     "avg_launch_ms": round(avg_launch_ms, 4),
+                     "launches_per_step": launches_per_step,
+                     "integrator_share_of_step": round(transit_ms / args.steps / ms, 4)},
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(W.opts_dp45(), cams, args.cpu_stride)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * rt.h -- C ABI of the MI355X (gfx950) ray tracer for the uniaxial-dielectric
+ * cylindrical invisibility cloaks of Halimeh & Wegener, "Photorealistic ray
+ * tracing of free-space invisibility cloaks made of uniaxial dielectrics".
+ *
+ * Conventions (every entry point):
+ *  - Array arguments are DEVICE pointers (HIP global memory) owned by the
+ *    caller; the library never frees or retains them past the call.
+ *  - `stream` is a hipStream_t (NULL = the null stream). Calls validate their
+ *    arguments synchronously, then enqueue work asynchronously on `stream`
+ *    and return. Results are valid once the stream has been synchronized.
+ *  - Return value: RT_OK or an RT_E_* code; rt_last_error() gives a
+ *    thread-local message for the last failed call. No C++ exception crosses
+ *    the ABI. Argument errors are reported before anything is enqueued.
+ *  - Per-ray outcomes are never call failures: they are reported in the
+ *    per-ray status arrays (RT_RAY_*).
+ *  - Units: lengths in the cloak's units, c0 = omega = 1, so the ODE time of
+ *    Eq. (2)/(8) is the optical path length and |k| is the phase index.
+ *  - Handles (rt_cloak) are immutable after creation and may be used from
+ *    several streams at once; calls that run concurrently must not share
+ *    output buffers.
+ *  - The library allocates a device workspace on first use and grows it when
+ *    a larger call needs it (hipMalloc, synchronous); it is released by
+ *    rt_release_workspace() or at process exit.
+ */
+#ifndef RT_H
+#define RT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { RT_OK = 0, RT_E_INVALID = 1, RT_E_NOMEM = 2, RT_E_DEVICE = 3, RT_E_UNSUPPORTED = 4 };
+
+/* Optic-axis field of the cloak: Eq. (14) (c along r) or Eq. (15) (c along theta). */
+enum { RT_AXIS_RADIAL = 0, RT_AXIS_AZIMUTHAL = 1 };
+
+/* Ray branch inside the cloak (Sect. 2): ordinary (Eq. (2)) or extraordinary (Eq. (8)). */
+enum { RT_POL_ORDINARY = 0, RT_POL_EXTRAORDINARY = 1 };
+
+enum { RT_SCHEME_RK4 = 0, RT_SCHEME_DP45 = 1 };
+enum { RT_PREC_FP64 = 0, RT_PREC_MIXED = 1 };
+
+/* Per-ray outcome. */
+enum {
+    RT_RAY_EXITED = 0,    /* crossed the cloak and left it through an interface */
+    RT_RAY_MISSED = 1,    /* never touched the cloak */
+    RT_RAY_ABSORBED = 2,  /* reached the inner radius where no mirror reflects it */
+    RT_RAY_MAXSTEPS = 3,  /* step budget exhausted inside the cloak */
+    RT_RAY_DIVERGED = 4,  /* non-finite state or step-size collapse */
+    RT_RAY_TIR = 5,       /* more internal reflections than max_bounces */
+    RT_RAY_INVALID = 6,   /* non-finite input, zero direction or origin inside the cloak */
+    RT_RAY_REFLECTED = 7  /* reflected at the entry (evanescent transmission, metal end disk) */
+};
+
+typedef struct rt_cloak_s *rt_cloak;
+
+/* Cloak geometry and material (Sect. 4, Eqs. (13)-(15)). The material fills
+   r1 <= r <= r2, z0 <= z <= z1 (z0 = -INFINITY, z1 = +INFINITY: infinitely
+   long cylinder). inner_mirror = 1: r < r1 is the perfect metal cylinder the
+   cloak hides (Sect. 4), including its end disks; 0: r < r1 absorbs. */
+typedef struct {
+    double r1, r2;
+    double z0, z1;
+    int32_t axis;
+    int32_t inner_mirror;
+} rt_cloak_desc;
+
+/* Integration options. scheme: RT_SCHEME_RK4 (fixed step h, the paper's
+   fourth-order Runge-Kutta, Sect. 4) or RT_SCHEME_DP45 (Dormand-Prince 5(4),
+   initial step h, tolerances rtol/atol, maximum step hmax). precision:
+   RT_PREC_FP64, or RT_PREC_MIXED (FP32 derivative evaluation where
+   r - r1 >= fp64_band, FP64 state and step combination everywhere).
+   r_out: report radius of rt_trace_batch (>= r2). max_steps: step attempts per
+   ray. max_bounces: internal reflections (inner mirror, total internal
+   reflection) per ray. block / refill_period: integrator launch shape
+   (threads per block, steps between refills of finished lanes; 0 = library
+   default). */
+typedef struct {
+    int32_t scheme;
+    int32_t precision;
+    double h, rtol, atol, hmax;
+    double fp64_band;
+    double r_out;
+    int64_t max_steps;
+    int32_t max_bounces;
+    int32_t block;
+    int32_t refill_period;
+    int32_t reserved;
+} rt_trace_opts;
+
+/* Pinhole camera: eye, look-at point, up vector, vertical full field of view
+   (degrees), image w x h (row 0 at the top, square pixels), spp samples per
+   pixel (a perfect square; 1 = pixel centre, m*m = stratified m x m grid
+   jittered by SplitMix64 outputs keyed by (camera index, pixel, sample)). */
+typedef struct {
+    double eye[3], look[3], up[3];
+    double fov_deg;
+    int32_t w, h, spp, reserved;
+    uint64_t seed;
+} rt_camera;
+
+/* Backdrop: axis-aligned room [lo, hi] seen from inside, checkerboard tiles
+   of side `tile`, colour rgb[face][parity] with faces x-, x+, y-, y+, z-, z+
+   and parity (floor(u/tile) + floor(v/tile)) mod 2 of the in-face coordinates. */
+typedef struct {
+    double lo[3], hi[3];
+    double tile;
+    float rgb[6][2][3];
+} rt_room;
+
+/* Optional per-sample outputs of rt_render, each laid out per image
+   (camera-major, then branch) over ns = w*h*spp samples; NULL fields are not
+   written. rec: SoA 7 x ns doubles per image (origin and direction of the
+   last vacuum ray, optical path from the eye to the room); status: RT_RAY_*;
+   code: face*2 + parity of the room point seen, 12 = black; nsteps:
+   integrator step attempts. */
+typedef struct {
+    double *rec;
+    int32_t *status;
+    uint8_t *code;
+    int32_t *nsteps;
+} rt_render_aux;
+
+/* Build a cloak handle (host-side constants; no device memory).
+   Errors: RT_E_INVALID unless 0 < r1 < r2, z0 < z1, axis in {0, 1}. */
+int rt_build_cloak(const rt_cloak_desc *desc, rt_cloak *out);
+
+/* Free a handle from rt_build_cloak. NULL is accepted. */
+int rt_free_cloak(rt_cloak cloak);
+
+/* Trace n vacuum rays through the cloak (Sects. 2-4): vacuum leg to the
+   cloak, double refraction into branch `pol` (Sect. 3, Eqs. (6), (9)-(11)),
+   integration of Eq. (2) (ordinary) or Eq. (8) (extraordinary), reflection at
+   the inner metal cylinder (Sect. 4), exit refraction into vacuum (Sect. 3),
+   and the vacuum leg to the cylinder r = r_out.
+     in6:    SoA 6 x n doubles: origin x,y,z then direction x,y,z (any length > 0)
+     out6:   SoA 6 x n doubles: point where the outgoing ray crosses r = r_out
+             (the last state for rays that did not leave), unit direction
+     opl:    n doubles, optical path from the origin to out6's point
+     status: n int32, RT_RAY_*
+     hres:   n doubles or NULL, |v^T M v - 1| at the last interface (NaN if the
+             ray never entered)
+     nsteps: n int32 or NULL, integrator step attempts
+   n = 0 is a no-op. Errors: RT_E_INVALID (NULL handle/options/required
+   pointer, n < 0, r_out < r2, bad options), RT_E_NOMEM (workspace),
+   RT_E_DEVICE (launch failure). */
+int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64_t n,
+                   const double *in6, double *out6, double *opl, int32_t *status,
+                   double *hres, int32_t *nsteps, void *stream);
+
+/* Render n_cams views of the room with the cloak (NULL = empty room) for each
+   branch in pol_mask (bit 0 ordinary, bit 1 extraordinary), tracing each
+   branch separately (Sect. 4): camera rays, cloak transit as in
+   rt_trace_batch, room shading.
+     rgb: float32 [n_cams][npol][h][w][3], mean colour over the samples of each
+          pixel (npol = popcount(pol_mask), ordinary first); black for absorbed,
+          totally reflected, diverged or step-limited samples
+     aux: NULL or optional per-sample outputs (see rt_render_aux)
+   All cameras must share w, h and spp. Errors as rt_trace_batch. */
+int rt_render(rt_cloak cloak, const rt_trace_opts *opts, const rt_room *room,
+              const rt_camera *cams, int32_t n_cams, int32_t pol_mask, float *rgb,
+              const rt_render_aux *aux, void *stream);
+
+/* Timing of the integrator kernel, for benchmarks. While enabled, every
+   launch of the transit integrator is bracketed by HIP events recorded on the
+   caller's stream. rt_profile_read waits for the recorded events, returns the
+   summed duration (ms) and the number of launches since the last read, and
+   forgets them. */
+int rt_profile_enable(int32_t on);
+int rt_profile_read(double *transit_ms, int64_t *launches);
+
+/* Release the library's device workspace (synchronizes the device first). */
+int rt_release_workspace(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *rt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RT_H */

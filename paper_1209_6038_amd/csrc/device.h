@@ -1,0 +1,607 @@
+// device.h -- device-side math of the cloak tracer for gfx950.
+//
+// Halimeh & Wegener, "Photorealistic ray tracing of free-space invisibility
+// cloaks made of uniaxial dielectrics":
+//   material      Eq. (14) radial / Eq. (15) azimuthal cloak, optic axis r or
+//                 theta, mu = 1 (Sect. 2)
+//   metric        Eq. (7): in the cylindrical frame M = diag(m_r, m_theta, m_z)
+//                 with eps_e across the optic axis and eps_o along it (the
+//                 extraordinary ray), or n_o^2 I (the ordinary ray, for which
+//                 Eq. (2) is Eq. (8) with M = n_o^2 I)
+//   ray equation  Eq. (8) (Eq. (2) as its isotropic case), evaluated as the
+//                 Euler-Lagrange equations of L = v^T M v / 2 in cylindrical
+//                 coordinates, which is the same vector field with no 3x3
+//                 tensor algebra
+//   refraction    Sect. 3: tangential k continuous (Eq. (11)); the normal
+//                 component solves k^T M^-1 k = 1, the dispersion relation
+//                 behind Eq. (9); ray velocity v = M^-1 k (Eq. (6))
+//   stepping      classical RK4 (Sect. 4) and Dormand-Prince 5(4)
+// Units: c0 = omega = 1, so the ODE time is the optical path length.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtk {
+
+// ---------------------------------------------------------------------------
+// parameters passed by value to every kernel
+// ---------------------------------------------------------------------------
+struct CloakP {
+  double a, b, z0, z1;  // radii and axial extent
+  double kappa;         // (b / (b - a))^2
+  double a2, b2;        // a^2, b^2
+  int axis, mirror;     // 0 radial / 1 azimuthal; inner metal cylinder
+};
+
+struct OptsP {
+  double h0, rtol, atol, hmax, band, r_out;
+  long long max_steps;
+  int scheme, precision, max_bounces, pad;
+};
+
+// branch kind = axis * 2 + pol
+enum { K_RO = 0, K_RE = 1, K_AO = 2, K_AE = 3 };
+
+// internal slot states (final states are the RT_RAY_* codes 0..7)
+enum { ST_ACTIVE = 100, ST_EVENT = 101 };
+
+// boundary ids
+enum { B_SIDE = 0, B_INNER = 1, B_TOP = 2, B_BOTTOM = 3 };
+
+// ---------------------------------------------------------------------------
+// fast FP64 reciprocal and reciprocal square root: hardware estimate refined
+// by two Newton steps (quadratic convergence to full double precision)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsq64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// ---------------------------------------------------------------------------
+// metric diag(m_r, m_theta, m_z) at radius r for a branch kind
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void metric_diag(int kind, double kappa, double a, double r,
+                                            double& mr, double& mt, double& mz) {
+  double q = (r - a) / r;
+  double ks = kappa * q * q;
+  switch (kind) {
+    case K_RO: mr = kappa; mt = kappa; mz = kappa; break;
+    case K_RE: mr = kappa; mt = ks; mz = ks; break;
+    case K_AO: mr = ks; mt = ks; mz = ks; break;
+    default:   mr = kappa; mt = ks; mz = kappa; break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// acceleration dv/dt of Eq. (8)/(2) at (p, v), FP64.
+// With w = 1/r, q = (r-a)/r, s = q^2, s' = ds/dr = 2 a q w^2, g = s'/s:
+//   a_r     = [-m_r' v_r^2 + m_t' v_t^2 + m_z' v_z^2 - 2 (m_r - m_t) v_t^2 / r] / (2 m_r)
+//   a_theta = -(m_t'/m_t) v_r v_t,   a_z = -(m_z'/m_z) v_r v_z
+// ---------------------------------------------------------------------------
+template <int KIND>
+__device__ __forceinline__ void accel64(double a, double px, double py, double vx, double vy,
+                                        double vz, double& ax, double& ay, double& az) {
+  if constexpr (KIND == K_RO) {
+    ax = 0.0; ay = 0.0; az = 0.0;
+    return;
+  } else {
+    double r2 = fma(px, px, py * py);
+    double w = rsq64(r2);
+    double w2 = w * w;
+    double q = fma(-a, w, 1.0);
+    double P = fma(px, vx, py * vy);   // r v_r
+    double Q = fma(px, vy, -py * vx);  // r v_t
+    double vr = P * w, vt = Q * w;
+    double g = 2.0 * a * w2 * rcp64(q);
+    double vt2 = vt * vt;
+    double ar, at;
+    if constexpr (KIND == K_RE) {
+      // m = (k, k s, k s)
+      double s = q * q;
+      double sp = g * s;
+      ar = fma(0.5 * sp, fma(vz, vz, vt2), -(1.0 - s) * vt2 * w);
+      at = -g * vr * vt;
+      az = -g * vr * vz;
+    } else if constexpr (KIND == K_AE) {
+      // m = (k, k s, k)
+      double s = q * q;
+      double sp = g * s;
+      ar = fma(0.5 * sp, vt2, -(1.0 - s) * vt2 * w);
+      at = -g * vr * vt;
+      az = 0.0;
+    } else {
+      // K_AO: m = k s I
+      ar = 0.5 * g * fma(vz, vz, fma(-vr, vr, vt2));
+      at = -g * vr * vt;
+      az = -g * vr * vz;
+    }
+    ar *= w;
+    at *= w;
+    ax = fma(ar, px, -at * py);
+    ay = fma(ar, py, at * px);
+  }
+}
+
+// Mixed precision: r^2 - a^2 is formed in FP64 (no cancellation near r = a),
+// everything else of the derivative evaluation in FP32.
+template <int KIND>
+__device__ __forceinline__ void accel32(double a, double px, double py, double vx, double vy,
+                                        double vz, double& ax, double& ay, double& az) {
+  if constexpr (KIND == K_RO) {
+    ax = 0.0; ay = 0.0; az = 0.0;
+    return;
+  } else {
+    double d64 = fma(px, px, fma(py, py, -a * a));  // r^2 - a^2
+    float d = (float)d64;
+    float fa = (float)a;
+    float x = (float)px, y = (float)py;
+    float fvx = (float)vx, fvy = (float)vy, fvz = (float)vz;
+    float r2 = d + fa * fa;
+    float w = __builtin_amdgcn_rsqf(r2);
+    float r = r2 * w;
+    float w2 = w * w;
+    float q = d * w2 * __builtin_amdgcn_rcpf(1.0f + fa * w);  // (r^2-a^2)/(r (r+a)) = (r-a)/r
+    (void)r;
+    float P = fmaf(x, fvx, y * fvy);
+    float Q = fmaf(x, fvy, -y * fvx);
+    float vr = P * w, vt = Q * w;
+    float g = 2.0f * fa * w2 * __builtin_amdgcn_rcpf(q);
+    float vt2 = vt * vt;
+    float ar, at, fz;
+    if constexpr (KIND == K_RE) {
+      float s = q * q;
+      float sp = g * s;
+      ar = fmaf(0.5f * sp, fmaf(fvz, fvz, vt2), -(1.0f - s) * vt2 * w);
+      at = -g * vr * vt;
+      fz = -g * vr * fvz;
+    } else if constexpr (KIND == K_AE) {
+      float s = q * q;
+      float sp = g * s;
+      ar = fmaf(0.5f * sp, vt2, -(1.0f - s) * vt2 * w);
+      at = -g * vr * vt;
+      fz = 0.0f;
+    } else {
+      ar = 0.5f * g * fmaf(fvz, fvz, fmaf(-vr, vr, vt2));
+      at = -g * vr * vt;
+      fz = -g * vr * fvz;
+    }
+    ar *= w;
+    at *= w;
+    ax = (double)fmaf(ar, x, -at * y);
+    ay = (double)fmaf(ar, y, at * x);
+    az = (double)fz;
+  }
+}
+
+// precision dispatch: MIXED uses FP32 unless r - a < band
+template <int KIND, bool MIXED>
+__device__ __forceinline__ void accel(double a, double band2, double px, double py, double vx,
+                                      double vy, double vz, double& ax, double& ay, double& az) {
+  if constexpr (MIXED) {
+    // band2 = (a + band)^2: FP64 inside the band next to the inner radius
+    if (fma(px, px, py * py) < band2) accel64<KIND>(a, px, py, vx, vy, vz, ax, ay, az);
+    else accel32<KIND>(a, px, py, vx, vy, vz, ax, ay, az);
+  } else {
+    (void)band2;
+    accel64<KIND>(a, px, py, vx, vy, vz, ax, ay, az);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dormand & Prince (1980) RK5(4)7M tableau and the products used below.
+// For y = (x, v) with dx/dt = v the stage inputs only need the stage
+// accelerations A_l:
+//   V_s = v + h sum_l a_sl A_l
+//   X_s = x + h (c_s v + h sum_l (a a)_sl A_l),   (a a)_sl = sum_j a_sj a_jl
+// The seventh stage input is the fifth-order solution (first same as last);
+// the embedded error is h^2 sum_l (e a)_l A_l for x (the weights e = b - b*
+// sum to zero) and h sum_j e_j A_j for v.
+// ---------------------------------------------------------------------------
+struct DP {
+  static constexpr double A[7][7] = {
+      {0, 0, 0, 0, 0, 0, 0},
+      {1.0 / 5, 0, 0, 0, 0, 0, 0},
+      {3.0 / 40, 9.0 / 40, 0, 0, 0, 0, 0},
+      {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0, 0},
+      {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0, 0},
+      {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0, 0},
+      {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0}};
+  static constexpr double E[7] = {71.0 / 57600, 0, -71.0 / 16695, 71.0 / 1920,
+                                  -17253.0 / 339200, 22.0 / 525, -1.0 / 40};
+};
+
+constexpr double dp_c(int s) {
+  double c = 0;
+  for (int j = 0; j < 7; ++j) c += DP::A[s][j];
+  return c;
+}
+constexpr double dp_aa(int s, int l) {
+  double t = 0;
+  for (int j = 0; j < 7; ++j) t += DP::A[s][j] * DP::A[j][l];
+  return t;
+}
+constexpr double dp_ea(int l) {
+  double t = 0;
+  for (int j = 0; j < 7; ++j) t += DP::E[j] * DP::A[j][l];
+  return t;
+}
+
+// One DP45 attempt. Inputs: state (x, v), A[0] = acceleration at the state.
+// Outputs: fifth-order state (xn, vn), A[6] = acceleration there, and the sum
+// of squared scaled errors (accept when <= 6, i.e. RMS <= 1).
+template <int KIND, bool MIXED>
+__device__ __forceinline__ double dp45_attempt(double a, double band2, const double x[3],
+                                               const double v[3], double A[7][3], double h,
+                                               double rtol, double atol, double xn[3],
+                                               double vn[3]) {
+#pragma unroll
+  for (int s = 1; s < 7; ++s) {
+    double X[3], V[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double ax = 0.0, av = 0.0;
+#pragma unroll
+      for (int l = 0; l < s; ++l) {
+        if (dp_aa(s, l) != 0.0) ax = fma(dp_aa(s, l), A[l][i], ax);
+        if (DP::A[s][l] != 0.0) av = fma(DP::A[s][l], A[l][i], av);
+      }
+      V[i] = fma(h, av, v[i]);
+      X[i] = fma(h, fma(h, ax, dp_c(s) * v[i]), x[i]);
+    }
+    accel<KIND, MIXED>(a, band2, X[0], X[1], V[0], V[1], V[2], A[s][0], A[s][1], A[s][2]);
+    if (s == 6) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) { xn[i] = X[i]; vn[i] = V[i]; }
+    }
+  }
+  double sum = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double ex = 0.0, ev = 0.0;
+#pragma unroll
+    for (int l = 0; l < 7; ++l) {
+      if (dp_ea(l) != 0.0) ex = fma(dp_ea(l), A[l][i], ex);
+      if (DP::E[l] != 0.0) ev = fma(DP::E[l], A[l][i], ev);
+    }
+    ex *= h * h;
+    ev *= h;
+    double sx = fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol);
+    double sv = fma(rtol, fmax(fabs(v[i]), fabs(vn[i])), atol);
+    double qx = ex / sx, qv = ev / sv;
+    sum = fma(qx, qx, fma(qv, qv, sum));
+  }
+  return sum;
+}
+
+// step-size factor from the summed squared error: 0.9 * RMS^(-1/5) clipped
+// to [0.2, 5]; evaluated in FP32 (a controller heuristic, not part of the
+// solution's accuracy)
+__device__ __forceinline__ double dp45_factor(double sum, bool after_reject) {
+  float fac;
+  if (sum == 0.0) fac = 5.0f;
+  else if (!(sum == sum)) fac = 0.2f;
+  else {
+    float rms2 = (float)(sum * (1.0 / 6.0));
+    fac = 0.9f * exp2f(-0.1f * log2f(rms2));
+    fac = fminf(5.0f, fmaxf(0.2f, fac));
+  }
+  if (after_reject && fac > 1.0f) fac = 1.0f;
+  return (double)fac;
+}
+
+// classical RK4 step for y = (x, v); A1 = acceleration at the state
+template <int KIND, bool MIXED>
+__device__ __forceinline__ void rk4_step(double a, double band2, const double x[3],
+                                         const double v[3], const double A1[3], double h,
+                                         double xn[3], double vn[3]) {
+  double hh = 0.5 * h;
+  double V2[3], V3[3], V4[3], A2[3], A3[3], A4[3], X[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { X[i] = fma(hh, v[i], x[i]); V2[i] = fma(hh, A1[i], v[i]); }
+  accel<KIND, MIXED>(a, band2, X[0], X[1], V2[0], V2[1], V2[2], A2[0], A2[1], A2[2]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { X[i] = fma(hh, V2[i], x[i]); V3[i] = fma(hh, A2[i], v[i]); }
+  accel<KIND, MIXED>(a, band2, X[0], X[1], V3[0], V3[1], V3[2], A3[0], A3[1], A3[2]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { X[i] = fma(h, V3[i], x[i]); V4[i] = fma(h, A3[i], v[i]); }
+  accel<KIND, MIXED>(a, band2, X[0], X[1], V4[0], V4[1], V4[2], A4[0], A4[1], A4[2]);
+  double h6 = h * (1.0 / 6.0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    xn[i] = fma(h6, v[i] + 2.0 * (V2[i] + V3[i]) + V4[i], x[i]);
+    vn[i] = fma(h6, A1[i] + 2.0 * (A2[i] + A3[i]) + A4[i], v[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// kind dispatch helpers (wave-uniform in practice: slots are grouped by kind)
+// ---------------------------------------------------------------------------
+template <bool MIXED>
+__device__ __forceinline__ void accel_k(int kind, double a, double band2, const double x[3],
+                                        const double v[3], double A[3]) {
+  switch (kind) {
+    case K_RE: accel<K_RE, MIXED>(a, band2, x[0], x[1], v[0], v[1], v[2], A[0], A[1], A[2]); break;
+    case K_AO: accel<K_AO, MIXED>(a, band2, x[0], x[1], v[0], v[1], v[2], A[0], A[1], A[2]); break;
+    case K_AE: accel<K_AE, MIXED>(a, band2, x[0], x[1], v[0], v[1], v[2], A[0], A[1], A[2]); break;
+    default: A[0] = 0.0; A[1] = 0.0; A[2] = 0.0; break;
+  }
+}
+
+// single-step map of the active scheme (for boundary root finding)
+template <bool MIXED>
+__device__ __forceinline__ void step_map(int kind, int scheme, double a, double band2,
+                                         const double x[3], const double v[3],
+                                         const double A1[3], double h, double xn[3],
+                                         double vn[3]) {
+  if (scheme == 0) {
+    switch (kind) {
+      case K_RE: rk4_step<K_RE, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
+      case K_AO: rk4_step<K_AO, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
+      case K_AE: rk4_step<K_AE, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
+      default: rk4_step<K_RO, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
+    }
+  } else {
+    double A[7][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) A[0][i] = A1[i];
+    switch (kind) {
+      case K_RE: dp45_attempt<K_RE, MIXED>(a, band2, x, v, A, h, 1.0, 1.0, xn, vn); break;
+      case K_AO: dp45_attempt<K_AO, MIXED>(a, band2, x, v, A, h, 1.0, 1.0, xn, vn); break;
+      case K_AE: dp45_attempt<K_AE, MIXED>(a, band2, x, v, A, h, 1.0, 1.0, xn, vn); break;
+      default: dp45_attempt<K_RO, MIXED>(a, band2, x, v, A, h, 1.0, 1.0, xn, vn); break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool inside_open(const CloakP& c, const double x[3]) {
+  double r2 = fma(x[0], x[0], x[1] * x[1]);
+  return r2 > c.a2 && r2 < c.b2 && x[2] > c.z0 && x[2] < c.z1;
+}
+
+// signed constraint value, negative inside
+__device__ __forceinline__ double gval(const CloakP& c, int id, const double x[3]) {
+  double r = sqrt(fma(x[0], x[0], x[1] * x[1]));
+  switch (id) {
+    case B_SIDE: return r - c.b;
+    case B_INNER: return c.a - r;
+    case B_TOP: return x[2] - c.z1;
+    default: return c.z0 - x[2];
+  }
+}
+
+// first entry of o + s d (s > 0) into r <= b, z0 <= z <= z1; surf B_SIDE /
+// B_TOP / B_BOTTOM. Stable quadratic roots.
+__device__ __forceinline__ bool vacuum_entry(const CloakP& c, const double o[3], const double d[3],
+                                             double& s_out, int& surf) {
+  bool found = false;
+  double best = __builtin_inf();
+  double A = fma(d[0], d[0], d[1] * d[1]);
+  double B = fma(o[0], d[0], o[1] * d[1]);
+  double C = fma(o[0], o[0], fma(o[1], o[1], -c.b2));
+  if (A > 0.0 && C > 0.0) {
+    double disc = fma(B, B, -A * C);
+    if (disc >= 0.0) {
+      double sq = sqrt(disc);
+      double qq = -(B + copysign(sq, B));
+      double s1 = qq / A, s2 = C / qq;
+      double s = fmin(s1, s2);
+      double z = fma(s, d[2], o[2]);
+      if (s > 0.0 && z >= c.z0 && z <= c.z1) { best = s; surf = B_SIDE; found = true; }
+    }
+  }
+  if (d[2] < 0.0 && o[2] > c.z1 && c.z1 < __builtin_inf()) {
+    double s = (c.z1 - o[2]) / d[2];
+    double x = fma(s, d[0], o[0]), y = fma(s, d[1], o[1]);
+    if (s > 0.0 && fma(x, x, y * y) <= c.b2 && s < best) { best = s; surf = B_TOP; found = true; }
+  }
+  if (d[2] > 0.0 && o[2] < c.z0 && c.z0 > -__builtin_inf()) {
+    double s = (c.z0 - o[2]) / d[2];
+    double x = fma(s, d[0], o[0]), y = fma(s, d[1], o[1]);
+    if (s > 0.0 && fma(x, x, y * y) <= c.b2 && s < best) { best = s; surf = B_BOTTOM; found = true; }
+  }
+  s_out = best;
+  return found;
+}
+
+// outward normal of boundary `id` at x (the inner boundary's normal points
+// into the metal, i.e. along -r_hat seen from the material ... we return r_hat;
+// reflection only needs the line)
+__device__ __forceinline__ void boundary_normal(int id, const double x[3], double n[3]) {
+  if (id == B_TOP) { n[0] = 0.0; n[1] = 0.0; n[2] = 1.0; return; }
+  if (id == B_BOTTOM) { n[0] = 0.0; n[1] = 0.0; n[2] = -1.0; return; }
+  double w = rsq64(fma(x[0], x[0], x[1] * x[1]));
+  n[0] = x[0] * w; n[1] = x[1] * w; n[2] = 0.0;
+}
+
+__device__ __forceinline__ void reflect3(double v[3], const double n[3]) {
+  double d = 2.0 * (v[0] * n[0] + v[1] * n[1] + v[2] * n[2]);
+  v[0] = fma(-d, n[0], v[0]);
+  v[1] = fma(-d, n[1], v[1]);
+  v[2] = fma(-d, n[2], v[2]);
+}
+
+// local frame (r_hat, t_hat, z_hat) at x
+__device__ __forceinline__ void local_frame(const double x[3], double rh[2], double th[2], double& r) {
+  double r2 = fma(x[0], x[0], x[1] * x[1]);
+  double w = rsq64(r2);
+  r = r2 * w;
+  rh[0] = x[0] * w; rh[1] = x[1] * w;
+  th[0] = -rh[1]; th[1] = rh[0];
+}
+
+// Entry refraction (Sect. 3) at a point of boundary `surf` with outward
+// normal along r_hat (side) or +/- z (caps). kin: unit vacuum direction.
+// Returns false if the transmitted wave is evanescent. v: ray velocity.
+__device__ __forceinline__ bool refract_in(const CloakP& c, int kind, int surf, const double x[3],
+                                           const double kin[3], double v[3]) {
+  double rh[2], th[2], r;
+  local_frame(x, rh, th, r);
+  double mr, mt, mz;
+  metric_diag(kind, c.kappa, c.a, r, mr, mt, mz);
+  double kr = kin[0] * rh[0] + kin[1] * rh[1];
+  double kt = kin[0] * th[0] + kin[1] * th[1];
+  double kz = kin[2];
+  double q2;
+  if (surf == B_SIDE) {
+    q2 = mr * (1.0 - kt * kt / mt - kz * kz / mz);
+    if (!(q2 >= 0.0)) return false;
+    kr = -sqrt(q2);  // into the material: -r_hat
+  } else {
+    q2 = mz * (1.0 - kr * kr / mr - kt * kt / mt);
+    if (!(q2 >= 0.0)) return false;
+    kz = surf == B_TOP ? -sqrt(q2) : sqrt(q2);
+  }
+  double vr = kr / mr, vt = kt / mt;
+  v[0] = vr * rh[0] + vt * th[0];
+  v[1] = vr * rh[1] + vt * th[1];
+  v[2] = kz / mz;
+  return true;
+}
+
+// Exit refraction into vacuum at boundary `id` (Sect. 3): k = M v, tangential
+// part kept, normal part sqrt(1 - |k_t|^2) outward. Returns false on total
+// internal reflection. Also returns |v^T M v - 1| in hres.
+__device__ __forceinline__ bool refract_out(const CloakP& c, int kind, int id, const double x[3],
+                                            const double v[3], double d[3], double& hres) {
+  double rh[2], th[2], r;
+  local_frame(x, rh, th, r);
+  double mr, mt, mz;
+  metric_diag(kind, c.kappa, c.a, r, mr, mt, mz);
+  double vr = v[0] * rh[0] + v[1] * rh[1];
+  double vt = v[0] * th[0] + v[1] * th[1];
+  double vz = v[2];
+  hres = fabs(fma(mr * vr, vr, fma(mt * vt, vt, mz * vz * vz)) - 1.0);
+  double kr = mr * vr, kt = mt * vt, kz = mz * vz;
+  if (id == B_SIDE) {
+    double t2 = fma(kt, kt, kz * kz);
+    if (t2 > 1.0) return false;
+    kr = sqrt(1.0 - t2);
+  } else {
+    double t2 = fma(kr, kr, kt * kt);
+    if (t2 > 1.0) return false;
+    kz = id == B_TOP ? sqrt(1.0 - t2) : -sqrt(1.0 - t2);
+  }
+  d[0] = kr * rh[0] + kt * th[0];
+  d[1] = kr * rh[1] + kt * th[1];
+  d[2] = kz;
+  return true;
+}
+
+// same-mode specular reflection inside the material at boundary `id`: M is
+// diagonal in (r, theta, z), so the reflected wave flips the normal component
+__device__ __forceinline__ void reflect_inside(int id, const double x[3], double v[3]) {
+  double n[3];
+  boundary_normal(id, x, n);
+  reflect3(v, n);
+}
+
+__device__ __forceinline__ double hamiltonian_res(const CloakP& c, int kind, const double x[3],
+                                                  const double v[3]) {
+  double rh[2], th[2], r;
+  local_frame(x, rh, th, r);
+  double mr, mt, mz;
+  metric_diag(kind, c.kappa, c.a, r, mr, mt, mz);
+  double vr = v[0] * rh[0] + v[1] * rh[1];
+  double vt = v[0] * th[0] + v[1] * th[1];
+  return fabs(fma(mr * vr, vr, fma(mt * vt, vt, mz * v[2] * v[2])) - 1.0);
+}
+
+// larger root of |p + s d|_xy = R (outgoing crossing), 0 if none
+__device__ __forceinline__ double leave_radius(const double p[3], const double d[3], double R) {
+  double A = fma(d[0], d[0], d[1] * d[1]);
+  if (!(A > 0.0)) return 0.0;
+  double B = fma(p[0], d[0], p[1] * d[1]);
+  double C = fma(p[0], p[0], fma(p[1], p[1], -R * R));
+  double disc = fma(B, B, -A * C);
+  if (disc < 0.0) return 0.0;
+  double sq = sqrt(disc);
+  double s = (B <= 0.0) ? (sq - B) / A : -C / (B + sq);
+  return s > 0.0 ? s : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// camera and room
+// ---------------------------------------------------------------------------
+struct CamP {
+  double eye[3], F[3], R[3], U[3];
+  double tan_half, aspect;
+  int w, h, spp, m;
+  unsigned long long seed;
+};
+
+// SplitMix64 (Steele, Lea & Flood 2014): n-th output of the generator seeded
+// with `seed`
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long seed,
+                                                         unsigned long long n) {
+  unsigned long long z = seed + n * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ void camera_ray(const CamP& cam, int cam_index, long long pix, int smp,
+                                           double d[3]) {
+  long long row = pix / cam.w, col = pix - row * cam.w;
+  double ox = 0.5, oy = 0.5;
+  if (cam.spp > 1) {
+    unsigned long long key = ((unsigned long long)cam_index << 40) ^
+                             ((unsigned long long)pix << 8) ^ (unsigned long long)smp;
+    double x1 = (double)(splitmix64(cam.seed, 2 * key + 1) >> 11) * 0x1.0p-53;
+    double x2 = (double)(splitmix64(cam.seed, 2 * key + 2) >> 11) * 0x1.0p-53;
+    ox = ((double)(smp % cam.m) + x1) / cam.m;
+    oy = ((double)(smp / cam.m) + x2) / cam.m;
+  }
+  double u = ((col + ox) / cam.w * 2.0 - 1.0) * cam.tan_half * cam.aspect;
+  double v = (1.0 - (row + oy) / cam.h * 2.0) * cam.tan_half;
+  double dx = cam.F[0] + u * cam.R[0] + v * cam.U[0];
+  double dy = cam.F[1] + u * cam.R[1] + v * cam.U[1];
+  double dz = cam.F[2] + u * cam.R[2] + v * cam.U[2];
+  double w = rsq64(fma(dx, dx, fma(dy, dy, dz * dz)));
+  d[0] = dx * w; d[1] = dy * w; d[2] = dz * w;
+}
+
+struct RoomP {
+  double lo[3], hi[3], tile, inv_tile;
+};
+
+// face*2 + parity of the room point hit by o + s d (s >= 0) from inside
+__device__ __forceinline__ int room_code(const RoomP& rm, const double o[3], const double d[3],
+                                         double& s_hit) {
+  double best = __builtin_inf();
+  int face = -1;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    if (d[ax] != 0.0) {
+      double plane = d[ax] > 0.0 ? rm.hi[ax] : rm.lo[ax];
+      double s = (plane - o[ax]) / d[ax];
+      if (s < best) { best = s; face = 2 * ax + (d[ax] > 0.0 ? 1 : 0); }
+    }
+  }
+  if (face < 0) { s_hit = 0.0; return 12; }
+  if (best < 0.0) best = 0.0;
+  s_hit = best;
+  int ax = face >> 1;
+  int ua = ax == 0 ? 1 : 0;
+  int va = ax == 2 ? 1 : 2;
+  double pu = fma(best, d[ua], o[ua]);
+  double pv = fma(best, d[va], o[va]);
+  long long par = ((long long)floor(pu / rm.tile) + (long long)floor(pv / rm.tile)) & 1;
+  return face * 2 + (int)par;
+}
+
+}  // namespace rtk

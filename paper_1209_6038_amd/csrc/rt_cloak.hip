@@ -1,0 +1,1047 @@
+// rt_cloak.hip -- kernels and C ABI of the cloak ray tracer (gfx950).
+//
+// Pipeline of one call (all launches on the caller's stream):
+//   1. entry kernel   vacuum ray -> cloak intersection -> Sect. 3 refraction;
+//                     rays that miss (or reflect at the entry) are finished
+//                     here, rays that enter get a slot in the work table,
+//                     grouped by branch
+//   2. transit pass   persistent integrator: one ray per lane, state in
+//                     registers; lanes whose ray stops are refilled from the
+//                     pass queue with a wave-aggregated atomic every
+//                     `refill_period` steps; a ray stops when a step ends
+//                     outside the material (event), or on the step limit
+//   3. event kernel   root-find of the step length that lands on the
+//                     boundary, then exit refraction (Sect. 3), same-mode
+//                     total internal reflection, or the inner metal mirror
+//                     (Sect. 4); reflected rays go to the next pass queue
+//   (2-3 repeat max_bounces + 1 times)
+//   4. finish kernel  vacuum leg to r_out (trace) or to the room (render)
+//   5. resolve        (render) per-pixel mean of the sample colours
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/rt.h"
+#include "device.h"
+
+using namespace rtk;
+
+struct rt_cloak_s {
+  rt_cloak_desc d;
+};
+
+namespace {
+
+// counters in device memory
+enum {
+  C_N0 = 0,       // slots in segment 0
+  C_N1 = 1,       // slots in segment 1
+  C_QN = 2,       // C_QN + p: entries of the queue read by pass p (p >= 1)
+  C_FETCH = 20,   // C_FETCH + p: work counter of transit pass p
+  C_COUNT = 40
+};
+constexpr int MAX_PASSES = 16;
+
+struct Table {
+  double *px, *py, *pz, *vx, *vy, *vz;
+  double *t, *h, *opl0, *hres;
+  int *nsteps, *bounces, *status, *kind;
+  long long *key;
+  int *q0, *q1;
+  unsigned int *ctr;
+  long long cap;  // capacity of one segment; segment 1 starts at cap
+};
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+  unsigned int lane = __lane_id();
+  return lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+// wave-aggregated append: returns this lane's index (valid where `want`)
+__device__ __forceinline__ unsigned int wave_append(unsigned int *counter, bool want) {
+  unsigned long long m = __ballot(want);
+  unsigned int base = 0;
+  if (m != 0ull) {
+    int leader = __ffsll((unsigned long long)m) - 1;
+    if ((int)__lane_id() == leader) base = atomicAdd(counter, (unsigned int)__popcll(m));
+    base = __shfl(base, leader);
+  }
+  return base + (unsigned int)__popcll(m & lanemask_lt());
+}
+
+__device__ __forceinline__ bool finite6(const double x[3], const double v[3]) {
+  return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) &&
+         isfinite(v[1]) && isfinite(v[2]);
+}
+
+__device__ __forceinline__ int slot_of(const Table &T, int pass, unsigned int idx, unsigned int n0,
+                                       const int *qin) {
+  if (pass == 0) return idx < n0 ? (int)idx : (int)(T.cap + (idx - n0));
+  return qin[idx];
+}
+
+__device__ __forceinline__ void load_state(const Table &T, int s, double x[3], double v[3]) {
+  x[0] = T.px[s]; x[1] = T.py[s]; x[2] = T.pz[s];
+  v[0] = T.vx[s]; v[1] = T.vy[s]; v[2] = T.vz[s];
+}
+
+__device__ __forceinline__ void store_state(const Table &T, int s, const double x[3],
+                                            const double v[3]) {
+  T.px[s] = x[0]; T.py[s] = x[1]; T.pz[s] = x[2];
+  T.vx[s] = v[0]; T.vy[s] = v[1]; T.vz[s] = v[2];
+}
+
+__device__ __forceinline__ void put_slot(const Table &T, int s, const double x[3], const double v[3],
+                                         int kind, long long key, double opl0, double h0) {
+  store_state(T, s, x, v);
+  T.t[s] = 0.0;
+  T.h[s] = h0;
+  T.opl0[s] = opl0;
+  T.hres[s] = __builtin_nan("");
+  T.nsteps[s] = 0;
+  T.bounces[s] = 0;
+  T.status[s] = ST_ACTIVE;
+  T.kind[s] = kind;
+  T.key[s] = key;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+__global__ void k_zero(unsigned int *p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// rt_trace_batch entry: one thread per input ray
+__global__ void __launch_bounds__(256) k_tb_entry(CloakP c, OptsP o, Table T, int kind, long long n,
+                                                  const double *__restrict__ in6,
+                                                  double *__restrict__ out6, double *__restrict__ opl,
+                                                  int *__restrict__ status, double *__restrict__ hres,
+                                                  int *__restrict__ nsteps) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  bool enter = false;
+  double x[3], v[3], s = 0.0;
+  if (i < n) {
+    double org[3], d[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { org[j] = in6[j * n + i]; d[j] = in6[(3 + j) * n + i]; }
+    double dl = sqrt(fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2])));
+    bool ok = isfinite(org[0]) && isfinite(org[1]) && isfinite(org[2]) && isfinite(dl) && dl > 0.0;
+    if (ok) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) d[j] /= dl;
+      double r2 = fma(org[0], org[0], org[1] * org[1]);
+      ok = !(r2 < c.b2 && org[2] > c.z0 && org[2] < c.z1);
+    }
+    int st = RT_RAY_INVALID;
+    double p[3] = {org[0], org[1], org[2]}, L = 0.0;
+    if (ok) {
+      int surf;
+      st = RT_RAY_MISSED;
+      if (vacuum_entry(c, org, d, s, surf)) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) x[j] = fma(s, d[j], org[j]);
+        if (surf == B_TOP) x[2] = c.z1;
+        if (surf == B_BOTTOM) x[2] = c.z0;
+        double r2 = fma(x[0], x[0], x[1] * x[1]);
+        double nrm[3];
+        boundary_normal(surf, x, nrm);
+        if (surf != B_SIDE && r2 <= c.a2) {
+          p[0] = x[0]; p[1] = x[1]; p[2] = x[2];
+          L = s;
+          if (c.mirror) { reflect3(d, nrm); st = RT_RAY_REFLECTED; }
+          else st = RT_RAY_ABSORBED;
+        } else if (refract_in(c, kind, surf, x, d, v)) {
+          enter = true;
+        } else {
+          p[0] = x[0]; p[1] = x[1]; p[2] = x[2];
+          L = s;
+          reflect3(d, nrm);
+          st = RT_RAY_REFLECTED;
+        }
+      }
+      if (!enter && st != RT_RAY_ABSORBED) {
+        double sl = leave_radius(p, d, o.r_out);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) p[j] = fma(sl, d[j], p[j]);
+        L += sl;
+      }
+    }
+    if (!enter) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) { out6[j * n + i] = p[j]; out6[(3 + j) * n + i] = d[j]; }
+      opl[i] = L;
+      status[i] = st;
+      if (hres) hres[i] = __builtin_nan("");
+      if (nsteps) nsteps[i] = 0;
+    }
+  }
+  unsigned int sl = wave_append(T.ctr + C_N0, enter);
+  if (enter) put_slot(T, (int)sl, x, v, kind, i, s, o.h0);
+}
+
+// persistent transit integrator
+template <bool MIXED>
+__global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int pass, int refill) {
+  unsigned int n0 = 0, n;
+  const int *qin = nullptr;
+  if (pass == 0) {
+    n0 = T.ctr[C_N0];
+    n = n0 + T.ctr[C_N1];
+  } else {
+    n = T.ctr[C_QN + pass];
+    qin = (pass & 1) ? T.q0 : T.q1;
+  }
+  unsigned int *fetch = T.ctr + C_FETCH + pass;
+  const double a = c.a;
+  const double band2 = (c.a + o.band) * (c.a + o.band);
+  int slot = -1;
+  bool exhausted = false, after_reject = false;
+  double x[3], v[3], A1[3], h = 0.0, t = 0.0;
+  int ns = 0, kind = 0;
+
+  for (;;) {
+    bool need = slot < 0 && !exhausted;
+    unsigned long long m = __ballot(need);
+    if (m != 0ull) {
+      int leader = __ffsll((unsigned long long)m) - 1;
+      unsigned int cnt = (unsigned int)__popcll(m);
+      unsigned int base = 0;
+      if ((int)__lane_id() == leader) base = atomicAdd(fetch, cnt);
+      base = __shfl(base, leader);
+      if (base + cnt >= n) exhausted = true;
+      if (need) {
+        unsigned int idx = base + (unsigned int)__popcll(m & lanemask_lt());
+        if (idx < n) {
+          slot = slot_of(T, pass, idx, n0, qin);
+          load_state(T, slot, x, v);
+          t = T.t[slot];
+          h = T.h[slot];
+          ns = T.nsteps[slot];
+          kind = T.kind[slot];
+          after_reject = false;
+          accel_k<MIXED>(kind, a, band2, x, v, A1);
+        }
+      }
+    }
+    if (__ballot(slot >= 0) == 0ull) break;
+
+    for (int it = 0; it < refill; ++it) {
+      if (slot >= 0) {
+        int stop = -1;  // final status of this ray, if it stops in this step
+        if (ns >= o.max_steps) {
+          stop = RT_RAY_MAXSTEPS;
+        } else {
+          ++ns;
+          double xn[3], vn[3], hs = h;
+          bool acc = true;
+          if (o.scheme == RT_SCHEME_RK4) {
+            switch (kind) {
+              case K_RE: rk4_step<K_RE, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
+              case K_AO: rk4_step<K_AO, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
+              case K_AE: rk4_step<K_AE, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
+              default: rk4_step<K_RO, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
+            }
+          } else {
+            double A[7][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) A[0][i] = A1[i];
+            double sum;
+            switch (kind) {
+              case K_RE: sum = dp45_attempt<K_RE, MIXED>(a, band2, x, v, A, h, o.rtol, o.atol, xn, vn); break;
+              case K_AO: sum = dp45_attempt<K_AO, MIXED>(a, band2, x, v, A, h, o.rtol, o.atol, xn, vn); break;
+              case K_AE: sum = dp45_attempt<K_AE, MIXED>(a, band2, x, v, A, h, o.rtol, o.atol, xn, vn); break;
+              default: sum = dp45_attempt<K_RO, MIXED>(a, band2, x, v, A, h, o.rtol, o.atol, xn, vn); break;
+            }
+            if (!(sum <= 6.0)) {
+              h *= dp45_factor(sum, false);
+              after_reject = true;
+              acc = false;
+              if (!(h >= 1e-12)) stop = RT_RAY_DIVERGED;
+            } else {
+              h = fmin(h * dp45_factor(sum, after_reject), o.hmax);
+              after_reject = false;
+#pragma unroll
+              for (int i = 0; i < 3; ++i) A1[i] = A[6][i];
+            }
+          }
+          if (acc) {
+            if (!finite6(xn, vn)) {
+              stop = RT_RAY_DIVERGED;
+            } else if (!inside_open(c, xn)) {
+              stop = ST_EVENT;
+              h = hs;  // the event kernel re-takes the crossing step from x
+            } else {
+#pragma unroll
+              for (int i = 0; i < 3; ++i) { x[i] = xn[i]; v[i] = vn[i]; }
+              t += hs;
+              if (o.scheme == RT_SCHEME_RK4) accel_k<MIXED>(kind, a, band2, x, v, A1);
+            }
+          }
+        }
+        if (stop >= 0) {
+          store_state(T, slot, x, v);
+          T.t[slot] = t;
+          T.h[slot] = h;
+          T.nsteps[slot] = ns;
+          T.status[slot] = stop;
+          slot = -1;
+        }
+      }
+    }
+  }
+}
+
+// boundary crossing of one step: safeguarded Newton on the step length
+template <bool MIXED>
+__device__ double crossing(const CloakP &c, const OptsP &o, int kind, int id, double band2,
+                           const double x[3], const double v[3], const double A1[3], double h,
+                           double phi_h, double xs[3], double vs[3]) {
+  const double tol = 1e-13 * c.b;
+  double lo = 0.0, hi = h;
+  double flo = fmin(gval(c, id, x), -1e-300), fhi = phi_h;
+  double hs = lo + (hi - lo) * (-flo) / (fhi - flo);
+  if (!(hs > lo && hs < hi)) hs = 0.5 * (lo + hi);
+  for (int it = 0; it < 100; ++it) {
+    step_map<MIXED>(kind, o.scheme, c.a, band2, x, v, A1, hs, xs, vs);
+    double f = gval(c, id, xs);
+    if (fabs(f) <= tol) return hs;
+    if (f < 0.0) { lo = hs; flo = f; } else { hi = hs; fhi = f; }
+    double dfdh;
+    if (id == B_TOP) dfdh = vs[2];
+    else if (id == B_BOTTOM) dfdh = -vs[2];
+    else {
+      double vr = (xs[0] * vs[0] + xs[1] * vs[1]) * rsq64(fma(xs[0], xs[0], xs[1] * xs[1]));
+      dfdh = id == B_SIDE ? vr : -vr;
+    }
+    double hn = hs - f / dfdh;
+    if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
+    if (!(hi > lo) || hn == hs) return hs;
+    hs = hn;
+  }
+  return hs;
+}
+
+template <bool MIXED>
+__global__ void __launch_bounds__(256) k_event(CloakP c, OptsP o, Table T, int pass) {
+  unsigned int n0 = 0, n;
+  const int *qin = nullptr;
+  if (pass == 0) {
+    n0 = T.ctr[C_N0];
+    n = n0 + T.ctr[C_N1];
+  } else {
+    n = T.ctr[C_QN + pass];
+    qin = (pass & 1) ? T.q0 : T.q1;
+  }
+  int *qout = (pass & 1) ? T.q1 : T.q0;
+  unsigned int *qcount = T.ctr + C_QN + pass + 1;
+  const double band2 = (c.a + o.band) * (c.a + o.band);
+  unsigned int stride = gridDim.x * blockDim.x;
+  unsigned int n_round = (n + 63u) & ~63u;  // whole waves for the append ballot
+  for (unsigned int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n_round; idx += stride) {
+    bool requeue = false;
+    int slot = -1;
+    if (idx < n) {
+      slot = slot_of(T, pass, idx, n0, qin);
+      if (T.status[slot] == ST_EVENT) {
+        double x[3], v[3], A1[3], xn[3], vn[3];
+        load_state(T, slot, x, v);
+        double h = T.h[slot], t = T.t[slot];
+        int kind = T.kind[slot], bounces = T.bounces[slot];
+        accel_k<MIXED>(kind, c.a, band2, x, v, A1);
+        step_map<MIXED>(kind, o.scheme, c.a, band2, x, v, A1, h, xn, vn);
+        int best = -1;
+        double hb = h;
+        double xb[3], vb[3];
+        for (int id = 0; id < 4; ++id) {
+          double g = gval(c, id, xn);
+          if (g >= 0.0) {
+            double xs[3], vs[3];
+            double hc = crossing<MIXED>(c, o, kind, id, band2, x, v, A1, h, g, xs, vs);
+            if (best < 0 || hc < hb) {
+              best = id; hb = hc;
+#pragma unroll
+              for (int i = 0; i < 3; ++i) { xb[i] = xs[i]; vb[i] = vs[i]; }
+            }
+          }
+        }
+        int st;
+        double hr = __builtin_nan("");
+        if (best < 0) {
+          // no constraint violated by the re-taken step: keep integrating
+#pragma unroll
+          for (int i = 0; i < 3; ++i) { xb[i] = xn[i]; vb[i] = vn[i]; }
+          t += h;
+          st = ST_ACTIVE;
+          requeue = true;
+        } else {
+          t += hb;
+          if (best == B_INNER) {
+            if (c.mirror && c.axis == RT_AXIS_RADIAL && bounces < o.max_bounces) {
+              reflect_inside(B_INNER, xb, vb);
+              ++bounces;
+              st = ST_ACTIVE;
+              requeue = true;
+            } else {
+              st = RT_RAY_ABSORBED;
+            }
+          } else {
+            double d[3];
+            if (refract_out(c, kind, best, xb, vb, d, hr)) {
+              st = RT_RAY_EXITED;
+#pragma unroll
+              for (int i = 0; i < 3; ++i) vb[i] = d[i];
+            } else if (bounces < o.max_bounces) {
+              reflect_inside(best, xb, vb);
+              ++bounces;
+              st = ST_ACTIVE;
+              requeue = true;
+            } else {
+              st = RT_RAY_TIR;
+            }
+          }
+        }
+        store_state(T, slot, xb, vb);
+        T.t[slot] = t;
+        T.h[slot] = o.h0;
+        T.bounces[slot] = bounces;
+        T.status[slot] = st;
+        T.hres[slot] = hr;
+      }
+    }
+    unsigned int qi = wave_append(qcount, requeue);
+    if (requeue) qout[qi] = slot;
+  }
+}
+
+// rt_trace_batch finish: vacuum leg of the entered rays to r_out
+__global__ void __launch_bounds__(256) k_tb_finish(CloakP c, OptsP o, Table T, long long n,
+                                                   double *__restrict__ out6, double *__restrict__ opl,
+                                                   int *__restrict__ status, double *__restrict__ hres,
+                                                   int *__restrict__ nsteps) {
+  unsigned int n0 = T.ctr[C_N0];
+  unsigned int stride = gridDim.x * blockDim.x;
+  for (unsigned int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n0; idx += stride) {
+    int s = (int)idx;
+    long long i = T.key[s];
+    double x[3], v[3];
+    load_state(T, s, x, v);
+    int st = T.status[s];
+    int kind = T.kind[s];
+    double L = T.opl0[s] + T.t[s];
+    double hr = T.hres[s];
+    if (st == RT_RAY_EXITED) {
+      double sl = leave_radius(x, v, o.r_out);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) x[j] = fma(sl, v[j], x[j]);
+      L += sl;
+    } else {
+      hr = hamiltonian_res(c, kind, x, v);
+      double w = rsq64(fma(v[0], v[0], fma(v[1], v[1], v[2] * v[2])));
+#pragma unroll
+      for (int j = 0; j < 3; ++j) v[j] *= w;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { out6[j * n + i] = x[j]; out6[(3 + j) * n + i] = v[j]; }
+    opl[i] = L;
+    status[i] = st;
+    if (hres) hres[i] = hr;
+    if (nsteps) nsteps[i] = T.nsteps[s];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// render kernels
+// ---------------------------------------------------------------------------
+struct RenderP {
+  long long g0, g1;   // chunk of the flattened (camera, pixel, sample) index
+  long long ns_img;   // samples per image = w*h*spp
+  int npol, pol0, pol1, spp;
+  int has_cloak, pad;
+  unsigned char *codes;  // chunk-local codes [npol][g1-g0]
+  double *rec;           // aux (may be NULL)
+  int *st;
+  unsigned char *code;
+  int *nsteps;
+};
+
+__device__ __forceinline__ void rd_write(const RenderP &R, int pi, long long gidx, int code,
+                                         int st, const double p[3], const double d[3], double L,
+                                         int nsteps) {
+  R.codes[(long long)pi * (R.g1 - R.g0) + (gidx - R.g0)] = (unsigned char)code;
+  long long cam = gidx / R.ns_img, loc = gidx - cam * R.ns_img;
+  long long img = cam * R.npol + pi;
+  if (R.st) R.st[img * R.ns_img + loc] = st;
+  if (R.code) R.code[img * R.ns_img + loc] = (unsigned char)code;
+  if (R.nsteps) R.nsteps[img * R.ns_img + loc] = nsteps;
+  if (R.rec) {
+    double *r = R.rec + img * 7 * R.ns_img + loc;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { r[j * R.ns_img] = p[j]; r[(3 + j) * R.ns_img] = d[j]; }
+    r[6 * R.ns_img] = L;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
+                                                const CamP *__restrict__ cams, Table T, RenderP R) {
+  long long gidx = R.g0 + (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  bool valid = gidx < R.g1;
+  double org[3] = {0, 0, 0}, d[3] = {0, 0, 1}, x[3] = {0, 0, 0}, s = 0.0;
+  int surf = 0;
+  bool hitc = false, disk = false;
+  if (valid) {
+    long long cam = gidx / R.ns_img, loc = gidx - cam * R.ns_img;
+    long long pix = loc / R.spp;
+    int smp = (int)(loc - pix * R.spp);
+    const CamP &C = cams[cam];
+    org[0] = C.eye[0]; org[1] = C.eye[1]; org[2] = C.eye[2];
+    camera_ray(C, (int)cam, pix, smp, d);
+    if (R.has_cloak) hitc = vacuum_entry(c, org, d, s, surf);
+    if (hitc) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) x[j] = fma(s, d[j], org[j]);
+      if (surf == B_TOP) x[2] = c.z1;
+      if (surf == B_BOTTOM) x[2] = c.z0;
+      disk = surf != B_SIDE && fma(x[0], x[0], x[1] * x[1]) <= c.a2;
+    }
+  }
+  for (int pi = 0; pi < R.npol; ++pi) {
+    int kind = c.axis * 2 + (pi == 0 ? R.pol0 : R.pol1);
+    bool enter = false;
+    double v[3] = {0, 0, 0};
+    if (valid) {
+      int st = RT_RAY_MISSED;
+      double p[3] = {org[0], org[1], org[2]}, dd[3] = {d[0], d[1], d[2]}, L = 0.0;
+      if (hitc) {
+        double nrm[3];
+        boundary_normal(surf, x, nrm);
+        if (disk) {
+          p[0] = x[0]; p[1] = x[1]; p[2] = x[2];
+          L = s;
+          if (c.mirror) { reflect3(dd, nrm); st = RT_RAY_REFLECTED; }
+          else st = RT_RAY_ABSORBED;
+        } else if (refract_in(c, kind, surf, x, d, v)) {
+          enter = true;
+        } else {
+          p[0] = x[0]; p[1] = x[1]; p[2] = x[2];
+          L = s;
+          reflect3(dd, nrm);
+          st = RT_RAY_REFLECTED;
+        }
+      }
+      if (!enter) {
+        int code = 12;
+        if (st != RT_RAY_ABSORBED) {
+          double sh;
+          code = room_code(rm, p, dd, sh);
+          L += sh;
+        }
+        rd_write(R, pi, gidx, code, st, p, dd, L, 0);
+      }
+    }
+    unsigned int sl = wave_append(T.ctr + C_N0 + pi, enter);
+    if (enter) put_slot(T, (int)(pi * T.cap + sl), x, v, kind, gidx, s, o.h0);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_rd_finish(CloakP c, RoomP rm, Table T, RenderP R) {
+  unsigned int n0 = T.ctr[C_N0], n = n0 + T.ctr[C_N1];
+  unsigned int stride = gridDim.x * blockDim.x;
+  for (unsigned int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
+    int pi = idx < n0 ? 0 : 1;
+    int s = (int)(idx < n0 ? idx : T.cap + (idx - n0));
+    double x[3], v[3];
+    load_state(T, s, x, v);
+    int st = T.status[s];
+    double L = T.opl0[s] + T.t[s];
+    int code = 12;
+    if (st == RT_RAY_EXITED) {
+      double sh;
+      code = room_code(rm, x, v, sh);
+      L += sh;
+    } else {
+      double w = rsq64(fma(v[0], v[0], fma(v[1], v[1], v[2] * v[2])));
+#pragma unroll
+      for (int j = 0; j < 3; ++j) v[j] *= w;
+    }
+    rd_write(R, pi, T.key[s], code, st, x, v, L, T.nsteps[s]);
+  }
+}
+
+// per-pixel mean colour; the 13-entry colour table is staged in LDS
+__global__ void __launch_bounds__(256) k_rd_resolve(RenderP R, const float *__restrict__ table39,
+                                                    float *__restrict__ rgb, long long npix) {
+  __shared__ float tab[39];
+  if (threadIdx.x < 39) tab[threadIdx.x] = table39[threadIdx.x];
+  __syncthreads();
+  long long chunk = R.g1 - R.g0;
+  long long pix_in_chunk = chunk / R.spp;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pix_in_chunk * R.npol) return;
+  int pi = (int)(i / pix_in_chunk);
+  long long lp = i - pi * pix_in_chunk;
+  const unsigned char *cd = R.codes + pi * chunk + lp * R.spp;
+  float r = 0.f, g = 0.f, b = 0.f;
+  for (int k = 0; k < R.spp; ++k) {
+    int cc = cd[k];
+    r += tab[3 * cc];
+    g += tab[3 * cc + 1];
+    b += tab[3 * cc + 2];
+  }
+  float inv = 1.0f / (float)R.spp;
+  long long gpix = R.g0 / R.spp + lp;  // flattened (camera, pixel)
+  long long cam = gpix / npix, pix = gpix - cam * npix;
+  float *o = rgb + ((cam * R.npol + pi) * npix + pix) * 3;
+  o[0] = r * inv;
+  o[1] = g * inv;
+  o[2] = b * inv;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct Workspace {
+  void *base = nullptr;
+  size_t bytes = 0;
+  long long cap = 0;
+  Table T{};
+  unsigned char *codes = nullptr;
+  long long codes_len = 0;
+  CamP *cams = nullptr;
+  int cams_cap = 0;
+  float *table = nullptr;
+  int device = -1;
+};
+
+std::mutex g_ws_mu;
+Workspace g_ws;
+int g_num_cu = 0;
+
+// integrator timing (rt_profile_*): event pairs around every transit launch
+struct ProfEvent {
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfEvent> g_prof;
+
+void prof_begin(hipStream_t s, ProfEvent &pe, bool &on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  on = g_prof_on;
+  if (!on) return;
+  if (hipEventCreate(&pe.a) != hipSuccess || hipEventCreate(&pe.b) != hipSuccess) {
+    on = false;
+    return;
+  }
+  (void)hipEventRecord(pe.a, s);
+}
+
+void prof_end(hipStream_t s, ProfEvent &pe, bool on) {
+  if (!on) return;
+  (void)hipEventRecord(pe.b, s);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.push_back(pe);
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Ensure the workspace holds two segments of `cap` slots, `codes_len` code
+// bytes and `ncam` camera records. Caller holds g_ws_mu.
+int ensure_workspace(long long cap, long long codes_len, int ncam) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(RT_E_DEVICE, "hipGetDevice failed");
+  if (g_ws.base && g_ws.device == dev && g_ws.cap >= cap && g_ws.codes_len >= codes_len &&
+      g_ws.cams_cap >= ncam)
+    return RT_OK;
+  cap = std::max(cap, g_ws.device == dev ? g_ws.cap : 0LL);
+  codes_len = std::max(codes_len, g_ws.device == dev ? g_ws.codes_len : 0LL);
+  ncam = std::max(ncam, g_ws.device == dev ? g_ws.cams_cap : 0);
+  cap = std::max(cap, 1024LL);
+  codes_len = std::max(codes_len, 1024LL);
+  ncam = std::max(ncam, 16);
+  if (g_ws.base) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g_ws.base);
+    g_ws.base = nullptr;
+  }
+  long long ns = 2 * cap;
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t o = off; off = align_up(off + b); return o; };
+  size_t o_d = take(sizeof(double) * 10 * ns);
+  size_t o_i = take(sizeof(int) * 4 * ns);
+  size_t o_k = take(sizeof(long long) * ns);
+  size_t o_q = take(sizeof(int) * 2 * ns);
+  size_t o_c = take(sizeof(unsigned int) * C_COUNT);
+  size_t o_codes = take((size_t)codes_len);
+  size_t o_cams = take(sizeof(CamP) * ncam);
+  size_t o_tab = take(sizeof(float) * 64);
+  void *p = nullptr;
+  if (hipMalloc(&p, off) != hipSuccess) {
+    (void)hipGetLastError();
+    g_ws = Workspace{};
+    return fail(RT_E_NOMEM, "hipMalloc of %zu bytes for the workspace failed", off);
+  }
+  char *b = (char *)p;
+  Table &T = g_ws.T;
+  double *D = (double *)(b + o_d);
+  T.px = D; T.py = D + ns; T.pz = D + 2 * ns; T.vx = D + 3 * ns; T.vy = D + 4 * ns; T.vz = D + 5 * ns;
+  T.t = D + 6 * ns; T.h = D + 7 * ns; T.opl0 = D + 8 * ns; T.hres = D + 9 * ns;
+  int *I = (int *)(b + o_i);
+  T.nsteps = I; T.bounces = I + ns; T.status = I + 2 * ns; T.kind = I + 3 * ns;
+  T.key = (long long *)(b + o_k);
+  T.q0 = (int *)(b + o_q);
+  T.q1 = T.q0 + ns;
+  T.ctr = (unsigned int *)(b + o_c);
+  T.cap = cap;
+  g_ws.base = p;
+  g_ws.bytes = off;
+  g_ws.cap = cap;
+  g_ws.codes = (unsigned char *)(b + o_codes);
+  g_ws.codes_len = codes_len;
+  g_ws.cams = (CamP *)(b + o_cams);
+  g_ws.cams_cap = ncam;
+  g_ws.table = (float *)(b + o_tab);
+  g_ws.device = dev;
+  return RT_OK;
+}
+
+int num_cu() {
+  if (g_num_cu == 0) {
+    int dev = 0, n = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    g_num_cu = n;
+  }
+  return g_num_cu;
+}
+
+int check_desc(const rt_cloak_desc *d) {
+  if (!d) return fail(RT_E_INVALID, "cloak description is NULL");
+  if (!(d->r1 > 0.0) || !(d->r2 > d->r1) || !std::isfinite(d->r2))
+    return fail(RT_E_INVALID, "need 0 < r1 < r2 < inf (got r1=%g r2=%g)", d->r1, d->r2);
+  if (!(d->z1 > d->z0)) return fail(RT_E_INVALID, "need z0 < z1 (got %g, %g)", d->z0, d->z1);
+  if (d->axis != RT_AXIS_RADIAL && d->axis != RT_AXIS_AZIMUTHAL)
+    return fail(RT_E_INVALID, "axis must be RT_AXIS_RADIAL or RT_AXIS_AZIMUTHAL (got %d)", d->axis);
+  if (d->inner_mirror != 0 && d->inner_mirror != 1)
+    return fail(RT_E_INVALID, "inner_mirror must be 0 or 1");
+  return RT_OK;
+}
+
+CloakP make_cloak(const rt_cloak_desc &d) {
+  CloakP c;
+  c.a = d.r1; c.b = d.r2; c.z0 = d.z0; c.z1 = d.z1;
+  double q = d.r2 / (d.r2 - d.r1);
+  c.kappa = q * q;
+  c.a2 = d.r1 * d.r1; c.b2 = d.r2 * d.r2;
+  c.axis = d.axis; c.mirror = d.inner_mirror;
+  return c;
+}
+
+int check_opts(const rt_trace_opts *o, double r2, bool need_rout) {
+  if (!o) return fail(RT_E_INVALID, "options are NULL");
+  if (o->scheme != RT_SCHEME_RK4 && o->scheme != RT_SCHEME_DP45)
+    return fail(RT_E_INVALID, "scheme must be RT_SCHEME_RK4 or RT_SCHEME_DP45");
+  if (o->precision != RT_PREC_FP64 && o->precision != RT_PREC_MIXED)
+    return fail(RT_E_INVALID, "precision must be RT_PREC_FP64 or RT_PREC_MIXED");
+  if (!(o->h > 0.0) || !std::isfinite(o->h)) return fail(RT_E_INVALID, "h must be > 0");
+  if (o->scheme == RT_SCHEME_DP45) {
+    if (!(o->rtol > 0.0) || !(o->atol > 0.0)) return fail(RT_E_INVALID, "rtol and atol must be > 0");
+    if (!(o->hmax >= o->h)) return fail(RT_E_INVALID, "hmax must be >= h");
+  }
+  if (o->precision == RT_PREC_MIXED && !(o->fp64_band >= 0.0))
+    return fail(RT_E_INVALID, "fp64_band must be >= 0");
+  if (need_rout && !(o->r_out >= r2)) return fail(RT_E_INVALID, "r_out (%g) must be >= r2 (%g)", o->r_out, r2);
+  if (o->max_steps < 1) return fail(RT_E_INVALID, "max_steps must be >= 1");
+  if (o->max_bounces < 0 || o->max_bounces >= MAX_PASSES)
+    return fail(RT_E_INVALID, "max_bounces must be in [0, %d)", MAX_PASSES);
+  if (o->block != 0 && (o->block < 64 || o->block > 256 || o->block % 64))
+    return fail(RT_E_INVALID, "block must be 0 or a multiple of 64 in [64, 256]");
+  if (o->refill_period < 0 || o->refill_period > 1024)
+    return fail(RT_E_INVALID, "refill_period must be in [0, 1024]");
+  return RT_OK;
+}
+
+OptsP make_opts(const rt_trace_opts &o) {
+  OptsP p;
+  p.h0 = o.h; p.rtol = o.rtol; p.atol = o.atol; p.hmax = o.scheme == RT_SCHEME_DP45 ? o.hmax : o.h;
+  p.band = o.precision == RT_PREC_MIXED ? o.fp64_band : 0.0;
+  p.r_out = o.r_out;
+  p.max_steps = o.max_steps;
+  p.scheme = o.scheme; p.precision = o.precision; p.max_bounces = o.max_bounces; p.pad = 0;
+  return p;
+}
+
+int launch_err(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return RT_OK;
+}
+
+unsigned int grid_for(long long n, int block) {
+  long long g = (n + block - 1) / block;
+  return (unsigned int)std::max(1LL, g);
+}
+
+// transit + event passes over the slots already placed in the table
+template <bool MIXED>
+int run_passes(const CloakP &c, const OptsP &o, const Table &T, int block, int refill,
+               hipStream_t s) {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_transit<MIXED>, block, 0) != hipSuccess ||
+      occ <= 0)
+    occ = 1;
+  unsigned int grid = (unsigned int)(num_cu() * occ);
+  int passes = o.max_bounces + 1;
+  for (int p = 0; p < passes; ++p) {
+    ProfEvent pe;
+    bool on;
+    prof_begin(s, pe, on);
+    hipLaunchKernelGGL(k_transit<MIXED>, dim3(grid), dim3(block), 0, s, c, o, T, p, refill);
+    prof_end(s, pe, on);
+    hipLaunchKernelGGL(k_event<MIXED>, dim3(num_cu() * 8), dim3(256), 0, s, c, o, T, p);
+  }
+  return launch_err("transit/event launch");
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *rt_last_error(void) { return g_err.c_str(); }
+
+int rt_build_cloak(const rt_cloak_desc *desc, rt_cloak *out) {
+  if (!out) return fail(RT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int e = check_desc(desc);
+  if (e) return e;
+  rt_cloak h = new (std::nothrow) rt_cloak_s;
+  if (!h) return fail(RT_E_NOMEM, "host allocation failed");
+  h->d = *desc;
+  *out = h;
+  return RT_OK;
+}
+
+int rt_free_cloak(rt_cloak cloak) {
+  delete cloak;
+  return RT_OK;
+}
+
+int rt_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return RT_OK;
+}
+
+int rt_profile_read(double *transit_ms, int64_t *launches) {
+  if (!transit_ms || !launches) return fail(RT_E_INVALID, "outputs are NULL");
+  std::vector<ProfEvent> ev;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    ev.swap(g_prof);
+  }
+  double tot = 0.0;
+  int err = RT_OK;
+  for (auto &pe : ev) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pe.b) != hipSuccess || hipEventElapsedTime(&ms, pe.a, pe.b) != hipSuccess)
+      err = fail(RT_E_DEVICE, "event timing failed");
+    tot += ms;
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  *transit_ms = tot;
+  *launches = (int64_t)ev.size();
+  return err;
+}
+
+int rt_release_workspace(void) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  if (g_ws.base) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g_ws.base);
+  }
+  g_ws = Workspace{};
+  return RT_OK;
+}
+
+int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64_t n,
+                   const double *in6, double *out6, double *opl, int32_t *status, double *hres,
+                   int32_t *nsteps, void *stream) {
+  if (!cloak) return fail(RT_E_INVALID, "cloak handle is NULL");
+  int e = check_opts(opts, cloak->d.r2, true);
+  if (e) return e;
+  if (pol != RT_POL_ORDINARY && pol != RT_POL_EXTRAORDINARY)
+    return fail(RT_E_INVALID, "pol must be RT_POL_ORDINARY or RT_POL_EXTRAORDINARY");
+  if (n < 0) return fail(RT_E_INVALID, "n must be >= 0");
+  if (n == 0) return RT_OK;
+  if (n > (1LL << 30)) return fail(RT_E_INVALID, "n must be <= 2^30 per call");
+  if (!in6 || !out6 || !opl || !status) return fail(RT_E_INVALID, "in6, out6, opl and status are required");
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  e = ensure_workspace(n, 0, 0);
+  if (e) return e;
+  const Table &T = g_ws.T;
+  CloakP c = make_cloak(cloak->d);
+  OptsP o = make_opts(*opts);
+  int block = opts->block ? opts->block : 256;
+  int refill = opts->refill_period ? opts->refill_period : 1;
+  int kind = c.axis * 2 + pol;
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, T.ctr, (int)C_COUNT);
+  hipLaunchKernelGGL(k_tb_entry, dim3(grid_for(n, 256)), dim3(256), 0, s, c, o, T, kind, (long long)n,
+                     in6, out6, opl, status, hres, nsteps);
+  e = launch_err("entry launch");
+  if (e) return e;
+  e = o.precision == RT_PREC_MIXED ? run_passes<true>(c, o, T, block, refill, s)
+                                   : run_passes<false>(c, o, T, block, refill, s);
+  if (e) return e;
+  hipLaunchKernelGGL(k_tb_finish, dim3(num_cu() * 8), dim3(256), 0, s, c, o, T, (long long)n, out6,
+                     opl, status, hres, nsteps);
+  return launch_err("finish launch");
+}
+
+int rt_render(rt_cloak cloak, const rt_trace_opts *opts, const rt_room *room, const rt_camera *cams,
+              int32_t n_cams, int32_t pol_mask, float *rgb, const rt_render_aux *aux, void *stream) {
+  double r2 = cloak ? cloak->d.r2 : 0.0;
+  int e = check_opts(opts, r2, false);
+  if (e) return e;
+  if (!room || !cams || !rgb) return fail(RT_E_INVALID, "room, cams and rgb are required");
+  if (n_cams < 1) return fail(RT_E_INVALID, "n_cams must be >= 1");
+  if (pol_mask < 1 || pol_mask > 3) return fail(RT_E_INVALID, "pol_mask must be 1, 2 or 3");
+  if (!(room->tile > 0.0)) return fail(RT_E_INVALID, "room tile must be > 0");
+  for (int k = 0; k < 3; ++k)
+    if (!(room->hi[k] > room->lo[k])) return fail(RT_E_INVALID, "room needs lo < hi");
+  const int w = cams[0].w, h = cams[0].h, spp = cams[0].spp;
+  int m = (int)std::lround(std::sqrt((double)spp));
+  if (w < 1 || h < 1 || spp < 1 || m * m != spp || spp > 256)
+    return fail(RT_E_INVALID, "camera needs w, h >= 1 and spp a perfect square <= 256");
+  for (int k = 1; k < n_cams; ++k)
+    if (cams[k].w != w || cams[k].h != h || cams[k].spp != spp)
+      return fail(RT_E_INVALID, "all cameras must share w, h and spp");
+  const long long npix = (long long)w * h;
+  const long long ns_img = npix * spp;
+  if (ns_img > (1LL << 30)) return fail(RT_E_INVALID, "w*h*spp must be <= 2^30");
+  int npol = (pol_mask == 3) ? 2 : 1;
+  int pol0 = (pol_mask & 1) ? RT_POL_ORDINARY : RT_POL_EXTRAORDINARY;
+  int pol1 = RT_POL_EXTRAORDINARY;
+
+  // host-side camera bases
+  CamP *hc = new (std::nothrow) CamP[n_cams];
+  if (!hc) return fail(RT_E_NOMEM, "host allocation failed");
+  for (int k = 0; k < n_cams; ++k) {
+    const rt_camera &C = cams[k];
+    double F[3], R[3], U[3];
+    for (int j = 0; j < 3; ++j) F[j] = C.look[j] - C.eye[j];
+    double fl = std::sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
+    R[0] = F[1] * C.up[2] - F[2] * C.up[1];
+    R[1] = F[2] * C.up[0] - F[0] * C.up[2];
+    R[2] = F[0] * C.up[1] - F[1] * C.up[0];
+    if (!(fl > 0.0) || !(C.fov_deg > 0.0 && C.fov_deg < 180.0)) {
+      delete[] hc;
+      return fail(RT_E_INVALID, "camera %d: eye == look or fov outside (0, 180)", k);
+    }
+    for (int j = 0; j < 3; ++j) F[j] /= fl;
+    R[0] = F[1] * C.up[2] - F[2] * C.up[1];
+    R[1] = F[2] * C.up[0] - F[0] * C.up[2];
+    R[2] = F[0] * C.up[1] - F[1] * C.up[0];
+    double rl = std::sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+    if (!(rl > 0.0)) {
+      delete[] hc;
+      return fail(RT_E_INVALID, "camera %d: up is parallel to the view direction", k);
+    }
+    for (int j = 0; j < 3; ++j) R[j] /= rl;
+    U[0] = R[1] * F[2] - R[2] * F[1];
+    U[1] = R[2] * F[0] - R[0] * F[2];
+    U[2] = R[0] * F[1] - R[1] * F[0];
+    CamP &P = hc[k];
+    for (int j = 0; j < 3; ++j) { P.eye[j] = C.eye[j]; P.F[j] = F[j]; P.R[j] = R[j]; P.U[j] = U[j]; }
+    P.tan_half = std::tan(0.5 * C.fov_deg * M_PI / 180.0);
+    P.aspect = (double)w / (double)h;
+    P.w = w; P.h = h; P.spp = spp; P.m = m;
+    P.seed = C.seed;
+  }
+  CloakP c{};
+  if (cloak) c = make_cloak(cloak->d);
+  OptsP o = make_opts(*opts);
+  RoomP rm;
+  for (int j = 0; j < 3; ++j) { rm.lo[j] = room->lo[j]; rm.hi[j] = room->hi[j]; }
+  rm.tile = room->tile;
+  rm.inv_tile = 1.0 / room->tile;
+  float table[64] = {0};
+  for (int f = 0; f < 6; ++f)
+    for (int q = 0; q < 2; ++q)
+      for (int j = 0; j < 3; ++j) table[(f * 2 + q) * 3 + j] = room->rgb[f][q][j];
+
+  hipStream_t s = (hipStream_t)stream;
+  const long long total = ns_img * n_cams;
+  const long long chunk_max = (1LL << 24) / spp * spp;
+  const long long chunk = std::min(total, std::max(chunk_max, (long long)spp));
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  e = ensure_workspace(chunk, chunk * npol, n_cams);
+  if (e) { delete[] hc; return e; }
+  (void)hipMemcpyAsync(g_ws.cams, hc, sizeof(CamP) * n_cams, hipMemcpyHostToDevice, s);
+  (void)hipMemcpyAsync(g_ws.table, table, sizeof(float) * 39, hipMemcpyHostToDevice, s);
+  // the copies read host memory asynchronously: wait before freeing it
+  (void)hipStreamSynchronize(s);
+  delete[] hc;
+  const Table &T = g_ws.T;
+  int block = opts->block ? opts->block : 256;
+  int refill = opts->refill_period ? opts->refill_period : 1;
+  RenderP R;
+  R.ns_img = ns_img; R.npol = npol; R.pol0 = pol0; R.pol1 = pol1; R.spp = spp;
+  R.has_cloak = cloak ? 1 : 0; R.pad = 0;
+  R.codes = g_ws.codes;
+  R.rec = aux ? aux->rec : nullptr;
+  R.st = aux ? aux->status : nullptr;
+  R.code = aux ? aux->code : nullptr;
+  R.nsteps = aux ? aux->nsteps : nullptr;
+  for (long long g0 = 0; g0 < total; g0 += chunk) {
+    R.g0 = g0;
+    R.g1 = std::min(total, g0 + chunk);
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, T.ctr, (int)C_COUNT);
+    hipLaunchKernelGGL(k_rd_gen, dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, c, o, rm,
+                       g_ws.cams, T, R);
+    e = launch_err("render generate launch");
+    if (e) return e;
+    if (cloak) {
+      e = o.precision == RT_PREC_MIXED ? run_passes<true>(c, o, T, block, refill, s)
+                                       : run_passes<false>(c, o, T, block, refill, s);
+      if (e) return e;
+      hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, c, rm, T, R);
+    }
+    long long nres = (R.g1 - R.g0) / spp * npol;
+    hipLaunchKernelGGL(k_rd_resolve, dim3(grid_for(nres, 256)), dim3(256), 0, s, R, g_ws.table, rgb,
+                       npix);
+    e = launch_err("render finish launch");
+    if (e) return e;
+  }
+  return RT_OK;
+}
+
+}  // extern "C"

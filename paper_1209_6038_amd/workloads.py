@@ -149,3 +149,9 @@ def surrogate_entries(n: int, seed: int, height: float = HEIGHT) -> np.ndarray:
     out[:, 2] = rng.uniform(-0.5 * math.pi, 0.5 * math.pi, n)
     out[:, 3] = rng.uniform(-0.5 * math.pi, 0.5 * math.pi, n)
     return out
+
+
+def render_opts(precision: int = 0, **kw) -> dict:
+    """Integration options of the 3-D render workload: Dormand-Prince 5(4) at
+    tolerance 1e-8, FP64 band 0.05 next to the inner radius in mixed mode."""
+    return opts_dp45(1e-8, precision=precision, fp64_band=0.05, **kw)

@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI (no GPU needed, no compute calls)."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_1209_6038_amd import build as B
+from paper_1209_6038_amd import rt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rt.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if B.is_stale():
+        B.build()
+    return rt.lib()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("rt_build_cloak", "rt_trace_batch", "rt_render", "rt_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", rt.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s+(rt_\w+)", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in declared_functions():
+        assert hasattr(lib, n)
+
+
+def test_struct_layouts_match_header():
+    """Compile the header with gcc and compare sizeof/offsetof with ctypes."""
+    fields = {
+        "rt_cloak_desc": (rt.CloakDesc, ["r1", "z0", "axis", "inner_mirror"]),
+        "rt_trace_opts": (rt.TraceOpts, ["scheme", "h", "fp64_band", "r_out", "max_steps",
+                                         "max_bounces", "refill_period"]),
+        "rt_camera": (rt.Camera, ["eye", "fov_deg", "w", "spp", "seed"]),
+        "rt_room": (rt.Room, ["lo", "tile", "rgb"]),
+        "rt_render_aux": (rt.RenderAux, ["rec", "status", "code", "nsteps"]),
+    }
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void){"]
+    for s, (_, fs) in fields.items():
+        lines.append(f'printf("{s} %zu\\n", sizeof({s}));')
+        for f in fs:
+            lines.append(f'printf("{s}.{f} %zu\\n", offsetof({s}, {f}));')
+    lines.append("return 0;}")
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write("\n".join(lines))
+        subprocess.run(["gcc", "-std=c11", "-o", exe, c], check=True)
+        got = dict(l.split() for l in subprocess.run([exe], capture_output=True, text=True,
+                                                     check=True).stdout.splitlines())
+    for s, (cls, fs) in fields.items():
+        assert int(got[s]) == ctypes.sizeof(cls), s
+        for f in fs:
+            assert int(got[f"{s}.{f}"]) == getattr(cls, f).offset, f"{s}.{f}"
+
+
+def test_argument_validation_needs_no_gpu(lib):
+    """Invalid descriptions are rejected synchronously before any device use."""
+    h = ctypes.c_void_p()
+    bad = rt.CloakDesc(2.0, 1.0, -1e300, 1e300, 0, 1)
+    assert lib.rt_build_cloak(ctypes.byref(bad), ctypes.byref(h)) == rt.RT_E_INVALID
+    assert b"r1 < r2" in lib.rt_last_error()
+    bad = rt.CloakDesc(1.0, 2.0, 0.0, 4.0, 7, 1)
+    assert lib.rt_build_cloak(ctypes.byref(bad), ctypes.byref(h)) == rt.RT_E_INVALID
+    good = rt.CloakDesc(1.0, 2.0, 0.0, 4.0, 1, 1)
+    assert lib.rt_build_cloak(ctypes.byref(good), ctypes.byref(h)) == rt.RT_OK
+    o = rt.trace_opts({"scheme": 1, "h": 1e-2, "hmax": 1e-3})
+    assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 10, None, None, None, None, None, None,
+                              None) == rt.RT_E_INVALID
+    o = rt.trace_opts({"scheme": 0, "h": 1e-3, "r_out": 1.5})
+    assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 10, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None) == rt.RT_E_INVALID
+    assert b"r_out" in lib.rt_last_error()
+    o = rt.trace_opts({"scheme": 0, "h": 1e-3})
+    assert lib.rt_trace_batch(h, ctypes.byref(o), 5, 10, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None) == rt.RT_E_INVALID
+    assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 0, None, None, None, None, None, None,
+                              None) == rt.RT_OK  # n = 0 is a no-op
+    assert lib.rt_free_cloak(h) == rt.RT_OK
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The package never imports, links or loads the oracle."""
+    pkg = os.path.join(ROOT, "paper_1209_6038_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "cloak_oracle" not in txt, f

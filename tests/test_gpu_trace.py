@@ -1,0 +1,115 @@
+"""GPU parity of rt_trace_batch against the FP64 oracle (through the C ABI)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1209_6038_amd import workloads as W
+from tests.gpu_helpers import check_trace, gpu_trace, say
+
+pytestmark = pytest.mark.gpu
+
+RESOLVED_H = 5e-8  # |H-1| above which fixed-step RK4 has not resolved a ray
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("branch", [0, 1])
+def test_inplane_rk4_parity(axis, branch):
+    """2-D bundles at 8 angles, RK4 h = 1e-3, FP64 (the in-plane workload)."""
+    rays = W.inplane_bundle(64, 8)
+    c = W.cloak(axis)
+    op = W.opts_rk4()
+    say(f"case inplane rk4 axis={axis} branch={branch} n={rays.shape[1]}")
+    g = gpu_trace(c, op, branch, rays)
+    o = oracle.trace(c, op, branch, rays)
+    resolved = ~(o["hres"] > RESOLVED_H)
+    say(f"  unresolved by RK4: {(~resolved).sum()}")
+    check_trace(g, o, mask=resolved, opl_tol=2e-6, label=f"inplane a{axis} b{branch}")
+    assert (g["nsteps"][resolved] == o["nsteps"][resolved]).all()
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("branch", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_3d_dp45_parity(axis, branch, precision):
+    """Random 3-D rays against the finite cloak (z in [0, 4], caps, metal end
+    disk), Dormand-Prince 5(4) at 1e-8, FP64 or mixed precision."""
+    rays = W.random_rays(1024, seed=100 + 10 * axis + branch, z_range=(-1.0, 5.0))
+    c = W.cloak(axis, height=W.HEIGHT)
+    op = W.opts_dp45(precision=precision, fp64_band=0.05)
+    say(f"case 3d dp45 axis={axis} branch={branch} precision={precision}")
+    g = gpu_trace(c, op, branch, rays)
+    o = oracle.trace(c, W.opts_dp45(), branch, rays)
+    say(f"  status counts oracle {np.bincount(o['status'], minlength=8)}")
+    check_trace(g, o, opl_tol=2e-6, label=f"3d a{axis} b{branch} p{precision}")
+
+
+def test_inplane_full_size_sampled():
+    """The full in-plane workload (16384 impact parameters x 8 angles, radial
+    cloak, extraordinary rays, RK4 h = 1e-3) on the GPU; 256 sampled rays
+    re-traced by the oracle."""
+    rays = W.inplane_bundle(16384, 8)
+    c = W.cloak(0)
+    op = W.opts_rk4()
+    say("case inplane full size")
+    g = gpu_trace(c, op, 1, rays)
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(rays.shape[1], 256, replace=False))
+    o = oracle.trace(c, op, 1, rays[:, idx])
+    gs = {k: v[..., idx] for k, v in g.items()}
+    resolved = ~(o["hres"] > RESOLVED_H)
+    check_trace(gs, o, mask=resolved, label="inplane full sampled")
+    # exact cloaking of resolved rays (Sect. 4): exits on the incident line
+    p = rays[0] * (-rays[4]) + rays[1] * rays[3]
+    hit = (np.abs(p) < 1.9) & (np.abs(p) > 0.3)
+    assert (g["status"][hit] == 0).all()
+    want = rays[:3, hit] + 2.0 * np.sqrt(9.0 - p[hit] ** 2) * rays[3:, hit]
+    assert np.abs(g["out"][:3, hit] - want).max() < 3e-9
+
+
+def test_edge_cases():
+    """Invalid inputs, misses, metal end disk, step limit, bounce limit, n = 1."""
+    c = W.cloak(0, height=4.0)
+    rays = np.array([
+        [0.5, np.nan, 5.0, 5.0, 0.3, 5.0, 3.0],
+        [0.0, 0.0, 5.0, 5.0, 0.2, 0.3, 0.1],
+        [1.0, 1.0, 1.0, 1.0, 8.0, 1.0, 2.0],
+        [1.0, 1.0, 0.0, 0.0, 0.0, -1.0, -1.0],
+        [0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.02],
+        [0.0, 0.0, 0.0, 0.0, -1.0, 0.0, 0.0],
+    ])
+    for op in (W.opts_dp45(), W.opts_rk4(), W.opts_dp45(max_steps=1), W.opts_rk4(max_steps=5),
+               W.opts_dp45(max_bounces=0)):
+        for branch in (0, 1):
+            say(f"case edge {op['scheme']} {op['max_steps']} {op['max_bounces']} b{branch}")
+            g = gpu_trace(c, op, branch, rays)
+            o = oracle.trace(c, op, branch, rays)
+            check_trace(g, o, label="edge")
+    one = rays[:, 2:3].copy()
+    g = gpu_trace(c, W.opts_dp45(), 1, one)
+    o = oracle.trace(c, W.opts_dp45(), 1, one)
+    check_trace(g, o, label="n=1")
+
+
+def test_empty_batch_is_noop():
+    import torch
+    from paper_1209_6038_amd import rt
+    cl = rt.Cloak(W.cloak(0))
+    r = rt.trace_batch(cl, W.opts_rk4(), 1, torch.empty((6, 0), dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    assert r["out"].shape == (6, 0)
+
+
+def test_scheduling_does_not_change_results():
+    """Per-ray results are independent of the launch shape (block size,
+    refill period) and bitwise reproducible."""
+    rays = W.random_rays(2048, seed=7, z_range=(0.0, 4.0))
+    c = W.cloak(1, height=4.0)
+    base = gpu_trace(c, W.opts_dp45(), 1, rays)
+    for kw in ({"block": 64, "refill_period": 1}, {"block": 128, "refill_period": 4},
+               {"block": 256, "refill_period": 16}, {}):
+        say(f"case scheduling {kw}")
+        g = gpu_trace(c, W.opts_dp45(**kw), 1, rays)
+        for k in base:
+            np.testing.assert_array_equal(np.nan_to_num(g[k], nan=-7.0), np.nan_to_num(base[k], nan=-7.0))
