@@ -75,7 +75,7 @@ typedef struct {
    r - r1 >= fp64_band, FP64 state and step combination everywhere).
    r_out: report radius of rt_trace_batch (>= r2). max_steps: step attempts per
    ray. max_bounces: internal reflections (inner mirror, total internal
-   reflection) per ray. block / refill_period: integrator launch shape
+   reflection) per ray, 0..64. block / refill_period: integrator launch shape
    (threads per block, steps between refills of finished lanes; 0 = library
    default). */
 typedef struct {

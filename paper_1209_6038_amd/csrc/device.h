@@ -279,7 +279,7 @@ __device__ __forceinline__ double dp45_attempt(double a, double band2, const dou
     ev *= h;
     double sx = fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol);
     double sv = fma(rtol, fmax(fabs(v[i]), fabs(vn[i])), atol);
-    double qx = ex / sx, qv = ev / sv;
+    double qx = ex * rcp64(sx), qv = ev * rcp64(sv);
     sum = fma(qx, qx, fma(qv, qv, sum));
   }
   return sum;
@@ -336,32 +336,6 @@ __device__ __forceinline__ void accel_k(int kind, double a, double band2, const 
     case K_AO: accel<K_AO, MIXED>(a, band2, x[0], x[1], v[0], v[1], v[2], A[0], A[1], A[2]); break;
     case K_AE: accel<K_AE, MIXED>(a, band2, x[0], x[1], v[0], v[1], v[2], A[0], A[1], A[2]); break;
     default: A[0] = 0.0; A[1] = 0.0; A[2] = 0.0; break;
-  }
-}
-
-// single-step map of the active scheme (for boundary root finding)
-template <bool MIXED>
-__device__ __forceinline__ void step_map(int kind, int scheme, double a, double band2,
-                                         const double x[3], const double v[3],
-                                         const double A1[3], double h, double xn[3],
-                                         double vn[3]) {
-  if (scheme == 0) {
-    switch (kind) {
-      case K_RE: rk4_step<K_RE, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
-      case K_AO: rk4_step<K_AO, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
-      case K_AE: rk4_step<K_AE, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
-      default: rk4_step<K_RO, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
-    }
-  } else {
-    double A[7][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) A[0][i] = A1[i];
-    switch (kind) {
-      case K_RE: dp45_attempt<K_RE, MIXED>(a, band2, x, v, A, h, 1.0, 1.0, xn, vn); break;
-      case K_AO: dp45_attempt<K_AO, MIXED>(a, band2, x, v, A, h, 1.0, 1.0, xn, vn); break;
-      case K_AE: dp45_attempt<K_AE, MIXED>(a, band2, x, v, A, h, 1.0, 1.0, xn, vn); break;
-      default: dp45_attempt<K_RO, MIXED>(a, band2, x, v, A, h, 1.0, 1.0, xn, vn); break;
-    }
   }
 }
 

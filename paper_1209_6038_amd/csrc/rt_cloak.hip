@@ -4,17 +4,13 @@
 //   1. entry kernel   vacuum ray -> cloak intersection -> Sect. 3 refraction;
 //                     rays that miss (or reflect at the entry) are finished
 //                     here, rays that enter get a slot in the work table,
-//                     grouped by branch
-//   2. transit pass   persistent integrator: one ray per lane, state in
-//                     registers; lanes whose ray stops are refilled from the
-//                     pass queue with a wave-aggregated atomic every
-//                     `refill_period` steps; a ray stops when a step ends
-//                     outside the material (event), or on the step limit
-//   3. event kernel   root-find of the step length that lands on the
-//                     boundary, then exit refraction (Sect. 3), same-mode
-//                     total internal reflection, or the inner metal mirror
-//                     (Sect. 4); reflected rays go to the next pass queue
-//   (2-3 repeat max_bounces + 1 times)
+//                     grouped by branch, with a difficulty key
+//   2. sort           counting sort of the slots, hardest rays first
+//   3. integrator     persistent kernel: one ray per lane, FP64 state in
+//                     registers, refilled from the queue in wave-private
+//                     chunks every `refill_period` steps; boundary crossings,
+//                     exit refraction, total internal reflection and the
+//                     inner metal mirror are handled in line (k_transit)
 //   4. finish kernel  vacuum leg to r_out (trace) or to the room (render)
 //   5. resolve        (render) per-pixel mean of the sample colours
 #include <hip/hip_runtime.h>
@@ -43,18 +39,23 @@ namespace {
 enum {
   C_N0 = 0,       // slots in segment 0
   C_N1 = 1,       // slots in segment 1
-  C_QN = 2,       // C_QN + p: entries of the queue read by pass p (p >= 1)
-  C_FETCH = 20,   // C_FETCH + p: work counter of transit pass p
-  C_COUNT = 40
+  C_FETCH = 2,    // work counter of the integrator
+  C_HIST = 40,    // NBIN bins: slots per (difficulty, kind) key
+  C_OFF = 104,    // NBIN bins: scatter offsets of the keys
+  C_COUNT = 168
 };
-constexpr int MAX_PASSES = 16;
+constexpr int NBUCKET = 16;           // difficulty buckets
+constexpr int NBIN = NBUCKET * 4;     // x 4 branch kinds
+constexpr int MAX_BOUNCES = 64;
+constexpr unsigned int FETCH_CHUNK = 64;  // rays claimed per wave per atomic
 
 struct Table {
   double *px, *py, *pz, *vx, *vy, *vz;
   double *t, *h, *opl0, *hres;
   int *nsteps, *bounces, *status, *kind;
   long long *key;
-  int *q0, *q1;
+  int *order;   // integrator queue: slots sorted hardest first
+  int *key0;    // sort key of each slot
   unsigned int *ctr;
   long long cap;  // capacity of one segment; segment 1 starts at cap
 };
@@ -96,10 +97,26 @@ __device__ __forceinline__ bool finite6(const double x[3], const double v[3]) {
          isfinite(v[1]) && isfinite(v[2]);
 }
 
-__device__ __forceinline__ int slot_of(const Table &T, int pass, unsigned int idx, unsigned int n0,
-                                       const int *qin) {
-  if (pass == 0) return idx < n0 ? (int)idx : (int)(T.cap + (idx - n0));
-  return qin[idx];
+__device__ __forceinline__ int seg_slot(const Table &T, unsigned int idx, unsigned int n0) {
+  return idx < n0 ? (int)idx : (int)(T.cap + (idx - n0));
+}
+
+// Sort key of an entering ray: rays whose conserved angular momentum p_theta
+// (and axial wave number p_z, for the branches whose metric is singular in
+// both) is small pass close to r = a, where the adaptive step shrinks; they
+// take the most steps and are integrated first so that a launch ends on
+// short rays. key = (NBUCKET-1 - bucket) * 4 + kind, bucket = -log2(p).
+__device__ __forceinline__ int sort_key(const CloakP &c, int kind, const double x[3],
+                                        const double d[3]) {
+  int bucket = 0;
+  if (kind != K_RO) {
+    double pth = fabs(x[0] * d[1] - x[1] * d[0]) / c.b;
+    double p = kind == K_AE ? pth : sqrt(fma(pth, pth, d[2] * d[2]));
+    int e = 0;
+    (void)frexp(p, &e);  // p = f 2^e, f in [0.5, 1)
+    bucket = min(max(1 - e, 0), NBUCKET - 1);
+  }
+  return (NBUCKET - 1 - bucket) * 4 + kind;
 }
 
 __device__ __forceinline__ void load_state(const Table &T, int s, double x[3], double v[3]) {
@@ -114,8 +131,9 @@ __device__ __forceinline__ void store_state(const Table &T, int s, const double 
 }
 
 __device__ __forceinline__ void put_slot(const Table &T, int s, const double x[3], const double v[3],
-                                         int kind, long long key, double opl0, double h0) {
+                                         int kind, long long key, double opl0, double h0, int skey) {
   store_state(T, s, x, v);
+  T.key0[s] = skey;
   T.t[s] = 0.0;
   T.h[s] = h0;
   T.opl0[s] = opl0;
@@ -144,6 +162,7 @@ __global__ void __launch_bounds__(256) k_tb_entry(CloakP c, OptsP o, Table T, in
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   bool enter = false;
   double x[3], v[3], s = 0.0;
+  int skey = 0;
   if (i < n) {
     double org[3], d[3];
 #pragma unroll
@@ -176,6 +195,7 @@ __global__ void __launch_bounds__(256) k_tb_entry(CloakP c, OptsP o, Table T, in
           else st = RT_RAY_ABSORBED;
         } else if (refract_in(c, kind, surf, x, d, v)) {
           enter = true;
+          skey = sort_key(c, kind, x, d);
         } else {
           p[0] = x[0]; p[1] = x[1]; p[2] = x[2];
           L = s;
@@ -200,240 +220,270 @@ __global__ void __launch_bounds__(256) k_tb_entry(CloakP c, OptsP o, Table T, in
     }
   }
   unsigned int sl = wave_append(T.ctr + C_N0, enter);
-  if (enter) put_slot(T, (int)sl, x, v, kind, i, s, o.h0);
+  if (enter) put_slot(T, (int)sl, x, v, kind, i, s, o.h0, skey);
 }
 
-// persistent transit integrator
-template <bool MIXED>
-__global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int pass, int refill) {
-  unsigned int n0 = 0, n;
-  const int *qin = nullptr;
-  if (pass == 0) {
-    n0 = T.ctr[C_N0];
-    n = n0 + T.ctr[C_N1];
-  } else {
-    n = T.ctr[C_QN + pass];
-    qin = (pass & 1) ? T.q0 : T.q1;
+// counting sort of the entered slots by key (LDS-privatized histogram,
+// single-wave scan, block-reserved scatter)
+__global__ void __launch_bounds__(256) k_sort_hist(Table T) {
+  __shared__ unsigned int lh[NBIN];
+  for (int i = threadIdx.x; i < NBIN; i += blockDim.x) lh[i] = 0;
+  __syncthreads();
+  unsigned int n0 = T.ctr[C_N0], n = n0 + T.ctr[C_N1];
+  unsigned int stride = gridDim.x * blockDim.x;
+  for (unsigned int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride)
+    atomicAdd(&lh[T.key0[seg_slot(T, idx, n0)]], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < NBIN; i += blockDim.x)
+    if (lh[i]) atomicAdd(&T.ctr[C_HIST + i], lh[i]);
+}
+
+__global__ void k_sort_scan(Table T) {
+  if (threadIdx.x == 0) {
+    unsigned int acc = 0;
+    for (int i = 0; i < NBIN; ++i) {
+      T.ctr[C_OFF + i] = acc;
+      acc += T.ctr[C_HIST + i];
+    }
   }
-  unsigned int *fetch = T.ctr + C_FETCH + pass;
-  const double a = c.a;
+}
+
+__global__ void __launch_bounds__(256) k_sort_scatter(Table T) {
+  __shared__ unsigned int lc[NBIN], lb[NBIN];
+  unsigned int n0 = T.ctr[C_N0], n = n0 + T.ctr[C_N1];
+  unsigned int stride = gridDim.x * blockDim.x;
+  unsigned int rounds = (n + stride - 1) / stride;
+  for (unsigned int r = 0; r < rounds; ++r) {
+    for (int i = threadIdx.x; i < NBIN; i += blockDim.x) lc[i] = 0;
+    __syncthreads();
+    unsigned int idx = r * stride + blockIdx.x * blockDim.x + threadIdx.x;
+    int slot = -1, key = 0;
+    unsigned int local = 0;
+    if (idx < n) {
+      slot = seg_slot(T, idx, n0);
+      key = T.key0[slot];
+      local = atomicAdd(&lc[key], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NBIN; i += blockDim.x)
+      lb[i] = lc[i] ? atomicAdd(&T.ctr[C_OFF + i], lc[i]) : 0u;
+    __syncthreads();
+    if (slot >= 0) T.order[lb[key] + local] = slot;
+    __syncthreads();
+  }
+}
+
+// d g / d h of boundary `id` along the end velocity of a trial step
+__device__ __forceinline__ double gslope(int id, const double xs[3], const double vs[3]) {
+  if (id == B_TOP) return vs[2];
+  if (id == B_BOTTOM) return -vs[2];
+  double vr = (xs[0] * vs[0] + xs[1] * vs[1]) * rsq64(fma(xs[0], xs[0], xs[1] * xs[1]));
+  return id == B_SIDE ? vr : -vr;
+}
+
+// integrator state of one lane (lives in registers)
+struct Lane {
+  double x[3], v[3], A1[3];  // base state and its acceleration
+  double h, t;               // next step length, optical path so far
+  double lo, hi, ht;         // boundary search: bracket and trial length
+  int ns, bounces, rid, riter;
+  bool after_reject;
+};
+
+// One iteration of a lane of branch KIND: one attempt of the scheme from the
+// base state, then either the step controller (stepping) or one safeguarded
+// Newton update of the crossing length (rid >= 0: locating the crossing of
+// boundary rid). Returns the final status when the ray stops, else -1.
+template <int KIND, bool MIXED>
+__device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o, double band2,
+                                       double tol, double &hr) {
+  if (L.rid < 0 && L.ns >= o.max_steps) return RT_RAY_MAXSTEPS;
+  const double hs = L.rid < 0 ? L.h : L.ht;
+  double xn[3], vn[3];
+  double A[7][3];
+  double sum = 0.0;
+  if (o.scheme == RT_SCHEME_RK4) {
+    rk4_step<KIND, MIXED>(c.a, band2, L.x, L.v, L.A1, hs, xn, vn);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) A[0][i] = L.A1[i];
+    sum = dp45_attempt<KIND, MIXED>(c.a, band2, L.x, L.v, A, hs, o.rtol, o.atol, xn, vn);
+  }
+  if (L.rid < 0) {
+    // ---- stepping ----
+    ++L.ns;
+    if (o.scheme == RT_SCHEME_DP45) {
+      if (!(sum <= 6.0)) {
+        L.h *= dp45_factor(sum, false);
+        L.after_reject = true;
+        return (L.h >= 1e-12) ? -1 : RT_RAY_DIVERGED;
+      }
+      L.h = fmin(L.h * dp45_factor(sum, L.after_reject), o.hmax);
+      L.after_reject = false;
+    }
+    if (!finite6(xn, vn)) return RT_RAY_DIVERGED;
+    if (inside_open(c, xn)) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) { L.x[i] = xn[i]; L.v[i] = vn[i]; }
+      L.t += hs;
+      if (o.scheme == RT_SCHEME_RK4) {
+        accel<KIND, MIXED>(c.a, band2, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) L.A1[i] = A[6][i];
+      }
+      return -1;
+    }
+    // the step left the material: search the earliest crossing, starting
+    // from the boundary with the smallest linearly interpolated fraction
+    double best = 2.0;
+    int rid = B_SIDE;
+#pragma unroll
+    for (int id = 0; id < 4; ++id) {
+      double g1 = gval(c, id, xn);
+      if (g1 >= 0.0) {
+        double g0 = fmin(gval(c, id, L.x), -1e-300);
+        double fr = -g0 / (g1 - g0);
+        if (fr < best) { best = fr; rid = id; }
+      }
+    }
+    L.rid = rid;
+    L.lo = 0.0;
+    L.hi = hs;
+    L.ht = hs * fmin(fmax(best, 1e-3), 1.0 - 1e-3);
+    L.riter = 0;
+    return -1;
+  }
+  // ---- locating the crossing of boundary rid ----
+  if (!finite6(xn, vn)) return RT_RAY_DIVERGED;
+  double f = gval(c, L.rid, xn);
+  ++L.riter;
+  if (!(fabs(f) <= tol || L.riter >= 100 || !(L.hi - L.lo > 1e-300))) {
+    if (f < 0.0) L.lo = L.ht; else L.hi = L.ht;
+    double hn = L.ht - f / gslope(L.rid, xn, vn);
+    if (!(hn > L.lo && hn < L.hi)) hn = 0.5 * (L.lo + L.hi);
+    L.ht = hn;
+    return -1;
+  }
+  // an earlier crossing of another boundary takes precedence
+  int other = -1;
+#pragma unroll
+  for (int id = 0; id < 4; ++id)
+    if (id != L.rid && gval(c, id, xn) > tol) other = id;
+  if (other >= 0) {
+    L.rid = other;
+    L.lo = 0.0;
+    L.hi = L.ht;
+    L.ht = 0.5 * L.ht;
+    L.riter = 0;
+    return -1;
+  }
+  // the ray is on boundary rid at (xn, vn)
+  L.t += L.ht;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { L.x[i] = xn[i]; L.v[i] = vn[i]; }
+  const int rid = L.rid;
+  L.rid = -1;
+  if (rid == B_INNER) {
+    if (!(c.mirror && c.axis == RT_AXIS_RADIAL && L.bounces < o.max_bounces)) return RT_RAY_ABSORBED;
+    reflect_inside(B_INNER, L.x, L.v);
+  } else {
+    double d[3];
+    if (refract_out(c, KIND, rid, L.x, L.v, d, hr)) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) L.v[i] = d[i];
+      return RT_RAY_EXITED;
+    }
+    if (L.bounces >= o.max_bounces) return RT_RAY_TIR;
+    reflect_inside(rid, L.x, L.v);
+  }
+  // continue from the boundary point after the reflection
+  ++L.bounces;
+  L.h = o.h0;
+  L.after_reject = false;
+  accel<KIND, MIXED>(c.a, band2, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
+  return -1;
+}
+
+// Persistent integrator with in-line boundary events.
+// Every iteration each active lane makes one attempt of the scheme from its
+// base state (x, v). A lane is either stepping (accept/reject by the error
+// controller) or locating a boundary crossing: after an accepted step that
+// ends outside the material, the step is re-taken from the same base state
+// with lengths chosen by a safeguarded Newton iteration on the boundary
+// function g until |g| <= 1e-13 b. The crossing then goes through the
+// interface: exit refraction (the ray stops), same-mode total internal
+// reflection or the inner metal mirror (the ray continues from the boundary
+// point with the step controller restarted). Only this bookkeeping diverges;
+// the attempt itself is the same code for every lane of a branch.
+template <bool MIXED>
+__global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int refill) {
+  const unsigned int n = T.ctr[C_N0] + T.ctr[C_N1];
+  unsigned int *fetch = T.ctr + C_FETCH;
   const double band2 = (c.a + o.band) * (c.a + o.band);
-  int slot = -1;
-  bool exhausted = false, after_reject = false;
-  double x[3], v[3], A1[3], h = 0.0, t = 0.0;
-  int ns = 0, kind = 0;
+  const double tol = 1e-13 * c.b;
+  int slot = -1, kind = 0;
+  Lane L;
+  L.h = 0.0; L.t = 0.0; L.lo = 0.0; L.hi = 0.0; L.ht = 0.0;
+  L.ns = 0; L.bounces = 0; L.rid = -1; L.riter = 0; L.after_reject = false;
+  // wave-private chunk [cur, end) of the queue, refilled with one atomic per
+  // FETCH_CHUNK rays; cur, end and drained are wave-uniform
+  unsigned int cur = 0, end = 0;
+  bool drained = false;
 
   for (;;) {
-    bool need = slot < 0 && !exhausted;
-    unsigned long long m = __ballot(need);
-    if (m != 0ull) {
-      int leader = __ffsll((unsigned long long)m) - 1;
-      unsigned int cnt = (unsigned int)__popcll(m);
-      unsigned int base = 0;
-      if ((int)__lane_id() == leader) base = atomicAdd(fetch, cnt);
-      base = __shfl(base, leader);
-      if (base + cnt >= n) exhausted = true;
-      if (need) {
-        unsigned int idx = base + (unsigned int)__popcll(m & lanemask_lt());
-        if (idx < n) {
-          slot = slot_of(T, pass, idx, n0, qin);
-          load_state(T, slot, x, v);
-          t = T.t[slot];
-          h = T.h[slot];
-          ns = T.nsteps[slot];
-          kind = T.kind[slot];
-          after_reject = false;
-          accel_k<MIXED>(kind, a, band2, x, v, A1);
-        }
+    for (int round = 0; round < 2; ++round) {
+      bool need = slot < 0;
+      unsigned long long m = __ballot(need);
+      if (m == 0ull) break;
+      if (cur >= end) {
+        if (drained) break;
+        unsigned int base = 0;
+        if (__lane_id() == 0) base = atomicAdd(fetch, FETCH_CHUNK);
+        base = __shfl(base, 0);
+        cur = base;
+        end = min(base + FETCH_CHUNK, n);
+        if (base + FETCH_CHUNK >= n) drained = true;
+        if (cur >= end) break;
       }
+      unsigned int idx = cur + (unsigned int)__popcll(m & lanemask_lt());
+      if (need && idx < end) {
+        slot = T.order[idx];
+        load_state(T, slot, L.x, L.v);
+        L.t = T.t[slot];
+        L.h = T.h[slot];
+        L.ns = T.nsteps[slot];
+        L.bounces = T.bounces[slot];
+        kind = T.kind[slot];
+        L.after_reject = false;
+        L.rid = -1;
+        accel_k<MIXED>(kind, c.a, band2, L.x, L.v, L.A1);
+      }
+      cur = min(cur + (unsigned int)__popcll(m), end);
     }
     if (__ballot(slot >= 0) == 0ull) break;
 
     for (int it = 0; it < refill; ++it) {
       if (slot >= 0) {
-        int stop = -1;  // final status of this ray, if it stops in this step
-        if (ns >= o.max_steps) {
-          stop = RT_RAY_MAXSTEPS;
-        } else {
-          ++ns;
-          double xn[3], vn[3], hs = h;
-          bool acc = true;
-          if (o.scheme == RT_SCHEME_RK4) {
-            switch (kind) {
-              case K_RE: rk4_step<K_RE, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
-              case K_AO: rk4_step<K_AO, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
-              case K_AE: rk4_step<K_AE, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
-              default: rk4_step<K_RO, MIXED>(a, band2, x, v, A1, h, xn, vn); break;
-            }
-          } else {
-            double A[7][3];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) A[0][i] = A1[i];
-            double sum;
-            switch (kind) {
-              case K_RE: sum = dp45_attempt<K_RE, MIXED>(a, band2, x, v, A, h, o.rtol, o.atol, xn, vn); break;
-              case K_AO: sum = dp45_attempt<K_AO, MIXED>(a, band2, x, v, A, h, o.rtol, o.atol, xn, vn); break;
-              case K_AE: sum = dp45_attempt<K_AE, MIXED>(a, band2, x, v, A, h, o.rtol, o.atol, xn, vn); break;
-              default: sum = dp45_attempt<K_RO, MIXED>(a, band2, x, v, A, h, o.rtol, o.atol, xn, vn); break;
-            }
-            if (!(sum <= 6.0)) {
-              h *= dp45_factor(sum, false);
-              after_reject = true;
-              acc = false;
-              if (!(h >= 1e-12)) stop = RT_RAY_DIVERGED;
-            } else {
-              h = fmin(h * dp45_factor(sum, after_reject), o.hmax);
-              after_reject = false;
-#pragma unroll
-              for (int i = 0; i < 3; ++i) A1[i] = A[6][i];
-            }
-          }
-          if (acc) {
-            if (!finite6(xn, vn)) {
-              stop = RT_RAY_DIVERGED;
-            } else if (!inside_open(c, xn)) {
-              stop = ST_EVENT;
-              h = hs;  // the event kernel re-takes the crossing step from x
-            } else {
-#pragma unroll
-              for (int i = 0; i < 3; ++i) { x[i] = xn[i]; v[i] = vn[i]; }
-              t += hs;
-              if (o.scheme == RT_SCHEME_RK4) accel_k<MIXED>(kind, a, band2, x, v, A1);
-            }
-          }
+        double hr = __builtin_nan("");
+        int stop;
+        switch (kind) {
+          case K_RE: stop = iterate<K_RE, MIXED>(L, c, o, band2, tol, hr); break;
+          case K_AO: stop = iterate<K_AO, MIXED>(L, c, o, band2, tol, hr); break;
+          case K_AE: stop = iterate<K_AE, MIXED>(L, c, o, band2, tol, hr); break;
+          default: stop = iterate<K_RO, MIXED>(L, c, o, band2, tol, hr); break;
         }
         if (stop >= 0) {
-          store_state(T, slot, x, v);
-          T.t[slot] = t;
-          T.h[slot] = h;
-          T.nsteps[slot] = ns;
+          store_state(T, slot, L.x, L.v);
+          T.t[slot] = L.t;
+          T.nsteps[slot] = L.ns;
+          T.bounces[slot] = L.bounces;
           T.status[slot] = stop;
+          T.hres[slot] = hr;
           slot = -1;
         }
       }
     }
-  }
-}
-
-// boundary crossing of one step: safeguarded Newton on the step length
-template <bool MIXED>
-__device__ double crossing(const CloakP &c, const OptsP &o, int kind, int id, double band2,
-                           const double x[3], const double v[3], const double A1[3], double h,
-                           double phi_h, double xs[3], double vs[3]) {
-  const double tol = 1e-13 * c.b;
-  double lo = 0.0, hi = h;
-  double flo = fmin(gval(c, id, x), -1e-300), fhi = phi_h;
-  double hs = lo + (hi - lo) * (-flo) / (fhi - flo);
-  if (!(hs > lo && hs < hi)) hs = 0.5 * (lo + hi);
-  for (int it = 0; it < 100; ++it) {
-    step_map<MIXED>(kind, o.scheme, c.a, band2, x, v, A1, hs, xs, vs);
-    double f = gval(c, id, xs);
-    if (fabs(f) <= tol) return hs;
-    if (f < 0.0) { lo = hs; flo = f; } else { hi = hs; fhi = f; }
-    double dfdh;
-    if (id == B_TOP) dfdh = vs[2];
-    else if (id == B_BOTTOM) dfdh = -vs[2];
-    else {
-      double vr = (xs[0] * vs[0] + xs[1] * vs[1]) * rsq64(fma(xs[0], xs[0], xs[1] * xs[1]));
-      dfdh = id == B_SIDE ? vr : -vr;
-    }
-    double hn = hs - f / dfdh;
-    if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
-    if (!(hi > lo) || hn == hs) return hs;
-    hs = hn;
-  }
-  return hs;
-}
-
-template <bool MIXED>
-__global__ void __launch_bounds__(256) k_event(CloakP c, OptsP o, Table T, int pass) {
-  unsigned int n0 = 0, n;
-  const int *qin = nullptr;
-  if (pass == 0) {
-    n0 = T.ctr[C_N0];
-    n = n0 + T.ctr[C_N1];
-  } else {
-    n = T.ctr[C_QN + pass];
-    qin = (pass & 1) ? T.q0 : T.q1;
-  }
-  int *qout = (pass & 1) ? T.q1 : T.q0;
-  unsigned int *qcount = T.ctr + C_QN + pass + 1;
-  const double band2 = (c.a + o.band) * (c.a + o.band);
-  unsigned int stride = gridDim.x * blockDim.x;
-  unsigned int n_round = (n + 63u) & ~63u;  // whole waves for the append ballot
-  for (unsigned int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n_round; idx += stride) {
-    bool requeue = false;
-    int slot = -1;
-    if (idx < n) {
-      slot = slot_of(T, pass, idx, n0, qin);
-      if (T.status[slot] == ST_EVENT) {
-        double x[3], v[3], A1[3], xn[3], vn[3];
-        load_state(T, slot, x, v);
-        double h = T.h[slot], t = T.t[slot];
-        int kind = T.kind[slot], bounces = T.bounces[slot];
-        accel_k<MIXED>(kind, c.a, band2, x, v, A1);
-        step_map<MIXED>(kind, o.scheme, c.a, band2, x, v, A1, h, xn, vn);
-        int best = -1;
-        double hb = h;
-        double xb[3], vb[3];
-        for (int id = 0; id < 4; ++id) {
-          double g = gval(c, id, xn);
-          if (g >= 0.0) {
-            double xs[3], vs[3];
-            double hc = crossing<MIXED>(c, o, kind, id, band2, x, v, A1, h, g, xs, vs);
-            if (best < 0 || hc < hb) {
-              best = id; hb = hc;
-#pragma unroll
-              for (int i = 0; i < 3; ++i) { xb[i] = xs[i]; vb[i] = vs[i]; }
-            }
-          }
-        }
-        int st;
-        double hr = __builtin_nan("");
-        if (best < 0) {
-          // no constraint violated by the re-taken step: keep integrating
-#pragma unroll
-          for (int i = 0; i < 3; ++i) { xb[i] = xn[i]; vb[i] = vn[i]; }
-          t += h;
-          st = ST_ACTIVE;
-          requeue = true;
-        } else {
-          t += hb;
-          if (best == B_INNER) {
-            if (c.mirror && c.axis == RT_AXIS_RADIAL && bounces < o.max_bounces) {
-              reflect_inside(B_INNER, xb, vb);
-              ++bounces;
-              st = ST_ACTIVE;
-              requeue = true;
-            } else {
-              st = RT_RAY_ABSORBED;
-            }
-          } else {
-            double d[3];
-            if (refract_out(c, kind, best, xb, vb, d, hr)) {
-              st = RT_RAY_EXITED;
-#pragma unroll
-              for (int i = 0; i < 3; ++i) vb[i] = d[i];
-            } else if (bounces < o.max_bounces) {
-              reflect_inside(best, xb, vb);
-              ++bounces;
-              st = ST_ACTIVE;
-              requeue = true;
-            } else {
-              st = RT_RAY_TIR;
-            }
-          }
-        }
-        store_state(T, slot, xb, vb);
-        T.t[slot] = t;
-        T.h[slot] = o.h0;
-        T.bounces[slot] = bounces;
-        T.status[slot] = st;
-        T.hres[slot] = hr;
-      }
-    }
-    unsigned int qi = wave_append(qcount, requeue);
-    if (requeue) qout[qi] = slot;
   }
 }
 
@@ -563,7 +613,7 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
       }
     }
     unsigned int sl = wave_append(T.ctr + C_N0 + pi, enter);
-    if (enter) put_slot(T, (int)(pi * T.cap + sl), x, v, kind, gidx, s, o.h0);
+    if (enter) put_slot(T, (int)(pi * T.cap + sl), x, v, kind, gidx, s, o.h0, sort_key(c, kind, x, d));
   }
 }
 
@@ -712,8 +762,8 @@ int ensure_workspace(long long cap, long long codes_len, int ncam) {
   int *I = (int *)(b + o_i);
   T.nsteps = I; T.bounces = I + ns; T.status = I + 2 * ns; T.kind = I + 3 * ns;
   T.key = (long long *)(b + o_k);
-  T.q0 = (int *)(b + o_q);
-  T.q1 = T.q0 + ns;
+  T.order = (int *)(b + o_q);
+  T.key0 = T.order + ns;
   T.ctr = (unsigned int *)(b + o_c);
   T.cap = cap;
   g_ws.base = p;
@@ -776,8 +826,8 @@ int check_opts(const rt_trace_opts *o, double r2, bool need_rout) {
     return fail(RT_E_INVALID, "fp64_band must be >= 0");
   if (need_rout && !(o->r_out >= r2)) return fail(RT_E_INVALID, "r_out (%g) must be >= r2 (%g)", o->r_out, r2);
   if (o->max_steps < 1) return fail(RT_E_INVALID, "max_steps must be >= 1");
-  if (o->max_bounces < 0 || o->max_bounces >= MAX_PASSES)
-    return fail(RT_E_INVALID, "max_bounces must be in [0, %d)", MAX_PASSES);
+  if (o->max_bounces < 0 || o->max_bounces > MAX_BOUNCES)
+    return fail(RT_E_INVALID, "max_bounces must be in [0, %d]", MAX_BOUNCES);
   if (o->block != 0 && (o->block < 64 || o->block > 256 || o->block % 64))
     return fail(RT_E_INVALID, "block must be 0 or a multiple of 64 in [64, 256]");
   if (o->refill_period < 0 || o->refill_period > 1024)
@@ -806,25 +856,25 @@ unsigned int grid_for(long long n, int block) {
   return (unsigned int)std::max(1LL, g);
 }
 
-// transit + event passes over the slots already placed in the table
+// integrate the slots already placed in the table: order them hardest
+// first, then one persistent integrator launch
 template <bool MIXED>
-int run_passes(const CloakP &c, const OptsP &o, const Table &T, int block, int refill,
-               hipStream_t s) {
+int run_transit(const CloakP &c, const OptsP &o, const Table &T, int block, int refill,
+                hipStream_t s) {
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_transit<MIXED>, block, 0) != hipSuccess ||
       occ <= 0)
     occ = 1;
   unsigned int grid = (unsigned int)(num_cu() * occ);
-  int passes = o.max_bounces + 1;
-  for (int p = 0; p < passes; ++p) {
-    ProfEvent pe;
-    bool on;
-    prof_begin(s, pe, on);
-    hipLaunchKernelGGL(k_transit<MIXED>, dim3(grid), dim3(block), 0, s, c, o, T, p, refill);
-    prof_end(s, pe, on);
-    hipLaunchKernelGGL(k_event<MIXED>, dim3(num_cu() * 8), dim3(256), 0, s, c, o, T, p);
-  }
-  return launch_err("transit/event launch");
+  hipLaunchKernelGGL(k_sort_hist, dim3(num_cu() * 4), dim3(256), 0, s, T);
+  hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(64), 0, s, T);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(num_cu() * 4), dim3(256), 0, s, T);
+  ProfEvent pe;
+  bool on;
+  prof_begin(s, pe, on);
+  hipLaunchKernelGGL(k_transit<MIXED>, dim3(grid), dim3(block), 0, s, c, o, T, refill);
+  prof_end(s, pe, on);
+  return launch_err("transit launch");
 }
 
 }  // namespace
@@ -913,13 +963,13 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
   int block = opts->block ? opts->block : 256;
   int refill = opts->refill_period ? opts->refill_period : 1;
   int kind = c.axis * 2 + pol;
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, T.ctr, (int)C_COUNT);
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, T.ctr, (int)C_COUNT);
   hipLaunchKernelGGL(k_tb_entry, dim3(grid_for(n, 256)), dim3(256), 0, s, c, o, T, kind, (long long)n,
                      in6, out6, opl, status, hres, nsteps);
   e = launch_err("entry launch");
   if (e) return e;
-  e = o.precision == RT_PREC_MIXED ? run_passes<true>(c, o, T, block, refill, s)
-                                   : run_passes<false>(c, o, T, block, refill, s);
+  e = o.precision == RT_PREC_MIXED ? run_transit<true>(c, o, T, block, refill, s)
+                                   : run_transit<false>(c, o, T, block, refill, s);
   if (e) return e;
   hipLaunchKernelGGL(k_tb_finish, dim3(num_cu() * 8), dim3(256), 0, s, c, o, T, (long long)n, out6,
                      opl, status, hres, nsteps);
@@ -1024,14 +1074,14 @@ int rt_render(rt_cloak cloak, const rt_trace_opts *opts, const rt_room *room, co
   for (long long g0 = 0; g0 < total; g0 += chunk) {
     R.g0 = g0;
     R.g1 = std::min(total, g0 + chunk);
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, T.ctr, (int)C_COUNT);
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, T.ctr, (int)C_COUNT);
     hipLaunchKernelGGL(k_rd_gen, dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, c, o, rm,
                        g_ws.cams, T, R);
     e = launch_err("render generate launch");
     if (e) return e;
     if (cloak) {
-      e = o.precision == RT_PREC_MIXED ? run_passes<true>(c, o, T, block, refill, s)
-                                       : run_passes<false>(c, o, T, block, refill, s);
+      e = o.precision == RT_PREC_MIXED ? run_transit<true>(c, o, T, block, refill, s)
+                                       : run_transit<false>(c, o, T, block, refill, s);
       if (e) return e;
       hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, c, rm, T, R);
     }

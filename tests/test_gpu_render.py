@@ -85,13 +85,17 @@ def test_render_small_parity(axis):
 
 
 def test_render_empty_room():
+    """No cloak: camera rays hit the room directly. Codes agree except where a
+    ray lands exactly on a tile edge (the elevation-0 camera sits at z = 2, a
+    tile boundary, so symmetric rays produce exact ties)."""
     cams = W.render_views(res=32)
     rgb, aux = gpu_render(None, W.render_opts(), cams, 2)
     room = W.room()
     for k, cam in enumerate(cams):
         o = oracle.render_samples(None, W.opts_dp45(), room, cam, k, 1, np.arange(32 * 32))
-        assert (aux["code"][k, 0] == o["code"]).all()
         assert (aux["status"][k, 0] == 1).all()
+        compare_samples(aux["code"][k, 0], aux["rec"][k, 0], aux["status"][k, 0], o, room,
+                        f"empty cam{k}", pos_tol=1e-13, dir_tol=1e-13)
 
 
 @pytest.mark.parametrize("axis", [0, 1])
