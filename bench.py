@@ -6,7 +6,8 @@ azimuthal uniaxial cloaks (R1 = 1, R2 = 2, height 4) in the checkerboard room
 [-10,10]^2 x [0,10] (0.5 tiles), pinhole camera at distance 8 from (0,0,2),
 60 deg field of view, elevations 0/15/30/45 deg, 1024 x 1024 pixels,
 ordinary and extraordinary branch traced separately, Dormand-Prince 5(4) at
-tolerance 1e-8. One step = rt_render of both cloaks (16.8 M camera rays).
+tolerance 1e-8. One step = one rt_render_multi call rendering both cloaks
+(16.8 M camera rays, one integrator launch).
 
 Metric: Mrays/s traced through the cloak = rays that enter the cloak material
 per second of step time (all camera rays per second are reported too).
@@ -47,6 +48,34 @@ def attempt_flops(kind: int, scheme: int) -> int:
     return RK4_COMBINE_FLOPS + RK4_STAGES * ACCEL_FLOPS[kind]
 
 
+# HBM traffic of one integrator launch from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) of this benchmark, scaled by the same counters on a
+# plain device copy of known size (bench.py --copy-probe). Valid only for the
+# integrator source it was measured on; reported as null otherwise.
+TRAFFIC = {"source_sha256": "c5a6e9966dc8c97f447738137c417f9aea6d24083d2cd075038fb3849bd441d4",
+           "bytes_per_launch": 910121638}
+
+
+def integrator_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in ("paper_1209_6038_amd/csrc/rt_cloak.hip", "paper_1209_6038_amd/csrc/device.h"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def copy_probe(nbytes: int = 1 << 30) -> None:
+    """One plain device-to-device copy of nbytes (for counter calibration)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes}), flush=True)
+
+
 def cpu_baseline(opts, cams, stride, entered_only=True):
     """Time the oracle on every `stride`-th pixel of every image."""
     import numpy as np
@@ -76,15 +105,20 @@ def cpu_baseline(opts, cams, stride, entered_only=True):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--res", type=int, default=1024)
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed")
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
-    ap.add_argument("--cpu-stride", type=int, default=31)
+    ap.add_argument("--cpu-stride", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it "
               "(see DESIGN.md for how the path would shard)", file=sys.stderr)
@@ -105,26 +139,25 @@ def main():
     opts = W.render_opts(precision=args.precision, refill_period=args.refill, block=args.block)
     cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
     room = W.room()
-    outs = [torch.empty((len(cams), 2, args.res, args.res, 3), dtype=torch.float32, device=dev)
-            for _ in cloaks]
+    out = torch.empty((2, len(cams), 2, args.res, args.res, 3), dtype=torch.float32, device=dev)
 
     def step():
-        for cl, out in zip(cloaks, outs):
-            rt.render(cl, opts, room, cams, 3, out=out)
+        # both cloaks, 4 views, both branches in one pass (one integrator launch)
+        rt.render_multi(cloaks, opts, room, cams, 3, out=out)
 
     # untimed counting pass: entering rays and integrator step attempts
     entered = 0
     flops = 0
-    for ci, cl in enumerate(cloaks):
-        _, aux = rt.render(cl, opts, room, cams, 3, aux=True)
-        torch.cuda.synchronize()
-        st = aux["status"].cpu().numpy()
-        ns = aux["nsteps"].cpu().numpy().astype(np.int64)
-        entered += int(np.isin(st, (0, 2, 3, 4, 5)).sum())
+    _, aux = rt.render_multi(cloaks, opts, room, cams, 3, aux=True)
+    torch.cuda.synchronize()
+    st = aux["status"].cpu().numpy()
+    ns = aux["nsteps"].cpu().numpy().astype(np.int64)
+    del aux
+    entered += int(np.isin(st, (0, 2, 3, 4, 5)).sum())
+    for ci in range(2):
         for pi, pol in enumerate((0, 1)):
             kind = ci * 2 + pol
-            flops += int(ns[:, pi].sum()) * attempt_flops(kind, opts["scheme"])
-        del aux
+            flops += int(ns[ci, :, pi].sum()) * attempt_flops(kind, opts["scheme"])
     camera_rays = 2 * len(cams) * 2 * args.res * args.res
 
     for _ in range(args.warmup):
@@ -172,7 +205,9 @@ def main():
                    "precision": "fp64" if args.precision == 0 else "mixed",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": (TRAFFIC["bytes_per_launch"]
+                                 if TRAFFIC["source_sha256"] == integrator_source_hash() else None),
                      "kernel": "k_transit (integrator)",
                      "avg_launch_ms": round(avg_launch_ms, 4),
                      "launches_per_step": launches_per_step,

@@ -172,6 +172,18 @@ int rt_render(rt_cloak cloak, const rt_trace_opts *opts, const rt_room *room,
 int rt_profile_enable(int32_t on);
 int rt_profile_read(double *transit_ms, int64_t *launches);
 
+/* Render the same views for several cloaks in one pass (Fig. 1 vs Fig. 2 of
+   the paper: the radial and the azimuthal cloak seen identically), so that
+   one integrator launch carries the rays of every (cloak, branch) pair.
+   cloaks: n_cloaks (0..2) handles sharing r1, r2, z0, z1 and inner_mirror
+   (they may differ in the optic axis); n_cloaks = 0 renders the empty room.
+   rgb: float32 [max(n_cloaks,1)][n_cams][npol][h][w][3]; aux arrays follow
+   the same [cloak][camera][branch] image order. Otherwise as rt_render;
+   RT_E_INVALID if the cloaks' geometries differ. */
+int rt_render_multi(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts,
+                    const rt_room *room, const rt_camera *cams, int32_t n_cams, int32_t pol_mask,
+                    float *rgb, const rt_render_aux *aux, void *stream);
+
 /* Release the library's device workspace (synchronizes the device first). */
 int rt_release_workspace(void);
 

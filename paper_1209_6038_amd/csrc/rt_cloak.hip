@@ -35,19 +35,23 @@ struct rt_cloak_s {
 
 namespace {
 
+// segments of the work table: one per (cloak, branch) of a call, each of
+// `cap` slots; the integrator's waves stay on one segment at a time
+constexpr int NSEG = 4;
+
 // counters in device memory
 enum {
-  C_N0 = 0,       // slots in segment 0
-  C_N1 = 1,       // slots in segment 1
-  C_FETCH = 2,    // work counter of the integrator
-  C_HIST = 40,    // NBIN bins: slots per (difficulty, kind) key
-  C_OFF = 104,    // NBIN bins: scatter offsets of the keys
-  C_COUNT = 168
+  C_N = 0,        // C_N + s: slots used in segment s
+  C_FETCH = 4,    // C_FETCH + s: integrator work counter of segment s
+  C_HIST = 8,     // NBIN bins: slots per (segment, difficulty) key
+  C_OFF = 72,     // NBIN bins: scatter offsets of the keys
+  C_COUNT = 136
 };
-constexpr int NBUCKET = 16;           // difficulty buckets
-constexpr int NBIN = NBUCKET * 4;     // x 4 branch kinds
 constexpr int MAX_BOUNCES = 64;
 constexpr unsigned int FETCH_CHUNK = 64;  // rays claimed per wave per atomic
+constexpr int LONG_RAY_ATTEMPTS = 64;      // see the issue priority in k_transit
+constexpr int NBUCKET = 16;               // difficulty buckets
+constexpr int NBIN = NBUCKET * NSEG;
 
 struct Table {
   double *px, *py, *pz, *vx, *vy, *vz;
@@ -57,7 +61,7 @@ struct Table {
   int *order;   // integrator queue: slots sorted hardest first
   int *key0;    // sort key of each slot
   unsigned int *ctr;
-  long long cap;  // capacity of one segment; segment 1 starts at cap
+  long long cap;  // capacity of one segment; segment s starts at s * cap
 };
 
 thread_local std::string g_err;
@@ -97,15 +101,45 @@ __device__ __forceinline__ bool finite6(const double x[3], const double v[3]) {
          isfinite(v[1]) && isfinite(v[2]);
 }
 
-__device__ __forceinline__ int seg_slot(const Table &T, unsigned int idx, unsigned int n0) {
-  return idx < n0 ? (int)idx : (int)(T.cap + (idx - n0));
+// queue position -> (segment, slot) over the concatenation of the used
+// parts of the segments
+struct SegMap {
+  unsigned int off[NSEG + 1];
+};
+
+__device__ __forceinline__ SegMap seg_map(const Table &T) {
+  SegMap m;
+  m.off[0] = 0;
+#pragma unroll
+  for (int q = 0; q < NSEG; ++q) m.off[q + 1] = m.off[q] + T.ctr[C_N + q];
+  return m;
+}
+
+__device__ __forceinline__ int seg_of(const SegMap &m, unsigned int idx) {
+  int q = 0;
+#pragma unroll
+  for (int k = 1; k < NSEG; ++k) q += idx >= m.off[k] ? 1 : 0;
+  return q;
+}
+
+// m.off[q] for a run-time q without dynamic indexing (keeps SegMap in registers)
+__device__ __forceinline__ unsigned int off_of(const SegMap &m, int q) {
+  unsigned int r = 0;
+#pragma unroll
+  for (int k = 0; k <= NSEG; ++k) r = (k == q) ? m.off[k] : r;
+  return r;
+}
+
+__device__ __forceinline__ int slot_at(const Table &T, const SegMap &m, unsigned int idx, int &seg) {
+  seg = seg_of(m, idx);
+  return (int)(seg * T.cap + (idx - off_of(m, seg)));
 }
 
 // Sort key of an entering ray: rays whose conserved angular momentum p_theta
 // (and axial wave number p_z, for the branches whose metric is singular in
 // both) is small pass close to r = a, where the adaptive step shrinks; they
 // take the most steps and are integrated first so that a launch ends on
-// short rays. key = (NBUCKET-1 - bucket) * 4 + kind, bucket = -log2(p).
+// short rays. key = NBUCKET-1 - bucket with bucket = -log2(p).
 __device__ __forceinline__ int sort_key(const CloakP &c, int kind, const double x[3],
                                         const double d[3]) {
   int bucket = 0;
@@ -116,7 +150,7 @@ __device__ __forceinline__ int sort_key(const CloakP &c, int kind, const double 
     (void)frexp(p, &e);  // p = f 2^e, f in [0.5, 1)
     bucket = min(max(1 - e, 0), NBUCKET - 1);
   }
-  return (NBUCKET - 1 - bucket) * 4 + kind;
+  return NBUCKET - 1 - bucket;
 }
 
 __device__ __forceinline__ void load_state(const Table &T, int s, double x[3], double v[3]) {
@@ -219,7 +253,7 @@ __global__ void __launch_bounds__(256) k_tb_entry(CloakP c, OptsP o, Table T, in
       if (nsteps) nsteps[i] = 0;
     }
   }
-  unsigned int sl = wave_append(T.ctr + C_N0, enter);
+  unsigned int sl = wave_append(T.ctr + C_N, enter);
   if (enter) put_slot(T, (int)sl, x, v, kind, i, s, o.h0, skey);
 }
 
@@ -229,10 +263,14 @@ __global__ void __launch_bounds__(256) k_sort_hist(Table T) {
   __shared__ unsigned int lh[NBIN];
   for (int i = threadIdx.x; i < NBIN; i += blockDim.x) lh[i] = 0;
   __syncthreads();
-  unsigned int n0 = T.ctr[C_N0], n = n0 + T.ctr[C_N1];
+  const SegMap m = seg_map(T);
+  const unsigned int n = m.off[NSEG];
   unsigned int stride = gridDim.x * blockDim.x;
-  for (unsigned int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride)
-    atomicAdd(&lh[T.key0[seg_slot(T, idx, n0)]], 1u);
+  for (unsigned int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
+    int seg;
+    int slot = slot_at(T, m, idx, seg);
+    atomicAdd(&lh[seg * NBUCKET + T.key0[slot]], 1u);
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < NBIN; i += blockDim.x)
     if (lh[i]) atomicAdd(&T.ctr[C_HIST + i], lh[i]);
@@ -250,7 +288,8 @@ __global__ void k_sort_scan(Table T) {
 
 __global__ void __launch_bounds__(256) k_sort_scatter(Table T) {
   __shared__ unsigned int lc[NBIN], lb[NBIN];
-  unsigned int n0 = T.ctr[C_N0], n = n0 + T.ctr[C_N1];
+  const SegMap m = seg_map(T);
+  const unsigned int n = m.off[NSEG];
   unsigned int stride = gridDim.x * blockDim.x;
   unsigned int rounds = (n + stride - 1) / stride;
   for (unsigned int r = 0; r < rounds; ++r) {
@@ -260,8 +299,9 @@ __global__ void __launch_bounds__(256) k_sort_scatter(Table T) {
     int slot = -1, key = 0;
     unsigned int local = 0;
     if (idx < n) {
-      slot = seg_slot(T, idx, n0);
-      key = T.key0[slot];
+      int seg;
+      slot = slot_at(T, m, idx, seg);
+      key = seg * NBUCKET + T.key0[slot];
       local = atomicAdd(&lc[key], 1u);
     }
     __syncthreads();
@@ -385,7 +425,9 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
   const int rid = L.rid;
   L.rid = -1;
   if (rid == B_INNER) {
-    if (!(c.mirror && c.axis == RT_AXIS_RADIAL && L.bounces < o.max_bounces)) return RT_RAY_ABSORBED;
+    // optic axis along the mirror normal (radial cloak): one reflected ray
+    if (!(c.mirror && (KIND == K_RO || KIND == K_RE) && L.bounces < o.max_bounces))
+      return RT_RAY_ABSORBED;
     reflect_inside(B_INNER, L.x, L.v);
   } else {
     double d[3];
@@ -418,8 +460,11 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
 // the attempt itself is the same code for every lane of a branch.
 template <bool MIXED>
 __global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int refill) {
-  const unsigned int n = T.ctr[C_N0] + T.ctr[C_N1];
-  unsigned int *fetch = T.ctr + C_FETCH;
+  // the queue holds the used parts of the segments one after the other,
+  // each sorted hardest first; a wave works on one segment at a time so that
+  // its lanes run the same branch code, and moves on to the next segment
+  // that still has rays when its own is drained
+  const SegMap sm = seg_map(T);
   const double band2 = (c.a + o.band) * (c.a + o.band);
   const double tol = 1e-13 * c.b;
   int slot = -1, kind = 0;
@@ -427,24 +472,43 @@ __global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int
   L.h = 0.0; L.t = 0.0; L.lo = 0.0; L.hi = 0.0; L.ht = 0.0;
   L.ns = 0; L.bounces = 0; L.rid = -1; L.riter = 0; L.after_reject = false;
   // wave-private chunk [cur, end) of the queue, refilled with one atomic per
-  // FETCH_CHUNK rays; cur, end and drained are wave-uniform
+  // FETCH_CHUNK rays; cur, end, seg and drained are wave-uniform
   unsigned int cur = 0, end = 0;
-  bool drained = false;
+  unsigned int drained = 0;  // bit q: segment q has no rays left
+  int nused = 0;
+#pragma unroll
+  for (int q = 0; q < NSEG; ++q) {
+    if (sm.off[q + 1] == sm.off[q]) drained |= 1u << q;
+    else ++nused;
+  }
+  const unsigned int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int seg = 0;
+  if (nused > 0) {
+    // start on the (wave mod nused)-th used segment
+    int k = (int)(wave % (unsigned int)nused);
+    for (int q = 0; q < NSEG; ++q)
+      if (!(drained >> q & 1u)) {
+        if (k == 0) { seg = q; break; }
+        --k;
+      }
+  }
 
   for (;;) {
-    for (int round = 0; round < 2; ++round) {
+    for (int round = 0; round < 2 * NSEG; ++round) {
       bool need = slot < 0;
       unsigned long long m = __ballot(need);
       if (m == 0ull) break;
       if (cur >= end) {
-        if (drained) break;
+        if (drained == (1u << NSEG) - 1u) break;
+        while (drained >> seg & 1u) seg = (seg + 1) % NSEG;
+        const unsigned int off = off_of(sm, seg), len = off_of(sm, seg + 1) - off;
         unsigned int base = 0;
-        if (__lane_id() == 0) base = atomicAdd(fetch, FETCH_CHUNK);
+        if (__lane_id() == 0) base = atomicAdd(T.ctr + C_FETCH + seg, FETCH_CHUNK);
         base = __shfl(base, 0);
-        cur = base;
-        end = min(base + FETCH_CHUNK, n);
-        if (base + FETCH_CHUNK >= n) drained = true;
-        if (cur >= end) break;
+        if (base + FETCH_CHUNK >= len) drained |= 1u << seg;
+        cur = off + min(base, len);
+        end = off + min(base + FETCH_CHUNK, len);
+        if (cur >= end) continue;
       }
       unsigned int idx = cur + (unsigned int)__popcll(m & lanemask_lt());
       if (need && idx < end) {
@@ -462,6 +526,13 @@ __global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int
       cur = min(cur + (unsigned int)__popcll(m), end);
     }
     if (__ballot(slot >= 0) == 0ull) break;
+
+    // A wave that holds a ray past LONG_RAY_ATTEMPTS attempts is on the
+    // launch's critical path (the longest rays take ~1500 attempts where the
+    // mean is ~40): give it issue priority over the waves that share its
+    // SIMD, which fill the remaining issue slots.
+    if (__ballot(slot >= 0 && L.ns > LONG_RAY_ATTEMPTS) != 0ull) __builtin_amdgcn_s_setprio(3);
+    else __builtin_amdgcn_s_setprio(0);
 
     for (int it = 0; it < refill; ++it) {
       if (slot >= 0) {
@@ -492,7 +563,7 @@ __global__ void __launch_bounds__(256) k_tb_finish(CloakP c, OptsP o, Table T, l
                                                    double *__restrict__ out6, double *__restrict__ opl,
                                                    int *__restrict__ status, double *__restrict__ hres,
                                                    int *__restrict__ nsteps) {
-  unsigned int n0 = T.ctr[C_N0];
+  unsigned int n0 = T.ctr[C_N];
   unsigned int stride = gridDim.x * blockDim.x;
   for (unsigned int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n0; idx += stride) {
     int s = (int)idx;
@@ -529,21 +600,26 @@ __global__ void __launch_bounds__(256) k_tb_finish(CloakP c, OptsP o, Table T, l
 struct RenderP {
   long long g0, g1;   // chunk of the flattened (camera, pixel, sample) index
   long long ns_img;   // samples per image = w*h*spp
-  int npol, pol0, pol1, spp;
+  int n_cams, ncl, npol, spp;
+  int axis[2];        // optic axis of each cloak
+  int pol[2];         // branch of each traced polarization
   int has_cloak, pad;
-  unsigned char *codes;  // chunk-local codes [npol][g1-g0]
+  unsigned char *codes;  // chunk-local codes [segment][g1-g0]
   double *rec;           // aux (may be NULL)
   int *st;
   unsigned char *code;
   int *nsteps;
 };
 
-__device__ __forceinline__ void rd_write(const RenderP &R, int pi, long long gidx, int code,
+// segment q = cloak * npol + polarization; images are laid out
+// [cloak][camera][polarization]
+__device__ __forceinline__ void rd_write(const RenderP &R, int q, long long gidx, int code,
                                          int st, const double p[3], const double d[3], double L,
                                          int nsteps) {
-  R.codes[(long long)pi * (R.g1 - R.g0) + (gidx - R.g0)] = (unsigned char)code;
+  R.codes[(long long)q * (R.g1 - R.g0) + (gidx - R.g0)] = (unsigned char)code;
   long long cam = gidx / R.ns_img, loc = gidx - cam * R.ns_img;
-  long long img = cam * R.npol + pi;
+  int ci = q / R.npol, pi = q - ci * R.npol;
+  long long img = ((long long)ci * R.n_cams + cam) * R.npol + pi;
   if (R.st) R.st[img * R.ns_img + loc] = st;
   if (R.code) R.code[img * R.ns_img + loc] = (unsigned char)code;
   if (R.nsteps) R.nsteps[img * R.ns_img + loc] = nsteps;
@@ -555,6 +631,7 @@ __device__ __forceinline__ void rd_write(const RenderP &R, int pi, long long gid
   }
 }
 
+// camera rays of a chunk; one thread per sample, every (cloak, branch)
 __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
                                                 const CamP *__restrict__ cams, Table T, RenderP R) {
   long long gidx = R.g0 + (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -578,8 +655,9 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
       disk = surf != B_SIDE && fma(x[0], x[0], x[1] * x[1]) <= c.a2;
     }
   }
-  for (int pi = 0; pi < R.npol; ++pi) {
-    int kind = c.axis * 2 + (pi == 0 ? R.pol0 : R.pol1);
+  for (int q = 0; q < R.ncl * R.npol; ++q) {
+    int ci = q / R.npol, pi = q - ci * R.npol;
+    int kind = R.axis[ci] * 2 + R.pol[pi];
     bool enter = false;
     double v[3] = {0, 0, 0};
     if (valid) {
@@ -609,20 +687,21 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
           code = room_code(rm, p, dd, sh);
           L += sh;
         }
-        rd_write(R, pi, gidx, code, st, p, dd, L, 0);
+        rd_write(R, q, gidx, code, st, p, dd, L, 0);
       }
     }
-    unsigned int sl = wave_append(T.ctr + C_N0 + pi, enter);
-    if (enter) put_slot(T, (int)(pi * T.cap + sl), x, v, kind, gidx, s, o.h0, sort_key(c, kind, x, d));
+    unsigned int sl = wave_append(T.ctr + C_N + q, enter);
+    if (enter) put_slot(T, (int)(q * T.cap + sl), x, v, kind, gidx, s, o.h0, sort_key(c, kind, x, d));
   }
 }
 
-__global__ void __launch_bounds__(256) k_rd_finish(CloakP c, RoomP rm, Table T, RenderP R) {
-  unsigned int n0 = T.ctr[C_N0], n = n0 + T.ctr[C_N1];
+__global__ void __launch_bounds__(256) k_rd_finish(RoomP rm, Table T, RenderP R) {
+  const SegMap m = seg_map(T);
+  const unsigned int n = m.off[NSEG];
   unsigned int stride = gridDim.x * blockDim.x;
   for (unsigned int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
-    int pi = idx < n0 ? 0 : 1;
-    int s = (int)(idx < n0 ? idx : T.cap + (idx - n0));
+    int q;
+    int s = slot_at(T, m, idx, q);
     double x[3], v[3];
     load_state(T, s, x, v);
     int st = T.status[s];
@@ -637,7 +716,7 @@ __global__ void __launch_bounds__(256) k_rd_finish(CloakP c, RoomP rm, Table T, 
 #pragma unroll
       for (int j = 0; j < 3; ++j) v[j] *= w;
     }
-    rd_write(R, pi, T.key[s], code, st, x, v, L, T.nsteps[s]);
+    rd_write(R, q, T.key[s], code, st, x, v, L, T.nsteps[s]);
   }
 }
 
@@ -650,10 +729,10 @@ __global__ void __launch_bounds__(256) k_rd_resolve(RenderP R, const float *__re
   long long chunk = R.g1 - R.g0;
   long long pix_in_chunk = chunk / R.spp;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= pix_in_chunk * R.npol) return;
-  int pi = (int)(i / pix_in_chunk);
-  long long lp = i - pi * pix_in_chunk;
-  const unsigned char *cd = R.codes + pi * chunk + lp * R.spp;
+  if (i >= pix_in_chunk * R.ncl * R.npol) return;
+  int q = (int)(i / pix_in_chunk);
+  long long lp = i - q * pix_in_chunk;
+  const unsigned char *cd = R.codes + q * chunk + lp * R.spp;
   float r = 0.f, g = 0.f, b = 0.f;
   for (int k = 0; k < R.spp; ++k) {
     int cc = cd[k];
@@ -664,7 +743,8 @@ __global__ void __launch_bounds__(256) k_rd_resolve(RenderP R, const float *__re
   float inv = 1.0f / (float)R.spp;
   long long gpix = R.g0 / R.spp + lp;  // flattened (camera, pixel)
   long long cam = gpix / npix, pix = gpix - cam * npix;
-  float *o = rgb + ((cam * R.npol + pi) * npix + pix) * 3;
+  int ci = q / R.npol, pi = q - ci * R.npol;
+  float *o = rgb + ((((long long)ci * R.n_cams + cam) * R.npol + pi) * npix + pix) * 3;
   o[0] = r * inv;
   o[1] = g * inv;
   o[2] = b * inv;
@@ -718,7 +798,7 @@ void prof_end(hipStream_t s, ProfEvent &pe, bool on) {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Ensure the workspace holds two segments of `cap` slots, `codes_len` code
+// Ensure the workspace holds NSEG segments of `cap` slots, `codes_len` code
 // bytes and `ncam` camera records. Caller holds g_ws_mu.
 int ensure_workspace(long long cap, long long codes_len, int ncam) {
   int dev = 0;
@@ -737,7 +817,7 @@ int ensure_workspace(long long cap, long long codes_len, int ncam) {
     (void)hipFree(g_ws.base);
     g_ws.base = nullptr;
   }
-  long long ns = 2 * cap;
+  long long ns = (long long)NSEG * cap;
   size_t off = 0;
   auto take = [&](size_t b) { size_t o = off; off = align_up(off + b); return o; };
   size_t o_d = take(sizeof(double) * 10 * ns);
@@ -961,7 +1041,7 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
   CloakP c = make_cloak(cloak->d);
   OptsP o = make_opts(*opts);
   int block = opts->block ? opts->block : 256;
-  int refill = opts->refill_period ? opts->refill_period : 1;
+  int refill = opts->refill_period ? opts->refill_period : 2;
   int kind = c.axis * 2 + pol;
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, T.ctr, (int)C_COUNT);
   hipLaunchKernelGGL(k_tb_entry, dim3(grid_for(n, 256)), dim3(256), 0, s, c, o, T, kind, (long long)n,
@@ -976,9 +1056,19 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
   return launch_err("finish launch");
 }
 
-int rt_render(rt_cloak cloak, const rt_trace_opts *opts, const rt_room *room, const rt_camera *cams,
-              int32_t n_cams, int32_t pol_mask, float *rgb, const rt_render_aux *aux, void *stream) {
-  double r2 = cloak ? cloak->d.r2 : 0.0;
+int rt_render_multi(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts,
+                    const rt_room *room, const rt_camera *cams, int32_t n_cams, int32_t pol_mask,
+                    float *rgb, const rt_render_aux *aux, void *stream) {
+  if (n_cloaks < 0 || n_cloaks > 2) return fail(RT_E_INVALID, "n_cloaks must be 0, 1 or 2");
+  if (n_cloaks > 0 && !cloaks) return fail(RT_E_INVALID, "cloaks is NULL");
+  for (int k = 0; k < n_cloaks; ++k)
+    if (!cloaks[k]) return fail(RT_E_INVALID, "cloak handle %d is NULL", k);
+  for (int k = 1; k < n_cloaks; ++k) {
+    const rt_cloak_desc &a = cloaks[0]->d, &b = cloaks[k]->d;
+    if (a.r1 != b.r1 || a.r2 != b.r2 || a.z0 != b.z0 || a.z1 != b.z1 || a.inner_mirror != b.inner_mirror)
+      return fail(RT_E_INVALID, "cloaks of one call must share r1, r2, z0, z1 and inner_mirror");
+  }
+  double r2 = n_cloaks ? cloaks[0]->d.r2 : 0.0;
   int e = check_opts(opts, r2, false);
   if (e) return e;
   if (!room || !cams || !rgb) return fail(RT_E_INVALID, "room, cams and rgb are required");
@@ -997,9 +1087,8 @@ int rt_render(rt_cloak cloak, const rt_trace_opts *opts, const rt_room *room, co
   const long long npix = (long long)w * h;
   const long long ns_img = npix * spp;
   if (ns_img > (1LL << 30)) return fail(RT_E_INVALID, "w*h*spp must be <= 2^30");
-  int npol = (pol_mask == 3) ? 2 : 1;
-  int pol0 = (pol_mask & 1) ? RT_POL_ORDINARY : RT_POL_EXTRAORDINARY;
-  int pol1 = RT_POL_EXTRAORDINARY;
+  const int npol = (pol_mask == 3) ? 2 : 1;
+  const int ncl = n_cloaks > 0 ? n_cloaks : 1;  // the empty room renders as one "cloak"
 
   // host-side camera bases
   CamP *hc = new (std::nothrow) CamP[n_cams];
@@ -1009,9 +1098,6 @@ int rt_render(rt_cloak cloak, const rt_trace_opts *opts, const rt_room *room, co
     double F[3], R[3], U[3];
     for (int j = 0; j < 3; ++j) F[j] = C.look[j] - C.eye[j];
     double fl = std::sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
-    R[0] = F[1] * C.up[2] - F[2] * C.up[1];
-    R[1] = F[2] * C.up[0] - F[0] * C.up[2];
-    R[2] = F[0] * C.up[1] - F[1] * C.up[0];
     if (!(fl > 0.0) || !(C.fov_deg > 0.0 && C.fov_deg < 180.0)) {
       delete[] hc;
       return fail(RT_E_INVALID, "camera %d: eye == look or fov outside (0, 180)", k);
@@ -1037,7 +1123,7 @@ int rt_render(rt_cloak cloak, const rt_trace_opts *opts, const rt_room *room, co
     P.seed = C.seed;
   }
   CloakP c{};
-  if (cloak) c = make_cloak(cloak->d);
+  if (n_cloaks) c = make_cloak(cloaks[0]->d);
   OptsP o = make_opts(*opts);
   RoomP rm;
   for (int j = 0; j < 3; ++j) { rm.lo[j] = room->lo[j]; rm.hi[j] = room->hi[j]; }
@@ -1053,7 +1139,7 @@ int rt_render(rt_cloak cloak, const rt_trace_opts *opts, const rt_room *room, co
   const long long chunk_max = (1LL << 24) / spp * spp;
   const long long chunk = std::min(total, std::max(chunk_max, (long long)spp));
   std::lock_guard<std::mutex> lk(g_ws_mu);
-  e = ensure_workspace(chunk, chunk * npol, n_cams);
+  e = ensure_workspace(chunk, chunk * ncl * npol, n_cams);
   if (e) { delete[] hc; return e; }
   (void)hipMemcpyAsync(g_ws.cams, hc, sizeof(CamP) * n_cams, hipMemcpyHostToDevice, s);
   (void)hipMemcpyAsync(g_ws.table, table, sizeof(float) * 39, hipMemcpyHostToDevice, s);
@@ -1062,10 +1148,15 @@ int rt_render(rt_cloak cloak, const rt_trace_opts *opts, const rt_room *room, co
   delete[] hc;
   const Table &T = g_ws.T;
   int block = opts->block ? opts->block : 256;
-  int refill = opts->refill_period ? opts->refill_period : 1;
+  int refill = opts->refill_period ? opts->refill_period : 2;
   RenderP R;
-  R.ns_img = ns_img; R.npol = npol; R.pol0 = pol0; R.pol1 = pol1; R.spp = spp;
-  R.has_cloak = cloak ? 1 : 0; R.pad = 0;
+  R.ns_img = ns_img; R.n_cams = n_cams; R.ncl = ncl; R.npol = npol; R.spp = spp;
+  R.axis[0] = n_cloaks > 0 ? cloaks[0]->d.axis : 0;
+  R.axis[1] = n_cloaks > 1 ? cloaks[1]->d.axis : 0;
+  R.pol[0] = (pol_mask & 1) ? RT_POL_ORDINARY : RT_POL_EXTRAORDINARY;
+  R.pol[1] = RT_POL_EXTRAORDINARY;
+  R.has_cloak = n_cloaks > 0 ? 1 : 0;
+  R.pad = 0;
   R.codes = g_ws.codes;
   R.rec = aux ? aux->rec : nullptr;
   R.st = aux ? aux->status : nullptr;
@@ -1079,19 +1170,25 @@ int rt_render(rt_cloak cloak, const rt_trace_opts *opts, const rt_room *room, co
                        g_ws.cams, T, R);
     e = launch_err("render generate launch");
     if (e) return e;
-    if (cloak) {
+    if (n_cloaks) {
       e = o.precision == RT_PREC_MIXED ? run_transit<true>(c, o, T, block, refill, s)
                                        : run_transit<false>(c, o, T, block, refill, s);
       if (e) return e;
-      hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, c, rm, T, R);
+      hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, rm, T, R);
     }
-    long long nres = (R.g1 - R.g0) / spp * npol;
+    long long nres = (R.g1 - R.g0) / spp * ncl * npol;
     hipLaunchKernelGGL(k_rd_resolve, dim3(grid_for(nres, 256)), dim3(256), 0, s, R, g_ws.table, rgb,
                        npix);
     e = launch_err("render finish launch");
     if (e) return e;
   }
   return RT_OK;
+}
+
+int rt_render(rt_cloak cloak, const rt_trace_opts *opts, const rt_room *room, const rt_camera *cams,
+              int32_t n_cams, int32_t pol_mask, float *rgb, const rt_render_aux *aux, void *stream) {
+  return rt_render_multi(cloak ? &cloak : nullptr, cloak ? 1 : 0, opts, room, cams, n_cams, pol_mask,
+                         rgb, aux, stream);
 }
 
 }  // extern "C"

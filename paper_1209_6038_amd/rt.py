@@ -23,7 +23,7 @@ RK4, DP45 = 0, 1
 FP64, MIXED = 0, 1
 STATUS_NAMES = ["EXITED", "MISSED", "ABSORBED", "MAXSTEPS", "DIVERGED", "TIR", "INVALID", "REFLECTED"]
 
-EXPORTED = ["rt_build_cloak", "rt_free_cloak", "rt_trace_batch", "rt_render",
+EXPORTED = ["rt_build_cloak", "rt_free_cloak", "rt_trace_batch", "rt_render", "rt_render_multi",
             "rt_profile_enable", "rt_profile_read", "rt_release_workspace", "rt_last_error"]
 
 
@@ -81,6 +81,9 @@ def lib():
         L.rt_trace_batch.argtypes = [vp, ctypes.POINTER(TraceOpts), i32, i64, vp, vp, vp, vp, vp, vp, vp]
         L.rt_render.argtypes = [vp, ctypes.POINTER(TraceOpts), ctypes.POINTER(Room),
                                 ctypes.POINTER(Camera), i32, i32, vp, ctypes.POINTER(RenderAux), vp]
+        L.rt_render_multi.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(TraceOpts),
+                                      ctypes.POINTER(Room), ctypes.POINTER(Camera), i32, i32, vp,
+                                      ctypes.POINTER(RenderAux), vp]
         L.rt_release_workspace.argtypes = []
         L.rt_profile_enable.argtypes = [i32]
         L.rt_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
@@ -183,6 +186,39 @@ def trace_batch(cloak: Cloak, opts: dict, pol: int, in6, with_aux: bool = True):
         r["hres"] = hres
         r["nsteps"] = ns
     return r
+
+
+def render_multi(cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: int,
+                 aux: bool = False, out=None):
+    """rt_render_multi: the same views for several cloaks (sharing geometry) in
+    one pass. Returns rgb float32 (n_cloaks, n_cams, npol, h, w, 3) and, with
+    aux=True, dict(rec, status, code, nsteps) in the same image order."""
+    import torch
+    n = len(cams)
+    ncl = max(len(cloaks), 1)
+    w, h, spp = int(cams[0]["w"]), int(cams[0]["h"]), int(cams[0].get("spp", 1))
+    npol = 2 if pol_mask == 3 else 1
+    dev = torch.device("cuda", torch.cuda.current_device())
+    rgb = out if out is not None else torch.empty((ncl, n, npol, h, w, 3), dtype=torch.float32,
+                                                  device=dev)
+    carr = (Camera * n)(*[camera(c) for c in cams])
+    harr = (ctypes.c_void_p * max(len(cloaks), 1))(*[c.handle for c in cloaks])
+    rm = room(room_d)
+    o = trace_opts(opts)
+    aux_s = None
+    aux_t = None
+    if aux:
+        ns = w * h * spp
+        aux_t = {"rec": torch.empty((ncl, n, npol, 7, ns), dtype=torch.float64, device=dev),
+                 "status": torch.empty((ncl, n, npol, ns), dtype=torch.int32, device=dev),
+                 "code": torch.empty((ncl, n, npol, ns), dtype=torch.uint8, device=dev),
+                 "nsteps": torch.empty((ncl, n, npol, ns), dtype=torch.int32, device=dev)}
+        aux_s = RenderAux(aux_t["rec"].data_ptr(), aux_t["status"].data_ptr(), aux_t["code"].data_ptr(),
+                          aux_t["nsteps"].data_ptr())
+    _check(lib().rt_render_multi(harr, len(cloaks), ctypes.byref(o), ctypes.byref(rm), carr, n,
+                                 int(pol_mask), _ptr(rgb),
+                                 ctypes.byref(aux_s) if aux_s is not None else None, _stream()))
+    return (rgb, aux_t) if aux else rgb
 
 
 def render(cloak, opts: dict, room_d: dict, cams: list, pol_mask: int, aux: bool = False,

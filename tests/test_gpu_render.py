@@ -116,23 +116,53 @@ def test_render_jittered_samples(axis):
         np.testing.assert_allclose(rgb[k, 0].reshape(-1, 3)[same], col[same], atol=1e-6)
 
 
-@pytest.mark.parametrize("axis", [0, 1])
-def test_render_full_size_sampled(axis):
-    """The 3-D render workload at full size (4 elevations, 1024 x 1024, both
-    branches) in the launch configuration the benchmark times; sampled
-    pixels re-traced by the oracle."""
+def test_render_full_size_sampled():
+    """The 3-D render workload at full size (both cloaks in one pass, 4
+    elevations, 1024 x 1024, both branches) in the launch configuration the
+    benchmark times; sampled pixels re-traced by the oracle."""
+    import torch
+    from paper_1209_6038_amd import rt
     cams = W.render_views(res=1024)
-    c = W.cloak(axis, height=W.HEIGHT)
-    say(f"case render full size axis={axis}")
-    rgb, aux = gpu_render(c, W.render_opts(), cams, 3)
+    descs = [W.cloak(a, height=W.HEIGHT) for a in (0, 1)]
+    cls = [rt.Cloak(d) for d in descs]
+    say("case render full size, both cloaks")
+    rgb, aux = rt.render_multi(cls, W.render_opts(), W.room(), cams, 3, aux=True)
+    torch.cuda.synchronize()
+    aux = {k: v.cpu().numpy() for k, v in aux.items()}
     room = W.room()
-    rng = np.random.default_rng(axis)
-    for k, cam in enumerate(cams):
-        for pi, branch in enumerate((0, 1)):
-            st = aux["status"][k, pi]
-            hits = np.flatnonzero(st != 1)
-            ids = np.unique(np.concatenate([rng.choice(st.size, 64, replace=False),
-                                            rng.choice(hits, min(96, hits.size), replace=False)]))
-            o = oracle.render_samples(c, W.opts_dp45(), room, cam, k, branch, ids)
-            compare_samples(aux["code"][k, pi][ids], aux["rec"][k, pi][:, ids],
-                            aux["status"][k, pi][ids], o, room, f"full a{axis} cam{k} b{branch}")
+    rng = np.random.default_rng(3)
+    for ci, c in enumerate(descs):
+        for k, cam in enumerate(cams):
+            for pi, branch in enumerate((0, 1)):
+                st = aux["status"][ci, k, pi]
+                hits = np.flatnonzero(st != 1)
+                ids = np.unique(np.concatenate([rng.choice(st.size, 64, replace=False),
+                                                rng.choice(hits, min(96, hits.size), replace=False)]))
+                o = oracle.render_samples(c, W.opts_dp45(), room, cam, k, branch, ids)
+                compare_samples(aux["code"][ci, k, pi][ids], aux["rec"][ci, k, pi][:, ids],
+                                aux["status"][ci, k, pi][ids], o, room,
+                                f"full a{c['axis']} cam{k} b{branch}")
+
+
+def test_render_multi_equals_single_calls():
+    """One pass over both cloaks gives bit-identical images, records and step
+    counts to one call per cloak (per-ray work does not depend on batching)."""
+    import torch
+    from paper_1209_6038_amd import rt
+    cams = [W.orbit_camera(0.3, 20.0, 64, 64), W.orbit_camera(2.0, 40.0, 64, 64)]
+    cls = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
+    rgb_m, aux_m = rt.render_multi(cls, W.render_opts(), W.room(), cams, 3, aux=True)
+    for ci, cl in enumerate(cls):
+        rgb_s, aux_s = rt.render(cl, W.render_opts(), W.room(), cams, 3, aux=True)
+        torch.cuda.synchronize()
+        assert torch.equal(rgb_m[ci], rgb_s)
+        for key in ("status", "code", "nsteps"):
+            assert torch.equal(aux_m[key][ci], aux_s[key]), key
+        assert torch.equal(torch.nan_to_num(aux_m["rec"][ci]), torch.nan_to_num(aux_s["rec"]))
+
+
+def test_render_multi_rejects_mismatched_geometry():
+    from paper_1209_6038_amd import rt
+    cls = [rt.Cloak(W.cloak(0, height=4.0)), rt.Cloak(W.cloak(1, height=3.0))]
+    with pytest.raises(rt.RtError):
+        rt.render_multi(cls, W.render_opts(), W.room(), [W.orbit_camera(0.0, 10.0, 8, 8)], 3)
