@@ -12,6 +12,11 @@ tolerance 1e-8. One step = one rt_render_multi call rendering both cloaks
 Metric: Mrays/s traced through the cloak = rays that enter the cloak material
 per second of step time (all camera rays per second are reported too).
 
+--workload batched times the batched workload instead: 64 seeded views
+(azimuth U[0, 2 pi), elevation U[0, 60] deg) at 512 x 512, both cloaks, both
+branches, recorded once into a HIP graph (rt_render_plan_*) and replayed, with
+the integrator's launch shape chosen by rt_autotune_render.
+
 Prints one JSON line. --gpus N with N > 1 exits: this build runs on one GPU.
 """
 from __future__ import annotations
@@ -108,6 +113,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--res", type=int, default=1024)
+    ap.add_argument("--workload", choices=("render3d", "batched"), default="render3d")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed")
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
@@ -135,15 +141,26 @@ def main():
         B.build()
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-    cams = W.render_views(res=args.res)
+    batched = args.workload == "batched"
+    cams = W.batched_views(64, 512) if batched else W.render_views(res=args.res)
+    res = int(cams[0]["w"])
     opts = W.render_opts(precision=args.precision, refill_period=args.refill, block=args.block)
     cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
     room = W.room()
-    out = torch.empty((2, len(cams), 2, args.res, args.res, 3), dtype=torch.float32, device=dev)
+    out = torch.empty((2, len(cams), 2, res, res, 3), dtype=torch.float32, device=dev)
+    tuned_ms = None
+    if batched:
+        if not (args.refill or args.block):
+            opts, tuned_ms = rt.autotune_render(cloaks, opts, room, cams, 3)
+        plan = rt.RenderPlan(cloaks, opts, room, cams, 3)
 
-    def step():
-        # both cloaks, 4 views, both branches in one pass (one integrator launch)
-        rt.render_multi(cloaks, opts, room, cams, 3, out=out)
+        def step():
+            # the whole batch: one replay of the captured graph
+            plan.launch()
+    else:
+        def step():
+            # both cloaks, 4 views, both branches in one pass (one integrator launch)
+            rt.render_multi(cloaks, opts, room, cams, 3, out=out)
 
     # untimed counting pass: entering rays and integrator step attempts
     entered = 0
@@ -158,7 +175,7 @@ def main():
         for pi, pol in enumerate((0, 1)):
             kind = ci * 2 + pol
             flops += int(ns[ci, :, pi].sum()) * attempt_flops(kind, opts["scheme"])
-    camera_rays = 2 * len(cams) * 2 * args.res * args.res
+    camera_rays = 2 * len(cams) * 2 * res * res
 
     for _ in range(args.warmup):
         step()
@@ -175,9 +192,21 @@ def main():
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     transit_ms, launches = rt.profile_read()
+    launches_per_step = launches / args.steps
+    if batched:
+        # graph replays carry no timing events: time the integrator of the
+        # same batch in eager launches (same kernels, same launch shape)
+        for _ in range(2):
+            rt.render_multi(cloaks, opts, room, cams, 3, out=out)
+        torch.cuda.synchronize()
+        rt.profile_read()
+        for _ in range(args.steps):
+            rt.render_multi(cloaks, opts, room, cams, 3, out=out)
+        torch.cuda.synchronize()
+        transit_ms, launches = rt.profile_read()
+        launches_per_step = launches / args.steps
     rt.profile_enable(False)
 
-    launches_per_step = launches / args.steps
     avg_launch_ms = transit_ms / max(launches, 1)
     flops_per_launch = flops / launches_per_step
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
@@ -196,9 +225,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == 0 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "3-D render: radial + azimuthal uniaxial cloaks (R1=1, R2=2, "
-                               "height 4), checkerboard room 20x20x10, 4 elevations x 1024^2 px, "
-                               "ordinary + extraordinary, DP45 tol 1e-8",
+        "config": {"workload": ("batched: 64 seeded views x 512^2 px (azimuth U[0,2pi), elevation "
+                                "U[0,60] deg), radial + azimuthal cloaks, ordinary + extraordinary, "
+                                "DP45 tol 1e-8, one HIP-graph replay per step" if batched else
+                                "3-D render: radial + azimuthal uniaxial cloaks (R1=1, R2=2, "
+                                "height 4), checkerboard room 20x20x10, 4 elevations x 1024^2 px, "
+                                "ordinary + extraordinary, DP45 tol 1e-8"),
+                   "launch_shape": {"block": opts.get("block") or 256,
+                                    "refill_period": opts.get("refill_period") or 2,
+                                    "autotuned_ms": tuned_ms},
+                   "miss_fraction": round(1.0 - entered / camera_rays, 4),
                    "camera_rays_per_step": camera_rays,
                    "rays_entering_cloak_per_step": entered,
                    "all_camera_rays_per_s_M": round(camera_rays / (ms * 1e-3) / 1e6, 3),
@@ -213,7 +249,7 @@ def main():
                      "launches_per_step": launches_per_step,
                      "integrator_share_of_step": round(transit_ms / args.steps / ms, 4)},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not batched:
         rec["cpu_baseline"] = cpu_baseline(W.opts_dp45(), cams, args.cpu_stride)
     print(json.dumps(rec), flush=True)
 

@@ -56,6 +56,7 @@ enum {
 };
 
 typedef struct rt_cloak_s *rt_cloak;
+typedef struct rt_plan_s *rt_plan;
 
 /* Cloak geometry and material (Sect. 4, Eqs. (13)-(15)). The material fills
    r1 <= r <= r2, z0 <= z <= z1 (z0 = -INFINITY, z1 = +INFINITY: infinitely
@@ -183,6 +184,34 @@ int rt_profile_read(double *transit_ms, int64_t *launches);
 int rt_render_multi(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts,
                     const rt_room *room, const rt_camera *cams, int32_t n_cams, int32_t pol_mask,
                     float *rgb, const rt_render_aux *aux, void *stream);
+
+/* Render plan: one batch of views (the arguments of rt_render_multi, fixed
+   at creation) recorded once into a HIP graph -- work-table reset, camera-ray
+   generation and entry refraction, the hardest-first ordering, the
+   persistent integrator, shading and the per-pixel resolve -- and replayed by
+   rt_render_plan_launch. The plan owns its device workspace and a copy of the
+   cameras; `rgb` and `aux` must stay valid while the plan exists, and every
+   launch overwrites them. Launches of one plan must not overlap (each launch
+   reuses the plan's workspace). The launch shape is taken from opts, else from
+   an earlier rt_autotune_render of the same batch shape, else the defaults.
+   Errors: as rt_render_multi, RT_E_DEVICE if capture or instantiation fails. */
+int rt_render_plan_create(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts,
+                          const rt_room *room, const rt_camera *cams, int32_t n_cams,
+                          int32_t pol_mask, float *rgb, const rt_render_aux *aux, rt_plan *out);
+int rt_render_plan_launch(rt_plan plan, void *stream);
+int rt_render_plan_destroy(rt_plan plan);
+
+/* Autotuner of the integrator's launch shape for a batch: times every block
+   size in {64, 128, 256} x refill period in {1, 2, 4, 8} on the batch itself
+   (one warm-up and two timed renders each, into `rgb`, which is overwritten),
+   writes opts with the fastest shape into `tuned` and its time per render
+   into `best_ms` (may be NULL), and remembers the choice for later calls of
+   the same batch shape that leave block and refill_period at 0. The shape
+   does not change any result (per-ray work is independent of scheduling).
+   Synchronous. */
+int rt_autotune_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts,
+                       const rt_room *room, const rt_camera *cams, int32_t n_cams, int32_t pol_mask,
+                       float *rgb, rt_trace_opts *tuned, double *best_ms);
 
 /* Release the library's device workspace (synchronizes the device first). */
 int rt_release_workspace(void);

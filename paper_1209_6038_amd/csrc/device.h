@@ -72,9 +72,9 @@ __device__ __forceinline__ double rsq64(double x) {
 // ---------------------------------------------------------------------------
 // metric diag(m_r, m_theta, m_z) at radius r for a branch kind
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void metric_diag(int kind, double kappa, double a, double r,
+__device__ __forceinline__ void metric_diag(int kind, double kappa, double a, double w,
                                             double& mr, double& mt, double& mz) {
-  double q = (r - a) / r;
+  double q = fma(-a, w, 1.0);  // (r - a) / r with w = 1/r
   double ks = kappa * q * q;
   switch (kind) {
     case K_RO: mr = kappa; mt = kappa; mz = kappa; break;
@@ -367,14 +367,28 @@ __device__ __forceinline__ bool inside_open(const CloakP& c, const double x[3]) 
   return r2 > c.a2 && r2 < c.b2 && x[2] > c.z0 && x[2] < c.z1;
 }
 
-// signed constraint value, negative inside
-__device__ __forceinline__ double gval(const CloakP& c, int id, const double x[3]) {
-  double r = sqrt(fma(x[0], x[0], x[1] * x[1]));
+// Boundary functions used inside the integrator, negative inside and equal
+// to the distance to first order: (r^2 - b^2) / (2 b), (a^2 - r^2) / (2 a),
+// z - z1, z0 - z. |g| <= tol places the state within tol (1 + O(tol/b)) of
+// the boundary; no square root is needed, and dg/dh along a velocity v is
+// (x v_x + y v_y) / b (resp. -/a) or +-v_z.
+__device__ __forceinline__ double gsq(const CloakP& c, int id, const double x[3]) {
+  double r2 = fma(x[0], x[0], x[1] * x[1]);
   switch (id) {
-    case B_SIDE: return r - c.b;
-    case B_INNER: return c.a - r;
+    case B_SIDE: return (r2 - c.b2) * (0.5 / c.b);
+    case B_INNER: return (c.a2 - r2) * (0.5 / c.a);
     case B_TOP: return x[2] - c.z1;
     default: return c.z0 - x[2];
+  }
+}
+
+__device__ __forceinline__ double gsq_slope(const CloakP& c, int id, const double x[3], const double v[3]) {
+  double rv = fma(x[0], v[0], x[1] * v[1]);
+  switch (id) {
+    case B_SIDE: return rv / c.b;
+    case B_INNER: return -rv / c.a;
+    case B_TOP: return v[2];
+    default: return -v[2];
   }
 }
 
@@ -429,11 +443,10 @@ __device__ __forceinline__ void reflect3(double v[3], const double n[3]) {
   v[2] = fma(-d, n[2], v[2]);
 }
 
-// local frame (r_hat, t_hat, z_hat) at x
-__device__ __forceinline__ void local_frame(const double x[3], double rh[2], double th[2], double& r) {
+// local frame (r_hat, t_hat, z_hat) at x; w = 1/r
+__device__ __forceinline__ void local_frame(const double x[3], double rh[2], double th[2], double& w) {
   double r2 = fma(x[0], x[0], x[1] * x[1]);
-  double w = rsq64(r2);
-  r = r2 * w;
+  w = rsq64_1(r2);
   rh[0] = x[0] * w; rh[1] = x[1] * w;
   th[0] = -rh[1]; th[1] = rh[0];
 }
@@ -443,10 +456,10 @@ __device__ __forceinline__ void local_frame(const double x[3], double rh[2], dou
 // Returns false if the transmitted wave is evanescent. v: ray velocity.
 __device__ __forceinline__ bool refract_in(const CloakP& c, int kind, int surf, const double x[3],
                                            const double kin[3], double v[3]) {
-  double rh[2], th[2], r;
-  local_frame(x, rh, th, r);
+  double rh[2], th[2], w;
+  local_frame(x, rh, th, w);
   double mr, mt, mz;
-  metric_diag(kind, c.kappa, c.a, r, mr, mt, mz);
+  metric_diag(kind, c.kappa, c.a, w, mr, mt, mz);
   double kr = kin[0] * rh[0] + kin[1] * rh[1];
   double kt = kin[0] * th[0] + kin[1] * th[1];
   double kz = kin[2];
@@ -472,10 +485,10 @@ __device__ __forceinline__ bool refract_in(const CloakP& c, int kind, int surf, 
 // internal reflection. Also returns |v^T M v - 1| in hres.
 __device__ __forceinline__ bool refract_out(const CloakP& c, int kind, int id, const double x[3],
                                             const double v[3], double d[3], double& hres) {
-  double rh[2], th[2], r;
-  local_frame(x, rh, th, r);
+  double rh[2], th[2], w;
+  local_frame(x, rh, th, w);
   double mr, mt, mz;
-  metric_diag(kind, c.kappa, c.a, r, mr, mt, mz);
+  metric_diag(kind, c.kappa, c.a, w, mr, mt, mz);
   double vr = v[0] * rh[0] + v[1] * rh[1];
   double vt = v[0] * th[0] + v[1] * th[1];
   double vz = v[2];
@@ -506,10 +519,10 @@ __device__ __forceinline__ void reflect_inside(int id, const double x[3], double
 
 __device__ __forceinline__ double hamiltonian_res(const CloakP& c, int kind, const double x[3],
                                                   const double v[3]) {
-  double rh[2], th[2], r;
-  local_frame(x, rh, th, r);
+  double rh[2], th[2], w;
+  local_frame(x, rh, th, w);
   double mr, mt, mz;
-  metric_diag(kind, c.kappa, c.a, r, mr, mt, mz);
+  metric_diag(kind, c.kappa, c.a, w, mr, mt, mz);
   double vr = v[0] * rh[0] + v[1] * rh[1];
   double vt = v[0] * th[0] + v[1] * th[1];
   return fabs(fma(mr * vr, vr, fma(mt * vt, vt, mz * v[2] * v[2])) - 1.0);

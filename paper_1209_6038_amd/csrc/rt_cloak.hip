@@ -20,7 +20,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -32,6 +34,8 @@ using namespace rtk;
 struct rt_cloak_s {
   rt_cloak_desc d;
 };
+
+struct rt_plan_s;
 
 namespace {
 
@@ -313,14 +317,6 @@ __global__ void __launch_bounds__(256) k_sort_scatter(Table T) {
   }
 }
 
-// d g / d h of boundary `id` along the end velocity of a trial step
-__device__ __forceinline__ double gslope(int id, const double xs[3], const double vs[3]) {
-  if (id == B_TOP) return vs[2];
-  if (id == B_BOTTOM) return -vs[2];
-  double vr = (xs[0] * vs[0] + xs[1] * vs[1]) * rsq64(fma(xs[0], xs[0], xs[1] * xs[1]));
-  return id == B_SIDE ? vr : -vr;
-}
-
 // integrator state of one lane (lives in registers)
 struct Lane {
   double x[3], v[3], A1[3];  // base state and its acceleration
@@ -380,9 +376,9 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
     int rid = B_SIDE;
 #pragma unroll
     for (int id = 0; id < 4; ++id) {
-      double g1 = gval(c, id, xn);
+      double g1 = gsq(c, id, xn);
       if (g1 >= 0.0) {
-        double g0 = fmin(gval(c, id, L.x), -1e-300);
+        double g0 = fmin(gsq(c, id, L.x), -1e-300);
         double fr = -g0 / (g1 - g0);
         if (fr < best) { best = fr; rid = id; }
       }
@@ -396,11 +392,11 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
   }
   // ---- locating the crossing of boundary rid ----
   if (!finite6(xn, vn)) return RT_RAY_DIVERGED;
-  double f = gval(c, L.rid, xn);
+  double f = gsq(c, L.rid, xn);
   ++L.riter;
   if (!(fabs(f) <= tol || L.riter >= 100 || !(L.hi - L.lo > 1e-300))) {
     if (f < 0.0) L.lo = L.ht; else L.hi = L.ht;
-    double hn = L.ht - f / gslope(L.rid, xn, vn);
+    double hn = L.ht - f / gsq_slope(c, L.rid, xn, vn);
     if (!(hn > L.lo && hn < L.hi)) hn = 0.5 * (L.lo + L.hi);
     L.ht = hn;
     return -1;
@@ -409,7 +405,7 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
   int other = -1;
 #pragma unroll
   for (int id = 0; id < 4; ++id)
-    if (id != L.rid && gval(c, id, xn) > tol) other = id;
+    if (id != L.rid && gsq(c, id, xn) > tol) other = id;
   if (other >= 0) {
     L.rid = other;
     L.lo = 0.0;
@@ -655,39 +651,42 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
       disk = surf != B_SIDE && fma(x[0], x[0], x[1] * x[1]) <= c.a2;
     }
   }
+  // rays that miss the cloak or hit the metal end disk see the same room
+  // point for every (cloak, branch): shade them once
+  int vcode = 12, vst = RT_RAY_MISSED;
+  double vp[3] = {org[0], org[1], org[2]}, vd[3] = {d[0], d[1], d[2]}, vL = 0.0;
+  if (valid && (!hitc || disk)) {
+    if (disk) {
+      double nrm[3];
+      boundary_normal(surf, x, nrm);
+      vp[0] = x[0]; vp[1] = x[1]; vp[2] = x[2];
+      vL = s;
+      if (c.mirror) { reflect3(vd, nrm); vst = RT_RAY_REFLECTED; }
+      else vst = RT_RAY_ABSORBED;
+    }
+    if (vst != RT_RAY_ABSORBED) {
+      double sh;
+      vcode = room_code(rm, vp, vd, sh);
+      vL += sh;
+    }
+  }
   for (int q = 0; q < R.ncl * R.npol; ++q) {
     int ci = q / R.npol, pi = q - ci * R.npol;
-    int kind = R.axis[ci] * 2 + R.pol[pi];
+    int kind = (ci == 0 ? R.axis[0] : R.axis[1]) * 2 + (pi == 0 ? R.pol[0] : R.pol[1]);
     bool enter = false;
     double v[3] = {0, 0, 0};
     if (valid) {
-      int st = RT_RAY_MISSED;
-      double p[3] = {org[0], org[1], org[2]}, dd[3] = {d[0], d[1], d[2]}, L = 0.0;
-      if (hitc) {
-        double nrm[3];
+      if (!hitc || disk) {
+        rd_write(R, q, gidx, vcode, vst, vp, vd, vL, 0);
+      } else if (refract_in(c, kind, surf, x, d, v)) {
+        enter = true;
+      } else {
+        // evanescent transmission into this branch: reflected at the entry
+        double nrm[3], dd[3] = {d[0], d[1], d[2]}, sh;
         boundary_normal(surf, x, nrm);
-        if (disk) {
-          p[0] = x[0]; p[1] = x[1]; p[2] = x[2];
-          L = s;
-          if (c.mirror) { reflect3(dd, nrm); st = RT_RAY_REFLECTED; }
-          else st = RT_RAY_ABSORBED;
-        } else if (refract_in(c, kind, surf, x, d, v)) {
-          enter = true;
-        } else {
-          p[0] = x[0]; p[1] = x[1]; p[2] = x[2];
-          L = s;
-          reflect3(dd, nrm);
-          st = RT_RAY_REFLECTED;
-        }
-      }
-      if (!enter) {
-        int code = 12;
-        if (st != RT_RAY_ABSORBED) {
-          double sh;
-          code = room_code(rm, p, dd, sh);
-          L += sh;
-        }
-        rd_write(R, q, gidx, code, st, p, dd, L, 0);
+        reflect3(dd, nrm);
+        int code = room_code(rm, x, dd, sh);
+        rd_write(R, q, gidx, code, RT_RAY_REFLECTED, x, dd, s + sh, 0);
       }
     }
     unsigned int sl = wave_append(T.ctr + C_N + q, enter);
@@ -753,17 +752,20 @@ __global__ void __launch_bounds__(256) k_rd_resolve(RenderP R, const float *__re
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+// Device workspace: the work table (NSEG segments of `cap` slots), the colour
+// codes of one render chunk, camera records and the colour table. The direct
+// calls share one (g_ws); every render plan owns its own.
 struct Workspace {
   void *base = nullptr;
   size_t bytes = 0;
   long long cap = 0;
+  long long codes_len = 0;
+  int cams_cap = 0;
+  int device = -1;
   Table T{};
   unsigned char *codes = nullptr;
-  long long codes_len = 0;
   CamP *cams = nullptr;
-  int cams_cap = 0;
   float *table = nullptr;
-  int device = -1;
 };
 
 std::mutex g_ws_mu;
@@ -798,25 +800,30 @@ void prof_end(hipStream_t s, ProfEvent &pe, bool on) {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Ensure the workspace holds NSEG segments of `cap` slots, `codes_len` code
-// bytes and `ncam` camera records. Caller holds g_ws_mu.
-int ensure_workspace(long long cap, long long codes_len, int ncam) {
+void ws_free(Workspace &ws) {
+  if (ws.base) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ws.base);
+  }
+  ws = Workspace{};
+}
+
+// Make `ws` hold NSEG segments of `cap` slots, `codes_len` code bytes and
+// `ncam` camera records (grows, never shrinks; synchronous hipMalloc).
+int ws_reserve(Workspace &ws, long long cap, long long codes_len, int ncam) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(RT_E_DEVICE, "hipGetDevice failed");
-  if (g_ws.base && g_ws.device == dev && g_ws.cap >= cap && g_ws.codes_len >= codes_len &&
-      g_ws.cams_cap >= ncam)
+  if (ws.base && ws.device == dev && ws.cap >= cap && ws.codes_len >= codes_len && ws.cams_cap >= ncam)
     return RT_OK;
-  cap = std::max(cap, g_ws.device == dev ? g_ws.cap : 0LL);
-  codes_len = std::max(codes_len, g_ws.device == dev ? g_ws.codes_len : 0LL);
-  ncam = std::max(ncam, g_ws.device == dev ? g_ws.cams_cap : 0);
+  if (ws.device == dev) {
+    cap = std::max(cap, ws.cap);
+    codes_len = std::max(codes_len, ws.codes_len);
+    ncam = std::max(ncam, ws.cams_cap);
+  }
   cap = std::max(cap, 1024LL);
   codes_len = std::max(codes_len, 1024LL);
   ncam = std::max(ncam, 16);
-  if (g_ws.base) {
-    (void)hipDeviceSynchronize();
-    (void)hipFree(g_ws.base);
-    g_ws.base = nullptr;
-  }
+  ws_free(ws);
   long long ns = (long long)NSEG * cap;
   size_t off = 0;
   auto take = [&](size_t b) { size_t o = off; off = align_up(off + b); return o; };
@@ -831,11 +838,10 @@ int ensure_workspace(long long cap, long long codes_len, int ncam) {
   void *p = nullptr;
   if (hipMalloc(&p, off) != hipSuccess) {
     (void)hipGetLastError();
-    g_ws = Workspace{};
     return fail(RT_E_NOMEM, "hipMalloc of %zu bytes for the workspace failed", off);
   }
   char *b = (char *)p;
-  Table &T = g_ws.T;
+  Table &T = ws.T;
   double *D = (double *)(b + o_d);
   T.px = D; T.py = D + ns; T.pz = D + 2 * ns; T.vx = D + 3 * ns; T.vy = D + 4 * ns; T.vz = D + 5 * ns;
   T.t = D + 6 * ns; T.h = D + 7 * ns; T.opl0 = D + 8 * ns; T.hres = D + 9 * ns;
@@ -846,15 +852,15 @@ int ensure_workspace(long long cap, long long codes_len, int ncam) {
   T.key0 = T.order + ns;
   T.ctr = (unsigned int *)(b + o_c);
   T.cap = cap;
-  g_ws.base = p;
-  g_ws.bytes = off;
-  g_ws.cap = cap;
-  g_ws.codes = (unsigned char *)(b + o_codes);
-  g_ws.codes_len = codes_len;
-  g_ws.cams = (CamP *)(b + o_cams);
-  g_ws.cams_cap = ncam;
-  g_ws.table = (float *)(b + o_tab);
-  g_ws.device = dev;
+  ws.base = p;
+  ws.bytes = off;
+  ws.cap = cap;
+  ws.codes = (unsigned char *)(b + o_codes);
+  ws.codes_len = codes_len;
+  ws.cams = (CamP *)(b + o_cams);
+  ws.cams_cap = ncam;
+  ws.table = (float *)(b + o_tab);
+  ws.device = dev;
   return RT_OK;
 }
 
@@ -936,25 +942,202 @@ unsigned int grid_for(long long n, int block) {
   return (unsigned int)std::max(1LL, g);
 }
 
-// integrate the slots already placed in the table: order them hardest
-// first, then one persistent integrator launch
 template <bool MIXED>
-int run_transit(const CloakP &c, const OptsP &o, const Table &T, int block, int refill,
-                hipStream_t s) {
+unsigned int transit_grid(int block) {
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_transit<MIXED>, block, 0) != hipSuccess ||
       occ <= 0)
     occ = 1;
-  unsigned int grid = (unsigned int)(num_cu() * occ);
+  return (unsigned int)(num_cu() * occ);
+}
+
+// integrate the slots already placed in the table: order them hardest
+// first, then one persistent integrator launch (kernel launches only)
+template <bool MIXED>
+void run_transit(const CloakP &c, const OptsP &o, const Table &T, int block, int refill,
+                 unsigned int grid, hipStream_t s, bool profile) {
   hipLaunchKernelGGL(k_sort_hist, dim3(num_cu() * 4), dim3(256), 0, s, T);
   hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(64), 0, s, T);
   hipLaunchKernelGGL(k_sort_scatter, dim3(num_cu() * 4), dim3(256), 0, s, T);
   ProfEvent pe;
-  bool on;
-  prof_begin(s, pe, on);
+  bool on = false;
+  if (profile) prof_begin(s, pe, on);
   hipLaunchKernelGGL(k_transit<MIXED>, dim3(grid), dim3(block), 0, s, c, o, T, refill);
-  prof_end(s, pe, on);
-  return launch_err("transit launch");
+  if (profile) prof_end(s, pe, on);
+}
+
+// launch shapes chosen by rt_autotune_render, keyed by the batch's shape
+struct TuneKey {
+  int n_cloaks, n_cams, w, h, spp, pol_mask, scheme, precision;
+  bool operator<(const TuneKey &k) const {
+    return std::tie(n_cloaks, n_cams, w, h, spp, pol_mask, scheme, precision) <
+           std::tie(k.n_cloaks, k.n_cams, k.w, k.h, k.spp, k.pol_mask, k.scheme, k.precision);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tuned;
+
+// A render call prepared on the host: validated inputs, camera bases, colour
+// table and launch shape. enqueue_render only launches kernels (no
+// allocation, no synchronization), so it can be captured into a HIP graph.
+struct RenderJob {
+  CloakP c{};
+  OptsP o{};
+  RoomP rm{};
+  RenderP R{};
+  std::vector<CamP> cams;
+  float table[64] = {0};
+  long long total = 0, chunk = 0, npix = 0;
+  int n_cloaks = 0, block = 256, refill = 2;
+  unsigned int grid = 0;
+  TuneKey key{};
+};
+
+}  // namespace
+
+struct rt_plan_s {
+  RenderJob J;
+  Workspace ws;
+  float *rgb = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int prepare_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts,
+                   const rt_room *room, const rt_camera *cams, int32_t n_cams, int32_t pol_mask,
+                   const rt_render_aux *aux, RenderJob &J) {
+  if (n_cloaks < 0 || n_cloaks > 2) return fail(RT_E_INVALID, "n_cloaks must be 0, 1 or 2");
+  if (n_cloaks > 0 && !cloaks) return fail(RT_E_INVALID, "cloaks is NULL");
+  for (int k = 0; k < n_cloaks; ++k)
+    if (!cloaks[k]) return fail(RT_E_INVALID, "cloak handle %d is NULL", k);
+  for (int k = 1; k < n_cloaks; ++k) {
+    const rt_cloak_desc &a = cloaks[0]->d, &b = cloaks[k]->d;
+    if (a.r1 != b.r1 || a.r2 != b.r2 || a.z0 != b.z0 || a.z1 != b.z1 || a.inner_mirror != b.inner_mirror)
+      return fail(RT_E_INVALID, "cloaks of one call must share r1, r2, z0, z1 and inner_mirror");
+  }
+  double r2 = n_cloaks ? cloaks[0]->d.r2 : 0.0;
+  int e = check_opts(opts, r2, false);
+  if (e) return e;
+  if (!room || !cams) return fail(RT_E_INVALID, "room and cams are required");
+  if (n_cams < 1) return fail(RT_E_INVALID, "n_cams must be >= 1");
+  if (pol_mask < 1 || pol_mask > 3) return fail(RT_E_INVALID, "pol_mask must be 1, 2 or 3");
+  if (!(room->tile > 0.0)) return fail(RT_E_INVALID, "room tile must be > 0");
+  for (int k = 0; k < 3; ++k)
+    if (!(room->hi[k] > room->lo[k])) return fail(RT_E_INVALID, "room needs lo < hi");
+  const int w = cams[0].w, h = cams[0].h, spp = cams[0].spp;
+  int m = (int)std::lround(std::sqrt((double)spp));
+  if (w < 1 || h < 1 || spp < 1 || m * m != spp || spp > 256)
+    return fail(RT_E_INVALID, "camera needs w, h >= 1 and spp a perfect square <= 256");
+  for (int k = 1; k < n_cams; ++k)
+    if (cams[k].w != w || cams[k].h != h || cams[k].spp != spp)
+      return fail(RT_E_INVALID, "all cameras must share w, h and spp");
+  const long long npix = (long long)w * h;
+  const long long ns_img = npix * spp;
+  if (ns_img > (1LL << 30)) return fail(RT_E_INVALID, "w*h*spp must be <= 2^30");
+  const int npol = (pol_mask == 3) ? 2 : 1;
+  const int ncl = n_cloaks > 0 ? n_cloaks : 1;  // the empty room renders as one image set
+
+  J.cams.resize(n_cams);
+  for (int k = 0; k < n_cams; ++k) {
+    const rt_camera &C = cams[k];
+    double F[3], R[3], U[3];
+    for (int j = 0; j < 3; ++j) F[j] = C.look[j] - C.eye[j];
+    double fl = std::sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
+    if (!(fl > 0.0) || !(C.fov_deg > 0.0 && C.fov_deg < 180.0))
+      return fail(RT_E_INVALID, "camera %d: eye == look or fov outside (0, 180)", k);
+    for (int j = 0; j < 3; ++j) F[j] /= fl;
+    R[0] = F[1] * C.up[2] - F[2] * C.up[1];
+    R[1] = F[2] * C.up[0] - F[0] * C.up[2];
+    R[2] = F[0] * C.up[1] - F[1] * C.up[0];
+    double rl = std::sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+    if (!(rl > 0.0)) return fail(RT_E_INVALID, "camera %d: up is parallel to the view direction", k);
+    for (int j = 0; j < 3; ++j) R[j] /= rl;
+    U[0] = R[1] * F[2] - R[2] * F[1];
+    U[1] = R[2] * F[0] - R[0] * F[2];
+    U[2] = R[0] * F[1] - R[1] * F[0];
+    CamP &P = J.cams[k];
+    for (int j = 0; j < 3; ++j) { P.eye[j] = C.eye[j]; P.F[j] = F[j]; P.R[j] = R[j]; P.U[j] = U[j]; }
+    P.tan_half = std::tan(0.5 * C.fov_deg * M_PI / 180.0);
+    P.aspect = (double)w / (double)h;
+    P.w = w; P.h = h; P.spp = spp; P.m = m;
+    P.seed = C.seed;
+  }
+  if (n_cloaks) J.c = make_cloak(cloaks[0]->d);
+  J.o = make_opts(*opts);
+  for (int j = 0; j < 3; ++j) { J.rm.lo[j] = room->lo[j]; J.rm.hi[j] = room->hi[j]; }
+  J.rm.tile = room->tile;
+  J.rm.inv_tile = 1.0 / room->tile;
+  for (int f = 0; f < 6; ++f)
+    for (int q = 0; q < 2; ++q)
+      for (int j = 0; j < 3; ++j) J.table[(f * 2 + q) * 3 + j] = room->rgb[f][q][j];
+  J.total = ns_img * n_cams;
+  const long long chunk_max = (1LL << 24) / spp * spp;
+  J.chunk = std::min(J.total, std::max(chunk_max, (long long)spp));
+  J.npix = npix;
+  J.n_cloaks = n_cloaks;
+  J.key = TuneKey{n_cloaks, n_cams, w, h, spp, pol_mask, opts->scheme, opts->precision};
+  J.block = opts->block ? opts->block : 256;
+  J.refill = opts->refill_period ? opts->refill_period : 2;
+  if (!opts->block && !opts->refill_period) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(J.key);
+    if (it != g_tuned.end()) { J.block = it->second.first; J.refill = it->second.second; }
+  }
+  J.grid = J.o.precision == RT_PREC_MIXED ? transit_grid<true>(J.block) : transit_grid<false>(J.block);
+  RenderP &R = J.R;
+  R.ns_img = ns_img; R.n_cams = n_cams; R.ncl = ncl; R.npol = npol; R.spp = spp;
+  R.axis[0] = n_cloaks > 0 ? cloaks[0]->d.axis : 0;
+  R.axis[1] = n_cloaks > 1 ? cloaks[1]->d.axis : 0;
+  R.pol[0] = (pol_mask & 1) ? RT_POL_ORDINARY : RT_POL_EXTRAORDINARY;
+  R.pol[1] = RT_POL_EXTRAORDINARY;
+  R.has_cloak = n_cloaks > 0 ? 1 : 0;
+  R.pad = 0;
+  R.codes = nullptr;
+  R.rec = aux ? aux->rec : nullptr;
+  R.st = aux ? aux->status : nullptr;
+  R.code = aux ? aux->code : nullptr;
+  R.nsteps = aux ? aux->nsteps : nullptr;
+  return RT_OK;
+}
+
+int ws_reserve_for(Workspace &ws, const RenderJob &J) {
+  return ws_reserve(ws, J.chunk, J.chunk * J.R.ncl * J.R.npol, (int)J.cams.size());
+}
+
+// copy the job's camera records and colour table into the workspace
+// (synchronous: the host vectors may be freed afterwards)
+int upload_job(const RenderJob &J, const Workspace &ws, hipStream_t s) {
+  if (hipMemcpyAsync(ws.cams, J.cams.data(), sizeof(CamP) * J.cams.size(), hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(ws.table, J.table, sizeof(float) * 39, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(RT_E_DEVICE, "upload of camera records failed");
+  return RT_OK;
+}
+
+void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStream_t s, bool profile) {
+  const Table &T = ws.T;
+  RenderP R = J.R;
+  R.codes = ws.codes;
+  for (long long g0 = 0; g0 < J.total; g0 += J.chunk) {
+    R.g0 = g0;
+    R.g1 = std::min(J.total, g0 + J.chunk);
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, T.ctr, (int)C_COUNT);
+    hipLaunchKernelGGL(k_rd_gen, dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
+                       ws.cams, T, R);
+    if (J.n_cloaks) {
+      if (J.o.precision == RT_PREC_MIXED)
+        run_transit<true>(J.c, J.o, T, J.block, J.refill, J.grid, s, profile);
+      else
+        run_transit<false>(J.c, J.o, T, J.block, J.refill, J.grid, s, profile);
+      hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, J.rm, T, R);
+    }
+    long long nres = (R.g1 - R.g0) / R.spp * R.ncl * R.npol;
+    hipLaunchKernelGGL(k_rd_resolve, dim3(grid_for(nres, 256)), dim3(256), 0, s, R, ws.table, rgb,
+                       J.npix);
+  }
 }
 
 }  // namespace
@@ -1013,11 +1196,7 @@ int rt_profile_read(double *transit_ms, int64_t *launches) {
 
 int rt_release_workspace(void) {
   std::lock_guard<std::mutex> lk(g_ws_mu);
-  if (g_ws.base) {
-    (void)hipDeviceSynchronize();
-    (void)hipFree(g_ws.base);
-  }
-  g_ws = Workspace{};
+  ws_free(g_ws);
   return RT_OK;
 }
 
@@ -1035,7 +1214,7 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
   if (!in6 || !out6 || !opl || !status) return fail(RT_E_INVALID, "in6, out6, opl and status are required");
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_ws_mu);
-  e = ensure_workspace(n, 0, 0);
+  e = ws_reserve(g_ws, n, 0, 0);
   if (e) return e;
   const Table &T = g_ws.T;
   CloakP c = make_cloak(cloak->d);
@@ -1043,13 +1222,15 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
   int block = opts->block ? opts->block : 256;
   int refill = opts->refill_period ? opts->refill_period : 2;
   int kind = c.axis * 2 + pol;
+  unsigned int grid = o.precision == RT_PREC_MIXED ? transit_grid<true>(block) : transit_grid<false>(block);
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, T.ctr, (int)C_COUNT);
   hipLaunchKernelGGL(k_tb_entry, dim3(grid_for(n, 256)), dim3(256), 0, s, c, o, T, kind, (long long)n,
                      in6, out6, opl, status, hres, nsteps);
   e = launch_err("entry launch");
   if (e) return e;
-  e = o.precision == RT_PREC_MIXED ? run_transit<true>(c, o, T, block, refill, s)
-                                   : run_transit<false>(c, o, T, block, refill, s);
+  if (o.precision == RT_PREC_MIXED) run_transit<true>(c, o, T, block, refill, grid, s, true);
+  else run_transit<false>(c, o, T, block, refill, grid, s, true);
+  e = launch_err("transit launch");
   if (e) return e;
   hipLaunchKernelGGL(k_tb_finish, dim3(num_cu() * 8), dim3(256), 0, s, c, o, T, (long long)n, out6,
                      opl, status, hres, nsteps);
@@ -1059,136 +1240,130 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
 int rt_render_multi(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts,
                     const rt_room *room, const rt_camera *cams, int32_t n_cams, int32_t pol_mask,
                     float *rgb, const rt_render_aux *aux, void *stream) {
-  if (n_cloaks < 0 || n_cloaks > 2) return fail(RT_E_INVALID, "n_cloaks must be 0, 1 or 2");
-  if (n_cloaks > 0 && !cloaks) return fail(RT_E_INVALID, "cloaks is NULL");
-  for (int k = 0; k < n_cloaks; ++k)
-    if (!cloaks[k]) return fail(RT_E_INVALID, "cloak handle %d is NULL", k);
-  for (int k = 1; k < n_cloaks; ++k) {
-    const rt_cloak_desc &a = cloaks[0]->d, &b = cloaks[k]->d;
-    if (a.r1 != b.r1 || a.r2 != b.r2 || a.z0 != b.z0 || a.z1 != b.z1 || a.inner_mirror != b.inner_mirror)
-      return fail(RT_E_INVALID, "cloaks of one call must share r1, r2, z0, z1 and inner_mirror");
-  }
-  double r2 = n_cloaks ? cloaks[0]->d.r2 : 0.0;
-  int e = check_opts(opts, r2, false);
+  if (!rgb) return fail(RT_E_INVALID, "rgb is required");
+  RenderJob J;
+  int e = prepare_render(cloaks, n_cloaks, opts, room, cams, n_cams, pol_mask, aux, J);
   if (e) return e;
-  if (!room || !cams || !rgb) return fail(RT_E_INVALID, "room, cams and rgb are required");
-  if (n_cams < 1) return fail(RT_E_INVALID, "n_cams must be >= 1");
-  if (pol_mask < 1 || pol_mask > 3) return fail(RT_E_INVALID, "pol_mask must be 1, 2 or 3");
-  if (!(room->tile > 0.0)) return fail(RT_E_INVALID, "room tile must be > 0");
-  for (int k = 0; k < 3; ++k)
-    if (!(room->hi[k] > room->lo[k])) return fail(RT_E_INVALID, "room needs lo < hi");
-  const int w = cams[0].w, h = cams[0].h, spp = cams[0].spp;
-  int m = (int)std::lround(std::sqrt((double)spp));
-  if (w < 1 || h < 1 || spp < 1 || m * m != spp || spp > 256)
-    return fail(RT_E_INVALID, "camera needs w, h >= 1 and spp a perfect square <= 256");
-  for (int k = 1; k < n_cams; ++k)
-    if (cams[k].w != w || cams[k].h != h || cams[k].spp != spp)
-      return fail(RT_E_INVALID, "all cameras must share w, h and spp");
-  const long long npix = (long long)w * h;
-  const long long ns_img = npix * spp;
-  if (ns_img > (1LL << 30)) return fail(RT_E_INVALID, "w*h*spp must be <= 2^30");
-  const int npol = (pol_mask == 3) ? 2 : 1;
-  const int ncl = n_cloaks > 0 ? n_cloaks : 1;  // the empty room renders as one "cloak"
-
-  // host-side camera bases
-  CamP *hc = new (std::nothrow) CamP[n_cams];
-  if (!hc) return fail(RT_E_NOMEM, "host allocation failed");
-  for (int k = 0; k < n_cams; ++k) {
-    const rt_camera &C = cams[k];
-    double F[3], R[3], U[3];
-    for (int j = 0; j < 3; ++j) F[j] = C.look[j] - C.eye[j];
-    double fl = std::sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
-    if (!(fl > 0.0) || !(C.fov_deg > 0.0 && C.fov_deg < 180.0)) {
-      delete[] hc;
-      return fail(RT_E_INVALID, "camera %d: eye == look or fov outside (0, 180)", k);
-    }
-    for (int j = 0; j < 3; ++j) F[j] /= fl;
-    R[0] = F[1] * C.up[2] - F[2] * C.up[1];
-    R[1] = F[2] * C.up[0] - F[0] * C.up[2];
-    R[2] = F[0] * C.up[1] - F[1] * C.up[0];
-    double rl = std::sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
-    if (!(rl > 0.0)) {
-      delete[] hc;
-      return fail(RT_E_INVALID, "camera %d: up is parallel to the view direction", k);
-    }
-    for (int j = 0; j < 3; ++j) R[j] /= rl;
-    U[0] = R[1] * F[2] - R[2] * F[1];
-    U[1] = R[2] * F[0] - R[0] * F[2];
-    U[2] = R[0] * F[1] - R[1] * F[0];
-    CamP &P = hc[k];
-    for (int j = 0; j < 3; ++j) { P.eye[j] = C.eye[j]; P.F[j] = F[j]; P.R[j] = R[j]; P.U[j] = U[j]; }
-    P.tan_half = std::tan(0.5 * C.fov_deg * M_PI / 180.0);
-    P.aspect = (double)w / (double)h;
-    P.w = w; P.h = h; P.spp = spp; P.m = m;
-    P.seed = C.seed;
-  }
-  CloakP c{};
-  if (n_cloaks) c = make_cloak(cloaks[0]->d);
-  OptsP o = make_opts(*opts);
-  RoomP rm;
-  for (int j = 0; j < 3; ++j) { rm.lo[j] = room->lo[j]; rm.hi[j] = room->hi[j]; }
-  rm.tile = room->tile;
-  rm.inv_tile = 1.0 / room->tile;
-  float table[64] = {0};
-  for (int f = 0; f < 6; ++f)
-    for (int q = 0; q < 2; ++q)
-      for (int j = 0; j < 3; ++j) table[(f * 2 + q) * 3 + j] = room->rgb[f][q][j];
-
   hipStream_t s = (hipStream_t)stream;
-  const long long total = ns_img * n_cams;
-  const long long chunk_max = (1LL << 24) / spp * spp;
-  const long long chunk = std::min(total, std::max(chunk_max, (long long)spp));
   std::lock_guard<std::mutex> lk(g_ws_mu);
-  e = ensure_workspace(chunk, chunk * ncl * npol, n_cams);
-  if (e) { delete[] hc; return e; }
-  (void)hipMemcpyAsync(g_ws.cams, hc, sizeof(CamP) * n_cams, hipMemcpyHostToDevice, s);
-  (void)hipMemcpyAsync(g_ws.table, table, sizeof(float) * 39, hipMemcpyHostToDevice, s);
-  // the copies read host memory asynchronously: wait before freeing it
-  (void)hipStreamSynchronize(s);
-  delete[] hc;
-  const Table &T = g_ws.T;
-  int block = opts->block ? opts->block : 256;
-  int refill = opts->refill_period ? opts->refill_period : 2;
-  RenderP R;
-  R.ns_img = ns_img; R.n_cams = n_cams; R.ncl = ncl; R.npol = npol; R.spp = spp;
-  R.axis[0] = n_cloaks > 0 ? cloaks[0]->d.axis : 0;
-  R.axis[1] = n_cloaks > 1 ? cloaks[1]->d.axis : 0;
-  R.pol[0] = (pol_mask & 1) ? RT_POL_ORDINARY : RT_POL_EXTRAORDINARY;
-  R.pol[1] = RT_POL_EXTRAORDINARY;
-  R.has_cloak = n_cloaks > 0 ? 1 : 0;
-  R.pad = 0;
-  R.codes = g_ws.codes;
-  R.rec = aux ? aux->rec : nullptr;
-  R.st = aux ? aux->status : nullptr;
-  R.code = aux ? aux->code : nullptr;
-  R.nsteps = aux ? aux->nsteps : nullptr;
-  for (long long g0 = 0; g0 < total; g0 += chunk) {
-    R.g0 = g0;
-    R.g1 = std::min(total, g0 + chunk);
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, T.ctr, (int)C_COUNT);
-    hipLaunchKernelGGL(k_rd_gen, dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, c, o, rm,
-                       g_ws.cams, T, R);
-    e = launch_err("render generate launch");
-    if (e) return e;
-    if (n_cloaks) {
-      e = o.precision == RT_PREC_MIXED ? run_transit<true>(c, o, T, block, refill, s)
-                                       : run_transit<false>(c, o, T, block, refill, s);
-      if (e) return e;
-      hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, rm, T, R);
-    }
-    long long nres = (R.g1 - R.g0) / spp * ncl * npol;
-    hipLaunchKernelGGL(k_rd_resolve, dim3(grid_for(nres, 256)), dim3(256), 0, s, R, g_ws.table, rgb,
-                       npix);
-    e = launch_err("render finish launch");
-    if (e) return e;
-  }
-  return RT_OK;
+  e = ws_reserve_for(g_ws, J);
+  if (e) return e;
+  e = upload_job(J, g_ws, s);
+  if (e) return e;
+  enqueue_render(J, g_ws, rgb, s, true);
+  return launch_err("render launch");
 }
 
 int rt_render(rt_cloak cloak, const rt_trace_opts *opts, const rt_room *room, const rt_camera *cams,
               int32_t n_cams, int32_t pol_mask, float *rgb, const rt_render_aux *aux, void *stream) {
   return rt_render_multi(cloak ? &cloak : nullptr, cloak ? 1 : 0, opts, room, cams, n_cams, pol_mask,
                          rgb, aux, stream);
+}
+
+int rt_render_plan_create(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts,
+                          const rt_room *room, const rt_camera *cams, int32_t n_cams,
+                          int32_t pol_mask, float *rgb, const rt_render_aux *aux, rt_plan *out) {
+  if (!out) return fail(RT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!rgb) return fail(RT_E_INVALID, "rgb is required");
+  rt_plan p = new (std::nothrow) rt_plan_s;
+  if (!p) return fail(RT_E_NOMEM, "host allocation failed");
+  int e = prepare_render(cloaks, n_cloaks, opts, room, cams, n_cams, pol_mask, aux, p->J);
+  if (!e) e = ws_reserve_for(p->ws, p->J);
+  hipStream_t cs = nullptr;
+  if (!e && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+    e = fail(RT_E_DEVICE, "stream creation failed");
+  if (!e) e = upload_job(p->J, p->ws, cs);
+  if (!e) {
+    p->rgb = rgb;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      e = fail(RT_E_DEVICE, "stream capture failed to start");
+    } else {
+      enqueue_render(p->J, p->ws, rgb, cs, false);
+      hipGraph_t g = nullptr;
+      if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) {
+        e = fail(RT_E_DEVICE, "stream capture failed");
+      } else {
+        p->graph = g;
+        if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess)
+          e = fail(RT_E_DEVICE, "graph instantiation failed");
+      }
+    }
+  }
+  if (cs) (void)hipStreamDestroy(cs);
+  if (e) {
+    rt_render_plan_destroy(p);
+    return e;
+  }
+  *out = p;
+  return RT_OK;
+}
+
+int rt_render_plan_launch(rt_plan plan, void *stream) {
+  if (!plan || !plan->exec) return fail(RT_E_INVALID, "plan is NULL");
+  if (hipGraphLaunch(plan->exec, (hipStream_t)stream) != hipSuccess)
+    return fail(RT_E_DEVICE, "graph launch failed: %s", hipGetErrorString(hipGetLastError()));
+  return RT_OK;
+}
+
+int rt_render_plan_destroy(rt_plan plan) {
+  if (!plan) return RT_OK;
+  (void)hipDeviceSynchronize();
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  ws_free(plan->ws);
+  delete plan;
+  return RT_OK;
+}
+
+int rt_autotune_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts,
+                       const rt_room *room, const rt_camera *cams, int32_t n_cams, int32_t pol_mask,
+                       float *rgb, rt_trace_opts *tuned, double *best_ms) {
+  if (!rgb || !tuned) return fail(RT_E_INVALID, "rgb and tuned are required");
+  RenderJob J;
+  int e = prepare_render(cloaks, n_cloaks, opts, room, cams, n_cams, pol_mask, nullptr, J);
+  if (e) return e;
+  static const int blocks[] = {64, 128, 256};
+  static const int refills[] = {1, 2, 4, 8};
+  hipStream_t s = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&a) != hipSuccess ||
+      hipEventCreate(&b) != hipSuccess)
+    return fail(RT_E_DEVICE, "stream/event creation failed");
+  double best = 1e300;
+  int bb = J.block, br = J.refill;
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    e = ws_reserve_for(g_ws, J);
+    if (!e) e = upload_job(J, g_ws, s);
+    for (int bi = 0; !e && bi < 3; ++bi)
+      for (int ri = 0; !e && ri < 4; ++ri) {
+        J.block = blocks[bi];
+        J.refill = refills[ri];
+        J.grid = J.o.precision == RT_PREC_MIXED ? transit_grid<true>(J.block) : transit_grid<false>(J.block);
+        enqueue_render(J, g_ws, rgb, s, false);  // warm-up
+        (void)hipEventRecord(a, s);
+        for (int rep = 0; rep < 2; ++rep) enqueue_render(J, g_ws, rgb, s, false);
+        (void)hipEventRecord(b, s);
+        float ms = 0.f;
+        if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+          e = fail(RT_E_DEVICE, "timing failed");
+          break;
+        }
+        if (ms * 0.5 < best) { best = ms * 0.5; bb = J.block; br = J.refill; }
+      }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipStreamDestroy(s);
+  if (e) return e;
+  *tuned = *opts;
+  tuned->block = bb;
+  tuned->refill_period = br;
+  if (best_ms) *best_ms = best;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[J.key] = {bb, br};
+  return RT_OK;
 }
 
 }  // extern "C"

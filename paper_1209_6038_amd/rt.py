@@ -24,7 +24,9 @@ FP64, MIXED = 0, 1
 STATUS_NAMES = ["EXITED", "MISSED", "ABSORBED", "MAXSTEPS", "DIVERGED", "TIR", "INVALID", "REFLECTED"]
 
 EXPORTED = ["rt_build_cloak", "rt_free_cloak", "rt_trace_batch", "rt_render", "rt_render_multi",
-            "rt_profile_enable", "rt_profile_read", "rt_release_workspace", "rt_last_error"]
+            "rt_render_plan_create", "rt_render_plan_launch", "rt_render_plan_destroy",
+            "rt_autotune_render", "rt_profile_enable", "rt_profile_read", "rt_release_workspace",
+            "rt_last_error"]
 
 
 class RtError(RuntimeError):
@@ -84,6 +86,14 @@ def lib():
         L.rt_render_multi.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(TraceOpts),
                                       ctypes.POINTER(Room), ctypes.POINTER(Camera), i32, i32, vp,
                                       ctypes.POINTER(RenderAux), vp]
+        L.rt_render_plan_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(TraceOpts),
+                                            ctypes.POINTER(Room), ctypes.POINTER(Camera), i32, i32, vp,
+                                            ctypes.POINTER(RenderAux), ctypes.POINTER(vp)]
+        L.rt_render_plan_launch.argtypes = [vp, vp]
+        L.rt_render_plan_destroy.argtypes = [vp]
+        L.rt_autotune_render.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(TraceOpts),
+                                         ctypes.POINTER(Room), ctypes.POINTER(Camera), i32, i32, vp,
+                                         ctypes.POINTER(TraceOpts), ctypes.POINTER(ctypes.c_double)]
         L.rt_release_workspace.argtypes = []
         L.rt_profile_enable.argtypes = [i32]
         L.rt_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
@@ -248,6 +258,78 @@ def render(cloak, opts: dict, room_d: dict, cams: list, pol_mask: int, aux: bool
                            ctypes.byref(rm), carr, n, int(pol_mask), _ptr(rgb),
                            ctypes.byref(aux_s) if aux_s is not None else None, _stream()))
     return (rgb, aux_t) if aux else rgb
+
+
+def _alloc_render_outputs(ncl, cams, pol_mask, aux, out=None):
+    import torch
+    n = len(cams)
+    w, h, spp = int(cams[0]["w"]), int(cams[0]["h"]), int(cams[0].get("spp", 1))
+    npol = 2 if pol_mask == 3 else 1
+    dev = torch.device("cuda", torch.cuda.current_device())
+    rgb = out if out is not None else torch.empty((ncl, n, npol, h, w, 3), dtype=torch.float32,
+                                                  device=dev)
+    aux_t = aux_s = None
+    if aux:
+        ns = w * h * spp
+        aux_t = {"rec": torch.empty((ncl, n, npol, 7, ns), dtype=torch.float64, device=dev),
+                 "status": torch.empty((ncl, n, npol, ns), dtype=torch.int32, device=dev),
+                 "code": torch.empty((ncl, n, npol, ns), dtype=torch.uint8, device=dev),
+                 "nsteps": torch.empty((ncl, n, npol, ns), dtype=torch.int32, device=dev)}
+        aux_s = RenderAux(aux_t["rec"].data_ptr(), aux_t["status"].data_ptr(), aux_t["code"].data_ptr(),
+                          aux_t["nsteps"].data_ptr())
+    return rgb, aux_t, aux_s
+
+
+class RenderPlan:
+    """rt_render_plan_*: a batch of views captured once into a HIP graph.
+
+    Owns its output tensors (rgb, and aux if requested); launch() replays the
+    graph on torch's current stream and overwrites them."""
+
+    def __init__(self, cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: int,
+                 aux: bool = False):
+        self.rgb, self.aux, aux_s = _alloc_render_outputs(max(len(cloaks), 1), cams, pol_mask, aux)
+        carr = (Camera * len(cams))(*[camera(c) for c in cams])
+        harr = (ctypes.c_void_p * max(len(cloaks), 1))(*[c.handle for c in cloaks])
+        self._cloaks = list(cloaks)  # keep the handles alive with the plan
+        h = ctypes.c_void_p()
+        _check(lib().rt_render_plan_create(harr, len(cloaks), ctypes.byref(trace_opts(opts)),
+                                           ctypes.byref(room(room_d)), carr, len(cams), int(pol_mask),
+                                           _ptr(self.rgb),
+                                           ctypes.byref(aux_s) if aux_s is not None else None,
+                                           ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self):
+        _check(lib().rt_render_plan_launch(self.handle, _stream()))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().rt_render_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune_render(cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: int):
+    """rt_autotune_render: returns (opts with the fastest block/refill_period,
+    best milliseconds per render)."""
+    rgb, _, _ = _alloc_render_outputs(max(len(cloaks), 1), cams, pol_mask, False)
+    carr = (Camera * len(cams))(*[camera(c) for c in cams])
+    harr = (ctypes.c_void_p * max(len(cloaks), 1))(*[c.handle for c in cloaks])
+    tuned = TraceOpts()
+    ms = ctypes.c_double()
+    _check(lib().rt_autotune_render(harr, len(cloaks), ctypes.byref(trace_opts(opts)),
+                                    ctypes.byref(room(room_d)), carr, len(cams), int(pol_mask),
+                                    _ptr(rgb), ctypes.byref(tuned), ctypes.byref(ms)))
+    out = dict(opts)
+    out["block"] = tuned.block
+    out["refill_period"] = tuned.refill_period
+    return out, ms.value
 
 
 def profile_enable(on: bool = True):
