@@ -1,0 +1,65 @@
+"""Pins of the FP64 MLP reference used to check the GPU surrogate kernels."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+
+def test_bf16_rounding_definition():
+    # exactly representable values stay; halfway cases round to even
+    x = np.array([1.0, -2.5, 0.15625, 2.0 ** 127, 0.0], dtype=np.float32)
+    np.testing.assert_array_equal(mlp.to_bf16(x), x.astype(np.float64))
+    one_plus = np.float32(1.0) + np.float32(2.0 ** -8)   # halfway between 1 and 1+2^-7: ties to even (1)
+    assert mlp.to_bf16(np.array([one_plus]))[0] == 1.0
+    three_q = np.float32(1.0) + np.float32(3 * 2.0 ** -8)  # halfway, rounds up to even 1+2^-6
+    assert mlp.to_bf16(np.array([three_q]))[0] == 1.0 + 2.0 ** -6
+    assert mlp.to_bf16(np.array([1.0 + 2.0 ** -9], dtype=np.float32))[0] == 1.0
+
+
+def test_forward_matches_torch_cpu():
+    import torch
+    p = mlp.init_params(3)
+    x = np.random.default_rng(4).normal(size=(17, 6))
+    y, _ = mlp.forward(p, x)
+    layers = []
+    for i in range(5):
+        lin = torch.nn.Linear(mlp.SIZES[i], mlp.SIZES[i + 1], dtype=torch.float64)
+        with torch.no_grad():
+            lin.weight.copy_(torch.from_numpy(p[2 * i].T))
+            lin.bias.copy_(torch.from_numpy(p[2 * i + 1]))
+        layers.append(lin)
+        if i < 4:
+            layers.append(torch.nn.SiLU())
+    net = torch.nn.Sequential(*layers)
+    with torch.no_grad():
+        yt = net(torch.from_numpy(x)).numpy()
+    np.testing.assert_allclose(y, yt, rtol=1e-12, atol=1e-13)
+
+
+def test_backward_matches_finite_differences():
+    p = mlp.init_params(5)
+    rng = np.random.default_rng(6)
+    x = rng.normal(size=(9, 6))
+    t = rng.normal(size=(9, 5))
+    w = np.array([1.0, 2.0, 0.5, 1.0, 3.0])
+    loss, g = mlp.loss_and_grads(p, x, t, w)
+    eps = 1e-6
+    for li in range(10):
+        P = p[li]
+        flat_idx = rng.choice(P.size, 4, replace=False)
+        for fi in flat_idx:
+            idx = np.unravel_index(fi, P.shape)
+            old = P[idx]
+            P[idx] = old + eps
+            lp, _ = mlp.loss_and_grads(p, x, t, w)
+            P[idx] = old - eps
+            lm, _ = mlp.loss_and_grads(p, x, t, w)
+            P[idx] = old
+            fd = (lp - lm) / (2 * eps)
+            assert g[li][idx] == pytest.approx(fd, rel=2e-5, abs=1e-8), (li, idx)
+
+
+def test_silu_derivative():
+    z = np.linspace(-8, 8, 33)
+    fd = (mlp.silu(z + 1e-6) - mlp.silu(z - 1e-6)) / 2e-6
+    np.testing.assert_allclose(mlp.silu_grad(z), fd, rtol=1e-7, atol=1e-9)
