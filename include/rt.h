@@ -57,6 +57,7 @@ enum {
 
 typedef struct rt_cloak_s *rt_cloak;
 typedef struct rt_plan_s *rt_plan;
+typedef struct rt_model_s *rt_model;
 
 /* Cloak geometry and material (Sect. 4, Eqs. (13)-(15)). The material fills
    r1 <= r <= r2, z0 <= z <= z1 (z0 = -INFINITY, z1 = +INFINITY: infinitely
@@ -212,6 +213,130 @@ int rt_render_plan_destroy(rt_plan plan);
 int rt_autotune_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts,
                        const rt_room *room, const rt_camera *cams, int32_t n_cams, int32_t pol_mask,
                        float *rgb, rt_trace_opts *tuned, double *best_ms);
+
+/* Descriptor a handle was built from. */
+int rt_cloak_get_desc(rt_cloak cloak, rt_cloak_desc *out);
+
+/* ---------------------------------------------------------------------------
+   Transit in entry/exit parameters. A ray enters the cloak through its side
+   r = r2 at azimuth phi and height z, travelling with horizontal angle alpha
+   to the inward normal (positive towards +theta) and elevation beta; it
+   leaves (after the transit of rt_trace_batch: Sects. 2-4) on the outgoing
+   ray, described at its crossing of r = r2 by azimuth phi', height z',
+   horizontal angle alpha' to the outward normal and elevation beta', and T,
+   the optical path from the entry point to that crossing (Eqs. (2)/(8) time,
+   App. of units: c0 = omega = 1). For a side-to-side transit the wave
+   numbers along the surface are conserved (Sect. 3 at both interfaces, and
+   p_theta, p_z of the cylindrical metric in between), so alpha' = alpha and
+   beta' = beta.
+     x6:  float32 SoA 6 x ld (rows 0..n-1 used): phi, z, alpha, beta, the
+          branch bit (0 ordinary, 1 extraordinary) and the optic-axis bit
+          (0 radial Eq. (14), 1 azimuthal Eq. (15)); |alpha|, |beta| < pi/2
+     y5:  float32 SoA 5 x ld: phi' in [0, 2 pi), z', alpha', beta', T
+   --------------------------------------------------------------------------- */
+
+/* Exact transit of every ray (or of the rays with mask[i] != 0; the others'
+   outputs are left untouched) by the integrator of rt_trace_batch, all
+   (axis, branch) pairs in one persistent launch.
+   cloaks: 1 or 2 handles with different optic axes sharing r1, r2, z0, z1,
+   inner_mirror; a ray whose axis bit has no handle is RT_RAY_INVALID.
+   status: n int32 (RT_RAY_*); y5 is NaN for rays that did not leave.
+   nsteps: n int32 or NULL. r_out in opts is ignored. Errors as
+   rt_trace_batch; n <= 2^28. */
+int rt_transit_exact(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts, int64_t n,
+                     int64_t ld, const float *x6, const uint8_t *mask, float *y5, int32_t *status,
+                     int32_t *nsteps, void *stream);
+
+/* ---------------------------------------------------------------------------
+   Learned surrogate of the transit (not part of the paper): an MLP
+   6 -> 256 -> 256 -> 256 -> 256 -> 5 with SiLU, layers 2-4 on BF16 matrix
+   cores with FP32 accumulation, layers 1 and 5 in FP32. It predicts the
+   targets (t0..t4) of a transit:
+     t0 = dtheta - base, t1 = (z' - z) cos(beta) / 2 r2, t2 = alpha' - alpha,
+     t3 = beta' - beta,  t4 = T cos(beta) / 2 r2,
+   where dtheta is the signed azimuth the ray sweeps (sign of alpha) and
+   base = sign(alpha) pi for the azimuthal cloak's extraordinary branch, 0
+   otherwise. A model belongs to the device current at its creation; calls on
+   one model must not overlap (they share its activation buffers). Arrays are
+   device pointers unless stated; n <= 2^24, ld >= n.
+   --------------------------------------------------------------------------- */
+typedef struct {
+    float lr, beta1, beta2, eps, weight_decay;  /* AdamW */
+    float huber;  /* loss per element: 0 = squared error; delta > 0 = Huber (quadratic to delta) */
+} rt_train_opts;
+
+/* Gate of rt_surrogate_infer: a prediction is replaced by the exact transit
+   when its (axis, branch, alpha, beta) cell of the trust map is untrusted,
+   when the predicted exit violates the conservation of the tangential wave
+   numbers (max(|k_theta' - k_theta|, |k_z' - k_z|)) by more than hres_max,
+   or when the predicted exit height is within cap_margin of an end cap. */
+typedef struct {
+    double tol;         /* calibration: largest exit error a trusted cell may show */
+    double hres_max;    /* conservation residual limit */
+    double cap_margin;  /* exit-height margin from the caps */
+    int32_t min_count;  /* calibration rays a cell needs to be trusted */
+    int32_t reserved;
+} rt_gate_opts;
+
+/* New model with weights and biases uniform in +-1/sqrt(fan_in) (seeded),
+   identity scaling and no trusted cells. */
+int rt_surrogate_create(uint64_t seed, rt_model *out);
+int rt_surrogate_free(rt_model model);
+int rt_surrogate_nparams(int64_t *count);  /* 200,453 */
+/* FP32 parameters in host memory: W1 [6][256], b1, W2 [256][256], b2, W3,
+   b3, W4, b4, W5 [256][5], b5, each weight (fan_in, fan_out) row-major.
+   set_params also resets the optimizer state. Synchronous. */
+int rt_surrogate_get_params(rt_model model, float *host);
+int rt_surrogate_set_params(rt_model model, const float *host);
+/* Standardization (host, 22 floats): in_off[6], in_scale[6] (input k enters
+   as (x_k - in_off_k) in_scale_k), out_mean[5], out_std[5] (the network's
+   output o is (t_o - out_mean_o) / out_std_o). Synchronous. */
+int rt_surrogate_get_scaling(rt_model model, float *scaling22);
+int rt_surrogate_set_scaling(rt_model model, const float *scaling22);
+/* Set the standardization from the weighted moments of x6 and t5 (rows
+   with w = 0 ignored, w NULL = all ones); out_std is floored at 1e-3.
+   Synchronous. */
+int rt_surrogate_fit_scaling(rt_model model, int64_t n, int64_t ld, const float *x6, const float *t5,
+                             const float *w, void *stream);
+/* Training targets of transits: t5 (SoA 5 x ld) from the entries x6 and the
+   exact exits y5/status of rt_transit_exact; w[i] = 1 for a finished
+   side-to-side transit, 0 otherwise (its t5 entries are 0). */
+int rt_surrogate_encode(const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int64_t ld, const float *x6,
+                        const float *y5, const int32_t *status, float *t5, float *w, void *stream);
+/* Loss L = (1/n) sum_i w_i sum_o rho(y_io - (t_io - out_mean_o)/out_std_o)
+   of one batch (w NULL = all ones) and its gradient, rho(d) = d^2, or for
+   huber = delta > 0 the Huber function (d^2 up to |d| = delta, then
+   2 delta |d| - delta^2). grads: NPARAM floats (device, same layout as
+   get_params) or NULL; loss: 1 float (device) or NULL. */
+int rt_surrogate_grad(rt_model model, int64_t n, int64_t ld, const float *x6, const float *t5, const float *w,
+                      float huber, float *grads, float *loss, void *stream);
+/* One AdamW step on a batch (bias-corrected moments, decoupled weight
+   decay on the weights only). */
+int rt_surrogate_train(rt_model model, int64_t n, int64_t ld, const float *x6, const float *t5, const float *w,
+                       const rt_train_opts *opts, float *loss, void *stream);
+/* Network prediction of the targets, de-standardized: t5 SoA 5 x ld. */
+int rt_surrogate_forward(rt_model model, int64_t n, int64_t ld, const float *x6, float *t5, void *stream);
+/* Build the trust map: predicts the calibration rays x6, measures each
+   one's exit error max(|x - x_exact| / r2, angle(d, d_exact)) against the
+   exact exits, and trusts a cell when it holds >= min_count rays, all of
+   them side-to-side transits with error <= tol. Stores `gate` in the model.
+   trusted_fraction (host, may be NULL): share of trusted cells. Synchronous. */
+int rt_surrogate_calibrate(rt_model model, const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int64_t ld,
+                           const float *x6, const float *y5_exact, const int32_t *status_exact,
+                           const rt_gate_opts *gate, double *trusted_fraction, void *stream);
+/* Trust map (host, 4 x cells_alpha x cells_beta bytes, (axis*2+branch)
+   major, uniform cells over (-pi/2, pi/2)^2); host may be NULL. */
+int rt_surrogate_get_map(rt_model model, uint8_t *host, int32_t *cells_alpha, int32_t *cells_beta);
+/* Surrogate transit with exact fallback: y5/status as rt_transit_exact.
+   fallback[i] (n bytes) = 1 where the gate rejected the prediction and the
+   exact integrator traced the ray, 0 where y5 is the network's. Needs a
+   calibrated model. */
+int rt_surrogate_infer(rt_model model, const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts,
+                       int64_t n, int64_t ld, const float *x6, float *y5, uint8_t *fallback, int32_t *status,
+                       void *stream);
+/* Model file: parameters, scaling, gate and trust map. */
+int rt_surrogate_save(rt_model model, const char *path);
+int rt_surrogate_load(const char *path, rt_model *out);
 
 /* Release the library's device workspace (synchronizes the device first). */
 int rt_release_workspace(void);

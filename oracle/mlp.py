@@ -5,19 +5,20 @@ The surrogate is not part of the paper; this module is pinned by finite
 differences (backward against forward) and by torch.nn on the CPU (forward).
 
 Precision model of the GPU path, reproduced here when bf16=True:
-  layer 1 (6 inputs) in FP32 on the vector units: z1 = x W1 + b1
-  layers 2..5 on BF16 matrix cores with FP32 accumulation: the activations
-  and weights are rounded to BF16 (round to nearest even) before each
-  product, products and sums are exact here (FP64) and only the final FP32
-  rounding order differs from the GPU.
-Backward uses the same rounding points: the incoming gradient of a BF16
-product is rounded to BF16, weight gradients are accumulated in FP64 here.
+  layers 1 (6 -> 256) and 5 (256 -> 5) in FP32 on the vector units: no
+  rounding of operands (FP64 here),
+  layers 2..4 (256 -> 256) on BF16 matrix cores with FP32 accumulation: the
+  activations and weights are rounded to BF16 (round to nearest even)
+  before each product; products and sums are exact here (FP64).
+Backward uses the same rounding points: the gradient entering a BF16
+product is rounded to BF16; weight gradients are accumulated in FP64 here.
 """
 from __future__ import annotations
 
 import numpy as np
 
 SIZES = [6, 256, 256, 256, 256, 5]
+BF16_LAYERS = (1, 2, 3)  # 0-based: the three 256 x 256 layers
 
 
 def to_bf16(a):
@@ -60,10 +61,10 @@ def forward(params, x, bf16=False):
     h = acts[0]
     for i in range(5):
         W, b = params[2 * i], params[2 * i + 1]
-        if i == 0:
-            z = h @ W + b  # FP32 vector layer on the GPU
-        else:
+        if i in BF16_LAYERS:
             z = r(h) @ r(W) + b
+        else:
+            z = h @ W + b  # FP32 vector layer on the GPU
         zs.append(z)
         if i < 4:
             h = silu(z)
@@ -73,25 +74,28 @@ def forward(params, x, bf16=False):
     return h, (zs, acts)
 
 
-def loss_and_grads(params, x, t, w=None, bf16=False):
-    """Mean over the batch of sum_o w_o (y_o - t_o)^2 and its gradients."""
+def loss_and_grads(params, x, t, w=None, bf16=False, huber=0.0):
+    """Mean over the batch of sum_o w_o rho(y_o - t_o) and its gradients,
+    rho(d) = d^2, or the Huber function for huber = delta > 0 (d^2 for
+    |d| <= delta, 2 delta |d| - delta^2 beyond)."""
     n = x.shape[0]
     w = np.ones(5) if w is None else np.asarray(w, dtype=np.float64)
     y, (zs, acts) = forward(params, x, bf16)
     d = y - t
-    loss = float((w * d * d).sum() / n)
+    big = (huber > 0) & (np.abs(d) > huber)
+    rho = np.where(big, 2.0 * huber * np.abs(d) - huber * huber, d * d)
+    drho = np.where(big, 2.0 * huber * np.sign(d), 2.0 * d)
+    loss = float((w * rho).sum() / n)
     r = to_bf16 if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     grads = [None] * 10
-    g = 2.0 * w * d / n  # dL/dz5
+    g = w * drho / n  # dL/dz5
     for i in range(4, -1, -1):
         W = params[2 * i]
         a_in = acts[i]
-        if i == 0:
-            grads[0] = a_in.T @ g
-        else:
-            grads[2 * i] = r(a_in).T @ r(g)
+        q = r if i in BF16_LAYERS else (lambda a: a)
+        grads[2 * i] = q(a_in).T @ q(g)
         grads[2 * i + 1] = g.sum(axis=0)
         if i > 0:
-            da = r(g) @ r(W).T
+            da = q(g) @ q(W).T
             g = da * silu_grad(zs[i - 1])
     return loss, grads

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librt_cloak.so")
-SOURCES = [os.path.join(HERE, "csrc", "rt_cloak.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "rt_cloak.hip"), os.path.join(HERE, "csrc", "surrogate.hip")]
 HEADERS = [os.path.join(HERE, "csrc", "device.h"), os.path.join(ROOT, "include", "rt.h")]
 
 HIPCC_FLAGS = [

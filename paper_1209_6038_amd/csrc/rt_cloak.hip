@@ -590,6 +590,100 @@ __global__ void __launch_bounds__(256) k_tb_finish(CloakP c, OptsP o, Table T, l
   }
 }
 
+// rt_transit_exact entry: ray i enters through the side r = b at azimuth
+// phi, height z, with horizontal angle alpha to the inward normal and
+// elevation beta; its (cloak axis, branch) pair picks segment and metric.
+// Rays outside the mask are skipped; invalid rays are finished at once.
+__global__ void __launch_bounds__(256) k_sx_entry(CloakP c, OptsP o, Table T, long long n, long long ld,
+                                                  const float *__restrict__ x6,
+                                                  const unsigned char *__restrict__ mask, int have_axes,
+                                                  float *__restrict__ y5, int *__restrict__ status,
+                                                  int *__restrict__ nsteps) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  bool entered = false;
+  double x[3], v[3];
+  int kind = 0, skey = 0;
+  if (i < n && (!mask || mask[i])) {
+    const double phi = x6[i], z = x6[ld + i], al = x6[2 * ld + i], be = x6[3 * ld + i];
+    const float pol = x6[4 * ld + i], axis = x6[5 * ld + i];
+    bool ok = isfinite(phi) && isfinite(z) && fabs(al) < 0.5 * M_PI && fabs(be) < 0.5 * M_PI &&
+              z >= c.z0 && z <= c.z1 && (pol == 0.0f || pol == 1.0f) && (axis == 0.0f || axis == 1.0f);
+    if (ok) {
+      kind = (axis == 0.0f ? 0 : 2) + (pol == 0.0f ? 0 : 1);
+      ok = (have_axes >> (kind >> 1)) & 1;
+    }
+    int st = RT_RAY_INVALID;
+    if (ok) {
+      double sp, cp, sa, ca, sb, cb;
+      sincos(phi, &sp, &cp);
+      sincos(al, &sa, &ca);
+      sincos(be, &sb, &cb);
+      x[0] = c.b * cp; x[1] = c.b * sp; x[2] = z;
+      // d = cos(beta) (cos(alpha) (-r) + sin(alpha) theta) + sin(beta) z
+      const double d[3] = {cb * (-ca * cp - sa * sp), cb * (-ca * sp + sa * cp), sb};
+      if (refract_in(c, kind, B_SIDE, x, d, v)) {
+        entered = true;
+        skey = sort_key(c, kind, x, d);
+      } else {
+        st = RT_RAY_REFLECTED;
+      }
+    }
+    if (!entered) {
+      for (int j = 0; j < 5; ++j) y5[j * ld + i] = __builtin_nanf("");
+      status[i] = st;
+      if (nsteps) nsteps[i] = 0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const bool want = entered && kind == q;
+    unsigned int sl = wave_append(T.ctr + C_N + q, want);
+    if (want) put_slot(T, (int)(q * T.cap + sl), x, v, q, i, 0.0, o.h0, skey);
+  }
+}
+
+// rt_transit_exact finish: vacuum leg of the outgoing ray back to r = b
+// (zero for side exits) and its exit parameters
+__global__ void __launch_bounds__(256) k_sx_finish(CloakP c, Table T, long long ld, float *__restrict__ y5,
+                                                   int *__restrict__ status, int *__restrict__ nsteps) {
+  const SegMap m = seg_map(T);
+  const unsigned int n = m.off[NSEG];
+  unsigned int stride = gridDim.x * blockDim.x;
+  for (unsigned int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
+    int seg;
+    int s = slot_at(T, m, idx, seg);
+    long long i = T.key[s];
+    int st = T.status[s];
+    float out[5];
+    if (st == RT_RAY_EXITED) {
+      double x[3], v[3];
+      load_state(T, s, x, v);
+      double w = rsq64(fma(v[0], v[0], fma(v[1], v[1], v[2] * v[2])));
+#pragma unroll
+      for (int j = 0; j < 3; ++j) v[j] *= w;
+      double sl = leave_radius(x, v, c.b);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) x[j] = fma(sl, v[j], x[j]);
+      double phi = atan2(x[1], x[0]);
+      if (phi < 0.0) phi += 2.0 * M_PI;
+      double rl = rsq64(fma(x[0], x[0], x[1] * x[1]));
+      double vr = (x[0] * v[0] + x[1] * v[1]) * rl, vt = (x[0] * v[1] - x[1] * v[0]) * rl;
+      out[0] = (float)phi;
+      out[1] = (float)x[2];
+      out[2] = (float)atan2(vt, vr);
+      out[3] = (float)asin(fmin(1.0, fmax(-1.0, v[2])));
+      out[4] = (float)(T.opl0[s] + T.t[s] + sl);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 5; ++j) out[j] = __builtin_nanf("");
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) y5[j * ld + i] = out[j];
+    status[i] = st;
+    if (nsteps) nsteps[i] = T.nsteps[s];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // render kernels
 // ---------------------------------------------------------------------------
@@ -1145,6 +1239,8 @@ void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStre
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+void rt_set_error_message(const char *msg) { g_err = msg; }
+
 extern "C" {
 
 const char *rt_last_error(void) { return g_err.c_str(); }
@@ -1158,6 +1254,12 @@ int rt_build_cloak(const rt_cloak_desc *desc, rt_cloak *out) {
   if (!h) return fail(RT_E_NOMEM, "host allocation failed");
   h->d = *desc;
   *out = h;
+  return RT_OK;
+}
+
+int rt_cloak_get_desc(rt_cloak cloak, rt_cloak_desc *out) {
+  if (!cloak || !out) return fail(RT_E_INVALID, "cloak and out are required");
+  *out = cloak->d;
   return RT_OK;
 }
 
@@ -1234,6 +1336,51 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
   if (e) return e;
   hipLaunchKernelGGL(k_tb_finish, dim3(num_cu() * 8), dim3(256), 0, s, c, o, T, (long long)n, out6,
                      opl, status, hres, nsteps);
+  return launch_err("finish launch");
+}
+
+int rt_transit_exact(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts, int64_t n,
+                     int64_t ld, const float *x6, const uint8_t *mask, float *y5, int32_t *status,
+                     int32_t *nsteps, void *stream) {
+  if (n_cloaks < 1 || n_cloaks > 2 || !cloaks) return fail(RT_E_INVALID, "need 1 or 2 cloak handles");
+  for (int k = 0; k < n_cloaks; ++k)
+    if (!cloaks[k]) return fail(RT_E_INVALID, "cloak handle %d is NULL", k);
+  int have_axes = 0;
+  for (int k = 0; k < n_cloaks; ++k) {
+    const rt_cloak_desc &a = cloaks[0]->d, &b = cloaks[k]->d;
+    if (a.r1 != b.r1 || a.r2 != b.r2 || a.z0 != b.z0 || a.z1 != b.z1 || a.inner_mirror != b.inner_mirror)
+      return fail(RT_E_INVALID, "cloaks of one call must share r1, r2, z0, z1 and inner_mirror");
+    if (have_axes & (1 << b.axis)) return fail(RT_E_INVALID, "two cloaks with the same optic axis");
+    have_axes |= 1 << b.axis;
+  }
+  int e = check_opts(opts, cloaks[0]->d.r2, false);
+  if (e) return e;
+  if (n < 0) return fail(RT_E_INVALID, "n must be >= 0");
+  if (n == 0) return RT_OK;
+  if (n > (1LL << 28)) return fail(RT_E_INVALID, "n must be <= 2^28 per call");
+  if (ld < n) return fail(RT_E_INVALID, "ld must be >= n");
+  if (!x6 || !y5 || !status) return fail(RT_E_INVALID, "x6, y5 and status are required");
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  e = ws_reserve(g_ws, n, 0, 0);
+  if (e) return e;
+  const Table &T = g_ws.T;
+  CloakP c = make_cloak(cloaks[0]->d);
+  OptsP o = make_opts(*opts);
+  int block = opts->block ? opts->block : 256;
+  int refill = opts->refill_period ? opts->refill_period : 2;
+  unsigned int grid = o.precision == RT_PREC_MIXED ? transit_grid<true>(block) : transit_grid<false>(block);
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, T.ctr, (int)C_COUNT);
+  hipLaunchKernelGGL(k_sx_entry, dim3(grid_for(n, 256)), dim3(256), 0, s, c, o, T, (long long)n,
+                     (long long)ld, x6, mask, have_axes, y5, status, nsteps);
+  e = launch_err("entry launch");
+  if (e) return e;
+  if (o.precision == RT_PREC_MIXED) run_transit<true>(c, o, T, block, refill, grid, s, true);
+  else run_transit<false>(c, o, T, block, refill, grid, s, true);
+  e = launch_err("transit launch");
+  if (e) return e;
+  hipLaunchKernelGGL(k_sx_finish, dim3(num_cu() * 8), dim3(256), 0, s, c, T, (long long)ld, y5, status,
+                     nsteps);
   return launch_err("finish launch");
 }
 

@@ -1,0 +1,1305 @@
+// surrogate.hip -- multilayer-perceptron surrogate of the cloak transit:
+// entry ray on the outer cylinder -> exit ray and optical path length.
+//
+// Network: 6 inputs -> 256 -> 256 -> 256 -> 256 -> 5 outputs, SiLU after the
+// four hidden layers; inputs and targets are standardized with offsets and
+// scales stored in the model. Precision by layer:
+//   layer 1 (6 -> 256) and layer 5 (256 -> 5): FP32 on the vector units
+//     (too thin for matrix cores; FP32 keeps the inputs' and outputs'
+//     precision),
+//   layers 2-4 (256 -> 256, 98% of the flops): BF16 x BF16 products with
+//     FP32 accumulation on MFMA (v_mfma_f32_16x16x32_bf16).
+// Training minimizes the mean squared error of the standardized targets
+// with AdamW on FP32 master weights; the BF16 copies of W2..W4 are refreshed
+// after every step.
+//
+// The surrogate is not part of the paper. The exact integrator
+// (rt_transit_exact) labels its training data, judges its error, and
+// replaces its prediction wherever the gate rejects it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "../../include/rt.h"
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace sg {
+
+constexpr int NIN = 6, HID = 256, NOUT = 5;
+// FP32 parameter vector, weights stored (fan_in, fan_out) row-major:
+// W1 [6][256], b1, W2 [256][256], b2, W3, b3, W4, b4, W5 [256][5], b5 [5]
+constexpr long long OFF_W1 = 0;
+constexpr long long OFF_B1 = OFF_W1 + NIN * HID;
+constexpr long long OFF_W2 = OFF_B1 + HID;
+constexpr long long OFF_B2 = OFF_W2 + HID * HID;
+constexpr long long OFF_W3 = OFF_B2 + HID;
+constexpr long long OFF_B3 = OFF_W3 + HID * HID;
+constexpr long long OFF_W4 = OFF_B3 + HID;
+constexpr long long OFF_B4 = OFF_W4 + HID * HID;
+constexpr long long OFF_W5 = OFF_B4 + HID;
+constexpr long long OFF_B5 = OFF_W5 + HID * NOUT;
+constexpr long long NPARAM = OFF_B5 + NOUT;  // 200,453
+// BF16 copies of W2, W3, W4, each transposed to [out][in] so that the 8
+// consecutive inputs an MFMA lane needs for one output are one 16-byte load
+constexpr long long NBF = 3LL * HID * HID;
+// scaling block: in_off[6], in_scale[6], out_mean[5], out_std[5], then the loss
+constexpr int S_INOFF = 0, S_INSCALE = 6, S_OMEAN = 12, S_OSTD = 17, S_LOSS = 22, NSCAL = 24;
+// trust map: (axis, branch) x alpha cells x beta cells
+constexpr int NCELL_A = 128, NCELL_B = 128, NCOMBO = 4;
+constexpr int NCELLS = NCOMBO * NCELL_A * NCELL_B;
+constexpr float OUT_STD_FLOOR = 1e-3f;
+constexpr float PI_F = 3.14159265358979f;
+
+}  // namespace sg
+
+// the library's thread-local error message (shared with the tracer)
+void rt_set_error_message(const char *msg);
+
+namespace sg {
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  rt_set_error_message(buf);
+  return code;
+}
+
+__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float dsilu_f(float z) {
+  float s = 1.0f / (1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+// ---------------------------------------------------------------------------
+// Tiled GEMM on MFMA: C(M x N) = A(M x K) B(K x N) with strided operands
+// (A(i,k) = A[i*sa0 + k*sa1], B(k,j) = B[k*sb0 + j*sb1]), BF16 in, FP32
+// accumulation. 64 x 64 tile per 256-thread block (4 waves of 32 x 32, each
+// 2 x 2 MFMA 16x16x32 tiles), K in steps of 32 staged through LDS. Split-K
+// over blockIdx.z (each z-slice covers `kchunk` of K) with atomic FP32 sums.
+// Epilogues:
+//   EPI_BIAS_SILU  z = acc + bias: Cf <- z, Cb <- bf16(silu z), Ca <- silu z
+//   EPI_DSILU      g = acc * silu'(Z): Cf <- g, Cb <- bf16(g)
+//   EPI_ATOMIC     Cf += acc
+// (each output pointer may be NULL)
+// ---------------------------------------------------------------------------
+enum { EPI_BIAS_SILU = 0, EPI_DSILU = 1, EPI_ATOMIC = 2 };
+
+struct Gemm {
+  const bf16 *A;
+  long long sa0, sa1;
+  const bf16 *B;
+  long long sb0, sb1;
+  int M, N, K, kchunk, epi;
+  const float *bias;
+  const float *Z;
+  long long ldz;
+  float *Cf;
+  long long ldcf;
+  bf16 *Cb;
+  long long ldcb;
+  float *Ca;
+  long long ldca;
+};
+
+__global__ void __launch_bounds__(256) k_gemm(Gemm g) {
+  __shared__ bf16 As[64][40];  // [row][k], padded rows
+  __shared__ bf16 Bs[64][40];  // [col][k]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;  // row tiles on x (up to 2^31 blocks)
+  const int kbeg = blockIdx.z * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
+  const bool a_rowmajor = g.sa1 == 1, b_colmajor = g.sb0 == 1;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kbeg; k0 < kend; k0 += 32) {
+    // the element order follows each operand's unit stride (coalesced loads)
+    for (int e = tid; e < 64 * 32; e += 256) {
+      int r, kk;
+      if (a_rowmajor) { r = e >> 5; kk = e & 31; } else { kk = e >> 6; r = e & 63; }
+      const int gi = row0 + r, gk = k0 + kk;
+      As[r][kk] = (gi < g.M && gk < kend) ? g.A[gi * g.sa0 + gk * g.sa1] : (bf16)0.0f;
+    }
+    for (int e = tid; e < 64 * 32; e += 256) {
+      int cc, kk;
+      if (b_colmajor) { cc = e >> 5; kk = e & 31; } else { kk = e >> 6; cc = e & 63; }
+      const int gj = col0 + cc, gk = k0 + kk;
+      Bs[cc][kk] = (gj < g.N && gk < kend) ? g.B[gk * g.sb0 + gj * g.sb1] : (bf16)0.0f;
+    }
+    __syncthreads();
+    // operand layout of v_mfma_f32_16x16x32_bf16: lane l holds
+    // A[l%16][8*(l/16) + j] and B[8*(l/16) + j][l%16], j = 0..7
+    bf16x8 af[2], bfr[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int r = wm * 32 + t * 16 + (lane & 15);
+      const int c = wn * 32 + t * 16 + (lane & 15);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        af[t][j] = As[r][8 * (lane >> 4) + j];
+        bfr[t][j] = Bs[c][8 * (lane >> 4) + j];
+      }
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ti], bfr[tj], acc[ti][tj], 0, 0, 0);
+    __syncthreads();
+  }
+  // result layout: lane l holds D[4*(l/16) + i][l%16], i = 0..3
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wm * 32 + ti * 16 + 4 * (lane >> 4) + r;
+        const int col = col0 + wn * 32 + tj * 16 + (lane & 15);
+        if (row >= g.M || col >= g.N) continue;
+        const float y = acc[ti][tj][r];
+        if (g.epi == EPI_ATOMIC) {
+          atomicAdd(&g.Cf[row * g.ldcf + col], y);
+        } else if (g.epi == EPI_DSILU) {
+          const float d = y * dsilu_f(g.Z[row * g.ldz + col]);
+          if (g.Cf) g.Cf[row * g.ldcf + col] = d;
+          if (g.Cb) g.Cb[row * g.ldcb + col] = (bf16)d;
+        } else {
+          const float z = y + g.bias[col];
+          const float a = silu_f(z);
+          if (g.Cf) g.Cf[row * g.ldcf + col] = z;
+          if (g.Cb) g.Cb[row * g.ldcb + col] = (bf16)a;
+          if (g.Ca) g.Ca[row * g.ldca + col] = a;
+        }
+      }
+}
+
+// layer 1 in FP32: xn = (x - in_off) * in_scale, z1 = xn W1 + b1,
+// a1 = bf16(silu z1). One block per row, thread j = hidden unit j.
+__global__ void __launch_bounds__(256) k_layer1(const float *__restrict__ x, long long ld, int n,
+                                                const float *__restrict__ P, const float *__restrict__ sc,
+                                                float *__restrict__ z1, bf16 *__restrict__ a1) {
+  const int j = threadIdx.x;
+  float w[NIN];
+#pragma unroll
+  for (int k = 0; k < NIN; ++k) w[k] = P[OFF_W1 + k * HID + j];
+  const float b = P[OFF_B1 + j];
+  for (int row = blockIdx.x; row < n; row += gridDim.x) {
+    float z = b;
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) z = fmaf((x[k * ld + row] - sc[S_INOFF + k]) * sc[S_INSCALE + k], w[k], z);
+    if (z1) z1[(long long)row * HID + j] = z;
+    a1[(long long)row * HID + j] = (bf16)silu_f(z);
+  }
+}
+
+// layer 5 in FP32: y = a4 W5 + b5 (standardized outputs, n x 5 row-major).
+// One wave per row: lane l holds W5 rows 4l..4l+3 in registers and reads
+// a4[row][4l..4l+3]; the 5 dot products are reduced across the wave.
+__global__ void __launch_bounds__(256) k_layer5(const float *__restrict__ a4, int n, const float *__restrict__ P,
+                                                float *__restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwave = (gridDim.x * blockDim.x) >> 6;
+  float w[4][NOUT];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) w[q][o] = P[OFF_W5 + (4 * lane + q) * NOUT + o];
+  for (int row = wave; row < n; row += nwave) {
+    const float4 a = *reinterpret_cast<const float4 *>(a4 + (long long)row * HID + 4 * lane);
+    float s[NOUT];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) s[o] = a.x * w[0][o] + a.y * w[1][o] + a.z * w[2][o] + a.w * w[3][o];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int o = 0; o < NOUT; ++o) s[o] += __shfl_xor(s[o], off);
+    if (lane < NOUT) {
+      float v = s[0];
+#pragma unroll
+      for (int o = 1; o < NOUT; ++o) v = lane == o ? s[o] : v;
+      y[(long long)row * NOUT + lane] = v + P[OFF_B5 + lane];
+    }
+  }
+}
+
+// standardized outputs (n x 5) -> SoA targets (5 x ld)
+__global__ void k_destd(const float *__restrict__ y, int n, long long ld, const float *__restrict__ sc,
+                        float *__restrict__ t) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)n * NOUT) return;
+  const int row = (int)(i / NOUT), o = (int)(i - (long long)row * NOUT);
+  t[o * ld + row] = fmaf(y[i], sc[S_OSTD + o], sc[S_OMEAN + o]);
+}
+
+// loss on the standardized targets and its gradient; t is SoA (5 x ld),
+// w (n) the per-row weight (NULL = 1). Per element d = y - t:
+// huber = 0: d^2 (gradient 2 d); huber = delta > 0: d^2 for |d| <= delta,
+// 2 delta |d| - delta^2 beyond (gradient clipped to 2 delta sign(d)).
+// Loss and gradient are divided by n.
+__global__ void __launch_bounds__(256) k_loss(const float *__restrict__ y, const float *__restrict__ t, long long ld,
+                                              const float *__restrict__ wrow, int n, const float *__restrict__ sc,
+                                              float huber, float *__restrict__ dy, float *__restrict__ loss) {
+  __shared__ float part[256];
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.f;
+  if (i < (long long)n * NOUT) {
+    const int row = (int)(i / NOUT), o = (int)(i - (long long)row * NOUT);
+    const float wr = wrow ? wrow[row] : 1.0f;
+    float g = 0.f;
+    if (wr != 0.0f) {
+      const float tn = (t[o * ld + row] - sc[S_OMEAN + o]) / sc[S_OSTD + o];
+      const float d = y[i] - tn;
+      if (huber > 0.0f && fabsf(d) > huber) {
+        l = wr * (2.0f * huber * fabsf(d) - huber * huber);
+        g = 2.0f * wr * copysignf(huber, d);
+      } else {
+        l = wr * d * d;
+        g = 2.0f * wr * d;
+      }
+    }
+    dy[i] = g / (float)n;
+  }
+  part[threadIdx.x] = l;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(loss, part[0] / (float)n);
+}
+
+// backward of layer 5 (FP32): dW5 += a4^T dy, db5 += sum dy,
+// dz4 = (dy W5^T) * silu'(z4) -> FP32 and BF16 copies. Thread j = unit j.
+__global__ void __launch_bounds__(256) k_layer5_back(const float *__restrict__ dy, const float *__restrict__ a4,
+                                                     const float *__restrict__ z4, int n,
+                                                     const float *__restrict__ P, float *__restrict__ G,
+                                                     float *__restrict__ dzf, bf16 *__restrict__ dzb) {
+  const int j = threadIdx.x;
+  float w[NOUT], gw[NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f}, gb = 0.f;
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) w[o] = P[OFF_W5 + j * NOUT + o];
+  for (int row = blockIdx.x; row < n; row += gridDim.x) {
+    const long long e = (long long)row * HID + j;
+    const float a = a4[e];
+    float da = 0.f;
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+      const float d = dy[(long long)row * NOUT + o];
+      da = fmaf(d, w[o], da);
+      gw[o] = fmaf(a, d, gw[o]);
+    }
+    if (j < NOUT) gb += dy[(long long)row * NOUT + j];
+    const float g = da * dsilu_f(z4[e]);
+    dzf[e] = g;
+    dzb[e] = (bf16)g;
+  }
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) atomicAdd(&G[OFF_W5 + j * NOUT + o], gw[o]);
+  if (j < NOUT) atomicAdd(&G[OFF_B5 + j], gb);
+}
+
+// column sums of an (n x 256) FP32 matrix, accumulated into out[0..255]
+__global__ void __launch_bounds__(256) k_colsum(const float *__restrict__ d, int n, float *__restrict__ out) {
+  const int j = threadIdx.x;
+  float s = 0.f;
+  for (int row = blockIdx.x; row < n; row += gridDim.x) s += d[(long long)row * HID + j];
+  atomicAdd(&out[j], s);
+}
+
+// backward of layer 1 (FP32): dW1 += xn^T dz1, db1 += sum dz1
+__global__ void __launch_bounds__(256) k_layer1_back(const float *__restrict__ x, long long ld, int n,
+                                                     const float *__restrict__ sc, const float *__restrict__ dz1,
+                                                     float *__restrict__ G) {
+  const int j = threadIdx.x;
+  float gw[NIN] = {0, 0, 0, 0, 0, 0}, gb = 0.f;
+  for (int row = blockIdx.x; row < n; row += gridDim.x) {
+    const float d = dz1[(long long)row * HID + j];
+    gb += d;
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) gw[k] = fmaf((x[k * ld + row] - sc[S_INOFF + k]) * sc[S_INSCALE + k], d, gw[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < NIN; ++k) atomicAdd(&G[OFF_W1 + k * HID + j], gw[k]);
+  atomicAdd(&G[OFF_B1 + j], gb);
+}
+
+__global__ void k_fill(float *p, long long n, float v) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u32(unsigned int *p, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+__device__ __forceinline__ bool is_bias(long long i) {
+  return (i >= OFF_B1 && i < OFF_W2) || (i >= OFF_B2 && i < OFF_W3) || (i >= OFF_B3 && i < OFF_W4) ||
+         (i >= OFF_B4 && i < OFF_W5) || i >= OFF_B5;
+}
+
+// index of FP32 parameter i in the transposed BF16 copy (-1: no copy)
+__device__ __forceinline__ long long bf16_index(long long i) {
+  long long l, e;
+  if (i >= OFF_W2 && i < OFF_B2) { l = 0; e = i - OFF_W2; }
+  else if (i >= OFF_W3 && i < OFF_B3) { l = 1; e = i - OFF_W3; }
+  else if (i >= OFF_W4 && i < OFF_B4) { l = 2; e = i - OFF_W4; }
+  else return -1;
+  const long long in = e / HID, out = e - in * HID;
+  return l * HID * HID + out * HID + in;
+}
+
+// AdamW (decoupled weight decay on the weights, not the biases) on the FP32
+// master weights, then the BF16 copy of each updated W2..W4 entry
+__global__ void k_adamw(float *__restrict__ P, const float *__restrict__ G, float *__restrict__ m,
+                        float *__restrict__ v, bf16 *__restrict__ Pb, float lr, float wd, float b1, float b2,
+                        float c1, float c2, float eps) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NPARAM) return;
+  const float g = G[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * g;
+  const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  float p = P[i];
+  if (!is_bias(i)) p -= lr * wd * p;
+  p -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  P[i] = p;
+  const long long k = bf16_index(i);
+  if (k >= 0) Pb[k] = (bf16)p;
+}
+
+__global__ void k_refresh_bf16(const float *__restrict__ P, bf16 *__restrict__ Pb) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NPARAM) return;
+  const long long k = bf16_index(i);
+  if (k >= 0) Pb[k] = (bf16)P[i];
+}
+
+// masked first and second moments of the 6 inputs and 5 targets (FP64 sums)
+constexpr int NMOM = 2 * (NIN + NOUT) + 1;
+__global__ void __launch_bounds__(256) k_moments(const float *__restrict__ x, const float *__restrict__ t, long long ld,
+                                                 const float *__restrict__ wrow, int n, double *__restrict__ acc) {
+  double s[NMOM];
+#pragma unroll
+  for (int k = 0; k < NMOM; ++k) s[k] = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double wr = wrow ? wrow[i] : 1.0;
+    if (wr == 0.0) continue;
+    s[NMOM - 1] += wr;
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) {
+      const double v = x[k * ld + i];
+      s[2 * k] += wr * v;
+      s[2 * k + 1] += wr * v * v;
+    }
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+      const double v = t[o * ld + i];
+      s[2 * (NIN + o)] += wr * v;
+      s[2 * (NIN + o) + 1] += wr * v * v;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NMOM; ++k) {
+    double v = s[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&acc[k], v);
+  }
+}
+
+__global__ void k_fill_f64(double *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Target encoding. Entry (phi, z, alpha, beta) on r = b, exit (phi', z',
+// alpha', beta') on r = b, optical path T between them:
+//   t0 = dtheta - base,  t1 = (z' - z) cos(beta) / 2b,  t2 = alpha' - alpha,
+//   t3 = beta' - beta,   t4 = T cos(beta) / 2b.
+// dtheta is the signed azimuth swept by the ray. The conserved angular
+// momentum p_theta keeps its sign along the path (the inner mirror reflects
+// radially), so theta is monotonic with the sign s of alpha, and
+// dtheta = s * ((s (phi' - phi)) mod 2 pi) unwraps exactly for transits of
+// less than a full turn. base = s pi for the azimuthal cloak's
+// extraordinary branch, whose turning radius r - a = |p_theta| /
+// sqrt(kappa - p_z^2) shrinks to zero with p_theta while its angular rate
+// grows like 1/p_theta, so that dtheta -> s pi; base = 0 for the other
+// branches, whose dtheta is continuous through alpha = 0. The factors
+// cos(beta) / 2b make t1 and t4 the vertical travel and path length in
+// units of the vacuum chord 2b cos(alpha) / cos(beta), bounded for grazing
+// elevations.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float wrap2pi(float a) {
+  a = fmodf(a, 2.0f * PI_F);
+  return a < 0.0f ? a + 2.0f * PI_F : a;
+}
+
+__device__ __forceinline__ float dtheta_base(int kind, float s) { return kind == 3 ? s * PI_F : 0.0f; }
+
+__device__ __forceinline__ int kind_of(float pol, float axis) {
+  return (axis == 0.0f ? 0 : 2) + (pol == 0.0f ? 0 : 1);
+}
+
+__device__ __forceinline__ bool entry_ok(float phi, float z, float al, float be, float pol, float axis) {
+  return isfinite(phi) && isfinite(z) && fabsf(al) < 0.5f * PI_F && fabsf(be) < 0.5f * PI_F &&
+         (pol == 0.0f || pol == 1.0f) && (axis == 0.0f || axis == 1.0f);
+}
+
+__global__ void __launch_bounds__(256) k_encode(const float *__restrict__ x6, const float *__restrict__ y5,
+                                                const int *__restrict__ status, long long ld, long long n, float b,
+                                                float *__restrict__ t5, float *__restrict__ wrow) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float phi = x6[i], z = x6[ld + i], al = x6[2 * ld + i], be = x6[3 * ld + i];
+  const float pol = x6[4 * ld + i], axis = x6[5 * ld + i];
+  float t[NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  bool ok = status[i] == RT_RAY_EXITED && entry_ok(phi, z, al, be, pol, axis);
+  if (ok) {
+    const float s = al < 0.0f ? -1.0f : 1.0f;
+    const float dth = s * wrap2pi(s * (y5[i] - phi));
+    const float cb = cosf(be);
+    t[0] = dth - dtheta_base(kind_of(pol, axis), s);
+    t[1] = (y5[ld + i] - z) * cb / (2.0f * b);
+    t[2] = y5[2 * ld + i] - al;
+    t[3] = y5[3 * ld + i] - be;
+    t[4] = y5[4 * ld + i] * cb / (2.0f * b);
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) ok = ok && isfinite(t[o]);
+  }
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) t5[o * ld + i] = ok ? t[o] : 0.0f;
+  wrow[i] = ok ? 1.0f : 0.0f;
+}
+
+// standardized network outputs -> exit parameters (phi', z', alpha', beta', T)
+__device__ __forceinline__ void decode(const float *yrow, const float *sc, float phi, float z, float al, float be,
+                                       int kind, float b, float out[NOUT]) {
+  float t[NOUT];
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) t[o] = fmaf(yrow[o], sc[S_OSTD + o], sc[S_OMEAN + o]);
+  const float s = al < 0.0f ? -1.0f : 1.0f;
+  const float inv_cb = 1.0f / cosf(be);
+  out[0] = wrap2pi(phi + t[0] + dtheta_base(kind, s));
+  out[1] = z + t[1] * 2.0f * b * inv_cb;
+  out[2] = al + t[2];
+  out[3] = be + t[3];
+  out[4] = t[4] * 2.0f * b * inv_cb;
+}
+
+// cell of the trust map
+__device__ __forceinline__ int cell_of(int kind, float al, float be) {
+  int ia = (int)floorf((al + 0.5f * PI_F) * (NCELL_A / PI_F));
+  int ib = (int)floorf((be + 0.5f * PI_F) * (NCELL_B / PI_F));
+  ia = min(max(ia, 0), NCELL_A - 1);
+  ib = min(max(ib, 0), NCELL_B - 1);
+  return (kind * NCELL_A + ia) * NCELL_B + ib;
+}
+
+struct GateP {
+  float b, z0, z1;   // cloak radius r2 and material height range
+  float hres_max;    // conservation residual limit
+  float cap_margin;  // distance of the predicted exit height from a cap
+};
+
+// Gate and write the accepted predictions. A prediction is rejected (and
+// the exact integrator traces the ray) when
+//  - the entry is not a valid side entry,
+//  - its trust-map cell is not trusted,
+//  - the predicted exit ray violates the conservation of the tangential
+//    wave numbers (p_theta / b and p_z, equal at entry and exit on r = b
+//    for every side-to-side transit) by more than hres_max, or
+//  - the predicted exit height lies within cap_margin of an end cap or
+//    beyond it (z is monotonic along a transit since p_z keeps its sign,
+//    so an exit height inside the material with margin means the whole
+//    path stayed inside).
+__device__ __forceinline__ void gate_row(long long i, const float *__restrict__ x6, long long ld,
+                                         const float *yrow, const float *__restrict__ sc,
+                                         const unsigned char *__restrict__ map, const GateP &gp,
+                                         float *__restrict__ y5, unsigned char *__restrict__ fallback,
+                                         int *__restrict__ status) {
+  const float phi = x6[i], z = x6[ld + i], al = x6[2 * ld + i], be = x6[3 * ld + i];
+  const float pol = x6[4 * ld + i], axis = x6[5 * ld + i];
+  bool acc = entry_ok(phi, z, al, be, pol, axis) && z >= gp.z0 && z <= gp.z1;
+  float out[NOUT];
+  if (acc) {
+    const int kind = kind_of(pol, axis);
+    decode(yrow, sc, phi, z, al, be, kind, gp.b, out);
+    acc = map[cell_of(kind, al, be)] != 0;
+    const float kt = cosf(be) * sinf(al), kz = sinf(be);
+    const float kt2 = cosf(out[3]) * sinf(out[2]), kz2 = sinf(out[3]);
+    const float res = fmaxf(fabsf(kt2 - kt), fabsf(kz2 - kz));
+    acc = acc && res <= gp.hres_max;
+    acc = acc && out[1] >= gp.z0 + gp.cap_margin && out[1] <= gp.z1 - gp.cap_margin;
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) acc = acc && isfinite(out[o]);
+  }
+  fallback[i] = acc ? 0 : 1;
+  if (acc) {
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) y5[o * ld + i] = out[o];
+    status[i] = RT_RAY_EXITED;
+  }
+}
+
+// gate of the standardized outputs y (n x 5) of the fused forward
+__global__ void __launch_bounds__(256) k_decode_gate(const float *__restrict__ x6, long long ld, int n,
+                                                     const float *__restrict__ y, const float *__restrict__ sc,
+                                                     const unsigned char *__restrict__ map, GateP gp,
+                                                     float *__restrict__ y5, unsigned char *__restrict__ fallback,
+                                                     int *__restrict__ status) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) gate_row(i, x6, ld, y + i * NOUT, sc, map, gp, y5, fallback, status);
+}
+
+// ---------------------------------------------------------------------------
+// Fused inference: the whole network for FR rows per block, activations
+// resident in LDS (BF16, FR x 256, rows padded to 264 so that the 16 rows an
+// MFMA operand read touches fall in distinct banks). Wave w owns output
+// columns 64w..64w+63 of every hidden layer: 8 x 4 MFMA 16x16x32 tiles
+// (128 FP32 accumulators per lane); its B operands (transposed BF16 weights,
+// 8 consecutive inputs per lane) stream from L2 with one 16-byte load per
+// tile, its A operands come from the LDS tile. Layer 1 (FP32) fills the LDS
+// tile; layer 5 (FP32) reduces the layer-4 accumulators directly, across
+// lanes and then across the 4 waves through LDS, and the block writes the
+// standardized outputs (n x 5).
+// ---------------------------------------------------------------------------
+constexpr int FR = 128, ALD = HID + 8;
+
+__global__ void __launch_bounds__(256, 2) k_mlp_fused(const float *__restrict__ x6, long long ld, int n,
+                                                      const float *__restrict__ P, const bf16 *__restrict__ Wt,
+                                                      const float *__restrict__ sc, float *__restrict__ yout) {
+  __shared__ __attribute__((aligned(16))) bf16 act[FR * ALD];
+  __shared__ float xn[FR * NIN];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const long long row0 = (long long)blockIdx.x * FR;
+  // standardized inputs of the tile (rows past n read as zeros)
+  for (int e = tid; e < FR * NIN; e += 256) {
+    const int r = e / NIN, k = e - r * NIN;
+    const long long i = row0 + r;
+    xn[e] = i < n ? (x6[k * ld + i] - sc[S_INOFF + k]) * sc[S_INSCALE + k] : 0.0f;
+  }
+  __syncthreads();
+  {  // layer 1 (FP32): thread = hidden unit
+    float w1[NIN];
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) w1[k] = P[OFF_W1 + k * HID + tid];
+    const float b1 = P[OFF_B1 + tid];
+    for (int r = 0; r < FR; ++r) {
+      float z = b1;
+#pragma unroll
+      for (int k = 0; k < NIN; ++k) z = fmaf(xn[r * NIN + k], w1[k], z);
+      act[r * ALD + tid] = (bf16)silu_f(z);
+    }
+  }
+  __syncthreads();
+  const int q = lane >> 4, c16 = lane & 15, cb = 64 * w;
+  const long long offb[3] = {OFF_B2, OFF_B3, OFF_B4};
+  f32x4 acc[8][4];
+  for (int l = 0; l < 3; ++l) {
+    const bf16 *W = Wt + (long long)l * HID * HID;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int k0 = 0; k0 < HID; k0 += 32) {
+      bf16x8 bop[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        bop[c] = *reinterpret_cast<const bf16x8 *>(W + (cb + 16 * c + c16) * HID + k0 + 8 * q);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const bf16x8 aop = *reinterpret_cast<const bf16x8 *>(&act[(16 * r + c16) * ALD + k0 + 8 * q]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop[c], acc[r][c], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // every wave has read the layer's input tile
+    float bias[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bias[c] = P[offb[l] + cb + 16 * c + c16];
+    if (l < 2) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            act[(16 * r + 4 * q + i) * ALD + cb + 16 * c + c16] = (bf16)silu_f(acc[r][c][i] + bias[c]);
+      __syncthreads();
+    } else {
+      // layer 5 (FP32) on a4 = silu(z4): per-lane partial sums over this
+      // lane's 4 columns, reduced over the 16 lanes of a column group, then
+      // over the 4 waves in LDS (the activation tile is free now)
+      float w5[4][NOUT];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) w5[c][o] = P[OFF_W5 + (cb + 16 * c + c16) * NOUT + o];
+      float *red = reinterpret_cast<float *>(act);  // [4 waves][FR][NOUT]
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float s5[NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const float a4 = silu_f(acc[r][c][i] + bias[c]);
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) s5[o] = fmaf(a4, w5[c][o], s5[o]);
+          }
+#pragma unroll
+          for (int off = 1; off < 16; off <<= 1)
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) s5[o] += __shfl_xor(s5[o], off);
+          if (c16 == 0) {
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) red[(w * FR + 16 * r + 4 * q + i) * NOUT + o] = s5[o];
+          }
+        }
+      __syncthreads();
+      if (tid < FR) {
+        const long long i = row0 + tid;
+        if (i < n) {
+          float y[NOUT];
+#pragma unroll
+          for (int o = 0; o < NOUT; ++o)
+            y[o] = P[OFF_B5 + o] + red[(0 * FR + tid) * NOUT + o] + red[(1 * FR + tid) * NOUT + o] +
+                   red[(2 * FR + tid) * NOUT + o] + red[(3 * FR + tid) * NOUT + o];
+#pragma unroll
+          for (int o = 0; o < NOUT; ++o) yout[i * NOUT + o] = y[o];
+        }
+      }
+    }
+  }
+}
+
+// exit point and unit direction from exit parameters
+__device__ __forceinline__ void exit_ray(const float *p, float b, float x[3], float d[3]) {
+  float sp, cp, sa, ca, sb, cbt;
+  sincosf(p[0], &sp, &cp);
+  sincosf(p[2], &sa, &ca);
+  sincosf(p[3], &sb, &cbt);
+  x[0] = b * cp; x[1] = b * sp; x[2] = p[1];
+  d[0] = cbt * (ca * cp - sa * sp);
+  d[1] = cbt * (ca * sp + sa * cp);
+  d[2] = sb;
+}
+
+// error of the decoded prediction against the exact exit, per trust-map cell:
+// err = max(|x - x_exact| / b, angle(d, d_exact)); a ray the exact
+// integrator did not carry from side to side (absorbed, reflected, ...)
+// makes its cell untrusted
+__global__ void __launch_bounds__(256) k_calib(const float *__restrict__ x6, long long ld, int n,
+                                               const float *__restrict__ y, const float *__restrict__ sc,
+                                               const float *__restrict__ ye, const int *__restrict__ st, float b,
+                                               unsigned int *__restrict__ cmax, unsigned int *__restrict__ ccnt) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float phi = x6[i], z = x6[ld + i], al = x6[2 * ld + i], be = x6[3 * ld + i];
+  const float pol = x6[4 * ld + i], axis = x6[5 * ld + i];
+  if (!entry_ok(phi, z, al, be, pol, axis)) return;
+  const int kind = kind_of(pol, axis);
+  const int cell = cell_of(kind, al, be);
+  float err = INFINITY;
+  if (st[i] == RT_RAY_EXITED) {
+    float out[NOUT], ex[NOUT], xp[3], dp[3], xe[3], de[3];
+    decode(y + i * NOUT, sc, phi, z, al, be, kind, b, out);
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) ex[o] = ye[o * ld + i];
+    exit_ray(out, b, xp, dp);
+    exit_ray(ex, b, xe, de);
+    float ex2 = 0.f, dd2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      ex2 += (xp[j] - xe[j]) * (xp[j] - xe[j]);
+      dd2 += (dp[j] - de[j]) * (dp[j] - de[j]);
+    }
+    const float dang = 2.0f * asinf(fminf(1.0f, 0.5f * sqrtf(dd2)));
+    err = fmaxf(sqrtf(ex2) / b, dang);
+    if (!isfinite(err)) err = INFINITY;
+  }
+  atomicMax(&cmax[cell], __float_as_uint(err));  // err >= 0: uint order = float order
+  atomicAdd(&ccnt[cell], 1u);
+}
+
+unsigned int gblocks(long long n, int b) { return (unsigned int)std::max(1LL, (n + b - 1) / b); }
+
+}  // namespace sg
+
+using namespace sg;
+
+struct rt_model_s {
+  int device = -1;
+  void *base = nullptr;
+  float *P = nullptr, *G = nullptr, *m = nullptr, *v = nullptr;  // FP32 [NPARAM]
+  bf16 *Pb = nullptr;                                            // BF16 W2..W4
+  float *scal = nullptr;                                         // [NSCAL]
+  unsigned char *map = nullptr;                                  // trust map [NCELLS]
+  unsigned int *cal = nullptr;                                   // calibration max/count [2 * NCELLS]
+  double *mom = nullptr;                                         // moments [NMOM]
+  float h_scal[NSCAL] = {0};
+  std::vector<unsigned char> h_map;
+  int map_valid = 0;
+  rt_gate_opts gate{};
+  long long step = 0;
+  // activations for up to `cap` rows
+  long long cap = 0;
+  void *act = nullptr;
+  float *z[4] = {nullptr, nullptr, nullptr, nullptr};  // hidden pre-activations (FP32)
+  bf16 *a[3] = {nullptr, nullptr, nullptr};            // a1..a3 (BF16)
+  float *a4 = nullptr;                                 // a4 (FP32)
+  float *y = nullptr;                                  // standardized outputs [cap][5]
+  float *dy = nullptr;                                 // [cap][5]
+  float *dzf = nullptr;                                // [cap][256]
+  bf16 *dzb[2] = {nullptr, nullptr};
+  // standardized outputs of the fused inference kernel
+  long long ycap = 0;
+  float *yinf = nullptr;
+};
+
+namespace {
+
+int reserve_acts(rt_model mo, long long n) {
+  if (n <= mo->cap) return RT_OK;
+  if (mo->act) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(mo->act);
+    mo->act = nullptr;
+    mo->cap = 0;
+  }
+  const long long cap = std::max(n, 4096LL);
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t zb = al(sizeof(float) * cap * HID), ab = al(sizeof(bf16) * cap * HID);
+  const size_t yb = al(sizeof(float) * cap * NOUT);
+  const size_t bytes = 4 * zb + 3 * ab + zb + 2 * yb + zb + 2 * ab;
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(RT_E_NOMEM, "hipMalloc of %zu bytes for activations failed", bytes);
+  }
+  char *c = (char *)p;
+  size_t off = 0;
+  for (int l = 0; l < 4; ++l) { mo->z[l] = (float *)(c + off); off += zb; }
+  for (int l = 0; l < 3; ++l) { mo->a[l] = (bf16 *)(c + off); off += ab; }
+  mo->a4 = (float *)(c + off); off += zb;
+  mo->y = (float *)(c + off); off += yb;
+  mo->dy = (float *)(c + off); off += yb;
+  mo->dzf = (float *)(c + off); off += zb;
+  mo->dzb[0] = (bf16 *)(c + off); off += ab;
+  mo->dzb[1] = (bf16 *)(c + off); off += ab;
+  mo->act = p;
+  mo->cap = cap;
+  return RT_OK;
+}
+
+int reserve_yinf(rt_model mo, long long n) {
+  if (n <= mo->ycap) return RT_OK;
+  if (mo->yinf) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(mo->yinf);
+    mo->yinf = nullptr;
+    mo->ycap = 0;
+  }
+  const long long cap = std::max(n, 4096LL);
+  if (hipMalloc((void **)&mo->yinf, sizeof(float) * cap * NOUT) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(RT_E_NOMEM, "hipMalloc for %lld inference outputs failed", cap);
+  }
+  mo->ycap = cap;
+  return RT_OK;
+}
+
+// standardized outputs of n rows into mo->yinf (fused kernel)
+void infer_outputs(rt_model mo, const float *x, long long ld, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_fused, dim3(gblocks(n, FR)), dim3(256), 0, s, x, ld, n, mo->P, mo->Pb, mo->scal,
+                     mo->yinf);
+}
+
+void gemm(hipStream_t s, const bf16 *A, long long sa0, long long sa1, const bf16 *B, long long sb0, long long sb1,
+          int M, int N, int K, int epi, const float *bias, const float *Z, long long ldz, float *Cf, long long ldcf,
+          bf16 *Cb, long long ldcb, float *Ca, long long ldca, int splits = 1) {
+  int kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + 31) & ~31;
+  splits = (K + kchunk - 1) / kchunk;
+  Gemm g{A, sa0, sa1, B, sb0, sb1, M, N, K, kchunk, epi, bias, Z, ldz, Cf, ldcf, Cb, ldcb, Ca, ldca};
+  hipLaunchKernelGGL(k_gemm, dim3(gblocks(M, 64), gblocks(N, 64), splits), dim3(256), 0, s, g);
+}
+
+// transposed BF16 weights [out][in] of W2 (l = 0), W3 (1), W4 (2)
+const bf16 *wb(rt_model mo, int l) { return mo->Pb + (long long)l * HID * HID; }
+
+// layered forward of n rows for training: keeps every activation and the
+// pre-activations for backward (inference uses the fused kernel)
+void forward(rt_model mo, const float *x, long long ld, int n, bool train, hipStream_t s) {
+  const unsigned int rows_grid = (unsigned int)std::min(n, 8192);
+  hipLaunchKernelGGL(k_layer1, dim3(rows_grid), dim3(HID), 0, s, x, ld, n, mo->P, mo->scal,
+                     train ? mo->z[0] : nullptr, mo->a[0]);
+  const long long offb[3] = {OFF_B2, OFF_B3, OFF_B4};
+  for (int l = 1; l <= 3; ++l) {
+    const bool last = l == 3;
+    gemm(s, mo->a[l - 1], HID, 1, wb(mo, l - 1), 1, HID, n, HID, HID, EPI_BIAS_SILU, mo->P + offb[l - 1], nullptr,
+         0, train ? mo->z[l] : nullptr, HID, last ? nullptr : mo->a[l], HID, last ? mo->a4 : nullptr, HID);
+  }
+  hipLaunchKernelGGL(k_layer5, dim3(std::min(gblocks(n, 4), 4096u)), dim3(256), 0, s, mo->a4, n, mo->P, mo->y);
+}
+
+int split_for(int n) { return std::min(64, std::max(1, n / 512)); }
+
+// gradients of the loss of the last forward into mo->G; loss into scal[S_LOSS]
+void backward(rt_model mo, const float *x, const float *t, long long ld, const float *wrow, int n, float huber,
+              hipStream_t s) {
+  float *loss = mo->scal + S_LOSS;
+  const unsigned int rows_grid = (unsigned int)std::min(n, 2048);
+  hipLaunchKernelGGL(k_fill, dim3(gblocks(NPARAM, 256)), dim3(256), 0, s, mo->G, NPARAM, 0.0f);
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, loss, 1LL, 0.0f);
+  hipLaunchKernelGGL(k_loss, dim3(gblocks((long long)n * NOUT, 256)), dim3(256), 0, s, mo->y, t, ld, wrow, n,
+                     mo->scal, huber, mo->dy, loss);
+  hipLaunchKernelGGL(k_layer5_back, dim3(rows_grid), dim3(HID), 0, s, mo->dy, mo->a4, mo->z[3], n, mo->P, mo->G,
+                     mo->dzf, mo->dzb[1]);
+  // hidden layers from the top: dz of layer l (FP32 in dzf, BF16 in dzb[cur])
+  const long long offw[3] = {OFF_W2, OFF_W3, OFF_W4}, offb[3] = {OFF_B2, OFF_B3, OFF_B4};
+  int cur = 1;
+  for (int l = 3; l >= 1; --l) {
+    // dW_{l+1} += a_l^T dz (a_l: BF16 [n][256] read transposed), db_{l+1} += sum dz
+    gemm(s, mo->a[l - 1], 1, HID, mo->dzb[cur], HID, 1, HID, HID, n, EPI_ATOMIC, nullptr, nullptr, 0,
+         mo->G + offw[l - 1], HID, nullptr, 0, nullptr, 0, split_for(n));
+    hipLaunchKernelGGL(k_colsum, dim3(rows_grid), dim3(HID), 0, s, mo->dzf, n, mo->G + offb[l - 1]);
+    // dz_{l-1} = (dz W_{l+1}^T) * silu'(z_{l-1}); B(k, j) = W(in=j, out=k) = Wt[k][j]
+    gemm(s, mo->dzb[cur], HID, 1, wb(mo, l - 1), HID, 1, n, HID, HID, EPI_DSILU, nullptr, mo->z[l - 1], HID,
+         mo->dzf, HID, mo->dzb[cur ^ 1], HID, nullptr, 0);
+    cur ^= 1;
+  }
+  hipLaunchKernelGGL(k_layer1_back, dim3(rows_grid), dim3(HID), 0, s, x, ld, n, mo->scal, mo->dzf, mo->G);
+}
+
+int check_model(rt_model mo) {
+  if (!mo || !mo->P) return fail(RT_E_INVALID, "model is NULL");
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  if (dev != mo->device) return fail(RT_E_INVALID, "model was created on device %d, current is %d", mo->device, dev);
+  return RT_OK;
+}
+
+int check_rows(long long n, long long ld, const void *x6) {
+  if (n < 1 || n > (1LL << 24)) return fail(RT_E_INVALID, "n must be in [1, 2^24]");
+  if (ld < n) return fail(RT_E_INVALID, "ld must be >= n");
+  if (!x6) return fail(RT_E_INVALID, "x6 is required");
+  return RT_OK;
+}
+
+int upload_scal(rt_model mo) {
+  if (hipMemcpy(mo->scal, mo->h_scal, sizeof(float) * S_LOSS, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(RT_E_DEVICE, "copy of the scaling failed");
+  return RT_OK;
+}
+
+int upload_map(rt_model mo) {
+  if (hipMemcpy(mo->map, mo->h_map.data(), NCELLS, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(RT_E_DEVICE, "copy of the trust map failed");
+  return RT_OK;
+}
+
+int cloak_geometry(const rt_cloak *cloaks, int32_t n_cloaks, rt_cloak_desc &d) {
+  if (n_cloaks < 1 || n_cloaks > 2 || !cloaks || !cloaks[0]) return fail(RT_E_INVALID, "need 1 or 2 cloak handles");
+  if (rt_cloak_get_desc(cloaks[0], &d) != RT_OK) return fail(RT_E_INVALID, "bad cloak handle");
+  return RT_OK;
+}
+
+int launch_err(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return RT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rt_surrogate_create(uint64_t seed, rt_model *out) {
+  if (!out) return fail(RT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  rt_model mo = new (std::nothrow) rt_model_s;
+  if (!mo) return fail(RT_E_NOMEM, "host allocation failed");
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t pb = al(sizeof(float) * NPARAM), bb = al(sizeof(bf16) * NBF), sb = al(sizeof(float) * NSCAL),
+               mb = al(NCELLS), cb = al(sizeof(unsigned int) * 2 * NCELLS), ob = al(sizeof(double) * NMOM);
+  const size_t bytes = 4 * pb + bb + sb + mb + cb + ob;
+  if (hipMalloc(&mo->base, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete mo;
+    return fail(RT_E_NOMEM, "hipMalloc of the model failed");
+  }
+  (void)hipGetDevice(&mo->device);
+  char *c = (char *)mo->base;
+  size_t off = 0;
+  mo->P = (float *)(c + off); off += pb;
+  mo->G = (float *)(c + off); off += pb;
+  mo->m = (float *)(c + off); off += pb;
+  mo->v = (float *)(c + off); off += pb;
+  mo->Pb = (bf16 *)(c + off); off += bb;
+  mo->scal = (float *)(c + off); off += sb;
+  mo->map = (unsigned char *)(c + off); off += mb;
+  mo->cal = (unsigned int *)(c + off); off += cb;
+  mo->mom = (double *)(c + off); off += ob;
+  // weights and biases uniform in +-1/sqrt(fan_in) from a seeded Mersenne
+  // twister, drawn layer by layer (weights row-major, then biases)
+  std::vector<float> h(NPARAM, 0.0f);
+  std::mt19937_64 rng(seed);
+  const int fan_in[5] = {NIN, HID, HID, HID, HID}, fan_out[5] = {HID, HID, HID, HID, NOUT};
+  const long long offw[5] = {OFF_W1, OFF_W2, OFF_W3, OFF_W4, OFF_W5};
+  const long long offb[5] = {OFF_B1, OFF_B2, OFF_B3, OFF_B4, OFF_B5};
+  for (int l = 0; l < 5; ++l) {
+    const float k = 1.0f / std::sqrt((float)fan_in[l]);
+    std::uniform_real_distribution<float> U(-k, k);
+    for (long long e = 0; e < (long long)fan_in[l] * fan_out[l]; ++e) h[offw[l] + e] = U(rng);
+    for (int j = 0; j < fan_out[l]; ++j) h[offb[l] + j] = U(rng);
+  }
+  for (int k = 0; k < NIN; ++k) { mo->h_scal[S_INOFF + k] = 0.0f; mo->h_scal[S_INSCALE + k] = 1.0f; }
+  for (int o = 0; o < NOUT; ++o) { mo->h_scal[S_OMEAN + o] = 0.0f; mo->h_scal[S_OSTD + o] = 1.0f; }
+  mo->h_map.assign(NCELLS, 0);
+  mo->gate.tol = 1e-3;
+  mo->gate.hres_max = 1e-4;
+  mo->gate.cap_margin = 1e-2;
+  mo->gate.min_count = 8;
+  bool ok = hipMemcpy(mo->P, h.data(), sizeof(float) * NPARAM, hipMemcpyHostToDevice) == hipSuccess &&
+            upload_scal(mo) == RT_OK && upload_map(mo) == RT_OK;
+  if (ok) {
+    hipLaunchKernelGGL(k_fill, dim3(gblocks(NPARAM, 256)), dim3(256), 0, 0, mo->m, NPARAM, 0.0f);
+    hipLaunchKernelGGL(k_fill, dim3(gblocks(NPARAM, 256)), dim3(256), 0, 0, mo->v, NPARAM, 0.0f);
+    hipLaunchKernelGGL(k_refresh_bf16, dim3(gblocks(NPARAM, 256)), dim3(256), 0, 0, mo->P, mo->Pb);
+    ok = hipDeviceSynchronize() == hipSuccess;
+  }
+  if (!ok) {
+    (void)hipFree(mo->base);
+    delete mo;
+    return fail(RT_E_DEVICE, "model initialization failed");
+  }
+  *out = mo;
+  return RT_OK;
+}
+
+int rt_surrogate_free(rt_model mo) {
+  if (!mo) return RT_OK;
+  (void)hipDeviceSynchronize();
+  if (mo->act) (void)hipFree(mo->act);
+  if (mo->yinf) (void)hipFree(mo->yinf);
+  if (mo->base) (void)hipFree(mo->base);
+  delete mo;
+  return RT_OK;
+}
+
+int rt_surrogate_nparams(int64_t *count) {
+  if (!count) return fail(RT_E_INVALID, "count is NULL");
+  *count = NPARAM;
+  return RT_OK;
+}
+
+int rt_surrogate_get_params(rt_model mo, float *host) {
+  int e = check_model(mo);
+  if (e) return e;
+  if (!host) return fail(RT_E_INVALID, "host is NULL");
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(host, mo->P, sizeof(float) * NPARAM, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(RT_E_DEVICE, "copy failed");
+  return RT_OK;
+}
+
+int rt_surrogate_set_params(rt_model mo, const float *host) {
+  int e = check_model(mo);
+  if (e) return e;
+  if (!host) return fail(RT_E_INVALID, "host is NULL");
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(mo->P, host, sizeof(float) * NPARAM, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(RT_E_DEVICE, "copy failed");
+  hipLaunchKernelGGL(k_refresh_bf16, dim3(gblocks(NPARAM, 256)), dim3(256), 0, 0, mo->P, mo->Pb);
+  hipLaunchKernelGGL(k_fill, dim3(gblocks(NPARAM, 256)), dim3(256), 0, 0, mo->m, NPARAM, 0.0f);
+  hipLaunchKernelGGL(k_fill, dim3(gblocks(NPARAM, 256)), dim3(256), 0, 0, mo->v, NPARAM, 0.0f);
+  if (hipDeviceSynchronize() != hipSuccess) return fail(RT_E_DEVICE, "refresh failed");
+  mo->step = 0;
+  return RT_OK;
+}
+
+int rt_surrogate_get_scaling(rt_model mo, float *scaling22) {
+  int e = check_model(mo);
+  if (e) return e;
+  if (!scaling22) return fail(RT_E_INVALID, "scaling is NULL");
+  memcpy(scaling22, mo->h_scal, sizeof(float) * S_LOSS);
+  return RT_OK;
+}
+
+int rt_surrogate_set_scaling(rt_model mo, const float *scaling22) {
+  int e = check_model(mo);
+  if (e) return e;
+  if (!scaling22) return fail(RT_E_INVALID, "scaling is NULL");
+  for (int k = 0; k < S_LOSS; ++k)
+    if (!std::isfinite(scaling22[k])) return fail(RT_E_INVALID, "scaling values must be finite");
+  for (int o = 0; o < NOUT; ++o)
+    if (!(scaling22[S_OSTD + o] > 0.0f)) return fail(RT_E_INVALID, "out_std must be > 0");
+  memcpy(mo->h_scal, scaling22, sizeof(float) * S_LOSS);
+  if (hipDeviceSynchronize() != hipSuccess) return fail(RT_E_DEVICE, "synchronize failed");
+  return upload_scal(mo);
+}
+
+int rt_surrogate_fit_scaling(rt_model mo, int64_t n, int64_t ld, const float *x6, const float *t5, const float *w,
+                             void *stream) {
+  int e = check_model(mo);
+  if (!e) e = check_rows(n, ld, x6);
+  if (e) return e;
+  if (!t5) return fail(RT_E_INVALID, "t5 is required");
+  hipStream_t s = (hipStream_t)stream;
+  double h[NMOM];
+  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, mo->mom, NMOM);
+  hipLaunchKernelGGL(k_moments, dim3(std::min(gblocks(n, 256), 1024u)), dim3(256), 0, s, x6, t5, (long long)ld, w,
+                     (int)n, mo->mom);
+  if (hipMemcpyAsync(h, mo->mom, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(RT_E_DEVICE, "moments failed");
+  const double W = h[NMOM - 1];
+  if (!(W > 0.0)) return fail(RT_E_INVALID, "no row has a nonzero weight");
+  for (int k = 0; k < NIN + NOUT; ++k) {
+    const double mean = h[2 * k] / W;
+    const double var = std::max(0.0, h[2 * k + 1] / W - mean * mean);
+    const double sd = std::sqrt(var);
+    if (k < NIN) {
+      mo->h_scal[S_INOFF + k] = (float)mean;
+      mo->h_scal[S_INSCALE + k] = (float)(1.0 / std::max(sd, 1e-6));
+    } else {
+      mo->h_scal[S_OMEAN + (k - NIN)] = (float)mean;
+      mo->h_scal[S_OSTD + (k - NIN)] = std::max((float)sd, OUT_STD_FLOOR);
+    }
+  }
+  return upload_scal(mo);
+}
+
+int grad_impl(rt_model mo, int64_t n, int64_t ld, const float *x6, const float *t5, const float *w, float huber,
+              float *grads, float *loss, void *stream);
+
+int rt_surrogate_grad(rt_model mo, int64_t n, int64_t ld, const float *x6, const float *t5, const float *w,
+                      float huber, float *grads, float *loss, void *stream) {
+  if (!(huber >= 0.0f)) return fail(RT_E_INVALID, "huber must be >= 0");
+  return grad_impl(mo, n, ld, x6, t5, w, huber, grads, loss, stream);
+}
+
+int grad_impl(rt_model mo, int64_t n, int64_t ld, const float *x6, const float *t5, const float *w, float huber,
+              float *grads, float *loss, void *stream) {
+  int e = check_model(mo);
+  if (!e) e = check_rows(n, ld, x6);
+  if (e) return e;
+  if (!t5) return fail(RT_E_INVALID, "t5 is required");
+  e = reserve_acts(mo, n);
+  if (e) return e;
+  hipStream_t s = (hipStream_t)stream;
+  forward(mo, x6, ld, (int)n, true, s);
+  backward(mo, x6, t5, ld, w, (int)n, huber, s);
+  if (grads) (void)hipMemcpyAsync(grads, mo->G, sizeof(float) * NPARAM, hipMemcpyDeviceToDevice, s);
+  if (loss) (void)hipMemcpyAsync(loss, mo->scal + S_LOSS, sizeof(float), hipMemcpyDeviceToDevice, s);
+  return launch_err("gradient launch");
+}
+
+int rt_surrogate_train(rt_model mo, int64_t n, int64_t ld, const float *x6, const float *t5, const float *w,
+                       const rt_train_opts *opts, float *loss, void *stream) {
+  if (!opts) return fail(RT_E_INVALID, "opts is NULL");
+  if (!(opts->lr >= 0.0f) || !(opts->beta1 >= 0.0f && opts->beta1 < 1.0f) ||
+      !(opts->beta2 >= 0.0f && opts->beta2 < 1.0f) || !(opts->eps > 0.0f) || !(opts->weight_decay >= 0.0f) ||
+      !(opts->huber >= 0.0f))
+    return fail(RT_E_INVALID, "need lr >= 0, 0 <= beta1, beta2 < 1, eps > 0, weight_decay >= 0, huber >= 0");
+  int e = grad_impl(mo, n, ld, x6, t5, w, opts->huber, nullptr, loss, stream);
+  if (e) return e;
+  hipStream_t s = (hipStream_t)stream;
+  mo->step += 1;
+  const float c1 = 1.0f - (float)std::pow((double)opts->beta1, (double)mo->step);
+  const float c2 = 1.0f - (float)std::pow((double)opts->beta2, (double)mo->step);
+  hipLaunchKernelGGL(k_adamw, dim3(gblocks(NPARAM, 256)), dim3(256), 0, s, mo->P, mo->G, mo->m, mo->v, mo->Pb,
+                     opts->lr, opts->weight_decay, opts->beta1, opts->beta2, c1, c2, opts->eps);
+  return launch_err("optimizer launch");
+}
+
+int rt_surrogate_forward(rt_model mo, int64_t n, int64_t ld, const float *x6, float *t5, void *stream) {
+  int e = check_model(mo);
+  if (!e) e = check_rows(n, ld, x6);
+  if (e) return e;
+  if (!t5) return fail(RT_E_INVALID, "t5 is required");
+  e = reserve_yinf(mo, n);
+  if (e) return e;
+  hipStream_t s = (hipStream_t)stream;
+  infer_outputs(mo, x6, ld, (int)n, s);
+  hipLaunchKernelGGL(k_destd, dim3(gblocks(n * NOUT, 256)), dim3(256), 0, s, mo->yinf, (int)n, (long long)ld,
+                     mo->scal, t5);
+  return launch_err("forward launch");
+}
+
+int rt_surrogate_encode(const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int64_t ld, const float *x6,
+                        const float *y5, const int32_t *status, float *t5, float *w, void *stream) {
+  rt_cloak_desc d;
+  int e = cloak_geometry(cloaks, n_cloaks, d);
+  if (e) return e;
+  if (n == 0) return RT_OK;
+  e = check_rows(n, ld, x6);
+  if (e) return e;
+  if (!y5 || !status || !t5 || !w) return fail(RT_E_INVALID, "y5, status, t5 and w are required");
+  hipLaunchKernelGGL(k_encode, dim3(gblocks(n, 256)), dim3(256), 0, (hipStream_t)stream, x6, y5, status,
+                     (long long)ld, (long long)n, (float)d.r2, t5, w);
+  return launch_err("encode launch");
+}
+
+int rt_surrogate_calibrate(rt_model mo, const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int64_t ld,
+                           const float *x6, const float *y5_exact, const int32_t *status_exact,
+                           const rt_gate_opts *gate, double *trusted_fraction, void *stream) {
+  int e = check_model(mo);
+  if (e) return e;
+  rt_cloak_desc d;
+  e = cloak_geometry(cloaks, n_cloaks, d);
+  if (!e) e = check_rows(n, ld, x6);
+  if (e) return e;
+  if (!y5_exact || !status_exact || !gate) return fail(RT_E_INVALID, "y5_exact, status_exact and gate are required");
+  if (!(gate->tol > 0.0) || !(gate->hres_max > 0.0) || !(gate->cap_margin >= 0.0) || gate->min_count < 1)
+    return fail(RT_E_INVALID, "gate needs tol > 0, hres_max > 0, cap_margin >= 0, min_count >= 1");
+  e = reserve_yinf(mo, n);
+  if (e) return e;
+  hipStream_t s = (hipStream_t)stream;
+  infer_outputs(mo, x6, ld, (int)n, s);
+  hipLaunchKernelGGL(k_fill_u32, dim3(gblocks(2LL * NCELLS, 256)), dim3(256), 0, s, mo->cal, 2LL * NCELLS);
+  hipLaunchKernelGGL(k_calib, dim3(gblocks(n, 256)), dim3(256), 0, s, x6, (long long)ld, (int)n, mo->yinf, mo->scal,
+                     y5_exact, status_exact, (float)d.r2, mo->cal, mo->cal + NCELLS);
+  std::vector<unsigned int> h(2 * NCELLS);
+  if (hipMemcpyAsync(h.data(), mo->cal, sizeof(unsigned int) * 2 * NCELLS, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(RT_E_DEVICE, "calibration failed");
+  long long trusted = 0;
+  for (int c = 0; c < NCELLS; ++c) {
+    float mx;
+    memcpy(&mx, &h[c], sizeof(float));
+    const bool ok = h[NCELLS + c] >= (unsigned int)gate->min_count && mx <= (float)gate->tol;
+    mo->h_map[c] = ok ? 1 : 0;
+    trusted += ok;
+  }
+  mo->gate = *gate;
+  mo->map_valid = 1;
+  if (trusted_fraction) *trusted_fraction = (double)trusted / NCELLS;
+  return upload_map(mo);
+}
+
+int rt_surrogate_get_map(rt_model mo, uint8_t *host, int32_t *cells_alpha, int32_t *cells_beta) {
+  int e = check_model(mo);
+  if (e) return e;
+  if (cells_alpha) *cells_alpha = NCELL_A;
+  if (cells_beta) *cells_beta = NCELL_B;
+  if (host) memcpy(host, mo->h_map.data(), NCELLS);
+  return RT_OK;
+}
+
+int rt_surrogate_infer(rt_model mo, const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts, int64_t n,
+                       int64_t ld, const float *x6, float *y5, uint8_t *fallback, int32_t *status, void *stream) {
+  int e = check_model(mo);
+  if (e) return e;
+  rt_cloak_desc d;
+  e = cloak_geometry(cloaks, n_cloaks, d);
+  if (e) return e;
+  if (!opts) return fail(RT_E_INVALID, "opts is NULL");
+  if (n == 0) return RT_OK;
+  e = check_rows(n, ld, x6);
+  if (e) return e;
+  if (!y5 || !fallback || !status) return fail(RT_E_INVALID, "y5, fallback and status are required");
+  if (!mo->map_valid) return fail(RT_E_INVALID, "the model has no calibrated trust map (rt_surrogate_calibrate)");
+  hipStream_t s = (hipStream_t)stream;
+  GateP gp;
+  gp.b = (float)d.r2;
+  gp.z0 = std::isfinite(d.z0) ? (float)d.z0 : -INFINITY;
+  gp.z1 = std::isfinite(d.z1) ? (float)d.z1 : INFINITY;
+  gp.hres_max = (float)mo->gate.hres_max;
+  gp.cap_margin = (float)mo->gate.cap_margin;
+  e = reserve_yinf(mo, n);
+  if (e) return e;
+  infer_outputs(mo, x6, ld, (int)n, s);
+  hipLaunchKernelGGL(k_decode_gate, dim3(gblocks(n, 256)), dim3(256), 0, s, x6, (long long)ld, (int)n, mo->yinf,
+                     mo->scal, mo->map, gp, y5, fallback, status);
+  e = launch_err("surrogate launch");
+  if (e) return e;
+  // the exact integrator traces the rejected rays (one persistent launch)
+  e = rt_transit_exact(cloaks, n_cloaks, opts, n, ld, x6, fallback, y5, status, nullptr, stream);
+  return e;
+}
+
+int rt_surrogate_save(rt_model mo, const char *path) {
+  int e = check_model(mo);
+  if (e) return e;
+  if (!path) return fail(RT_E_INVALID, "path is NULL");
+  std::vector<float> h(NPARAM);
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(h.data(), mo->P, sizeof(float) * NPARAM, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(RT_E_DEVICE, "copy failed");
+  FILE *f = fopen(path, "wb");
+  if (!f) return fail(RT_E_INVALID, "cannot open %s", path);
+  const char magic[8] = {'R', 'T', 'M', 'L', 'P', '0', '2', '\0'};
+  const long long np = NPARAM, nc = NCELLS;
+  const int valid = mo->map_valid;
+  bool ok = fwrite(magic, 1, 8, f) == 8 && fwrite(&np, sizeof(np), 1, f) == 1 &&
+            fwrite(mo->h_scal, sizeof(float), S_LOSS, f) == (size_t)S_LOSS &&
+            fwrite(h.data(), sizeof(float), NPARAM, f) == (size_t)NPARAM && fwrite(&nc, sizeof(nc), 1, f) == 1 &&
+            fwrite(&valid, sizeof(valid), 1, f) == 1 && fwrite(&mo->gate, sizeof(mo->gate), 1, f) == 1 &&
+            fwrite(mo->h_map.data(), 1, NCELLS, f) == (size_t)NCELLS;
+  ok = (fclose(f) == 0) && ok;
+  return ok ? RT_OK : fail(RT_E_INVALID, "write to %s failed", path);
+}
+
+int rt_surrogate_load(const char *path, rt_model *out) {
+  if (!path || !out) return fail(RT_E_INVALID, "path and out are required");
+  *out = nullptr;
+  FILE *f = fopen(path, "rb");
+  if (!f) return fail(RT_E_INVALID, "cannot open %s", path);
+  char magic[8];
+  long long np = 0, nc = 0;
+  int valid = 0;
+  float scal[S_LOSS];
+  rt_gate_opts gate;
+  std::vector<float> h(NPARAM);
+  std::vector<unsigned char> map(NCELLS);
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "RTMLP02", 8) == 0 && fread(&np, sizeof(np), 1, f) == 1 &&
+            np == NPARAM && fread(scal, sizeof(float), S_LOSS, f) == (size_t)S_LOSS &&
+            fread(h.data(), sizeof(float), NPARAM, f) == (size_t)NPARAM && fread(&nc, sizeof(nc), 1, f) == 1 &&
+            nc == NCELLS && fread(&valid, sizeof(valid), 1, f) == 1 && fread(&gate, sizeof(gate), 1, f) == 1 &&
+            fread(map.data(), 1, NCELLS, f) == (size_t)NCELLS;
+  fclose(f);
+  if (!ok) return fail(RT_E_INVALID, "%s is not a surrogate file of this layout", path);
+  rt_model mo = nullptr;
+  int e = rt_surrogate_create(0, &mo);
+  if (e) return e;
+  e = rt_surrogate_set_scaling(mo, scal);
+  if (!e) e = rt_surrogate_set_params(mo, h.data());
+  if (!e) {
+    mo->h_map = map;
+    mo->map_valid = valid;
+    mo->gate = gate;
+    e = upload_map(mo);
+  }
+  if (e) {
+    rt_surrogate_free(mo);
+    return e;
+  }
+  *out = mo;
+  return RT_OK;
+}
+
+}  // extern "C"

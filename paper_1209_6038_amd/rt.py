@@ -26,7 +26,13 @@ STATUS_NAMES = ["EXITED", "MISSED", "ABSORBED", "MAXSTEPS", "DIVERGED", "TIR", "
 EXPORTED = ["rt_build_cloak", "rt_free_cloak", "rt_trace_batch", "rt_render", "rt_render_multi",
             "rt_render_plan_create", "rt_render_plan_launch", "rt_render_plan_destroy",
             "rt_autotune_render", "rt_profile_enable", "rt_profile_read", "rt_release_workspace",
-            "rt_last_error"]
+            "rt_last_error", "rt_cloak_get_desc", "rt_transit_exact",
+            "rt_surrogate_create", "rt_surrogate_free", "rt_surrogate_nparams",
+            "rt_surrogate_get_params", "rt_surrogate_set_params", "rt_surrogate_get_scaling",
+            "rt_surrogate_set_scaling", "rt_surrogate_fit_scaling", "rt_surrogate_encode",
+            "rt_surrogate_grad", "rt_surrogate_train", "rt_surrogate_forward",
+            "rt_surrogate_calibrate", "rt_surrogate_get_map", "rt_surrogate_infer",
+            "rt_surrogate_save", "rt_surrogate_load"]
 
 
 class RtError(RuntimeError):
@@ -60,6 +66,17 @@ class Camera(ctypes.Structure):
 class Room(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("tile", ctypes.c_double), ("rgb", ctypes.c_float * 36)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("weight_decay", ctypes.c_float), ("huber", ctypes.c_float)]
+
+
+class GateOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("hres_max", ctypes.c_double),
+                ("cap_margin", ctypes.c_double), ("min_count", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class RenderAux(ctypes.Structure):
@@ -98,6 +115,29 @@ def lib():
         L.rt_profile_enable.argtypes = [i32]
         L.rt_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.rt_last_error.restype = ctypes.c_char_p
+        L.rt_cloak_get_desc.argtypes = [vp, ctypes.POINTER(CloakDesc)]
+        L.rt_transit_exact.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(TraceOpts), i64, i64,
+                                       vp, vp, vp, vp, vp, vp]
+        L.rt_surrogate_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(vp)]
+        L.rt_surrogate_free.argtypes = [vp]
+        L.rt_surrogate_nparams.argtypes = [ctypes.POINTER(i64)]
+        L.rt_surrogate_get_params.argtypes = [vp, vp]
+        L.rt_surrogate_set_params.argtypes = [vp, vp]
+        L.rt_surrogate_get_scaling.argtypes = [vp, vp]
+        L.rt_surrogate_set_scaling.argtypes = [vp, vp]
+        L.rt_surrogate_fit_scaling.argtypes = [vp, i64, i64, vp, vp, vp, vp]
+        L.rt_surrogate_encode.argtypes = [ctypes.POINTER(vp), i32, i64, i64, vp, vp, vp, vp, vp, vp]
+        L.rt_surrogate_grad.argtypes = [vp, i64, i64, vp, vp, vp, ctypes.c_float, vp, vp, vp]
+        L.rt_surrogate_train.argtypes = [vp, i64, i64, vp, vp, vp, ctypes.POINTER(TrainOpts), vp, vp]
+        L.rt_surrogate_forward.argtypes = [vp, i64, i64, vp, vp, vp]
+        L.rt_surrogate_calibrate.argtypes = [vp, ctypes.POINTER(vp), i32, i64, i64, vp, vp, vp,
+                                             ctypes.POINTER(GateOpts), ctypes.POINTER(ctypes.c_double),
+                                             vp]
+        L.rt_surrogate_get_map.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.rt_surrogate_infer.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(TraceOpts), i64,
+                                         i64, vp, vp, vp, vp, vp]
+        L.rt_surrogate_save.argtypes = [vp, ctypes.c_char_p]
+        L.rt_surrogate_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
         for name in EXPORTED:
             getattr(L, name).restype = ctypes.c_char_p if name == "rt_last_error" else ctypes.c_int
         _lib = L
@@ -346,3 +386,162 @@ def profile_read():
 
 def release_workspace():
     _check(lib().rt_release_workspace())
+
+
+# ---------------------------------------------------------------------------
+# transit in entry/exit parameters and the learned surrogate
+# ---------------------------------------------------------------------------
+def _handles(cloaks):
+    return (ctypes.c_void_p * len(cloaks))(*[c.handle for c in cloaks])
+
+
+def _check_soa(x, rows, dtype):
+    import torch
+    assert x.is_cuda and x.dtype == dtype and x.dim() == 2 and x.shape[0] == rows, (x.shape, x.dtype)
+    assert x.stride(1) == 1, "SoA rows must be contiguous"
+    return x.stride(0)
+
+
+def transit_exact(cloaks: list, opts: dict, x6, mask=None, y5=None, status=None, nsteps=False):
+    """rt_transit_exact on float32 CUDA x6 (6, n) (entry phi, z, alpha, beta,
+    branch bit, axis bit). Returns (y5 (5, n) float32, status int32[, nsteps])."""
+    import torch
+    ld = _check_soa(x6, 6, torch.float32)
+    n = x6.shape[1]
+    dev = x6.device
+    if y5 is None:
+        y5 = torch.empty((5, ld), dtype=torch.float32, device=dev)[:, :n]
+    if status is None:
+        status = torch.empty(n, dtype=torch.int32, device=dev)
+    assert y5.stride(0) == ld and y5.stride(1) == 1
+    ns = torch.empty(n, dtype=torch.int32, device=dev) if nsteps else None
+    _check(lib().rt_transit_exact(_handles(cloaks), len(cloaks), ctypes.byref(trace_opts(opts)), n, ld,
+                                  _ptr(x6), _ptr(mask), _ptr(y5), _ptr(status), _ptr(ns), _stream()))
+    return (y5, status, ns) if nsteps else (y5, status)
+
+
+def surrogate_encode(cloaks: list, x6, y5, status):
+    """Training targets t5 (5, n) and row weights w (n) of exact transits."""
+    import torch
+    ld = _check_soa(x6, 6, torch.float32)
+    assert y5.stride(0) == ld
+    n = x6.shape[1]
+    t5 = torch.empty((5, ld), dtype=torch.float32, device=x6.device)[:, :n]
+    w = torch.empty(n, dtype=torch.float32, device=x6.device)
+    _check(lib().rt_surrogate_encode(_handles(cloaks), len(cloaks), n, ld, _ptr(x6), _ptr(y5),
+                                     _ptr(status), _ptr(t5), _ptr(w), _stream()))
+    return t5, w
+
+
+class Surrogate:
+    """Owning wrapper of an rt_model (the transit MLP)."""
+
+    NPARAM = 200453
+
+    def __init__(self, seed: int = 0, path: str | None = None):
+        h = ctypes.c_void_p()
+        if path is not None:
+            _check(lib().rt_surrogate_load(path.encode(), ctypes.byref(h)))
+        else:
+            _check(lib().rt_surrogate_create(int(seed), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().rt_surrogate_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.NPARAM, dtype=np.float32)
+        _check(lib().rt_surrogate_get_params(self.handle, out.ctypes.data))
+        return out
+
+    def set_params(self, p: np.ndarray):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.NPARAM
+        _check(lib().rt_surrogate_set_params(self.handle, p.ctypes.data))
+
+    def get_scaling(self) -> np.ndarray:
+        out = np.empty(22, dtype=np.float32)
+        _check(lib().rt_surrogate_get_scaling(self.handle, out.ctypes.data))
+        return out
+
+    def set_scaling(self, sc: np.ndarray):
+        sc = np.ascontiguousarray(sc, dtype=np.float32)
+        _check(lib().rt_surrogate_set_scaling(self.handle, sc.ctypes.data))
+
+    def fit_scaling(self, x6, t5, w=None):
+        import torch
+        ld = _check_soa(x6, 6, torch.float32)
+        _check(lib().rt_surrogate_fit_scaling(self.handle, x6.shape[1], ld, _ptr(x6), _ptr(t5), _ptr(w),
+                                              _stream()))
+
+    def grad(self, x6, t5, w=None, huber=0.0):
+        """(gradient (NPARAM,) float32 tensor, loss (1,) tensor) of one batch."""
+        import torch
+        ld = _check_soa(x6, 6, torch.float32)
+        g = torch.empty(self.NPARAM, dtype=torch.float32, device=x6.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x6.device)
+        _check(lib().rt_surrogate_grad(self.handle, x6.shape[1], ld, _ptr(x6), _ptr(t5), _ptr(w),
+                                       float(huber), _ptr(g), _ptr(loss), _stream()))
+        return g, loss
+
+    def train_step(self, x6, t5, w=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                   weight_decay=0.0, huber=0.0, loss=None):
+        import torch
+        ld = _check_soa(x6, 6, torch.float32)
+        o = TrainOpts(lr, beta1, beta2, eps, weight_decay, huber)
+        _check(lib().rt_surrogate_train(self.handle, x6.shape[1], ld, _ptr(x6), _ptr(t5), _ptr(w),
+                                        ctypes.byref(o), _ptr(loss), _stream()))
+
+    def forward(self, x6):
+        import torch
+        ld = _check_soa(x6, 6, torch.float32)
+        n = x6.shape[1]
+        t5 = torch.empty((5, ld), dtype=torch.float32, device=x6.device)[:, :n]
+        _check(lib().rt_surrogate_forward(self.handle, n, ld, _ptr(x6), _ptr(t5), _stream()))
+        return t5
+
+    def calibrate(self, cloaks, x6, y5_exact, status_exact, tol=1e-3, hres_max=1e-4,
+                  cap_margin=1e-2, min_count=8) -> float:
+        import torch
+        ld = _check_soa(x6, 6, torch.float32)
+        g = GateOpts(tol, hres_max, cap_margin, min_count, 0)
+        frac = ctypes.c_double()
+        _check(lib().rt_surrogate_calibrate(self.handle, _handles(cloaks), len(cloaks), x6.shape[1], ld,
+                                            _ptr(x6), _ptr(y5_exact), _ptr(status_exact),
+                                            ctypes.byref(g), ctypes.byref(frac), _stream()))
+        return frac.value
+
+    def trust_map(self) -> np.ndarray:
+        na, nb = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().rt_surrogate_get_map(self.handle, None, ctypes.byref(na), ctypes.byref(nb)))
+        out = np.empty((4, na.value, nb.value), dtype=np.uint8)
+        _check(lib().rt_surrogate_get_map(self.handle, out.ctypes.data, None, None))
+        return out
+
+    def infer(self, cloaks, opts: dict, x6, y5=None, fallback=None, status=None):
+        """Surrogate transit with exact fallback: (y5, status, fallback)."""
+        import torch
+        ld = _check_soa(x6, 6, torch.float32)
+        n = x6.shape[1]
+        dev = x6.device
+        if y5 is None:
+            y5 = torch.empty((5, ld), dtype=torch.float32, device=dev)[:, :n]
+        if fallback is None:
+            fallback = torch.empty(n, dtype=torch.uint8, device=dev)
+        if status is None:
+            status = torch.empty(n, dtype=torch.int32, device=dev)
+        _check(lib().rt_surrogate_infer(self.handle, _handles(cloaks), len(cloaks),
+                                        ctypes.byref(trace_opts(opts)), n, ld, _ptr(x6), _ptr(y5),
+                                        _ptr(fallback), _ptr(status), _stream()))
+        return y5, status, fallback
+
+    def save(self, path: str):
+        _check(lib().rt_surrogate_save(self.handle, path.encode()))

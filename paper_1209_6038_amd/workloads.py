@@ -151,6 +151,22 @@ def surrogate_entries(n: int, seed: int, height: float = HEIGHT) -> np.ndarray:
     return out
 
 
+def surrogate_features(n: int, seed: int, height: float = HEIGHT) -> np.ndarray:
+    """Surrogate inputs: the entry parameters of surrogate_entries plus a
+    branch bit (0 ordinary, 1 extraordinary) and an optic-axis bit (0 radial,
+    1 azimuthal), each uniform. float32 SoA (6, n)."""
+    e = surrogate_entries(n, seed, height)
+    rng = np.random.default_rng(seed + 0x5EED)
+    out = np.empty((6, n), dtype=np.float32)
+    out[:4] = e.T
+    out[4] = rng.integers(0, 2, n)
+    out[5] = rng.integers(0, 2, n)
+    # keep |alpha|, |beta| < pi/2 after rounding to float32
+    lim = np.nextafter(np.float32(0.5 * math.pi), np.float32(0.0))
+    out[2:4] = np.clip(out[2:4], -lim, lim)
+    return out
+
+
 def render_opts(precision: int = 0, **kw) -> dict:
     """Integration options of the 3-D render workload: Dormand-Prince 5(4) at
     tolerance 1e-8, FP64 band 0.05 next to the inner radius in mixed mode."""

@@ -36,13 +36,14 @@ def test_forward_matches_torch_cpu():
     np.testing.assert_allclose(y, yt, rtol=1e-12, atol=1e-13)
 
 
-def test_backward_matches_finite_differences():
+@pytest.mark.parametrize("huber", [0.0, 0.3])
+def test_backward_matches_finite_differences(huber):
     p = mlp.init_params(5)
     rng = np.random.default_rng(6)
     x = rng.normal(size=(9, 6))
     t = rng.normal(size=(9, 5))
     w = np.array([1.0, 2.0, 0.5, 1.0, 3.0])
-    loss, g = mlp.loss_and_grads(p, x, t, w)
+    loss, g = mlp.loss_and_grads(p, x, t, w, huber=huber)
     eps = 1e-6
     for li in range(10):
         P = p[li]
@@ -51,9 +52,9 @@ def test_backward_matches_finite_differences():
             idx = np.unravel_index(fi, P.shape)
             old = P[idx]
             P[idx] = old + eps
-            lp, _ = mlp.loss_and_grads(p, x, t, w)
+            lp, _ = mlp.loss_and_grads(p, x, t, w, huber=huber)
             P[idx] = old - eps
-            lm, _ = mlp.loss_and_grads(p, x, t, w)
+            lm, _ = mlp.loss_and_grads(p, x, t, w, huber=huber)
             P[idx] = old
             fd = (lp - lm) / (2 * eps)
             assert g[li][idx] == pytest.approx(fd, rel=2e-5, abs=1e-8), (li, idx)
@@ -63,3 +64,24 @@ def test_silu_derivative():
     z = np.linspace(-8, 8, 33)
     fd = (mlp.silu(z + 1e-6) - mlp.silu(z - 1e-6)) / 2e-6
     np.testing.assert_allclose(mlp.silu_grad(z), fd, rtol=1e-7, atol=1e-9)
+
+
+def test_huber_limits():
+    """Huber with a delta above every residual is the squared error; with a
+    small delta every residual is on the linear branch, whose value is
+    2 delta |d| - delta^2 summed (a closed form checked directly)."""
+    p = mlp.init_params(11)
+    rng = np.random.default_rng(12)
+    x = rng.normal(size=(7, 6))
+    t = rng.normal(size=(7, 5)) + 3.0
+    l2, g2 = mlp.loss_and_grads(p, x, t)
+    lh, gh = mlp.loss_and_grads(p, x, t, huber=1e3)
+    assert lh == pytest.approx(l2, rel=1e-14)
+    for a, b in zip(g2, gh):
+        np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-15)
+    y, _ = mlp.forward(p, x)
+    d = np.abs(y - t)
+    delta = 1e-3
+    assert d.min() > delta
+    ls, _ = mlp.loss_and_grads(p, x, t, huber=delta)
+    assert ls == pytest.approx((2 * delta * d - delta * delta).sum() / 7, rel=1e-13)
