@@ -275,7 +275,7 @@ typedef struct {
     double hres_max;    /* conservation residual limit */
     double cap_margin;  /* exit-height margin from the caps */
     int32_t min_count;  /* calibration rays a cell needs to be trusted */
-    int32_t reserved;
+    int32_t dilate;     /* also distrust cells within this many cells (same axis and branch) of an untrusted one */
 } rt_gate_opts;
 
 /* New model with weights and biases uniform in +-1/sqrt(fan_in) (seeded),
@@ -319,7 +319,10 @@ int rt_surrogate_forward(rt_model model, int64_t n, int64_t ld, const float *x6,
 /* Build the trust map: predicts the calibration rays x6, measures each
    one's exit error max(|x - x_exact| / r2, angle(d, d_exact)) against the
    exact exits, and trusts a cell when it holds >= min_count rays, all of
-   them side-to-side transits with error <= tol. Stores `gate` in the model.
+   them side-to-side transits with error <= tol, and no cell within
+   `dilate` cells of it (in alpha and beta) fails that test (discontinuities
+   of the transit run along thin curves that a cell's calibration rays can
+   miss). Stores `gate` in the model.
    trusted_fraction (host, may be NULL): share of trusted cells. Synchronous. */
 int rt_surrogate_calibrate(rt_model model, const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int64_t ld,
                            const float *x6, const float *y5_exact, const int32_t *status_exact,

@@ -190,7 +190,23 @@ __global__ void __launch_bounds__(256) k_gemm(Gemm g) {
       }
 }
 
-// layer 1 in FP32: xn = (x - in_off) * in_scale, z1 = xn W1 + b1,
+// Network input features of entry i. The transit of the infinite cylinder
+// is invariant under rotation about and translation along its axis, so the
+// exit offsets do not depend on phi or z; those two slots carry instead the
+// entry's tangential wave numbers k_theta = cos(beta) sin(alpha) and
+// k_z = sin(beta), the invariants p_theta / r2 and p_z of the transit:
+//   f = (k_theta, k_z, alpha, beta, branch bit, axis bit).
+__device__ __forceinline__ void features(const float *__restrict__ x6, long long ld, long long i, float f[NIN]) {
+  const float al = x6[2 * ld + i], be = x6[3 * ld + i];
+  f[0] = cosf(be) * sinf(al);
+  f[1] = sinf(be);
+  f[2] = al;
+  f[3] = be;
+  f[4] = x6[4 * ld + i];
+  f[5] = x6[5 * ld + i];
+}
+
+// layer 1 in FP32: xn = (f - in_off) * in_scale, z1 = xn W1 + b1,
 // a1 = bf16(silu z1). One block per row, thread j = hidden unit j.
 __global__ void __launch_bounds__(256) k_layer1(const float *__restrict__ x, long long ld, int n,
                                                 const float *__restrict__ P, const float *__restrict__ sc,
@@ -201,9 +217,11 @@ __global__ void __launch_bounds__(256) k_layer1(const float *__restrict__ x, lon
   for (int k = 0; k < NIN; ++k) w[k] = P[OFF_W1 + k * HID + j];
   const float b = P[OFF_B1 + j];
   for (int row = blockIdx.x; row < n; row += gridDim.x) {
+    float f[NIN];
+    features(x, ld, row, f);
     float z = b;
 #pragma unroll
-    for (int k = 0; k < NIN; ++k) z = fmaf((x[k * ld + row] - sc[S_INOFF + k]) * sc[S_INSCALE + k], w[k], z);
+    for (int k = 0; k < NIN; ++k) z = fmaf((f[k] - sc[S_INOFF + k]) * sc[S_INSCALE + k], w[k], z);
     if (z1) z1[(long long)row * HID + j] = z;
     a1[(long long)row * HID + j] = (bf16)silu_f(z);
   }
@@ -332,9 +350,11 @@ __global__ void __launch_bounds__(256) k_layer1_back(const float *__restrict__ x
   float gw[NIN] = {0, 0, 0, 0, 0, 0}, gb = 0.f;
   for (int row = blockIdx.x; row < n; row += gridDim.x) {
     const float d = dz1[(long long)row * HID + j];
+    float f[NIN];
+    features(x, ld, row, f);
     gb += d;
 #pragma unroll
-    for (int k = 0; k < NIN; ++k) gw[k] = fmaf((x[k * ld + row] - sc[S_INOFF + k]) * sc[S_INSCALE + k], d, gw[k]);
+    for (int k = 0; k < NIN; ++k) gw[k] = fmaf((f[k] - sc[S_INOFF + k]) * sc[S_INSCALE + k], d, gw[k]);
   }
 #pragma unroll
   for (int k = 0; k < NIN; ++k) atomicAdd(&G[OFF_W1 + k * HID + j], gw[k]);
@@ -394,7 +414,7 @@ __global__ void k_refresh_bf16(const float *__restrict__ P, bf16 *__restrict__ P
   if (k >= 0) Pb[k] = (bf16)P[i];
 }
 
-// masked first and second moments of the 6 inputs and 5 targets (FP64 sums)
+// masked first and second moments of the 6 input features and 5 targets (FP64 sums)
 constexpr int NMOM = 2 * (NIN + NOUT) + 1;
 __global__ void __launch_bounds__(256) k_moments(const float *__restrict__ x, const float *__restrict__ t, long long ld,
                                                  const float *__restrict__ wrow, int n, double *__restrict__ acc) {
@@ -405,9 +425,11 @@ __global__ void __launch_bounds__(256) k_moments(const float *__restrict__ x, co
     const double wr = wrow ? wrow[i] : 1.0;
     if (wr == 0.0) continue;
     s[NMOM - 1] += wr;
+    float f[NIN];
+    features(x, ld, i, f);
 #pragma unroll
     for (int k = 0; k < NIN; ++k) {
-      const double v = x[k * ld + i];
+      const double v = f[k];
       s[2 * k] += wr * v;
       s[2 * k + 1] += wr * v * v;
     }
@@ -435,27 +457,67 @@ __global__ void k_fill_f64(double *p, int n) {
 // ---------------------------------------------------------------------------
 // Target encoding. Entry (phi, z, alpha, beta) on r = b, exit (phi', z',
 // alpha', beta') on r = b, optical path T between them:
-//   t0 = dtheta - base,  t1 = (z' - z) cos(beta) / 2b,  t2 = alpha' - alpha,
-//   t3 = beta' - beta,   t4 = T cos(beta) / 2b.
-// dtheta is the signed azimuth swept by the ray. The conserved angular
-// momentum p_theta keeps its sign along the path (the inner mirror reflects
-// radially), so theta is monotonic with the sign s of alpha, and
-// dtheta = s * ((s (phi' - phi)) mod 2 pi) unwraps exactly for transits of
-// less than a full turn. base = s pi for the azimuthal cloak's
-// extraordinary branch, whose turning radius r - a = |p_theta| /
-// sqrt(kappa - p_z^2) shrinks to zero with p_theta while its angular rate
-// grows like 1/p_theta, so that dtheta -> s pi; base = 0 for the other
-// branches, whose dtheta is continuous through alpha = 0. The factors
-// cos(beta) / 2b make t1 and t4 the vertical travel and path length in
-// units of the vacuum chord 2b cos(alpha) / cos(beta), bounded for grazing
-// elevations.
+//   t0 = dtheta - dtheta_0,  t1 = (dz - dz_0) cos(beta) / 2b,
+//   t2 = alpha' - alpha,     t3 = beta' - beta,
+//   t4 = (T - T_0) cos(beta) / 2b,
+// with dz = z' - z and dtheta the signed azimuth swept by the ray. The
+// conserved angular momentum p_theta keeps its sign along the path (the
+// inner mirror reflects radially), so theta is monotonic with the sign s of
+// alpha, and dtheta = s * ((s (phi' - phi)) mod 2 pi) unwraps exactly for
+// transits of less than a full turn. The factors cos(beta) / 2b measure
+// vertical travel and path length in units of the vacuum chord
+// 2b cos(alpha) / cos(beta), bounded at grazing elevations.
+//
+// (dtheta_0, dz_0, T_0) is the closed-form transit where one exists (zero
+// otherwise), so that the network learns a residual:
+//  - radial cloak, ordinary branch: M = kappa I (Eq. (14): eps_o = kappa),
+//    a homogeneous medium of index n = sqrt(kappa) = b / (b - a); the ray is
+//    straight inside, with horizontal wave number k_h = sqrt(n^2 - k_z^2)
+//    and horizontal impact parameter p = b |k_theta| / k_h, and reflects
+//    specularly off the metal cylinder when p <= a (Sect. 4);
+//  - azimuthal cloak, extraordinary branch: M = diag(kappa, kappa s, kappa)
+//    (Eq. (15)) makes the line element drho^2 + rho^2 dtheta^2 + dzeta^2 with
+//    rho = sqrt(kappa) (r - a), zeta = sqrt(kappa) z: a straight line in
+//    (rho, theta, zeta) at unit speed, entering at rho = b with tangential
+//    speed k_theta and axial speed k_z / sqrt(kappa).
+// The radial cloak's extraordinary and the azimuthal cloak's ordinary
+// branch have no closed form: zero baseline.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float wrap2pi(float a) {
   a = fmodf(a, 2.0f * PI_F);
   return a < 0.0f ? a + 2.0f * PI_F : a;
 }
 
-__device__ __forceinline__ float dtheta_base(int kind, float s) { return kind == 3 ? s * PI_F : 0.0f; }
+// half the azimuth swept along a chord of a circle of radius 1 with impact
+// parameter u in [0, 1]: acos(u), in a form accurate near u = 1
+__device__ __forceinline__ float half_sweep(float u) { return atan2f(sqrtf(fmaxf(0.f, (1.f - u) * (1.f + u))), u); }
+
+__device__ __forceinline__ void baseline(int kind, float al, float be, float a, float b, float &dth, float &dz,
+                                         float &T) {
+  dth = 0.f; dz = 0.f; T = 0.f;
+  const float s = al < 0.0f ? -1.0f : 1.0f;
+  const float kt = fabsf(cosf(be) * sinf(al)), kz = sinf(be);
+  const float n = b / (b - a), kap = n * n;
+  if (kind == 0) {
+    const float kh = sqrtf(kap - kz * kz);
+    const float u = kt / kh;  // p / b
+    float sweep = half_sweep(u), lh = b * sqrtf(fmaxf(0.f, (1.f - u) * (1.f + u)));
+    const float ua = u * (b / a);  // p / a
+    if (ua <= 1.0f) {
+      sweep -= half_sweep(ua);
+      lh -= a * sqrtf(fmaxf(0.f, (1.f - ua) * (1.f + ua)));
+    }
+    dth = 2.0f * s * sweep;
+    dz = 2.0f * lh * kz / kh;
+    T = 2.0f * lh * kap / kh;
+  } else if (kind == 3) {
+    const float h = sqrtf(1.0f - kz * kz / kap);
+    const float u = kt / h;
+    dth = 2.0f * s * half_sweep(u);
+    T = 2.0f * b * sqrtf(fmaxf(0.f, (1.f - u) * (1.f + u))) / h;
+    dz = T * kz / kap;
+  }
+}
 
 __device__ __forceinline__ int kind_of(float pol, float axis) {
   return (axis == 0.0f ? 0 : 2) + (pol == 0.0f ? 0 : 1);
@@ -467,8 +529,8 @@ __device__ __forceinline__ bool entry_ok(float phi, float z, float al, float be,
 }
 
 __global__ void __launch_bounds__(256) k_encode(const float *__restrict__ x6, const float *__restrict__ y5,
-                                                const int *__restrict__ status, long long ld, long long n, float b,
-                                                float *__restrict__ t5, float *__restrict__ wrow) {
+                                                const int *__restrict__ status, long long ld, long long n, float a,
+                                                float b, float *__restrict__ t5, float *__restrict__ wrow) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float phi = x6[i], z = x6[ld + i], al = x6[2 * ld + i], be = x6[3 * ld + i];
@@ -479,11 +541,13 @@ __global__ void __launch_bounds__(256) k_encode(const float *__restrict__ x6, co
     const float s = al < 0.0f ? -1.0f : 1.0f;
     const float dth = s * wrap2pi(s * (y5[i] - phi));
     const float cb = cosf(be);
-    t[0] = dth - dtheta_base(kind_of(pol, axis), s);
-    t[1] = (y5[ld + i] - z) * cb / (2.0f * b);
+    float dth0, dz0, T0;
+    baseline(kind_of(pol, axis), al, be, a, b, dth0, dz0, T0);
+    t[0] = dth - dth0;
+    t[1] = (y5[ld + i] - z - dz0) * cb / (2.0f * b);
     t[2] = y5[2 * ld + i] - al;
     t[3] = y5[3 * ld + i] - be;
-    t[4] = y5[4 * ld + i] * cb / (2.0f * b);
+    t[4] = (y5[4 * ld + i] - T0) * cb / (2.0f * b);
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) ok = ok && isfinite(t[o]);
   }
@@ -494,17 +558,18 @@ __global__ void __launch_bounds__(256) k_encode(const float *__restrict__ x6, co
 
 // standardized network outputs -> exit parameters (phi', z', alpha', beta', T)
 __device__ __forceinline__ void decode(const float *yrow, const float *sc, float phi, float z, float al, float be,
-                                       int kind, float b, float out[NOUT]) {
+                                       int kind, float a, float b, float out[NOUT]) {
   float t[NOUT];
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) t[o] = fmaf(yrow[o], sc[S_OSTD + o], sc[S_OMEAN + o]);
-  const float s = al < 0.0f ? -1.0f : 1.0f;
+  float dth0, dz0, T0;
+  baseline(kind, al, be, a, b, dth0, dz0, T0);
   const float inv_cb = 1.0f / cosf(be);
-  out[0] = wrap2pi(phi + t[0] + dtheta_base(kind, s));
-  out[1] = z + t[1] * 2.0f * b * inv_cb;
+  out[0] = wrap2pi(phi + t[0] + dth0);
+  out[1] = z + dz0 + t[1] * 2.0f * b * inv_cb;
   out[2] = al + t[2];
   out[3] = be + t[3];
-  out[4] = t[4] * 2.0f * b * inv_cb;
+  out[4] = T0 + t[4] * 2.0f * b * inv_cb;
 }
 
 // cell of the trust map
@@ -517,7 +582,7 @@ __device__ __forceinline__ int cell_of(int kind, float al, float be) {
 }
 
 struct GateP {
-  float b, z0, z1;   // cloak radius r2 and material height range
+  float a, b, z0, z1;  // cloak radii r1, r2 and material height range
   float hres_max;    // conservation residual limit
   float cap_margin;  // distance of the predicted exit height from a cap
 };
@@ -544,7 +609,7 @@ __device__ __forceinline__ void gate_row(long long i, const float *__restrict__ 
   float out[NOUT];
   if (acc) {
     const int kind = kind_of(pol, axis);
-    decode(yrow, sc, phi, z, al, be, kind, gp.b, out);
+    decode(yrow, sc, phi, z, al, be, kind, gp.a, gp.b, out);
     acc = map[cell_of(kind, al, be)] != 0;
     const float kt = cosf(be) * sinf(al), kz = sinf(be);
     const float kt2 = cosf(out[3]) * sinf(out[2]), kz2 = sinf(out[3]);
@@ -593,11 +658,17 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fused(const float *__restrict__ 
   __shared__ float xn[FR * NIN];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const long long row0 = (long long)blockIdx.x * FR;
-  // standardized inputs of the tile (rows past n read as zeros)
-  for (int e = tid; e < FR * NIN; e += 256) {
-    const int r = e / NIN, k = e - r * NIN;
-    const long long i = row0 + r;
-    xn[e] = i < n ? (x6[k * ld + i] - sc[S_INOFF + k]) * sc[S_INSCALE + k] : 0.0f;
+  // standardized input features of the tile (rows past n read as zeros)
+  if (tid < FR) {
+    const long long i = row0 + tid;
+    float f[NIN] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (i < n) {
+      features(x6, ld, i, f);
+#pragma unroll
+      for (int k = 0; k < NIN; ++k) f[k] = (f[k] - sc[S_INOFF + k]) * sc[S_INSCALE + k];
+    }
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) xn[tid * NIN + k] = f[k];
   }
   __syncthreads();
   {  // layer 1 (FP32): thread = hidden unit
@@ -713,8 +784,9 @@ __device__ __forceinline__ void exit_ray(const float *p, float b, float x[3], fl
 // makes its cell untrusted
 __global__ void __launch_bounds__(256) k_calib(const float *__restrict__ x6, long long ld, int n,
                                                const float *__restrict__ y, const float *__restrict__ sc,
-                                               const float *__restrict__ ye, const int *__restrict__ st, float b,
-                                               unsigned int *__restrict__ cmax, unsigned int *__restrict__ ccnt) {
+                                               const float *__restrict__ ye, const int *__restrict__ st, float a,
+                                               float b, unsigned int *__restrict__ cmax,
+                                               unsigned int *__restrict__ ccnt) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float phi = x6[i], z = x6[ld + i], al = x6[2 * ld + i], be = x6[3 * ld + i];
@@ -725,7 +797,7 @@ __global__ void __launch_bounds__(256) k_calib(const float *__restrict__ x6, lon
   float err = INFINITY;
   if (st[i] == RT_RAY_EXITED) {
     float out[NOUT], ex[NOUT], xp[3], dp[3], xe[3], de[3];
-    decode(y + i * NOUT, sc, phi, z, al, be, kind, b, out);
+    decode(y + i * NOUT, sc, phi, z, al, be, kind, a, b, out);
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) ex[o] = ye[o * ld + i];
     exit_ray(out, b, xp, dp);
@@ -1160,7 +1232,7 @@ int rt_surrogate_encode(const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int
   if (e) return e;
   if (!y5 || !status || !t5 || !w) return fail(RT_E_INVALID, "y5, status, t5 and w are required");
   hipLaunchKernelGGL(k_encode, dim3(gblocks(n, 256)), dim3(256), 0, (hipStream_t)stream, x6, y5, status,
-                     (long long)ld, (long long)n, (float)d.r2, t5, w);
+                     (long long)ld, (long long)n, (float)d.r1, (float)d.r2, t5, w);
   return launch_err("encode launch");
 }
 
@@ -1174,27 +1246,41 @@ int rt_surrogate_calibrate(rt_model mo, const rt_cloak *cloaks, int32_t n_cloaks
   if (!e) e = check_rows(n, ld, x6);
   if (e) return e;
   if (!y5_exact || !status_exact || !gate) return fail(RT_E_INVALID, "y5_exact, status_exact and gate are required");
-  if (!(gate->tol > 0.0) || !(gate->hres_max > 0.0) || !(gate->cap_margin >= 0.0) || gate->min_count < 1)
-    return fail(RT_E_INVALID, "gate needs tol > 0, hres_max > 0, cap_margin >= 0, min_count >= 1");
+  if (!(gate->tol > 0.0) || !(gate->hres_max > 0.0) || !(gate->cap_margin >= 0.0) || gate->min_count < 1 ||
+      gate->dilate < 0 || gate->dilate > 8)
+    return fail(RT_E_INVALID, "gate needs tol > 0, hres_max > 0, cap_margin >= 0, min_count >= 1, 0 <= dilate <= 8");
   e = reserve_yinf(mo, n);
   if (e) return e;
   hipStream_t s = (hipStream_t)stream;
   infer_outputs(mo, x6, ld, (int)n, s);
   hipLaunchKernelGGL(k_fill_u32, dim3(gblocks(2LL * NCELLS, 256)), dim3(256), 0, s, mo->cal, 2LL * NCELLS);
   hipLaunchKernelGGL(k_calib, dim3(gblocks(n, 256)), dim3(256), 0, s, x6, (long long)ld, (int)n, mo->yinf, mo->scal,
-                     y5_exact, status_exact, (float)d.r2, mo->cal, mo->cal + NCELLS);
+                     y5_exact, status_exact, (float)d.r1, (float)d.r2, mo->cal, mo->cal + NCELLS);
   std::vector<unsigned int> h(2 * NCELLS);
   if (hipMemcpyAsync(h.data(), mo->cal, sizeof(unsigned int) * 2 * NCELLS, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(RT_E_DEVICE, "calibration failed");
-  long long trusted = 0;
+  std::vector<unsigned char> good(NCELLS);
   for (int c = 0; c < NCELLS; ++c) {
     float mx;
     memcpy(&mx, &h[c], sizeof(float));
-    const bool ok = h[NCELLS + c] >= (unsigned int)gate->min_count && mx <= (float)gate->tol;
-    mo->h_map[c] = ok ? 1 : 0;
-    trusted += ok;
+    good[c] = h[NCELLS + c] >= (unsigned int)gate->min_count && mx <= (float)gate->tol;
   }
+  const int dl = gate->dilate;
+  long long trusted = 0;
+  for (int k = 0; k < NCOMBO; ++k)
+    for (int ia = 0; ia < NCELL_A; ++ia)
+      for (int ib = 0; ib < NCELL_B; ++ib) {
+        bool ok = true;
+        for (int da = -dl; da <= dl && ok; ++da)
+          for (int db = -dl; db <= dl && ok; ++db) {
+            const int ja = ia + da, jb = ib + db;
+            if (ja < 0 || ja >= NCELL_A || jb < 0 || jb >= NCELL_B) continue;
+            ok = good[(k * NCELL_A + ja) * NCELL_B + jb] != 0;
+          }
+        mo->h_map[(k * NCELL_A + ia) * NCELL_B + ib] = ok ? 1 : 0;
+        trusted += ok;
+      }
   mo->gate = *gate;
   mo->map_valid = 1;
   if (trusted_fraction) *trusted_fraction = (double)trusted / NCELLS;
@@ -1225,6 +1311,7 @@ int rt_surrogate_infer(rt_model mo, const rt_cloak *cloaks, int32_t n_cloaks, co
   if (!mo->map_valid) return fail(RT_E_INVALID, "the model has no calibrated trust map (rt_surrogate_calibrate)");
   hipStream_t s = (hipStream_t)stream;
   GateP gp;
+  gp.a = (float)d.r1;
   gp.b = (float)d.r2;
   gp.z0 = std::isfinite(d.z0) ? (float)d.z0 : -INFINITY;
   gp.z1 = std::isfinite(d.z1) ? (float)d.z1 : INFINITY;

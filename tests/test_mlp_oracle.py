@@ -85,3 +85,23 @@ def test_huber_limits():
     assert d.min() > delta
     ls, _ = mlp.loss_and_grads(p, x, t, huber=delta)
     assert ls == pytest.approx((2 * delta * d - delta * delta).sum() / 7, rel=1e-13)
+
+
+def test_features_are_the_tangential_wave_numbers():
+    """k_theta and k_z are the components of the unit entry direction
+    d = cos(beta) (cos(alpha) (-r) + sin(alpha) theta) + sin(beta) z along
+    theta and z (built here from the vectors, not the formula)."""
+    rng = np.random.default_rng(3)
+    x6 = np.stack([rng.uniform(0, 6.28, 50), rng.uniform(0, 4, 50), rng.uniform(-1.5, 1.5, 50),
+                   rng.uniform(-1.5, 1.5, 50), rng.integers(0, 2, 50), rng.integers(0, 2, 50)])
+    f = mlp.features(x6)
+    for i in range(50):
+        phi, al, be = x6[0, i], x6[2, i], x6[3, i]
+        rh = np.array([np.cos(phi), np.sin(phi), 0.0])
+        th = np.array([-np.sin(phi), np.cos(phi), 0.0])
+        ez = np.array([0.0, 0.0, 1.0])
+        d = np.cos(be) * (np.cos(al) * -rh + np.sin(al) * th) + np.sin(be) * ez
+        assert abs(np.linalg.norm(d) - 1) < 1e-12
+        assert f[i, 0] == pytest.approx(d @ th, abs=1e-13)
+        assert f[i, 1] == pytest.approx(d @ ez, abs=1e-13)
+        assert list(f[i, 2:]) == [al, be, x6[4, i], x6[5, i]]
