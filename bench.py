@@ -69,8 +69,8 @@ def attempt_flops(kind: int, scheme: int) -> int:
 # (FETCH_SIZE, WRITE_SIZE) of this benchmark, scaled by the same counters on a
 # plain device copy of known size (bench.py --copy-probe). Valid only for the
 # integrator source it was measured on; reported as null otherwise.
-TRAFFIC = {"source_sha256": "c5a6e9966dc8c97f447738137c417f9aea6d24083d2cd075038fb3849bd441d4",
-           "bytes_per_launch": 910121638}
+TRAFFIC = {"source_sha256": "bf84df4c5f40b43633f9c3a155f12d8cbd2d503a11f5632d1bd438e421b14b3a",
+           "bytes_per_launch": 856791040}
 
 
 def integrator_source_hash() -> str:
@@ -205,13 +205,64 @@ def surrogate_leg(steps: int, n_train: int, log):
     }
 
 
+def orbit_workload(args):
+    """The large-render workload timed plain: 36-frame orbit at 30 deg
+    elevation, 4096 x 4096 px, 4 jittered samples per pixel, radial and
+    azimuthal cloaks, both branches; one rt_render_multi call per frame."""
+    import numpy as np
+    import torch
+    from paper_1209_6038_amd import rt
+    from paper_1209_6038_amd import workloads as W
+
+    frames = W.orbit_frames(36, 4096, 4)
+    opts = W.render_opts()
+    cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
+    room = W.room()
+    dev = torch.device("cuda", 0)
+    out = torch.empty((2, 1, 2, 4096, 4096, 3), dtype=torch.float32, device=dev)
+    # entering rays per frame (untimed counting pass, status only)
+    # the orbit is symmetric up to the jitter: every 9th frame is counted
+    entered = 0
+    counted = frames[::9]
+    for f in counted:
+        _, aux = rt.render_multi(cloaks, opts, room, [f], 3, aux=True)
+        torch.cuda.synchronize()
+        entered += int(torch.isin(aux["status"], torch.tensor([0, 2, 3, 4, 5], device=dev,
+                                                                dtype=torch.int32)).sum())
+        del aux
+    entered_per_frame = entered / len(counted)
+    rt.render_multi(cloaks, opts, room, [frames[0]], 3, out=out)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for f in frames:
+        rt.render_multi(cloaks, opts, room, [f], 3, out=out)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    samples = 36 * 4096 * 4096 * 4 * 2 * 2
+    return {
+        "metric": "Mrays/s traced through cloak at <=1e-6 exit error", "unit": "Mrays/s",
+        "value": round(entered_per_frame * 36 / (ms * 1e-3) / 1e6, 3), "n_gpus": 1,
+        "ms_per_step": round(ms, 2), "steps": 1, "warmup": 1, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "large render: 36-frame orbit at 30 deg elevation, 4096^2 px x 4 jittered spp, "
+                               "radial + azimuthal cloaks, ordinary + extraordinary, DP45 tol 1e-8, plain tracer",
+                   "ray_branch_samples": samples, "ms_per_frame": round(ms / 36, 2),
+                   "all_samples_per_s_M": round(samples / (ms * 1e-3) / 1e6, 1),
+                   "entered_per_frame_estimate": int(entered_per_frame),
+                   "frames_counted_for_entered": len(counted)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--res", type=int, default=1024)
-    ap.add_argument("--workload", choices=("render3d", "batched"), default="render3d")
+    ap.add_argument("--workload", choices=("render3d", "batched", "orbit"), default="render3d")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed")
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
@@ -242,6 +293,9 @@ def main():
         B.build()
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if args.workload == "orbit":
+        print(json.dumps(orbit_workload(args)), flush=True)
+        return
     batched = args.workload == "batched"
     cams = W.batched_views(64, 512) if batched else W.render_views(res=args.res)
     res = int(cams[0]["w"])
