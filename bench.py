@@ -262,7 +262,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--res", type=int, default=1024)
-    ap.add_argument("--workload", choices=("render3d", "batched", "orbit"), default="render3d")
+    ap.add_argument("--workload", choices=("render3d", "batched", "orbit", "surrogate"), default="render3d")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed")
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
@@ -295,6 +295,12 @@ def main():
     dev = torch.device("cuda", 0)
     if args.workload == "orbit":
         print(json.dumps(orbit_workload(args)), flush=True)
+        return
+    if args.workload == "surrogate":
+        torch.cuda.set_device(0)
+        rec = surrogate_leg(args.surrogate_steps, args.surrogate_train,
+                            lambda msg: print(msg, file=sys.stderr, flush=True))
+        print(json.dumps({"config": {"workload": "surrogate leg only"}, "surrogate": rec}), flush=True)
         return
     batched = args.workload == "batched"
     cams = W.batched_views(64, 512) if batched else W.render_views(res=args.res)
