@@ -34,6 +34,16 @@ def to_bf16(a):
     return out
 
 
+def features(x6):
+    """Network input features of entries x6 (6, n): the tangential wave
+    numbers k_theta = cos(beta) sin(alpha) and k_z = sin(beta) in place of
+    the azimuth and height (which the transit of the infinite cylinder does
+    not depend on), then alpha, beta and the two bits. Returns (n, 6)."""
+    x6 = np.asarray(x6, dtype=np.float64)
+    al, be = x6[2], x6[3]
+    return np.stack([np.cos(be) * np.sin(al), np.sin(be), al, be, x6[4], x6[5]], axis=1)
+
+
 def silu(z):
     return z / (1.0 + np.exp(-z))
 
