@@ -69,8 +69,8 @@ def attempt_flops(kind: int, scheme: int) -> int:
 # (FETCH_SIZE, WRITE_SIZE) of this benchmark, scaled by the same counters on a
 # plain device copy of known size (bench.py --copy-probe). Valid only for the
 # integrator source it was measured on; reported as null otherwise.
-TRAFFIC = {"source_sha256": "bf84df4c5f40b43633f9c3a155f12d8cbd2d503a11f5632d1bd438e421b14b3a",
-           "bytes_per_launch": 856791040}
+TRAFFIC = {"source_sha256": "636e1a6c175e8a4dea249d64444d277f0e40bfae7413b181ed2d476347bdbc61",
+           "bytes_per_launch": 811038720}
 
 
 def integrator_source_hash() -> str:

@@ -454,74 +454,53 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
 // reflection or the inner metal mirror (the ray continues from the boundary
 // point with the step controller restarted). Only this bookkeeping diverges;
 // the attempt itself is the same code for every lane of a branch.
-template <bool MIXED>
-__global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int refill) {
-  // the queue holds the used parts of the segments one after the other,
-  // each sorted hardest first; a wave works on one segment at a time so that
-  // its lanes run the same branch code, and moves on to the next segment
-  // that still has rays when its own is drained
-  const SegMap sm = seg_map(T);
-  const double band2 = (c.a + o.band) * (c.a + o.band);
-  const double tol = 1e-13 * c.b;
-  int slot = -1, kind = 0;
+// Integrate the rays of segment `seg` (all of one branch, KIND) with the
+// calling wave until the segment's queue is drained and every lane of the
+// wave is idle. The wave claims chunks of FETCH_CHUNK queue positions with
+// one atomic each and refills its idle lanes every `refill` attempts. The
+// lane state lives here, specialized for the branch, so no code of another
+// branch is interleaved with the step loop.
+template <int KIND, bool MIXED>
+__device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, const Table &T, const SegMap &sm,
+                                            int seg, double band2, double tol, int refill,
+                                            unsigned int &drained) {
+  int slot = -1;
   Lane L;
   L.h = 0.0; L.t = 0.0; L.lo = 0.0; L.hi = 0.0; L.ht = 0.0;
+  L.x[0] = L.x[1] = L.x[2] = 0.0; L.v[0] = L.v[1] = L.v[2] = 0.0; L.A1[0] = L.A1[1] = L.A1[2] = 0.0;
   L.ns = 0; L.bounces = 0; L.rid = -1; L.riter = 0; L.after_reject = false;
-  // wave-private chunk [cur, end) of the queue, refilled with one atomic per
-  // FETCH_CHUNK rays; cur, end, seg and drained are wave-uniform
+  // wave-private chunk [cur, end) of the queue; cur, end and drained are wave-uniform
   unsigned int cur = 0, end = 0;
-  unsigned int drained = 0;  // bit q: segment q has no rays left
-  int nused = 0;
-#pragma unroll
-  for (int q = 0; q < NSEG; ++q) {
-    if (sm.off[q + 1] == sm.off[q]) drained |= 1u << q;
-    else ++nused;
-  }
-  const unsigned int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  int seg = 0;
-  if (nused > 0) {
-    // start on the (wave mod nused)-th used segment
-    int k = (int)(wave % (unsigned int)nused);
-    for (int q = 0; q < NSEG; ++q)
-      if (!(drained >> q & 1u)) {
-        if (k == 0) { seg = q; break; }
-        --k;
-      }
-  }
-
+  const unsigned int off = off_of(sm, seg), len = off_of(sm, seg + 1) - off;
   for (;;) {
-    for (int round = 0; round < 2 * NSEG; ++round) {
-      bool need = slot < 0;
-      unsigned long long m = __ballot(need);
-      if (m == 0ull) break;
+    unsigned long long m = __ballot(slot < 0);
+    while (m != 0ull) {
       if (cur >= end) {
-        if (drained == (1u << NSEG) - 1u) break;
-        while (drained >> seg & 1u) seg = (seg + 1) % NSEG;
-        const unsigned int off = off_of(sm, seg), len = off_of(sm, seg + 1) - off;
+        if (drained >> seg & 1u) break;
         unsigned int base = 0;
         if (__lane_id() == 0) base = atomicAdd(T.ctr + C_FETCH + seg, FETCH_CHUNK);
         base = __shfl(base, 0);
         if (base + FETCH_CHUNK >= len) drained |= 1u << seg;
         cur = off + min(base, len);
         end = off + min(base + FETCH_CHUNK, len);
-        if (cur >= end) continue;
+        continue;
       }
-      unsigned int idx = cur + (unsigned int)__popcll(m & lanemask_lt());
-      if (need && idx < end) {
+      const unsigned int idx = cur + (unsigned int)__popcll(m & lanemask_lt());
+      if (slot < 0 && idx < end) {
         slot = T.order[idx];
         load_state(T, slot, L.x, L.v);
         L.t = T.t[slot];
         L.h = T.h[slot];
         L.ns = T.nsteps[slot];
         L.bounces = T.bounces[slot];
-        kind = T.kind[slot];
         L.after_reject = false;
         L.rid = -1;
-        accel_k<MIXED>(kind, c.a, band2, L.x, L.v, L.A1);
+        accel<KIND, MIXED>(c.a, band2, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
       }
       cur = min(cur + (unsigned int)__popcll(m), end);
+      m = __ballot(slot < 0);
     }
-    if (__ballot(slot >= 0) == 0ull) break;
+    if (__ballot(slot >= 0) == 0ull) return;
 
     // A wave that holds a ray past LONG_RAY_ATTEMPTS attempts is on the
     // launch's critical path (the longest rays take ~1500 attempts where the
@@ -533,13 +512,7 @@ __global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int
     for (int it = 0; it < refill; ++it) {
       if (slot >= 0) {
         double hr = __builtin_nan("");
-        int stop;
-        switch (kind) {
-          case K_RE: stop = iterate<K_RE, MIXED>(L, c, o, band2, tol, hr); break;
-          case K_AO: stop = iterate<K_AO, MIXED>(L, c, o, band2, tol, hr); break;
-          case K_AE: stop = iterate<K_AE, MIXED>(L, c, o, band2, tol, hr); break;
-          default: stop = iterate<K_RO, MIXED>(L, c, o, band2, tol, hr); break;
-        }
+        const int stop = iterate<KIND, MIXED>(L, c, o, band2, tol, hr);
         if (stop >= 0) {
           store_state(T, slot, L.x, L.v);
           T.t[slot] = L.t;
@@ -550,6 +523,46 @@ __global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int
           slot = -1;
         }
       }
+    }
+  }
+}
+
+template <bool MIXED>
+__global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int refill) {
+  // the queue holds the used parts of the segments one after the other,
+  // each sorted hardest first and holding one branch (every entry kernel
+  // fills segment q with one (cloak, branch) pair); a wave integrates one
+  // segment at a time and moves on to the next one that still has rays
+  const SegMap sm = seg_map(T);
+  const double band2 = (c.a + o.band) * (c.a + o.band);
+  const double tol = 1e-13 * c.b;
+  unsigned int drained = 0;  // bit q: this wave found segment q's queue exhausted
+  int nused = 0;
+#pragma unroll
+  for (int q = 0; q < NSEG; ++q) {
+    if (sm.off[q + 1] == sm.off[q]) drained |= 1u << q;
+    else ++nused;
+  }
+  if (nused == 0) return;
+  // start on the (wave mod nused)-th used segment
+  const unsigned int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int seg = 0;
+  {
+    int k = (int)(wave % (unsigned int)nused);
+    for (int q = 0; q < NSEG; ++q)
+      if (!(drained >> q & 1u)) {
+        if (k == 0) { seg = q; break; }
+        --k;
+      }
+  }
+  while (drained != (1u << NSEG) - 1u) {
+    while (drained >> seg & 1u) seg = (seg + 1) % NSEG;
+    const int kind = __builtin_amdgcn_readfirstlane(T.kind[(long long)seg * T.cap]);
+    switch (kind) {
+      case K_RE: run_segment<K_RE, MIXED>(c, o, T, sm, seg, band2, tol, refill, drained); break;
+      case K_AO: run_segment<K_AO, MIXED>(c, o, T, sm, seg, band2, tol, refill, drained); break;
+      case K_AE: run_segment<K_AE, MIXED>(c, o, T, sm, seg, band2, tol, refill, drained); break;
+      default: run_segment<K_RO, MIXED>(c, o, T, sm, seg, band2, tol, refill, drained); break;
     }
   }
 }

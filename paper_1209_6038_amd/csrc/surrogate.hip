@@ -32,6 +32,8 @@
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace sg {
@@ -50,8 +52,9 @@ constexpr long long OFF_B4 = OFF_W4 + HID * HID;
 constexpr long long OFF_W5 = OFF_B4 + HID;
 constexpr long long OFF_B5 = OFF_W5 + HID * NOUT;
 constexpr long long NPARAM = OFF_B5 + NOUT;  // 200,453
-// BF16 copies of W2, W3, W4, each transposed to [out][in] so that the 8
-// consecutive inputs an MFMA lane needs for one output are one 16-byte load
+// BF16 copies of W2, W3, W4: transposed [out][in] (forward: the 8
+// consecutive inputs an MFMA lane needs for one output are one 16-byte
+// load) and row-major [in][out] (backward through the layer); NBF per copy
 constexpr long long NBF = 3LL * HID * HID;
 // scaling block: in_off[6], in_scale[6], out_mean[5], out_std[5], then the loss
 constexpr int S_INOFF = 0, S_INSCALE = 6, S_OMEAN = 12, S_OSTD = 17, S_LOSS = 22, NSCAL = 24;
@@ -78,9 +81,14 @@ int fail(int code, const char *fmt, ...) {
   return code;
 }
 
-__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU and its derivative with the hardware reciprocal (about 1 ulp): the
+// activations are rounded to BF16 or feed FP32 layers whose inputs carry
+// far more error than that, and an IEEE division would cost ~10
+// instructions per activation. Training and inference share these.
+__device__ __forceinline__ float sigmoid_f(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_f(float z) { return z * sigmoid_f(z); }
 __device__ __forceinline__ float dsilu_f(float z) {
-  float s = 1.0f / (1.0f + __expf(-z));
+  const float s = sigmoid_f(z);
   return s * (1.0f + z * (1.0f - s));
 }
 
@@ -115,34 +123,60 @@ struct Gemm {
   long long ldca;
 };
 
+// Stage a 64 x 32 operand tile (rows r0.., k k0..) into LDS as T[row][k].
+// P(row, k) = P[row * s_row + k * s_k]; rows < nrow and k < kend valid,
+// zeros elsewhere. One 8-element vector per thread: along k when s_k == 1,
+// along rows (stored transposed) when s_row == 1, else element-wise.
+__device__ __forceinline__ void stage_tile(bf16 (*T)[40], const bf16 *__restrict__ P, long long s_row, long long s_k,
+                                           int r0, int nrow, int k0, int kend, int tid) {
+  if (s_k == 1) {
+    const int r = tid >> 2, kk = (tid & 3) * 8;
+    const int gr = r0 + r, gk = k0 + kk;
+    const bf16 *src = P + gr * s_row + gk;
+    if (gr < nrow && gk + 8 <= kend && ((s_row & 7) == 0)) {
+      *reinterpret_cast<bf16x8 *>(&T[r][kk]) = *reinterpret_cast<const bf16x8 *>(src);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) T[r][kk + e] = (gr < nrow && gk + e < kend) ? src[e] : (bf16)0.0f;
+    }
+  } else if (s_row == 1) {
+    const int kk = tid >> 3, r = (tid & 7) * 8;
+    const int gr = r0 + r, gk = k0 + kk;
+    const bf16 *src = P + gk * s_k + gr;
+    if (gk < kend && gr + 8 <= nrow && ((s_k & 7) == 0)) {
+      const bf16x8 v = *reinterpret_cast<const bf16x8 *>(src);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) T[r + e][kk] = v[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) T[r + e][kk] = (gk < kend && gr + e < nrow) ? src[e] : (bf16)0.0f;
+    }
+  } else {
+    for (int e = tid; e < 64 * 32; e += 256) {
+      const int r = e >> 5, kk = e & 31;
+      const int gr = r0 + r, gk = k0 + kk;
+      T[r][kk] = (gr < nrow && gk < kend) ? P[gr * s_row + gk * s_k] : (bf16)0.0f;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256) k_gemm(Gemm g) {
-  __shared__ bf16 As[64][40];  // [row][k], padded rows
-  __shared__ bf16 Bs[64][40];  // [col][k]
+  __shared__ __attribute__((aligned(16))) bf16 As[64][40];  // [row][k], padded rows
+  __shared__ __attribute__((aligned(16))) bf16 Bs[64][40];  // [col][k]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
   const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;  // row tiles on x (up to 2^31 blocks)
   const int kbeg = blockIdx.z * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
-  const bool a_rowmajor = g.sa1 == 1, b_colmajor = g.sb0 == 1;
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = kbeg; k0 < kend; k0 += 32) {
-    // the element order follows each operand's unit stride (coalesced loads)
-    for (int e = tid; e < 64 * 32; e += 256) {
-      int r, kk;
-      if (a_rowmajor) { r = e >> 5; kk = e & 31; } else { kk = e >> 6; r = e & 63; }
-      const int gi = row0 + r, gk = k0 + kk;
-      As[r][kk] = (gi < g.M && gk < kend) ? g.A[gi * g.sa0 + gk * g.sa1] : (bf16)0.0f;
-    }
-    for (int e = tid; e < 64 * 32; e += 256) {
-      int cc, kk;
-      if (b_colmajor) { cc = e >> 5; kk = e & 31; } else { kk = e >> 6; cc = e & 63; }
-      const int gj = col0 + cc, gk = k0 + kk;
-      Bs[cc][kk] = (gj < g.N && gk < kend) ? g.B[gk * g.sb0 + gj * g.sb1] : (bf16)0.0f;
-    }
-    __syncthreads();
+    // A(i, k) = A[i*sa0 + k*sa1]; B staged as its transpose: B(k, j) = B[j*sb1 + k*sb0]
+    stage_tile(As, g.A, g.sa0, g.sa1, row0, g.M, k0, kend, tid);
+    stage_tile(Bs, g.B, g.sb1, g.sb0, col0, g.N, k0, kend, tid);
+  __syncthreads();
     // operand layout of v_mfma_f32_16x16x32_bf16: lane l holds
     // A[l%16][8*(l/16) + j] and B[8*(l/16) + j][l%16], j = 0..7
     bf16x8 af[2], bfr[2];
@@ -210,20 +244,42 @@ __device__ __forceinline__ void features(const float *__restrict__ x6, long long
 // a1 = bf16(silu z1). One block per row, thread j = hidden unit j.
 __global__ void __launch_bounds__(256) k_layer1(const float *__restrict__ x, long long ld, int n,
                                                 const float *__restrict__ P, const float *__restrict__ sc,
-                                                float *__restrict__ z1, bf16 *__restrict__ a1) {
+                                                float *__restrict__ z1, bf16 *__restrict__ a1,
+                                                float *__restrict__ xf) {
+  // features of a tile of 64 rows, computed once per row
+  __shared__ float xs[64][NIN];
   const int j = threadIdx.x;
   float w[NIN];
 #pragma unroll
   for (int k = 0; k < NIN; ++k) w[k] = P[OFF_W1 + k * HID + j];
   const float b = P[OFF_B1 + j];
-  for (int row = blockIdx.x; row < n; row += gridDim.x) {
-    float f[NIN];
-    features(x, ld, row, f);
-    float z = b;
+  for (int r0 = blockIdx.x * 64; r0 < n; r0 += gridDim.x * 64) {
+    if (j < 64) {
+      const int row = r0 + j;
+      float f[NIN] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (row < n) {
+        features(x, ld, row, f);
 #pragma unroll
-    for (int k = 0; k < NIN; ++k) z = fmaf((f[k] - sc[S_INOFF + k]) * sc[S_INSCALE + k], w[k], z);
-    if (z1) z1[(long long)row * HID + j] = z;
-    a1[(long long)row * HID + j] = (bf16)silu_f(z);
+        for (int k = 0; k < NIN; ++k) f[k] = (f[k] - sc[S_INOFF + k]) * sc[S_INSCALE + k];
+        if (xf) {
+#pragma unroll
+          for (int k = 0; k < NIN; ++k) xf[(long long)row * NIN + k] = f[k];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NIN; ++k) xs[j][k] = f[k];
+    }
+    __syncthreads();
+    const int rn = min(64, n - r0);
+    for (int r = 0; r < rn; ++r) {
+      float z = b;
+#pragma unroll
+      for (int k = 0; k < NIN; ++k) z = fmaf(xs[r][k], w[k], z);
+      const long long row = r0 + r;
+      if (z1) z1[row * HID + j] = z;
+      a1[row * HID + j] = (bf16)silu_f(z);
+    }
+    __syncthreads();
   }
 }
 
@@ -314,9 +370,12 @@ __global__ void __launch_bounds__(256) k_layer5_back(const float *__restrict__ d
   float w[NOUT], gw[NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f}, gb = 0.f;
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) w[o] = P[OFF_W5 + j * NOUT + o];
-  for (int row = blockIdx.x; row < n; row += gridDim.x) {
+  const int per = (n + gridDim.x - 1) / gridDim.x;
+  const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+#pragma unroll 4
+  for (int row = r0; row < r1; ++row) {
     const long long e = (long long)row * HID + j;
-    const float a = a4[e];
+    const float a = a4[e], zz = z4[e];
     float da = 0.f;
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
@@ -325,7 +384,7 @@ __global__ void __launch_bounds__(256) k_layer5_back(const float *__restrict__ d
       gw[o] = fmaf(a, d, gw[o]);
     }
     if (j < NOUT) gb += dy[(long long)row * NOUT + j];
-    const float g = da * dsilu_f(z4[e]);
+    const float g = da * dsilu_f(zz);
     dzf[e] = g;
     dzb[e] = (bf16)g;
   }
@@ -334,27 +393,46 @@ __global__ void __launch_bounds__(256) k_layer5_back(const float *__restrict__ d
   if (j < NOUT) atomicAdd(&G[OFF_B5 + j], gb);
 }
 
-// column sums of an (n x 256) FP32 matrix, accumulated into out[0..255]
+// column sums of an (n x 256) FP32 matrix, accumulated into out[0..255];
+// each block sums a contiguous run of rows, 8 loads in flight per thread
 __global__ void __launch_bounds__(256) k_colsum(const float *__restrict__ d, int n, float *__restrict__ out) {
   const int j = threadIdx.x;
-  float s = 0.f;
-  for (int row = blockIdx.x; row < n; row += gridDim.x) s += d[(long long)row * HID + j];
-  atomicAdd(&out[j], s);
+  const int per = (n + gridDim.x - 1) / gridDim.x;
+  const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int row = r0;
+  for (; row + 8 <= r1; row += 8)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += d[(long long)(row + u) * HID + j];
+  for (; row < r1; ++row) s[0] += d[(long long)row * HID + j];
+  atomicAdd(&out[j], ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
 }
 
-// backward of layer 1 (FP32): dW1 += xn^T dz1, db1 += sum dz1
-__global__ void __launch_bounds__(256) k_layer1_back(const float *__restrict__ x, long long ld, int n,
-                                                     const float *__restrict__ sc, const float *__restrict__ dz1,
-                                                     float *__restrict__ G) {
+// backward of layer 1 (FP32): dW1 += xn^T dz1, db1 += sum dz1, with the
+// standardized features xn saved by the forward; contiguous rows per block
+__global__ void __launch_bounds__(256) k_layer1_back(const float *__restrict__ xf, int n,
+                                                     const float *__restrict__ dz1, float *__restrict__ G) {
   const int j = threadIdx.x;
+  const int per = (n + gridDim.x - 1) / gridDim.x;
+  const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
   float gw[NIN] = {0, 0, 0, 0, 0, 0}, gb = 0.f;
-  for (int row = blockIdx.x; row < n; row += gridDim.x) {
+  int row = r0;
+  for (; row + 4 <= r1; row += 4) {
+    float d[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) d[u] = dz1[(long long)(row + u) * HID + j];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      gb += d[u];
+#pragma unroll
+      for (int k = 0; k < NIN; ++k) gw[k] = fmaf(xf[(long long)(row + u) * NIN + k], d[u], gw[k]);
+    }
+  }
+  for (; row < r1; ++row) {
     const float d = dz1[(long long)row * HID + j];
-    float f[NIN];
-    features(x, ld, row, f);
     gb += d;
 #pragma unroll
-    for (int k = 0; k < NIN; ++k) gw[k] = fmaf((f[k] - sc[S_INOFF + k]) * sc[S_INSCALE + k], d, gw[k]);
+    for (int k = 0; k < NIN; ++k) gw[k] = fmaf(xf[(long long)row * NIN + k], d, gw[k]);
   }
 #pragma unroll
   for (int k = 0; k < NIN; ++k) atomicAdd(&G[OFF_W1 + k * HID + j], gw[k]);
@@ -376,14 +454,16 @@ __device__ __forceinline__ bool is_bias(long long i) {
          (i >= OFF_B4 && i < OFF_W5) || i >= OFF_B5;
 }
 
-// index of FP32 parameter i in the transposed BF16 copy (-1: no copy)
-__device__ __forceinline__ long long bf16_index(long long i) {
+// index of FP32 parameter i in the transposed BF16 copy (-1: no copy);
+// its row-major copy sits at NBF + (layer offset + e)
+__device__ __forceinline__ long long bf16_index(long long i, long long &rowmajor) {
   long long l, e;
   if (i >= OFF_W2 && i < OFF_B2) { l = 0; e = i - OFF_W2; }
   else if (i >= OFF_W3 && i < OFF_B3) { l = 1; e = i - OFF_W3; }
   else if (i >= OFF_W4 && i < OFF_B4) { l = 2; e = i - OFF_W4; }
   else return -1;
   const long long in = e / HID, out = e - in * HID;
+  rowmajor = NBF + l * HID * HID + e;
   return l * HID * HID + out * HID + in;
 }
 
@@ -403,15 +483,23 @@ __global__ void k_adamw(float *__restrict__ P, const float *__restrict__ G, floa
   if (!is_bias(i)) p -= lr * wd * p;
   p -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
   P[i] = p;
-  const long long k = bf16_index(i);
-  if (k >= 0) Pb[k] = (bf16)p;
+  long long kr;
+  const long long k = bf16_index(i, kr);
+  if (k >= 0) {
+    Pb[k] = (bf16)p;
+    Pb[kr] = (bf16)p;
+  }
 }
 
 __global__ void k_refresh_bf16(const float *__restrict__ P, bf16 *__restrict__ Pb) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= NPARAM) return;
-  const long long k = bf16_index(i);
-  if (k >= 0) Pb[k] = (bf16)P[i];
+  long long kr;
+  const long long k = bf16_index(i, kr);
+  if (k >= 0) {
+    Pb[k] = (bf16)P[i];
+    Pb[kr] = (bf16)P[i];
+  }
 }
 
 // masked first and second moments of the 6 input features and 5 targets (FP64 sums)
@@ -627,43 +715,80 @@ __device__ __forceinline__ void gate_row(long long i, const float *__restrict__ 
   }
 }
 
-// gate of the standardized outputs y (n x 5) of the fused forward
-__global__ void __launch_bounds__(256) k_decode_gate(const float *__restrict__ x6, long long ld, int n,
-                                                     const float *__restrict__ y, const float *__restrict__ sc,
-                                                     const unsigned char *__restrict__ map, GateP gp,
-                                                     float *__restrict__ y5, unsigned char *__restrict__ fallback,
-                                                     int *__restrict__ status) {
+// First half of the gate, on the inputs alone: entries whose trust-map cell
+// is trusted (and that are valid side entries) are appended to idx for the
+// network; the others go to the exact transit (fallback = 1).
+__global__ void __launch_bounds__(256) k_pregate(const float *__restrict__ x6, long long ld, int n,
+                                                 const unsigned char *__restrict__ map, GateP gp,
+                                                 unsigned char *__restrict__ fallback, int *__restrict__ idx,
+                                                 unsigned int *__restrict__ count) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) gate_row(i, x6, ld, y + i * NOUT, sc, map, gp, y5, fallback, status);
+  bool take = false;
+  if (i < n) {
+    const float phi = x6[i], z = x6[ld + i], al = x6[2 * ld + i], be = x6[3 * ld + i];
+    const float pol = x6[4 * ld + i], axis = x6[5 * ld + i];
+    take = entry_ok(phi, z, al, be, pol, axis) && z >= gp.z0 && z <= gp.z1 &&
+           map[cell_of(kind_of(pol, axis), al, be)] != 0;
+    fallback[i] = take ? 0 : 1;
+  }
+  const unsigned long long m = __ballot(take);
+  unsigned int base = 0;
+  if (m != 0ull) {
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    if ((int)__lane_id() == leader) base = atomicAdd(count, (unsigned int)__popcll(m));
+    base = __shfl(base, leader);
+  }
+  const unsigned int lane = __lane_id();
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  if (take) idx[base + (unsigned int)__popcll(m & below)] = (int)i;
+}
+
+// second half of the gate on the network's outputs of the compacted entries
+__global__ void __launch_bounds__(256) k_gate_idx(const float *__restrict__ x6, long long ld,
+                                                  const int *__restrict__ idx, const unsigned int *count,
+                                                  const float *__restrict__ y, const float *__restrict__ sc,
+                                                  const unsigned char *__restrict__ map, GateP gp,
+                                                  float *__restrict__ y5, unsigned char *__restrict__ fallback,
+                                                  int *__restrict__ status) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < (long long)*count) gate_row(idx[p], x6, ld, y + p * NOUT, sc, map, gp, y5, fallback, status);
 }
 
 // ---------------------------------------------------------------------------
 // Fused inference: the whole network for FR rows per block, activations
-// resident in LDS (BF16, FR x 256, rows padded to 264 so that the 16 rows an
-// MFMA operand read touches fall in distinct banks). Wave w owns output
-// columns 64w..64w+63 of every hidden layer: 8 x 4 MFMA 16x16x32 tiles
-// (128 FP32 accumulators per lane); its B operands (transposed BF16 weights,
-// 8 consecutive inputs per lane) stream from L2 with one 16-byte load per
-// tile, its A operands come from the LDS tile. Layer 1 (FP32) fills the LDS
-// tile; layer 5 (FP32) reduces the layer-4 accumulators directly, across
-// lanes and then across the 4 waves through LDS, and the block writes the
-// standardized outputs (n x 5).
+// resident in LDS (BF16, FR x 256, rows padded to 264 so that the 16 rows
+// an operand read touches fall in distinct banks). Each hidden layer is
+// computed transposed, out^T = W^T act^T, so that an MFMA 16x16x32 tile's
+// A operand is 8 consecutive inputs of one output unit (one 16-byte load of
+// the transposed BF16 weights, streamed from L2), its B operand 8
+// consecutive inputs of one row (one 16-byte LDS read), and each lane's 4
+// results are 4 consecutive output units of one row (one 8-byte LDS store).
+// Wave w owns output units 64w..64w+63: 4 unit tiles x 8 row tiles, 128 FP32
+// accumulators per lane. Layer 1 (FP32) fills the tile; layer 5 (FP32)
+// reduces the layer-4 accumulators over each lane's 16 units, across the 4
+// lane groups of a wave, then across the 4 waves through LDS, and the block
+// writes the standardized outputs (n x 5).
 // ---------------------------------------------------------------------------
 constexpr int FR = 128, ALD = HID + 8;
 
+// With idx != NULL, row r of the network is entry idx[r] for r < *count
+// (a compacted subset); otherwise row r is entry r, r < n.
 __global__ void __launch_bounds__(256, 2) k_mlp_fused(const float *__restrict__ x6, long long ld, int n,
+                                                      const int *__restrict__ idx, const unsigned int *count,
                                                       const float *__restrict__ P, const bf16 *__restrict__ Wt,
                                                       const float *__restrict__ sc, float *__restrict__ yout) {
   __shared__ __attribute__((aligned(16))) bf16 act[FR * ALD];
   __shared__ float xn[FR * NIN];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const long long row0 = (long long)blockIdx.x * FR;
+  if (idx) n = (int)*count;  // block-uniform
+  if (row0 >= n) return;
   // standardized input features of the tile (rows past n read as zeros)
   if (tid < FR) {
     const long long i = row0 + tid;
     float f[NIN] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (i < n) {
-      features(x6, ld, i, f);
+      features(x6, ld, idx ? (long long)idx[i] : i, f);
 #pragma unroll
       for (int k = 0; k < NIN; ++k) f[k] = (f[k] - sc[S_INOFF + k]) * sc[S_INSCALE + k];
     }
@@ -671,95 +796,117 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fused(const float *__restrict__ 
     for (int k = 0; k < NIN; ++k) xn[tid * NIN + k] = f[k];
   }
   __syncthreads();
-  {  // layer 1 (FP32): thread = hidden unit
-    float w1[NIN];
+  {  // layer 1 (FP32): thread = pair of hidden units x half of the rows
+    const int u = 2 * (tid & 127), rb = (tid >> 7) * (FR / 2);
+    float w0[NIN], w1[NIN];
 #pragma unroll
-    for (int k = 0; k < NIN; ++k) w1[k] = P[OFF_W1 + k * HID + tid];
-    const float b1 = P[OFF_B1 + tid];
-    for (int r = 0; r < FR; ++r) {
-      float z = b1;
+    for (int k = 0; k < NIN; ++k) {
+      w0[k] = P[OFF_W1 + k * HID + u];
+      w1[k] = P[OFF_W1 + k * HID + u + 1];
+    }
+    const float b0 = P[OFF_B1 + u], b1 = P[OFF_B1 + u + 1];
+    for (int r = rb; r < rb + FR / 2; ++r) {
+      float z0 = b0, z1 = b1;
 #pragma unroll
-      for (int k = 0; k < NIN; ++k) z = fmaf(xn[r * NIN + k], w1[k], z);
-      act[r * ALD + tid] = (bf16)silu_f(z);
+      for (int k = 0; k < NIN; ++k) {
+        z0 = fmaf(xn[r * NIN + k], w0[k], z0);
+        z1 = fmaf(xn[r * NIN + k], w1[k], z1);
+      }
+      bf16x2 pr;
+      pr[0] = (bf16)silu_f(z0);
+      pr[1] = (bf16)silu_f(z1);
+      *reinterpret_cast<bf16x2 *>(&act[r * ALD + u]) = pr;
     }
   }
   __syncthreads();
-  const int q = lane >> 4, c16 = lane & 15, cb = 64 * w;
+  const int q = lane >> 4, c16 = lane & 15, ub = 64 * w;
   const long long offb[3] = {OFF_B2, OFF_B3, OFF_B4};
-  f32x4 acc[8][4];
+  f32x4 acc[4][8];  // [unit tile][row tile]
   for (int l = 0; l < 3; ++l) {
     const bf16 *W = Wt + (long long)l * HID * HID;
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
+    for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+      for (int tj = 0; tj < 8; ++tj) acc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
     for (int k0 = 0; k0 < HID; k0 += 32) {
-      bf16x8 bop[4];
+      bf16x8 aop[4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        bop[c] = *reinterpret_cast<const bf16x8 *>(W + (cb + 16 * c + c16) * HID + k0 + 8 * q);
+      for (int ti = 0; ti < 4; ++ti)
+        aop[ti] = *reinterpret_cast<const bf16x8 *>(W + (ub + 16 * ti + c16) * HID + k0 + 8 * q);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const bf16x8 aop = *reinterpret_cast<const bf16x8 *>(&act[(16 * r + c16) * ALD + k0 + 8 * q]);
+      for (int tj = 0; tj < 8; ++tj) {
+        const bf16x8 bop = *reinterpret_cast<const bf16x8 *>(&act[(16 * tj + c16) * ALD + k0 + 8 * q]);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop[c], acc[r][c], 0, 0, 0);
+        for (int ti = 0; ti < 4; ++ti)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop[ti], bop, acc[ti][tj], 0, 0, 0);
       }
     }
     __syncthreads();  // every wave has read the layer's input tile
-    float bias[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) bias[c] = P[offb[l] + cb + 16 * c + c16];
     if (l < 2) {
 #pragma unroll
-      for (int r = 0; r < 8; ++r)
+      for (int ti = 0; ti < 4; ++ti) {
+        const int u0 = ub + 16 * ti + 4 * q;  // this lane's 4 consecutive units
+        float bias[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int r = 0; r < 4; ++r) bias[r] = P[offb[l] + u0 + r];
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            act[(16 * r + 4 * q + i) * ALD + cb + 16 * c + c16] = (bf16)silu_f(acc[r][c][i] + bias[c]);
+        for (int tj = 0; tj < 8; ++tj) {
+          bf16x4 pk;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) pk[r] = (bf16)silu_f(acc[ti][tj][r] + bias[r]);
+          *reinterpret_cast<bf16x4 *>(&act[(16 * tj + c16) * ALD + u0]) = pk;
+        }
+      }
       __syncthreads();
     } else {
-      // layer 5 (FP32) on a4 = silu(z4): per-lane partial sums over this
-      // lane's 4 columns, reduced over the 16 lanes of a column group, then
-      // over the 4 waves in LDS (the activation tile is free now)
-      float w5[4][NOUT];
+      // layer 5 (FP32) on a4 = silu(z4): partial sums over this lane's 16
+      // units for each of its 8 rows, then over the 4 lane groups
+      float s5[8][NOUT];
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+      for (int tj = 0; tj < 8; ++tj)
 #pragma unroll
-        for (int o = 0; o < NOUT; ++o) w5[c][o] = P[OFF_W5 + (cb + 16 * c + c16) * NOUT + o];
+        for (int o = 0; o < NOUT; ++o) s5[tj][o] = 0.0f;
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti) {
+        const int u0 = ub + 16 * ti + 4 * q;
+        float bias[4], w5[4][NOUT];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          bias[r] = P[offb[l] + u0 + r];
+#pragma unroll
+          for (int o = 0; o < NOUT; ++o) w5[r][o] = P[OFF_W5 + (u0 + r) * NOUT + o];
+        }
+#pragma unroll
+        for (int tj = 0; tj < 8; ++tj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float a4 = silu_f(acc[ti][tj][r] + bias[r]);
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) s5[tj][o] = fmaf(a4, w5[r][o], s5[tj][o]);
+          }
+      }
       float *red = reinterpret_cast<float *>(act);  // [4 waves][FR][NOUT]
 #pragma unroll
-      for (int r = 0; r < 8; ++r)
+      for (int tj = 0; tj < 8; ++tj) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          float s5[NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const float a4 = silu_f(acc[r][c][i] + bias[c]);
-#pragma unroll
-            for (int o = 0; o < NOUT; ++o) s5[o] = fmaf(a4, w5[c][o], s5[o]);
-          }
-#pragma unroll
-          for (int off = 1; off < 16; off <<= 1)
-#pragma unroll
-            for (int o = 0; o < NOUT; ++o) s5[o] += __shfl_xor(s5[o], off);
-          if (c16 == 0) {
-#pragma unroll
-            for (int o = 0; o < NOUT; ++o) red[(w * FR + 16 * r + 4 * q + i) * NOUT + o] = s5[o];
-          }
+        for (int o = 0; o < NOUT; ++o) {
+          s5[tj][o] += __shfl_xor(s5[tj][o], 16);
+          s5[tj][o] += __shfl_xor(s5[tj][o], 32);
         }
+        if (q == 0) {
+#pragma unroll
+          for (int o = 0; o < NOUT; ++o) red[(w * FR + 16 * tj + c16) * NOUT + o] = s5[tj][o];
+        }
+      }
       __syncthreads();
       if (tid < FR) {
         const long long i = row0 + tid;
         if (i < n) {
-          float y[NOUT];
 #pragma unroll
           for (int o = 0; o < NOUT; ++o)
-            y[o] = P[OFF_B5 + o] + red[(0 * FR + tid) * NOUT + o] + red[(1 * FR + tid) * NOUT + o] +
-                   red[(2 * FR + tid) * NOUT + o] + red[(3 * FR + tid) * NOUT + o];
-#pragma unroll
-          for (int o = 0; o < NOUT; ++o) yout[i * NOUT + o] = y[o];
+            yout[i * NOUT + o] = P[OFF_B5 + o] + ((red[(0 * FR + tid) * NOUT + o] + red[(1 * FR + tid) * NOUT + o]) +
+                                                  (red[(2 * FR + tid) * NOUT + o] + red[(3 * FR + tid) * NOUT + o]));
         }
       }
     }
@@ -846,9 +993,13 @@ struct rt_model_s {
   float *dy = nullptr;                                 // [cap][5]
   float *dzf = nullptr;                                // [cap][256]
   bf16 *dzb[2] = {nullptr, nullptr};
-  // standardized outputs of the fused inference kernel
+  float *xf = nullptr;                                 // standardized input features [cap][6]
+  // standardized outputs of the fused inference kernel, and the compacted
+  // entry list of the gated inference
   long long ycap = 0;
   float *yinf = nullptr;
+  int *idx = nullptr;
+  unsigned int *count = nullptr;
 };
 
 namespace {
@@ -864,8 +1015,8 @@ int reserve_acts(rt_model mo, long long n) {
   const long long cap = std::max(n, 4096LL);
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t zb = al(sizeof(float) * cap * HID), ab = al(sizeof(bf16) * cap * HID);
-  const size_t yb = al(sizeof(float) * cap * NOUT);
-  const size_t bytes = 4 * zb + 3 * ab + zb + 2 * yb + zb + 2 * ab;
+  const size_t yb = al(sizeof(float) * cap * NOUT), fb = al(sizeof(float) * cap * NIN);
+  const size_t bytes = 4 * zb + 3 * ab + zb + 2 * yb + zb + 2 * ab + fb;
   void *p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
@@ -881,6 +1032,7 @@ int reserve_acts(rt_model mo, long long n) {
   mo->dzf = (float *)(c + off); off += zb;
   mo->dzb[0] = (bf16 *)(c + off); off += ab;
   mo->dzb[1] = (bf16 *)(c + off); off += ab;
+  mo->xf = (float *)(c + off); off += fb;
   mo->act = p;
   mo->cap = cap;
   return RT_OK;
@@ -895,18 +1047,21 @@ int reserve_yinf(rt_model mo, long long n) {
     mo->ycap = 0;
   }
   const long long cap = std::max(n, 4096LL);
-  if (hipMalloc((void **)&mo->yinf, sizeof(float) * cap * NOUT) != hipSuccess) {
+  const size_t yb = (sizeof(float) * cap * NOUT + 255) & ~(size_t)255;
+  if (hipMalloc((void **)&mo->yinf, yb + sizeof(int) * cap + 256) != hipSuccess) {
     (void)hipGetLastError();
     return fail(RT_E_NOMEM, "hipMalloc for %lld inference outputs failed", cap);
   }
+  mo->idx = (int *)((char *)mo->yinf + yb);
+  mo->count = (unsigned int *)((char *)mo->idx + ((sizeof(int) * cap + 255) & ~(size_t)255));
   mo->ycap = cap;
   return RT_OK;
 }
 
 // standardized outputs of n rows into mo->yinf (fused kernel)
 void infer_outputs(rt_model mo, const float *x, long long ld, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_fused, dim3(gblocks(n, FR)), dim3(256), 0, s, x, ld, n, mo->P, mo->Pb, mo->scal,
-                     mo->yinf);
+  hipLaunchKernelGGL(k_mlp_fused, dim3(gblocks(n, FR)), dim3(256), 0, s, x, ld, n, nullptr, nullptr, mo->P, mo->Pb,
+                     mo->scal, mo->yinf);
 }
 
 void gemm(hipStream_t s, const bf16 *A, long long sa0, long long sa1, const bf16 *B, long long sb0, long long sb1,
@@ -919,15 +1074,15 @@ void gemm(hipStream_t s, const bf16 *A, long long sa0, long long sa1, const bf16
   hipLaunchKernelGGL(k_gemm, dim3(gblocks(M, 64), gblocks(N, 64), splits), dim3(256), 0, s, g);
 }
 
-// transposed BF16 weights [out][in] of W2 (l = 0), W3 (1), W4 (2)
+// BF16 weights of W2 (l = 0), W3 (1), W4 (2): transposed [out][in] and row-major [in][out]
 const bf16 *wb(rt_model mo, int l) { return mo->Pb + (long long)l * HID * HID; }
+const bf16 *wr(rt_model mo, int l) { return mo->Pb + NBF + (long long)l * HID * HID; }
 
 // layered forward of n rows for training: keeps every activation and the
 // pre-activations for backward (inference uses the fused kernel)
 void forward(rt_model mo, const float *x, long long ld, int n, bool train, hipStream_t s) {
-  const unsigned int rows_grid = (unsigned int)std::min(n, 8192);
-  hipLaunchKernelGGL(k_layer1, dim3(rows_grid), dim3(HID), 0, s, x, ld, n, mo->P, mo->scal,
-                     train ? mo->z[0] : nullptr, mo->a[0]);
+  hipLaunchKernelGGL(k_layer1, dim3(std::min(gblocks(n, 64), 4096u)), dim3(HID), 0, s, x, ld, n, mo->P, mo->scal,
+                     train ? mo->z[0] : nullptr, mo->a[0], train ? mo->xf : nullptr);
   const long long offb[3] = {OFF_B2, OFF_B3, OFF_B4};
   for (int l = 1; l <= 3; ++l) {
     const bool last = l == 3;
@@ -943,7 +1098,10 @@ int split_for(int n) { return std::min(64, std::max(1, n / 512)); }
 void backward(rt_model mo, const float *x, const float *t, long long ld, const float *wrow, int n, float huber,
               hipStream_t s) {
   float *loss = mo->scal + S_LOSS;
-  const unsigned int rows_grid = (unsigned int)std::min(n, 2048);
+  // reductions over rows: each block sums a contiguous run of >= 32 rows
+  // (loads in flight per thread), and at most 256 partial sums per
+  // parameter meet in atomics
+  const unsigned int rows_grid = (unsigned int)std::min(256, std::max(1, n / 32));
   hipLaunchKernelGGL(k_fill, dim3(gblocks(NPARAM, 256)), dim3(256), 0, s, mo->G, NPARAM, 0.0f);
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, loss, 1LL, 0.0f);
   hipLaunchKernelGGL(k_loss, dim3(gblocks((long long)n * NOUT, 256)), dim3(256), 0, s, mo->y, t, ld, wrow, n,
@@ -958,12 +1116,12 @@ void backward(rt_model mo, const float *x, const float *t, long long ld, const f
     gemm(s, mo->a[l - 1], 1, HID, mo->dzb[cur], HID, 1, HID, HID, n, EPI_ATOMIC, nullptr, nullptr, 0,
          mo->G + offw[l - 1], HID, nullptr, 0, nullptr, 0, split_for(n));
     hipLaunchKernelGGL(k_colsum, dim3(rows_grid), dim3(HID), 0, s, mo->dzf, n, mo->G + offb[l - 1]);
-    // dz_{l-1} = (dz W_{l+1}^T) * silu'(z_{l-1}); B(k, j) = W(in=j, out=k) = Wt[k][j]
-    gemm(s, mo->dzb[cur], HID, 1, wb(mo, l - 1), HID, 1, n, HID, HID, EPI_DSILU, nullptr, mo->z[l - 1], HID,
+    // dz_{l-1} = (dz W_{l+1}^T) * silu'(z_{l-1}); B(k, j) = W(in=j, out=k), row-major copy
+    gemm(s, mo->dzb[cur], HID, 1, wr(mo, l - 1), 1, HID, n, HID, HID, EPI_DSILU, nullptr, mo->z[l - 1], HID,
          mo->dzf, HID, mo->dzb[cur ^ 1], HID, nullptr, 0);
     cur ^= 1;
   }
-  hipLaunchKernelGGL(k_layer1_back, dim3(rows_grid), dim3(HID), 0, s, x, ld, n, mo->scal, mo->dzf, mo->G);
+  hipLaunchKernelGGL(k_layer1_back, dim3(rows_grid), dim3(HID), 0, s, mo->xf, n, mo->dzf, mo->G);
 }
 
 int check_model(rt_model mo) {
@@ -1015,7 +1173,7 @@ int rt_surrogate_create(uint64_t seed, rt_model *out) {
   rt_model mo = new (std::nothrow) rt_model_s;
   if (!mo) return fail(RT_E_NOMEM, "host allocation failed");
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t pb = al(sizeof(float) * NPARAM), bb = al(sizeof(bf16) * NBF), sb = al(sizeof(float) * NSCAL),
+  const size_t pb = al(sizeof(float) * NPARAM), bb = al(sizeof(bf16) * 2 * NBF), sb = al(sizeof(float) * NSCAL),
                mb = al(NCELLS), cb = al(sizeof(unsigned int) * 2 * NCELLS), ob = al(sizeof(double) * NMOM);
   const size_t bytes = 4 * pb + bb + sb + mb + cb + ob;
   if (hipMalloc(&mo->base, bytes) != hipSuccess) {
@@ -1319,9 +1477,15 @@ int rt_surrogate_infer(rt_model mo, const rt_cloak *cloaks, int32_t n_cloaks, co
   gp.cap_margin = (float)mo->gate.cap_margin;
   e = reserve_yinf(mo, n);
   if (e) return e;
-  infer_outputs(mo, x6, ld, (int)n, s);
-  hipLaunchKernelGGL(k_decode_gate, dim3(gblocks(n, 256)), dim3(256), 0, s, x6, (long long)ld, (int)n, mo->yinf,
-                     mo->scal, mo->map, gp, y5, fallback, status);
+  // trusted entries only go through the network (compacted), then the
+  // output half of the gate
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, mo->count, 1LL);
+  hipLaunchKernelGGL(k_pregate, dim3(gblocks(n, 256)), dim3(256), 0, s, x6, (long long)ld, (int)n, mo->map, gp,
+                     fallback, mo->idx, mo->count);
+  hipLaunchKernelGGL(k_mlp_fused, dim3(gblocks(n, FR)), dim3(256), 0, s, x6, (long long)ld, (int)n, mo->idx,
+                     mo->count, mo->P, mo->Pb, mo->scal, mo->yinf);
+  hipLaunchKernelGGL(k_gate_idx, dim3(gblocks(n, 256)), dim3(256), 0, s, x6, (long long)ld, mo->idx, mo->count,
+                     mo->yinf, mo->scal, mo->map, gp, y5, fallback, status);
   e = launch_err("surrogate launch");
   if (e) return e;
   // the exact integrator traces the rejected rays (one persistent launch)
