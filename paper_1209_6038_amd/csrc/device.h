@@ -547,6 +547,7 @@ __device__ __forceinline__ double leave_radius(const double p[3], const double d
 struct CamP {
   double eye[3], F[3], R[3], U[3];
   double tan_half, aspect;
+  double inv_w, inv_h;  // 1/w, 1/h when w, h are powers of two (exact), else 0
   int w, h, spp, m;
   unsigned long long seed;
 };
@@ -563,7 +564,8 @@ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long seed
 
 __device__ __forceinline__ void camera_ray(const CamP& cam, int cam_index, long long pix, int smp,
                                            double d[3]) {
-  long long row = pix / cam.w, col = pix - row * cam.w;
+  // pix < w h <= 2^30: 32-bit index arithmetic
+  const unsigned int p32 = (unsigned int)pix, row = p32 / (unsigned int)cam.w, col = p32 - row * (unsigned int)cam.w;
   double ox = 0.5, oy = 0.5;
   if (cam.spp > 1) {
     unsigned long long key = ((unsigned long long)cam_index << 40) ^
@@ -573,8 +575,11 @@ __device__ __forceinline__ void camera_ray(const CamP& cam, int cam_index, long 
     ox = ((double)(smp % cam.m) + x1) / cam.m;
     oy = ((double)(smp / cam.m) + x2) / cam.m;
   }
-  double u = ((col + ox) / cam.w * 2.0 - 1.0) * cam.tan_half * cam.aspect;
-  double v = (1.0 - (row + oy) / cam.h * 2.0) * cam.tan_half;
+  // a power-of-two size divides exactly as a multiplication by its inverse
+  const double fx = cam.inv_w > 0.0 ? ((double)col + ox) * cam.inv_w : ((double)col + ox) / cam.w;
+  const double fy = cam.inv_h > 0.0 ? ((double)row + oy) * cam.inv_h : ((double)row + oy) / cam.h;
+  double u = (fx * 2.0 - 1.0) * cam.tan_half * cam.aspect;
+  double v = (1.0 - fy * 2.0) * cam.tan_half;
   double dx = cam.F[0] + u * cam.R[0] + v * cam.U[0];
   double dy = cam.F[1] + u * cam.R[1] + v * cam.U[1];
   double dz = cam.F[2] + u * cam.R[2] + v * cam.U[2];
@@ -584,21 +589,26 @@ __device__ __forceinline__ void camera_ray(const CamP& cam, int cam_index, long 
 
 struct RoomP {
   double lo[3], hi[3], tile, inv_tile;
+  int tile_pow2, pad;  // tile is a power of two: floor(u / tile) == floor(u * inv_tile) exactly
 };
 
 // face*2 + parity of the room point hit by o + s d (s >= 0) from inside
 __device__ __forceinline__ int room_code(const RoomP& rm, const double o[3], const double d[3],
                                          double& s_hit) {
-  double best = __builtin_inf();
+  // nearest wall: compare the distances (plane - o)/d as fractions with
+  // positive denominators (no division), then divide once for the winner
+  double bn = 1.0, bd = 0.0;  // best = bn / bd, +inf to start
   int face = -1;
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
     if (d[ax] != 0.0) {
-      double plane = d[ax] > 0.0 ? rm.hi[ax] : rm.lo[ax];
-      double s = (plane - o[ax]) / d[ax];
-      if (s < best) { best = s; face = 2 * ax + (d[ax] > 0.0 ? 1 : 0); }
+      const double plane = d[ax] > 0.0 ? rm.hi[ax] : rm.lo[ax];
+      const double num = d[ax] > 0.0 ? plane - o[ax] : o[ax] - plane;
+      const double den = fabs(d[ax]);
+      if (num * bd < bn * den) { bn = num; bd = den; face = 2 * ax + (d[ax] > 0.0 ? 1 : 0); }
     }
   }
+  double best = face >= 0 ? bn / bd : 0.0;
   if (face < 0) { s_hit = 0.0; return 12; }
   if (best < 0.0) best = 0.0;
   s_hit = best;
@@ -607,7 +617,9 @@ __device__ __forceinline__ int room_code(const RoomP& rm, const double o[3], con
   int va = ax == 2 ? 1 : 2;
   double pu = fma(best, d[ua], o[ua]);
   double pv = fma(best, d[va], o[va]);
-  long long par = ((long long)floor(pu / rm.tile) + (long long)floor(pv / rm.tile)) & 1;
+  const double fu = rm.tile_pow2 ? floor(pu * rm.inv_tile) : floor(pu / rm.tile);
+  const double fv = rm.tile_pow2 ? floor(pv * rm.inv_tile) : floor(pv / rm.tile);
+  long long par = ((long long)fu + (long long)fv) & 1;
   return face * 2 + (int)par;
 }
 

@@ -45,17 +45,26 @@ constexpr int NSEG = 4;
 
 // counters in device memory
 enum {
-  C_N = 0,        // C_N + s: slots used in segment s
-  C_FETCH = 4,    // C_FETCH + s: integrator work counter of segment s
-  C_HIST = 8,     // NBIN bins: slots per (segment, difficulty) key
-  C_OFF = 72,     // NBIN bins: scatter offsets of the keys
-  C_COUNT = 136
+  // the per-segment counters sit on separate 128-byte lines: the atomics of
+  // different segments then go to different L2 channels instead of
+  // serializing on one line
+  C_LINE = 32,
+  C_NBASE = 0,               // C_N(s): slots used in segment s
+  C_FBASE = NSEG * C_LINE,   // C_FETCH(s): integrator work counter of segment s
+  C_HBASE = 2 * NSEG * C_LINE,       // C_HIST(bin): slots per (segment, difficulty) key
+  C_OBASE = C_HBASE + 64 * C_LINE,   // C_OFF(bin): scatter offset of the key
+  C_COUNT = C_OBASE + 64 * C_LINE
 };
 constexpr int MAX_BOUNCES = 64;
 constexpr unsigned int FETCH_CHUNK = 64;  // rays claimed per wave per atomic
 constexpr int LONG_RAY_ATTEMPTS = 64;      // see the issue priority in k_transit
 constexpr int NBUCKET = 16;               // difficulty buckets
 constexpr int NBIN = NBUCKET * NSEG;
+static_assert(NBIN <= 64, "counter layout holds 64 bins");
+__host__ __device__ constexpr int C_N(int s) { return C_NBASE + s * C_LINE; }
+__host__ __device__ constexpr int C_FETCH(int s) { return C_FBASE + s * C_LINE; }
+__host__ __device__ constexpr int C_HIST(int b) { return C_HBASE + b * C_LINE; }
+__host__ __device__ constexpr int C_OFF(int b) { return C_OBASE + b * C_LINE; }
 
 struct Table {
   double *px, *py, *pz, *vx, *vy, *vz;
@@ -88,16 +97,24 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
   return lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
 }
 
-// wave-aggregated append: returns this lane's index (valid where `want`)
-__device__ __forceinline__ unsigned int wave_append(unsigned int *counter, bool want) {
-  unsigned long long m = __ballot(want);
-  unsigned int base = 0;
-  if (m != 0ull) {
-    int leader = __ffsll((unsigned long long)m) - 1;
-    if ((int)__lane_id() == leader) base = atomicAdd(counter, (unsigned int)__popcll(m));
-    base = __shfl(base, leader);
+// Block-aggregated append: this thread's index in the counter's range
+// (valid where `want`), with one global atomic per block instead of one per
+// wave. Every thread of the block must call it (it synchronizes); `sh` is
+// block-shared scratch of at least 2 * (blockDim.x / 64) + 1 words.
+__device__ __forceinline__ unsigned int block_append(unsigned int *counter, bool want, unsigned int *sh) {
+  const unsigned long long m = __ballot(want);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (__lane_id() == 0) sh[w] = (unsigned int)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int tot = 0;
+    for (int k = 0; k < nw; ++k) { sh[nw + k] = tot; tot += sh[k]; }
+    sh[2 * nw] = tot ? atomicAdd(counter, tot) : 0u;
   }
-  return base + (unsigned int)__popcll(m & lanemask_lt());
+  __syncthreads();
+  const unsigned int idx = sh[2 * nw] + sh[nw + w] + (unsigned int)__popcll(m & lanemask_lt());
+  __syncthreads();  // scratch free for the next call
+  return idx;
 }
 
 __device__ __forceinline__ bool finite6(const double x[3], const double v[3]) {
@@ -115,7 +132,7 @@ __device__ __forceinline__ SegMap seg_map(const Table &T) {
   SegMap m;
   m.off[0] = 0;
 #pragma unroll
-  for (int q = 0; q < NSEG; ++q) m.off[q + 1] = m.off[q] + T.ctr[C_N + q];
+  for (int q = 0; q < NSEG; ++q) m.off[q + 1] = m.off[q] + T.ctr[C_N(q)];
   return m;
 }
 
@@ -257,7 +274,8 @@ __global__ void __launch_bounds__(256) k_tb_entry(CloakP c, OptsP o, Table T, in
       if (nsteps) nsteps[i] = 0;
     }
   }
-  unsigned int sl = wave_append(T.ctr + C_N, enter);
+  __shared__ unsigned int sh[16];
+  unsigned int sl = block_append(T.ctr + C_N(0), enter, sh);
   if (enter) put_slot(T, (int)sl, x, v, kind, i, s, o.h0, skey);
 }
 
@@ -277,15 +295,15 @@ __global__ void __launch_bounds__(256) k_sort_hist(Table T) {
   }
   __syncthreads();
   for (int i = threadIdx.x; i < NBIN; i += blockDim.x)
-    if (lh[i]) atomicAdd(&T.ctr[C_HIST + i], lh[i]);
+    if (lh[i]) atomicAdd(&T.ctr[C_HIST(i)], lh[i]);
 }
 
 __global__ void k_sort_scan(Table T) {
   if (threadIdx.x == 0) {
     unsigned int acc = 0;
     for (int i = 0; i < NBIN; ++i) {
-      T.ctr[C_OFF + i] = acc;
-      acc += T.ctr[C_HIST + i];
+      T.ctr[C_OFF(i)] = acc;
+      acc += T.ctr[C_HIST(i)];
     }
   }
 }
@@ -310,7 +328,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(Table T) {
     }
     __syncthreads();
     for (int i = threadIdx.x; i < NBIN; i += blockDim.x)
-      lb[i] = lc[i] ? atomicAdd(&T.ctr[C_OFF + i], lc[i]) : 0u;
+      lb[i] = lc[i] ? atomicAdd(&T.ctr[C_OFF(i)], lc[i]) : 0u;
     __syncthreads();
     if (slot >= 0) T.order[lb[key] + local] = slot;
     __syncthreads();
@@ -478,7 +496,7 @@ __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, con
       if (cur >= end) {
         if (drained >> seg & 1u) break;
         unsigned int base = 0;
-        if (__lane_id() == 0) base = atomicAdd(T.ctr + C_FETCH + seg, FETCH_CHUNK);
+        if (__lane_id() == 0) base = atomicAdd(T.ctr + C_FETCH(seg), FETCH_CHUNK);
         base = __shfl(base, 0);
         if (base + FETCH_CHUNK >= len) drained |= 1u << seg;
         cur = off + min(base, len);
@@ -572,7 +590,7 @@ __global__ void __launch_bounds__(256) k_tb_finish(CloakP c, OptsP o, Table T, l
                                                    double *__restrict__ out6, double *__restrict__ opl,
                                                    int *__restrict__ status, double *__restrict__ hres,
                                                    int *__restrict__ nsteps) {
-  unsigned int n0 = T.ctr[C_N];
+  unsigned int n0 = T.ctr[C_N(0)];
   unsigned int stride = gridDim.x * blockDim.x;
   for (unsigned int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n0; idx += stride) {
     int s = (int)idx;
@@ -647,10 +665,11 @@ __global__ void __launch_bounds__(256) k_sx_entry(CloakP c, OptsP o, Table T, lo
       if (nsteps) nsteps[i] = 0;
     }
   }
+  __shared__ unsigned int sh[16];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const bool want = entered && kind == q;
-    unsigned int sl = wave_append(T.ctr + C_N + q, want);
+    unsigned int sl = block_append(T.ctr + C_N(q), want, sh);
     if (want) put_slot(T, (int)(q * T.cap + sl), x, v, q, i, 0.0, o.h0, skey);
   }
 }
@@ -706,7 +725,7 @@ struct RenderP {
   int n_cams, ncl, npol, spp;
   int axis[2];        // optic axis of each cloak
   int pol[2];         // branch of each traced polarization
-  int has_cloak, pad;
+  int has_cloak, idx32;  // idx32: every flattened sample index < 2^32
   unsigned char *codes;  // chunk-local codes [segment][g1-g0]
   double *rec;           // aux (may be NULL)
   int *st;
@@ -714,13 +733,27 @@ struct RenderP {
   int *nsteps;
 };
 
+// flattened sample index -> (camera, sample within the image), in 32-bit
+// arithmetic when every index fits (64-bit division is a long sequence)
+__device__ __forceinline__ void split_index(const RenderP &R, long long gidx, long long &cam, long long &loc) {
+  if (R.idx32) {
+    const unsigned int g = (unsigned int)gidx, ns = (unsigned int)R.ns_img, c32 = g / ns;
+    cam = c32;
+    loc = g - c32 * ns;
+  } else {
+    cam = gidx / R.ns_img;
+    loc = gidx - cam * R.ns_img;
+  }
+}
+
 // segment q = cloak * npol + polarization; images are laid out
 // [cloak][camera][polarization]
 __device__ __forceinline__ void rd_write(const RenderP &R, int q, long long gidx, int code,
                                          int st, const double p[3], const double d[3], double L,
                                          int nsteps) {
   R.codes[(long long)q * (R.g1 - R.g0) + (gidx - R.g0)] = (unsigned char)code;
-  long long cam = gidx / R.ns_img, loc = gidx - cam * R.ns_img;
+  long long cam, loc;
+  split_index(R, gidx, cam, loc);
   int ci = q / R.npol, pi = q - ci * R.npol;
   long long img = ((long long)ci * R.n_cams + cam) * R.npol + pi;
   if (R.st) R.st[img * R.ns_img + loc] = st;
@@ -743,9 +776,11 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
   int surf = 0;
   bool hitc = false, disk = false;
   if (valid) {
-    long long cam = gidx / R.ns_img, loc = gidx - cam * R.ns_img;
-    long long pix = loc / R.spp;
-    int smp = (int)(loc - pix * R.spp);
+    long long cam, loc;
+    split_index(R, gidx, cam, loc);
+    const unsigned int l32 = (unsigned int)loc, sp = (unsigned int)R.spp;  // loc < ns_img <= 2^30
+    const long long pix = l32 / sp;
+    const int smp = (int)(l32 - (unsigned int)pix * sp);
     const CamP &C = cams[cam];
     org[0] = C.eye[0]; org[1] = C.eye[1]; org[2] = C.eye[2];
     camera_ray(C, (int)cam, pix, smp, d);
@@ -777,6 +812,7 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
       vL += sh;
     }
   }
+  __shared__ unsigned int sh[16];
   for (int q = 0; q < R.ncl * R.npol; ++q) {
     int ci = q / R.npol, pi = q - ci * R.npol;
     int kind = (ci == 0 ? R.axis[0] : R.axis[1]) * 2 + (pi == 0 ? R.pol[0] : R.pol[1]);
@@ -796,7 +832,7 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
         rd_write(R, q, gidx, code, RT_RAY_REFLECTED, x, dd, s + sh, 0);
       }
     }
-    unsigned int sl = wave_append(T.ctr + C_N + q, enter);
+    unsigned int sl = block_append(T.ctr + C_N(q), enter, sh);
     if (enter) put_slot(T, (int)(q * T.cap + sl), x, v, kind, gidx, s, o.h0, sort_key(c, kind, x, d));
   }
 }
@@ -836,8 +872,16 @@ __global__ void __launch_bounds__(256) k_rd_resolve(RenderP R, const float *__re
   long long pix_in_chunk = chunk / R.spp;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= pix_in_chunk * R.ncl * R.npol) return;
-  int q = (int)(i / pix_in_chunk);
-  long long lp = i - q * pix_in_chunk;
+  int q;
+  long long lp;
+  if (R.idx32) {  // every index below fits 32 bits
+    const unsigned int i32 = (unsigned int)i, pc = (unsigned int)pix_in_chunk;
+    q = (int)(i32 / pc);
+    lp = i32 - (unsigned int)q * pc;
+  } else {
+    q = (int)(i / pix_in_chunk);
+    lp = i - q * pix_in_chunk;
+  }
   const unsigned char *cd = R.codes + q * chunk + lp * R.spp;
   float r = 0.f, g = 0.f, b = 0.f;
   for (int k = 0; k < R.spp; ++k) {
@@ -848,7 +892,15 @@ __global__ void __launch_bounds__(256) k_rd_resolve(RenderP R, const float *__re
   }
   float inv = 1.0f / (float)R.spp;
   long long gpix = R.g0 / R.spp + lp;  // flattened (camera, pixel)
-  long long cam = gpix / npix, pix = gpix - cam * npix;
+  long long cam, pix;
+  if (R.idx32) {
+    const unsigned int g32 = (unsigned int)gpix, np = (unsigned int)npix, c32 = g32 / np;
+    cam = c32;
+    pix = g32 - c32 * np;
+  } else {
+    cam = gpix / npix;
+    pix = gpix - cam * npix;
+  }
   int ci = q / R.npol, pi = q - ci * R.npol;
   float *o = rgb + ((((long long)ci * R.n_cams + cam) * R.npol + pi) * npix + pix) * 3;
   o[0] = r * inv;
@@ -1168,6 +1220,8 @@ int prepare_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts
     for (int j = 0; j < 3; ++j) { P.eye[j] = C.eye[j]; P.F[j] = F[j]; P.R[j] = R[j]; P.U[j] = U[j]; }
     P.tan_half = std::tan(0.5 * C.fov_deg * M_PI / 180.0);
     P.aspect = (double)w / (double)h;
+    P.inv_w = (w & (w - 1)) == 0 ? 1.0 / w : 0.0;
+    P.inv_h = (h & (h - 1)) == 0 ? 1.0 / h : 0.0;
     P.w = w; P.h = h; P.spp = spp; P.m = m;
     P.seed = C.seed;
   }
@@ -1176,6 +1230,11 @@ int prepare_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts
   for (int j = 0; j < 3; ++j) { J.rm.lo[j] = room->lo[j]; J.rm.hi[j] = room->hi[j]; }
   J.rm.tile = room->tile;
   J.rm.inv_tile = 1.0 / room->tile;
+  {
+    int ex = 0;
+    J.rm.tile_pow2 = std::frexp(room->tile, &ex) == 0.5 ? 1 : 0;  // tile = 2^(ex-1)
+    J.rm.pad = 0;
+  }
   for (int f = 0; f < 6; ++f)
     for (int q = 0; q < 2; ++q)
       for (int j = 0; j < 3; ++j) J.table[(f * 2 + q) * 3 + j] = room->rgb[f][q][j];
@@ -1200,7 +1259,7 @@ int prepare_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts
   R.pol[0] = (pol_mask & 1) ? RT_POL_ORDINARY : RT_POL_EXTRAORDINARY;
   R.pol[1] = RT_POL_EXTRAORDINARY;
   R.has_cloak = n_cloaks > 0 ? 1 : 0;
-  R.pad = 0;
+  R.idx32 = ns_img * n_cams <= 0xffffffffLL ? 1 : 0;
   R.codes = nullptr;
   R.rec = aux ? aux->rec : nullptr;
   R.st = aux ? aux->status : nullptr;
@@ -1231,7 +1290,7 @@ void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStre
   for (long long g0 = 0; g0 < J.total; g0 += J.chunk) {
     R.g0 = g0;
     R.g1 = std::min(J.total, g0 + J.chunk);
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, T.ctr, (int)C_COUNT);
+    hipLaunchKernelGGL(k_zero, dim3((C_COUNT + 255) / 256), dim3(256), 0, s, T.ctr, (int)C_COUNT);
     hipLaunchKernelGGL(k_rd_gen, dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
                        ws.cams, T, R);
     if (J.n_cloaks) {
@@ -1338,7 +1397,7 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
   int refill = opts->refill_period ? opts->refill_period : 2;
   int kind = c.axis * 2 + pol;
   unsigned int grid = o.precision == RT_PREC_MIXED ? transit_grid<true>(block) : transit_grid<false>(block);
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, T.ctr, (int)C_COUNT);
+  hipLaunchKernelGGL(k_zero, dim3((C_COUNT + 255) / 256), dim3(256), 0, s, T.ctr, (int)C_COUNT);
   hipLaunchKernelGGL(k_tb_entry, dim3(grid_for(n, 256)), dim3(256), 0, s, c, o, T, kind, (long long)n,
                      in6, out6, opl, status, hres, nsteps);
   e = launch_err("entry launch");
@@ -1383,7 +1442,7 @@ int rt_transit_exact(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_op
   int block = opts->block ? opts->block : 256;
   int refill = opts->refill_period ? opts->refill_period : 2;
   unsigned int grid = o.precision == RT_PREC_MIXED ? transit_grid<true>(block) : transit_grid<false>(block);
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, T.ctr, (int)C_COUNT);
+  hipLaunchKernelGGL(k_zero, dim3((C_COUNT + 255) / 256), dim3(256), 0, s, T.ctr, (int)C_COUNT);
   hipLaunchKernelGGL(k_sx_entry, dim3(grid_for(n, 256)), dim3(256), 0, s, c, o, T, (long long)n,
                      (long long)ld, x6, mask, have_axes, y5, status, nsteps);
   e = launch_err("entry launch");

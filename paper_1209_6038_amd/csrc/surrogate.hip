@@ -1106,8 +1106,9 @@ void backward(rt_model mo, const float *x, const float *t, long long ld, const f
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, loss, 1LL, 0.0f);
   hipLaunchKernelGGL(k_loss, dim3(gblocks((long long)n * NOUT, 256)), dim3(256), 0, s, mo->y, t, ld, wrow, n,
                      mo->scal, huber, mo->dy, loss);
-  hipLaunchKernelGGL(k_layer5_back, dim3(rows_grid), dim3(HID), 0, s, mo->dy, mo->a4, mo->z[3], n, mo->P, mo->G,
-                     mo->dzf, mo->dzb[1]);
+  // layer 5 accumulates 1285 gradient entries per block: a quarter of the blocks
+  hipLaunchKernelGGL(k_layer5_back, dim3(std::max(1u, rows_grid / 4)), dim3(HID), 0, s, mo->dy, mo->a4, mo->z[3], n,
+                     mo->P, mo->G, mo->dzf, mo->dzb[1]);
   // hidden layers from the top: dz of layer l (FP32 in dzf, BF16 in dzb[cur])
   const long long offw[3] = {OFF_W2, OFF_W3, OFF_W4}, offb[3] = {OFF_B2, OFF_B3, OFF_B4};
   int cur = 1;
