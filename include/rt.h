@@ -21,7 +21,9 @@
  *    output buffers.
  *  - The library allocates a device workspace on first use and grows it when
  *    a larger call needs it (hipMalloc, synchronous); it is released by
- *    rt_release_workspace() or at process exit.
+ *    rt_release_workspace() or at process exit. Renders are processed in
+ *    chunks of up to 2^26 camera samples, with a workspace of ~0.5 KB per
+ *    sample of a chunk (~31 GB for a 4096 x 4096 x 4 spp view).
  */
 #ifndef RT_H
 #define RT_H
@@ -79,7 +81,8 @@ typedef struct {
    ray. max_bounces: internal reflections (inner mirror, total internal
    reflection) per ray, 0..64. block / refill_period: integrator launch shape
    (threads per block, steps between refills of finished lanes; 0 = library
-   default). */
+   default). max_chunk: renders only, camera samples per integrator launch
+   (0 = 2^26; results do not depend on it). */
 typedef struct {
     int32_t scheme;
     int32_t precision;
@@ -90,7 +93,7 @@ typedef struct {
     int32_t max_bounces;
     int32_t block;
     int32_t refill_period;
-    int32_t reserved;
+    int32_t max_chunk;
 } rt_trace_opts;
 
 /* Pinhole camera: eye, look-at point, up vector, vertical full field of view

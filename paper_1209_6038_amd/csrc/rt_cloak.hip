@@ -1077,6 +1077,7 @@ int check_opts(const rt_trace_opts *o, double r2, bool need_rout) {
     return fail(RT_E_INVALID, "block must be 0 or a multiple of 64 in [64, 256]");
   if (o->refill_period < 0 || o->refill_period > 1024)
     return fail(RT_E_INVALID, "refill_period must be in [0, 1024]");
+  if (o->max_chunk < 0 || o->max_chunk > (1 << 26)) return fail(RT_E_INVALID, "max_chunk must be in [0, 2^26]");
   return RT_OK;
 }
 
@@ -1239,7 +1240,12 @@ int prepare_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts
     for (int q = 0; q < 2; ++q)
       for (int j = 0; j < 3; ++j) J.table[(f * 2 + q) * 3 + j] = room->rgb[f][q][j];
   J.total = ns_img * n_cams;
-  const long long chunk_max = (1LL << 24) / spp * spp;
+  // samples per chunk: one integrator launch each. Rays whose paths pass
+  // very close to r = a take tens of thousands of attempts; they are sorted
+  // first and run alongside the rest of their launch, so fewer, larger
+  // launches hide them (a 4096^2 x 4 spp frame is one chunk; the work table
+  // then takes ~0.5 KB per sample, ~31 GB)
+  const long long chunk_max = (opts->max_chunk > 0 ? (long long)opts->max_chunk : (1LL << 26)) / spp * spp;
   J.chunk = std::min(J.total, std::max(chunk_max, (long long)spp));
   J.npix = npix;
   J.n_cloaks = n_cloaks;

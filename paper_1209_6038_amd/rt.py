@@ -53,7 +53,7 @@ class TraceOpts(ctypes.Structure):
                 ("hmax", ctypes.c_double), ("fp64_band", ctypes.c_double),
                 ("r_out", ctypes.c_double), ("max_steps", ctypes.c_int64),
                 ("max_bounces", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("refill_period", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("refill_period", ctypes.c_int32), ("max_chunk", ctypes.c_int32)]
 
 
 class Camera(ctypes.Structure):
@@ -169,7 +169,7 @@ def trace_opts(d: dict) -> TraceOpts:
                      float(d.get("hmax", 0.5)), float(d.get("fp64_band", 0.05)),
                      float(d.get("r_out", 3.0)), int(d.get("max_steps", 1_000_000)),
                      int(d.get("max_bounces", 4)), int(d.get("block", 0)),
-                     int(d.get("refill_period", 0)), 0)
+                     int(d.get("refill_period", 0)), int(d.get("max_chunk", 0)))
 
 
 def camera(d: dict) -> Camera:

@@ -48,7 +48,7 @@ def test_struct_layouts_match_header():
     fields = {
         "rt_cloak_desc": (rt.CloakDesc, ["r1", "z0", "axis", "inner_mirror"]),
         "rt_trace_opts": (rt.TraceOpts, ["scheme", "h", "fp64_band", "r_out", "max_steps",
-                                         "max_bounces", "refill_period"]),
+                                         "max_bounces", "refill_period", "max_chunk"]),
         "rt_camera": (rt.Camera, ["eye", "fov_deg", "w", "spp", "seed"]),
         "rt_room": (rt.Room, ["lo", "tile", "rgb"]),
         "rt_render_aux": (rt.RenderAux, ["rec", "status", "code", "nsteps"]),

@@ -166,3 +166,20 @@ def test_render_multi_rejects_mismatched_geometry():
     cls = [rt.Cloak(W.cloak(0, height=4.0)), rt.Cloak(W.cloak(1, height=3.0))]
     with pytest.raises(rt.RtError):
         rt.render_multi(cls, W.render_opts(), W.room(), [W.orbit_camera(0.0, 10.0, 8, 8)], 3)
+
+
+def test_render_in_small_chunks_equals_one_launch():
+    """A render split into many chunks (one integrator launch each, chunk
+    boundaries inside images and between samples of a pixel's stratum run)
+    gives the single-launch render bit for bit."""
+    import torch
+    from paper_1209_6038_amd import rt
+    cams = [W.orbit_camera(0.3, 25.0, 96, 96, spp=4, seed=9), W.orbit_camera(2.0, 40.0, 96, 96, spp=4, seed=9)]
+    cls = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
+    say("case chunked render: 2 views x 96^2 x 4 spp, chunks of 5000 samples vs one launch")
+    a, aux_a = rt.render_multi(cls, W.render_opts(), W.room(), cams, 3, aux=True)
+    b, aux_b = rt.render_multi(cls, W.render_opts(max_chunk=5000), W.room(), cams, 3, aux=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    for key in ("status", "code", "nsteps"):
+        assert torch.equal(aux_a[key], aux_b[key]), key
