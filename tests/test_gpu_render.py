@@ -183,3 +183,33 @@ def test_render_in_small_chunks_equals_one_launch():
     assert torch.equal(a, b)
     for key in ("status", "code", "nsteps"):
         assert torch.equal(aux_a[key], aux_b[key]), key
+
+
+def test_orbit_frame_full_size_sampled():
+    """One frame of the large-render workload at full size (4096^2 x 4
+    jittered spp, both cloaks, both branches, one launch): sampled pixels,
+    half of them where the cloak is, re-rendered by the oracle. Pixel means
+    of the 4 samples must agree; a sample whose wall hit lies on a tile edge
+    to rounding may flip parity, so one differing pixel per image is
+    allowed."""
+    import torch
+    from paper_1209_6038_amd import rt
+    frame = W.orbit_frames(36, 4096, 4)[5]
+    descs = [W.cloak(a, height=W.HEIGHT) for a in (0, 1)]
+    cls = [rt.Cloak(d) for d in descs]
+    say("case orbit frame 5: 4096^2 x 4 spp, 2 cloaks x 2 branches")
+    rgb = rt.render_multi(cls, W.render_opts(), W.room(), [frame], 3)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    rows = np.concatenate([rng.integers(0, 4096, 24), rng.integers(1400, 2800, 24)])
+    cols = np.concatenate([rng.integers(0, 4096, 24), rng.integers(1600, 2500, 24)])
+    pix = rows * 4096 + cols
+    rt_, ct_ = torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()
+    g = rgb[:, 0][:, :, rt_, ct_].cpu().numpy()  # (cloak, branch, pixel, rgb)
+    for ci, c in enumerate(descs):
+        for pi in range(2):
+            o, _ = oracle.render_pixels(c, W.opts_dp45(), W.room(), frame, 0, pi, pix)
+            d = np.abs(g[ci, pi] - o).max(axis=1)
+            bad = int((d > 1e-6).sum())
+            say(f"  cloak axis {c['axis']} branch {pi}: {bad} of {len(pix)} pixels differ")
+            assert bad <= 1
