@@ -205,6 +205,56 @@ def surrogate_leg(steps: int, n_train: int, log):
     }
 
 
+def inplane_workload(args):
+    """The 2-D workload: radial cloak, extraordinary branch, 16,384 parallel
+    in-plane rays (impact parameters on the midpoint grid of [-3, 3]) at each
+    of 8 incidence angles, RK4 h = 1e-3 (the paper's fixed-step scheme),
+    FP64, exits reported at r = 3. One step = one rt_trace_batch call."""
+    import numpy as np
+    import torch
+    from paper_1209_6038_amd import rt
+    from paper_1209_6038_amd import workloads as W
+
+    rays = torch.from_numpy(W.inplane_bundle(16384, 8)).cuda()
+    opts = W.opts_rk4(1e-3)
+    cl = rt.Cloak(W.cloak(W.RADIAL))
+    r = rt.trace_batch(cl, opts, W.EXTRAORDINARY, rays)
+    torch.cuda.synchronize()
+    st = r["status"].cpu().numpy()
+    entered = int((st != 1).sum())
+    attempts = int(r["nsteps"].cpu().numpy().astype(np.int64).sum())
+    for _ in range(args.warmup):
+        rt.trace_batch(cl, opts, W.EXTRAORDINARY, rays, with_aux=False)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    rt.profile_enable(True)
+    rt.profile_read()
+    a.record()
+    for _ in range(args.steps):
+        rt.trace_batch(cl, opts, W.EXTRAORDINARY, rays, with_aux=False)
+    b.record()
+    torch.cuda.synchronize()
+    transit_ms, launches = rt.profile_read()
+    rt.profile_enable(False)
+    ms = a.elapsed_time(b) / args.steps
+    launch_ms = transit_ms / max(1, launches)
+    flops = attempts * attempt_flops(1, 0)
+    achieved = flops / (launch_ms * 1e-3) / 1e12
+    return {
+        "metric": "Mrays/s traced through cloak at <=1e-6 exit error", "unit": "Mrays/s",
+        "value": round(entered / (ms * 1e-3) / 1e6, 3), "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "2-D in-plane: radial cloak, extraordinary branch, 16384 rays x 8 angles, "
+                               "RK4 h=1e-3, FP64, exits at r=3",
+                   "rays": int(rays.shape[1]), "entering": entered, "rk4_steps": attempts},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_transit (integrator)", "avg_launch_ms": round(launch_ms, 4)},
+    }
+
+
 def orbit_workload(args):
     """The large-render workload timed plain: 36-frame orbit at 30 deg
     elevation, 4096 x 4096 px, 4 jittered samples per pixel, radial and
@@ -262,7 +312,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--res", type=int, default=1024)
-    ap.add_argument("--workload", choices=("render3d", "batched", "orbit", "surrogate"), default="render3d")
+    ap.add_argument("--workload", choices=("render3d", "batched", "orbit", "surrogate", "inplane"),
+                    default="render3d")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed")
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
@@ -278,8 +329,8 @@ def main():
         copy_probe()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it "
-              "(see DESIGN.md for how the path would shard)", file=sys.stderr)
+        print("bench.py: runs on one GPU only; across GPUs the render would shard by camera or image "
+              "tile (no exchange but the image gather), which is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -295,6 +346,9 @@ def main():
     dev = torch.device("cuda", 0)
     if args.workload == "orbit":
         print(json.dumps(orbit_workload(args)), flush=True)
+        return
+    if args.workload == "inplane":
+        print(json.dumps(inplane_workload(args)), flush=True)
         return
     if args.workload == "surrogate":
         torch.cuda.set_device(0)
