@@ -26,7 +26,7 @@ entries are traced by the plain exact transit and by surrogate + exact
 fallback (both timed with HIP events, inputs resident), and the accepted
 predictions' exit errors are measured against the exact exits.
 
-Prints one JSON line. --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line. --gpus N with N > 1 exits: the implementation runs on one GPU.
 """
 from __future__ import annotations
 
