@@ -399,7 +399,7 @@ static void step_map(const orc_opts *o, const rhs_ctx *ctx, const double *y,
 }
 
 /* Bisection for the step length hs in (0, h] at which the step map puts the
-   state on boundary `id`, to |g| <= 1e-13 b. */
+   state on boundary `id`, to |g| <= 1e-13 b; g < 0 at 0 and g >= 0 at h. */
 static double crossing(const orc_cloak *c, const orc_opts *o, const rhs_ctx *ctx,
                        const double *y, const double *k1, double h, int id, double *yout) {
     double lo = 0.0, hi = h, mid = h, tol = 1e-13 * c->b;
@@ -452,6 +452,25 @@ static int integrate(const orc_cloak *c, int branch, const orc_opts *o, double *
                 double hc = crossing(c, o, &ctx, y, k1, h, id, yc);
                 if (first < 0 || hc < hfirst) {
                     first = id; hfirst = hc;
+                    memcpy(yfirst, yc, sizeof(yc));
+                }
+            }
+        }
+        /* The radial cloak's ordinary branch moves in a homogeneous medium
+           (Eq. (14): eps_o = kappa constant), so a step is a straight chord,
+           and a chord can dip into r < a and come back out within one step
+           with both ends outside: its point of closest approach to the axis
+           then lies inside, and the crossing is searched before it. */
+        if (first < 0 && c->axis == ORC_AXIS_RADIAL && branch == ORC_ORDINARY) {
+            double dx = yn[0] - y[0], dy = yn[1] - y[1];
+            double dd = dx * dx + dy * dy;
+            if (dd > 0.0) {
+                double f = -(y[0] * dx + y[1] * dy) / dd;
+                double px = y[0] + f * dx, py = y[1] + f * dy;
+                if (f > 0.0 && f < 1.0 && px * px + py * py < c->a * c->a) {
+                    double yc[6];
+                    hfirst = crossing(c, o, &ctx, y, k1, f * h, EV_INNER, yc);
+                    first = EV_INNER;
                     memcpy(yfirst, yc, sizeof(yc));
                 }
             }

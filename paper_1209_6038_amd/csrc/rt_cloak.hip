@@ -377,6 +377,29 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
     }
     if (!finite6(xn, vn)) return RT_RAY_DIVERGED;
     if (inside_open(c, xn)) {
+      if constexpr (KIND == K_RO) {
+        // homogeneous medium (Eq. (14): eps_o = kappa): the step is a
+        // straight chord, which can dip into r < a and come back out
+        // within one step. If its closest approach to the axis lies inside,
+        // search the crossing before that point, starting from the chord's
+        // first root of |x + tau (xn - x)|_xy = a.
+        const double dx = xn[0] - L.x[0], dy = xn[1] - L.x[1];
+        const double dd = fma(dx, dx, dy * dy);
+        if (dd > 0.0) {
+          const double f = -fma(L.x[0], dx, L.x[1] * dy) / dd;
+          const double px = fma(f, dx, L.x[0]), py = fma(f, dy, L.x[1]);
+          const double pc2 = fma(px, px, py * py);
+          if (f > 0.0 && f < 1.0 && pc2 < c.a2) {
+            const double tau = f - sqrt((c.a2 - pc2) / dd);
+            L.rid = B_INNER;
+            L.lo = 0.0;
+            L.hi = f * hs;
+            L.ht = hs * fmin(fmax(tau, 1e-3 * f), (1.0 - 1e-3) * f);
+            L.riter = 0;
+            return -1;
+          }
+        }
+      }
 #pragma unroll
       for (int i = 0; i < 3; ++i) { L.x[i] = xn[i]; L.v[i] = vn[i]; }
       L.t += hs;

@@ -186,14 +186,10 @@ def test_closed_form_baselines_match_the_exact_transit():
     straight line in (sqrt(kappa)(r - a), theta, sqrt(kappa) z)) are exact
     transits: a network with zero output decodes to them, and they match the
     integrator's exits, and the encoded targets of exact transits vanish, to
-    float32 resolution. The other two branches have no baseline.
-
-    Excluded: radial-o rays whose horizontal impact parameter is within 1%
-    of the mirror radius. The integrator (like the oracle) detects events
-    by a sign change of the boundary function at step ends; in the
-    homogeneous medium its steps grow to h_max, so a chord that dips into
-    r < a for less than a step is not reflected there, while the closed
-    form is."""
+    float32 resolution. The other two branches have no baseline. This
+    includes the radial-o rays whose chord only just dips into the metal
+    cylinder (near-grazing entries), which the integrator finds inside a
+    step by the chord's closest approach."""
     import torch
     from paper_1209_6038_amd import rt
     from paper_1209_6038_amd import surrogate as S
@@ -209,14 +205,8 @@ def test_closed_form_baselines_match_the_exact_transit():
     torch.cuda.synchronize()
     kind = (x[5] * 2 + x[4]).long()
     err, operr = S.exit_error(y_s, y_ex)
-    kt = (torch.cos(x[3]) * torch.sin(x[2])).abs().double()
-    kz = torch.sin(x[3]).double()
-    n = W.R2 / (W.R2 - W.R1)
-    ua = kt / torch.sqrt(n * n - kz * kz) * (W.R2 / W.R1)  # horizontal impact parameter / a
-    grazing = (kind == 0) & ((ua - 1.0).abs() < 1e-2)
-    say(f"radial-o rays grazing the mirror (excluded): {int(grazing.sum())}")
     for k in (0, 3):
-        sel = (kind == k) & (fb == 0) & (w > 0) & ~grazing
+        sel = (kind == k) & (fb == 0) & (w > 0)
         assert sel.sum() > 4000
         e = S.summarize_errors(err, sel)
         say(f"kind {k}: baseline exit error {e}, max opl rel err {float(operr[sel].max()):.2e}")

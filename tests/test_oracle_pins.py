@@ -336,6 +336,39 @@ def test_radial_ordinary_3d_is_a_lens_with_mirror():
         assert r["opl"][i] == pytest.approx(opl, abs=1e-10)
 
 
+def test_radial_ordinary_grazing_the_mirror_is_reflected():
+    """Radial-o rays whose straight chord inside only just dips into the
+    metal cylinder (horizontal impact parameter 0.99..0.9999 a, reached by
+    near-grazing entries) must still be reflected: with the adaptive scheme
+    a step grows to h_max in the homogeneous medium, longer than the dip,
+    so the crossing has to be found inside the step. Checked against the
+    closed form (straight lines, Snell at r = b, mirror at r = a)."""
+    a, b = 1.0, 2.0
+    n = b / (b - a)
+    rays = []
+    for frac in (0.0, 0.5, 0.9):
+        for u in (0.99, 0.995, 0.999, 0.9999):
+            # p_h = b kt / sqrt(n^2 - kz^2) = u a with kt^2 + kz^2 < 1 needs
+            # needs kz < 2 sqrt((1 - u^2) / (4 - u^2)) for b = 2a, n = 2
+            kz = frac * 2.0 * math.sqrt((1.0 - u * u) / (4.0 - u * u))
+            kt = u * a * math.sqrt(n * n - kz * kz) / b
+            kr = math.sqrt(1.0 - kt * kt - kz * kz)
+            phi = 0.3 + 2.0 * frac + u
+            rh = np.array([math.cos(phi), math.sin(phi), 0.0])
+            th = np.array([-math.sin(phi), math.cos(phi), 0.0])
+            d = -kr * rh + kt * th + kz * np.array([0.0, 0.0, 1.0])
+            p = b * rh + np.array([0.0, 0.0, 0.5])
+            rays.append(np.concatenate([p - 0.5 * d, d]))
+    rays = np.array(rays).T
+    r = oracle.trace(W.cloak(0), W.opts_dp45(1e-8, r_out=2.0), O, rays)
+    assert (r["status"] == 0).all()
+    for i in range(rays.shape[1]):
+        pe, de, opl = CF.cf3_radial_o(rays[:3, i], rays[3:, i])
+        np.testing.assert_allclose(r["out"][:3, i], pe, atol=1e-7)
+        np.testing.assert_allclose(r["out"][3:, i], de, atol=1e-7)
+        assert r["opl"][i] == pytest.approx(opl, abs=1e-7)
+
+
 @pytest.mark.parametrize("axis,branch", [(0, 1), (1, 0)])
 def test_integrable_3d_cases_match_quadrature(axis, branch):
     rays = CF.aimed_rays(12, 13 + axis)
