@@ -244,24 +244,29 @@ int rt_cloak_get_desc(rt_cloak cloak, rt_cloak_desc *out);
    cloaks: 1 or 2 handles with different optic axes sharing r1, r2, z0, z1,
    inner_mirror; a ray whose axis bit has no handle is RT_RAY_INVALID.
    status: n int32 (RT_RAY_*); y5 is NaN for rays that did not leave.
+   hres:   n floats or NULL, |v^T M v - 1| at the exit interface (NaN if the
+           ray never entered): the integrator's drift from the ray
+           Hamiltonian, which grows where it cannot resolve the path (entries
+           with p_theta -> 0 pass next to the singular r = r1).
    nsteps: n int32 or NULL. r_out in opts is ignored. Errors as
    rt_trace_batch; n <= 2^28. */
 int rt_transit_exact(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts, int64_t n,
                      int64_t ld, const float *x6, const uint8_t *mask, float *y5, int32_t *status,
-                     int32_t *nsteps, void *stream);
+                     float *hres, int32_t *nsteps, void *stream);
 
 /* ---------------------------------------------------------------------------
    Learned surrogate of the transit (not part of the paper): an MLP
    6 -> 256 -> 256 -> 256 -> 256 -> 5 with SiLU, layers 2-4 on BF16 matrix
    cores with FP32 accumulation, layers 1 and 5 in FP32. It predicts the
-   targets (t0..t4) of a transit:
-     t0 = dtheta - base, t1 = (z' - z) cos(beta) / 2 r2, t2 = alpha' - alpha,
-     t3 = beta' - beta,  t4 = T cos(beta) / 2 r2,
-   where dtheta is the signed azimuth the ray sweeps (sign of alpha) and
-   base = sign(alpha) pi for the azimuthal cloak's extraordinary branch, 0
-   otherwise. A model belongs to the device current at its creation; calls on
-   one model must not overlap (they share its activation buffers). Arrays are
-   device pointers unless stated; n <= 2^24, ld >= n.
+   residuals (t0..t4) of a transit against the closed-form transit of the
+   infinite cylinder (dtheta_0, dz_0, T_0), which exists for all four
+   (axis, branch) pairs of Eqs. (14)/(15):
+     t0 = dtheta - dtheta_0, t1 = (z' - z) - dz_0, t2 = alpha' - alpha,
+     t3 = beta' - beta,      t4 = T - T_0,
+   where dtheta is the signed azimuth the ray sweeps (sign of alpha). A model
+   belongs to the device current at its creation; calls on one model must
+   not overlap (they share its activation buffers). Arrays are device
+   pointers unless stated; n <= 2^24, ld >= n.
    --------------------------------------------------------------------------- */
 typedef struct {
     float lr, beta1, beta2, eps, weight_decay;  /* AdamW */
@@ -279,6 +284,7 @@ typedef struct {
     double cap_margin;  /* exit-height margin from the caps */
     int32_t min_count;  /* calibration rays a cell needs to be trusted */
     int32_t dilate;     /* also distrust cells within this many cells (same axis and branch) of an untrusted one */
+    double unresolved;  /* calibration: exits whose exact transit drifted by |H - 1| > this are no reference */
 } rt_gate_opts;
 
 /* New model with weights and biases uniform in +-1/sqrt(fan_in) (seeded),
@@ -325,11 +331,15 @@ int rt_surrogate_forward(rt_model model, int64_t n, int64_t ld, const float *x6,
    them side-to-side transits with error <= tol, and no cell within
    `dilate` cells of it (in alpha and beta) fails that test (discontinuities
    of the transit run along thin curves that a cell's calibration rays can
-   miss). Stores `gate` in the model.
-   trusted_fraction (host, may be NULL): share of trusted cells. Synchronous. */
+   miss). hres_exact (n floats from rt_transit_exact, or NULL): exits with
+   hres_exact > gate->unresolved (> 0) are left out, neither counted nor
+   failing, since the integrator did not resolve them. Stores `gate` in
+   the model. trusted_fraction (host, may be NULL): share of trusted cells.
+   Synchronous. */
 int rt_surrogate_calibrate(rt_model model, const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int64_t ld,
                            const float *x6, const float *y5_exact, const int32_t *status_exact,
-                           const rt_gate_opts *gate, double *trusted_fraction, void *stream);
+                           const float *hres_exact, const rt_gate_opts *gate, double *trusted_fraction,
+                           void *stream);
 /* Trust map (host, 4 x cells_alpha x cells_beta bytes, (axis*2+branch)
    major, uniform cells over (-pi/2, pi/2)^2); host may be NULL. */
 int rt_surrogate_get_map(rt_model model, uint8_t *host, int32_t *cells_alpha, int32_t *cells_beta);

@@ -700,7 +700,8 @@ __global__ void __launch_bounds__(256) k_sx_entry(CloakP c, OptsP o, Table T, lo
 // rt_transit_exact finish: vacuum leg of the outgoing ray back to r = b
 // (zero for side exits) and its exit parameters
 __global__ void __launch_bounds__(256) k_sx_finish(CloakP c, Table T, long long ld, float *__restrict__ y5,
-                                                   int *__restrict__ status, int *__restrict__ nsteps) {
+                                                   int *__restrict__ status, float *__restrict__ hres,
+                                                   int *__restrict__ nsteps) {
   const SegMap m = seg_map(T);
   const unsigned int n = m.off[NSEG];
   unsigned int stride = gridDim.x * blockDim.x;
@@ -735,6 +736,7 @@ __global__ void __launch_bounds__(256) k_sx_finish(CloakP c, Table T, long long 
 #pragma unroll
     for (int j = 0; j < 5; ++j) y5[j * ld + i] = out[j];
     status[i] = st;
+    if (hres) hres[i] = (float)T.hres[s];
     if (nsteps) nsteps[i] = T.nsteps[s];
   }
 }
@@ -1442,7 +1444,7 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
 
 int rt_transit_exact(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts, int64_t n,
                      int64_t ld, const float *x6, const uint8_t *mask, float *y5, int32_t *status,
-                     int32_t *nsteps, void *stream) {
+                     float *hres, int32_t *nsteps, void *stream) {
   if (n_cloaks < 1 || n_cloaks > 2 || !cloaks) return fail(RT_E_INVALID, "need 1 or 2 cloak handles");
   for (int k = 0; k < n_cloaks; ++k)
     if (!cloaks[k]) return fail(RT_E_INVALID, "cloak handle %d is NULL", k);
@@ -1481,7 +1483,7 @@ int rt_transit_exact(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_op
   e = launch_err("transit launch");
   if (e) return e;
   hipLaunchKernelGGL(k_sx_finish, dim3(num_cu() * 8), dim3(256), 0, s, c, T, (long long)ld, y5, status,
-                     nsteps);
+                     hres, nsteps);
   return launch_err("finish launch");
 }
 

@@ -545,16 +545,16 @@ __global__ void k_fill_f64(double *p, int n) {
 // ---------------------------------------------------------------------------
 // Target encoding. Entry (phi, z, alpha, beta) on r = b, exit (phi', z',
 // alpha', beta') on r = b, optical path T between them:
-//   t0 = dtheta - dtheta_0,  t1 = (dz - dz_0) cos(beta) / 2b,
-//   t2 = alpha' - alpha,     t3 = beta' - beta,
-//   t4 = (T - T_0) cos(beta) / 2b,
+//   t0 = dtheta - dtheta_0,  t1 = dz - dz_0,  t2 = alpha' - alpha,
+//   t3 = beta' - beta,       t4 = T - T_0,
 // with dz = z' - z and dtheta the signed azimuth swept by the ray. The
 // conserved angular momentum p_theta keeps its sign along the path (the
 // inner mirror reflects radially), so theta is monotonic with the sign s of
 // alpha, and dtheta = s * ((s (phi' - phi)) mod 2 pi) unwraps exactly for
-// transits of less than a full turn. The factors cos(beta) / 2b measure
-// vertical travel and path length in units of the vacuum chord
-// 2b cos(alpha) / cos(beta), bounded at grazing elevations.
+// transits of less than a full turn. All five residuals are bounded: the
+// refraction into the cloak keeps the rise and the path inside finite even
+// for entries at grazing elevation, so they enter unscaled (a residual
+// divided by cos(beta) would multiply the network's error by 1 / cos(beta)).
 //
 // (dtheta_0, dz_0, T_0) is the closed-form transit where one exists (zero
 // otherwise), so that the network learns a residual:
@@ -568,8 +568,20 @@ __global__ void k_fill_f64(double *p, int n) {
 //    rho = sqrt(kappa) (r - a), zeta = sqrt(kappa) z: a straight line in
 //    (rho, theta, zeta) at unit speed, entering at rho = b with tangential
 //    speed k_theta and axial speed k_z / sqrt(kappa).
-// The radial cloak's extraordinary and the azimuthal cloak's ordinary
-// branch have no closed form: zero baseline.
+//  - radial cloak, extraordinary branch, and azimuthal cloak, ordinary
+//    branch: both have m_theta = m_z = kappa s, so with p = b k_theta the
+//    Hamiltonian constraint gives m_r rdot^2 = Q(r) / (kappa (r - a)^2) for
+//    the quadratic Q(r) = kappa (r - a)^2 - p^2 - k_z^2 r^2, which equals
+//    (b k_n)^2 at r = b; the turning point is its larger root. The sweep,
+//    the rise and the optical path per unit r are
+//      radial e (m_r = kappa):      p / (u sqrt Q), k_z r^2 / (u sqrt Q),
+//                                   kappa u / sqrt Q            (u = r - a),
+//      azimuthal o (m_r = kappa s): p / (r sqrt Q), k_z r / sqrt Q,
+//                                   kappa u^2 / (r sqrt Q),
+//    sums of 1 / sqrt Q, x / sqrt Q and 1 / (x sqrt Q) for Q quadratic in x,
+//    integrated in closed form from the root to r = b (asinh, atan2 and
+//    asinh(sqrt y) / sqrt y, the last continued through y = 0 as
+//    asin(sqrt -y) / sqrt -y).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float wrap2pi(float a) {
   a = fmodf(a, 2.0f * PI_F);
@@ -604,6 +616,32 @@ __device__ __forceinline__ void baseline(int kind, float al, float be, float a, 
     dth = 2.0f * s * half_sweep(u);
     T = 2.0f * b * sqrtf(fmaxf(0.f, (1.f - u) * (1.f + u))) / h;
     dz = T * kz / kap;
+  } else {
+    const float p = b * kt, A = kap - kz * kz, kza2 = kz * kz * a * a;
+    const float S = sqrtf(fmaf(A, p * p, kap * kza2));  // half the root of the discriminant of Q
+    const float sq = b * cosf(al) * cosf(be);           // sqrt Q(b)
+    const float sA = sqrtf(A);
+    const float J0 = asinhf(sA * sq / S) / sA;          // int dx / sqrt Q from the root
+    if (kind == 1) {                                    // x = u: Q = A u^2 - 2 a k_z^2 u - (p^2 + k_z^2 a^2)
+      const float mC = fmaf(p, p, kza2), rm = sqrtf(mC);
+      const float J1 = fmaf(a * kz * kz, J0, sq) / A;   // int u du / sqrt Q
+      const float Jm = atan2f(rm * sq, fmaf(a * kz * kz, b - a, mC)) / rm;  // int du / (u sqrt Q)
+      dth = 2.0f * s * p * Jm;
+      dz = 2.0f * kz * (J1 + 2.0f * a * J0 + a * a * Jm);
+      T = 2.0f * kap * J1;
+    } else {                                            // x = r: Q = A r^2 - 2 kappa a r + kappa a^2 - p^2
+      const float C = fmaf(kap * a, a, -p * p);
+      const float y = C * sq * sq / (b * b * S * S);
+      float g;                                          // asinh(sqrt y) / sqrt y
+      if (fabsf(y) < 1e-3f) g = fmaf(y, fmaf(y, 0.075f, -1.0f / 6.0f), 1.0f);
+      else if (y > 0.0f) g = asinhf(sqrtf(y)) / sqrtf(y);
+      else g = asinf(sqrtf(-y)) / sqrtf(-y);
+      const float Jm = sq / (b * S) * g;                // int dr / (r sqrt Q)
+      const float J1 = fmaf(kap * a, J0, sq) / A;       // int r dr / sqrt Q
+      dth = 2.0f * s * p * Jm;
+      dz = 2.0f * kz * J1;
+      T = 2.0f * kap * (J1 - 2.0f * a * J0 + a * a * Jm);
+    }
   }
 }
 
@@ -628,14 +666,13 @@ __global__ void __launch_bounds__(256) k_encode(const float *__restrict__ x6, co
   if (ok) {
     const float s = al < 0.0f ? -1.0f : 1.0f;
     const float dth = s * wrap2pi(s * (y5[i] - phi));
-    const float cb = cosf(be);
     float dth0, dz0, T0;
     baseline(kind_of(pol, axis), al, be, a, b, dth0, dz0, T0);
     t[0] = dth - dth0;
-    t[1] = (y5[ld + i] - z - dz0) * cb / (2.0f * b);
+    t[1] = (y5[ld + i] - z) - dz0;
     t[2] = y5[2 * ld + i] - al;
     t[3] = y5[3 * ld + i] - be;
-    t[4] = (y5[4 * ld + i] - T0) * cb / (2.0f * b);
+    t[4] = y5[4 * ld + i] - T0;
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) ok = ok && isfinite(t[o]);
   }
@@ -652,12 +689,11 @@ __device__ __forceinline__ void decode(const float *yrow, const float *sc, float
   for (int o = 0; o < NOUT; ++o) t[o] = fmaf(yrow[o], sc[S_OSTD + o], sc[S_OMEAN + o]);
   float dth0, dz0, T0;
   baseline(kind, al, be, a, b, dth0, dz0, T0);
-  const float inv_cb = 1.0f / cosf(be);
   out[0] = wrap2pi(phi + t[0] + dth0);
-  out[1] = z + dz0 + t[1] * 2.0f * b * inv_cb;
+  out[1] = z + (dz0 + t[1]);
   out[2] = al + t[2];
   out[3] = be + t[3];
-  out[4] = T0 + t[4] * 2.0f * b * inv_cb;
+  out[4] = T0 + t[4];
 }
 
 // cell of the trust map
@@ -931,7 +967,8 @@ __device__ __forceinline__ void exit_ray(const float *p, float b, float x[3], fl
 // makes its cell untrusted
 __global__ void __launch_bounds__(256) k_calib(const float *__restrict__ x6, long long ld, int n,
                                                const float *__restrict__ y, const float *__restrict__ sc,
-                                               const float *__restrict__ ye, const int *__restrict__ st, float a,
+                                               const float *__restrict__ ye, const int *__restrict__ st,
+                                               const float *__restrict__ hres, float unresolved, float a,
                                                float b, unsigned int *__restrict__ cmax,
                                                unsigned int *__restrict__ ccnt) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -939,6 +976,8 @@ __global__ void __launch_bounds__(256) k_calib(const float *__restrict__ x6, lon
   const float phi = x6[i], z = x6[ld + i], al = x6[2 * ld + i], be = x6[3 * ld + i];
   const float pol = x6[4 * ld + i], axis = x6[5 * ld + i];
   if (!entry_ok(phi, z, al, be, pol, axis)) return;
+  // an exit the integrator did not resolve is no reference
+  if (hres && st[i] == RT_RAY_EXITED && !(hres[i] <= unresolved)) return;
   const int kind = kind_of(pol, axis);
   const int cell = cell_of(kind, al, be);
   float err = INFINITY;
@@ -1397,7 +1436,8 @@ int rt_surrogate_encode(const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int
 
 int rt_surrogate_calibrate(rt_model mo, const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int64_t ld,
                            const float *x6, const float *y5_exact, const int32_t *status_exact,
-                           const rt_gate_opts *gate, double *trusted_fraction, void *stream) {
+                           const float *hres_exact, const rt_gate_opts *gate, double *trusted_fraction,
+                           void *stream) {
   int e = check_model(mo);
   if (e) return e;
   rt_cloak_desc d;
@@ -1406,15 +1446,17 @@ int rt_surrogate_calibrate(rt_model mo, const rt_cloak *cloaks, int32_t n_cloaks
   if (e) return e;
   if (!y5_exact || !status_exact || !gate) return fail(RT_E_INVALID, "y5_exact, status_exact and gate are required");
   if (!(gate->tol > 0.0) || !(gate->hres_max > 0.0) || !(gate->cap_margin >= 0.0) || gate->min_count < 1 ||
-      gate->dilate < 0 || gate->dilate > 8)
-    return fail(RT_E_INVALID, "gate needs tol > 0, hres_max > 0, cap_margin >= 0, min_count >= 1, 0 <= dilate <= 8");
+      gate->dilate < 0 || gate->dilate > 8 || (hres_exact && !(gate->unresolved > 0.0)))
+    return fail(RT_E_INVALID, "gate needs tol > 0, hres_max > 0, cap_margin >= 0, min_count >= 1, "
+                              "0 <= dilate <= 8 and, with hres_exact, unresolved > 0");
   e = reserve_yinf(mo, n);
   if (e) return e;
   hipStream_t s = (hipStream_t)stream;
   infer_outputs(mo, x6, ld, (int)n, s);
   hipLaunchKernelGGL(k_fill_u32, dim3(gblocks(2LL * NCELLS, 256)), dim3(256), 0, s, mo->cal, 2LL * NCELLS);
   hipLaunchKernelGGL(k_calib, dim3(gblocks(n, 256)), dim3(256), 0, s, x6, (long long)ld, (int)n, mo->yinf, mo->scal,
-                     y5_exact, status_exact, (float)d.r1, (float)d.r2, mo->cal, mo->cal + NCELLS);
+                     y5_exact, status_exact, hres_exact, (float)gate->unresolved, (float)d.r1, (float)d.r2,
+                     mo->cal, mo->cal + NCELLS);
   std::vector<unsigned int> h(2 * NCELLS);
   if (hipMemcpyAsync(h.data(), mo->cal, sizeof(unsigned int) * 2 * NCELLS, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
@@ -1490,7 +1532,7 @@ int rt_surrogate_infer(rt_model mo, const rt_cloak *cloaks, int32_t n_cloaks, co
   e = launch_err("surrogate launch");
   if (e) return e;
   // the exact integrator traces the rejected rays (one persistent launch)
-  e = rt_transit_exact(cloaks, n_cloaks, opts, n, ld, x6, fallback, y5, status, nullptr, stream);
+  e = rt_transit_exact(cloaks, n_cloaks, opts, n, ld, x6, fallback, y5, status, nullptr, nullptr, stream);
   return e;
 }
 
@@ -1504,7 +1546,7 @@ int rt_surrogate_save(rt_model mo, const char *path) {
     return fail(RT_E_DEVICE, "copy failed");
   FILE *f = fopen(path, "wb");
   if (!f) return fail(RT_E_INVALID, "cannot open %s", path);
-  const char magic[8] = {'R', 'T', 'M', 'L', 'P', '0', '2', '\0'};
+  const char magic[8] = {'R', 'T', 'M', 'L', 'P', '0', '3', '\0'};
   const long long np = NPARAM, nc = NCELLS;
   const int valid = mo->map_valid;
   bool ok = fwrite(magic, 1, 8, f) == 8 && fwrite(&np, sizeof(np), 1, f) == 1 &&
@@ -1528,7 +1570,7 @@ int rt_surrogate_load(const char *path, rt_model *out) {
   rt_gate_opts gate;
   std::vector<float> h(NPARAM);
   std::vector<unsigned char> map(NCELLS);
-  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "RTMLP02", 8) == 0 && fread(&np, sizeof(np), 1, f) == 1 &&
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "RTMLP03", 8) == 0 && fread(&np, sizeof(np), 1, f) == 1 &&
             np == NPARAM && fread(scal, sizeof(float), S_LOSS, f) == (size_t)S_LOSS &&
             fread(h.data(), sizeof(float), NPARAM, f) == (size_t)NPARAM && fread(&nc, sizeof(nc), 1, f) == 1 &&
             nc == NCELLS && fread(&valid, sizeof(valid), 1, f) == 1 && fread(&gate, sizeof(gate), 1, f) == 1 &&

@@ -76,7 +76,7 @@ class TrainOpts(ctypes.Structure):
 class GateOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("hres_max", ctypes.c_double),
                 ("cap_margin", ctypes.c_double), ("min_count", ctypes.c_int32),
-                ("dilate", ctypes.c_int32)]
+                ("dilate", ctypes.c_int32), ("unresolved", ctypes.c_double)]
 
 
 class RenderAux(ctypes.Structure):
@@ -117,7 +117,7 @@ def lib():
         L.rt_last_error.restype = ctypes.c_char_p
         L.rt_cloak_get_desc.argtypes = [vp, ctypes.POINTER(CloakDesc)]
         L.rt_transit_exact.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(TraceOpts), i64, i64,
-                                       vp, vp, vp, vp, vp, vp]
+                                       vp, vp, vp, vp, vp, vp, vp]
         L.rt_surrogate_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(vp)]
         L.rt_surrogate_free.argtypes = [vp]
         L.rt_surrogate_nparams.argtypes = [ctypes.POINTER(i64)]
@@ -130,7 +130,7 @@ def lib():
         L.rt_surrogate_grad.argtypes = [vp, i64, i64, vp, vp, vp, ctypes.c_float, vp, vp, vp]
         L.rt_surrogate_train.argtypes = [vp, i64, i64, vp, vp, vp, ctypes.POINTER(TrainOpts), vp, vp]
         L.rt_surrogate_forward.argtypes = [vp, i64, i64, vp, vp, vp]
-        L.rt_surrogate_calibrate.argtypes = [vp, ctypes.POINTER(vp), i32, i64, i64, vp, vp, vp,
+        L.rt_surrogate_calibrate.argtypes = [vp, ctypes.POINTER(vp), i32, i64, i64, vp, vp, vp, vp,
                                              ctypes.POINTER(GateOpts), ctypes.POINTER(ctypes.c_double),
                                              vp]
         L.rt_surrogate_get_map.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -402,9 +402,10 @@ def _check_soa(x, rows, dtype):
     return x.stride(0)
 
 
-def transit_exact(cloaks: list, opts: dict, x6, mask=None, y5=None, status=None, nsteps=False):
+def transit_exact(cloaks: list, opts: dict, x6, mask=None, y5=None, status=None, nsteps=False, hres=False):
     """rt_transit_exact on float32 CUDA x6 (6, n) (entry phi, z, alpha, beta,
-    branch bit, axis bit). Returns (y5 (5, n) float32, status int32[, nsteps])."""
+    branch bit, axis bit). Returns (y5 (5, n) float32, status int32), then
+    hres float32 (|H - 1| at the exit) if hres, then nsteps int32 if nsteps."""
     import torch
     ld = _check_soa(x6, 6, torch.float32)
     n = x6.shape[1]
@@ -414,10 +415,16 @@ def transit_exact(cloaks: list, opts: dict, x6, mask=None, y5=None, status=None,
     if status is None:
         status = torch.empty(n, dtype=torch.int32, device=dev)
     assert y5.stride(0) == ld and y5.stride(1) == 1
+    hr = torch.empty(n, dtype=torch.float32, device=dev) if hres else None
     ns = torch.empty(n, dtype=torch.int32, device=dev) if nsteps else None
     _check(lib().rt_transit_exact(_handles(cloaks), len(cloaks), ctypes.byref(trace_opts(opts)), n, ld,
-                                  _ptr(x6), _ptr(mask), _ptr(y5), _ptr(status), _ptr(ns), _stream()))
-    return (y5, status, ns) if nsteps else (y5, status)
+                                  _ptr(x6), _ptr(mask), _ptr(y5), _ptr(status), _ptr(hr), _ptr(ns), _stream()))
+    out = (y5, status)
+    if hres:
+        out += (hr,)
+    if nsteps:
+        out += (ns,)
+    return out
 
 
 def surrogate_encode(cloaks: list, x6, y5, status):
@@ -509,13 +516,13 @@ class Surrogate:
         return t5
 
     def calibrate(self, cloaks, x6, y5_exact, status_exact, tol=1e-3, hres_max=1e-4,
-                  cap_margin=1e-2, min_count=8, dilate=0) -> float:
+                  cap_margin=1e-2, min_count=8, dilate=0, hres_exact=None, unresolved=1e-6) -> float:
         import torch
         ld = _check_soa(x6, 6, torch.float32)
-        g = GateOpts(tol, hres_max, cap_margin, min_count, dilate)
+        g = GateOpts(tol, hres_max, cap_margin, min_count, dilate, unresolved)
         frac = ctypes.c_double()
         _check(lib().rt_surrogate_calibrate(self.handle, _handles(cloaks), len(cloaks), x6.shape[1], ld,
-                                            _ptr(x6), _ptr(y5_exact), _ptr(status_exact),
+                                            _ptr(x6), _ptr(y5_exact), _ptr(status_exact), _ptr(hres_exact),
                                             ctypes.byref(g), ctypes.byref(frac), _stream()))
         return frac.value
 

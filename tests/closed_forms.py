@@ -185,6 +185,50 @@ def cf4_quadrature(axis, branch, o, d, a=1.0, b=2.0):
     return pe, exit_direction(pe, kt, kz), s_in + T
 
 
+def _asinh_ratio(x):
+    """asinh(sqrt(x))/sqrt(x) for x >= 0 and asin(sqrt(-x))/sqrt(-x) for
+    x < 0: one analytic function of x, 1 - x/6 + 3x^2/40 - ... near 0."""
+    if abs(x) < 1e-6:
+        return 1.0 - x / 6.0
+    if x > 0.0:
+        return math.asinh(math.sqrt(x)) / math.sqrt(x)
+    return math.asin(math.sqrt(-x)) / math.sqrt(-x)
+
+
+def cf4_elementary(axis, kt, kz, a=1.0, b=2.0):
+    """The integrable 3-D cases in closed form: (dtheta, dz, T) of the
+    side-to-side transit of the infinite cylinder for an entry with
+    tangential wave numbers (k_theta, k_z) on r = b.
+
+    With m_theta = m_z = kappa s in both cases, H = 1 gives
+    m_r rdot^2 = Q(r) / (kappa (r - a)^2) with the quadratic
+    Q(r) = kappa (r - a)^2 - p^2 - k_z^2 r^2 (p = b k_theta), Q(b) =
+    b^2 k_n^2 since kappa (b - a)^2 = b^2. The turning point is the larger
+    root of Q. Per unit r:
+      radial e    (m_r = kappa):   dtheta = p / (u sqrt Q),
+                  dz = k_z r^2 / (u sqrt Q), dt = kappa u / sqrt Q, u = r - a;
+      azimuthal o (m_r = kappa s): dtheta = p / (r sqrt Q),
+                  dz = k_z r / sqrt Q, dt = kappa u^2 / (r sqrt Q).
+    Each integrand is a combination of 1/sqrt Q, x/sqrt Q and 1/(x sqrt Q)
+    for a quadratic Q in x, whose integrals from a root are elementary."""
+    k = kappa(a, b)
+    p = b * kt
+    A = k - kz * kz                      # leading coefficient of Q
+    S = math.sqrt(A * p * p + k * kz * kz * a * a)   # sqrt(discriminant) / 2
+    Qb = b * b * max(0.0, 1.0 - kt * kt - kz * kz)
+    sq = math.sqrt(Qb)
+    J0 = math.asinh(math.sqrt(A * Qb) / S) / math.sqrt(A)     # int dx / sqrt Q
+    if axis == RADIAL:   # in u = r - a: Q = A u^2 - 2 a k_z^2 u - (p^2 + k_z^2 a^2)
+        mC = p * p + kz * kz * a * a
+        J1 = sq / A + a * kz * kz / A * J0                      # int u du / sqrt Q
+        Jm = math.atan2(math.sqrt(mC) * sq, a * kz * kz * (b - a) + mC) / math.sqrt(mC)
+        return 2.0 * p * Jm, 2.0 * kz * (J1 + 2.0 * a * J0 + a * a * Jm), 2.0 * k * J1
+    C = k * a * a - p * p  # in r: Q = A r^2 - 2 kappa a r + C
+    J1 = sq / A + k * a / A * J0                                # int r dr / sqrt Q
+    Jm = sq / (b * S) * _asinh_ratio(C * Qb / (b * b * S * S))  # int dr / (r sqrt Q)
+    return 2.0 * p * Jm, 2.0 * kz * J1, 2.0 * k * (J1 - 2.0 * a * J0 + a * a * Jm)
+
+
 def aimed_rays(n, seed, r_start=3.0, b=2.0, min_tangential=0.25, elev=True, min_ktheta=0.0):
     """Vacuum rays from r = r_start that hit the side of the infinite cylinder
     with tangential wave-vector (k_theta, k_z) of norm >= min_tangential

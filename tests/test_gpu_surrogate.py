@@ -181,15 +181,17 @@ def test_gradients_match_bf16_reference(masked, huber):
 
 
 def test_closed_form_baselines_match_the_exact_transit():
-    """The residual baselines (radial cloak ordinary branch: homogeneous
-    index sqrt(kappa) with the mirror; azimuthal cloak extraordinary branch:
-    straight line in (sqrt(kappa)(r - a), theta, sqrt(kappa) z)) are exact
-    transits: a network with zero output decodes to them, and they match the
-    integrator's exits, and the encoded targets of exact transits vanish, to
-    float32 resolution. The other two branches have no baseline. This
-    includes the radial-o rays whose chord only just dips into the metal
-    cylinder (near-grazing entries), which the integrator finds inside a
-    step by the chord's closest approach."""
+    """The residual baselines are exact transits of the infinite cylinder
+    for all four branches (radial cloak: homogeneous index sqrt(kappa) with
+    the mirror for the ordinary branch, the elementary quadrature for the
+    extraordinary one; azimuthal cloak: the elementary quadrature for the
+    ordinary branch, a straight line in (sqrt(kappa)(r - a), theta,
+    sqrt(kappa) z) for the extraordinary one): a network with zero output
+    decodes to them, they match the integrator's exits, and the encoded
+    targets of exact transits vanish, to float32 resolution. This includes
+    the radial-o rays whose chord only just dips into the metal cylinder
+    (near-grazing entries), which the integrator finds inside a step by the
+    chord's closest approach."""
     import torch
     from paper_1209_6038_amd import rt
     from paper_1209_6038_amd import surrogate as S
@@ -205,7 +207,7 @@ def test_closed_form_baselines_match_the_exact_transit():
     torch.cuda.synchronize()
     kind = (x[5] * 2 + x[4]).long()
     err, operr = S.exit_error(y_s, y_ex)
-    for k in (0, 3):
+    for k in range(4):
         sel = (kind == k) & (fb == 0) & (w > 0)
         assert sel.sum() > 4000
         e = S.summarize_errors(err, sel)
@@ -217,9 +219,6 @@ def test_closed_form_baselines_match_the_exact_transit():
         assert float(operr[sel].max()) < 1e-4
         for o in (0, 1, 4):
             assert float(t5[o][sel].abs().max()) < 1e-4, o
-    for k in (1, 2):
-        sel = (kind == k) & (w > 0)
-        assert float(t5[0][sel].abs().max()) > 0.5  # no baseline: the full sweep is the target
 
 
 def test_training_reduces_loss_and_save_load():
@@ -253,11 +252,14 @@ def test_training_reduces_loss_and_save_load():
 def test_surrogate_pipeline_small():
     """Small version of the surrogate workload: label entries with the exact
     transit, train briefly, calibrate the trust map on separate rays (about
-    30 per cell), then infer on held-out rays. The calibration bound is
-    empirical (a cell is judged on its calibration rays, and thin
-    discontinuity curves of the transit can cross a cell between them), so
-    accepted held-out rays are checked at p99 <= tol with at most 0.5% over
-    tol; rejected rays must carry exactly the exact transit's result."""
+    30 per cell) at half the tolerance, then infer on held-out rays. The
+    integrator is the judge only where it resolves the path: exits whose
+    Hamiltonian drift |H - 1| exceeds 1e-6 (entries with p_theta -> 0 that
+    pass next to the singular r = a) are no reference, in calibration and
+    here. The calibration bound is empirical (a cell is judged on its
+    calibration rays), so accepted held-out rays with a resolved reference
+    are checked at p99 and with at most 1e-4 of them over tol; rejected rays
+    must carry exactly the exact transit's result."""
     import torch
     from paper_1209_6038_amd import rt
     from paper_1209_6038_amd import surrogate as S
@@ -270,17 +272,18 @@ def test_surrogate_pipeline_small():
     last = S.train(m, x_tr, t_tr, w_tr, steps=3000, batch=8192, lr=2e-3, huber=0.01)
     say(f"train loss {last:.3e}")
     x_cal = S.features(2_000_000, seed=202)
-    y_cal, st_cal, _, _ = S.label(cloaks, x_cal, opts)
-    tol = 5e-2
-    frac = m.calibrate(cloaks, x_cal, y_cal, st_cal, tol=tol, min_count=16, dilate=1)
-    say(f"trusted cells {frac:.3f}")
+    y_cal, st_cal, h_cal = rt.transit_exact(cloaks, opts, x_cal, hres=True)
+    tol = 1e-3
+    frac = m.calibrate(cloaks, x_cal, y_cal, st_cal, tol=0.5 * tol, min_count=16, dilate=1,
+                       hres_exact=h_cal, unresolved=1e-6)
+    say(f"trusted cells {frac:.4f}")
     x_ev = S.features(200_000, seed=303)
-    y_ex, st_ex = rt.transit_exact(cloaks, opts, x_ev)
+    y_ex, st_ex, h_ex = rt.transit_exact(cloaks, opts, x_ev, hres=True)
     y_s, st_s, fb = m.infer(cloaks, opts, x_ev)
     torch.cuda.synchronize()
     acc = fb == 0
-    say(f"accepted {acc.float().mean().item():.3f}")
-    assert acc.float().mean().item() > 0.5
+    say(f"accepted {acc.float().mean().item():.4f}")
+    assert acc.float().mean().item() > 0.95
     err, _ = S.exit_error(y_s, y_ex)
     # an accepted ray the integrator did not carry across: a ray aimed at
     # the axis (p_theta ~ 0) that the integrator brings to the singular
@@ -290,12 +293,16 @@ def test_surrogate_pipeline_small():
     say(f"accepted but not exited by the integrator: {int(odd.sum())}, statuses "
         f"{torch.bincount(st_ex[odd].long(), minlength=8).tolist()}")
     assert int(odd.sum()) <= max(1, int(1e-4 * int(acc.sum())))
-    acc = acc & (st_ex == 0)
+    resolved = (st_ex == 0) & (h_ex <= 1e-6)
+    unres = acc & (st_ex == 0) & ~resolved
+    say(f"accepted with an unresolved reference: {int(unres.sum())}"
+        + (f", their max difference {float(err[unres].max()):.2e}" if bool(unres.any()) else ""))
+    acc = acc & resolved
     e = S.summarize_errors(err, acc)
-    say(f"accepted exit error {e}")
+    say(f"accepted exit error (resolved references) {e}")
     over = float((err[acc] > tol).float().mean())
     say(f"accepted over tol: {over:.2e}")
-    assert e["p99"] <= tol and over <= 5e-3
+    assert e["p99"] <= 1e-5 and over <= 1e-4
     rej = fb == 1
     assert torch.equal(st_s[rej], st_ex[rej])
     assert torch.equal(torch.nan_to_num(y_s[:, rej]), torch.nan_to_num(y_ex[:, rej]))

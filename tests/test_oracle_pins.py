@@ -381,6 +381,34 @@ def test_integrable_3d_cases_match_quadrature(axis, branch):
         assert r["hres"][i] < 1e-9
 
 
+@pytest.mark.parametrize("axis,branch", [(0, 1), (1, 0)])
+@pytest.mark.parametrize("a,b", [(1.0, 2.0), (1.0, 3.0), (1.0, 1.5)])
+def test_integrable_3d_cases_elementary_form(axis, branch, a, b):
+    """The elementary antiderivatives (which the surrogate's closed-form
+    baselines use) equal the numerical quadrature, for cloaks where the
+    constant term of the azimuthal-ordinary quadratic is positive (b < 2a),
+    zero at grazing (b = 2a) and negative (b > 2a); in the plane the
+    radial-cloak extraordinary transit is the undeviated chord."""
+    rng = np.random.default_rng(int(7 * b))
+    for _ in range(12):
+        phi, rr, pp = rng.uniform(0, 2 * math.pi), rng.uniform(0, 0.95 * b), rng.uniform(0, 2 * math.pi)
+        o = np.array([(b + 1) * math.cos(phi), (b + 1) * math.sin(phi), 0.3])
+        d = np.array([rr * math.cos(pp), rr * math.sin(pp), rng.uniform(-1, 1)]) - o
+        d /= np.linalg.norm(d)
+        s_in, p, rh, th, (kn, kt, kz) = CF.side_entry(o, d, b)
+        pe, de, opl = CF.cf4_quadrature(axis, branch, o, d, a=a, b=b)
+        dth, dz, T = CF.cf4_elementary(axis, kt, kz, a=a, b=b)
+        th0 = math.atan2(p[1], p[0])
+        np.testing.assert_allclose([b * math.cos(th0 + dth), b * math.sin(th0 + dth), p[2] + dz], pe, atol=1e-9)
+        assert s_in + T == pytest.approx(opl, abs=1e-9)
+    if axis == 0:
+        for al in (0.05, 0.7, 1.4):
+            dth, dz, T = CF.cf4_elementary(0, math.sin(al), 0.0, a=a, b=b)
+            assert dth == pytest.approx(math.pi - 2 * al, abs=1e-12)
+            assert T == pytest.approx(2 * b * math.cos(al), abs=1e-12)
+            assert dz == 0.0
+
+
 def test_which_rays_reach_the_metal_cylinder():
     """Sect. 4: in the radial cloak all ordinary rays reach the inner metal
     cylinder and no extraordinary ray does; in the azimuthal cloak no ray does.
