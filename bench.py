@@ -123,7 +123,73 @@ def cpu_baseline(opts, cams, stride, entered_only=True):
             "all_rays_per_s": n_rays / dt}
 
 
-def surrogate_leg(steps: int, n_train: int, log):
+def surrogate_render_leg(model, log, n_frames: int = 4, fpl: int = 2, difficulties=(0, 2, 3, 4)):
+    """The large render (4096^2 px x 4 jittered spp, radial + azimuthal
+    cloaks, both branches) of n_frames frames of the 36-frame orbit at 30 deg,
+    fpl frames per launch, plain (rt_render_multi) and with the surrogate
+    (rt_render_surrogate) for each threshold of difficulty (side entries of
+    at least that difficulty bucket go to the network): time per frame, share
+    of the offered side entries the gate accepts, and the image difference."""
+    import torch
+    from paper_1209_6038_amd import rt
+    from paper_1209_6038_amd import workloads as W
+    frames = W.orbit_frames(36, 4096, 4)[:: 36 // n_frames][:n_frames]
+    groups = [frames[i:i + fpl] for i in range(0, len(frames), fpl)]
+    opts = W.render_opts(max_chunk=fpl * 4096 * 4096 * 4)
+    cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
+    room = W.room()
+    dev = torch.device("cuda", 0)
+    out_p = torch.empty((len(groups), 2, fpl, 2, 4096, 4096, 3), dtype=torch.float32, device=dev)
+    out_s = torch.empty_like(out_p)
+
+    def timed(fn):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for k, g in enumerate(groups):
+            fn(k, g)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / len(frames)
+
+    def plain(k, g):
+        rt.render_multi(cloaks, opts, room, g, 3, out=out_p[k, :, :len(g)])
+
+    for k, g in enumerate(groups):  # warm-up
+        plain(k, g)
+    ms_p = timed(plain)
+    sweep = []
+    for dmin in difficulties:
+        offered = accepted = 0
+        for k, g in enumerate(groups):  # untimed pass: counts
+            _, (c0, c1) = rt.render_surrogate(model, cloaks, opts, room, g, 3, out=out_s[k, :, :len(g)],
+                                              counts=True, min_difficulty=dmin)
+            offered += c0
+            accepted += c1
+        torch.cuda.synchronize()
+        d = (out_s - out_p).abs().amax(dim=-1)
+        over = float((d > 1.0 / 255.0).float().mean())
+        dmax = float(d.max())
+        del d
+        ms_s = timed(lambda k, g: rt.render_surrogate(model, cloaks, opts, room, g, 3, out=out_s[k, :, :len(g)],
+                                                      min_difficulty=dmin))
+        log(f"surrogate render, min difficulty {dmin}: {ms_s:.1f} ms/frame (plain {ms_p:.1f}), "
+            f"accepted {accepted}/{offered} offered side entries, pixels over 1/255: {over:.2e}")
+        sweep.append({"min_difficulty": dmin, "surrogate_ms_per_frame": round(ms_s, 2),
+                      "speedup": round(ms_p / ms_s, 3), "offered_per_frame": offered // len(frames),
+                      "accepted_per_frame": accepted // len(frames),
+                      "pixels_over_1_255": over, "max_pixel_difference": round(dmax, 4)})
+    del out_p, out_s
+    best = max(sweep, key=lambda r: r["speedup"])
+    return {
+        "workload": (f"{len(frames)} frames of the 36-frame orbit at 30 deg elevation, 4096^2 px x 4 jittered spp, "
+                     f"radial + azimuthal cloaks (height 4), ordinary + extraordinary, {fpl} frames per launch"),
+        "plain_ms_per_frame": round(ms_p, 2), "speedup": best["speedup"], "best": best, "sweep": sweep,
+    }
+
+
+def surrogate_leg(steps: int, n_train: int, log, fpl: int = 2):
     """Train, calibrate and time the transit surrogate (see the module doc)."""
     import numpy as np
     import torch
@@ -212,7 +278,7 @@ def surrogate_leg(steps: int, n_train: int, log):
     ms_sur = timed(lambda: m.infer(cl, op, x_ev, y5=y_s, fallback=fb, status=st_s))
     ms_fwd = timed(lambda: m.forward(x_ev))
     mlp_tflops = MLP_MFMA_FLOPS * n / (ms_fwd * 1e-3) / 1e12
-    return {
+    rec = {
         "speedup": round(ms_plain / ms_sur, 3),
         "plain_Mrays_s": round(n / (ms_plain * 1e-3) / 1e6, 2),
         "surrogate_Mrays_s": round(n / (ms_sur * 1e-3) / 1e6, 2),
@@ -245,6 +311,9 @@ def surrogate_leg(steps: int, n_train: int, log):
                          "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(mlp_tflops / PEAK_BF16_TFLOPS, 4), "ms_per_1M_rays": round(ms_fwd, 4)},
     }
+    del x_ev, y_ex, st_ex, h_ex, y_s, st_s, fb, err, operr
+    rec["render"] = surrogate_render_leg(m, log, fpl=fpl)
+    return rec
 
 
 def inplane_workload(args):
@@ -300,36 +369,40 @@ def inplane_workload(args):
 def orbit_workload(args):
     """The large-render workload timed plain: 36-frame orbit at 30 deg
     elevation, 4096 x 4096 px, 4 jittered samples per pixel, radial and
-    azimuthal cloaks, both branches; one rt_render_multi call per frame."""
-    import numpy as np
+    azimuthal cloaks, both branches; `frames_per_launch` frames per
+    rt_render_multi call, one integrator launch each (a launch lasts at least
+    as long as its longest ray, so frames rendered together overlap one
+    frame's longest rays with the others' bulk)."""
     import torch
     from paper_1209_6038_amd import rt
     from paper_1209_6038_amd import workloads as W
 
+    fpl = args.frames_per_launch
     frames = W.orbit_frames(36, 4096, 4)
-    opts = W.render_opts()
+    groups = [frames[i:i + fpl] for i in range(0, len(frames), fpl)]
+    opts = W.render_opts(max_chunk=fpl * 4096 * 4096 * 4)
     cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
     room = W.room()
     dev = torch.device("cuda", 0)
-    out = torch.empty((2, 1, 2, 4096, 4096, 3), dtype=torch.float32, device=dev)
+    out = torch.empty((2, fpl, 2, 4096, 4096, 3), dtype=torch.float32, device=dev)
     # entering rays per frame (untimed counting pass, status only)
     # the orbit is symmetric up to the jitter: every 9th frame is counted
     entered = 0
     counted = frames[::9]
     for f in counted:
-        _, aux = rt.render_multi(cloaks, opts, room, [f], 3, aux=True)
+        _, aux = rt.render_multi(cloaks, W.render_opts(), room, [f], 3, aux=True)
         torch.cuda.synchronize()
         entered += int(torch.isin(aux["status"], torch.tensor([0, 2, 3, 4, 5], device=dev,
                                                                 dtype=torch.int32)).sum())
         del aux
     entered_per_frame = entered / len(counted)
-    rt.render_multi(cloaks, opts, room, [frames[0]], 3, out=out)
+    rt.render_multi(cloaks, opts, room, groups[0], 3, out=out[:, :len(groups[0])])
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record()
-    for f in frames:
-        rt.render_multi(cloaks, opts, room, [f], 3, out=out)
+    for g in groups:
+        rt.render_multi(cloaks, opts, room, g, 3, out=out[:, :len(g)])
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
@@ -341,6 +414,7 @@ def orbit_workload(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "large render: 36-frame orbit at 30 deg elevation, 4096^2 px x 4 jittered spp, "
                                "radial + azimuthal cloaks, ordinary + extraordinary, DP45 tol 1e-8, plain tracer",
+                   "frames_per_launch": fpl,
                    "ray_branch_samples": samples, "ms_per_frame": round(ms / 36, 2),
                    "all_samples_per_s_M": round(samples / (ms * 1e-3) / 1e6, 1),
                    "entered_per_frame_estimate": int(entered_per_frame),
@@ -354,6 +428,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--res", type=int, default=1024)
+    ap.add_argument("--frames-per-launch", type=int, default=2,
+                    help="orbit workload and surrogate render: 4096^2 x 4 spp frames per integrator launch (1-4)")
     ap.add_argument("--workload", choices=("render3d", "batched", "orbit", "surrogate", "inplane"),
                     default="render3d")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed")
@@ -367,6 +443,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
+    if not 1 <= args.frames_per_launch <= 4:
+        ap.error("--frames-per-launch must be in 1..4 (at most 2^28 samples per launch)")
     if args.copy_probe:
         copy_probe()
         return
@@ -395,7 +473,7 @@ def main():
     if args.workload == "surrogate":
         torch.cuda.set_device(0)
         rec = surrogate_leg(args.surrogate_steps, args.surrogate_train,
-                            lambda msg: print(msg, file=sys.stderr, flush=True))
+                            lambda msg: print(msg, file=sys.stderr, flush=True), args.frames_per_launch)
         print(json.dumps({"config": {"workload": "surrogate leg only"}, "surrogate": rec}), flush=True)
         return
     batched = args.workload == "batched"
@@ -512,7 +590,8 @@ def main():
         del out
         rt.release_workspace()
         rec["surrogate"] = surrogate_leg(args.surrogate_steps, args.surrogate_train,
-                                         lambda msg: print(msg, file=sys.stderr, flush=True))
+                                         lambda msg: print(msg, file=sys.stderr, flush=True),
+                                         args.frames_per_launch)
     print(json.dumps(rec), flush=True)
 
 

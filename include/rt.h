@@ -22,8 +22,9 @@
  *  - The library allocates a device workspace on first use and grows it when
  *    a larger call needs it (hipMalloc, synchronous); it is released by
  *    rt_release_workspace() or at process exit. Renders are processed in
- *    chunks of up to 2^26 camera samples, with a workspace of ~0.5 KB per
- *    sample of a chunk (~31 GB for a 4096 x 4096 x 4 spp view).
+ *    chunks of camera samples (2^26 unless max_chunk says otherwise, at most
+ *    2^28), with a workspace of ~0.5 KB per sample of a chunk (~31 GB for a
+ *    4096 x 4096 x 4 spp view).
  */
 #ifndef RT_H
 #define RT_H
@@ -81,8 +82,11 @@ typedef struct {
    ray. max_bounces: internal reflections (inner mirror, total internal
    reflection) per ray, 0..64. block / refill_period: integrator launch shape
    (threads per block, steps between refills of finished lanes; 0 = library
-   default). max_chunk: renders only, camera samples per integrator launch
-   (0 = 2^26; results do not depend on it). */
+   default). max_chunk: renders only, camera samples per integrator launch,
+   at most 2^28 (0 = 2^26; results do not depend on it). A launch lasts at
+   least as long as its longest ray (paths that pass close to r1 take tens of
+   thousands of attempts), so views rendered together in one launch overlap
+   one view's longest rays with the others' bulk. */
 typedef struct {
     int32_t scheme;
     int32_t precision;
@@ -350,6 +354,38 @@ int rt_surrogate_get_map(rt_model model, uint8_t *host, int32_t *cells_alpha, in
 int rt_surrogate_infer(rt_model model, const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts,
                        int64_t n, int64_t ld, const float *x6, float *y5, uint8_t *fallback, int32_t *status,
                        void *stream);
+/* Render as rt_render_multi, with the side-to-side transits taken from the
+   surrogate where its gate accepts them (not part of the paper): a camera
+   sample that refracts into the cloak through its side r = r2 with
+   difficulty >= min_difficulty is offered to the network, whose accepted
+   prediction gives the exit ray on r = r2 and, after its vacuum leg, the
+   sample's colour; rejected side entries, easier side entries and the
+   entries through the end caps are traced by the integrator, in one launch
+   per chunk. The difficulty is the integrator's ordering key: -log2 of the
+   conserved wave number p (p_theta / r2 for the azimuthal cloak's
+   extraordinary branch, |(p_theta / r2, p_z)| otherwise), as the bucket
+   floor(-log2 p) + 1 clamped to [0, 15], and 0 for the radial cloak's
+   ordinary branch; paths with small p pass close to r = r1, where the steps
+   shrink, so the bucket tracks the integration cost, while the network
+   costs the same for every ray. min_difficulty = 0 offers every side entry.
+   The exit error of an accepted ray is what the model's calibration bounds
+   (rt_surrogate_calibrate), so a sample's colour can differ from
+   rt_render_multi's where its room point lies that close to a tile edge.
+     model:  a calibrated model on the current device
+     min_difficulty: in [0, 16] (16 offers nothing)
+     counts: host int64[2] or NULL: side entries offered to the network and
+             entries whose prediction was accepted (summed over the chunks;
+             needs one more synchronization per chunk)
+   Synchronizes the stream once per chunk of samples (the network's launch
+   is sized by the number of side entries). Candidate rows take 61 bytes per
+   (sample, cloak, branch) of a chunk on top of rt_render_multi's workspace.
+   Errors: as rt_render_multi; RT_E_INVALID for a NULL model, n_cloaks < 1,
+   min_difficulty outside [0, 16] or an uncalibrated model. */
+int rt_render_surrogate(rt_model model, const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts,
+                        const rt_room *room, const rt_camera *cams, int32_t n_cams, int32_t pol_mask,
+                        int32_t min_difficulty, float *rgb, const rt_render_aux *aux, int64_t *counts,
+                        void *stream);
+
 /* Model file: parameters, scaling, gate and trust map. */
 int rt_surrogate_save(rt_model model, const char *path);
 int rt_surrogate_load(const char *path, rt_model *out);

@@ -28,6 +28,7 @@
 
 #include "../../include/rt.h"
 #include "device.h"
+#include "internal.h"
 
 using namespace rtk;
 
@@ -53,7 +54,9 @@ enum {
   C_FBASE = NSEG * C_LINE,   // C_FETCH(s): integrator work counter of segment s
   C_HBASE = 2 * NSEG * C_LINE,       // C_HIST(bin): slots per (segment, difficulty) key
   C_OBASE = C_HBASE + 64 * C_LINE,   // C_OFF(bin): scatter offset of the key
-  C_COUNT = C_OBASE + 64 * C_LINE
+  C_SUR = C_OBASE + 64 * C_LINE,     // surrogate render: side entries offered to the network
+  C_ACC = C_SUR + C_LINE,            // surrogate render: entries whose prediction was accepted
+  C_COUNT = C_ACC + C_LINE
 };
 constexpr int MAX_BOUNCES = 64;
 constexpr unsigned int FETCH_CHUNK = 64;  // rays claimed per wave per atomic
@@ -751,11 +754,24 @@ struct RenderP {
   int axis[2];        // optic axis of each cloak
   int pol[2];         // branch of each traced polarization
   int has_cloak, idx32;  // idx32: every flattened sample index < 2^32
+  int sur_min;           // surrogate render: side entries of difficulty bucket >= sur_min are candidates
   unsigned char *codes;  // chunk-local codes [segment][g1-g0]
   double *rec;           // aux (may be NULL)
   int *st;
   unsigned char *code;
   int *nsteps;
+};
+
+// Surrogate render: the side entries of a chunk that go to the network
+// first (candidates), one row each.
+struct CandP {
+  float *x6;          // SoA 6 x ld: phi, z, alpha, beta, branch bit, axis bit (the surrogate's inputs)
+  long long ld;       // rows allocated
+  long long *key;     // flattened sample index * NSEG + segment
+  float *s_in;        // vacuum distance from the eye to the entry
+  float *y5;          // SoA 5 x ld: predicted exit (phi', z', alpha', beta', T) of accepted rows
+  unsigned char *fb;  // 1 where the gate rejected the prediction
+  int *st;            // gate status (RT_RAY_EXITED where accepted)
 };
 
 // flattened sample index -> (camera, sample within the image), in 32-bit
@@ -792,9 +808,31 @@ __device__ __forceinline__ void rd_write(const RenderP &R, int q, long long gidx
   }
 }
 
-// camera rays of a chunk; one thread per sample, every (cloak, branch)
+// a side entry as surrogate input: azimuth and height of the entry point,
+// horizontal angle of the incident direction to the inward normal (positive
+// towards +theta), elevation, and the (branch, axis) bits of `kind`
+__device__ __forceinline__ void put_candidate(const CandP &C, unsigned int i, const double x[3], const double d[3],
+                                              int kind, long long gidx, int q, double s) {
+  double phi = atan2(x[1], x[0]);
+  if (phi < 0.0) phi += 2.0 * M_PI;
+  const double rl = rsq64(fma(x[0], x[0], x[1] * x[1]));
+  const double dr = (x[0] * d[0] + x[1] * d[1]) * rl, dt = (x[0] * d[1] - x[1] * d[0]) * rl;
+  float *X = C.x6 + i;
+  X[0] = (float)phi;
+  X[C.ld] = (float)x[2];
+  X[2 * C.ld] = (float)atan2(dt, -dr);
+  X[3 * C.ld] = (float)asin(fmin(1.0, fmax(-1.0, d[2])));
+  X[4 * C.ld] = (float)(kind & 1);
+  X[5 * C.ld] = (float)(kind >> 1);
+  C.key[i] = gidx * NSEG + q;
+  C.s_in[i] = (float)s;
+}
+
+// camera rays of a chunk; one thread per sample, every (cloak, branch).
+// SUR: side entries become surrogate candidates instead of work-table slots
+template <bool SUR>
 __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
-                                                const CamP *__restrict__ cams, Table T, RenderP R) {
+                                                const CamP *__restrict__ cams, Table T, RenderP R, CandP Cd) {
   long long gidx = R.g0 + (long long)blockIdx.x * blockDim.x + threadIdx.x;
   bool valid = gidx < R.g1;
   double org[3] = {0, 0, 0}, d[3] = {0, 0, 1}, x[3] = {0, 0, 0}, s = 0.0;
@@ -841,13 +879,15 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
   for (int q = 0; q < R.ncl * R.npol; ++q) {
     int ci = q / R.npol, pi = q - ci * R.npol;
     int kind = (ci == 0 ? R.axis[0] : R.axis[1]) * 2 + (pi == 0 ? R.pol[0] : R.pol[1]);
-    bool enter = false;
+    bool enter = false, cand = false;
     double v[3] = {0, 0, 0};
     if (valid) {
       if (!hitc || disk) {
         rd_write(R, q, gidx, vcode, vst, vp, vd, vL, 0);
       } else if (refract_in(c, kind, surf, x, d, v)) {
-        enter = true;
+        const int skey = sort_key(c, kind, x, d);
+        if (SUR && surf == B_SIDE && NBUCKET - 1 - skey >= R.sur_min) cand = true;
+        else enter = true;
       } else {
         // evanescent transmission into this branch: reflected at the entry
         double nrm[3], dd[3] = {d[0], d[1], d[2]}, sh;
@@ -859,7 +899,65 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
     }
     unsigned int sl = block_append(T.ctr + C_N(q), enter, sh);
     if (enter) put_slot(T, (int)(q * T.cap + sl), x, v, kind, gidx, s, o.h0, sort_key(c, kind, x, d));
+    if constexpr (SUR) {
+      const unsigned int ci2 = block_append(T.ctr + C_SUR, cand, sh);
+      if (cand) put_candidate(Cd, ci2, x, d, kind, gidx, q, s);
+    }
   }
+}
+
+// Surrogate render, after the gate: an accepted candidate's predicted exit
+// ray (on r = b, alpha' to the outward normal) takes its vacuum leg to the
+// room; a rejected one is generated again from its camera sample exactly as
+// k_rd_gen does and queued for the integrator in its segment.
+__global__ void __launch_bounds__(256) k_rd_sur_apply(CloakP c, OptsP o, RoomP rm, const CamP *__restrict__ cams,
+                                                      Table T, RenderP R, CandP Cd, unsigned int n) {
+  const unsigned int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  const long long key = valid ? Cd.key[i] : 0;
+  const int q = (int)(key & (NSEG - 1));
+  const long long gidx = key >> 2;
+  static_assert(NSEG == 4, "key packing assumes 4 segments");
+  const bool rej = valid && Cd.fb[i] != 0;
+  if (valid && !rej) {
+    const double ph = Cd.y5[i], ze = Cd.y5[Cd.ld + i], al = Cd.y5[2 * Cd.ld + i];
+    const double be = Cd.y5[3 * Cd.ld + i], Tt = Cd.y5[4 * Cd.ld + i];
+    const double cp = cos(ph), sp = sin(ph), cb = cos(be);
+    const double ca = cos(al), sa = sin(al);
+    double p[3] = {c.b * cp, c.b * sp, ze};
+    double dd[3] = {cb * (ca * cp - sa * sp), cb * (ca * sp + sa * cp), sin(be)};
+    double sh0;
+    const int code = room_code(rm, p, dd, sh0);
+    rd_write(R, q, gidx, code, RT_RAY_EXITED, p, dd, (double)Cd.s_in[i] + Tt + sh0, 0);
+  }
+  double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, d[3] = {0, 0, 1}, s = 0.0;
+  int kind = 0;
+  bool enter = false;
+  if (rej) {
+    long long cam, loc;
+    split_index(R, gidx, cam, loc);
+    const unsigned int l32 = (unsigned int)loc, sp32 = (unsigned int)R.spp;
+    const long long pix = l32 / sp32;
+    const int smp = (int)(l32 - (unsigned int)pix * sp32);
+    const CamP &C = cams[cam];
+    const double org[3] = {C.eye[0], C.eye[1], C.eye[2]};
+    camera_ray(C, (int)cam, pix, smp, d);
+    int surf = 0;
+    const bool hitc = vacuum_entry(c, org, d, s, surf);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) x[j] = fma(s, d[j], org[j]);
+    const int ci = q / R.npol, pi = q - ci * R.npol;
+    kind = (ci == 0 ? R.axis[0] : R.axis[1]) * 2 + (pi == 0 ? R.pol[0] : R.pol[1]);
+    enter = hitc && surf == B_SIDE && refract_in(c, kind, surf, x, d, v);
+    if (!enter) rd_write(R, q, gidx, 12, RT_RAY_INVALID, x, d, s, 0);  // not reached: k_rd_gen made it a candidate
+  }
+  __shared__ unsigned int sh[16];
+  for (int qq = 0; qq < R.ncl * R.npol; ++qq) {
+    const bool put = enter && q == qq;
+    const unsigned int sl = block_append(T.ctr + C_N(qq), put, sh);
+    if (put) put_slot(T, (int)(qq * T.cap + sl), x, v, kind, gidx, s, o.h0, sort_key(c, kind, x, d));
+  }
+  (void)block_append(T.ctr + C_ACC, valid && !rej, sh);
 }
 
 __global__ void __launch_bounds__(256) k_rd_finish(RoomP rm, Table T, RenderP R) {
@@ -1102,7 +1200,7 @@ int check_opts(const rt_trace_opts *o, double r2, bool need_rout) {
     return fail(RT_E_INVALID, "block must be 0 or a multiple of 64 in [64, 256]");
   if (o->refill_period < 0 || o->refill_period > 1024)
     return fail(RT_E_INVALID, "refill_period must be in [0, 1024]");
-  if (o->max_chunk < 0 || o->max_chunk > (1 << 26)) return fail(RT_E_INVALID, "max_chunk must be in [0, 2^26]");
+  if (o->max_chunk < 0 || o->max_chunk > (1 << 28)) return fail(RT_E_INVALID, "max_chunk must be in [0, 2^28]");
   return RT_OK;
 }
 
@@ -1322,8 +1420,8 @@ void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStre
     R.g0 = g0;
     R.g1 = std::min(J.total, g0 + J.chunk);
     hipLaunchKernelGGL(k_zero, dim3((C_COUNT + 255) / 256), dim3(256), 0, s, T.ctr, (int)C_COUNT);
-    hipLaunchKernelGGL(k_rd_gen, dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
-                       ws.cams, T, R);
+    hipLaunchKernelGGL(k_rd_gen<false>, dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
+                       ws.cams, T, R, CandP{});
     if (J.n_cloaks) {
       if (J.o.precision == RT_PREC_MIXED)
         run_transit<true>(J.c, J.o, T, J.block, J.refill, J.grid, s, profile);
@@ -1335,6 +1433,98 @@ void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStre
     hipLaunchKernelGGL(k_rd_resolve, dim3(grid_for(nres, 256)), dim3(256), 0, s, R, ws.table, rgb,
                        J.npix);
   }
+}
+
+// candidate rows of the surrogate render (grows, never shrinks)
+struct CandWs {
+  void *base = nullptr;
+  long long cap = 0;
+  int device = -1;
+  CandP P{};
+};
+CandWs g_cws;
+
+int cws_reserve(CandWs &w, long long cap) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(RT_E_DEVICE, "hipGetDevice failed");
+  if (w.base && w.device == dev && w.cap >= cap) return RT_OK;
+  if (w.base) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(w.base);
+    w = CandWs{};
+  }
+  cap = std::max(cap, 1024LL);
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t o = off; off = align_up(off + b); return o; };
+  const size_t o_x = take(sizeof(float) * 6 * cap), o_k = take(sizeof(long long) * cap);
+  const size_t o_s = take(sizeof(float) * cap), o_y = take(sizeof(float) * 5 * cap);
+  const size_t o_f = take((size_t)cap), o_t = take(sizeof(int) * cap);
+  void *p = nullptr;
+  if (hipMalloc(&p, off) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(RT_E_NOMEM, "hipMalloc of %zu bytes for the surrogate candidates failed", off);
+  }
+  char *b = (char *)p;
+  w.base = p;
+  w.cap = cap;
+  w.device = dev;
+  w.P.x6 = (float *)(b + o_x);
+  w.P.ld = cap;
+  w.P.key = (long long *)(b + o_k);
+  w.P.s_in = (float *)(b + o_s);
+  w.P.y5 = (float *)(b + o_y);
+  w.P.fb = (unsigned char *)(b + o_f);
+  w.P.st = (int *)(b + o_t);
+  return RT_OK;
+}
+
+// One render with the surrogate: per chunk, generation (side entries become
+// candidates), the network and its gate on the candidates, shading of the
+// accepted ones and re-queueing of the rejected ones, then the integrator
+// on the cap entries and the rejected side entries, shading and resolve as
+// in enqueue_render. The candidate count is read back once per chunk (the
+// network's launch is sized by it). counts[0] += candidates, counts[1] +=
+// accepted.
+int render_surrogate(rt_model model, const rt_cloak_desc &desc, const RenderJob &J, const Workspace &ws,
+                     const CandWs &cw, int min_difficulty, float *rgb, hipStream_t s, long long counts[2]) {
+  const Table &T = ws.T;
+  RenderP R = J.R;
+  R.sur_min = min_difficulty;
+  R.codes = ws.codes;
+  for (long long g0 = 0; g0 < J.total; g0 += J.chunk) {
+    R.g0 = g0;
+    R.g1 = std::min(J.total, g0 + J.chunk);
+    hipLaunchKernelGGL(k_zero, dim3((C_COUNT + 255) / 256), dim3(256), 0, s, T.ctr, (int)C_COUNT);
+    hipLaunchKernelGGL(k_rd_gen<true>, dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
+                       ws.cams, T, R, cw.P);
+    unsigned int nc = 0;
+    if (hipMemcpyAsync(&nc, T.ctr + C_SUR, sizeof(nc), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(RT_E_DEVICE, "surrogate render: candidate count read-back failed");
+    if ((long long)nc > cw.cap) return fail(RT_E_DEVICE, "surrogate render: candidate overflow");
+    if (nc > 0) {
+      int e = surrogate_predict_gated(model, desc, nc, cw.P.ld, cw.P.x6, cw.P.y5, cw.P.fb, cw.P.st, s);
+      if (e) return e;
+      hipLaunchKernelGGL(k_rd_sur_apply, dim3(grid_for(nc, 256)), dim3(256), 0, s, J.c, J.o, J.rm, ws.cams, T, R,
+                         cw.P, nc);
+    }
+    if (J.o.precision == RT_PREC_MIXED)
+      run_transit<true>(J.c, J.o, T, J.block, J.refill, J.grid, s, true);
+    else
+      run_transit<false>(J.c, J.o, T, J.block, J.refill, J.grid, s, true);
+    hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, J.rm, T, R);
+    long long nres = (R.g1 - R.g0) / R.spp * R.ncl * R.npol;
+    hipLaunchKernelGGL(k_rd_resolve, dim3(grid_for(nres, 256)), dim3(256), 0, s, R, ws.table, rgb, J.npix);
+    if (counts) {
+      unsigned int na = 0;
+      if (hipMemcpyAsync(&na, T.ctr + C_ACC, sizeof(na), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return fail(RT_E_DEVICE, "surrogate render: accepted count read-back failed");
+      counts[0] += nc;
+      counts[1] += na;
+    }
+  }
+  return RT_OK;
 }
 
 }  // namespace
@@ -1402,6 +1592,11 @@ int rt_profile_read(double *transit_ms, int64_t *launches) {
 int rt_release_workspace(void) {
   std::lock_guard<std::mutex> lk(g_ws_mu);
   ws_free(g_ws);
+  if (g_cws.base) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g_cws.base);
+    g_cws = CandWs{};
+  }
   return RT_OK;
 }
 
@@ -1502,6 +1697,34 @@ int rt_render_multi(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opt
   if (e) return e;
   enqueue_render(J, g_ws, rgb, s, true);
   return launch_err("render launch");
+}
+
+int rt_render_surrogate(rt_model model, const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts,
+                        const rt_room *room, const rt_camera *cams, int32_t n_cams, int32_t pol_mask,
+                        int32_t min_difficulty, float *rgb, const rt_render_aux *aux, int64_t *counts,
+                        void *stream) {
+  if (!model) return fail(RT_E_INVALID, "model is NULL");
+  if (min_difficulty < 0 || min_difficulty > NBUCKET)
+    return fail(RT_E_INVALID, "min_difficulty must be in [0, %d]", NBUCKET);
+  if (n_cloaks < 1) return fail(RT_E_INVALID, "the surrogate render needs at least one cloak");
+  if (!rgb) return fail(RT_E_INVALID, "rgb is required");
+  int e = surrogate_check_ready(model);
+  if (e) return e;
+  RenderJob J;
+  e = prepare_render(cloaks, n_cloaks, opts, room, cams, n_cams, pol_mask, aux, J);
+  if (e) return e;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  e = ws_reserve_for(g_ws, J);
+  if (!e) e = cws_reserve(g_cws, J.chunk * J.R.ncl * J.R.npol);
+  if (e) return e;
+  e = upload_job(J, g_ws, s);
+  if (e) return e;
+  long long c2[2] = {0, 0};
+  e = render_surrogate(model, cloaks[0]->d, J, g_ws, g_cws, min_difficulty, rgb, s, counts ? c2 : nullptr);
+  if (e) return e;
+  if (counts) { counts[0] = c2[0]; counts[1] = c2[1]; }
+  return launch_err("surrogate render launch");
 }
 
 int rt_render(rt_cloak cloak, const rt_trace_opts *opts, const rt_room *room, const rt_camera *cams,

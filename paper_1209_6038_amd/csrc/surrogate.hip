@@ -29,6 +29,7 @@
 #include <vector>
 
 #include "../../include/rt.h"
+#include "internal.h"
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -1205,6 +1206,46 @@ int launch_err(const char *what) {
 
 }  // namespace
 
+int surrogate_check_ready(rt_model mo) {
+  int e = check_model(mo);
+  if (e) return e;
+  if (!mo->map_valid) return fail(RT_E_INVALID, "the model has no calibrated trust map (rt_surrogate_calibrate)");
+  return RT_OK;
+}
+
+int surrogate_predict_gated(rt_model mo, const rt_cloak_desc &d, int64_t n, int64_t ld, const float *x6, float *y5,
+                            uint8_t *fallback, int32_t *status, hipStream_t s) {
+  int e = surrogate_check_ready(mo);
+  if (e) return e;
+  if (n == 0) return RT_OK;
+  if (n < 0 || ld < n || !x6 || !y5 || !fallback || !status)
+    return fail(RT_E_INVALID, "bad rows for the surrogate (n, ld or a NULL array)");
+  GateP gp;
+  gp.a = (float)d.r1;
+  gp.b = (float)d.r2;
+  gp.z0 = std::isfinite(d.z0) ? (float)d.z0 : -INFINITY;
+  gp.z1 = std::isfinite(d.z1) ? (float)d.z1 : INFINITY;
+  gp.hres_max = (float)mo->gate.hres_max;
+  gp.cap_margin = (float)mo->gate.cap_margin;
+  const long long batch = std::min<long long>(n, 1LL << 24);
+  e = reserve_yinf(mo, batch);
+  if (e) return e;
+  for (long long off = 0; off < n; off += batch) {
+    const int m = (int)std::min<long long>(batch, n - off);
+    const float *x = x6 + off;
+    // trusted entries only go through the network (compacted), then the
+    // output half of the gate
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, mo->count, 1LL);
+    hipLaunchKernelGGL(k_pregate, dim3(gblocks(m, 256)), dim3(256), 0, s, x, (long long)ld, m, mo->map, gp,
+                       fallback + off, mo->idx, mo->count);
+    hipLaunchKernelGGL(k_mlp_fused, dim3(gblocks(m, FR)), dim3(256), 0, s, x, (long long)ld, m, mo->idx, mo->count,
+                       mo->P, mo->Pb, mo->scal, mo->yinf);
+    hipLaunchKernelGGL(k_gate_idx, dim3(gblocks(m, 256)), dim3(256), 0, s, x, (long long)ld, mo->idx, mo->count,
+                       mo->yinf, mo->scal, mo->map, gp, y5 + off, fallback + off, status + off);
+  }
+  return launch_err("surrogate launch");
+}
+
 extern "C" {
 
 int rt_surrogate_create(uint64_t seed, rt_model *out) {
@@ -1509,31 +1550,10 @@ int rt_surrogate_infer(rt_model mo, const rt_cloak *cloaks, int32_t n_cloaks, co
   e = check_rows(n, ld, x6);
   if (e) return e;
   if (!y5 || !fallback || !status) return fail(RT_E_INVALID, "y5, fallback and status are required");
-  if (!mo->map_valid) return fail(RT_E_INVALID, "the model has no calibrated trust map (rt_surrogate_calibrate)");
-  hipStream_t s = (hipStream_t)stream;
-  GateP gp;
-  gp.a = (float)d.r1;
-  gp.b = (float)d.r2;
-  gp.z0 = std::isfinite(d.z0) ? (float)d.z0 : -INFINITY;
-  gp.z1 = std::isfinite(d.z1) ? (float)d.z1 : INFINITY;
-  gp.hres_max = (float)mo->gate.hres_max;
-  gp.cap_margin = (float)mo->gate.cap_margin;
-  e = reserve_yinf(mo, n);
-  if (e) return e;
-  // trusted entries only go through the network (compacted), then the
-  // output half of the gate
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, mo->count, 1LL);
-  hipLaunchKernelGGL(k_pregate, dim3(gblocks(n, 256)), dim3(256), 0, s, x6, (long long)ld, (int)n, mo->map, gp,
-                     fallback, mo->idx, mo->count);
-  hipLaunchKernelGGL(k_mlp_fused, dim3(gblocks(n, FR)), dim3(256), 0, s, x6, (long long)ld, (int)n, mo->idx,
-                     mo->count, mo->P, mo->Pb, mo->scal, mo->yinf);
-  hipLaunchKernelGGL(k_gate_idx, dim3(gblocks(n, 256)), dim3(256), 0, s, x6, (long long)ld, mo->idx, mo->count,
-                     mo->yinf, mo->scal, mo->map, gp, y5, fallback, status);
-  e = launch_err("surrogate launch");
+  e = surrogate_predict_gated(mo, d, n, ld, x6, y5, fallback, status, (hipStream_t)stream);
   if (e) return e;
   // the exact integrator traces the rejected rays (one persistent launch)
-  e = rt_transit_exact(cloaks, n_cloaks, opts, n, ld, x6, fallback, y5, status, nullptr, nullptr, stream);
-  return e;
+  return rt_transit_exact(cloaks, n_cloaks, opts, n, ld, x6, fallback, y5, status, nullptr, nullptr, stream);
 }
 
 int rt_surrogate_save(rt_model mo, const char *path) {

@@ -32,7 +32,7 @@ EXPORTED = ["rt_build_cloak", "rt_free_cloak", "rt_trace_batch", "rt_render", "r
             "rt_surrogate_set_scaling", "rt_surrogate_fit_scaling", "rt_surrogate_encode",
             "rt_surrogate_grad", "rt_surrogate_train", "rt_surrogate_forward",
             "rt_surrogate_calibrate", "rt_surrogate_get_map", "rt_surrogate_infer",
-            "rt_surrogate_save", "rt_surrogate_load"]
+            "rt_surrogate_save", "rt_surrogate_load", "rt_render_surrogate"]
 
 
 class RtError(RuntimeError):
@@ -103,6 +103,9 @@ def lib():
         L.rt_render_multi.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(TraceOpts),
                                       ctypes.POINTER(Room), ctypes.POINTER(Camera), i32, i32, vp,
                                       ctypes.POINTER(RenderAux), vp]
+        L.rt_render_surrogate.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(TraceOpts),
+                                          ctypes.POINTER(Room), ctypes.POINTER(Camera), i32, i32, i32, vp,
+                                          ctypes.POINTER(RenderAux), ctypes.POINTER(i64), vp]
         L.rt_render_plan_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(TraceOpts),
                                             ctypes.POINTER(Room), ctypes.POINTER(Camera), i32, i32, vp,
                                             ctypes.POINTER(RenderAux), ctypes.POINTER(vp)]
@@ -269,6 +272,48 @@ def render_multi(cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: i
                                  int(pol_mask), _ptr(rgb),
                                  ctypes.byref(aux_s) if aux_s is not None else None, _stream()))
     return (rgb, aux_t) if aux else rgb
+
+
+def render_surrogate(model, cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: int,
+                     aux: bool = False, out=None, counts: bool = False, min_difficulty: int = 0):
+    """rt_render_surrogate: render_multi with the side-to-side transits of
+    entries of difficulty >= min_difficulty taken from the calibrated
+    surrogate `model` (a Surrogate) where its gate accepts them. Returns rgb
+    as render_multi (then the aux dict if aux, then (candidates, accepted) if
+    counts)."""
+    import torch
+    n = len(cams)
+    ncl = len(cloaks)
+    w, h, spp = int(cams[0]["w"]), int(cams[0]["h"]), int(cams[0].get("spp", 1))
+    npol = 2 if pol_mask == 3 else 1
+    dev = torch.device("cuda", torch.cuda.current_device())
+    rgb = out if out is not None else torch.empty((ncl, n, npol, h, w, 3), dtype=torch.float32,
+                                                  device=dev)
+    carr = (Camera * n)(*[camera(c) for c in cams])
+    harr = (ctypes.c_void_p * max(ncl, 1))(*[c.handle for c in cloaks])
+    rm = room(room_d)
+    o = trace_opts(opts)
+    aux_s = None
+    aux_t = None
+    if aux:
+        ns = w * h * spp
+        aux_t = {"rec": torch.empty((ncl, n, npol, 7, ns), dtype=torch.float64, device=dev),
+                 "status": torch.empty((ncl, n, npol, ns), dtype=torch.int32, device=dev),
+                 "code": torch.empty((ncl, n, npol, ns), dtype=torch.uint8, device=dev),
+                 "nsteps": torch.empty((ncl, n, npol, ns), dtype=torch.int32, device=dev)}
+        aux_s = RenderAux(aux_t["rec"].data_ptr(), aux_t["status"].data_ptr(), aux_t["code"].data_ptr(),
+                          aux_t["nsteps"].data_ptr())
+    c2 = (ctypes.c_int64 * 2)(0, 0)
+    _check(lib().rt_render_surrogate(model.handle, harr, ncl, ctypes.byref(o), ctypes.byref(rm), carr, n,
+                                     int(pol_mask), int(min_difficulty), _ptr(rgb),
+                                     ctypes.byref(aux_s) if aux_s is not None else None,
+                                     c2 if counts else None, _stream()))
+    out_t = (rgb,)
+    if aux:
+        out_t += (aux_t,)
+    if counts:
+        out_t += ((int(c2[0]), int(c2[1])),)
+    return out_t if len(out_t) > 1 else rgb
 
 
 def render(cloak, opts: dict, room_d: dict, cams: list, pol_mask: int, aux: bool = False,
