@@ -337,8 +337,11 @@ int rt_surrogate_forward(rt_model model, int64_t n, int64_t ld, const float *x6,
    of the transit run along thin curves that a cell's calibration rays can
    miss). hres_exact (n floats from rt_transit_exact, or NULL): exits with
    hres_exact > gate->unresolved (> 0) are left out, neither counted nor
-   failing, since the integrator did not resolve them. Stores `gate` in
-   the model. trusted_fraction (host, may be NULL): share of trusted cells.
+   failing, since the integrator did not resolve them; with hres_exact and
+   cloaks of infinite height, so are totally reflected exits (a side entry
+   of the infinite cylinder conserves its tangential wave numbers and always
+   transmits at its exit; the status only arises from the integrator's
+   drift at grazing entries). Stores `gate` in the model. trusted_fraction (host, may be NULL): share of trusted cells.
    Synchronous. */
 int rt_surrogate_calibrate(rt_model model, const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int64_t ld,
                            const float *x6, const float *y5_exact, const int32_t *status_exact,

@@ -969,16 +969,22 @@ __device__ __forceinline__ void exit_ray(const float *p, float b, float x[3], fl
 __global__ void __launch_bounds__(256) k_calib(const float *__restrict__ x6, long long ld, int n,
                                                const float *__restrict__ y, const float *__restrict__ sc,
                                                const float *__restrict__ ye, const int *__restrict__ st,
-                                               const float *__restrict__ hres, float unresolved, float a,
-                                               float b, unsigned int *__restrict__ cmax,
+                                               const float *__restrict__ hres, float unresolved, bool infinite,
+                                               float a, float b, unsigned int *__restrict__ cmax,
                                                unsigned int *__restrict__ ccnt) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float phi = x6[i], z = x6[ld + i], al = x6[2 * ld + i], be = x6[3 * ld + i];
   const float pol = x6[4 * ld + i], axis = x6[5 * ld + i];
   if (!entry_ok(phi, z, al, be, pol, axis)) return;
-  // an exit the integrator did not resolve is no reference
+  // an exit the integrator did not resolve is no reference: a drifted
+  // Hamiltonian, or total internal reflection at the exit of a side entry
+  // into the infinite cylinder (impossible in exact arithmetic: the
+  // tangential wave numbers the ray entered with are conserved, so the exit
+  // refraction transmits; only drift beyond a grazing entry's normal wave
+  // number turns it evanescent)
   if (hres && st[i] == RT_RAY_EXITED && !(hres[i] <= unresolved)) return;
+  if (hres && infinite && st[i] == RT_RAY_TIR) return;
   const int kind = kind_of(pol, axis);
   const int cell = cell_of(kind, al, be);
   float err = INFINITY;
@@ -1496,8 +1502,8 @@ int rt_surrogate_calibrate(rt_model mo, const rt_cloak *cloaks, int32_t n_cloaks
   infer_outputs(mo, x6, ld, (int)n, s);
   hipLaunchKernelGGL(k_fill_u32, dim3(gblocks(2LL * NCELLS, 256)), dim3(256), 0, s, mo->cal, 2LL * NCELLS);
   hipLaunchKernelGGL(k_calib, dim3(gblocks(n, 256)), dim3(256), 0, s, x6, (long long)ld, (int)n, mo->yinf, mo->scal,
-                     y5_exact, status_exact, hres_exact, (float)gate->unresolved, (float)d.r1, (float)d.r2,
-                     mo->cal, mo->cal + NCELLS);
+                     y5_exact, status_exact, hres_exact, (float)gate->unresolved,
+                     !std::isfinite(d.z0) && !std::isfinite(d.z1), (float)d.r1, (float)d.r2, mo->cal, mo->cal + NCELLS);
   std::vector<unsigned int> h(2 * NCELLS);
   if (hipMemcpyAsync(h.data(), mo->cal, sizeof(unsigned int) * 2 * NCELLS, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)

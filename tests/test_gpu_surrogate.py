@@ -255,8 +255,8 @@ def test_surrogate_pipeline_small():
     30 per cell) at half the tolerance, then infer on held-out rays. The
     integrator is the judge only where it resolves the path: exits whose
     Hamiltonian drift |H - 1| exceeds 1e-6 (entries with p_theta -> 0 that
-    pass next to the singular r = a) are no reference, in calibration and
-    here. The calibration bound is empirical (a cell is judged on its
+    pass next to the singular r = a) and totally reflected exits (drift at
+    grazing entries) are no reference, in calibration and here. The calibration bound is empirical (a cell is judged on its
     calibration rays), so accepted held-out rays with a resolved reference
     are checked at p99 and with at most 1e-4 of them over tol; rejected rays
     must carry exactly the exact transit's result."""
@@ -289,14 +289,19 @@ def test_surrogate_pipeline_small():
     # the axis (p_theta ~ 0) that the integrator brings to the singular
     # r = a and absorbs (the measure-zero case of the inner-cylinder
     # reading), in a cell whose calibration rays all passed
-    odd = acc & (st_ex != 0)
+    odd = acc & (st_ex != 0) & (st_ex != 5)
     say(f"accepted but not exited by the integrator: {int(odd.sum())}, statuses "
         f"{torch.bincount(st_ex[odd].long(), minlength=8).tolist()}")
     assert int(odd.sum()) <= max(1, int(1e-4 * int(acc.sum())))
+    # unresolved references: a drifted Hamiltonian, or total internal
+    # reflection at the exit of a side entry into the infinite cylinder
+    # (impossible in exact arithmetic: the tangential wave numbers are
+    # conserved)
     resolved = (st_ex == 0) & (h_ex <= 1e-6)
-    unres = acc & (st_ex == 0) & ~resolved
-    say(f"accepted with an unresolved reference: {int(unres.sum())}"
-        + (f", their max difference {float(err[unres].max()):.2e}" if bool(unres.any()) else ""))
+    unres = acc & ~resolved & ((st_ex == 0) | (st_ex == 5))
+    ux = unres & (st_ex == 0)
+    say(f"accepted with an unresolved reference: {int(unres.sum())} ({int((unres & (st_ex == 5)).sum())} "
+        f"totally reflected)" + (f", max difference of the exited {float(err[ux].max()):.2e}" if bool(ux.any()) else ""))
     acc = acc & resolved
     e = S.summarize_errors(err, acc)
     say(f"accepted exit error (resolved references) {e}")
