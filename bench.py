@@ -66,16 +66,16 @@ def attempt_flops(kind: int, scheme: int) -> int:
     return RK4_COMBINE_FLOPS + RK4_STAGES * ACCEL_FLOPS[kind]
 
 
-# HBM traffic of one integrator launch from two rocprofv3 --pmc runs
-# (FETCH_SIZE, WRITE_SIZE) of this benchmark, scaled by the same counters on a
-# plain device copy of known size (bench.py --copy-probe). Valid only for the
-# integrator source it was measured on; reported as null otherwise.
 # Hamiltonian drift |v^T M v - 1| above which an exact exit is taken as not
 # resolved by the integrator (the surrogate is then judged elsewhere)
 UNRESOLVED = 1e-6
 
-TRAFFIC = {"source_sha256": "636e1a6c175e8a4dea249d64444d277f0e40bfae7413b181ed2d476347bdbc61",
-           "bytes_per_launch": 811038720}
+# HBM traffic of one integrator launch from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) of this benchmark, scaled by the same counters on a
+# plain device copy of known size (bench.py --copy-probe). Valid only for the
+# integrator source it was measured on; reported as null otherwise.
+TRAFFIC = {"source_sha256": "3cde2ce483e364da97147b3726c911c8f44b8905afb70cebb72a223016ddada3",
+           "bytes_per_launch": 775985152}
 
 
 def finite_json(obj):
