@@ -213,3 +213,21 @@ def test_orbit_frame_full_size_sampled():
             bad = int((d > 1e-6).sum())
             say(f"  cloak axis {c['axis']} branch {pi}: {bad} of {len(pix)} pixels differ")
             assert bad <= 1
+
+
+def test_two_large_frames_in_one_launch_equal_one_launch_each():
+    """Two 4096^2 x 4 spp frames (2^27 samples) in one integrator launch give
+    the same images as one launch per frame: work-table slots past 2^28 and
+    the codes of the second frame stay in range, and per-ray work does not
+    depend on the batching."""
+    import torch
+    from paper_1209_6038_amd import rt
+    frames = W.orbit_frames(36, 4096, 4)[:2]
+    cls = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
+    one = rt.render_multi(cls, W.render_opts(max_chunk=2 * 4096 * 4096 * 4), W.room(), frames, 3)
+    each = rt.render_multi(cls, W.render_opts(), W.room(), frames, 3)
+    torch.cuda.synchronize()
+    say(f"max |difference| {float((one - each).abs().max()):.3e}")
+    assert torch.equal(one, each)
+    del one, each
+    rt.release_workspace()
