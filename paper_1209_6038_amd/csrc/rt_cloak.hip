@@ -655,7 +655,7 @@ __global__ void __launch_bounds__(256) k_sx_entry(CloakP c, OptsP o, Table T, lo
                                                   const float *__restrict__ x6,
                                                   const unsigned char *__restrict__ mask, int have_axes,
                                                   float *__restrict__ y5, int *__restrict__ status,
-                                                  int *__restrict__ nsteps) {
+                                                  float *__restrict__ hres, int *__restrict__ nsteps) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   bool entered = false;
   double x[3], v[3];
@@ -688,6 +688,7 @@ __global__ void __launch_bounds__(256) k_sx_entry(CloakP c, OptsP o, Table T, lo
     if (!entered) {
       for (int j = 0; j < 5; ++j) y5[j * ld + i] = __builtin_nanf("");
       status[i] = st;
+      if (hres) hres[i] = __builtin_nanf("");
       if (nsteps) nsteps[i] = 0;
     }
   }
@@ -1670,7 +1671,7 @@ int rt_transit_exact(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_op
   unsigned int grid = o.precision == RT_PREC_MIXED ? transit_grid<true>(block) : transit_grid<false>(block);
   hipLaunchKernelGGL(k_zero, dim3((C_COUNT + 255) / 256), dim3(256), 0, s, T.ctr, (int)C_COUNT);
   hipLaunchKernelGGL(k_sx_entry, dim3(grid_for(n, 256)), dim3(256), 0, s, c, o, T, (long long)n,
-                     (long long)ld, x6, mask, have_axes, y5, status, nsteps);
+                     (long long)ld, x6, mask, have_axes, y5, status, hres, nsteps);
   e = launch_err("entry launch");
   if (e) return e;
   if (o.precision == RT_PREC_MIXED) run_transit<true>(c, o, T, block, refill, grid, s, true);
