@@ -120,17 +120,22 @@ typedef struct {
     float rgb[6][2][3];
 } rt_room;
 
-/* Optional per-sample outputs of rt_render, each laid out per image
-   (camera-major, then branch) over ns = w*h*spp samples; NULL fields are not
-   written. rec: SoA 7 x ns doubles per image (origin and direction of the
+/* Optional outputs of rt_render, each laid out per image (camera-major,
+   then branch); NULL fields are not written. Per sample (ns = w*h*spp
+   samples per image): rec: SoA 7 x ns doubles (origin and direction of the
    last vacuum ray, optical path from the eye to the room); status: RT_RAY_*;
    code: face*2 + parity of the room point seen, 12 = black; nsteps:
-   integrator step attempts. */
+   integrator step attempts. Per pixel (w*h floats per image): tof: time of
+   flight, the mean over the pixel's samples that reach the room of their
+   optical path from the eye (c0 = 1, so optical path = time; the ray ODE's
+   time inside the cloak, App. A), NaN if none does. With the empty room's
+   image it gives the time-of-flight difference the cloak makes (Sect. 4). */
 typedef struct {
     double *rec;
     int32_t *status;
     uint8_t *code;
     int32_t *nsteps;
+    float *tof;
 } rt_render_aux;
 
 /* Build a cloak handle (host-side constants; no device memory).

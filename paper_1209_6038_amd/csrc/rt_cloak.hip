@@ -757,10 +757,12 @@ struct RenderP {
   int has_cloak, idx32;  // idx32: every flattened sample index < 2^32
   int sur_min;           // surrogate render: side entries of difficulty bucket >= sur_min are candidates
   unsigned char *codes;  // chunk-local codes [segment][g1-g0]
+  float *topl;           // chunk-local optical path to the room [segment][g1-g0] (NaN: no room point); NULL unless tof
   double *rec;           // aux (may be NULL)
   int *st;
   unsigned char *code;
   int *nsteps;
+  float *tof;            // aux per-pixel time of flight (may be NULL)
 };
 
 // Surrogate render: the side entries of a chunk that go to the network
@@ -794,6 +796,7 @@ __device__ __forceinline__ void rd_write(const RenderP &R, int q, long long gidx
                                          int st, const double p[3], const double d[3], double L,
                                          int nsteps) {
   R.codes[(long long)q * (R.g1 - R.g0) + (gidx - R.g0)] = (unsigned char)code;
+  if (R.topl) R.topl[(long long)q * (R.g1 - R.g0) + (gidx - R.g0)] = code < 12 ? (float)L : __builtin_nanf("");
   long long cam, loc;
   split_index(R, gidx, cam, loc);
   int ci = q / R.npol, pi = q - ci * R.npol;
@@ -1015,6 +1018,13 @@ __global__ void __launch_bounds__(256) k_rd_resolve(RenderP R, const float *__re
     b += tab[3 * cc + 2];
   }
   float inv = 1.0f / (float)R.spp;
+  double tsum = 0.0;
+  int tn = 0;
+  if (R.tof) {
+    const float *tl = R.topl + q * chunk + lp * R.spp;
+    for (int k = 0; k < R.spp; ++k)
+      if (isfinite(tl[k])) { tsum += tl[k]; ++tn; }
+  }
   long long gpix = R.g0 / R.spp + lp;  // flattened (camera, pixel)
   long long cam, pix;
   if (R.idx32) {
@@ -1026,17 +1036,20 @@ __global__ void __launch_bounds__(256) k_rd_resolve(RenderP R, const float *__re
     pix = gpix - cam * npix;
   }
   int ci = q / R.npol, pi = q - ci * R.npol;
-  float *o = rgb + ((((long long)ci * R.n_cams + cam) * R.npol + pi) * npix + pix) * 3;
+  const long long img = ((long long)ci * R.n_cams + cam) * R.npol + pi;
+  float *o = rgb + (img * npix + pix) * 3;
   o[0] = r * inv;
   o[1] = g * inv;
   o[2] = b * inv;
+  if (R.tof) R.tof[img * npix + pix] = tn ? (float)(tsum / tn) : __builtin_nanf("");
 }
 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 // Device workspace: the work table (NSEG segments of `cap` slots), the colour
-// codes of one render chunk, camera records and the colour table. The direct
+// codes and optical paths of one render chunk, camera records and the colour
+// table. The direct
 // calls share one (g_ws); every render plan owns its own.
 struct Workspace {
   void *base = nullptr;
@@ -1047,6 +1060,7 @@ struct Workspace {
   int device = -1;
   Table T{};
   unsigned char *codes = nullptr;
+  float *topl = nullptr;  // per-sample optical path of a chunk (time-of-flight images)
   CamP *cams = nullptr;
   float *table = nullptr;
 };
@@ -1116,6 +1130,7 @@ int ws_reserve(Workspace &ws, long long cap, long long codes_len, int ncam) {
   size_t o_q = take(sizeof(int) * 2 * ns);
   size_t o_c = take(sizeof(unsigned int) * C_COUNT);
   size_t o_codes = take((size_t)codes_len);
+  size_t o_topl = take(sizeof(float) * (size_t)codes_len);
   size_t o_cams = take(sizeof(CamP) * ncam);
   size_t o_tab = take(sizeof(float) * 64);
   void *p = nullptr;
@@ -1139,6 +1154,7 @@ int ws_reserve(Workspace &ws, long long cap, long long codes_len, int ncam) {
   ws.bytes = off;
   ws.cap = cap;
   ws.codes = (unsigned char *)(b + o_codes);
+  ws.topl = (float *)(b + o_topl);
   ws.codes_len = codes_len;
   ws.cams = (CamP *)(b + o_cams);
   ws.cams_cap = ncam;
@@ -1395,6 +1411,8 @@ int prepare_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts
   R.st = aux ? aux->status : nullptr;
   R.code = aux ? aux->code : nullptr;
   R.nsteps = aux ? aux->nsteps : nullptr;
+  R.tof = aux ? aux->tof : nullptr;
+  R.topl = nullptr;
   return RT_OK;
 }
 
@@ -1417,6 +1435,7 @@ void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStre
   const Table &T = ws.T;
   RenderP R = J.R;
   R.codes = ws.codes;
+  R.topl = R.tof ? ws.topl : nullptr;
   for (long long g0 = 0; g0 < J.total; g0 += J.chunk) {
     R.g0 = g0;
     R.g1 = std::min(J.total, g0 + J.chunk);
@@ -1492,6 +1511,7 @@ int render_surrogate(rt_model model, const rt_cloak_desc &desc, const RenderJob 
   RenderP R = J.R;
   R.sur_min = min_difficulty;
   R.codes = ws.codes;
+  R.topl = R.tof ? ws.topl : nullptr;
   for (long long g0 = 0; g0 < J.total; g0 += J.chunk) {
     R.g0 = g0;
     R.g1 = std::min(J.total, g0 + J.chunk);

@@ -81,7 +81,21 @@ class GateOpts(ctypes.Structure):
 
 class RenderAux(ctypes.Structure):
     _fields_ = [("rec", ctypes.c_void_p), ("status", ctypes.c_void_p), ("code", ctypes.c_void_p),
-                ("nsteps", ctypes.c_void_p)]
+                ("nsteps", ctypes.c_void_p), ("tof", ctypes.c_void_p)]
+
+
+def _render_aux(lead: tuple, w: int, h: int, spp: int, dev):
+    """Per-sample (rec, status, code, nsteps) and per-pixel (tof) render
+    outputs for images of leading shape `lead`, and their rt_render_aux."""
+    import torch
+    ns = w * h * spp
+    aux_t = {"rec": torch.empty(lead + (7, ns), dtype=torch.float64, device=dev),
+             "status": torch.empty(lead + (ns,), dtype=torch.int32, device=dev),
+             "code": torch.empty(lead + (ns,), dtype=torch.uint8, device=dev),
+             "nsteps": torch.empty(lead + (ns,), dtype=torch.int32, device=dev),
+             "tof": torch.empty(lead + (h, w), dtype=torch.float32, device=dev)}
+    aux_s = RenderAux(*(aux_t[k].data_ptr() for k in ("rec", "status", "code", "nsteps", "tof")))
+    return aux_t, aux_s
 
 
 _lib = None
@@ -261,13 +275,7 @@ def render_multi(cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: i
     aux_s = None
     aux_t = None
     if aux:
-        ns = w * h * spp
-        aux_t = {"rec": torch.empty((ncl, n, npol, 7, ns), dtype=torch.float64, device=dev),
-                 "status": torch.empty((ncl, n, npol, ns), dtype=torch.int32, device=dev),
-                 "code": torch.empty((ncl, n, npol, ns), dtype=torch.uint8, device=dev),
-                 "nsteps": torch.empty((ncl, n, npol, ns), dtype=torch.int32, device=dev)}
-        aux_s = RenderAux(aux_t["rec"].data_ptr(), aux_t["status"].data_ptr(), aux_t["code"].data_ptr(),
-                          aux_t["nsteps"].data_ptr())
+        aux_t, aux_s = _render_aux((ncl, n, npol,), w, h, spp, dev)
     _check(lib().rt_render_multi(harr, len(cloaks), ctypes.byref(o), ctypes.byref(rm), carr, n,
                                  int(pol_mask), _ptr(rgb),
                                  ctypes.byref(aux_s) if aux_s is not None else None, _stream()))
@@ -296,13 +304,7 @@ def render_surrogate(model, cloaks: list, opts: dict, room_d: dict, cams: list, 
     aux_s = None
     aux_t = None
     if aux:
-        ns = w * h * spp
-        aux_t = {"rec": torch.empty((ncl, n, npol, 7, ns), dtype=torch.float64, device=dev),
-                 "status": torch.empty((ncl, n, npol, ns), dtype=torch.int32, device=dev),
-                 "code": torch.empty((ncl, n, npol, ns), dtype=torch.uint8, device=dev),
-                 "nsteps": torch.empty((ncl, n, npol, ns), dtype=torch.int32, device=dev)}
-        aux_s = RenderAux(aux_t["rec"].data_ptr(), aux_t["status"].data_ptr(), aux_t["code"].data_ptr(),
-                          aux_t["nsteps"].data_ptr())
+        aux_t, aux_s = _render_aux((ncl, n, npol,), w, h, spp, dev)
     c2 = (ctypes.c_int64 * 2)(0, 0)
     _check(lib().rt_render_surrogate(model.handle, harr, ncl, ctypes.byref(o), ctypes.byref(rm), carr, n,
                                      int(pol_mask), int(min_difficulty), _ptr(rgb),
@@ -332,13 +334,7 @@ def render(cloak, opts: dict, room_d: dict, cams: list, pol_mask: int, aux: bool
     aux_s = None
     aux_t = None
     if aux:
-        ns = w * h * spp
-        aux_t = {"rec": torch.empty((n, npol, 7, ns), dtype=torch.float64, device=dev),
-                 "status": torch.empty((n, npol, ns), dtype=torch.int32, device=dev),
-                 "code": torch.empty((n, npol, ns), dtype=torch.uint8, device=dev),
-                 "nsteps": torch.empty((n, npol, ns), dtype=torch.int32, device=dev)}
-        aux_s = RenderAux(aux_t["rec"].data_ptr(), aux_t["status"].data_ptr(), aux_t["code"].data_ptr(),
-                          aux_t["nsteps"].data_ptr())
+        aux_t, aux_s = _render_aux((n, npol,), w, h, spp, dev)
     _check(lib().rt_render(cloak.handle if cloak is not None else None, ctypes.byref(o),
                            ctypes.byref(rm), carr, n, int(pol_mask), _ptr(rgb),
                            ctypes.byref(aux_s) if aux_s is not None else None, _stream()))
@@ -355,13 +351,7 @@ def _alloc_render_outputs(ncl, cams, pol_mask, aux, out=None):
                                                   device=dev)
     aux_t = aux_s = None
     if aux:
-        ns = w * h * spp
-        aux_t = {"rec": torch.empty((ncl, n, npol, 7, ns), dtype=torch.float64, device=dev),
-                 "status": torch.empty((ncl, n, npol, ns), dtype=torch.int32, device=dev),
-                 "code": torch.empty((ncl, n, npol, ns), dtype=torch.uint8, device=dev),
-                 "nsteps": torch.empty((ncl, n, npol, ns), dtype=torch.int32, device=dev)}
-        aux_s = RenderAux(aux_t["rec"].data_ptr(), aux_t["status"].data_ptr(), aux_t["code"].data_ptr(),
-                          aux_t["nsteps"].data_ptr())
+        aux_t, aux_s = _render_aux((ncl, n, npol,), w, h, spp, dev)
     return rgb, aux_t, aux_s
 
 

@@ -64,6 +64,19 @@ def compare_samples(g_code, g_rec, g_st, o, room, label, pos_tol=1e-6, dir_tol=1
     say(f"  codes differing at tile edges: {diff.sum()} of {len(diff)}")
 
 
+def compare_tof(g_tof, o, spp):
+    """Per-pixel time of flight against the oracle's samples: the mean optical
+    path of the samples that reach the room (black ones left out), NaN where
+    none does. float32 output: 4e-6 relative."""
+    L = np.where(o["code"] < 12, o["rec"][6], np.nan).reshape(-1, spp)
+    cnt = np.isfinite(L).sum(axis=1)
+    want = np.where(cnt > 0, np.nansum(L, axis=1) / np.maximum(cnt, 1), np.nan)
+    g = g_tof.reshape(-1)
+    assert np.array_equal(np.isnan(g), np.isnan(want))
+    ok = np.isfinite(want)
+    assert (np.abs(g[ok] - want[ok]) <= 4e-6 * np.abs(want[ok]) + 1e-6).all()
+
+
 @pytest.mark.parametrize("axis", [0, 1])
 def test_render_small_parity(axis):
     cams = W.render_views(res=48)
@@ -82,6 +95,7 @@ def test_render_small_parity(axis):
                             f"small a{axis} cam{k} b{branch}")
             want = table[aux["code"][k, pi]].reshape(48, 48, 3)
             np.testing.assert_allclose(rgb[k, pi], want, atol=1e-7)
+            compare_tof(aux["tof"][k, pi], o, 1)
 
 
 def test_render_empty_room():
@@ -114,6 +128,7 @@ def test_render_jittered_samples(axis):
         col, _ = oracle.render_pixels(c, W.opts_dp45(), room, cam, k, 0, np.arange(24 * 24))
         same = (aux["code"][k, 0] == o["code"]).reshape(-1, 4).all(axis=1)
         np.testing.assert_allclose(rgb[k, 0].reshape(-1, 3)[same], col[same], atol=1e-6)
+        compare_tof(aux["tof"][k, 0], o, 4)
 
 
 def test_render_full_size_sampled():
@@ -159,6 +174,7 @@ def test_render_multi_equals_single_calls():
         for key in ("status", "code", "nsteps"):
             assert torch.equal(aux_m[key][ci], aux_s[key]), key
         assert torch.equal(torch.nan_to_num(aux_m["rec"][ci]), torch.nan_to_num(aux_s["rec"]))
+        assert torch.equal(torch.nan_to_num(aux_m["tof"][ci]), torch.nan_to_num(aux_s["tof"]))
 
 
 def test_render_multi_rejects_mismatched_geometry():
@@ -183,6 +199,7 @@ def test_render_in_small_chunks_equals_one_launch():
     assert torch.equal(a, b)
     for key in ("status", "code", "nsteps"):
         assert torch.equal(aux_a[key], aux_b[key]), key
+    assert torch.equal(torch.nan_to_num(aux_a["tof"]), torch.nan_to_num(aux_b["tof"]))
 
 
 def test_orbit_frame_full_size_sampled():

@@ -68,6 +68,7 @@ def test_surrogate_render_with_nothing_trusted_is_the_plain_render():
         for key in ("status", "code", "nsteps"):
             assert torch.equal(aux_p[key], aux_s[key]), key
         assert torch.equal(torch.nan_to_num(aux_p["rec"]), torch.nan_to_num(aux_s["rec"]))
+        assert torch.equal(torch.nan_to_num(aux_p["tof"]), torch.nan_to_num(aux_s["tof"]))
 
 
 @pytest.mark.parametrize("min_difficulty", [0, 2])

@@ -548,3 +548,30 @@ def test_elevation0_centre_row_is_cloaked_for_extraordinary_light():
         assert (np.abs(col - empty).max(axis=1) > 0).sum() <= 1
         col_o, _ = oracle.render_pixels(c, W.opts_rk4(), room, cam, 0, O, row)
         assert (np.abs(col_o - empty).max(axis=1) > 0).sum() > 5
+
+
+
+def test_elevation0_centre_row_time_of_flight_is_the_empty_rooms():
+    """Sect. 4: for in-plane polarized light the time-of-flight image with
+    cloak and cylinder equals the one without the cylinder in the cross-section
+    plane. An in-plane extraordinary ray's optical path inside is the
+    undeviated chord (CF1), so the centre row at elevation 0 takes the empty
+    room's optical path; ordinary rays (not cloaked) do not. Pixels whose ray
+    passes within 0.2 of the axis are left out: the fixed RK4 step h = 1e-3
+    loses accuracy as the path closes in on the singular r = a."""
+    n = 65
+    cam = W.orbit_camera(0.0, 0.0, n, n)
+    room = W.room()
+    ids = np.arange(n) + (n // 2) * n
+    empty = oracle.render_samples(None, W.opts_dp45(), room, cam, 0, E, ids)
+    eye, d = empty["rec"][:3], empty["rec"][3:6]
+    p = np.abs(eye[0] * d[1] - eye[1] * d[0]) / np.hypot(d[0], d[1])
+    for axis in (0, 1):
+        c = W.cloak(axis, height=4.0)
+        r = oracle.render_samples(c, W.opts_rk4(), room, cam, 0, E, ids)
+        sel = (r["status"] == 0) & (p >= 0.2) & (p < 2.0)
+        assert sel.sum() >= 10
+        np.testing.assert_allclose(r["rec"][6][sel], empty["rec"][6][sel], rtol=0, atol=1e-8)
+        ro = oracle.render_samples(c, W.opts_rk4(), room, cam, 0, O, ids)
+        selo = (ro["status"] == 0) & (p < 2.0)
+        assert (np.abs(ro["rec"][6][selo] - empty["rec"][6][selo]) > 1e-3).sum() > 5
