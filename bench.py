@@ -74,8 +74,8 @@ UNRESOLVED = 1e-6
 # (FETCH_SIZE, WRITE_SIZE) of this benchmark, scaled by the same counters on a
 # plain device copy of known size (bench.py --copy-probe). Valid only for the
 # integrator source it was measured on; reported as null otherwise.
-TRAFFIC = {"source_sha256": "3cde2ce483e364da97147b3726c911c8f44b8905afb70cebb72a223016ddada3",
-           "bytes_per_launch": 775985152}
+TRAFFIC = {"source_sha256": "3588458a586dfdba7a2945a8eee7f0c7207fedab9a84145a53225d1631bedc0b",
+           "bytes_per_launch": 775587552}
 
 
 def finite_json(obj):
