@@ -265,13 +265,14 @@ def test_surrogate_pipeline_small():
     """Small version of the surrogate workload: label entries with the exact
     transit, train briefly, calibrate the trust map on separate rays (about
     30 per cell) at half the tolerance, then infer on held-out rays. The
-    integrator is the judge only where it resolves the path: exits whose
+    integrator is the reference only where it resolves the path: exits whose
     Hamiltonian drift |H - 1| exceeds 1e-6 (entries with p_theta -> 0 that
     pass next to the singular r = a) and totally reflected exits (drift at
-    grazing entries) are no reference, in calibration and here. The calibration bound is empirical (a cell is judged on its
-    calibration rays), so accepted held-out rays with a resolved reference
-    are checked at p99 and with at most 1e-4 of them over tol; rejected rays
-    must carry exactly the exact transit's result."""
+    grazing entries) are no reference, in calibration and here. The
+    calibration bound is empirical (a cell is judged on its calibration
+    rays), so accepted held-out rays with a resolved reference are checked
+    at p99 and with at most 1e-4 of them over tol; rejected rays must carry
+    exactly the exact transit's result."""
     import torch
     from paper_1209_6038_amd import rt
     from paper_1209_6038_amd import surrogate as S
