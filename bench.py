@@ -253,6 +253,8 @@ def surrogate_leg(steps: int, n_train: int, log, fpl: int = 2):
     # drift at a grazing entry (the tangential wave numbers are conserved):
     # no reference either
     unres = acc_all & ~resolved & ((st_ex == 0) | (st_ex == 5))
+    ux = unres & (st_ex == 0)
+    unres_max = float(err[ux].max()) if bool(ux.any()) else 0.0
     kind = (x_ev[5] * 2 + x_ev[4]).long()
 
     def timed(fn, reps=5):
@@ -310,7 +312,7 @@ def surrogate_leg(steps: int, n_train: int, log, fpl: int = 2):
                       "not totally reflected)"),
         "accepted_with_unresolved_reference": {
             "n": int(unres.sum()), "totally_reflected": int((unres & (st_ex == 5)).sum()),
-            "max_difference_of_exited": float(f"{float(err[unres & (st_ex == 0)].max()) if bool((unres & (st_ex == 0)).any()) else 0.0:.3e}")},
+            "max_difference_of_exited": float(f"{unres_max:.3e}")},
         "accepted_opl_rel_error_p99": float(f"{S.summarize_errors(operr, acc).get('p99', 0.0):.3e}"),
         "network_vs_closed_form": {
             "note": "exit error vs the exact transit on the rays both accept: baselines + network, baselines alone",
