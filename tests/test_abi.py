@@ -108,3 +108,35 @@ def test_product_path_has_no_oracle_dependency():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "cloak_oracle" not in txt, f
+
+
+def test_render_argument_validation_needs_no_gpu(lib):
+    """Render arguments are checked on the host before any device use: the
+    number of cloaks, the branch mask, the stratified sample count, the
+    chunk limit (2^28 samples) and the surrogate model."""
+    from paper_1209_6038_amd import workloads as W
+    h = ctypes.c_void_p()
+    good = rt.CloakDesc(1.0, 2.0, 0.0, 4.0, 0, 1)
+    assert lib.rt_build_cloak(ctypes.byref(good), ctypes.byref(h)) == rt.RT_OK
+    harr = (ctypes.c_void_p * 3)(h, h, h)
+    room = rt.room(W.room())
+    fake_rgb = ctypes.c_void_p(8)  # never dereferenced on these paths
+
+    def render(ncl=1, cams=None, pol_mask=3, **opts):
+        cams = cams or [W.orbit_camera(0.3, 20.0, 8, 8)]
+        carr = (rt.Camera * len(cams))(*[rt.camera(c) for c in cams])
+        o = rt.trace_opts(W.render_opts(**opts))
+        return lib.rt_render_multi(harr, ncl, ctypes.byref(o), ctypes.byref(room), carr, len(cams), pol_mask,
+                                   fake_rgb, None, None)
+
+    assert render(ncl=3) == rt.RT_E_INVALID
+    assert render(pol_mask=0) == rt.RT_E_INVALID
+    assert render(cams=[W.orbit_camera(0.3, 20.0, 8, 8, spp=3)]) == rt.RT_E_INVALID
+    assert render(max_chunk=(1 << 28) + 1) == rt.RT_E_INVALID
+    assert b"max_chunk" in lib.rt_last_error()
+    cams = (rt.Camera * 1)(rt.camera(W.orbit_camera(0.3, 20.0, 8, 8)))
+    o = rt.trace_opts(W.render_opts())
+    assert lib.rt_render_surrogate(None, harr, 1, ctypes.byref(o), ctypes.byref(room), cams, 1, 3, 0, fake_rgb,
+                                   None, None, None) == rt.RT_E_INVALID
+    assert b"model" in lib.rt_last_error()
+    assert lib.rt_free_cloak(h) == rt.RT_OK
