@@ -124,89 +124,98 @@ struct Gemm {
   long long ldca;
 };
 
-// Stage a 64 x 32 operand tile (rows r0.., k k0..) into LDS as T[row][k].
-// P(row, k) = P[row * s_row + k * s_k]; rows < nrow and k < kend valid,
-// zeros elsewhere. One 8-element vector per thread: along k when s_k == 1,
-// along rows (stored transposed) when s_row == 1, else element-wise.
+// Stage an R x 32 operand tile (rows r0.., k k0..) into LDS as T[row][k],
+// in passes of 64 rows. P(row, k) = P[row * s_row + k * s_k]; rows < nrow
+// and k < kend valid, zeros elsewhere. One 8-element vector per thread and
+// pass: along k when s_k == 1, along rows (stored transposed) when
+// s_row == 1, else element-wise.
+template <int R>
 __device__ __forceinline__ void stage_tile(bf16 (*T)[40], const bf16 *__restrict__ P, long long s_row, long long s_k,
                                            int r0, int nrow, int k0, int kend, int tid) {
-  if (s_k == 1) {
-    const int r = tid >> 2, kk = (tid & 3) * 8;
-    const int gr = r0 + r, gk = k0 + kk;
-    const bf16 *src = P + gr * s_row + gk;
-    if (gr < nrow && gk + 8 <= kend && ((s_row & 7) == 0)) {
-      *reinterpret_cast<bf16x8 *>(&T[r][kk]) = *reinterpret_cast<const bf16x8 *>(src);
-    } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) T[r][kk + e] = (gr < nrow && gk + e < kend) ? src[e] : (bf16)0.0f;
-    }
-  } else if (s_row == 1) {
-    const int kk = tid >> 3, r = (tid & 7) * 8;
-    const int gr = r0 + r, gk = k0 + kk;
-    const bf16 *src = P + gk * s_k + gr;
-    if (gk < kend && gr + 8 <= nrow && ((s_k & 7) == 0)) {
-      const bf16x8 v = *reinterpret_cast<const bf16x8 *>(src);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) T[r + e][kk] = v[e];
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) T[r + e][kk] = (gk < kend && gr + e < nrow) ? src[e] : (bf16)0.0f;
-    }
-  } else {
-    for (int e = tid; e < 64 * 32; e += 256) {
-      const int r = e >> 5, kk = e & 31;
+  for (int pass = 0; pass < R / 64; ++pass) {
+    const int rb = 64 * pass;
+    if (s_k == 1) {
+      const int r = rb + (tid >> 2), kk = (tid & 3) * 8;
       const int gr = r0 + r, gk = k0 + kk;
-      T[r][kk] = (gr < nrow && gk < kend) ? P[gr * s_row + gk * s_k] : (bf16)0.0f;
+      const bf16 *src = P + gr * s_row + gk;
+      if (gr < nrow && gk + 8 <= kend && ((s_row & 7) == 0)) {
+        *reinterpret_cast<bf16x8 *>(&T[r][kk]) = *reinterpret_cast<const bf16x8 *>(src);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) T[r][kk + e] = (gr < nrow && gk + e < kend) ? src[e] : (bf16)0.0f;
+      }
+    } else if (s_row == 1) {
+      const int kk = tid >> 3, r = rb + (tid & 7) * 8;
+      const int gr = r0 + r, gk = k0 + kk;
+      const bf16 *src = P + gk * s_k + gr;
+      if (gk < kend && gr + 8 <= nrow && ((s_k & 7) == 0)) {
+        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(src);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) T[r + e][kk] = v[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) T[r + e][kk] = (gk < kend && gr + e < nrow) ? src[e] : (bf16)0.0f;
+      }
+    } else {
+      for (int e = tid; e < 64 * 32; e += 256) {
+        const int r = rb + (e >> 5), kk = e & 31;
+        const int gr = r0 + r, gk = k0 + kk;
+        T[r][kk] = (gr < nrow && gk < kend) ? P[gr * s_row + gk * s_k] : (bf16)0.0f;
+      }
     }
   }
 }
 
+// C = A B over the block's K chunk with an epilogue. 4 waves in 2 x 2, each
+// owning (16 WM) x (16 WN) outputs as WM x WN MFMA 16x16x32 tiles, so the
+// block tile is (32 WM) x (32 WN); each 32-deep K step stages both operand
+// tiles once and feeds WM * WN MFMAs per wave from 16-byte LDS reads.
+template <int WM, int WN>
 __global__ void __launch_bounds__(256) k_gemm(Gemm g) {
-  __shared__ __attribute__((aligned(16))) bf16 As[64][40];  // [row][k], padded rows
-  __shared__ __attribute__((aligned(16))) bf16 Bs[64][40];  // [col][k]
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  __shared__ __attribute__((aligned(16))) bf16 As[BM][40];  // [row][k], padded rows
+  __shared__ __attribute__((aligned(16))) bf16 Bs[BN][40];  // [col][k]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;  // row tiles on x (up to 2^31 blocks)
+  const int row0 = blockIdx.x * BM, col0 = blockIdx.y * BN;  // row tiles on x (up to 2^31 blocks)
   const int kbeg = blockIdx.z * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
-  f32x4 acc[2][2];
+  f32x4 acc[WM][WN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = kbeg; k0 < kend; k0 += 32) {
     // A(i, k) = A[i*sa0 + k*sa1]; B staged as its transpose: B(k, j) = B[j*sb1 + k*sb0]
-    stage_tile(As, g.A, g.sa0, g.sa1, row0, g.M, k0, kend, tid);
-    stage_tile(Bs, g.B, g.sb1, g.sb0, col0, g.N, k0, kend, tid);
-  __syncthreads();
+    stage_tile<BM>(As, g.A, g.sa0, g.sa1, row0, g.M, k0, kend, tid);
+    stage_tile<BN>(Bs, g.B, g.sb1, g.sb0, col0, g.N, k0, kend, tid);
+    __syncthreads();
     // operand layout of v_mfma_f32_16x16x32_bf16: lane l holds
-    // A[l%16][8*(l/16) + j] and B[8*(l/16) + j][l%16], j = 0..7
-    bf16x8 af[2], bfr[2];
+    // A[l%16][8*(l/16) + j] and B[8*(l/16) + j][l%16], j = 0..7 (rows of
+    // 80 bytes keep each 8-element read 16-byte aligned)
+    bf16x8 af[WM], bfr[WN];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int r = wm * 32 + t * 16 + (lane & 15);
-      const int c = wn * 32 + t * 16 + (lane & 15);
+    for (int t = 0; t < WM; ++t)
+      af[t] = *reinterpret_cast<const bf16x8 *>(&As[wm * 16 * WM + t * 16 + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        af[t][j] = As[r][8 * (lane >> 4) + j];
-        bfr[t][j] = Bs[c][8 * (lane >> 4) + j];
-      }
-    }
+    for (int t = 0; t < WN; ++t)
+      bfr[t] = *reinterpret_cast<const bf16x8 *>(&Bs[wn * 16 * WN + t * 16 + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
+    for (int ti = 0; ti < WM; ++ti)
 #pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
+      for (int tj = 0; tj < WN; ++tj)
         acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ti], bfr[tj], acc[ti][tj], 0, 0, 0);
     __syncthreads();
   }
   // result layout: lane l holds D[4*(l/16) + i][l%16], i = 0..3
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
+  for (int ti = 0; ti < WM; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
+    for (int tj = 0; tj < WN; ++tj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row0 + wm * 32 + ti * 16 + 4 * (lane >> 4) + r;
-        const int col = col0 + wn * 32 + tj * 16 + (lane & 15);
+        const int row = row0 + wm * 16 * WM + ti * 16 + 4 * (lane >> 4) + r;
+        const int col = col0 + wn * 16 * WN + tj * 16 + (lane & 15);
         if (row >= g.M || col >= g.N) continue;
         const float y = acc[ti][tj][r];
         if (g.epi == EPI_ATOMIC) {
@@ -363,9 +372,13 @@ __global__ void __launch_bounds__(256) k_loss(const float *__restrict__ y, const
 
 // backward of layer 5 (FP32): dW5 += a4^T dy, db5 += sum dy,
 // dz4 = (dy W5^T) * silu'(z4) -> FP32 and BF16 copies. Thread j = unit j.
+// partial sums of the layer-5 gradient (W5 [256][5] then b5 [5]) of each
+// block of k_layer5_back, summed over the blocks by k_layer5_reduce
+constexpr int L5_N = HID * NOUT + NOUT, L5_LD = 1288, L5_MAXB = 1024;
+
 __global__ void __launch_bounds__(256) k_layer5_back(const float *__restrict__ dy, const float *__restrict__ a4,
                                                      const float *__restrict__ z4, int n,
-                                                     const float *__restrict__ P, float *__restrict__ G,
+                                                     const float *__restrict__ P, float *__restrict__ part,
                                                      float *__restrict__ dzf, bf16 *__restrict__ dzb) {
   const int j = threadIdx.x;
   float w[NOUT], gw[NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f}, gb = 0.f;
@@ -389,9 +402,27 @@ __global__ void __launch_bounds__(256) k_layer5_back(const float *__restrict__ d
     dzf[e] = g;
     dzb[e] = (bf16)g;
   }
+  float *pb = part + (long long)blockIdx.x * L5_LD;
 #pragma unroll
-  for (int o = 0; o < NOUT; ++o) atomicAdd(&G[OFF_W5 + j * NOUT + o], gw[o]);
-  if (j < NOUT) atomicAdd(&G[OFF_B5 + j], gb);
+  for (int o = 0; o < NOUT; ++o) pb[j * NOUT + o] = gw[o];
+  if (j < NOUT) pb[HID * NOUT + j] = gb;
+}
+
+// G[W5], G[b5] = sums of the blocks' partials (the only contributions)
+__global__ void __launch_bounds__(256) k_layer5_reduce(const float *__restrict__ part, int nblocks,
+                                                       float *__restrict__ G) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= L5_N) return;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  int b = 0;
+  for (; b + 4 <= nblocks; b += 4) {
+    s0 += part[(long long)b * L5_LD + t];
+    s1 += part[(long long)(b + 1) * L5_LD + t];
+    s2 += part[(long long)(b + 2) * L5_LD + t];
+    s3 += part[(long long)(b + 3) * L5_LD + t];
+  }
+  for (; b < nblocks; ++b) s0 += part[(long long)b * L5_LD + t];
+  G[t < HID * NOUT ? OFF_W5 + t : OFF_B5 + (t - HID * NOUT)] = (s0 + s1) + (s2 + s3);
 }
 
 // column sums of an (n x 256) FP32 matrix, accumulated into out[0..255];
@@ -1035,6 +1066,7 @@ struct rt_model_s {
   float *z[4] = {nullptr, nullptr, nullptr, nullptr};  // hidden pre-activations (FP32)
   bf16 *a[3] = {nullptr, nullptr, nullptr};            // a1..a3 (BF16)
   float *a4 = nullptr;                                 // a4 (FP32)
+  float *p5 = nullptr;                                 // layer-5 gradient partials [L5_MAXB][L5_LD]
   float *y = nullptr;                                  // standardized outputs [cap][5]
   float *dy = nullptr;                                 // [cap][5]
   float *dzf = nullptr;                                // [cap][256]
@@ -1062,7 +1094,8 @@ int reserve_acts(rt_model mo, long long n) {
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t zb = al(sizeof(float) * cap * HID), ab = al(sizeof(bf16) * cap * HID);
   const size_t yb = al(sizeof(float) * cap * NOUT), fb = al(sizeof(float) * cap * NIN);
-  const size_t bytes = 4 * zb + 3 * ab + zb + 2 * yb + zb + 2 * ab + fb;
+  const size_t pb = al(sizeof(float) * L5_MAXB * L5_LD);
+  const size_t bytes = 4 * zb + 3 * ab + zb + 2 * yb + zb + 2 * ab + fb + pb;
   void *p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
@@ -1079,6 +1112,7 @@ int reserve_acts(rt_model mo, long long n) {
   mo->dzb[0] = (bf16 *)(c + off); off += ab;
   mo->dzb[1] = (bf16 *)(c + off); off += ab;
   mo->xf = (float *)(c + off); off += fb;
+  mo->p5 = (float *)(c + off); off += pb;
   mo->act = p;
   mo->cap = cap;
   return RT_OK;
@@ -1117,7 +1151,10 @@ void gemm(hipStream_t s, const bf16 *A, long long sa0, long long sa1, const bf16
   kchunk = (kchunk + 31) & ~31;
   splits = (K + kchunk - 1) / kchunk;
   Gemm g{A, sa0, sa1, B, sb0, sb1, M, N, K, kchunk, epi, bias, Z, ldz, Cf, ldcf, Cb, ldcb, Ca, ldca};
-  hipLaunchKernelGGL(k_gemm, dim3(gblocks(M, 64), gblocks(N, 64), splits), dim3(256), 0, s, g);
+  // 64 x 64 block tiles: 128 x 128 ones (k_gemm<4, 4>) measured slower on
+  // the training shapes, whose time goes to the epilogue's activation
+  // traffic rather than to the MFMAs
+  hipLaunchKernelGGL((k_gemm<2, 2>), dim3(gblocks(M, 64), gblocks(N, 64), splits), dim3(256), 0, s, g);
 }
 
 // BF16 weights of W2 (l = 0), W3 (1), W4 (2): transposed [out][in] and row-major [in][out]
@@ -1152,9 +1189,15 @@ void backward(rt_model mo, const float *x, const float *t, long long ld, const f
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, loss, 1LL, 0.0f);
   hipLaunchKernelGGL(k_loss, dim3(gblocks((long long)n * NOUT, 256)), dim3(256), 0, s, mo->y, t, ld, wrow, n,
                      mo->scal, huber, mo->dy, loss);
-  // layer 5 accumulates 1285 gradient entries per block: a quarter of the blocks
-  hipLaunchKernelGGL(k_layer5_back, dim3(std::max(1u, rows_grid / 4)), dim3(HID), 0, s, mo->dy, mo->a4, mo->z[3], n,
-                     mo->P, mo->G, mo->dzf, mo->dzb[1]);
+  // layer 5: its per-element work (dz of layer 4) is as large as a
+  // hidden layer's and parallel over rows, so it gets blocks of >= 16 rows
+  // (up to 1024 blocks, ~16 waves per CU); the blocks' partial sums of the
+  // 1285 layer-5 gradient entries are then added in a second pass (atomics
+  // from every block would serialize on the entries' few cache lines)
+  const int l5_grid = std::min(L5_MAXB, std::max(1, n / 16));
+  hipLaunchKernelGGL(k_layer5_back, dim3(l5_grid), dim3(HID), 0, s, mo->dy, mo->a4, mo->z[3], n, mo->P, mo->p5,
+                     mo->dzf, mo->dzb[1]);
+  hipLaunchKernelGGL(k_layer5_reduce, dim3((L5_N + 255) / 256), dim3(256), 0, s, mo->p5, l5_grid, mo->G);
   // hidden layers from the top: dz of layer l (FP32 in dzf, BF16 in dzb[cur])
   const long long offw[3] = {OFF_W2, OFF_W3, OFF_W4}, offb[3] = {OFF_B2, OFF_B3, OFF_B4};
   int cur = 1;
