@@ -7,7 +7,9 @@ azimuthal uniaxial cloaks (R1 = 1, R2 = 2, height 4) in the checkerboard room
 60 deg field of view, elevations 0/15/30/45 deg, 1024 x 1024 pixels,
 ordinary and extraordinary branch traced separately, Dormand-Prince 5(4) at
 tolerance 1e-8. One step = one rt_render_multi call rendering both cloaks
-(16.8 M camera rays, one integrator launch).
+(16.8 M camera rays, one integrator launch), with the integrator's launch
+shape (block size, refill period) chosen by rt_autotune_render on the batch
+beforehand (--block / --refill fix it instead).
 
 Metric: Mrays/s traced through the cloak = rays that enter the cloak material
 per second of step time (all camera rays per second are reported too).
@@ -138,7 +140,7 @@ def cpu_baseline(opts, cams, stride, entered_only=True):
             "all_rays_per_s": n_rays / dt}
 
 
-def mixed_precision_leg(cloaks, room, cams, ms_fp64, out, steps: int = 10):
+def mixed_precision_leg(cloaks, room, cams, ms_fp64, out, opts, steps: int = 10):
     """The same render with the derivative of Eq. (8) evaluated in FP32 away
     from the inner radius (FP64 within 0.05 of r = a, and for every event and
     refraction): time per step and the exit error of each sample against the
@@ -146,8 +148,8 @@ def mixed_precision_leg(cloaks, room, cams, ms_fp64, out, steps: int = 10):
     import torch
     from paper_1209_6038_amd import rt
     from paper_1209_6038_amd import workloads as W
-    om = W.render_opts(precision=1)
-    rgb_f, aux_f = rt.render_multi(cloaks, W.render_opts(), room, cams, 3, aux=True)
+    om = dict(opts, precision=1)  # the FP64 run's launch shape
+    rgb_f, aux_f = rt.render_multi(cloaks, opts, room, cams, 3, aux=True)
     rgb_m, aux_m = rt.render_multi(cloaks, om, room, cams, 3, aux=True)
     torch.cuda.synchronize()
     both = (aux_f["status"] == 0) & (aux_m["status"] == 0)
@@ -557,9 +559,11 @@ def main():
     room = W.room()
     out = torch.empty((2, len(cams), 2, res, res, 3), dtype=torch.float32, device=dev)
     tuned_ms = None
+    if not (args.refill or args.block):
+        # launch shape (block size, refill period) from the autotuner on this
+        # batch; per-ray results do not depend on it
+        opts, tuned_ms = rt.autotune_render(cloaks, opts, room, cams, 3)
     if batched:
-        if not (args.refill or args.block):
-            opts, tuned_ms = rt.autotune_render(cloaks, opts, room, cams, 3)
         plan = rt.RenderPlan(cloaks, opts, room, cams, 3)
 
         def step():
@@ -658,7 +662,7 @@ def main():
                      "integrator_share_of_step": round(transit_ms / args.steps / ms, 4)},
     }
     if not batched and args.precision == 0:
-        rec["mixed_precision"] = mixed_precision_leg(cloaks, room, cams, ms, out)
+        rec["mixed_precision"] = mixed_precision_leg(cloaks, room, cams, ms, out, opts)
     if not args.no_cpu_baseline and not batched:
         rec["cpu_baseline"] = cpu_baseline(W.opts_dp45(), cams, args.cpu_stride)
     if not args.no_surrogate:
