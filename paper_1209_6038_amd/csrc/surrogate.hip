@@ -208,30 +208,115 @@ __global__ void __launch_bounds__(256) k_gemm(Gemm g) {
     __syncthreads();
   }
   // result layout: lane l holds D[4*(l/16) + i][l%16], i = 0..3
+  if (g.epi == EPI_ATOMIC) {
+#pragma unroll
+    for (int ti = 0; ti < WM; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < WN; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = row0 + wm * 16 * WM + ti * 16 + 4 * (lane >> 4) + r;
+          const int col = col0 + wn * 16 * WN + tj * 16 + (lane & 15);
+          if (row < g.M && col < g.N) atomicAdd(&g.Cf[row * g.ldcf + col], acc[ti][tj][r]);
+        }
+    return;
+  }
+  // the elementwise epilogues read and write whole rows: the tile goes
+  // through LDS, and each thread then owns 16 consecutive columns of a row
+  // (64-byte FP32 and 32-byte BF16 vectors, full cache lines per row)
+  __shared__ __attribute__((aligned(16))) float Cs[BM][BN + 4];
 #pragma unroll
   for (int ti = 0; ti < WM; ++ti)
 #pragma unroll
     for (int tj = 0; tj < WN; ++tj)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + wm * 16 * WM + ti * 16 + 4 * (lane >> 4) + r;
-        const int col = col0 + wn * 16 * WN + tj * 16 + (lane & 15);
-        if (row >= g.M || col >= g.N) continue;
-        const float y = acc[ti][tj][r];
-        if (g.epi == EPI_ATOMIC) {
-          atomicAdd(&g.Cf[row * g.ldcf + col], y);
-        } else if (g.epi == EPI_DSILU) {
-          const float d = y * dsilu_f(g.Z[row * g.ldz + col]);
-          if (g.Cf) g.Cf[row * g.ldcf + col] = d;
-          if (g.Cb) g.Cb[row * g.ldcb + col] = (bf16)d;
+      for (int r = 0; r < 4; ++r)
+        Cs[wm * 16 * WM + ti * 16 + 4 * (lane >> 4) + r][wn * 16 * WN + tj * 16 + (lane & 15)] = acc[ti][tj][r];
+  __syncthreads();
+  static_assert(BM % 64 == 0 && BN % 64 == 0, "epilogue passes of 64 x 64");
+#pragma unroll
+  for (int rb = 0; rb < BM; rb += 64)
+#pragma unroll
+    for (int cb = 0; cb < BN; cb += 64) {
+      const int lr = rb + (tid >> 2), lc = cb + (tid & 3) * 16;
+      const int row = row0 + lr, col = col0 + lc;
+      if (row >= g.M) continue;
+      float v[16];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 t = *reinterpret_cast<const float4 *>(&Cs[lr][lc + 4 * q]);
+        v[4 * q] = t.x; v[4 * q + 1] = t.y; v[4 * q + 2] = t.z; v[4 * q + 3] = t.w;
+      }
+      if (col + 16 <= g.N) {
+        if (g.epi == EPI_DSILU) {
+          const float *zr = g.Z + (long long)row * g.ldz + col;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float4 zz = *reinterpret_cast<const float4 *>(zr + 4 * q);
+            v[4 * q] *= dsilu_f(zz.x); v[4 * q + 1] *= dsilu_f(zz.y);
+            v[4 * q + 2] *= dsilu_f(zz.z); v[4 * q + 3] *= dsilu_f(zz.w);
+          }
+          if (g.Cf) {
+            float *o = g.Cf + (long long)row * g.ldcf + col;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              *reinterpret_cast<float4 *>(o + 4 * q) = float4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+          }
+          if (g.Cb) {
+            bf16x8 b0, b1;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) { b0[e] = (bf16)v[e]; b1[e] = (bf16)v[8 + e]; }
+            bf16 *o = g.Cb + (long long)row * g.ldcb + col;
+            *reinterpret_cast<bf16x8 *>(o) = b0;
+            *reinterpret_cast<bf16x8 *>(o + 8) = b1;
+          }
         } else {
-          const float z = y + g.bias[col];
-          const float a = silu_f(z);
-          if (g.Cf) g.Cf[row * g.ldcf + col] = z;
-          if (g.Cb) g.Cb[row * g.ldcb + col] = (bf16)a;
-          if (g.Ca) g.Ca[row * g.ldca + col] = a;
+          float a[16];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float4 bb = *reinterpret_cast<const float4 *>(g.bias + col + 4 * q);
+            v[4 * q] += bb.x; v[4 * q + 1] += bb.y; v[4 * q + 2] += bb.z; v[4 * q + 3] += bb.w;
+          }
+#pragma unroll
+          for (int e = 0; e < 16; ++e) a[e] = silu_f(v[e]);
+          if (g.Cf) {
+            float *o = g.Cf + (long long)row * g.ldcf + col;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              *reinterpret_cast<float4 *>(o + 4 * q) = float4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+          }
+          if (g.Cb) {
+            bf16x8 b0, b1;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) { b0[e] = (bf16)a[e]; b1[e] = (bf16)a[8 + e]; }
+            bf16 *o = g.Cb + (long long)row * g.ldcb + col;
+            *reinterpret_cast<bf16x8 *>(o) = b0;
+            *reinterpret_cast<bf16x8 *>(o + 8) = b1;
+          }
+          if (g.Ca) {
+            float *o = g.Ca + (long long)row * g.ldca + col;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              *reinterpret_cast<float4 *>(o + 4 * q) = float4{a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]};
+          }
+        }
+      } else {
+        for (int e = 0; e < 16 && col + e < g.N; ++e) {
+          const long long c = col + e;
+          if (g.epi == EPI_DSILU) {
+            const float d = v[e] * dsilu_f(g.Z[row * g.ldz + c]);
+            if (g.Cf) g.Cf[row * g.ldcf + c] = d;
+            if (g.Cb) g.Cb[row * g.ldcb + c] = (bf16)d;
+          } else {
+            const float z = v[e] + g.bias[c];
+            const float a = silu_f(z);
+            if (g.Cf) g.Cf[row * g.ldcf + c] = z;
+            if (g.Cb) g.Cb[row * g.ldcb + c] = (bf16)a;
+            if (g.Ca) g.Ca[row * g.ldca + c] = a;
+          }
         }
       }
+    }
 }
 
 // Network input features of entry i. The transit of the infinite cylinder
