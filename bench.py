@@ -78,9 +78,21 @@ UNRESOLVED = 1e-6
 # HBM traffic of one integrator launch from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) of this benchmark, scaled by the same counters on a
 # plain device copy of known size (bench.py --copy-probe). Valid only for the
-# integrator source it was measured on; reported as null otherwise.
+# integrator source it was measured on; reported as null otherwise. Keyed by
+# the launch shape (block, refill period) of the measured run: the figure moves
+# by about 1% between shapes, and the one nearest the run's shape is reported
+# together with the shape it was taken at.
 TRAFFIC = {"source_sha256": "3588458a586dfdba7a2945a8eee7f0c7207fedab9a84145a53225d1631bedc0b",
-           "bytes_per_launch": 775587552}
+           "bytes_per_launch": {(256, 2): 775587552, (128, 4): 767206464}}
+
+
+def traffic_for(block, refill):
+    """(bytes per integrator launch, shape it was measured at) or (None, None)."""
+    if TRAFFIC["source_sha256"] != integrator_source_hash():
+        return None, None
+    shapes = TRAFFIC["bytes_per_launch"]
+    key = min(shapes, key=lambda k: (k[0] != block, abs(k[1] - refill)))
+    return shapes[key], list(key)
 
 
 def finite_json(obj):
@@ -624,6 +636,8 @@ def main():
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
     peak = PEAK_FP64_TFLOPS if args.precision == 0 else PEAK_FP32_TFLOPS
     value = entered / (ms * 1e-3) / 1e6
+    shape = (opts.get("block") or 256, opts.get("refill_period") or 2)
+    traffic, traffic_shape = traffic_for(*shape) if not batched else (None, None)
     rec = {
         "metric": "Mrays/s traced through cloak at <=1e-6 exit error; surrogate vs plain speedup at 1e-3",
         "value": round(value, 3),
@@ -643,8 +657,8 @@ def main():
                                 "3-D render: radial + azimuthal uniaxial cloaks (R1=1, R2=2, "
                                 "height 4), checkerboard room 20x20x10, 4 elevations x 1024^2 px, "
                                 "ordinary + extraordinary, DP45 tol 1e-8"),
-                   "launch_shape": {"block": opts.get("block") or 256,
-                                    "refill_period": opts.get("refill_period") or 2,
+                   "launch_shape": {"block": shape[0],
+                                    "refill_period": shape[1],
                                     "autotuned_ms": tuned_ms},
                    "miss_fraction": round(1.0 - entered / camera_rays, 4),
                    "camera_rays_per_step": camera_rays,
@@ -654,8 +668,8 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": (TRAFFIC["bytes_per_launch"]
-                                 if TRAFFIC["source_sha256"] == integrator_source_hash() else None),
+                     "traffic": traffic,
+                     "traffic_launch_shape": traffic_shape,
                      "kernel": "k_transit (integrator)",
                      "avg_launch_ms": round(avg_launch_ms, 4),
                      "launches_per_step": launches_per_step,
