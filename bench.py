@@ -52,9 +52,10 @@ MLP_MFMA_FLOPS = 2 * 3 * 256 * 256
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 with packed instructions
 
 # Algorithmic flops (FMA = 2; add, mul, div, sqrt, rcp = 1) of one evaluation
-# of dv/dt (Eq. (8), reduced cylindrical form) per branch kind
-# (radial-o, radial-e, azimuthal-o, azimuthal-e).
-ACCEL_FLOPS = {0: 0, 1: 41, 2: 37, 3: 37}
+# of dv/dt (Eq. (8), reduced cylindrical form, radial terms reduced with
+# 1 - s = a w (1 + q)) per branch kind (radial-o, radial-e, azimuthal-o,
+# azimuthal-e).
+ACCEL_FLOPS = {0: 0, 1: 35, 2: 37, 3: 31}
 # One Dormand-Prince 5(4) attempt on the 6-component state: stage inputs
 # (20 non-zero a_sj per component, 2 flops each, + 2 per stage) 312, embedded
 # error 78, scaled RMS norm 42, controller 5.

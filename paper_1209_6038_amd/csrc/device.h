@@ -31,6 +31,7 @@ struct CloakP {
   double a, b, z0, z1;  // radii and axial extent
   double kappa;         // (b / (b - a))^2
   double a2, b2;        // a^2, b^2
+  double inv_a, inv_b;  // 1/a, 1/b
   int axis, mirror;     // 0 radial / 1 azimuthal; inner metal cylinder
 };
 
@@ -109,6 +110,9 @@ __device__ __forceinline__ double rsq64_1(double x) {
 //   azimuthal-o  k s I:        a_r = g/2 (v_t^2 + v_z^2 - v_r^2),
 //                              a_t = -g v_r v_t, a_z = -g v_r v_z
 // (radial-o: k I, zero). s'/2 = a q w^2 needs no division; g = 2 a w^2 / q.
+// Since 1 - q = a w, (1 - s) / r = a w^2 (1 + q), and the radial terms reduce
+// to a_r = a w^2 (q v_z^2 - v_t^2) (radial-e) and a_r = -a w^2 v_t^2
+// (azimuthal-e).
 // ---------------------------------------------------------------------------
 template <int KIND>
 __device__ __forceinline__ void accel64(double a, double px, double py, double vx, double vy,
@@ -128,13 +132,11 @@ __device__ __forceinline__ void accel64(double a, double px, double py, double v
     double gvr = (2.0 * a) * w2 * rcp64_1(q) * (P * w);  // g v_r
     double ar, at;
     if constexpr (KIND == K_RE) {
-      double s = q * q;
-      ar = fma(a * q * w2, fma(vz, vz, vt2), -(1.0 - s) * vt2 * w);
+      ar = a * w2 * fma(q * vz, vz, -vt2);
       at = -gvr * vt;
       az = -gvr * vz;
     } else if constexpr (KIND == K_AE) {
-      double s = q * q;
-      ar = vt2 * fma(a * q, w2, -(1.0 - s) * w);
+      ar = -a * w2 * vt2;
       at = -gvr * vt;
       az = 0.0;
     } else {
@@ -286,7 +288,7 @@ __device__ __forceinline__ double dp45_attempt(double a, double band2, const dou
       for (int i = 0; i < 3; ++i) { xn[i] = X[i]; vn[i] = V[i]; }
     }
   }
-  double sum = 0.0;
+  double e6[6], s6[6];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     double ex = 0.0, ev = 0.0;
@@ -295,12 +297,36 @@ __device__ __forceinline__ double dp45_attempt(double a, double band2, const dou
       if (dp_ea(l) != 0.0) ex = fma(dp_ea(l), A[l][i], ex);
       if (DP::E[l] != 0.0) ev = fma(DP::E[l], A[l][i], ev);
     }
-    ex *= h * h;
-    ev *= h;
-    double sx = fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol);
-    double sv = fma(rtol, fmax(fabs(v[i]), fabs(vn[i])), atol);
-    double qx = ex * rcp64(sx), qv = ev * rcp64(sv);
-    sum = fma(qx, qx, fma(qv, qv, sum));
+    e6[2 * i] = ex * (h * h);
+    e6[2 * i + 1] = ev * h;
+    s6[2 * i] = fma(rtol, fmax(fabs(x[i]), fabs(xn[i])), atol);
+    s6[2 * i + 1] = fma(rtol, fmax(fabs(v[i]), fabs(vn[i])), atol);
+  }
+  double sum = 0.0;
+  if (atol >= 1e-40) {
+    // every scale is at least atol >= 1e-40, so the product of the six stays
+    // above 1e-240 (and overflows only for states beyond 1e50), and
+    // 1/s_k = (prod_{j != k} s_j) / prod_j s_j takes one reciprocal instead
+    // of six
+    double pre[6], suf[6];
+    pre[0] = 1.0;
+    suf[5] = 1.0;
+#pragma unroll
+    for (int k = 1; k < 6; ++k) pre[k] = pre[k - 1] * s6[k - 1];
+#pragma unroll
+    for (int k = 4; k >= 0; --k) suf[k] = suf[k + 1] * s6[k + 1];
+    const double r = rcp64(pre[5] * s6[5]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const double q = e6[k] * (pre[k] * suf[k]) * r;
+      sum = fma(q, q, sum);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const double q = e6[k] * rcp64(s6[k]);
+      sum = fma(q, q, sum);
+    }
   }
   return sum;
 }
@@ -385,8 +411,8 @@ __device__ __forceinline__ double gsq(const CloakP& c, int id, const double x[3]
 __device__ __forceinline__ double gsq_slope(const CloakP& c, int id, const double x[3], const double v[3]) {
   double rv = fma(x[0], v[0], x[1] * v[1]);
   switch (id) {
-    case B_SIDE: return rv / c.b;
-    case B_INNER: return -rv / c.a;
+    case B_SIDE: return rv * c.inv_b;
+    case B_INNER: return -rv * c.inv_a;
     case B_TOP: return v[2];
     default: return -v[2];
   }

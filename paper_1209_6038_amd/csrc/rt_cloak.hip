@@ -416,17 +416,21 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
     }
     // the step left the material: search the earliest crossing, starting
     // from the boundary with the smallest linearly interpolated fraction
-    double best = 2.0;
+    // -g0 / (g1 - g0) (compared as num * den' < num' * den, denominators
+    // positive; one reciprocal for the winner: the fraction only seeds the
+    // search)
+    double bn = 2.0, bd = 1.0;
     int rid = B_SIDE;
 #pragma unroll
     for (int id = 0; id < 4; ++id) {
       double g1 = gsq(c, id, xn);
       if (g1 >= 0.0) {
         double g0 = fmin(gsq(c, id, L.x), -1e-300);
-        double fr = -g0 / (g1 - g0);
-        if (fr < best) { best = fr; rid = id; }
+        double num = -g0, den = g1 - g0;
+        if (num * bd < bn * den) { bn = num; bd = den; rid = id; }
       }
     }
+    const double best = bn * rcp64_1(bd);
     L.rid = rid;
     L.lo = 0.0;
     L.hi = hs;
@@ -440,7 +444,7 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
   ++L.riter;
   if (!(fabs(f) <= tol || L.riter >= 100 || !(L.hi - L.lo > 1e-300))) {
     if (f < 0.0) L.lo = L.ht; else L.hi = L.ht;
-    double hn = L.ht - f / gsq_slope(c, L.rid, xn, vn);
+    double hn = L.ht - f * rcp64_1(gsq_slope(c, L.rid, xn, vn));
     if (!(hn > L.lo && hn < L.hi)) hn = 0.5 * (L.lo + L.hi);
     L.ht = hn;
     return -1;
@@ -1192,6 +1196,7 @@ CloakP make_cloak(const rt_cloak_desc &d) {
   double q = d.r2 / (d.r2 - d.r1);
   c.kappa = q * q;
   c.a2 = d.r1 * d.r1; c.b2 = d.r2 * d.r2;
+  c.inv_a = 1.0 / d.r1; c.inv_b = 1.0 / d.r2;
   c.axis = d.axis; c.mirror = d.inner_mirror;
   return c;
 }
