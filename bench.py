@@ -6,18 +6,23 @@ azimuthal uniaxial cloaks (R1 = 1, R2 = 2, height 4) in the checkerboard room
 [-10,10]^2 x [0,10] (0.5 tiles), pinhole camera at distance 8 from (0,0,2),
 60 deg field of view, elevations 0/15/30/45 deg, 1024 x 1024 pixels,
 ordinary and extraordinary branch traced separately, Dormand-Prince 5(4) at
-tolerance 1e-8. One step = one rt_render_multi call rendering both cloaks
-(16.8 M camera rays, one integrator launch), with the integrator's launch
-shape (block size, refill period) chosen by rt_autotune_render on the batch
-beforehand (--block / --refill fix it instead).
+tolerance 1e-8. One step renders both cloaks (16.8 M camera rays, one
+integrator launch), with the integrator's launch shape (block size, refill
+period) chosen by rt_autotune_render on the batch beforehand (--block /
+--refill fix it instead). The batch is recorded into --streams render plans
+(rt_render_plan_*, each with its own workspace and output images), and step k
+replays plan k mod S on stream k mod S: consecutive steps overlap, so one
+step's last rays and small kernels share the chip with the next step's bulk.
+The integrator's launch time for the roofline is measured on eager,
+one-at-a-time launches of the same batch (HIP events on the launch stream).
 
 Metric: Mrays/s traced through the cloak = rays that enter the cloak material
 per second of step time (all camera rays per second are reported too).
 
 --workload batched times the batched workload instead: 64 seeded views
 (azimuth U[0, 2 pi), elevation U[0, 60] deg) at 512 x 512, both cloaks, both
-branches, recorded once into a HIP graph (rt_render_plan_*) and replayed, with
-the integrator's launch shape chosen by rt_autotune_render.
+branches, replayed from render plans in the same way, with the integrator's
+launch shape chosen by rt_autotune_render.
 
 Surrogate leg (the "surrogate vs plain speedup at 1e-3" half of the metric,
 skipped with --no-surrogate): 10 M seeded entries on the outer cylinder of the
@@ -83,8 +88,8 @@ UNRESOLVED = 1e-6
 # the launch shape (block, refill period) of the measured run: the figure moves
 # by about 1% between shapes, and the one nearest the run's shape is reported
 # together with the shape it was taken at.
-TRAFFIC = {"source_sha256": "3588458a586dfdba7a2945a8eee7f0c7207fedab9a84145a53225d1631bedc0b",
-           "bytes_per_launch": {(256, 2): 775587552, (128, 4): 767206464}}
+TRAFFIC = {"source_sha256": "ab189b21863ba513b566880dfa9e6bc77a003d60120f9af90828d69822320082",
+           "bytes_per_launch": {(256, 8): 790980768}}
 
 
 def traffic_for(block, refill):
@@ -521,6 +526,8 @@ def main():
                     default="render3d")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed")
     ap.add_argument("--refill", type=int, default=0)
+    ap.add_argument("--streams", type=int, default=3,
+                    help="render plans replayed on this many streams, consecutive steps overlapping")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--cpu-stride", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -531,6 +538,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
+    if not 1 <= args.streams <= 4:
+        ap.error("--streams must be in 1..4")
     if not 1 <= args.frames_per_launch <= 4:
         ap.error("--frames-per-launch must be in 1..4 (at most 2^28 samples per launch)")
     if args.copy_probe:
@@ -576,16 +585,15 @@ def main():
         # launch shape (block size, refill period) from the autotuner on this
         # batch; per-ray results do not depend on it
         opts, tuned_ms = rt.autotune_render(cloaks, opts, room, cams, 3)
-    if batched:
-        plan = rt.RenderPlan(cloaks, opts, room, cams, 3)
+    # one plan per stream (own workspace and images); step k replays plan
+    # k mod S on stream k mod S: all cloaks, views and branches of the batch
+    # in one pass (one integrator launch)
+    plans = [rt.RenderPlan(cloaks, opts, room, cams, 3) for _ in range(args.streams)]
+    streams = [torch.cuda.Stream() for _ in range(args.streams)]
 
-        def step():
-            # the whole batch: one replay of the captured graph
-            plan.launch()
-    else:
-        def step():
-            # both cloaks, 4 views, both branches in one pass (one integrator launch)
-            rt.render_multi(cloaks, opts, room, cams, 3, out=out)
+    def step(k):
+        with torch.cuda.stream(streams[k % args.streams]):
+            plans[k % args.streams].launch()
 
     # untimed counting pass: entering rays and integrator step attempts
     entered = 0
@@ -602,34 +610,38 @@ def main():
             flops += int(ns[ci, :, pi].sum()) * attempt_flops(kind, opts["scheme"])
     camera_rays = 2 * len(cams) * 2 * res * res
 
-    for _ in range(args.warmup):
-        step()
+    for k in range(max(args.warmup, args.streams)):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # every plan rendered the batch: the images agree with an eager render
+    rt.render_multi(cloaks, opts, room, cams, 3, out=out)
+    torch.cuda.synchronize()
+    images_equal = all(torch.equal(p.rgb, out) for p in plans)
+    for p in plans:
+        p.close()
+    del plans
+    # graph replays carry no timing events, and overlapped launches share the
+    # chip: time the integrator on eager, one-at-a-time launches of the same
+    # batch (same kernels, same launch shape), HIP events on the launch stream
+    rt.render_multi(cloaks, opts, room, cams, 3, out=out)
     torch.cuda.synchronize()
     rt.profile_enable(True)
     rt.profile_read()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     e0.record()
     for _ in range(args.steps):
-        step()
+        rt.render_multi(cloaks, opts, room, cams, 3, out=out)
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    eager_ms = e0.elapsed_time(e1) / args.steps
     transit_ms, launches = rt.profile_read()
     launches_per_step = launches / args.steps
-    if batched:
-        # graph replays carry no timing events: time the integrator of the
-        # same batch in eager launches (same kernels, same launch shape)
-        for _ in range(2):
-            rt.render_multi(cloaks, opts, room, cams, 3, out=out)
-        torch.cuda.synchronize()
-        rt.profile_read()
-        for _ in range(args.steps):
-            rt.render_multi(cloaks, opts, room, cams, 3, out=out)
-        torch.cuda.synchronize()
-        transit_ms, launches = rt.profile_read()
-        launches_per_step = launches / args.steps
     rt.profile_enable(False)
 
     avg_launch_ms = transit_ms / max(launches, 1)
@@ -658,6 +670,9 @@ def main():
                                 "3-D render: radial + azimuthal uniaxial cloaks (R1=1, R2=2, "
                                 "height 4), checkerboard room 20x20x10, 4 elevations x 1024^2 px, "
                                 "ordinary + extraordinary, DP45 tol 1e-8"),
+                   "streams": args.streams,
+                   "eager_ms_per_step": round(eager_ms, 4),
+                   "images_equal_across_streams": images_equal,
                    "launch_shape": {"block": shape[0],
                                     "refill_period": shape[1],
                                     "autotuned_ms": tuned_ms},
@@ -674,10 +689,10 @@ def main():
                      "kernel": "k_transit (integrator)",
                      "avg_launch_ms": round(avg_launch_ms, 4),
                      "launches_per_step": launches_per_step,
-                     "integrator_share_of_step": round(transit_ms / args.steps / ms, 4)},
+                     "integrator_share_of_eager_step": round(transit_ms / args.steps / eager_ms, 4)},
     }
     if not batched and args.precision == 0:
-        rec["mixed_precision"] = mixed_precision_leg(cloaks, room, cams, ms, out, opts)
+        rec["mixed_precision"] = mixed_precision_leg(cloaks, room, cams, eager_ms, out, opts)
     if not args.no_cpu_baseline and not batched:
         rec["cpu_baseline"] = cpu_baseline(W.opts_dp45(), cams, args.cpu_stride)
     if not args.no_surrogate:
