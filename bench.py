@@ -69,6 +69,11 @@ DP45_STAGES = 6
 # RK4: stage inputs 3 x 6 FMA + 3, final combination 6 x 8.
 RK4_COMBINE_FLOPS = 75 + 48
 RK4_STAGES = 4
+# The Hamiltonian form (scheme 2): one evaluation of (dx/dtau, dk/dtau,
+# dt/dtau) in the reduced cylindrical form per branch kind, and the RK4
+# combination of the 7-component state (x, k, t).
+HAM_RHS_FLOPS = {0: 3, 1: 48, 2: 18, 3: 51}
+HAM_COMBINE_FLOPS = 78
 
 
 def attempt_flops(kind: int, scheme: int) -> int:
@@ -458,6 +463,87 @@ def inplane_workload(args):
     }
 
 
+def hamiltonian_workload(args):
+    """The comparison of Sect. 4: the ray equation Eq. (8) with fixed RK4
+    steps in the optical path t against the Hamiltonian form (state (x, k),
+    H = k^T eps k - eps_o eps_e, fixed RK4 steps in the ray parameter tau),
+    on rays for which perfect cloaking is expected: the in-plane workload's
+    extraordinary rays through the radial cloak (16,384 impact parameters x 8
+    angles), whose exact exit is the incident line continued (CF1). Two sets
+    of entering rays: impact parameter 0.3 <= |p| < 1.999 ("wide"), and
+    1e-3 <= |p| < 0.3 ("near axis"; closer in, both forms stall). For each
+    form and set, a sweep of step sizes gives the largest exit error
+    (position / R2 and direction; a ray that does not exit counts as
+    infinite) and the time per rt_trace_batch call on that set (HIP events);
+    the forms are compared at the largest step that meets 1e-8."""
+    import numpy as np
+    import torch
+    from paper_1209_6038_amd import rt
+    from paper_1209_6038_amd import workloads as W
+
+    bundle = W.inplane_bundle(16384, 8)
+    pb = bundle[0] * (-bundle[4]) + bundle[1] * bundle[3]
+    sets = {"wide": (np.abs(pb) >= 0.3) & (np.abs(pb) < 1.999),
+            "near_axis": (np.abs(pb) >= 1e-3) & (np.abs(pb) < 0.3)}
+    cl = rt.Cloak(W.cloak(W.RADIAL))
+    target = 1e-8
+
+    def sweep(make, steps, sel):
+        rays_np = np.ascontiguousarray(bundle[:, sel])
+        rays = torch.from_numpy(rays_np).cuda()
+        o, d, p = rays_np[:3], rays_np[3:], pb[sel]
+        want = o + 2.0 * np.sqrt(9.0 - p ** 2) * d
+        rows = []
+        for h in steps:
+            opts = make(h)
+            r = rt.trace_batch(cl, opts, W.EXTRAORDINARY, rays)
+            torch.cuda.synchronize()
+            st = r["status"].cpu().numpy()
+            out = r["out"].cpu().numpy()
+            err = np.maximum(np.linalg.norm(out[:3] - want, axis=0) / W.R2, np.linalg.norm(out[3:] - d, axis=0))
+            err = np.where(st == 0, err, np.inf)
+            ns = r["nsteps"].cpu().numpy().astype(np.int64)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            rt.profile_enable(True)
+            rt.profile_read()
+            a.record()
+            for _ in range(3):
+                rt.trace_batch(cl, opts, W.EXTRAORDINARY, rays, with_aux=False)
+            b.record()
+            torch.cuda.synchronize()
+            transit_ms, launches = rt.profile_read()
+            rt.profile_enable(False)
+            launch_ms = transit_ms / max(1, launches)
+            per_step = (HAM_COMBINE_FLOPS + 4 * HAM_RHS_FLOPS[1] if opts["scheme"] == 2
+                        else attempt_flops(1, 0))
+            tflops = float(ns.sum()) * per_step / (launch_ms * 1e-3) / 1e12
+            rows.append({"step": h, "ms_per_call": round(a.elapsed_time(b) / 3, 4),
+                         "integrator_launch_ms": round(launch_ms, 4),
+                         "integrator_fp64_frac": round(tflops / PEAK_FP64_TFLOPS, 4),
+                         "steps_per_ray": round(float(ns.mean()), 1), "max_steps_of_a_ray": int(ns.max()),
+                         "max_exit_err": float(f"{err.max():.3e}"), "not_exited": int((st != 0).sum())})
+        return rows
+
+    res = {}
+    for name, sel in sets.items():
+        eq8 = sweep(lambda h: W.opts_rk4(h, max_steps=200_000), (4e-3, 2e-3, 1e-3, 5e-4, 2.5e-4), sel)
+        ham = sweep(lambda h: W.opts_rk4_ham(h, max_steps=200_000), (1.6e-2, 8e-3, 4e-3, 2e-3, 1e-3), sel)
+        ok_e = [r for r in eq8 if r["max_exit_err"] <= target]
+        ok_h = [r for r in ham if r["max_exit_err"] <= target]
+        e = max(ok_e, key=lambda r: r["step"]) if ok_e else None
+        h = max(ok_h, key=lambda r: r["step"]) if ok_h else None
+        res[name] = {"rays": int(sel.sum()), "eq8_rk4_in_t": eq8, "hamiltonian_rk4_in_tau": ham,
+                     "at_target": {"eq8": e and {"step": e["step"], "ms_per_call": e["ms_per_call"]},
+                                   "hamiltonian": h and {"step": h["step"], "ms_per_call": h["ms_per_call"]},
+                                   "time_ratio_hamiltonian_over_eq8": (round(h["ms_per_call"] / e["ms_per_call"], 3)
+                                                                       if e and h else None)}}
+    return {"config": {"workload": "Sect. 4 comparison: Eq. (8) vs the Hamiltonian form, fixed-step RK4, "
+                                   "in-plane radial cloak, extraordinary rays, exact exit = incident line (CF1), "
+                                   "FP64", "target_exit_error": target, "max_steps": 200_000},
+            **res}
+
+
 def orbit_workload(args):
     """The large-render workload timed plain: 36-frame orbit at 30 deg
     elevation, 4096 x 4096 px, 4 jittered samples per pixel, radial and
@@ -522,7 +608,7 @@ def main():
     ap.add_argument("--res", type=int, default=1024)
     ap.add_argument("--frames-per-launch", type=int, default=2,
                     help="orbit workload and surrogate render: 4096^2 x 4 spp frames per integrator launch (1-4)")
-    ap.add_argument("--workload", choices=("render3d", "batched", "orbit", "surrogate", "inplane"),
+    ap.add_argument("--workload", choices=("render3d", "batched", "orbit", "surrogate", "inplane", "hamiltonian"),
                     default="render3d")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed")
     ap.add_argument("--refill", type=int, default=0)
@@ -566,6 +652,9 @@ def main():
         return
     if args.workload == "inplane":
         print(json.dumps(finite_json(inplane_workload(args))), flush=True)
+        return
+    if args.workload == "hamiltonian":
+        print(json.dumps(finite_json(hamiltonian_workload(args))), flush=True)
         return
     if args.workload == "surrogate":
         torch.cuda.set_device(0)

@@ -43,7 +43,7 @@ enum { RT_AXIS_RADIAL = 0, RT_AXIS_AZIMUTHAL = 1 };
 /* Ray branch inside the cloak (Sect. 2): ordinary (Eq. (2)) or extraordinary (Eq. (8)). */
 enum { RT_POL_ORDINARY = 0, RT_POL_EXTRAORDINARY = 1 };
 
-enum { RT_SCHEME_RK4 = 0, RT_SCHEME_DP45 = 1 };
+enum { RT_SCHEME_RK4 = 0, RT_SCHEME_DP45 = 1, RT_SCHEME_RK4_HAM = 2 };
 enum { RT_PREC_FP64 = 0, RT_PREC_MIXED = 1 };
 
 /* Per-ray outcome. */
@@ -75,7 +75,14 @@ typedef struct {
 
 /* Integration options. scheme: RT_SCHEME_RK4 (fixed step h, the paper's
    fourth-order Runge-Kutta, Sect. 4) or RT_SCHEME_DP45 (Dormand-Prince 5(4),
-   initial step h, tolerances rtol/atol, maximum step hmax). precision:
+   initial step h, tolerances rtol/atol, maximum step hmax), both on the ray
+   equation Eq. (8)/(2) in (x, v). RT_SCHEME_RK4_HAM: the Hamiltonian form the
+   paper compares against (Sect. 4): state (x, k), H = k^T A k - f with A = eps
+   and f = eps_o eps_e (extraordinary) or A = I and f = eps_o (ordinary),
+   classical RK4 with the fixed step h in the ray parameter tau
+   (dx/dtau = 2 A k, dt/dtau = 2 f); FP64 only. Interfaces, events and
+   outputs are those of the other schemes (k is converted to v = M^-1 k at
+   every interface). precision:
    RT_PREC_FP64, or RT_PREC_MIXED (FP32 derivative evaluation where
    r - r1 >= fp64_band, FP64 state and step combination everywhere).
    r_out: report radius of rt_trace_batch (>= r2). max_steps: step attempts per

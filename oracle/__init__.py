@@ -9,7 +9,7 @@ with ctypes, and fed plain numpy arrays.
 
 Descriptions are plain dicts (the same keys the GPU binding accepts):
   cloak:  r1, r2, z0, z1, axis (0 radial Eq. (14), 1 azimuthal Eq. (15)), inner_mirror
-  opts:   scheme (0 RK4, 1 DP45), h, rtol, atol, hmax, r_out, max_steps, max_bounces
+  opts:   scheme (0 RK4, 1 DP45, 2 RK4 on the Hamiltonian form), h, rtol, atol, hmax, r_out, max_steps, max_bounces
   camera: eye, look, up, fov_deg, w, h, spp, seed
   room:   lo, hi, tile, rgb (6 faces x 2 parities x 3)
 """

@@ -19,6 +19,11 @@
  *                           bisection; ray velocity from Eq. (6)
  *   - integrator:           classical fourth-order Runge-Kutta (Sect. 4), and
  *                           the Dormand-Prince 5(4) pair for adaptive runs
+ *   - Hamiltonian form:     the alternative tracer Sect. 4 compares against:
+ *                           H(x, k) = k^T A k - f from the Cartesian tensor
+ *                           of Eq. (1) (A = eps, f = eps_o eps_e, or A = I,
+ *                           f = eps_o), gradient by dual numbers, RK4 in the
+ *                           ray parameter
  *   - inner metal cylinder: single specular reflection (Sect. 4)
  * Units: c0 = omega = 1, so |k| is the phase index and the ODE time is the
  * optical path length. Everything is FP64, plain loops, no SIMD intrinsics.
@@ -488,6 +493,157 @@ static int integrate(const orc_cloak *c, int branch, const orc_opts *o, double *
 }
 
 /* ------------------------------------------------------------------ */
+/* Hamiltonian form of the ray equations (Sect. 4: the alternative the  */
+/* paper compares its Eq. (8) tracer against)                          */
+/* ------------------------------------------------------------------ */
+/* H(x, k) = k^T A(x) k - f(x) vanishes on every ray. Extraordinary wave:
+   A = eps, f = eps_o eps_e, since k^T eps k = eps_o eps_e is the uniaxial
+   dispersion relation (Eq. (6) with M = eps_o eps_e eps^-1, Eq. (7)).
+   Ordinary wave: A = I, f = eps_o. With the ray parameter tau,
+   dx/dtau = dH/dk = 2 A k and dk/dtau = -dH/dx; because the ray velocity is
+   v = dx/dt = M^-1 k = A k / f, the optical path advances as dt/dtau = 2 f. */
+static void ham_parts(const orc_cloak *c, int branch, const dual x[3], dual A[3][3], dual *f) {
+    dual E[3][3], eo, ee;
+    eps_cart(c, x, E, &eo, &ee);
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            A[i][j] = branch == ORC_EXTRAORDINARY ? E[i][j] : dk(i == j ? 1.0 : 0.0);
+    *f = branch == ORC_EXTRAORDINARY ? dmul(eo, ee) : eo;
+}
+
+/* y = (x, k, t): dy/dtau, the gradient of H by forward-mode duals */
+static void rhs_ham(const orc_cloak *c, int branch, const double *y, double *dy) {
+    const double *k = y + 3;
+    double A[3][3], dH[3], f = 0.0;
+    for (int m = 0; m < 3; m++) {
+        dual x[3], Ad[3][3], fd;
+        for (int i = 0; i < 3; i++) x[i] = mkd(y[i], i == m ? 1.0 : 0.0);
+        ham_parts(c, branch, x, Ad, &fd);
+        double s = 0.0;
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                A[i][j] = Ad[i][j].v;
+                s += k[i] * Ad[i][j].d * k[j];
+            }
+        dH[m] = s - fd.d;
+        f = fd.v;
+    }
+    for (int i = 0; i < 3; i++) {
+        double s = 0.0;
+        for (int j = 0; j < 3; j++) s += A[i][j] * k[j];
+        dy[i] = 2.0 * s;
+        dy[3 + i] = -dH[i];
+    }
+    dy[6] = 2.0 * f;
+}
+
+/* classical RK4 in tau on the 7-component state (x, k, t) */
+static void rk4_ham(const orc_cloak *c, int branch, const double *y, double h, double *out) {
+    double k1[7], k2[7], k3[7], k4[7], t[7];
+    rhs_ham(c, branch, y, k1);
+    for (int i = 0; i < 7; i++) t[i] = y[i] + 0.5 * h * k1[i];
+    rhs_ham(c, branch, t, k2);
+    for (int i = 0; i < 7; i++) t[i] = y[i] + 0.5 * h * k2[i];
+    rhs_ham(c, branch, t, k3);
+    for (int i = 0; i < 7; i++) t[i] = y[i] + h * k3[i];
+    rhs_ham(c, branch, t, k4);
+    for (int i = 0; i < 7; i++)
+        out[i] = y[i] + h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+}
+
+/* k = M v = f A^-1 v, and back v = A k / f, at the point x */
+static void ham_v_to_k(const orc_cloak *c, int branch, const double *x, const double *v, double *k) {
+    dual xd[3] = { dk(x[0]), dk(x[1]), dk(x[2]) }, Ad[3][3], fd;
+    ham_parts(c, branch, xd, Ad, &fd);
+    double A[3][3], Ai[3][3];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) A[i][j] = Ad[i][j].v;
+    inv3(A, Ai);
+    for (int i = 0; i < 3; i++) k[i] = fd.v * (Ai[i][0] * v[0] + Ai[i][1] * v[1] + Ai[i][2] * v[2]);
+}
+
+static void ham_k_to_v(const orc_cloak *c, int branch, const double *x, const double *k, double *v) {
+    dual xd[3] = { dk(x[0]), dk(x[1]), dk(x[2]) }, Ad[3][3], fd;
+    ham_parts(c, branch, xd, Ad, &fd);
+    for (int i = 0; i < 3; i++)
+        v[i] = (Ad[i][0].v * k[0] + Ad[i][1].v * k[1] + Ad[i][2].v * k[2]) / fd.v;
+}
+
+/* bisection on the tau step for boundary `id`, as crossing() */
+static double crossing_ham(const orc_cloak *c, int branch, const double *y, double h, int id,
+                           double *yout) {
+    double lo = 0.0, hi = h, mid = h, tol = 1e-13 * c->b;
+    double ym[7];
+    for (int it = 0; it < 400; it++) {
+        double m = 0.5 * (lo + hi);
+        if (!(m > lo && m < hi)) break;
+        mid = m;
+        rk4_ham(c, branch, y, mid, ym);
+        double g = gfun(c, id, ym);
+        if (fabs(g) <= tol) break;
+        if (g < 0.0) lo = mid; else hi = mid;
+    }
+    rk4_ham(c, branch, y, mid, yout);
+    return mid;
+}
+
+/* integrate() for the Hamiltonian form with fixed RK4 steps in tau. y holds
+   (x, v) on entry and return (converted to and from k at the ends); *t
+   advances by the optical path. */
+static int integrate_ham(const orc_cloak *c, int branch, const orc_opts *o, double *y,
+                         double *t, int64_t *nsteps) {
+    double z[7], zn[7], h = o->h;
+    memcpy(z, y, 3 * sizeof(double));
+    ham_v_to_k(c, branch, y, y + 3, z + 3);
+    z[6] = 0.0;
+    int ev = -1;
+    for (;;) {
+        if (*nsteps >= o->max_steps) { ev = EV_MAXSTEPS; break; }
+        (*nsteps)++;
+        rk4_ham(c, branch, z, h, zn);
+        int fin = 1;
+        for (int i = 0; i < 7; i++) fin &= isfinite(zn[i]) ? 1 : 0;
+        if (!fin) { ev = EV_DIVERGED; break; }
+        int first = -1;
+        double hfirst = 0.0, zfirst[7];
+        for (int id = 0; id < 4; id++) {
+            if (gfun(c, id, zn) >= 0.0) {
+                double zc[7];
+                double hc = crossing_ham(c, branch, z, h, id, zc);
+                if (first < 0 || hc < hfirst) {
+                    first = id; hfirst = hc;
+                    memcpy(zfirst, zc, sizeof(zc));
+                }
+            }
+        }
+        /* radial-o: straight chords (A = I, f constant); a chord can dip
+           into r < a and leave it again within one step */
+        if (first < 0 && c->axis == ORC_AXIS_RADIAL && branch == ORC_ORDINARY) {
+            double dx = zn[0] - z[0], dy = zn[1] - z[1];
+            double dd = dx * dx + dy * dy;
+            if (dd > 0.0) {
+                double f = -(z[0] * dx + z[1] * dy) / dd;
+                double px = z[0] + f * dx, py = z[1] + f * dy;
+                if (f > 0.0 && f < 1.0 && px * px + py * py < c->a * c->a) {
+                    crossing_ham(c, branch, z, f * h, EV_INNER, zfirst);
+                    first = EV_INNER;
+                }
+            }
+        }
+        if (first >= 0) {
+            memcpy(z, zfirst, sizeof(zfirst));
+            ev = first;
+            break;
+        }
+        memcpy(z, zn, sizeof(zn));
+    }
+    memcpy(y, z, 3 * sizeof(double));
+    ham_k_to_v(c, branch, z, z + 3, y + 3);
+    *t += z[6];
+    return ev;
+}
+
+/* ------------------------------------------------------------------ */
 /* Sect. 3: refraction at the vacuum/crystal interface                 */
 /* ------------------------------------------------------------------ */
 
@@ -697,7 +853,8 @@ static int trace_vacuum(const orc_cloak *c, int branch, const orc_opts *o,
     double t = 0.0;
     int bounces = 0, status;
     for (;;) {
-        int ev = integrate(c, branch, o, y, &t, nsteps);
+        int ev = o->scheme == ORC_RK4_HAM ? integrate_ham(c, branch, o, y, &t, nsteps)
+                                          : integrate(c, branch, o, y, &t, nsteps);
         if (ev == EV_MAXSTEPS) { status = ORC_MAXSTEPS; break; }
         if (ev == EV_DIVERGED) { status = ORC_DIVERGED; break; }
         double nn[3];

@@ -372,6 +372,106 @@ __device__ __forceinline__ void rk4_step(double a, double band2, const double x[
 }
 
 // ---------------------------------------------------------------------------
+// Hamiltonian form of the ray equations (the alternative of Sect. 4):
+// H(x, k) = k^T A k - f with A = diag(A_r, A_t, A_z) in (r_hat, theta_hat,
+// z_hat); A = eps, f = eps_o eps_e = kappa^2 s for the extraordinary branches,
+// A = I, f = eps_o for the ordinary ones. H = f (k^T M^-1 k - 1), so A = f M^-1:
+//   radial-e    A = kappa (s, 1, 1),    f = kappa^2 s
+//   azimuthal-e A = kappa (s, 1, s),    f = kappa^2 s
+//   azimuthal-o A = I,                  f = kappa s
+//   radial-o    A = I,                  f = kappa
+// dx/dtau = 2 A k; with k_r = k . r_hat, k_t = k . theta_hat,
+//   dk/dtau = -r_hat [A_t' |k_xy|^2 + (A_r' - A_t') k_r^2 + A_z' k_z^2 - f']
+//             - 2 (A_r - A_t) k_r k_t theta_hat / r,
+// and the optical path advances as dt/dtau = 2 f (v = M^-1 k = A k / f).
+// ---------------------------------------------------------------------------
+template <int KIND>
+__device__ __forceinline__ void ham_rhs(double a, double kappa, const double x[3], const double k[3],
+                                        double dx[3], double dk[3], double& dt) {
+  if constexpr (KIND == K_RO) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { dx[i] = 2.0 * k[i]; dk[i] = 0.0; }
+    dt = 2.0 * kappa;
+  } else {
+    const double r2 = fma(x[0], x[0], x[1] * x[1]);
+    const double w = rsq64_1(r2);
+    const double q = fma(-a, w, 1.0);
+    const double s = q * q;
+    const double sp = 2.0 * a * q * w * w;  // ds/dr
+    if constexpr (KIND == K_AO) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) dx[i] = 2.0 * k[i];
+      const double g = kappa * sp * w;  // f' along r_hat, r_hat = w x
+      dk[0] = g * x[0];
+      dk[1] = g * x[1];
+      dk[2] = 0.0;
+      dt = 2.0 * kappa * s;
+    } else {
+      const double kr = fma(x[0], k[0], x[1] * k[1]) * w;
+      const double kt = fma(x[0], k[1], -x[1] * k[0]) * w;
+      // dx/dtau = 2 kappa (s k_r r_hat + k_t theta_hat, (1 or s) k_z)
+      const double ur = 2.0 * kappa * s * kr * w, ut = 2.0 * kappa * kt * w;
+      dx[0] = fma(ur, x[0], -ut * x[1]);
+      dx[1] = fma(ur, x[1], ut * x[0]);
+      double P;  // radial component of dk/dtau
+      if constexpr (KIND == K_RE) {
+        dx[2] = 2.0 * kappa * k[2];
+        P = -kappa * sp * fma(kr, kr, -kappa);
+      } else {
+        dx[2] = 2.0 * kappa * s * k[2];
+        P = -kappa * sp * (fma(kr, kr, k[2] * k[2]) - kappa);
+      }
+      const double Qt = 2.0 * kappa * (1.0 - s) * kr * kt * w;  // theta component
+      dk[0] = fma(P * w, x[0], -Qt * w * x[1]);
+      dk[1] = fma(P * w, x[1], Qt * w * x[0]);
+      dk[2] = 0.0;
+      dt = 2.0 * kappa * kappa * s;
+    }
+  }
+}
+
+// classical RK4 with step h in tau on (x, k); dt = optical path of the step
+template <int KIND>
+__device__ __forceinline__ void rk4_ham_step(double a, double kappa, const double x[3], const double k[3],
+                                             double h, double xn[3], double kn[3], double& dt) {
+  double d1x[3], d1k[3], d2x[3], d2k[3], d3x[3], d3k[3], d4x[3], d4k[3], X[3], K[3];
+  double t1, t2, t3, t4;
+  const double hh = 0.5 * h;
+  ham_rhs<KIND>(a, kappa, x, k, d1x, d1k, t1);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { X[i] = fma(hh, d1x[i], x[i]); K[i] = fma(hh, d1k[i], k[i]); }
+  ham_rhs<KIND>(a, kappa, X, K, d2x, d2k, t2);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { X[i] = fma(hh, d2x[i], x[i]); K[i] = fma(hh, d2k[i], k[i]); }
+  ham_rhs<KIND>(a, kappa, X, K, d3x, d3k, t3);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { X[i] = fma(h, d3x[i], x[i]); K[i] = fma(h, d3k[i], k[i]); }
+  ham_rhs<KIND>(a, kappa, X, K, d4x, d4k, t4);
+  const double h6 = h * (1.0 / 6.0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    xn[i] = fma(h6, d1x[i] + 2.0 * (d2x[i] + d3x[i]) + d4x[i], x[i]);
+    kn[i] = fma(h6, d1k[i] + 2.0 * (d2k[i] + d3k[i]) + d4k[i], k[i]);
+  }
+  dt = h6 * (t1 + 2.0 * (t2 + t3) + t4);
+}
+
+// k = M v (to_k) or v = M^-1 k at x, M diagonal in (r_hat, theta_hat, z_hat)
+template <int KIND>
+__device__ __forceinline__ void ham_convert(double a, double kappa, const double x[3], double u[3],
+                                            bool to_k) {
+  const double w = rsq64(fma(x[0], x[0], x[1] * x[1]));
+  double mr, mt, mz;
+  metric_diag(KIND, kappa, a, w, mr, mt, mz);
+  const double fr = to_k ? mr : 1.0 / mr, ft = to_k ? mt : 1.0 / mt, fz = to_k ? mz : 1.0 / mz;
+  const double ur = fma(x[0], u[0], x[1] * u[1]) * w * fr;
+  const double ut = fma(x[0], u[1], -x[1] * u[0]) * w * ft;
+  u[0] = fma(ur, x[0], -ut * x[1]) * w;
+  u[1] = fma(ur, x[1], ut * x[0]) * w;
+  u[2] *= fz;
+}
+
+// ---------------------------------------------------------------------------
 // kind dispatch helpers (wave-uniform in practice: slots are grouped by kind)
 // ---------------------------------------------------------------------------
 template <bool MIXED>

@@ -351,7 +351,7 @@ struct Lane {
 // base state, then either the step controller (stepping) or one safeguarded
 // Newton update of the crossing length (rid >= 0: locating the crossing of
 // boundary rid). Returns the final status when the ray stops, else -1.
-template <int KIND, bool MIXED>
+template <int KIND, bool MIXED, bool HAM>
 __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o, double band2,
                                        double tol, double &hr) {
   if (L.rid < 0 && L.ns >= o.max_steps) return RT_RAY_MAXSTEPS;
@@ -359,7 +359,11 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
   double xn[3], vn[3];
   double A[7][3];
   double sum = 0.0;
-  if (o.scheme == RT_SCHEME_RK4) {
+  double dts = hs;  // optical path of the attempt: its length but in the Hamiltonian form
+  if constexpr (HAM) {
+    // state (x, k); the step is in the ray parameter tau
+    rk4_ham_step<KIND>(c.a, c.kappa, L.x, L.v, hs, xn, vn, dts);
+  } else if (o.scheme == RT_SCHEME_RK4) {
     rk4_step<KIND, MIXED>(c.a, band2, L.x, L.v, L.A1, hs, xn, vn);
   } else {
 #pragma unroll
@@ -405,12 +409,14 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i) { L.x[i] = xn[i]; L.v[i] = vn[i]; }
-      L.t += hs;
-      if (o.scheme == RT_SCHEME_RK4) {
-        accel<KIND, MIXED>(c.a, band2, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
-      } else {
+      L.t += dts;
+      if constexpr (!HAM) {
+        if (o.scheme == RT_SCHEME_RK4) {
+          accel<KIND, MIXED>(c.a, band2, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
+        } else {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) L.A1[i] = A[6][i];
+          for (int i = 0; i < 3; ++i) L.A1[i] = A[6][i];
+        }
       }
       return -1;
     }
@@ -444,7 +450,16 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
   ++L.riter;
   if (!(fabs(f) <= tol || L.riter >= 100 || !(L.hi - L.lo > 1e-300))) {
     if (f < 0.0) L.lo = L.ht; else L.hi = L.ht;
-    double hn = L.ht - f * rcp64_1(gsq_slope(c, L.rid, xn, vn));
+    double slope;
+    if constexpr (HAM) {
+      // dg/dtau along dx/dtau at the trial point
+      double dx[3], dk[3], dt_;
+      ham_rhs<KIND>(c.a, c.kappa, xn, vn, dx, dk, dt_);
+      slope = gsq_slope(c, L.rid, xn, dx);
+    } else {
+      slope = gsq_slope(c, L.rid, xn, vn);
+    }
+    double hn = L.ht - f * rcp64_1(slope);
     if (!(hn > L.lo && hn < L.hi)) hn = 0.5 * (L.lo + L.hi);
     L.ht = hn;
     return -1;
@@ -463,9 +478,10 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
     return -1;
   }
   // the ray is on boundary rid at (xn, vn)
-  L.t += L.ht;
+  L.t += dts;
 #pragma unroll
   for (int i = 0; i < 3; ++i) { L.x[i] = xn[i]; L.v[i] = vn[i]; }
+  if constexpr (HAM) ham_convert<KIND>(c.a, c.kappa, L.x, L.v, false);  // k -> v
   const int rid = L.rid;
   L.rid = -1;
   if (rid == B_INNER) {
@@ -487,7 +503,8 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
   ++L.bounces;
   L.h = o.h0;
   L.after_reject = false;
-  accel<KIND, MIXED>(c.a, band2, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
+  if constexpr (HAM) ham_convert<KIND>(c.a, c.kappa, L.x, L.v, true);  // v -> k
+  else accel<KIND, MIXED>(c.a, band2, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
   return -1;
 }
 
@@ -508,7 +525,7 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
 // one atomic each and refills its idle lanes every `refill` attempts. The
 // lane state lives here, specialized for the branch, so no code of another
 // branch is interleaved with the step loop.
-template <int KIND, bool MIXED>
+template <int KIND, bool MIXED, bool HAM>
 __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, const Table &T, const SegMap &sm,
                                             int seg, double band2, double tol, int refill,
                                             unsigned int &drained) {
@@ -543,7 +560,8 @@ __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, con
         L.bounces = T.bounces[slot];
         L.after_reject = false;
         L.rid = -1;
-        accel<KIND, MIXED>(c.a, band2, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
+        if constexpr (HAM) ham_convert<KIND>(c.a, c.kappa, L.x, L.v, true);  // v -> k
+        else accel<KIND, MIXED>(c.a, band2, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
       }
       cur = min(cur + (unsigned int)__popcll(m), end);
       m = __ballot(slot < 0);
@@ -560,8 +578,11 @@ __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, con
     for (int it = 0; it < refill; ++it) {
       if (slot >= 0) {
         double hr = __builtin_nan("");
-        const int stop = iterate<KIND, MIXED>(L, c, o, band2, tol, hr);
+        const int stop = iterate<KIND, MIXED, HAM>(L, c, o, band2, tol, hr);
         if (stop >= 0) {
+          // the Hamiltonian form holds k until an interface: report v
+          if constexpr (HAM)
+            if (stop == RT_RAY_MAXSTEPS || stop == RT_RAY_DIVERGED) ham_convert<KIND>(c.a, c.kappa, L.x, L.v, false);
           store_state(T, slot, L.x, L.v);
           T.t[slot] = L.t;
           T.nsteps[slot] = L.ns;
@@ -575,7 +596,7 @@ __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, con
   }
 }
 
-template <bool MIXED>
+template <bool MIXED, bool HAM>
 __global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int refill) {
   // the queue holds the used parts of the segments one after the other,
   // each sorted hardest first and holding one branch (every entry kernel
@@ -607,10 +628,10 @@ __global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int
     while (drained >> seg & 1u) seg = (seg + 1) % NSEG;
     const int kind = __builtin_amdgcn_readfirstlane(T.kind[(long long)seg * T.cap]);
     switch (kind) {
-      case K_RE: run_segment<K_RE, MIXED>(c, o, T, sm, seg, band2, tol, refill, drained); break;
-      case K_AO: run_segment<K_AO, MIXED>(c, o, T, sm, seg, band2, tol, refill, drained); break;
-      case K_AE: run_segment<K_AE, MIXED>(c, o, T, sm, seg, band2, tol, refill, drained); break;
-      default: run_segment<K_RO, MIXED>(c, o, T, sm, seg, band2, tol, refill, drained); break;
+      case K_RE: run_segment<K_RE, MIXED, HAM>(c, o, T, sm, seg, band2, tol, refill, drained); break;
+      case K_AO: run_segment<K_AO, MIXED, HAM>(c, o, T, sm, seg, band2, tol, refill, drained); break;
+      case K_AE: run_segment<K_AE, MIXED, HAM>(c, o, T, sm, seg, band2, tol, refill, drained); break;
+      default: run_segment<K_RO, MIXED, HAM>(c, o, T, sm, seg, band2, tol, refill, drained); break;
     }
   }
 }
@@ -1203,10 +1224,12 @@ CloakP make_cloak(const rt_cloak_desc &d) {
 
 int check_opts(const rt_trace_opts *o, double r2, bool need_rout) {
   if (!o) return fail(RT_E_INVALID, "options are NULL");
-  if (o->scheme != RT_SCHEME_RK4 && o->scheme != RT_SCHEME_DP45)
-    return fail(RT_E_INVALID, "scheme must be RT_SCHEME_RK4 or RT_SCHEME_DP45");
+  if (o->scheme != RT_SCHEME_RK4 && o->scheme != RT_SCHEME_DP45 && o->scheme != RT_SCHEME_RK4_HAM)
+    return fail(RT_E_INVALID, "scheme must be RT_SCHEME_RK4, RT_SCHEME_DP45 or RT_SCHEME_RK4_HAM");
   if (o->precision != RT_PREC_FP64 && o->precision != RT_PREC_MIXED)
     return fail(RT_E_INVALID, "precision must be RT_PREC_FP64 or RT_PREC_MIXED");
+  if (o->scheme == RT_SCHEME_RK4_HAM && o->precision != RT_PREC_FP64)
+    return fail(RT_E_UNSUPPORTED, "the Hamiltonian form runs in FP64 only");
   if (!(o->h > 0.0) || !std::isfinite(o->h)) return fail(RT_E_INVALID, "h must be > 0");
   if (o->scheme == RT_SCHEME_DP45) {
     if (!(o->rtol > 0.0) || !(o->atol > 0.0)) return fail(RT_E_INVALID, "rtol and atol must be > 0");
@@ -1247,18 +1270,24 @@ unsigned int grid_for(long long n, int block) {
   return (unsigned int)std::max(1LL, g);
 }
 
-template <bool MIXED>
-unsigned int transit_grid(int block) {
+template <bool MIXED, bool HAM>
+unsigned int transit_grid_t(int block) {
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_transit<MIXED>, block, 0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_transit<MIXED, HAM>, block, 0) != hipSuccess ||
       occ <= 0)
     occ = 1;
   return (unsigned int)(num_cu() * occ);
 }
 
+// the integrator variant the options select: FP64, mixed precision or the
+// Hamiltonian form
+unsigned int transit_grid(const OptsP &o, int block) {
+  if (o.scheme == RT_SCHEME_RK4_HAM) return transit_grid_t<false, true>(block);
+  return o.precision == RT_PREC_MIXED ? transit_grid_t<true, false>(block) : transit_grid_t<false, false>(block);
+}
+
 // integrate the slots already placed in the table: order them hardest
 // first, then one persistent integrator launch (kernel launches only)
-template <bool MIXED>
 void run_transit(const CloakP &c, const OptsP &o, const Table &T, int block, int refill,
                  unsigned int grid, hipStream_t s, bool profile) {
   hipLaunchKernelGGL(k_sort_hist, dim3(num_cu() * 4), dim3(256), 0, s, T);
@@ -1267,7 +1296,12 @@ void run_transit(const CloakP &c, const OptsP &o, const Table &T, int block, int
   ProfEvent pe;
   bool on = false;
   if (profile) prof_begin(s, pe, on);
-  hipLaunchKernelGGL(k_transit<MIXED>, dim3(grid), dim3(block), 0, s, c, o, T, refill);
+  if (o.scheme == RT_SCHEME_RK4_HAM)
+    hipLaunchKernelGGL((k_transit<false, true>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
+  else if (o.precision == RT_PREC_MIXED)
+    hipLaunchKernelGGL((k_transit<true, false>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
+  else
+    hipLaunchKernelGGL((k_transit<false, false>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
   if (profile) prof_end(s, pe, on);
 }
 
@@ -1402,7 +1436,7 @@ int prepare_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts
     auto it = g_tuned.find(J.key);
     if (it != g_tuned.end()) { J.block = it->second.first; J.refill = it->second.second; }
   }
-  J.grid = J.o.precision == RT_PREC_MIXED ? transit_grid<true>(J.block) : transit_grid<false>(J.block);
+  J.grid = transit_grid(J.o, J.block);
   RenderP &R = J.R;
   R.ns_img = ns_img; R.n_cams = n_cams; R.ncl = ncl; R.npol = npol; R.spp = spp;
   R.axis[0] = n_cloaks > 0 ? cloaks[0]->d.axis : 0;
@@ -1448,10 +1482,7 @@ void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStre
     hipLaunchKernelGGL(k_rd_gen<false>, dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
                        ws.cams, T, R, CandP{});
     if (J.n_cloaks) {
-      if (J.o.precision == RT_PREC_MIXED)
-        run_transit<true>(J.c, J.o, T, J.block, J.refill, J.grid, s, profile);
-      else
-        run_transit<false>(J.c, J.o, T, J.block, J.refill, J.grid, s, profile);
+      run_transit(J.c, J.o, T, J.block, J.refill, J.grid, s, profile);
       hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, J.rm, T, R);
     }
     long long nres = (R.g1 - R.g0) / R.spp * R.ncl * R.npol;
@@ -1534,10 +1565,7 @@ int render_surrogate(rt_model model, const rt_cloak_desc &desc, const RenderJob 
       hipLaunchKernelGGL(k_rd_sur_apply, dim3(grid_for(nc, 256)), dim3(256), 0, s, J.c, J.o, J.rm, ws.cams, T, R,
                          cw.P, nc);
     }
-    if (J.o.precision == RT_PREC_MIXED)
-      run_transit<true>(J.c, J.o, T, J.block, J.refill, J.grid, s, true);
-    else
-      run_transit<false>(J.c, J.o, T, J.block, J.refill, J.grid, s, true);
+    run_transit(J.c, J.o, T, J.block, J.refill, J.grid, s, true);
     hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, J.rm, T, R);
     long long nres = (R.g1 - R.g0) / R.spp * R.ncl * R.npol;
     hipLaunchKernelGGL(k_rd_resolve, dim3(grid_for(nres, 256)), dim3(256), 0, s, R, ws.table, rgb, J.npix);
@@ -1648,14 +1676,13 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
   int block = opts->block ? opts->block : 256;
   int refill = opts->refill_period ? opts->refill_period : 2;
   int kind = c.axis * 2 + pol;
-  unsigned int grid = o.precision == RT_PREC_MIXED ? transit_grid<true>(block) : transit_grid<false>(block);
+  unsigned int grid = transit_grid(o, block);
   hipLaunchKernelGGL(k_zero, dim3((C_COUNT + 255) / 256), dim3(256), 0, s, T.ctr, (int)C_COUNT);
   hipLaunchKernelGGL(k_tb_entry, dim3(grid_for(n, 256)), dim3(256), 0, s, c, o, T, kind, (long long)n,
                      in6, out6, opl, status, hres, nsteps);
   e = launch_err("entry launch");
   if (e) return e;
-  if (o.precision == RT_PREC_MIXED) run_transit<true>(c, o, T, block, refill, grid, s, true);
-  else run_transit<false>(c, o, T, block, refill, grid, s, true);
+  run_transit(c, o, T, block, refill, grid, s, true);
   e = launch_err("transit launch");
   if (e) return e;
   hipLaunchKernelGGL(k_tb_finish, dim3(num_cu() * 8), dim3(256), 0, s, c, o, T, (long long)n, out6,
@@ -1693,14 +1720,13 @@ int rt_transit_exact(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_op
   OptsP o = make_opts(*opts);
   int block = opts->block ? opts->block : 256;
   int refill = opts->refill_period ? opts->refill_period : 2;
-  unsigned int grid = o.precision == RT_PREC_MIXED ? transit_grid<true>(block) : transit_grid<false>(block);
+  unsigned int grid = transit_grid(o, block);
   hipLaunchKernelGGL(k_zero, dim3((C_COUNT + 255) / 256), dim3(256), 0, s, T.ctr, (int)C_COUNT);
   hipLaunchKernelGGL(k_sx_entry, dim3(grid_for(n, 256)), dim3(256), 0, s, c, o, T, (long long)n,
                      (long long)ld, x6, mask, have_axes, y5, status, hres, nsteps);
   e = launch_err("entry launch");
   if (e) return e;
-  if (o.precision == RT_PREC_MIXED) run_transit<true>(c, o, T, block, refill, grid, s, true);
-  else run_transit<false>(c, o, T, block, refill, grid, s, true);
+  run_transit(c, o, T, block, refill, grid, s, true);
   e = launch_err("transit launch");
   if (e) return e;
   hipLaunchKernelGGL(k_sx_finish, dim3(num_cu() * 8), dim3(256), 0, s, c, T, (long long)ld, y5, status,
@@ -1839,7 +1865,7 @@ int rt_autotune_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_
       for (int ri = 0; !e && ri < 4; ++ri) {
         J.block = blocks[bi];
         J.refill = refills[ri];
-        J.grid = J.o.precision == RT_PREC_MIXED ? transit_grid<true>(J.block) : transit_grid<false>(J.block);
+        J.grid = transit_grid(J.o, J.block);
         enqueue_render(J, g_ws, rgb, s, false);  // warm-up
         (void)hipEventRecord(a, s);
         for (int rep = 0; rep < 2; ++rep) enqueue_render(J, g_ws, rgb, s, false);

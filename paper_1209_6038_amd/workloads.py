@@ -39,6 +39,17 @@ def opts_rk4(h: float = 1e-3, r_out: float = 3.0, **kw) -> dict:
     return d
 
 
+def opts_rk4_ham(h: float = 3e-3, r_out: float = 3.0, **kw) -> dict:
+    """Classical RK4 with the fixed step h in the ray parameter tau of the
+    Hamiltonian form (scheme 2); dt/dtau = 2 eps_o eps_e = 8 at r = 2 of the
+    R1 = 1, R2 = 2 cloak, so h = 3e-3 is a step of 0.024 in optical path
+    there, shrinking towards r = R1."""
+    d = {"scheme": 2, "precision": 0, "h": h, "rtol": 1e-8, "atol": 1e-8, "hmax": 0.5,
+         "r_out": r_out, "max_steps": 1_000_000, "max_bounces": 4}
+    d.update(kw)
+    return d
+
+
 def opts_dp45(tol: float = 1e-8, h0: float = 1e-2, r_out: float = 3.0, **kw) -> dict:
     d = {"scheme": 1, "precision": 0, "h": h0, "rtol": tol, "atol": tol, "hmax": 0.5,
          "r_out": r_out, "max_steps": 1_000_000, "max_bounces": 4}

@@ -96,6 +96,14 @@ def test_argument_validation_needs_no_gpu(lib):
                               ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None) == rt.RT_E_INVALID
     assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 0, None, None, None, None, None, None,
                               None) == rt.RT_OK  # n = 0 is a no-op
+    # the Hamiltonian form (scheme 2) runs in FP64 only; scheme 3 does not exist
+    o = rt.trace_opts({"scheme": rt.RK4_HAM, "precision": rt.MIXED, "h": 1e-3, "fp64_band": 0.05})
+    assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 10, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None) == rt.RT_E_UNSUPPORTED
+    assert b"FP64" in lib.rt_last_error()
+    o = rt.trace_opts({"scheme": 3, "h": 1e-3})
+    assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 10, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None) == rt.RT_E_INVALID
     assert lib.rt_free_cloak(h) == rt.RT_OK
 
 

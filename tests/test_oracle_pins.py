@@ -575,3 +575,76 @@ def test_elevation0_centre_row_time_of_flight_is_the_empty_rooms():
         ro = oracle.render_samples(c, W.opts_rk4(), room, cam, 0, O, ids)
         selo = (ro["status"] == 0) & (p < 2.0)
         assert (np.abs(ro["rec"][6][selo] - empty["rec"][6][selo]) > 1e-3).sum() > 5
+
+
+# --------------------------------------------------------------------------
+# the Hamiltonian form (Sect. 4): state (x, k), H = k^T A k - f, fixed RK4
+# steps in the ray parameter tau (dt/dtau = 2 f)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("axis", [0, 1])
+def test_hamiltonian_form_cloaks_inplane_rays_exactly(axis):
+    """CF1 through the Hamiltonian form: every in-plane extraordinary ray,
+    the ones aimed almost at the axis included, leaves along its incident
+    line with the vacuum time of flight."""
+    rays = W.inplane_bundle(48, 2)
+    r = oracle.trace(W.cloak(axis), W.opts_rk4_ham(h=2e-3), E, rays)
+    pe, de, s, p = _exact_inplane(rays)
+    hit = np.abs(p) < 2.0
+    assert (r["status"][hit] == 0).all() and (r["status"][~hit] == 1).all()
+    assert np.linalg.norm(r["out"][:3] - pe, axis=0)[hit].max() < 3e-9
+    assert np.linalg.norm(r["out"][3:] - de, axis=0)[hit].max() < 3e-9
+    assert np.abs(r["opl"] - s)[hit].max() < 3e-9
+    assert np.nanmax(r["hres"][hit]) < 1e-10
+
+
+@pytest.mark.parametrize("case", ["cf2_azimuthal_e", "cf3_radial_o", "cf4_radial_e", "cf4_azimuthal_o"])
+def test_hamiltonian_form_matches_the_3d_closed_forms(case):
+    """The 3-D cases with closed forms (virtual straight line, lens with
+    mirror, the two quadratures) through the Hamiltonian form: exit point,
+    direction and optical path (from dt/dtau = 2 f) agree."""
+    axis, branch = {"cf2_azimuthal_e": (1, E), "cf3_radial_o": (0, O), "cf4_radial_e": (0, E),
+                    "cf4_azimuthal_o": (1, O)}[case]
+    rays = CF.aimed_rays(24, 11, min_ktheta=0.2) if case == "cf2_azimuthal_e" else CF.aimed_rays(12, 13 + axis)
+    r = oracle.trace(W.cloak(axis), W.opts_rk4_ham(h=2e-3, r_out=2.0), branch, rays)
+    assert (r["status"] == 0).all()
+    for i in range(rays.shape[1]):
+        o, d = rays[:3, i], rays[3:, i]
+        if case == "cf2_azimuthal_e":
+            pe, de, opl = CF.cf2_azimuthal_e(o, d)
+        elif case == "cf3_radial_o":
+            pe, de, opl = CF.cf3_radial_o(o, d)
+        else:
+            pe, de, opl = CF.cf4_quadrature(axis, branch, o, d)
+        np.testing.assert_allclose(r["out"][:3, i], pe, atol=3e-9)
+        np.testing.assert_allclose(r["out"][3:, i], de, atol=3e-9)
+        assert r["opl"][i] == pytest.approx(opl, abs=3e-9)
+
+
+def test_hamiltonian_form_is_fourth_order_in_tau():
+    rays = W.inplane_bundle(32, 2)
+    pe, de, s, p = _exact_inplane(rays)
+    res = (np.abs(p) >= 0.3) & (np.abs(p) < 2.0)
+    errs = []
+    for h in (8e-3, 4e-3):
+        r = oracle.trace(W.cloak(0), W.opts_rk4_ham(h=h), E, rays)
+        errs.append(np.linalg.norm(r["out"][:3] - pe, axis=0)[res].max())
+    assert 10.0 < errs[0] / errs[1] < 24.0
+
+
+def test_hamiltonian_form_resolves_rays_aimed_near_the_axis():
+    """In-plane extraordinary rays of the radial cloak aimed within 0.3 of
+    the axis pass close to r = a, where Eq. (8)'s right-hand side is singular;
+    there f = kappa^2 s -> 0 slows the ray in tau, so fixed tau steps shorten
+    in optical path by themselves. At tau step 2e-3 (fewer steps per ray than
+    Eq. (8) at h = 1e-3) every such ray exits within 1e-8, while fixed steps of
+    Eq. (8) leave some of them far off."""
+    rays = W.inplane_bundle(48, 2)
+    pe, de, s, p = _exact_inplane(rays)
+    near = np.abs(p) < 0.3
+    rh = oracle.trace(W.cloak(0), W.opts_rk4_ham(h=2e-3), E, rays)
+    rl = oracle.trace(W.cloak(0), W.opts_rk4(h=1e-3), E, rays)
+    eh = np.linalg.norm(rh["out"][:3] - pe, axis=0)[near]
+    el = np.linalg.norm(rl["out"][:3] - pe, axis=0)[near]
+    assert (rh["status"][near] == 0).all() and eh.max() < 1e-8
+    assert np.nanmax(el) > 1e-6
+    assert rh["nsteps"][near].mean() < rl["nsteps"][near].mean()
