@@ -98,6 +98,27 @@ def test_render_small_parity(axis):
             compare_tof(aux["tof"][k, pi], o, 1)
 
 
+@pytest.mark.parametrize("axis", [0, 1])
+def test_render_hamiltonian_form_parity(axis):
+    """The 3-D render with the Hamiltonian form (RK4 in tau, step 2e-3) on
+    both branches, against the oracle's Hamiltonian tracer sample by sample:
+    statuses, exit rays within the 1e-6 bar, colour codes and the time of
+    flight (from dt/dtau = 2 f). The step limit bounds the rays aimed at the
+    axis, which stall in tau; both sides stop them the same way."""
+    cams = W.render_views(res=32)
+    c = W.cloak(axis, height=W.HEIGHT)
+    op = W.opts_rk4_ham(h=2e-3, max_steps=100_000)
+    say(f"case render hamiltonian axis={axis}")
+    rgb, aux = gpu_render(c, op, cams, 3)
+    room = W.room()
+    for k, cam in enumerate(cams):
+        for pi, branch in enumerate((0, 1)):
+            o = oracle.render_samples(c, op, room, cam, k, branch, np.arange(32 * 32))
+            compare_samples(aux["code"][k, pi], aux["rec"][k, pi], aux["status"][k, pi], o, room,
+                            f"ham a{axis} cam{k} b{branch}")
+            compare_tof(aux["tof"][k, pi], o, 1)
+
+
 def test_render_empty_room():
     """No cloak: camera rays hit the room directly. Codes agree except where a
     ray lands exactly on a tile edge (the elevation-0 camera sits at z = 2, a
