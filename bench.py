@@ -9,7 +9,8 @@ ordinary and extraordinary branch traced separately, Dormand-Prince 5(4) at
 tolerance 1e-8. One step renders both cloaks (16.8 M camera rays, one
 integrator launch), with the integrator's launch shape (block size, refill
 period) chosen by rt_autotune_render on the batch beforehand (--block /
---refill fix it instead). The batch is recorded into --streams render plans
+--refill fix it instead). The batch is recorded into --streams render plans (default 3; the GPU
+runs 4 hardware queues, and a fourth stream can share one)
 (rt_render_plan_*, each with its own workspace and output images), and step k
 replays plan k mod S on stream k mod S: consecutive steps overlap, so one
 step's last rays and small kernels share the chip with the next step's bulk.

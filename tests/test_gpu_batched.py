@@ -90,23 +90,25 @@ def test_autotuner_choice_does_not_change_results():
     assert torch.equal(a, b)
 
 
-def test_overlapped_plans_on_three_streams_match_eager_render():
-    """The benchmark's step loop: the 3-D render (4 views x 1024^2, both
-    cloaks and branches) recorded into three plans, step k replayed from plan
-    k mod 3 on stream k mod 3 so that consecutive steps overlap. Each plan
-    owns its workspace: every replay gives the eager render bit for bit."""
+@pytest.mark.parametrize("n_streams", [3, 4])
+def test_overlapped_plans_match_eager_render(n_streams):
+    """The benchmark's step loop (3 streams by default): the 3-D render
+    (4 views x 1024^2, both cloaks and branches) recorded into one plan per
+    stream, step k replayed from plan k mod S on stream k mod S so that
+    consecutive steps overlap. Each plan owns its workspace: every replay
+    gives the eager render bit for bit."""
     import torch
     from paper_1209_6038_amd import rt
     cams = W.render_views(res=1024)
     cls = _cloaks()
     opts = W.render_opts()
-    say("case render3d: eager render, then 3 plans x 3 overlapped replays")
+    say(f"case render3d: eager render, then {n_streams} plans x 3 overlapped replays")
     rgb_e, aux_e = rt.render_multi(cls, opts, W.room(), cams, 3, aux=True)
     torch.cuda.synchronize()
-    plans = [rt.RenderPlan(cls, opts, W.room(), cams, 3, aux=True) for _ in range(3)]
-    streams = [torch.cuda.Stream() for _ in range(3)]
+    plans = [rt.RenderPlan(cls, opts, W.room(), cams, 3, aux=True) for _ in range(n_streams)]
+    streams = [torch.cuda.Stream() for _ in range(n_streams)]
     for rnd in range(3):
-        for k in range(3):
+        for k in range(n_streams):
             with torch.cuda.stream(streams[k]):
                 plans[k].launch()
         torch.cuda.synchronize()
@@ -116,6 +118,6 @@ def test_overlapped_plans_on_three_streams_match_eager_render():
                 assert torch.equal(p.aux[key], aux_e[key]), (rnd, k, key)
             assert torch.equal(torch.nan_to_num(p.aux["rec"]), torch.nan_to_num(aux_e["rec"])), (rnd, k)
             p.rgb.zero_()
-        say(f"  round {rnd}: 3 plans equal to the eager render")
+        say(f"  round {rnd}: {n_streams} plans equal to the eager render")
     for p in plans:
         p.close()
