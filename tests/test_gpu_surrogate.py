@@ -343,3 +343,36 @@ def test_infer_with_nothing_trusted_is_exact():
     assert bool((fb == 1).all())
     assert torch.equal(st_s, st_ex)
     assert torch.equal(torch.nan_to_num(y_s), torch.nan_to_num(y_ex))
+
+
+def test_infer_rows_do_not_depend_on_the_batch():
+    """Every row of rt_surrogate_infer gets what it would get alone: rows of
+    a strided subset equal the full batch's bit for bit (accepted
+    predictions, flags, statuses), and the rejected rows equal the exact
+    transit's."""
+    import torch
+    from paper_1209_6038_amd import rt
+    from paper_1209_6038_amd import surrogate as S
+    cloaks = S.make_cloaks(None)
+    opts = S.exact_opts()
+    m = rt.Surrogate(seed=0)
+    m.set_params(np.zeros(rt.Surrogate.NPARAM, np.float32))
+    x_cal = S.features(40000, seed=8)
+    y_cal, st_cal = rt.transit_exact(cloaks, opts, x_cal)
+    m.calibrate(cloaks, x_cal, y_cal, st_cal, tol=5e-4, min_count=4)
+    x = S.features(60000, seed=9)
+    y_s, st_s, fb = m.infer(cloaks, opts, x)
+    y_ex, st_ex = rt.transit_exact(cloaks, opts, x)
+    torch.cuda.synchronize()
+    rej = fb == 1
+    say(f"rejected {int(rej.sum())} of {x.shape[1]}")
+    assert 0 < int(rej.sum()) < x.shape[1]
+    assert torch.equal(st_s[rej], st_ex[rej])
+    assert torch.equal(torch.nan_to_num(y_s[:, rej]), torch.nan_to_num(y_ex[:, rej]))
+    sub = torch.arange(1, x.shape[1], 3, device=x.device)
+    xs = x[:, sub].contiguous()
+    y2, st2, fb2 = m.infer(cloaks, opts, xs)
+    torch.cuda.synchronize()
+    assert torch.equal(fb2, fb[sub])
+    assert torch.equal(st2, st_s[sub])
+    assert torch.equal(torch.nan_to_num(y2), torch.nan_to_num(y_s[:, sub]))
