@@ -92,7 +92,8 @@ def test_edge_cases():
         [0.0, 0.0, 0.0, 0.0, -1.0, 0.0, 0.0],
     ])
     for op in (W.opts_dp45(), W.opts_rk4(), W.opts_dp45(max_steps=1), W.opts_rk4(max_steps=5),
-               W.opts_dp45(max_bounces=0)):
+               W.opts_dp45(max_bounces=0), W.opts_rk4_ham(), W.opts_rk4_ham(max_steps=5),
+               W.opts_rk4_ham(max_bounces=0)):
         for branch in (0, 1):
             say(f"case edge {op['scheme']} {op['max_steps']} {op['max_bounces']} b{branch}")
             g = gpu_trace(c, op, branch, rays)
@@ -125,6 +126,11 @@ def test_scheduling_does_not_change_results():
         g = gpu_trace(c, W.opts_dp45(**kw), 1, rays)
         for k in base:
             np.testing.assert_array_equal(np.nan_to_num(g[k], nan=-7.0), np.nan_to_num(base[k], nan=-7.0))
+    # the Hamiltonian form likewise
+    base = gpu_trace(c, W.opts_rk4_ham(), 1, rays)
+    g = gpu_trace(c, W.opts_rk4_ham(block=64, refill_period=1), 1, rays)
+    for k in base:
+        np.testing.assert_array_equal(np.nan_to_num(g[k], nan=-7.0), np.nan_to_num(base[k], nan=-7.0))
 
 
 @pytest.mark.parametrize("axis", [0, 1])
