@@ -95,7 +95,8 @@ UNRESOLVED = 1e-6
 # by about 1% between shapes, and the one nearest the run's shape is reported
 # together with the shape it was taken at.
 TRAFFIC = {"source_sha256": "9a1e6cdf7fb91511e26720ceb35607a934fc9a2eab0e12a861d66b6b0bac8514",
-           "bytes_per_launch": {(256, 2): 777297088}}
+           "bytes_per_launch": {(256, 2): 777297088, (256, 4): 781341696, (256, 8): 789943968,
+                                (128, 4): 767144192, (128, 8): 773026656}}
 
 
 def traffic_for(block, refill):
