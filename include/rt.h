@@ -80,7 +80,8 @@ typedef struct {
    paper compares against (Sect. 4): state (x, k), H = k^T A k - f with A = eps
    and f = eps_o eps_e (extraordinary) or A = I and f = eps_o (ordinary),
    classical RK4 with the fixed step h in the ray parameter tau
-   (dx/dtau = 2 A k, dt/dtau = 2 f); FP64 only. Interfaces, events and
+   (dx/dtau = 2 A k, dt/dtau = 2 f); FP64 only (with RT_PREC_MIXED the call
+   returns RT_E_UNSUPPORTED). Interfaces, events and
    outputs are those of the other schemes (k is converted to v = M^-1 k at
    every interface). precision:
    RT_PREC_FP64, or RT_PREC_MIXED (FP32 derivative evaluation where
