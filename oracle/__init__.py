@@ -73,7 +73,7 @@ def lib():
         L = ctypes.CDLL(_LIB_PATH)
         L.orc_trace.argtypes = [ctypes.POINTER(_Cloak), ctypes.POINTER(_Opts), ctypes.c_int32,
                                 ctypes.c_int64, c_double_p, c_double_p, c_double_p, c_int32_p,
-                                c_double_p, c_int64_p]
+                                c_double_p, c_int64_p, c_double_p]
         L.orc_render_samples.argtypes = [ctypes.POINTER(_Cloak), ctypes.POINTER(_Opts),
                                          ctypes.POINTER(_Room), ctypes.POINTER(_Camera),
                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
@@ -89,6 +89,12 @@ def lib():
         L.orc_refract_out.argtypes = [ctypes.c_double, ctypes.c_double, c_double_p, c_double_p,
                                       c_double_p, ctypes.c_int32, c_double_p]
         L.orc_refract_out.restype = ctypes.c_int32
+        L.orc_fresnel_in.argtypes = [ctypes.c_double, ctypes.c_double, c_double_p, c_double_p,
+                                     c_double_p, c_double_p, c_double_p]
+        L.orc_fresnel_in.restype = ctypes.c_int32
+        L.orc_fresnel_out.argtypes = [ctypes.c_double, ctypes.c_double, c_double_p, c_double_p,
+                                      c_double_p, ctypes.c_int32, c_double_p, c_double_p]
+        L.orc_fresnel_out.restype = ctypes.c_int32
         L.orc_camera_ray.argtypes = [ctypes.POINTER(_Camera), ctypes.c_int32, ctypes.c_int64,
                                      c_double_p, c_double_p]
         L.orc_room_code.argtypes = [ctypes.POINTER(_Room), c_double_p, c_double_p, c_double_p]
@@ -144,7 +150,10 @@ def trace(cloak, opts, branch, rays6):
     """Trace vacuum rays (SoA array 6 x n: origin, direction) through the cloak.
 
     Returns a dict with out (6 x n: point on r = r_out, unit direction), opl,
-    status, hres (|H-1| at the last interface) and nsteps (step attempts).
+    status, hres (|H-1| at the last interface), nsteps (step attempts) and
+    trans (the Eq. (12) weight of the reported ray: unpolarized entry
+    transmission x same-mode internal reflectances x exit transmission; 1 for
+    a miss, 0 when the ray does not exit).
     """
     rays6 = np.ascontiguousarray(rays6, dtype=np.float64)
     n = rays6.shape[1]
@@ -153,10 +162,11 @@ def trace(cloak, opts, branch, rays6):
     st = np.empty(n, dtype=np.int32)
     hr = np.empty(n)
     ns = np.empty(n, dtype=np.int64)
+    tr = np.empty(n)
     c, o = _cloak(cloak), _opts(opts)
     lib().orc_trace(ctypes.byref(c), ctypes.byref(o), int(branch), n, _ptr(rays6), _ptr(out),
-                    _ptr(opl), _ptr(st, c_int32_p), _ptr(hr), _ptr(ns, c_int64_p))
-    return {"out": out, "opl": opl, "status": st, "hres": hr, "nsteps": ns}
+                    _ptr(opl), _ptr(st, c_int32_p), _ptr(hr), _ptr(ns, c_int64_p), _ptr(tr))
+    return {"out": out, "opl": opl, "status": st, "hres": hr, "nsteps": ns, "trans": tr}
 
 
 def render_samples(cloak, opts, room, camera, cam_index, branch, ids):
@@ -231,6 +241,28 @@ def refract_out(eps_o, eps_e, chat, nhat, v_in, branch):
     st = lib().orc_refract_out(float(eps_o), float(eps_e), _ptr(chat), _ptr(nhat), _ptr(v_in),
                                int(branch), _ptr(d))
     return st, d
+
+
+def fresnel_in(eps_o, eps_e, chat, nhat, kin):
+    """Eq. (12) at the entry, unpolarized: ((T_o, T_e), R)."""
+    chat, nhat, kin = (np.ascontiguousarray(a, dtype=np.float64) for a in (chat, nhat, kin))
+    T = np.empty(2)
+    R = np.empty(1)
+    st = lib().orc_fresnel_in(float(eps_o), float(eps_e), _ptr(chat), _ptr(nhat), _ptr(kin), _ptr(T), _ptr(R))
+    assert st == 0
+    return T, float(R[0])
+
+
+def fresnel_out(eps_o, eps_e, chat, nhat, k_in, branch):
+    """Eq. (12) at the exit for an incident wave of `branch` with wave
+    vector k_in: (T, (R_o, R_e))."""
+    chat, nhat, k_in = (np.ascontiguousarray(a, dtype=np.float64) for a in (chat, nhat, k_in))
+    T = np.empty(1)
+    R = np.empty(2)
+    st = lib().orc_fresnel_out(float(eps_o), float(eps_e), _ptr(chat), _ptr(nhat), _ptr(k_in), int(branch),
+                               _ptr(T), _ptr(R))
+    assert st == 0
+    return float(T[0]), R
 
 
 def camera_ray(camera, cam_index, sample_id):

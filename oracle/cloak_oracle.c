@@ -30,6 +30,7 @@
  */
 #include "cloak_oracle.h"
 
+#include <complex.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -758,6 +759,231 @@ int32_t orc_refract_out(double eps_o, double eps_e, const double chat[3],
 }
 
 /* ------------------------------------------------------------------ */
+/* Sect. 3, Eq. (12): intensity transmission at the interface          */
+/* ------------------------------------------------------------------ */
+/* Plane waves exp(i k.x) with omega = c0 = 1 and mu = 1: H = k x E and
+   D = -k x H = eps E. Crystal: eps = eps_o (I - c c^T) + eps_e c c^T.
+   Ordinary wave: E = k x c, k.k = eps_o. Extraordinary wave: D in the plane
+   of k and c and perpendicular to k, D = (k.k) c - (c.k) k, E = eps^-1 D,
+   k^T eps k = eps_o eps_e. Normal components q of k = kt + q n come from the
+   dispersion relations; complex q (evanescent waves) are allowed. The
+   boundary conditions are continuity of tangential E and H; the powers are
+   the normal components of Re(E x H*) / 2 (Eq. (12)). */
+typedef double complex zc;
+
+static void zcross(const zc a[3], const zc b[3], zc r[3]) {
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static zc zdot(const zc a[3], const zc b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static double zflux(const zc E[3], const zc H[3], const double n[3]) {
+    zc Hc[3] = { conj(H[0]), conj(H[1]), conj(H[2]) }, S[3];
+    zcross(E, Hc, S);
+    return 0.5 * creal(S[0] * n[0] + S[1] * n[1] + S[2] * n[2]);
+}
+
+/* normal component of the wave vector: dir = +1 for a wave that carries
+   power towards +n (or decays towards +n), -1 towards -n */
+static zc q_iso(double eps, double ktt, int dir) {
+    double d = eps - ktt;
+    return d >= 0.0 ? dir * sqrt(d) : dir * I * sqrt(-d);
+}
+
+static zc q_extra(double eo, double ee, const double c[3], const double n[3], const double kt[3], int dir) {
+    /* (n^T eps n) q^2 + 2 (n^T eps kt) q + kt^T eps kt - eo ee = 0; the ray
+       direction eps k has normal component (n^T eps kt) + q (n^T eps n) */
+    double cn = dot3(c, n), ck = dot3(c, kt);
+    double a = eo + (ee - eo) * cn * cn;
+    double b = eo * dot3(n, kt) + (ee - eo) * cn * ck;
+    double c0 = eo * dot3(kt, kt) + (ee - eo) * ck * ck - eo * ee;
+    double disc = b * b - a * c0;
+    return disc >= 0.0 ? (-b + dir * sqrt(disc)) / a : (-b + dir * I * sqrt(-disc)) / a;
+}
+
+/* fields of a crystal mode with wave vector k; t1 is a tangent used where
+   k is along c (ordinary and extraordinary waves then coincide) */
+static void crystal_mode(double eo, double ee, const double c[3], int ordinary, const zc k[3],
+                         const double t1[3], zc E[3], zc H[3]) {
+    zc cz[3] = { c[0], c[1], c[2] };
+    zc kc[3];
+    zcross(k, cz, kc);
+    double kk = creal(zdot(k, (const zc[3]){ conj(k[0]), conj(k[1]), conj(k[2]) }));
+    double deg = creal(zdot(kc, (const zc[3]){ conj(kc[0]), conj(kc[1]), conj(kc[2]) }));
+    if (deg <= 1e-24 * kk) {
+        zc u[3] = { t1[0], t1[1], t1[2] };
+        if (ordinary) {
+            for (int i = 0; i < 3; i++) E[i] = u[i];
+        } else {
+            zcross(k, u, E);
+        }
+    } else if (ordinary) {
+        for (int i = 0; i < 3; i++) E[i] = kc[i];
+    } else {
+        zc kkz = zdot(k, k), ckz = zdot(cz, k), D[3];
+        for (int i = 0; i < 3; i++) D[i] = kkz * cz[i] - ckz * k[i];
+        zc cd = zdot(cz, D);
+        for (int i = 0; i < 3; i++) E[i] = (D[i] - cd * cz[i]) / eo + cd * cz[i] / ee;
+    }
+    zcross(k, E, H);
+}
+
+/* complex Gaussian elimination with partial pivoting, 4 x 4 */
+static int zsolve4(zc A[4][4], zc b[4], zc x[4]) {
+    for (int col = 0; col < 4; col++) {
+        int piv = col;
+        for (int r = col + 1; r < 4; r++)
+            if (cabs(A[r][col]) > cabs(A[piv][col])) piv = r;
+        if (cabs(A[piv][col]) == 0.0) return 1;
+        if (piv != col) {
+            for (int j = 0; j < 4; j++) { zc t = A[col][j]; A[col][j] = A[piv][j]; A[piv][j] = t; }
+            zc t = b[col]; b[col] = b[piv]; b[piv] = t;
+        }
+        for (int r = col + 1; r < 4; r++) {
+            zc f = A[r][col] / A[col][col];
+            for (int j = col; j < 4; j++) A[r][j] -= f * A[col][j];
+            b[r] -= f * b[col];
+        }
+    }
+    for (int r = 3; r >= 0; r--) {
+        zc s = b[r];
+        for (int j = r + 1; j < 4; j++) s -= A[r][j] * x[j];
+        x[r] = s / A[r][r];
+    }
+    return 0;
+}
+
+static void tangent_basis(const double n[3], const double kt[3], double t1[3], double t2[3]) {
+    double l = norm3(kt);
+    if (l > 1e-12) {
+        for (int i = 0; i < 3; i++) t1[i] = kt[i] / l;
+    } else {
+        any_tangent(n, t1);
+    }
+    t2[0] = n[1] * t1[2] - n[2] * t1[1];
+    t2[1] = n[2] * t1[0] - n[0] * t1[2];
+    t2[2] = n[0] * t1[1] - n[1] * t1[0];
+}
+
+/* rows: tangential E (t1, t2), tangential H (t1, t2) of a field pair */
+static void tangential(const zc E[3], const zc H[3], const double t1[3], const double t2[3], zc col[4]) {
+    col[0] = E[0] * t1[0] + E[1] * t1[1] + E[2] * t1[2];
+    col[1] = E[0] * t2[0] + E[1] * t2[1] + E[2] * t2[2];
+    col[2] = H[0] * t1[0] + H[1] * t1[1] + H[2] * t1[2];
+    col[3] = H[0] * t2[0] + H[1] * t2[1] + H[2] * t2[2];
+}
+
+int32_t orc_fresnel_in(double eps_o, double eps_e, const double chat[3], const double nhat[3],
+                       const double kin[3], double T[2], double *R) {
+    double kn = dot3(kin, nhat), kt[3], t1[3], t2[3];
+    for (int i = 0; i < 3; i++) kt[i] = kin[i] - kn * nhat[i];
+    tangent_basis(nhat, kt, t1, t2);
+    double ktt = dot3(kt, kt);
+    zc qr = q_iso(1.0, ktt, +1), qo = q_iso(eps_o, ktt, -1), qe = q_extra(eps_o, eps_e, chat, nhat, kt, -1);
+    zc kr[3], ko[3], ke[3], ki[3];
+    for (int i = 0; i < 3; i++) {
+        kr[i] = kt[i] + qr * nhat[i];
+        ko[i] = kt[i] + qo * nhat[i];
+        ke[i] = kt[i] + qe * nhat[i];
+        ki[i] = kin[i];
+    }
+    /* vacuum polarizations: s along t2 (perpendicular to the plane of incidence) */
+    zc s[3] = { t2[0], t2[1], t2[2] }, Es[3], Hs[3], Ep[3], Hp[3], Eo[3], Ho[3], Ee[3], He[3];
+    for (int i = 0; i < 3; i++) Es[i] = s[i];
+    zcross(kr, Es, Hs);
+    zcross(kr, Es, Ep);
+    zcross(kr, Ep, Hp);
+    crystal_mode(eps_o, eps_e, chat, 1, ko, t1, Eo, Ho);
+    crystal_mode(eps_o, eps_e, chat, 0, ke, t1, Ee, He);
+    double To = 0.0, Te = 0.0, Rr = 0.0;
+    for (int pol = 0; pol < 2; pol++) {
+        zc Ei[3], Hi[3];
+        if (pol == 0) {
+            for (int i = 0; i < 3; i++) Ei[i] = s[i];
+        } else {
+            zcross(ki, s, Ei);
+        }
+        zcross(ki, Ei, Hi);
+        zc cols[4][4], A[4][4], b[4], x[4];
+        tangential(Es, Hs, t1, t2, cols[0]);
+        tangential(Ep, Hp, t1, t2, cols[1]);
+        tangential(Eo, Ho, t1, t2, cols[2]);
+        tangential(Ee, He, t1, t2, cols[3]);
+        zc inc[4];
+        tangential(Ei, Hi, t1, t2, inc);
+        for (int r = 0; r < 4; r++) {
+            A[r][0] = cols[0][r];
+            A[r][1] = cols[1][r];
+            A[r][2] = -cols[2][r];
+            A[r][3] = -cols[3][r];
+            b[r] = -inc[r];
+        }
+        if (zsolve4(A, b, x)) return 1;
+        double si = fabs(zflux(Ei, Hi, nhat));
+        zc E1[3], H1[3];
+        for (int i = 0; i < 3; i++) { E1[i] = x[2] * Eo[i]; H1[i] = x[2] * Ho[i]; }
+        To += fabs(zflux(E1, H1, nhat)) / si;
+        for (int i = 0; i < 3; i++) { E1[i] = x[3] * Ee[i]; H1[i] = x[3] * He[i]; }
+        Te += fabs(zflux(E1, H1, nhat)) / si;
+        for (int i = 0; i < 3; i++) { E1[i] = x[0] * Es[i] + x[1] * Ep[i]; H1[i] = x[0] * Hs[i] + x[1] * Hp[i]; }
+        Rr += fabs(zflux(E1, H1, nhat)) / si;
+    }
+    T[0] = 0.5 * To;
+    T[1] = 0.5 * Te;
+    if (R) *R = 0.5 * Rr;
+    return 0;
+}
+
+int32_t orc_fresnel_out(double eps_o, double eps_e, const double chat[3], const double nhat[3],
+                        const double k_in[3], int32_t branch, double *T, double R[2]) {
+    double kn = dot3(k_in, nhat), kt[3], t1[3], t2[3];
+    for (int i = 0; i < 3; i++) kt[i] = k_in[i] - kn * nhat[i];
+    tangent_basis(nhat, kt, t1, t2);
+    double ktt = dot3(kt, kt);
+    zc qo = q_iso(eps_o, ktt, -1), qe = q_extra(eps_o, eps_e, chat, nhat, kt, -1), qv = q_iso(1.0, ktt, +1);
+    zc km[3], ko[3], ke[3], kv[3];
+    for (int i = 0; i < 3; i++) {
+        km[i] = k_in[i];
+        ko[i] = kt[i] + qo * nhat[i];
+        ke[i] = kt[i] + qe * nhat[i];
+        kv[i] = kt[i] + qv * nhat[i];
+    }
+    zc Em[3], Hm[3], Eo[3], Ho[3], Ee[3], He[3], Es[3], Hs[3], Ep[3], Hp[3];
+    crystal_mode(eps_o, eps_e, chat, branch == ORC_ORDINARY, km, t1, Em, Hm);
+    crystal_mode(eps_o, eps_e, chat, 1, ko, t1, Eo, Ho);
+    crystal_mode(eps_o, eps_e, chat, 0, ke, t1, Ee, He);
+    for (int i = 0; i < 3; i++) Es[i] = t2[i];
+    zcross(kv, Es, Hs);
+    zcross(kv, Es, Ep);
+    zcross(kv, Ep, Hp);
+    zc cols[4][4], A[4][4], b[4], x[4], inc[4];
+    tangential(Eo, Ho, t1, t2, cols[0]);
+    tangential(Ee, He, t1, t2, cols[1]);
+    tangential(Es, Hs, t1, t2, cols[2]);
+    tangential(Ep, Hp, t1, t2, cols[3]);
+    tangential(Em, Hm, t1, t2, inc);
+    for (int r = 0; r < 4; r++) {
+        A[r][0] = cols[0][r];
+        A[r][1] = cols[1][r];
+        A[r][2] = -cols[2][r];
+        A[r][3] = -cols[3][r];
+        b[r] = -inc[r];
+    }
+    if (zsolve4(A, b, x)) return 1;
+    double si = fabs(zflux(Em, Hm, nhat));
+    zc E1[3], H1[3];
+    for (int i = 0; i < 3; i++) { E1[i] = x[0] * Eo[i]; H1[i] = x[0] * Ho[i]; }
+    R[0] = fabs(zflux(E1, H1, nhat)) / si;
+    for (int i = 0; i < 3; i++) { E1[i] = x[1] * Ee[i]; H1[i] = x[1] * He[i]; }
+    R[1] = fabs(zflux(E1, H1, nhat)) / si;
+    for (int i = 0; i < 3; i++) { E1[i] = x[2] * Es[i] + x[3] * Ep[i]; H1[i] = x[2] * Hs[i] + x[3] * Hp[i]; }
+    *T = fabs(zflux(E1, H1, nhat)) / si;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* vacuum geometry                                                     */
 /* ------------------------------------------------------------------ */
 enum { SURF_SIDE = 0, SURF_TOP = 2, SURF_BOTTOM = 3 };
@@ -818,15 +1044,25 @@ static void reflect(double *v, const double *n) {
    vacuum ray (for MISSED the input ray), opl the optical path up to p. */
 static int trace_vacuum(const orc_cloak *c, int branch, const orc_opts *o,
                         const double *o_in, const double *d_in, double *p, double *dout,
-                        double *opl, double *hres, int64_t *nsteps) {
+                        double *opl, double *hres, int64_t *nsteps, double *wt) {
     memcpy(p, o_in, 3 * sizeof(double));
     memcpy(dout, d_in, 3 * sizeof(double));
     *opl = 0.0;
     *hres = NAN;
-    if (!c) return ORC_MISSED;
+    /* Eq. (12) weight of the reported ray: 1 for a miss, the product of the
+       entry transmission, the same-mode reflectances of internal reflections
+       and the exit transmission for an exit, 0 otherwise */
+    if (wt) *wt = 0.0;
+    if (!c) {
+        if (wt) *wt = 1.0;
+        return ORC_MISSED;
+    }
     double s;
     int surf;
-    if (!first_entry(c, o_in, d_in, &s, &surf)) return ORC_MISSED;
+    if (!first_entry(c, o_in, d_in, &s, &surf)) {
+        if (wt) *wt = 1.0;
+        return ORC_MISSED;
+    }
     double x[3];
     for (int i = 0; i < 3; i++) x[i] = o_in[i] + s * d_in[i];
     if (surf == SURF_TOP) x[2] = c->z1;
@@ -850,8 +1086,12 @@ static int trace_vacuum(const orc_cloak *c, int branch, const orc_opts *o,
         return ORC_REFLECTED;
     }
     double y[6] = { x[0], x[1], x[2], v[0], v[1], v[2] };
-    double t = 0.0;
+    double t = 0.0, w = 0.0;
     int bounces = 0, status;
+    if (wt) {
+        double Tin[2];
+        if (orc_fresnel_in(eo, ee, ch, n, d_in, Tin, NULL) == 0) w = Tin[branch];
+    }
     for (;;) {
         int ev = o->scheme == ORC_RK4_HAM ? integrate_ham(c, branch, o, y, &t, nsteps)
                                           : integrate(c, branch, o, y, &t, nsteps);
@@ -873,15 +1113,29 @@ static int trace_vacuum(const orc_cloak *c, int branch, const orc_opts *o,
         outward_normal(ev, y, nn);
         double eo2, ee2, ch2[3], dd[3];
         material_at(c, y, &eo2, &ee2, ch2);
+        double Tout = 0.0, Rref[2] = { 0.0, 0.0 };
+        if (wt) {
+            /* k = M v of the wave meeting the interface */
+            double k[3], M[3][3];
+            if (branch == ORC_ORDINARY) {
+                for (int i = 0; i < 3; i++) k[i] = eo2 * y[3 + i];
+            } else {
+                metric_from_axis(eo2, ee2, ch2, M);
+                for (int i = 0; i < 3; i++) k[i] = M[i][0] * y[3] + M[i][1] * y[4] + M[i][2] * y[5];
+            }
+            if (orc_fresnel_out(eo2, ee2, ch2, nn, k, branch, &Tout, Rref) != 0) Tout = Rref[0] = Rref[1] = 0.0;
+        }
         if (orc_refract_out(eo2, ee2, ch2, nn, y + 3, branch, dd) == 0) {
             *hres = fabs(hamiltonian(c, branch, y) - 1.0);
             memcpy(p, y, 3 * sizeof(double));
             memcpy(dout, dd, sizeof(dd));
             status = ORC_EXITED;
+            w *= Tout;
             break;
         }
         /* total internal reflection: same-mode specular reflection */
         if (bounces >= o->max_bounces) { status = ORC_TIR; break; }
+        w *= Rref[branch];
         reflect(y + 3, nn);
         bounces++;
     }
@@ -892,6 +1146,7 @@ static int trace_vacuum(const orc_cloak *c, int branch, const orc_opts *o,
         for (int i = 0; i < 3; i++) dout[i] = y[3 + i] / l;
     }
     *opl += t;
+    if (wt) *wt = status == ORC_EXITED ? w : 0.0;
     return status;
 }
 
@@ -915,10 +1170,10 @@ static int origin_inside(const orc_cloak *c, const double *o) {
 
 void orc_trace(const orc_cloak *c, const orc_opts *o, int32_t branch, int64_t n,
                const double *in6, double *out6, double *opl, int32_t *status,
-               double *hres, int64_t *nsteps) {
+               double *hres, int64_t *nsteps, double *trans) {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; i++) {
-        double org[3], d[3], p[3], dout[3], L = 0.0, hr = NAN;
+        double org[3], d[3], p[3], dout[3], L = 0.0, hr = NAN, w = 0.0;
         int64_t ns = 0;
         int st;
         for (int j = 0; j < 3; j++) { org[j] = in6[j * n + i]; d[j] = in6[(3 + j) * n + i]; }
@@ -933,7 +1188,7 @@ void orc_trace(const orc_cloak *c, const orc_opts *o, int32_t branch, int64_t n,
             memcpy(p, org, sizeof(p));
             memcpy(dout, d, sizeof(dout));
         } else {
-            st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns);
+            st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, trans ? &w : NULL);
             if (st == ORC_EXITED || st == ORC_MISSED || st == ORC_REFLECTED) {
                 double s = leave_radius(p, dout, o->r_out);
                 for (int j = 0; j < 3; j++) p[j] += s * dout[j];
@@ -945,6 +1200,7 @@ void orc_trace(const orc_cloak *c, const orc_opts *o, int32_t branch, int64_t n,
         if (status) status[i] = st;
         if (hres) hres[i] = hr;
         if (nsteps) nsteps[i] = ns;
+        if (trans) trans[i] = w;
     }
 }
 
@@ -1040,7 +1296,7 @@ void orc_render_samples(const orc_cloak *c, const orc_opts *o, const orc_room *r
         double org[3], d[3], p[3], dout[3], L = 0.0, hr;
         int64_t ns = 0;
         orc_camera_ray(cam, cam_index, ids[i], org, d);
-        int st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns);
+        int st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, NULL);
         int cd = 12;
         if (st == ORC_EXITED || st == ORC_MISSED || st == ORC_REFLECTED) {
             double s;

@@ -62,11 +62,14 @@ typedef struct {
 /* Trace n vacuum rays (SoA 6 x n: ox,oy,oz,dx,dy,dz) through the cloak and
    report each outgoing ray where it crosses r = r_out. Outputs: SoA 6 x n
    (point, unit direction), optical path, status, |H-1| at the last interface
-   (NaN when the ray never entered) and step attempts. Any output pointer but
-   out6 may be NULL. OpenMP over rays. */
+   (NaN when the ray never entered), step attempts, and the Eq. (12) weight
+   of the reported ray (unpolarized entry transmission of the branch times
+   the same-mode reflectance of each internal reflection times the exit
+   transmission; 1 for a miss, 0 when the ray does not exit). Any output
+   pointer but out6 may be NULL. OpenMP over rays. */
 void orc_trace(const orc_cloak *c, const orc_opts *o, int32_t branch, int64_t n,
                const double *in6, double *out6, double *opl, int32_t *status,
-               double *hres, int64_t *nsteps);
+               double *hres, int64_t *nsteps, double *trans);
 
 /* Render selected samples: ids[i] = pixel * spp + sample, pixel = row * w + col.
    code = face * 2 + parity (0..11), 12 = black (absorbed, TIR, step limit,
@@ -77,6 +80,21 @@ void orc_render_samples(const orc_cloak *c, const orc_opts *o, const orc_room *r
                         const orc_camera *cam, int32_t cam_index, int32_t branch,
                         int64_t n, const int64_t *ids, uint8_t *code,
                         double *rec, int32_t *status);
+
+/* Eq. (12): intensity transmission of unpolarized light (the mean over two
+   orthogonal incident polarizations) from vacuum into the crystal, T[0]
+   ordinary and T[1] extraordinary, and the reflected vacuum fraction R.
+   nhat: normal pointing out of the crystal; kin: unit vacuum direction
+   (kin . nhat < 0). Returns nonzero if the continuity system is singular. */
+int32_t orc_fresnel_in(double eps_o, double eps_e, const double chat[3], const double nhat[3],
+                       const double kin[3], double T[2], double *R);
+
+/* Eq. (12) at the exit: an ordinary or extraordinary wave with wave vector
+   k_in (power towards +nhat) meets the crystal/vacuum interface; T is the
+   transmitted fraction (0 under total internal reflection), R[0] and R[1]
+   the fractions reflected into the ordinary and extraordinary waves. */
+int32_t orc_fresnel_out(double eps_o, double eps_e, const double chat[3], const double nhat[3],
+                        const double k_in[3], int32_t branch, double *T, double R[2]);
 
 /* Pieces exposed for the pin tests. */
 void orc_eps_cyl(const orc_cloak *c, double r, double out3[3]);

@@ -648,3 +648,118 @@ def test_hamiltonian_form_resolves_rays_aimed_near_the_axis():
     assert (rh["status"][near] == 0).all() and eh.max() < 1e-8
     assert np.nanmax(el) > 1e-6
     assert rh["nsteps"][near].mean() < rl["nsteps"][near].mean()
+
+
+# --------------------------------------------------------------------------
+# Eq. (12): intensity transmission at the interfaces (Sect. 3)
+# --------------------------------------------------------------------------
+def _unit(v):
+    return np.asarray(v, float) / np.linalg.norm(v)
+
+
+def test_fresnel_isotropic_limit_is_textbook_fresnel():
+    """eps_o = eps_e = n^2 with any axis: the two modes are two orthogonal
+    polarizations of one isotropic wave, T_o + T_e and R are the
+    unpolarized Fresnel coefficients, entering and leaving."""
+    rng = np.random.default_rng(21)
+    nz = np.array([0.0, 0.0, 1.0])
+    for nn in (1.3, 2.0):
+        for th in (0.0, 0.35, 0.9, 1.3, 1.52):
+            c = _unit(rng.normal(size=3))
+            kin = np.array([math.sin(th), 0.0, -math.cos(th)])
+            T, R = oracle.fresnel_in(nn * nn, nn * nn, c, nz, kin)
+            ci, st = math.cos(th), math.sin(th) / nn
+            ct = math.sqrt(1.0 - st * st)
+            rs = (ci - nn * ct) / (ci + nn * ct)
+            rp = (nn * ci - ct) / (nn * ci + ct)
+            ru = 0.5 * (rs * rs + rp * rp)
+            assert T.sum() == pytest.approx(1.0 - ru, abs=1e-12)
+            assert R == pytest.approx(ru, abs=1e-12)
+            # leaving: a wave inside at the refraction angle, either mode
+            k_in = nn * np.array([st, 0.0, ct])
+            for br in (O, E):
+                Tt, Rr = oracle.fresnel_out(nn * nn, nn * nn, c, nz, k_in, br)
+                assert Tt + Rr.sum() == pytest.approx(1.0, abs=1e-12)
+                assert min(1.0 - rs * rs, 1.0 - rp * rp) - 1e-12 <= Tt <= max(1.0 - rs * rs, 1.0 - rp * rp) + 1e-12
+
+
+def test_fresnel_optic_axis_normal_to_the_surface():
+    """Axis along the normal (the radial cloak's side): the ordinary wave is
+    the s wave of index n_o, the extraordinary the p wave with
+    r_p = (n_o n_e cos - sqrt(n_e^2 - sin^2)) / (n_o n_e cos + sqrt(n_e^2 - sin^2));
+    at r = b of the R1 = 1, R2 = 2 radial cloak (eps_o = 4, eps_e = 1)
+    T_e = (1 - 1/9) / 2 at every angle."""
+    nz = np.array([0.0, 0.0, 1.0])
+    for eo, ee in ((4.0, 1.0), (2.25, 3.0)):
+        no, ne = math.sqrt(eo), math.sqrt(ee)
+        for th in (0.0, 0.4, 1.0, 1.4):
+            kin = np.array([math.sin(th), 0.0, -math.cos(th)])
+            T, R = oracle.fresnel_in(eo, ee, nz, nz, kin)
+            ci, si = math.cos(th), math.sin(th)
+            rs = (ci - math.sqrt(eo - si * si)) / (ci + math.sqrt(eo - si * si))
+            rp = (no * ne * ci - math.sqrt(ee - si * si)) / (no * ne * ci + math.sqrt(ee - si * si))
+            assert T[0] == pytest.approx(0.5 * (1.0 - rs * rs), abs=1e-12)
+            assert T[1] == pytest.approx(0.5 * (1.0 - rp * rp), abs=1e-12)
+    T, _ = oracle.fresnel_in(4.0, 1.0, nz, nz, _unit([0.5, 0.2, -0.7]))
+    assert T[1] == pytest.approx(0.5 * (1.0 - 1.0 / 9.0), abs=1e-12)
+
+
+def test_fresnel_normal_incidence_with_the_axis_in_the_surface():
+    """Axis in the surface (the azimuthal cloak's side): at normal incidence
+    each mode takes half of unpolarized light with its own index."""
+    nz = np.array([0.0, 0.0, 1.0])
+    for eo, ee in ((1.0, 4.0), (2.0, 3.5)):
+        T, R = oracle.fresnel_in(eo, ee, np.array([1.0, 0.0, 0.0]), nz, -nz)
+        for t, eps in zip(T, (eo, ee)):
+            nn = math.sqrt(eps)
+            assert t == pytest.approx(0.5 * 4.0 * nn / (1.0 + nn) ** 2, abs=1e-12)
+
+
+def test_fresnel_conserves_energy_and_reflects_totally():
+    """Anisotropic cases with random axes: entering, T_o + T_e + R = 1;
+    leaving (the time-reversed transmitted waves), T + R_o + R_e = 1; beyond
+    the critical angle T = 0 and R_o + R_e = 1."""
+    rng = np.random.default_rng(22)
+    nz = np.array([0.0, 0.0, 1.0])
+    for _ in range(40):
+        eo, ee = rng.uniform(0.5, 5.0, 2)
+        c = _unit(rng.normal(size=3))
+        kin = _unit(rng.normal(size=3))
+        kin[2] = -abs(kin[2]) - 0.05
+        kin = _unit(kin)
+        T, R = oracle.fresnel_in(eo, ee, c, nz, kin)
+        assert (T >= 0).all() and R >= 0 and T.sum() + R == pytest.approx(1.0, abs=1e-11)
+        for br in (O, E):
+            st, k, _ = oracle.refract_in(eo, ee, c, nz, kin, br)
+            if st:
+                continue
+            Tt, Rr = oracle.fresnel_out(eo, ee, c, nz, -k, br)
+            assert Tt + Rr.sum() == pytest.approx(1.0, abs=1e-11)
+    for eo in (2.0, 4.0):
+        kt = 1.2
+        k_in = np.array([kt, 0.0, math.sqrt(eo - kt * kt)])
+        Tt, Rr = oracle.fresnel_out(eo, 1.5, _unit([0.3, 0.5, 0.8]), nz, k_in, O)
+        assert Tt == pytest.approx(0.0, abs=1e-12) and Rr.sum() == pytest.approx(1.0, abs=1e-11)
+
+
+def test_trace_weights():
+    """The Eq. (12) weight of a traced ray: 1 for a miss, in (0, 1] for an
+    exit, 0 otherwise; the azimuthal cloak's ordinary index is 1 at r = b, so
+    an in-plane ordinary ray crossing it side to side is not reflected at
+    either interface and keeps its share of unpolarized light."""
+    rays = W.random_rays(64, seed=5, z_range=(-1.0, 5.0))
+    for axis in (0, 1):
+        for br in (O, E):
+            r = oracle.trace(W.cloak(axis, height=W.HEIGHT), W.opts_dp45(), br, rays)
+            st, w = r["status"], r["trans"]
+            assert (w[st == 1] == 1.0).all()
+            assert ((w[st == 0] > 0) & (w[st == 0] <= 1.0)).all()
+            assert (w[(st != 0) & (st != 1)] == 0.0).all()
+    rays = W.inplane_bundle(16, 1)
+    p = rays[0] * (-rays[4]) + rays[1] * rays[3]
+    r = oracle.trace(W.cloak(1), W.opts_dp45(), O, rays)
+    hit = (r["status"] == 0) & (np.abs(p) < 1.5)
+    assert hit.sum() > 4
+    # in-plane: the ordinary polarization (perpendicular to theta_hat) is
+    # along z, i.e. s-polarized, and index-matched at both interfaces
+    np.testing.assert_allclose(r["trans"][hit], 0.5, atol=1e-12)
