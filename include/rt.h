@@ -166,12 +166,20 @@ int rt_free_cloak(rt_cloak cloak);
      hres:   n doubles or NULL, |v^T M v - 1| at the last interface (NaN if the
              ray never entered)
      nsteps: n int32 or NULL, integrator step attempts
+     trans:  n doubles or NULL, the ray's intensity weight from Eq. (12): the
+             unpolarized transmission into branch `pol` at entry, times the
+             same-branch reflectance at every internal reflection at the outer
+             surface or an end cap, times the transmission into vacuum at exit.
+             Plane-wave transmittances at a locally flat interface, from
+             continuity of tangential E and H (Sect. 3); the cross-polarized
+             reflected wave is dropped. 1 for a miss, 0 for a ray that did not
+             leave. Needs RT_PREC_FP64.
    n = 0 is a no-op. Errors: RT_E_INVALID (NULL handle/options/required
-   pointer, n < 0, r_out < r2, bad options), RT_E_NOMEM (workspace),
-   RT_E_DEVICE (launch failure). */
+   pointer, n < 0, r_out < r2, bad options), RT_E_UNSUPPORTED (trans with
+   RT_PREC_MIXED), RT_E_NOMEM (workspace), RT_E_DEVICE (launch failure). */
 int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64_t n,
                    const double *in6, double *out6, double *opl, int32_t *status,
-                   double *hres, int32_t *nsteps, void *stream);
+                   double *hres, int32_t *nsteps, double *trans, void *stream);
 
 /* Render n_cams views of the room with the cloak (NULL = empty room) for each
    branch in pol_mask (bit 0 ordinary, bit 1 extraordinary), tracing each

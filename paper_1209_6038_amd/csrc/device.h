@@ -472,6 +472,205 @@ __device__ __forceinline__ void ham_convert(double a, double kappa, const double
 }
 
 // ---------------------------------------------------------------------------
+// Eq. (12): intensity transmission at a plane interface (Sect. 3), from the
+// tangential fields alone. Local basis (t1, t2, n), n pointing out of the
+// crystal, t1 along the tangential wave vector, so every wave vector is
+// (k1, 0, q) with complex q for evanescent waves. Fields: H = k x E; the
+// normal power flux is Re(E1 H2* - E2 H1*) / 2. In vacuum k.E = 0 gives the
+// tangential H from the tangential E (admittance, with k2 = 0):
+//   H1 = -q E2,  H2 = (k1^2 + q^2) E1 / q.
+// Continuity of tangential E and H, with the vacuum wave eliminated through
+// its admittance, leaves a 2 x 2 complex system for the two crystal waves.
+// Crystal waves: ordinary E = k x c; extraordinary D = (k.k) c - (c.k) k,
+// E = eps^-1 D, eps^-1 = I / eo + (1 / ee - 1 / eo) c c^T; where k is along
+// c both coincide and E = (0, 1, 0), k x (0, 1, 0) are taken.
+// ---------------------------------------------------------------------------
+struct cplx {
+  double re, im;
+};
+__device__ __forceinline__ cplx cx(double r, double i = 0.0) { return cplx{r, i}; }
+__device__ __forceinline__ cplx operator+(cplx a, cplx b) { return cplx{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cplx operator-(cplx a, cplx b) { return cplx{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cplx operator*(cplx a, cplx b) {
+  return cplx{fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
+}
+__device__ __forceinline__ cplx operator*(double s, cplx a) { return cplx{s * a.re, s * a.im}; }
+__device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
+  const double d = 1.0 / fma(b.re, b.re, b.im * b.im);
+  return cplx{fma(a.re, b.re, a.im * b.im) * d, fma(a.im, b.re, -a.re * b.im) * d};
+}
+__device__ __forceinline__ double cabs2(cplx a) { return fma(a.re, a.re, a.im * a.im); }
+// Re(a b*)
+__device__ __forceinline__ double cre_conj(cplx a, cplx b) { return fma(a.re, b.re, a.im * b.im); }
+
+// normal component of a wave: dir = +1 carries power (or decays) towards
+// +n, -1 towards -n; ordinary / vacuum: q^2 = eps - k1^2
+__device__ __forceinline__ cplx q_iso_dev(double eps, double k1, int dir) {
+  const double d = eps - k1 * k1;
+  return d >= 0.0 ? cx(dir * sqrt(d)) : cx(0.0, dir * sqrt(-d));
+}
+
+// extraordinary: k^T eps k = eo ee with k = (k1, 0, q)
+__device__ __forceinline__ cplx q_extra_dev(double eo, double ee, const double c[3], double k1, int dir) {
+  const double de = ee - eo;
+  const double a = eo + de * c[2] * c[2];
+  const double b = de * c[2] * c[0] * k1;
+  const double c0 = fma(eo + de * c[0] * c[0], k1 * k1, -eo * ee);
+  const double disc = fma(b, b, -a * c0);
+  const double ia = 1.0 / a;
+  return disc >= 0.0 ? cx((-b + dir * sqrt(disc)) * ia) : cx(-b * ia, dir * sqrt(-disc) * ia);
+}
+
+// tangential (E1, E2, H1, H2) of a crystal wave k = (k1, 0, q)
+__device__ __forceinline__ void crystal_tangential(double eo, double ee, const double c[3], bool ordinary,
+                                                   double k1, cplx q, cplx f[4]) {
+  // k x c
+  const cplx kc0 = cx(0.0) - q * cx(c[1]);
+  const cplx kc1 = q * cx(c[0]) - cx(k1 * c[2]);
+  const cplx kc2 = cx(k1 * c[1]);
+  const double deg = cabs2(kc0) + cabs2(kc1) + cabs2(kc2);
+  const double kk = k1 * k1 + cabs2(q);
+  cplx E0, E1, E2;
+  if (deg <= 1e-24 * kk) {
+    if (ordinary) {
+      E0 = cx(0.0); E1 = cx(1.0); E2 = cx(0.0);
+    } else {  // k x (0, 1, 0)
+      E0 = cx(0.0) - q; E1 = cx(0.0); E2 = cx(k1);
+    }
+  } else if (ordinary) {
+    E0 = kc0; E1 = kc1; E2 = kc2;
+  } else {
+    const cplx kdk = cx(k1 * k1) + q * q;
+    const cplx cdk = cx(c[0] * k1) + cx(c[2]) * q;
+    const cplx D0 = kdk * cx(c[0]) - cdk * cx(k1);
+    const cplx D1 = kdk * cx(c[1]);
+    const cplx D2 = kdk * cx(c[2]) - cdk * q;
+    const cplx cD = cx(c[0]) * D0 + cx(c[1]) * D1 + cx(c[2]) * D2;
+    const double io = 1.0 / eo, g = 1.0 / ee - io;
+    E0 = io * D0 + (g * c[0]) * cD;
+    E1 = io * D1 + (g * c[1]) * cD;
+    E2 = io * D2 + (g * c[2]) * cD;
+  }
+  // H = k x E with k = (k1, 0, q)
+  f[0] = E0;
+  f[1] = E1;
+  f[2] = cx(0.0) - q * E1;       // H1 = k2 E2 - q E1 with k2 = 0... = -q E1
+  f[3] = q * E0 - cx(k1) * E2;   // H2 = q E0 - k1 E2
+}
+
+__device__ __forceinline__ double flux_t(const cplx f[4]) {
+  return 0.5 * (cre_conj(f[0], f[3]) - cre_conj(f[1], f[2]));
+}
+
+// local basis at an interface: n outward, t1 along the tangential part of k
+__device__ __forceinline__ void interface_basis(const double n[3], const double k[3], double t1[3], double t2[3],
+                                                double &k1) {
+  const double kn = k[0] * n[0] + k[1] * n[1] + k[2] * n[2];
+  double kt[3] = {k[0] - kn * n[0], k[1] - kn * n[1], k[2] - kn * n[2]};
+  k1 = sqrt(kt[0] * kt[0] + kt[1] * kt[1] + kt[2] * kt[2]);
+  if (k1 > 1e-12) {
+    const double ik = 1.0 / k1;
+    t1[0] = kt[0] * ik; t1[1] = kt[1] * ik; t1[2] = kt[2] * ik;
+  } else {
+    // any tangent: n x (the axis least aligned with n)
+    const double ax = fabs(n[0]), ay = fabs(n[1]), az = fabs(n[2]);
+    const double e[3] = {ax <= ay && ax <= az ? 1.0 : 0.0, (ay < ax && ay <= az) ? 1.0 : 0.0,
+                         (az < ax && az < ay) ? 1.0 : 0.0};
+    double u[3] = {n[1] * e[2] - n[2] * e[1], n[2] * e[0] - n[0] * e[2], n[0] * e[1] - n[1] * e[0]};
+    const double iu = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    t1[0] = u[0] * iu; t1[1] = u[1] * iu; t1[2] = u[2] * iu;
+    k1 = 0.0;
+  }
+  t2[0] = n[1] * t1[2] - n[2] * t1[1];
+  t2[1] = n[2] * t1[0] - n[0] * t1[2];
+  t2[2] = n[0] * t1[1] - n[1] * t1[0];
+}
+
+// Solve a x + b y = r (two complex 2-vectors per column) by Cramer's rule.
+__device__ __forceinline__ void solve2(const cplx a[2], const cplx b[2], const cplx r[2], cplx &x, cplx &y) {
+  const cplx det = a[0] * b[1] - a[1] * b[0];
+  x = cdiv(r[0] * b[1] - r[1] * b[0], det);
+  y = cdiv(a[0] * r[1] - a[1] * r[0], det);
+}
+
+// Unpolarized transmission from vacuum (unit direction d, n outward) into
+// the crystal wave of `extra` (0 ordinary, 1 extraordinary).
+__device__ __forceinline__ double fresnel_in_dev(double eo, double ee, const double cax[3], const double n[3],
+                                                 const double d[3], int extra) {
+  double t1[3], t2[3], k1;
+  interface_basis(n, d, t1, t2, k1);
+  const double c[3] = {cax[0] * t1[0] + cax[1] * t1[1] + cax[2] * t1[2],
+                       cax[0] * t2[0] + cax[1] * t2[1] + cax[2] * t2[2],
+                       cax[0] * n[0] + cax[1] * n[1] + cax[2] * n[2]};
+  const double qi = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];  // < 0
+  const cplx qr = q_iso_dev(1.0, k1, +1);
+  const cplx qo = q_iso_dev(eo, k1, -1), qe = q_extra_dev(eo, ee, c, k1, -1);
+  cplx fo[4], fe[4];
+  crystal_tangential(eo, ee, c, true, k1, qo, fo);
+  crystal_tangential(eo, ee, c, false, k1, qe, fe);
+  // reflected admittance Y (k2 = 0): H1 = -q E2, H2 = (k1^2 + q^2) / q E1
+  const cplx y22 = cdiv(cx(k1 * k1) + qr * qr, qr);
+  // columns h - Y e of the two crystal waves
+  const cplx A[2] = {fo[2] - (cx(0.0) - qr * fo[1]), fo[3] - y22 * fo[0]};
+  const cplx B[2] = {fe[2] - (cx(0.0) - qr * fe[1]), fe[3] - y22 * fe[0]};
+  double T = 0.0;
+  for (int pol = 0; pol < 2; ++pol) {
+    // s: E = (0, 1, 0); p: E = k x (0, 1, 0) = (-qi, 0, k1)
+    cplx fi[4];
+    if (pol == 0) {
+      fi[0] = cx(0.0); fi[1] = cx(1.0);
+      fi[2] = cx(-qi); fi[3] = cx(0.0);  // H = k x E: H1 = -qi E1, H2 = qi E0 - k1 E2
+    } else {
+      fi[0] = cx(-qi); fi[1] = cx(0.0);
+      fi[2] = cx(0.0); fi[3] = cx(-qi * qi - k1 * k1);
+    }
+    // H_i - Y E_i
+    const cplx r[2] = {fi[2] - (cx(0.0) - qr * fi[1]), fi[3] - y22 * fi[0]};
+    cplx ao, ae;
+    solve2(A, B, r, ao, ae);
+    const double si = fabs(flux_t(fi));
+    const double fm = extra ? cabs2(ae) * fabs(flux_t(fe)) : cabs2(ao) * fabs(flux_t(fo));
+    T += fm / si;
+  }
+  return 0.5 * T;
+}
+
+// A crystal wave of `extra` with wave vector k (power towards +n) meets the
+// interface: transmitted fraction T and the fraction R reflected into the
+// same wave type.
+__device__ __forceinline__ void fresnel_out_dev(double eo, double ee, const double cax[3], const double n[3],
+                                                const double k[3], int extra, double &T, double &R) {
+  double t1[3], t2[3], k1;
+  interface_basis(n, k, t1, t2, k1);
+  const double c[3] = {cax[0] * t1[0] + cax[1] * t1[1] + cax[2] * t1[2],
+                       cax[0] * t2[0] + cax[1] * t2[1] + cax[2] * t2[2],
+                       cax[0] * n[0] + cax[1] * n[1] + cax[2] * n[2]};
+  const double qm = k[0] * n[0] + k[1] * n[1] + k[2] * n[2];
+  const cplx qv = q_iso_dev(1.0, k1, +1);
+  const cplx qo = q_iso_dev(eo, k1, -1), qe = q_extra_dev(eo, ee, c, k1, -1);
+  cplx fm[4], fo[4], fe[4];
+  crystal_tangential(eo, ee, c, !extra, k1, cx(qm), fm);
+  crystal_tangential(eo, ee, c, true, k1, qo, fo);
+  crystal_tangential(eo, ee, c, false, k1, qe, fe);
+  const cplx y22 = cdiv(cx(k1 * k1) + qv * qv, qv);
+  // (h - Y e) of the reflected waves; right side Y e_m - h_m
+  const cplx A[2] = {fo[2] - (cx(0.0) - qv * fo[1]), fo[3] - y22 * fo[0]};
+  const cplx B[2] = {fe[2] - (cx(0.0) - qv * fe[1]), fe[3] - y22 * fe[0]};
+  const cplx r[2] = {(cx(0.0) - qv * fm[1]) - fm[2], y22 * fm[0] - fm[3]};
+  cplx bo, be;
+  solve2(A, B, r, bo, be);
+  const double si = fabs(flux_t(fm));
+  // transmitted tangential E = e_m + bo e_o + be e_e, H from the admittance
+  cplx ft[4];
+  ft[0] = fm[0] + bo * fo[0] + be * fe[0];
+  ft[1] = fm[1] + bo * fo[1] + be * fe[1];
+  ft[2] = cx(0.0) - qv * ft[1];
+  ft[3] = y22 * ft[0];
+  T = fabs(flux_t(ft)) / si;
+  R = extra ? cabs2(be) * fabs(flux_t(fe)) / si : cabs2(bo) * fabs(flux_t(fo)) / si;
+}
+
+// ---------------------------------------------------------------------------
 // kind dispatch helpers (wave-uniform in practice: slots are grouped by kind)
 // ---------------------------------------------------------------------------
 template <bool MIXED>
@@ -550,6 +749,21 @@ __device__ __forceinline__ bool vacuum_entry(const CloakP& c, const double o[3],
   }
   s_out = best;
   return found;
+}
+
+// uniaxial principal values and optic axis at x (Eq. (14) / Eq. (15), Eq. (1))
+__device__ __forceinline__ void material_axis(const CloakP &c, const double x[3], double &eo, double &ee,
+                                              double cax[3]) {
+  const double w = rsq64(fma(x[0], x[0], x[1] * x[1]));
+  const double q = fma(-c.a, w, 1.0);
+  const double ks = c.kappa * q * q;
+  if (c.axis == 0) {  // radial: c = r_hat, eps_e = eps_r
+    eo = c.kappa; ee = ks;
+    cax[0] = x[0] * w; cax[1] = x[1] * w; cax[2] = 0.0;
+  } else {            // azimuthal: c = theta_hat, eps_e = eps_theta
+    eo = ks; ee = c.kappa;
+    cax[0] = -x[1] * w; cax[1] = x[0] * w; cax[2] = 0.0;
+  }
 }
 
 // outward normal of boundary `id` at x (the inner boundary's normal points

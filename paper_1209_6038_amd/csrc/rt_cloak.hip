@@ -72,6 +72,7 @@ __host__ __device__ constexpr int C_OFF(int b) { return C_OBASE + b * C_LINE; }
 struct Table {
   double *px, *py, *pz, *vx, *vy, *vz;
   double *t, *h, *opl0, *hres;
+  double *wt;  // Eq. (12) weight carried along the ray (rt_trace_batch with trans)
   int *nsteps, *bounces, *status, *kind;
   long long *key;
   int *order;   // integrator queue: slots sorted hardest first
@@ -216,10 +217,10 @@ __global__ void __launch_bounds__(256) k_tb_entry(CloakP c, OptsP o, Table T, in
                                                   const double *__restrict__ in6,
                                                   double *__restrict__ out6, double *__restrict__ opl,
                                                   int *__restrict__ status, double *__restrict__ hres,
-                                                  int *__restrict__ nsteps) {
+                                                  int *__restrict__ nsteps, double *__restrict__ trans) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   bool enter = false;
-  double x[3], v[3], s = 0.0;
+  double x[3], v[3], s = 0.0, w_in = 0.0;
   int skey = 0;
   if (i < n) {
     double org[3], d[3];
@@ -254,6 +255,11 @@ __global__ void __launch_bounds__(256) k_tb_entry(CloakP c, OptsP o, Table T, in
         } else if (refract_in(c, kind, surf, x, d, v)) {
           enter = true;
           skey = sort_key(c, kind, x, d);
+          if (trans) {
+            double eo, ee, cax[3];
+            material_axis(c, x, eo, ee, cax);
+            w_in = fresnel_in_dev(eo, ee, cax, nrm, d, kind & 1);
+          }
         } else {
           p[0] = x[0]; p[1] = x[1]; p[2] = x[2];
           L = s;
@@ -275,11 +281,15 @@ __global__ void __launch_bounds__(256) k_tb_entry(CloakP c, OptsP o, Table T, in
       status[i] = st;
       if (hres) hres[i] = __builtin_nan("");
       if (nsteps) nsteps[i] = 0;
+      if (trans) trans[i] = st == RT_RAY_MISSED ? 1.0 : 0.0;
     }
   }
   __shared__ unsigned int sh[16];
   unsigned int sl = block_append(T.ctr + C_N(0), enter, sh);
-  if (enter) put_slot(T, (int)sl, x, v, kind, i, s, o.h0, skey);
+  if (enter) {
+    put_slot(T, (int)sl, x, v, kind, i, s, o.h0, skey);
+    if (trans) T.wt[sl] = w_in;
+  }
 }
 
 // counting sort of the entered slots by key (LDS-privatized histogram,
@@ -345,13 +355,33 @@ struct Lane {
   double lo, hi, ht;         // boundary search: bracket and trial length
   int ns, bounces, rid, riter;
   bool after_reject;
+  double wt;  // Eq. (12) weight (FRES only)
 };
 
 // One iteration of a lane of branch KIND: one attempt of the scheme from the
 // base state, then either the step controller (stepping) or one safeguarded
 // Newton update of the crossing length (rid >= 0: locating the crossing of
 // boundary rid). Returns the final status when the ray stops, else -1.
-template <int KIND, bool MIXED, bool HAM>
+// Eq. (12) at an interface event of branch KIND: the wave k = M v meets
+// boundary rid at x; transmitted fraction and same-type reflected fraction
+template <int KIND>
+__device__ __forceinline__ void fresnel_event(const CloakP &c, int rid, const double x[3], const double v[3],
+                                              double &Tt, double &Rr) {
+  double eo, ee, cax[3], nrm[3], k[3];
+  material_axis(c, x, eo, ee, cax);
+  boundary_normal(rid, x, nrm);
+  double rh[2], th[2], w;
+  local_frame(x, rh, th, w);
+  double mr, mt, mz;
+  metric_diag(KIND, c.kappa, c.a, w, mr, mt, mz);
+  const double vr = v[0] * rh[0] + v[1] * rh[1], vt = v[0] * th[0] + v[1] * th[1];
+  k[0] = mr * vr * rh[0] + mt * vt * th[0];
+  k[1] = mr * vr * rh[1] + mt * vt * th[1];
+  k[2] = mz * v[2];
+  fresnel_out_dev(eo, ee, cax, nrm, k, KIND & 1, Tt, Rr);
+}
+
+template <int KIND, bool MIXED, bool HAM, bool FRES>
 __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o, double band2,
                                        double tol, double &hr) {
   if (L.rid < 0 && L.ns >= o.max_steps) return RT_RAY_MAXSTEPS;
@@ -491,12 +521,16 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
     reflect_inside(B_INNER, L.x, L.v);
   } else {
     double d[3];
+    double Tt = 0.0, Rr = 0.0;
+    if constexpr (FRES) fresnel_event<KIND>(c, rid, L.x, L.v, Tt, Rr);
     if (refract_out(c, KIND, rid, L.x, L.v, d, hr)) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) L.v[i] = d[i];
+      if constexpr (FRES) L.wt *= Tt;
       return RT_RAY_EXITED;
     }
     if (L.bounces >= o.max_bounces) return RT_RAY_TIR;
+    if constexpr (FRES) L.wt *= Rr;
     reflect_inside(rid, L.x, L.v);
   }
   // continue from the boundary point after the reflection
@@ -525,7 +559,7 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
 // one atomic each and refills its idle lanes every `refill` attempts. The
 // lane state lives here, specialized for the branch, so no code of another
 // branch is interleaved with the step loop.
-template <int KIND, bool MIXED, bool HAM>
+template <int KIND, bool MIXED, bool HAM, bool FRES>
 __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, const Table &T, const SegMap &sm,
                                             int seg, double band2, double tol, int refill,
                                             unsigned int &drained) {
@@ -562,6 +596,7 @@ __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, con
         L.rid = -1;
         if constexpr (HAM) ham_convert<KIND>(c.a, c.kappa, L.x, L.v, true);  // v -> k
         else accel<KIND, MIXED>(c.a, band2, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
+        if constexpr (FRES) L.wt = T.wt[slot];
       }
       cur = min(cur + (unsigned int)__popcll(m), end);
       m = __ballot(slot < 0);
@@ -578,7 +613,7 @@ __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, con
     for (int it = 0; it < refill; ++it) {
       if (slot >= 0) {
         double hr = __builtin_nan("");
-        const int stop = iterate<KIND, MIXED, HAM>(L, c, o, band2, tol, hr);
+        const int stop = iterate<KIND, MIXED, HAM, FRES>(L, c, o, band2, tol, hr);
         if (stop >= 0) {
           // the Hamiltonian form holds k until an interface: report v
           if constexpr (HAM)
@@ -589,6 +624,7 @@ __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, con
           T.bounces[slot] = L.bounces;
           T.status[slot] = stop;
           T.hres[slot] = hr;
+          if constexpr (FRES) T.wt[slot] = L.wt;
           slot = -1;
         }
       }
@@ -596,7 +632,7 @@ __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, con
   }
 }
 
-template <bool MIXED, bool HAM>
+template <bool MIXED, bool HAM, bool FRES>
 __global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int refill) {
   // the queue holds the used parts of the segments one after the other,
   // each sorted hardest first and holding one branch (every entry kernel
@@ -628,10 +664,10 @@ __global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int
     while (drained >> seg & 1u) seg = (seg + 1) % NSEG;
     const int kind = __builtin_amdgcn_readfirstlane(T.kind[(long long)seg * T.cap]);
     switch (kind) {
-      case K_RE: run_segment<K_RE, MIXED, HAM>(c, o, T, sm, seg, band2, tol, refill, drained); break;
-      case K_AO: run_segment<K_AO, MIXED, HAM>(c, o, T, sm, seg, band2, tol, refill, drained); break;
-      case K_AE: run_segment<K_AE, MIXED, HAM>(c, o, T, sm, seg, band2, tol, refill, drained); break;
-      default: run_segment<K_RO, MIXED, HAM>(c, o, T, sm, seg, band2, tol, refill, drained); break;
+      case K_RE: run_segment<K_RE, MIXED, HAM, FRES>(c, o, T, sm, seg, band2, tol, refill, drained); break;
+      case K_AO: run_segment<K_AO, MIXED, HAM, FRES>(c, o, T, sm, seg, band2, tol, refill, drained); break;
+      case K_AE: run_segment<K_AE, MIXED, HAM, FRES>(c, o, T, sm, seg, band2, tol, refill, drained); break;
+      default: run_segment<K_RO, MIXED, HAM, FRES>(c, o, T, sm, seg, band2, tol, refill, drained); break;
     }
   }
 }
@@ -640,7 +676,7 @@ __global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int
 __global__ void __launch_bounds__(256) k_tb_finish(CloakP c, OptsP o, Table T, long long n,
                                                    double *__restrict__ out6, double *__restrict__ opl,
                                                    int *__restrict__ status, double *__restrict__ hres,
-                                                   int *__restrict__ nsteps) {
+                                                   int *__restrict__ nsteps, double *__restrict__ trans) {
   unsigned int n0 = T.ctr[C_N(0)];
   unsigned int stride = gridDim.x * blockDim.x;
   for (unsigned int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n0; idx += stride) {
@@ -669,6 +705,7 @@ __global__ void __launch_bounds__(256) k_tb_finish(CloakP c, OptsP o, Table T, l
     status[i] = st;
     if (hres) hres[i] = hr;
     if (nsteps) nsteps[i] = T.nsteps[s];
+    if (trans) trans[i] = st == RT_RAY_EXITED ? T.wt[s] : 0.0;
   }
 }
 
@@ -1149,7 +1186,7 @@ int ws_reserve(Workspace &ws, long long cap, long long codes_len, int ncam) {
   long long ns = (long long)NSEG * cap;
   size_t off = 0;
   auto take = [&](size_t b) { size_t o = off; off = align_up(off + b); return o; };
-  size_t o_d = take(sizeof(double) * 10 * ns);
+  size_t o_d = take(sizeof(double) * 11 * ns);
   size_t o_i = take(sizeof(int) * 4 * ns);
   size_t o_k = take(sizeof(long long) * ns);
   size_t o_q = take(sizeof(int) * 2 * ns);
@@ -1167,7 +1204,7 @@ int ws_reserve(Workspace &ws, long long cap, long long codes_len, int ncam) {
   Table &T = ws.T;
   double *D = (double *)(b + o_d);
   T.px = D; T.py = D + ns; T.pz = D + 2 * ns; T.vx = D + 3 * ns; T.vy = D + 4 * ns; T.vz = D + 5 * ns;
-  T.t = D + 6 * ns; T.h = D + 7 * ns; T.opl0 = D + 8 * ns; T.hres = D + 9 * ns;
+  T.t = D + 6 * ns; T.h = D + 7 * ns; T.opl0 = D + 8 * ns; T.hres = D + 9 * ns; T.wt = D + 10 * ns;
   int *I = (int *)(b + o_i);
   T.nsteps = I; T.bounces = I + ns; T.status = I + 2 * ns; T.kind = I + 3 * ns;
   T.key = (long long *)(b + o_k);
@@ -1270,10 +1307,10 @@ unsigned int grid_for(long long n, int block) {
   return (unsigned int)std::max(1LL, g);
 }
 
-template <bool MIXED, bool HAM>
+template <bool MIXED, bool HAM, bool FRES>
 unsigned int transit_grid_t(int block) {
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_transit<MIXED, HAM>, block, 0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_transit<MIXED, HAM, FRES>, block, 0) != hipSuccess ||
       occ <= 0)
     occ = 1;
   return (unsigned int)(num_cu() * occ);
@@ -1281,27 +1318,34 @@ unsigned int transit_grid_t(int block) {
 
 // the integrator variant the options select: FP64, mixed precision or the
 // Hamiltonian form
-unsigned int transit_grid(const OptsP &o, int block) {
-  if (o.scheme == RT_SCHEME_RK4_HAM) return transit_grid_t<false, true>(block);
-  return o.precision == RT_PREC_MIXED ? transit_grid_t<true, false>(block) : transit_grid_t<false, false>(block);
+unsigned int transit_grid(const OptsP &o, int block, bool fres = false) {
+  if (o.scheme == RT_SCHEME_RK4_HAM)
+    return fres ? transit_grid_t<false, true, true>(block) : transit_grid_t<false, true, false>(block);
+  if (fres) return transit_grid_t<false, false, true>(block);
+  return o.precision == RT_PREC_MIXED ? transit_grid_t<true, false, false>(block)
+                                     : transit_grid_t<false, false, false>(block);
 }
 
 // integrate the slots already placed in the table: order them hardest
 // first, then one persistent integrator launch (kernel launches only)
 void run_transit(const CloakP &c, const OptsP &o, const Table &T, int block, int refill,
-                 unsigned int grid, hipStream_t s, bool profile) {
+                 unsigned int grid, hipStream_t s, bool profile, bool fres = false) {
   hipLaunchKernelGGL(k_sort_hist, dim3(num_cu() * 4), dim3(256), 0, s, T);
   hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(64), 0, s, T);
   hipLaunchKernelGGL(k_sort_scatter, dim3(num_cu() * 4), dim3(256), 0, s, T);
   ProfEvent pe;
   bool on = false;
   if (profile) prof_begin(s, pe, on);
-  if (o.scheme == RT_SCHEME_RK4_HAM)
-    hipLaunchKernelGGL((k_transit<false, true>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
+  if (o.scheme == RT_SCHEME_RK4_HAM && fres)
+    hipLaunchKernelGGL((k_transit<false, true, true>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
+  else if (o.scheme == RT_SCHEME_RK4_HAM)
+    hipLaunchKernelGGL((k_transit<false, true, false>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
+  else if (fres)
+    hipLaunchKernelGGL((k_transit<false, false, true>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
   else if (o.precision == RT_PREC_MIXED)
-    hipLaunchKernelGGL((k_transit<true, false>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
+    hipLaunchKernelGGL((k_transit<true, false, false>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
   else
-    hipLaunchKernelGGL((k_transit<false, false>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
+    hipLaunchKernelGGL((k_transit<false, false, false>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
   if (profile) prof_end(s, pe, on);
 }
 
@@ -1656,7 +1700,7 @@ int rt_release_workspace(void) {
 
 int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64_t n,
                    const double *in6, double *out6, double *opl, int32_t *status, double *hres,
-                   int32_t *nsteps, void *stream) {
+                   int32_t *nsteps, double *trans, void *stream) {
   if (!cloak) return fail(RT_E_INVALID, "cloak handle is NULL");
   int e = check_opts(opts, cloak->d.r2, true);
   if (e) return e;
@@ -1666,6 +1710,8 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
   if (n == 0) return RT_OK;
   if (n > (1LL << 30)) return fail(RT_E_INVALID, "n must be <= 2^30 per call");
   if (!in6 || !out6 || !opl || !status) return fail(RT_E_INVALID, "in6, out6, opl and status are required");
+  if (trans && opts->precision != RT_PREC_FP64)
+    return fail(RT_E_UNSUPPORTED, "the Eq. (12) weights are computed in FP64 only");
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_ws_mu);
   e = ws_reserve(g_ws, n, 0, 0);
@@ -1676,17 +1722,18 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
   int block = opts->block ? opts->block : 256;
   int refill = opts->refill_period ? opts->refill_period : 2;
   int kind = c.axis * 2 + pol;
-  unsigned int grid = transit_grid(o, block);
+  const bool fres = trans != nullptr;
+  unsigned int grid = transit_grid(o, block, fres);
   hipLaunchKernelGGL(k_zero, dim3((C_COUNT + 255) / 256), dim3(256), 0, s, T.ctr, (int)C_COUNT);
   hipLaunchKernelGGL(k_tb_entry, dim3(grid_for(n, 256)), dim3(256), 0, s, c, o, T, kind, (long long)n,
-                     in6, out6, opl, status, hres, nsteps);
+                     in6, out6, opl, status, hres, nsteps, trans);
   e = launch_err("entry launch");
   if (e) return e;
-  run_transit(c, o, T, block, refill, grid, s, true);
+  run_transit(c, o, T, block, refill, grid, s, true, fres);
   e = launch_err("transit launch");
   if (e) return e;
   hipLaunchKernelGGL(k_tb_finish, dim3(num_cu() * 8), dim3(256), 0, s, c, o, T, (long long)n, out6,
-                     opl, status, hres, nsteps);
+                     opl, status, hres, nsteps, trans);
   return launch_err("finish launch");
 }
 

@@ -111,7 +111,7 @@ def lib():
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.rt_build_cloak.argtypes = [ctypes.POINTER(CloakDesc), ctypes.POINTER(vp)]
         L.rt_free_cloak.argtypes = [vp]
-        L.rt_trace_batch.argtypes = [vp, ctypes.POINTER(TraceOpts), i32, i64, vp, vp, vp, vp, vp, vp, vp]
+        L.rt_trace_batch.argtypes = [vp, ctypes.POINTER(TraceOpts), i32, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.rt_render.argtypes = [vp, ctypes.POINTER(TraceOpts), ctypes.POINTER(Room),
                                 ctypes.POINTER(Camera), i32, i32, vp, ctypes.POINTER(RenderAux), vp]
         L.rt_render_multi.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(TraceOpts),
@@ -230,11 +230,13 @@ class Cloak:
             pass
 
 
-def trace_batch(cloak: Cloak, opts: dict, pol: int, in6, with_aux: bool = True):
+def trace_batch(cloak: Cloak, opts: dict, pol: int, in6, with_aux: bool = True,
+                with_trans: bool = False):
     """rt_trace_batch on a float64 CUDA tensor in6 of shape (6, n).
 
-    Returns dict(out=(6, n) float64, opl, status int32[, hres, nsteps]) of
-    device tensors (asynchronous on the current stream)."""
+    Returns dict(out=(6, n) float64, opl, status int32[, hres, nsteps][, trans])
+    of device tensors (asynchronous on the current stream). `trans` is the
+    Eq. (12) intensity weight of each ray (FP64 options only)."""
     import torch
     assert in6.is_cuda and in6.dtype == torch.float64 and in6.dim() == 2 and in6.shape[0] == 6
     in6 = in6.contiguous()
@@ -245,13 +247,16 @@ def trace_batch(cloak: Cloak, opts: dict, pol: int, in6, with_aux: bool = True):
     st = torch.empty(n, dtype=torch.int32, device=dev)
     hres = torch.empty(n, dtype=torch.float64, device=dev) if with_aux else None
     ns = torch.empty(n, dtype=torch.int32, device=dev) if with_aux else None
+    tr = torch.empty(n, dtype=torch.float64, device=dev) if with_trans else None
     o = trace_opts(opts)
     _check(lib().rt_trace_batch(cloak.handle, ctypes.byref(o), int(pol), int(n), _ptr(in6), _ptr(out),
-                                _ptr(opl), _ptr(st), _ptr(hres), _ptr(ns), _stream()))
+                                _ptr(opl), _ptr(st), _ptr(hres), _ptr(ns), _ptr(tr), _stream()))
     r = {"out": out, "opl": opl, "status": st}
     if with_aux:
         r["hres"] = hres
         r["nsteps"] = ns
+    if with_trans:
+        r["trans"] = tr
     return r
 
 

@@ -17,12 +17,12 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_trace(cloak_d, opts, branch, rays):
+def gpu_trace(cloak_d, opts, branch, rays, with_trans=False):
     import torch
     from paper_1209_6038_amd import rt
     c = rt.Cloak(cloak_d)
     t = torch.from_numpy(np.ascontiguousarray(rays)).cuda()
-    r = rt.trace_batch(c, opts, branch, t)
+    r = rt.trace_batch(c, opts, branch, t, with_trans=with_trans)
     torch.cuda.synchronize()
     out = {k: v.cpu().numpy() for k, v in r.items()}
     c.close()

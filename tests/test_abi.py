@@ -86,24 +86,30 @@ def test_argument_validation_needs_no_gpu(lib):
     assert lib.rt_build_cloak(ctypes.byref(good), ctypes.byref(h)) == rt.RT_OK
     o = rt.trace_opts({"scheme": 1, "h": 1e-2, "hmax": 1e-3})
     assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 10, None, None, None, None, None, None,
-                              None) == rt.RT_E_INVALID
+                              None, None) == rt.RT_E_INVALID
     o = rt.trace_opts({"scheme": 0, "h": 1e-3, "r_out": 1.5})
     assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 10, ctypes.c_void_p(8), ctypes.c_void_p(8),
-                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None) == rt.RT_E_INVALID
+                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None, None) == rt.RT_E_INVALID
     assert b"r_out" in lib.rt_last_error()
     o = rt.trace_opts({"scheme": 0, "h": 1e-3})
     assert lib.rt_trace_batch(h, ctypes.byref(o), 5, 10, ctypes.c_void_p(8), ctypes.c_void_p(8),
-                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None) == rt.RT_E_INVALID
+                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None, None) == rt.RT_E_INVALID
     assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 0, None, None, None, None, None, None,
-                              None) == rt.RT_OK  # n = 0 is a no-op
+                              None, None) == rt.RT_OK  # n = 0 is a no-op
     # the Hamiltonian form (scheme 2) runs in FP64 only; scheme 3 does not exist
     o = rt.trace_opts({"scheme": rt.RK4_HAM, "precision": rt.MIXED, "h": 1e-3, "fp64_band": 0.05})
     assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 10, ctypes.c_void_p(8), ctypes.c_void_p(8),
-                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None) == rt.RT_E_UNSUPPORTED
+                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None, None) == rt.RT_E_UNSUPPORTED
     assert b"FP64" in lib.rt_last_error()
+    # Eq. (12) weights are computed in FP64 only
+    o = rt.trace_opts({"scheme": rt.DP45, "precision": rt.MIXED, "h": 1e-2, "fp64_band": 0.05})
+    assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 10, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, ctypes.c_void_p(8),
+                              None) == rt.RT_E_UNSUPPORTED
+    assert b"Eq. (12)" in lib.rt_last_error()
     o = rt.trace_opts({"scheme": 3, "h": 1e-3})
     assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 10, ctypes.c_void_p(8), ctypes.c_void_p(8),
-                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None) == rt.RT_E_INVALID
+                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None, None) == rt.RT_E_INVALID
     assert lib.rt_free_cloak(h) == rt.RT_OK
 
 
@@ -145,6 +151,6 @@ def test_render_argument_validation_needs_no_gpu(lib):
     cams = (rt.Camera * 1)(rt.camera(W.orbit_camera(0.3, 20.0, 8, 8)))
     o = rt.trace_opts(W.render_opts())
     assert lib.rt_render_surrogate(None, harr, 1, ctypes.byref(o), ctypes.byref(room), cams, 1, 3, 0, fake_rgb,
-                                   None, None, None) == rt.RT_E_INVALID
+                                   None, None, None, None) == rt.RT_E_INVALID
     assert b"model" in lib.rt_last_error()
     assert lib.rt_free_cloak(h) == rt.RT_OK

@@ -57,6 +57,73 @@ def test_3d_dp45_parity(axis, branch, precision):
                     label=f"3d a{axis} b{branch} mixed")
 
 
+# The Eq. (12) weight is a smooth function of the state at each interface
+# except within a hair of a critical angle, so the 1e-6 agreement of the exit
+# states carries over to it; 1e-5 leaves room for the random sets' rays
+# closest to grazing.
+TRANS_TOL = 1e-5
+
+
+def check_trans(g, o, label):
+    ex = o["status"] == 0
+    assert np.array_equal(g["trans"][~ex], o["trans"][~ex]), label  # exactly 1 (miss) or 0
+    err = np.abs(g["trans"][ex] - o["trans"][ex])
+    say(f"{label}: trans n={ex.sum()} max err={err.max(initial=0):.3e} "
+        f"range [{o['trans'][ex].min(initial=1):.4f}, {o['trans'][ex].max(initial=0):.4f}]")
+    assert err.max(initial=0) <= TRANS_TOL, label
+    assert ((g["trans"] >= 0.0) & (g["trans"] <= 1.0 + 1e-12)).all(), label
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("branch", [0, 1])
+def test_3d_transmission_weights_parity(axis, branch):
+    """Eq. (12) weights (entry, internal reflections at the outer surface and
+    caps, exit) of random 3-D rays, DP45 1e-8 FP64, against the oracle's."""
+    rays = W.random_rays(1024, seed=300 + 10 * axis + branch, z_range=(-1.0, 5.0))
+    c = W.cloak(axis, height=W.HEIGHT)
+    op = W.opts_dp45()
+    say(f"case 3d trans axis={axis} branch={branch}")
+    g = gpu_trace(c, op, branch, rays, with_trans=True)
+    o = oracle.trace(c, op, branch, rays)
+    check_trace(g, o, opl_tol=2e-6, label=f"3d trans a{axis} b{branch}")
+    check_trans(g, o, f"3d trans a{axis} b{branch}")
+    # the weights leave the trajectories alone (the weighted integrator is its
+    # own instantiation, so the compiler may round in another order)
+    g0 = gpu_trace(c, op, branch, rays)
+    assert np.array_equal(g0["status"], g["status"])
+    fin = np.isfinite(g0["out"])
+    assert np.array_equal(fin, np.isfinite(g["out"]))
+    assert np.abs(g0["out"][fin] - g["out"][fin]).max(initial=0) < 1e-9
+
+
+def test_transmission_weights_other_paths():
+    """Eq. (12) weights in the Hamiltonian form and RK4, and with the bounce
+    limit at 0 (reflections then end the ray): the in-plane bundle against the
+    infinite cloaks, the edge rays against the finite ones."""
+    edge = np.array([
+        [0.5, np.nan, 5.0, 5.0, 0.3, 5.0, 3.0],
+        [0.0, 0.0, 5.0, 5.0, 0.2, 0.3, 0.1],
+        [1.0, 1.0, 1.0, 1.0, 8.0, 1.0, 2.0],
+        [1.0, 1.0, 0.0, 0.0, 0.0, -1.0, -1.0],
+        [0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.02],
+        [0.0, 0.0, 0.0, 0.0, -1.0, 0.0, 0.0],
+    ])
+    for axis in (0, 1):
+        for op in (W.opts_rk4_ham(), W.opts_rk4(), W.opts_dp45(max_bounces=0)):
+            for branch in (0, 1):
+                for c, rays in ((W.cloak(axis), W.inplane_bundle(32, 4)),
+                                (W.cloak(axis, height=4.0), edge)):
+                    label = (f"trans paths axis={axis} scheme={op['scheme']} "
+                             f"bounces={op['max_bounces']} b{branch} n={rays.shape[1]}")
+                    say(f"case {label}")
+                    g = gpu_trace(c, op, branch, rays, with_trans=True)
+                    o = oracle.trace(c, op, branch, rays)
+                    resolved = ~(o["hres"] > RESOLVED_H)
+                    check_trace(g, o, mask=resolved, label=label)
+                    check_trans({k: v[..., resolved] for k, v in g.items()},
+                                {k: v[..., resolved] for k, v in o.items()}, label)
+
+
 def test_inplane_full_size_sampled():
     """The full in-plane workload (16384 impact parameters x 8 angles, radial
     cloak, extraordinary rays, RK4 h = 1e-3) on the GPU; 256 sampled rays
