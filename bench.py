@@ -546,6 +546,76 @@ def hamiltonian_workload(args):
             **res}
 
 
+def weights_workload(args):
+    """Eq. (12) weights: 2^20 random 3-D rays (uniform over azimuth, height
+    [-1, 5], in-plane angle and elevation within 60 deg, starting on r = 3)
+    against the finite radial and azimuthal cloaks, each traced in both
+    branches, DP45 at 1e-8, FP64: one step = four rt_trace_batch calls with
+    the weights; the same four calls without them are timed beside."""
+    import numpy as np
+    import torch
+    from paper_1209_6038_amd import rt
+    from paper_1209_6038_amd import workloads as W
+
+    n = 1 << 20
+    rays = torch.from_numpy(W.random_rays(n, seed=11, z_range=(-1.0, 5.0))).cuda()
+    opts = W.opts_dp45()
+    cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (W.RADIAL, W.AZIMUTHAL)]
+    cases = [(ax, br) for ax in (0, 1) for br in (0, 1)]
+    entered, flops, summary = 0, 0, {}
+    for ax, br in cases:
+        r = rt.trace_batch(cloaks[ax], opts, br, rays, with_trans=True)
+        torch.cuda.synchronize()
+        st = r["status"].cpu().numpy()
+        w = r["trans"].cpu().numpy()
+        entered += int((st != 1).sum())
+        flops += int(r["nsteps"].cpu().numpy().astype(np.int64).sum()) * attempt_flops(2 * ax + br, 1)
+        ex = st == 0
+        summary[f"{'radial' if ax == 0 else 'azimuthal'}_{'o' if br == 0 else 'e'}"] = {
+            "exited": int(ex.sum()), "mean_weight_exited": round(float(w[ex].mean()), 5),
+            "entering_intensity_delivered": round(float(w[ex].sum() / max(1, (st != 1).sum())), 5)}
+
+    def run(trans, steps):
+        for _ in range(steps):
+            for ax, br in cases:
+                rt.trace_batch(cloaks[ax], opts, br, rays, with_aux=False, with_trans=trans)
+
+    timing = {}
+    for trans in (False, True):
+        run(trans, args.warmup)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        rt.profile_enable(True)
+        rt.profile_read()
+        a.record()
+        run(trans, args.steps)
+        b.record()
+        torch.cuda.synchronize()
+        transit_ms, launches = rt.profile_read()
+        rt.profile_enable(False)
+        timing[trans] = (a.elapsed_time(b) / args.steps, transit_ms / max(1, launches))
+    ms, launch_ms = timing[True]
+    achieved = flops / len(cases) / (launch_ms * 1e-3) / 1e12
+    return {
+        "metric": "Mrays/s traced through cloak at <=1e-6 exit error, with Eq. (12) weights",
+        "unit": "Mrays/s", "value": round(entered / (ms * 1e-3) / 1e6, 3), "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3-D random rays with Eq. (12) weights: 2^20 rays from r=3 (z in [-1,5], "
+                               "elevation <= 60 deg), radial + azimuthal cloaks (height 4), ordinary + "
+                               "extraordinary, DP45 tol 1e-8, FP64",
+                   "entering_per_step": entered, "ms_per_step_without_weights": round(timing[False][0], 4),
+                   "weights_cost": round(ms / timing[False][0], 4), "per_branch": summary},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_transit (integrator, weighted)", "avg_launch_ms": round(launch_ms, 4),
+                     "avg_launch_ms_without_weights": round(timing[False][1], 4),
+                     "note": "integration flops only; the Fresnel solves at the events are not counted"},
+    }
+
+
 def orbit_workload(args):
     """The large-render workload timed plain: 36-frame orbit at 30 deg
     elevation, 4096 x 4096 px, 4 jittered samples per pixel, radial and
@@ -610,7 +680,8 @@ def main():
     ap.add_argument("--res", type=int, default=1024)
     ap.add_argument("--frames-per-launch", type=int, default=2,
                     help="orbit workload and surrogate render: 4096^2 x 4 spp frames per integrator launch (1-4)")
-    ap.add_argument("--workload", choices=("render3d", "batched", "orbit", "surrogate", "inplane", "hamiltonian"),
+    ap.add_argument("--workload", choices=("render3d", "batched", "orbit", "surrogate", "inplane", "hamiltonian",
+                                           "weights"),
                     default="render3d")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed")
     ap.add_argument("--refill", type=int, default=0)
@@ -657,6 +728,9 @@ def main():
         return
     if args.workload == "hamiltonian":
         print(json.dumps(finite_json(hamiltonian_workload(args))), flush=True)
+        return
+    if args.workload == "weights":
+        print(json.dumps(finite_json(weights_workload(args))), flush=True)
         return
     if args.workload == "surrogate":
         torch.cuda.set_device(0)

@@ -124,6 +124,35 @@ def test_transmission_weights_other_paths():
                                 {k: v[..., resolved] for k, v in o.items()}, label)
 
 
+def test_transmission_weights_full_size_sampled():
+    """The weighted 3-D workload at full size (2^20 random rays, both cloaks,
+    both branches, DP45 1e-8, FP64): 256 sampled rays per case re-traced by
+    the oracle, weights and exits compared."""
+    import torch
+    from paper_1209_6038_amd import rt
+    rays = W.random_rays(1 << 20, seed=11, z_range=(-1.0, 5.0))
+    t = torch.from_numpy(rays).cuda()
+    rng = np.random.default_rng(12)
+    for axis in (0, 1):
+        c = W.cloak(axis, height=W.HEIGHT)
+        cl = rt.Cloak(c)
+        for branch in (0, 1):
+            say(f"case weights full size axis={axis} branch={branch}")
+            r = rt.trace_batch(cl, W.opts_dp45(), branch, t, with_trans=True)
+            torch.cuda.synchronize()
+            g = {k: v.cpu().numpy() for k, v in r.items()}
+            assert ((g["trans"] >= 0.0) & (g["trans"] <= 1.0 + 1e-12)).all()
+            assert (g["trans"][g["status"] == 1] == 1.0).all()
+            assert (g["trans"][(g["status"] != 0) & (g["status"] != 1)] == 0.0).all()
+            idx = np.sort(rng.choice(rays.shape[1], 256, replace=False))
+            o = oracle.trace(c, W.opts_dp45(), branch, rays[:, idx])
+            gs = {k: v[..., idx] for k, v in g.items()}
+            label = f"weights full a{axis} b{branch}"
+            check_trace(gs, o, label=label)
+            check_trans(gs, o, label)
+        cl.close()
+
+
 def test_inplane_full_size_sampled():
     """The full in-plane workload (16384 impact parameters x 8 angles, radial
     cloak, extraordinary rays, RK4 h = 1e-3) on the GPU; 256 sampled rays
