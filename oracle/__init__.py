@@ -77,7 +77,7 @@ def lib():
         L.orc_render_samples.argtypes = [ctypes.POINTER(_Cloak), ctypes.POINTER(_Opts),
                                          ctypes.POINTER(_Room), ctypes.POINTER(_Camera),
                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
-                                         c_int64_p, c_uint8_p, c_double_p, c_int32_p]
+                                         c_int64_p, c_uint8_p, c_double_p, c_int32_p, c_double_p]
         L.orc_eps_cyl.argtypes = [ctypes.POINTER(_Cloak), ctypes.c_double, c_double_p]
         L.orc_metric.argtypes = [ctypes.POINTER(_Cloak), c_double_p, c_double_p]
         L.orc_metric_det_form.argtypes = [ctypes.POINTER(_Cloak), c_double_p, c_double_p]
@@ -169,20 +169,28 @@ def trace(cloak, opts, branch, rays6):
     return {"out": out, "opl": opl, "status": st, "hres": hr, "nsteps": ns, "trans": tr}
 
 
-def render_samples(cloak, opts, room, camera, cam_index, branch, ids):
-    """Codes (face*2+parity, 12 = black), records (7 x n) and status of samples."""
+def render_samples(cloak, opts, room, camera, cam_index, branch, ids, weights=False):
+    """Codes (face*2+parity, 12 = black), records (7 x n), status and image
+    weight (the share of the sample's unpolarized light this branch carries to
+    the room: 1/2 for a ray that stays in vacuum, the Eq. (12) trace weight
+    for one that crosses the crystal, 0 otherwise; with weights=True) of
+    samples."""
     ids = np.ascontiguousarray(ids, dtype=np.int64)
     n = ids.shape[0]
     code = np.empty(n, dtype=np.uint8)
     rec = np.empty((7, n))
     st = np.empty(n, dtype=np.int32)
+    wimg = np.empty(n) if weights else None
     c = _cloak(cloak)
     o, rm, cm = _opts(opts), _room(room), _camera(camera)
     lib().orc_render_samples(ctypes.byref(c) if c is not None else None, ctypes.byref(o),
                              ctypes.byref(rm), ctypes.byref(cm), int(cam_index), int(branch), n,
                              _ptr(ids, c_int64_p), _ptr(code, c_uint8_p), _ptr(rec),
-                             _ptr(st, c_int32_p))
-    return {"code": code, "rec": rec, "status": st}
+                             _ptr(st, c_int32_p), None if wimg is None else _ptr(wimg))
+    out = {"code": code, "rec": rec, "status": st}
+    if weights:
+        out["wimg"] = wimg
+    return out
 
 
 def render_pixels(cloak, opts, room, camera, cam_index, branch, pixels):
@@ -195,6 +203,22 @@ def render_pixels(cloak, opts, room, camera, cam_index, branch, pixels):
     table[:12] = np.asarray(room["rgb"], dtype=np.float32).reshape(12, 3)
     col = table[r["code"]].reshape(len(pixels), spp, 3).mean(axis=1)
     return col, r
+
+
+def render_unpolarized_pixels(cloak, opts, room, camera, cam_index, pixels):
+    """Unpolarized RGB (float64, n x 3) of the given pixels: per sample, the
+    sum over the ordinary and extraordinary branch of its image weight times
+    the colour it sees, averaged over the pixel's samples (Eq. (12), Fig. 1c)."""
+    pixels = np.asarray(pixels, dtype=np.int64)
+    spp = int(camera.get("spp", 1))
+    ids = (pixels[:, None] * spp + np.arange(spp)[None, :]).reshape(-1)
+    table = np.zeros((13, 3))
+    table[:12] = np.asarray(room["rgb"], dtype=np.float32).reshape(12, 3)
+    col = np.zeros((len(ids), 3))
+    for branch in (0, 1):
+        r = render_samples(cloak, opts, room, camera, cam_index, branch, ids, weights=True)
+        col += r["wimg"][:, None] * table[r["code"]]
+    return col.reshape(len(pixels), spp, 3).mean(axis=1)
 
 
 def eps_cyl(cloak, r):

@@ -1290,13 +1290,26 @@ int32_t orc_room_code(const orc_room *room, const double o[3], const double d[3]
 void orc_render_samples(const orc_cloak *c, const orc_opts *o, const orc_room *room,
                         const orc_camera *cam, int32_t cam_index, int32_t branch,
                         int64_t n, const int64_t *ids, uint8_t *code,
-                        double *rec, int32_t *status) {
+                        double *rec, int32_t *status, double *wimg) {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; i++) {
-        double org[3], d[3], p[3], dout[3], L = 0.0, hr;
+        double org[3], d[3], p[3], dout[3], L = 0.0, hr, w = 0.0;
         int64_t ns = 0;
         orc_camera_ray(cam, cam_index, ids[i], org, d);
-        int st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, NULL);
+        int st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, wimg ? &w : NULL);
+        if (wimg) {
+            /* share of the sample's unpolarized light that this branch carries
+               to the room (Eq. (12)): a ray that stays in vacuum (a miss, or
+               the metal end disk, which reflects every polarization) splits
+               evenly over the two branch images; a ray through the crystal
+               carries its trace weight; light reflected at the crystal's
+               surface is not imaged */
+            double wi = 0.0;
+            if (st == ORC_MISSED) wi = 0.5;
+            else if (st == ORC_EXITED) wi = w;
+            else if (st == ORC_REFLECTED && c && sqrt(p[0] * p[0] + p[1] * p[1]) <= c->a) wi = 0.5;
+            wimg[i] = wi;
+        }
         int cd = 12;
         if (st == ORC_EXITED || st == ORC_MISSED || st == ORC_REFLECTED) {
             double s;

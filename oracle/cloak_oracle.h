@@ -79,7 +79,7 @@ void orc_trace(const orc_cloak *c, const orc_opts *o, int32_t branch, int64_t n,
 void orc_render_samples(const orc_cloak *c, const orc_opts *o, const orc_room *room,
                         const orc_camera *cam, int32_t cam_index, int32_t branch,
                         int64_t n, const int64_t *ids, uint8_t *code,
-                        double *rec, int32_t *status);
+                        double *rec, int32_t *status, double *wimg);
 
 /* Eq. (12): intensity transmission of unpolarized light (the mean over two
    orthogonal incident polarizations) from vacuum into the crystal, T[0]

@@ -763,3 +763,44 @@ def test_trace_weights():
     # in-plane: the ordinary polarization (perpendicular to theta_hat) is
     # along z, i.e. s-polarized, and index-matched at both interfaces
     np.testing.assert_allclose(r["trans"][hit], 0.5, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# unpolarized images (Eq. (12), Fig. 1c): per sample, the two branch images
+# weighted by the share of the sample's light each carries to the room
+# --------------------------------------------------------------------------
+def test_unpolarized_image_of_the_empty_room_is_the_room():
+    """Without a cloak every sample stays in vacuum: its light splits evenly
+    over the two branches, which see the same room point."""
+    cam = W.orbit_camera(0.3, 20.0, 16, 16, spp=4, seed=3)
+    room = W.room()
+    pix = np.arange(16 * 16)
+    u = oracle.render_unpolarized_pixels(None, W.opts_dp45(), room, cam, 0, pix)
+    col, _ = oracle.render_pixels(None, W.opts_dp45(), room, cam, 0, 1, pix)
+    np.testing.assert_allclose(u, col, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_unpolarized_image_weights_match_the_trace(axis):
+    """The render's per-sample weights against rt_trace-style tracing of the
+    same camera rays (the oracle's trace path, whose weights the Fresnel pins
+    fix): a miss weighs 1/2 per branch, an exit its trace weight, and the two
+    branches of one ray carry at most all of its light."""
+    cam = W.orbit_camera(0.0, 15.0, 24, 24)
+    room = W.room()
+    c = W.cloak(axis, height=W.HEIGHT)
+    ids = np.arange(24 * 24)
+    empty = oracle.render_samples(None, W.opts_dp45(), room, cam, 0, E, ids)
+    rays = np.ascontiguousarray(empty["rec"][:6])  # the camera rays themselves
+    tot = np.zeros(len(ids))
+    for branch in (O, E):
+        r = oracle.render_samples(c, W.opts_dp45(), room, cam, 0, branch, ids, weights=True)
+        t = oracle.trace(c, W.opts_dp45(), branch, rays)
+        miss = r["status"] == 1
+        ex = r["status"] == 0
+        assert miss.sum() > 50 and ex.sum() > 50
+        np.testing.assert_array_equal(r["wimg"][miss], 0.5)
+        np.testing.assert_allclose(r["wimg"][ex], t["trans"][ex], rtol=0, atol=1e-12)
+        assert (r["wimg"][~(miss | ex)] <= 0.5).all()
+        tot += r["wimg"]
+    assert (tot <= 1.0 + 1e-12).all() and (tot[ex] < 1.0).all()
