@@ -137,13 +137,24 @@ typedef struct {
    flight, the mean over the pixel's samples that reach the room of their
    optical path from the eye (c0 = 1, so optical path = time; the ray ODE's
    time inside the cloak, App. A), NaN if none does. With the empty room's
-   image it gives the time-of-flight difference the cloak makes (Sect. 4). */
+   image it gives the time-of-flight difference the cloak makes (Sect. 4).
+   unpol: the unpolarized image (Eq. (12), Fig. 1c), one per (cloak,
+   camera) rather than per branch (n_cloaks x n_cams x h x w x 3 floats, or
+   n_cams x h x w x 3 without a cloak): per sample, the sum over the two
+   branches of the share of its unpolarized light the branch carries to the
+   room times the colour it sees there, averaged over the pixel's samples.
+   A sample that stays in vacuum (a miss, the metal end disk) gives each
+   branch 1/2; one that crosses the crystal gives its branch the weight
+   rt_trace_batch reports as trans; light reflected at the crystal surface
+   is not imaged. Needs pol_mask = 3 and RT_PREC_FP64, else RT_E_UNSUPPORTED
+   (and always in rt_render_surrogate). */
 typedef struct {
     double *rec;
     int32_t *status;
     uint8_t *code;
     int32_t *nsteps;
     float *tof;
+    float *unpol;
 } rt_render_aux;
 
 /* Build a cloak handle (host-side constants; no device memory).

@@ -752,12 +752,14 @@ __device__ __forceinline__ bool vacuum_entry(const CloakP& c, const double o[3],
 }
 
 // uniaxial principal values and optic axis at x (Eq. (14) / Eq. (15), Eq. (1))
-__device__ __forceinline__ void material_axis(const CloakP &c, const double x[3], double &eo, double &ee,
-                                              double cax[3]) {
+// `axis` is the branch kind's (kind >> 1), not c.axis: cloaks rendered together
+// share one CloakP for their common geometry
+__device__ __forceinline__ void material_axis(const CloakP &c, int axis, const double x[3], double &eo,
+                                              double &ee, double cax[3]) {
   const double w = rsq64(fma(x[0], x[0], x[1] * x[1]));
   const double q = fma(-c.a, w, 1.0);
   const double ks = c.kappa * q * q;
-  if (c.axis == 0) {  // radial: c = r_hat, eps_e = eps_r
+  if (axis == 0) {  // radial: c = r_hat, eps_e = eps_r
     eo = c.kappa; ee = ks;
     cax[0] = x[0] * w; cax[1] = x[1] * w; cax[2] = 0.0;
   } else {            // azimuthal: c = theta_hat, eps_e = eps_theta

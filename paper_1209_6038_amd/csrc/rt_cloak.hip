@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(256) k_tb_entry(CloakP c, OptsP o, Table T, in
           skey = sort_key(c, kind, x, d);
           if (trans) {
             double eo, ee, cax[3];
-            material_axis(c, x, eo, ee, cax);
+            material_axis(c, kind >> 1, x, eo, ee, cax);
             w_in = fresnel_in_dev(eo, ee, cax, nrm, d, kind & 1);
           }
         } else {
@@ -368,7 +368,7 @@ template <int KIND>
 __device__ __forceinline__ void fresnel_event(const CloakP &c, int rid, const double x[3], const double v[3],
                                               double &Tt, double &Rr) {
   double eo, ee, cax[3], nrm[3], k[3];
-  material_axis(c, x, eo, ee, cax);
+  material_axis(c, KIND >> 1, x, eo, ee, cax);
   boundary_normal(rid, x, nrm);
   double rh[2], th[2], w;
   local_frame(x, rh, th, w);
@@ -825,6 +825,8 @@ struct RenderP {
   unsigned char *code;
   int *nsteps;
   float *tof;            // aux per-pixel time of flight (may be NULL)
+  float *twt;            // chunk-local Eq. (12) image weight [segment][g1-g0]; NULL unless unpol
+  float *unpol;          // aux per-pixel unpolarized image, per (cloak, camera) (may be NULL)
 };
 
 // Surrogate render: the side entries of a chunk that go to the network
@@ -856,8 +858,9 @@ __device__ __forceinline__ void split_index(const RenderP &R, long long gidx, lo
 // [cloak][camera][polarization]
 __device__ __forceinline__ void rd_write(const RenderP &R, int q, long long gidx, int code,
                                          int st, const double p[3], const double d[3], double L,
-                                         int nsteps) {
+                                         int nsteps, float wt = 0.f) {
   R.codes[(long long)q * (R.g1 - R.g0) + (gidx - R.g0)] = (unsigned char)code;
+  if (R.twt) R.twt[(long long)q * (R.g1 - R.g0) + (gidx - R.g0)] = wt;
   if (R.topl) R.topl[(long long)q * (R.g1 - R.g0) + (gidx - R.g0)] = code < 12 ? (float)L : __builtin_nanf("");
   long long cam, loc;
   split_index(R, gidx, cam, loc);
@@ -946,14 +949,20 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
     int ci = q / R.npol, pi = q - ci * R.npol;
     int kind = (ci == 0 ? R.axis[0] : R.axis[1]) * 2 + (pi == 0 ? R.pol[0] : R.pol[1]);
     bool enter = false, cand = false;
-    double v[3] = {0, 0, 0};
+    double v[3] = {0, 0, 0}, w_in = 0.0;
     if (valid) {
       if (!hitc || disk) {
-        rd_write(R, q, gidx, vcode, vst, vp, vd, vL, 0);
+        rd_write(R, q, gidx, vcode, vst, vp, vd, vL, 0, 0.5f);  // vacuum light splits evenly
       } else if (refract_in(c, kind, surf, x, d, v)) {
         const int skey = sort_key(c, kind, x, d);
         if (SUR && surf == B_SIDE && NBUCKET - 1 - skey >= R.sur_min) cand = true;
         else enter = true;
+        if (!SUR && R.twt) {
+          double nrm[3], eo, ee, cax[3];
+          boundary_normal(surf, x, nrm);
+          material_axis(c, kind >> 1, x, eo, ee, cax);
+          w_in = fresnel_in_dev(eo, ee, cax, nrm, d, kind & 1);
+        }
       } else {
         // evanescent transmission into this branch: reflected at the entry
         double nrm[3], dd[3] = {d[0], d[1], d[2]}, sh;
@@ -965,6 +974,7 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
     }
     unsigned int sl = block_append(T.ctr + C_N(q), enter, sh);
     if (enter) put_slot(T, (int)(q * T.cap + sl), x, v, kind, gidx, s, o.h0, sort_key(c, kind, x, d));
+    if (!SUR && enter && R.twt) T.wt[q * T.cap + sl] = w_in;
     if constexpr (SUR) {
       const unsigned int ci2 = block_append(T.ctr + C_SUR, cand, sh);
       if (cand) put_candidate(Cd, ci2, x, d, kind, gidx, q, s);
@@ -1047,7 +1057,8 @@ __global__ void __launch_bounds__(256) k_rd_finish(RoomP rm, Table T, RenderP R)
 #pragma unroll
       for (int j = 0; j < 3; ++j) v[j] *= w;
     }
-    rd_write(R, q, T.key[s], code, st, x, v, L, T.nsteps[s]);
+    rd_write(R, q, T.key[s], code, st, x, v, L, T.nsteps[s],
+             (R.twt && st == RT_RAY_EXITED) ? (float)T.wt[s] : 0.f);
   }
 }
 
@@ -1104,6 +1115,26 @@ __global__ void __launch_bounds__(256) k_rd_resolve(RenderP R, const float *__re
   o[1] = g * inv;
   o[2] = b * inv;
   if (R.tof) R.tof[img * npix + pix] = tn ? (float)(tsum / tn) : __builtin_nanf("");
+  if (R.unpol && pi == 0) {
+    // both branches of this cloak (segments q, q + 1), each sample's colour
+    // times the share of its light the branch carries
+    float ur = 0.f, ug = 0.f, ub = 0.f;
+    for (int b = 0; b < 2; ++b) {
+      const unsigned char *cb = R.codes + (q + b) * chunk + lp * R.spp;
+      const float *wb = R.twt + (q + b) * chunk + lp * R.spp;
+      for (int k = 0; k < R.spp; ++k) {
+        const int cc = cb[k];
+        const float wk = wb[k];
+        ur = fmaf(wk, tab[3 * cc], ur);
+        ug = fmaf(wk, tab[3 * cc + 1], ug);
+        ub = fmaf(wk, tab[3 * cc + 2], ub);
+      }
+    }
+    float *u = R.unpol + (((long long)ci * R.n_cams + cam) * npix + pix) * 3;
+    u[0] = ur * inv;
+    u[1] = ug * inv;
+    u[2] = ub * inv;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1123,6 +1154,7 @@ struct Workspace {
   Table T{};
   unsigned char *codes = nullptr;
   float *topl = nullptr;  // per-sample optical path of a chunk (time-of-flight images)
+  float *twt = nullptr;   // per-sample Eq. (12) image weight of a chunk (unpolarized images)
   CamP *cams = nullptr;
   float *table = nullptr;
 };
@@ -1193,6 +1225,7 @@ int ws_reserve(Workspace &ws, long long cap, long long codes_len, int ncam) {
   size_t o_c = take(sizeof(unsigned int) * C_COUNT);
   size_t o_codes = take((size_t)codes_len);
   size_t o_topl = take(sizeof(float) * (size_t)codes_len);
+  size_t o_twt = take(sizeof(float) * (size_t)codes_len);
   size_t o_cams = take(sizeof(CamP) * ncam);
   size_t o_tab = take(sizeof(float) * 64);
   void *p = nullptr;
@@ -1217,6 +1250,7 @@ int ws_reserve(Workspace &ws, long long cap, long long codes_len, int ncam) {
   ws.cap = cap;
   ws.codes = (unsigned char *)(b + o_codes);
   ws.topl = (float *)(b + o_topl);
+  ws.twt = (float *)(b + o_twt);
   ws.codes_len = codes_len;
   ws.cams = (CamP *)(b + o_cams);
   ws.cams_cap = ncam;
@@ -1480,7 +1514,8 @@ int prepare_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts
     auto it = g_tuned.find(J.key);
     if (it != g_tuned.end()) { J.block = it->second.first; J.refill = it->second.second; }
   }
-  J.grid = transit_grid(J.o, J.block);
+  const bool unpol = aux && aux->unpol;
+  J.grid = transit_grid(J.o, J.block, unpol);
   RenderP &R = J.R;
   R.ns_img = ns_img; R.n_cams = n_cams; R.ncl = ncl; R.npol = npol; R.spp = spp;
   R.axis[0] = n_cloaks > 0 ? cloaks[0]->d.axis : 0;
@@ -1496,6 +1531,12 @@ int prepare_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts
   R.nsteps = aux ? aux->nsteps : nullptr;
   R.tof = aux ? aux->tof : nullptr;
   R.topl = nullptr;
+  R.unpol = unpol ? aux->unpol : nullptr;
+  R.twt = nullptr;
+  if (unpol && npol != 2)
+    return fail(RT_E_UNSUPPORTED, "the unpolarized image needs both branches (pol_mask = 3)");
+  if (unpol && opts->precision != RT_PREC_FP64)
+    return fail(RT_E_UNSUPPORTED, "the Eq. (12) weights are computed in FP64 only");
   return RT_OK;
 }
 
@@ -1519,6 +1560,7 @@ void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStre
   RenderP R = J.R;
   R.codes = ws.codes;
   R.topl = R.tof ? ws.topl : nullptr;
+  R.twt = R.unpol ? ws.twt : nullptr;
   for (long long g0 = 0; g0 < J.total; g0 += J.chunk) {
     R.g0 = g0;
     R.g1 = std::min(J.total, g0 + J.chunk);
@@ -1526,7 +1568,7 @@ void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStre
     hipLaunchKernelGGL(k_rd_gen<false>, dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
                        ws.cams, T, R, CandP{});
     if (J.n_cloaks) {
-      run_transit(J.c, J.o, T, J.block, J.refill, J.grid, s, profile);
+      run_transit(J.c, J.o, T, J.block, J.refill, J.grid, s, profile, R.unpol != nullptr);
       hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, J.rm, T, R);
     }
     long long nres = (R.g1 - R.g0) / R.spp * R.ncl * R.npol;
@@ -1587,6 +1629,7 @@ int cws_reserve(CandWs &w, long long cap) {
 // accepted.
 int render_surrogate(rt_model model, const rt_cloak_desc &desc, const RenderJob &J, const Workspace &ws,
                      const CandWs &cw, int min_difficulty, float *rgb, hipStream_t s, long long counts[2]) {
+  if (J.R.unpol) return fail(RT_E_UNSUPPORTED, "the surrogate render makes no unpolarized image");
   const Table &T = ws.T;
   RenderP R = J.R;
   R.sur_min = min_difficulty;

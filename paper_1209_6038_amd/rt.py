@@ -81,7 +81,7 @@ class GateOpts(ctypes.Structure):
 
 class RenderAux(ctypes.Structure):
     _fields_ = [("rec", ctypes.c_void_p), ("status", ctypes.c_void_p), ("code", ctypes.c_void_p),
-                ("nsteps", ctypes.c_void_p), ("tof", ctypes.c_void_p)]
+                ("nsteps", ctypes.c_void_p), ("tof", ctypes.c_void_p), ("unpol", ctypes.c_void_p)]
 
 
 def _render_aux(lead: tuple, w: int, h: int, spp: int, dev):
@@ -261,10 +261,12 @@ def trace_batch(cloak: Cloak, opts: dict, pol: int, in6, with_aux: bool = True,
 
 
 def render_multi(cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: int,
-                 aux: bool = False, out=None):
+                 aux: bool = False, out=None, unpolarized: bool = False):
     """rt_render_multi: the same views for several cloaks (sharing geometry) in
     one pass. Returns rgb float32 (n_cloaks, n_cams, npol, h, w, 3) and, with
-    aux=True, dict(rec, status, code, nsteps) in the same image order."""
+    aux=True, dict(rec, status, code, nsteps) in the same image order; with
+    unpolarized=True (pol_mask 3, FP64) the dict also holds "unpol", the
+    Eq. (12) unpolarized images, float32 (n_cloaks, n_cams, h, w, 3)."""
     import torch
     n = len(cams)
     ncl = max(len(cloaks), 1)
@@ -281,10 +283,15 @@ def render_multi(cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: i
     aux_t = None
     if aux:
         aux_t, aux_s = _render_aux((ncl, n, npol,), w, h, spp, dev)
+    if unpolarized:
+        if aux_s is None:
+            aux_t, aux_s = {}, RenderAux()
+        aux_t["unpol"] = torch.empty((ncl, n, h, w, 3), dtype=torch.float32, device=dev)
+        aux_s.unpol = aux_t["unpol"].data_ptr()
     _check(lib().rt_render_multi(harr, len(cloaks), ctypes.byref(o), ctypes.byref(rm), carr, n,
                                  int(pol_mask), _ptr(rgb),
                                  ctypes.byref(aux_s) if aux_s is not None else None, _stream()))
-    return (rgb, aux_t) if aux else rgb
+    return (rgb, aux_t) if (aux or unpolarized) else rgb
 
 
 def render_surrogate(model, cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: int,

@@ -269,3 +269,46 @@ def test_two_large_frames_in_one_launch_equal_one_launch_each():
     assert torch.equal(one, each)
     del one, each
     rt.release_workspace()
+
+
+@pytest.mark.parametrize("spp", [1, 4])
+def test_unpolarized_image_parity(spp):
+    """Eq. (12) unpolarized images (rt_render_aux.unpol) of both cloaks in one
+    rt_render_multi call against the oracle's composition of the two branch
+    images with its per-sample weights; the branch images stay as without."""
+    import torch
+    from paper_1209_6038_amd import rt
+    n = 32
+    cams = [W.orbit_camera(az, el, n, n, spp=spp, seed=5) for az, el in ((0.0, 0.0), (0.7, 30.0))]
+    room = W.room()
+    ds = [W.cloak(0, height=W.HEIGHT), W.cloak(1, height=W.HEIGHT)]
+    cls = [rt.Cloak(d) for d in ds]
+    say(f"case unpolarized spp={spp}")
+    rgb, aux = rt.render_multi(cls, W.opts_dp45(), room, cams, 3, unpolarized=True)
+    rgb0 = rt.render_multi(cls, W.opts_dp45(), room, cams, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb, rgb0)
+    u = aux["unpol"].cpu().numpy()
+    for ci, d in enumerate(ds):
+        for k, cam in enumerate(cams):
+            o = oracle.render_unpolarized_pixels(d, W.opts_dp45(), room, cam, k, np.arange(n * n))
+            err = np.abs(u[ci, k].reshape(-1, 3) - o).max()
+            say(f"  cloak {ci} cam {k}: max |unpol - oracle| = {err:.3e}, mean {u[ci, k].mean():.4f}")
+            assert err <= 1e-5
+    # without a cloak the unpolarized image is the room
+    e_rgb, e_aux = rt.render_multi([], W.opts_dp45(), room, cams, 3, unpolarized=True)
+    torch.cuda.synchronize()
+    assert torch.allclose(e_aux["unpol"][0], e_rgb[0, :, 1], rtol=0, atol=1e-6)
+    for c in cls:
+        c.close()
+
+
+def test_unpolarized_image_needs_both_branches_and_fp64():
+    from paper_1209_6038_amd import rt
+    cam = W.orbit_camera(0.0, 0.0, 8, 8)
+    cl = rt.Cloak(W.cloak(0, height=W.HEIGHT))
+    for pol_mask, op in ((1, W.opts_dp45()), (3, W.opts_dp45(precision=1, fp64_band=0.05))):
+        with pytest.raises(rt.RtError) as e:
+            rt.render_multi([cl], op, W.room(), [cam], pol_mask, unpolarized=True)
+        assert e.value.code == rt.RT_E_UNSUPPORTED
+    cl.close()
