@@ -616,6 +616,60 @@ def weights_workload(args):
     }
 
 
+def unpolarized_workload(args):
+    """The headline render (both cloaks, 4 views of 1024^2, both branches,
+    DP45 1e-8, FP64) with the Eq. (12) unpolarized images, timed beside the
+    same render without them; one step = one rt_render_multi call."""
+    import torch
+    from paper_1209_6038_amd import rt
+    from paper_1209_6038_amd import workloads as W
+
+    cams = W.render_views(res=args.res)
+    opts = W.render_opts(block=args.block, refill_period=args.refill)
+    cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
+    room = W.room()
+    _, aux = rt.render_multi(cloaks, opts, room, cams, 3, aux=True, unpolarized=True)
+    torch.cuda.synchronize()
+    dev = aux["status"].device
+    entered = int(torch.isin(aux["status"], torch.tensor([0, 2, 3, 4, 5], device=dev, dtype=torch.int32)).sum())
+    mean_unpol = float(aux["unpol"].mean())
+    del aux
+    timing = {}
+    for unpol in (False, True):
+        for _ in range(args.warmup):
+            rt.render_multi(cloaks, opts, room, cams, 3, unpolarized=unpol)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        rt.profile_enable(True)
+        rt.profile_read()
+        a.record()
+        for _ in range(args.steps):
+            rt.render_multi(cloaks, opts, room, cams, 3, unpolarized=unpol)
+        b.record()
+        torch.cuda.synchronize()
+        transit_ms, launches = rt.profile_read()
+        rt.profile_enable(False)
+        timing[unpol] = (a.elapsed_time(b) / args.steps, transit_ms / max(1, launches))
+    ms, launch_ms = timing[True]
+    return {
+        "metric": "Mrays/s traced through cloak at <=1e-6 exit error, with Eq. (12) unpolarized images",
+        "unit": "Mrays/s", "value": round(entered / (ms * 1e-3) / 1e6, 3), "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3-D render with unpolarized images: radial + azimuthal cloaks (height 4), "
+                               "4 elevations x 1024^2 px, ordinary + extraordinary, DP45 tol 1e-8, FP64, "
+                               "eager calls",
+                   "entering_per_step": entered, "ms_per_step_without_images": round(timing[False][0], 4),
+                   "images_cost": round(ms / timing[False][0], 4), "mean_unpolarized_value": round(mean_unpol, 5)},
+        "roofline": {"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": None, "traffic": None, "kernel": "k_transit (integrator, weighted)",
+                     "avg_launch_ms": round(launch_ms, 4),
+                     "avg_launch_ms_without_images": round(timing[False][1], 4)},
+    }
+
+
 def orbit_workload(args):
     """The large-render workload timed plain: 36-frame orbit at 30 deg
     elevation, 4096 x 4096 px, 4 jittered samples per pixel, radial and
@@ -681,7 +735,7 @@ def main():
     ap.add_argument("--frames-per-launch", type=int, default=2,
                     help="orbit workload and surrogate render: 4096^2 x 4 spp frames per integrator launch (1-4)")
     ap.add_argument("--workload", choices=("render3d", "batched", "orbit", "surrogate", "inplane", "hamiltonian",
-                                           "weights"),
+                                           "weights", "unpolarized"),
                     default="render3d")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed")
     ap.add_argument("--refill", type=int, default=0)
@@ -731,6 +785,9 @@ def main():
         return
     if args.workload == "weights":
         print(json.dumps(finite_json(weights_workload(args))), flush=True)
+        return
+    if args.workload == "unpolarized":
+        print(json.dumps(finite_json(unpolarized_workload(args))), flush=True)
         return
     if args.workload == "surrogate":
         torch.cuda.set_device(0)
