@@ -363,22 +363,31 @@ struct Lane {
 // Newton update of the crossing length (rid >= 0: locating the crossing of
 // boundary rid). Returns the final status when the ray stops, else -1.
 // Eq. (12) at an interface event of branch KIND: the wave k = M v meets
-// boundary rid at x; transmitted fraction and same-type reflected fraction
+// boundary rid at x; transmitted fraction (.x) and same-type reflected
+// fraction (.y). Kept out of line, with scalar arguments: the events are rare
+// and their complex arithmetic would otherwise set the register allocation
+// of the whole integration loop.
 template <int KIND>
-__device__ __forceinline__ void fresnel_event(const CloakP &c, int rid, const double x[3], const double v[3],
-                                              double &Tt, double &Rr) {
+__device__ __noinline__ double2 fresnel_event(double kappa, double a, int rid, double x0, double x1,
+                                              double x2, double v0, double v1, double v2) {
+  CloakP c{};
+  c.kappa = kappa;
+  c.a = a;
+  const double x[3] = {x0, x1, x2};
   double eo, ee, cax[3], nrm[3], k[3];
   material_axis(c, KIND >> 1, x, eo, ee, cax);
   boundary_normal(rid, x, nrm);
   double rh[2], th[2], w;
   local_frame(x, rh, th, w);
   double mr, mt, mz;
-  metric_diag(KIND, c.kappa, c.a, w, mr, mt, mz);
-  const double vr = v[0] * rh[0] + v[1] * rh[1], vt = v[0] * th[0] + v[1] * th[1];
+  metric_diag(KIND, kappa, a, w, mr, mt, mz);
+  const double vr = v0 * rh[0] + v1 * rh[1], vt = v0 * th[0] + v1 * th[1];
   k[0] = mr * vr * rh[0] + mt * vt * th[0];
   k[1] = mr * vr * rh[1] + mt * vt * th[1];
-  k[2] = mz * v[2];
+  k[2] = mz * v2;
+  double Tt, Rr;
   fresnel_out_dev(eo, ee, cax, nrm, k, KIND & 1, Tt, Rr);
+  return make_double2(Tt, Rr);
 }
 
 template <int KIND, bool MIXED, bool HAM, bool FRES>
@@ -522,7 +531,11 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
   } else {
     double d[3];
     double Tt = 0.0, Rr = 0.0;
-    if constexpr (FRES) fresnel_event<KIND>(c, rid, L.x, L.v, Tt, Rr);
+    if constexpr (FRES) {
+      const double2 tr = fresnel_event<KIND>(c.kappa, c.a, rid, L.x[0], L.x[1], L.x[2], L.v[0], L.v[1], L.v[2]);
+      Tt = tr.x;
+      Rr = tr.y;
+    }
     if (refract_out(c, KIND, rid, L.x, L.v, d, hr)) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) L.v[i] = d[i];
