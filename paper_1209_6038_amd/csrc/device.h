@@ -793,6 +793,43 @@ __device__ __forceinline__ void local_frame(const double x[3], double rh[2], dou
   th[0] = -rh[1]; th[1] = rh[0];
 }
 
+// Eq. (12) at an exit, evaluated after the integration (one ray per lane):
+// the crystal wave that left through boundary rid at x is rebuilt from the
+// outgoing vacuum direction d. Its tangential k equals d's (Eq. (11)); its
+// normal component is the outward root of the branch's dispersion
+// k^T M^-1 k = 1, with M diagonal in (r, theta, z) and the normal one of
+// those axes.
+__device__ __forceinline__ double exit_transmission(const CloakP &c, int kind, int rid, const double x[3],
+                                                    const double d[3]) {
+  double rh[2], th[2], w;
+  local_frame(x, rh, th, w);
+  double mr, mt, mz;
+  metric_diag(kind, c.kappa, c.a, w, mr, mt, mz);
+  const double dr = d[0] * rh[0] + d[1] * rh[1], kt = d[0] * th[0] + d[1] * th[1];
+  double kr, kz;
+  if (rid == B_SIDE) {
+    kz = d[2];
+    kr = sqrt(fmax(mr * (1.0 - kt * kt / mt - kz * kz / mz), 0.0));
+  } else {
+    kr = dr;
+    const double q = sqrt(fmax(mz * (1.0 - kr * kr / mr - kt * kt / mt), 0.0));
+    kz = rid == B_TOP ? q : -q;
+  }
+  const double k[3] = {kr * rh[0] + kt * th[0], kr * rh[1] + kt * th[1], kz};
+  double eo, ee, cax[3], nrm[3], T, R;
+  material_axis(c, kind >> 1, x, eo, ee, cax);
+  boundary_normal(rid, x, nrm);
+  fresnel_out_dev(eo, ee, cax, nrm, k, kind & 1, T, R);
+  return T;
+}
+
+// outer boundary an exit point lies on (events are located to ~1e-13)
+__device__ __forceinline__ int exit_boundary(const CloakP &c, const double x[3]) {
+  if (fabs(x[2] - c.z1) <= 1e-9) return B_TOP;
+  if (fabs(x[2] - c.z0) <= 1e-9) return B_BOTTOM;
+  return B_SIDE;
+}
+
 // Entry refraction (Sect. 3) at a point of boundary `surf` with outward
 // normal along r_hat (side) or +/- z (caps). kin: unit vacuum direction.
 // Returns false if the transmitted wave is evanescent. v: ray velocity.

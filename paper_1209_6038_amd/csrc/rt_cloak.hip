@@ -530,20 +530,16 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
     reflect_inside(B_INNER, L.x, L.v);
   } else {
     double d[3];
-    double Tt = 0.0, Rr = 0.0;
-    if constexpr (FRES) {
-      const double2 tr = fresnel_event<KIND>(c.kappa, c.a, rid, L.x[0], L.x[1], L.x[2], L.v[0], L.v[1], L.v[2]);
-      Tt = tr.x;
-      Rr = tr.y;
-    }
     if (refract_out(c, KIND, rid, L.x, L.v, d, hr)) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) L.v[i] = d[i];
-      if constexpr (FRES) L.wt *= Tt;
-      return RT_RAY_EXITED;
+      return RT_RAY_EXITED;  // the exit transmission is applied by the finish kernel
     }
     if (L.bounces >= o.max_bounces) return RT_RAY_TIR;
-    if constexpr (FRES) L.wt *= Rr;
+    if constexpr (FRES) {
+      const double2 tr = fresnel_event<KIND>(c.kappa, c.a, rid, L.x[0], L.x[1], L.x[2], L.v[0], L.v[1], L.v[2]);
+      L.wt *= tr.y;
+    }
     reflect_inside(rid, L.x, L.v);
   }
   // continue from the boundary point after the reflection
@@ -701,6 +697,8 @@ __global__ void __launch_bounds__(256) k_tb_finish(CloakP c, OptsP o, Table T, l
     int kind = T.kind[s];
     double L = T.opl0[s] + T.t[s];
     double hr = T.hres[s];
+    double wt = 0.0;
+    if (trans && st == RT_RAY_EXITED) wt = T.wt[s] * exit_transmission(c, kind, exit_boundary(c, x), x, v);
     if (st == RT_RAY_EXITED) {
       double sl = leave_radius(x, v, o.r_out);
 #pragma unroll
@@ -718,7 +716,7 @@ __global__ void __launch_bounds__(256) k_tb_finish(CloakP c, OptsP o, Table T, l
     status[i] = st;
     if (hres) hres[i] = hr;
     if (nsteps) nsteps[i] = T.nsteps[s];
-    if (trans) trans[i] = st == RT_RAY_EXITED ? T.wt[s] : 0.0;
+    if (trans) trans[i] = wt;
   }
 }
 
@@ -1049,7 +1047,7 @@ __global__ void __launch_bounds__(256) k_rd_sur_apply(CloakP c, OptsP o, RoomP r
   (void)block_append(T.ctr + C_ACC, valid && !rej, sh);
 }
 
-__global__ void __launch_bounds__(256) k_rd_finish(RoomP rm, Table T, RenderP R) {
+__global__ void __launch_bounds__(256) k_rd_finish(CloakP c, RoomP rm, Table T, RenderP R) {
   const SegMap m = seg_map(T);
   const unsigned int n = m.off[NSEG];
   unsigned int stride = gridDim.x * blockDim.x;
@@ -1070,8 +1068,9 @@ __global__ void __launch_bounds__(256) k_rd_finish(RoomP rm, Table T, RenderP R)
 #pragma unroll
       for (int j = 0; j < 3; ++j) v[j] *= w;
     }
-    rd_write(R, q, T.key[s], code, st, x, v, L, T.nsteps[s],
-             (R.twt && st == RT_RAY_EXITED) ? (float)T.wt[s] : 0.f);
+    const double wt = (R.twt && st == RT_RAY_EXITED)
+                          ? T.wt[s] * exit_transmission(c, T.kind[s], exit_boundary(c, x), x, v) : 0.0;
+    rd_write(R, q, T.key[s], code, st, x, v, L, T.nsteps[s], (float)wt);
   }
 }
 
@@ -1582,7 +1581,7 @@ void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStre
                        ws.cams, T, R, CandP{});
     if (J.n_cloaks) {
       run_transit(J.c, J.o, T, J.block, J.refill, J.grid, s, profile, R.unpol != nullptr);
-      hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, J.rm, T, R);
+      hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, J.c, J.rm, T, R);
     }
     long long nres = (R.g1 - R.g0) / R.spp * R.ncl * R.npol;
     hipLaunchKernelGGL(k_rd_resolve, dim3(grid_for(nres, 256)), dim3(256), 0, s, R, ws.table, rgb,
@@ -1666,7 +1665,7 @@ int render_surrogate(rt_model model, const rt_cloak_desc &desc, const RenderJob 
                          cw.P, nc);
     }
     run_transit(J.c, J.o, T, J.block, J.refill, J.grid, s, true);
-    hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, J.rm, T, R);
+    hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, J.c, J.rm, T, R);
     long long nres = (R.g1 - R.g0) / R.spp * R.ncl * R.npol;
     hipLaunchKernelGGL(k_rd_resolve, dim3(grid_for(nres, 256)), dim3(256), 0, s, R, ws.table, rgb, J.npix);
     if (counts) {
