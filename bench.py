@@ -415,6 +415,58 @@ def surrogate_leg(steps: int, n_train: int, log, fpl: int = 2):
     return rec
 
 
+# MFMA flops of one training sample: the forward products of the three
+# 256 x 256 layers, and in backward the data gradient through them and the
+# weight gradient of each (the 6 -> 256 and 256 -> 5 layers run in FP32 on
+# the vector units and are not counted)
+TRAIN_MFMA_FLOPS = 3 * MLP_MFMA_FLOPS
+
+
+def train_workload(args):
+    """Surrogate training alone: AdamW steps of 65,536 rows (BF16 MFMA forward
+    and backward, FP32 master weights) over the 10 M labelled entries of the
+    surrogate leg, timed with HIP events on the launch stream, inputs
+    resident."""
+    import torch
+    from paper_1209_6038_amd import rt
+    from paper_1209_6038_amd import surrogate as S
+
+    cl = S.make_cloaks(None)
+    x_tr = S.features(args.surrogate_train, 1001)
+    _, _, t_tr, w_tr = S.label(cl, x_tr, S.exact_opts())
+    m = rt.Surrogate(seed=0)
+    m.fit_scaling(x_tr, t_tr, w_tr)
+    batch = 65536
+    nb = x_tr.shape[1] // batch
+    steps = args.surrogate_steps
+    loss = torch.zeros(1, dtype=torch.float32, device=x_tr.device)
+
+    def run(k0, k1):
+        for k in range(k0, k1):
+            j = (k % nb) * batch
+            m.train_step(x_tr[:, j:j + batch], t_tr[:, j:j + batch], w_tr[j:j + batch], lr=1e-3,
+                         huber=0.01, loss=loss)
+
+    run(0, 20)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    run(20, 20 + steps)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    tflops = TRAIN_MFMA_FLOPS * batch / (ms * 1e-3) / 1e12
+    return {"metric": "surrogate training samples/s", "unit": "M samples/s",
+            "value": round(batch / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4), "steps": steps,
+            "dtype": "bf16 x bf16 -> f32 (layers 2-4), f32 (layers 1, 5)", "data": "synthetic",
+            "config": {"workload": "surrogate training: AdamW steps of 65,536 rows of the 10 M labelled "
+                                   "entries, MLP 6-256x4-5", "final_loss": float(loss.item())},
+            "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": PEAK_BF16_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tflops / PEAK_BF16_TFLOPS, 4),
+                         "note": "MFMA flops of forward and backward per sample x batch / step time"}}
+
+
 def inplane_workload(args):
     """The 2-D workload: radial cloak, extraordinary branch, 16,384 parallel
     in-plane rays (impact parameters on the midpoint grid of [-3, 3]) at each
@@ -735,7 +787,7 @@ def main():
     ap.add_argument("--frames-per-launch", type=int, default=2,
                     help="orbit workload and surrogate render: 4096^2 x 4 spp frames per integrator launch (1-4)")
     ap.add_argument("--workload", choices=("render3d", "batched", "orbit", "surrogate", "inplane", "hamiltonian",
-                                           "weights", "unpolarized"),
+                                           "weights", "unpolarized", "train"),
                     default="render3d")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed")
     ap.add_argument("--refill", type=int, default=0)
@@ -788,6 +840,9 @@ def main():
         return
     if args.workload == "unpolarized":
         print(json.dumps(finite_json(unpolarized_workload(args))), flush=True)
+        return
+    if args.workload == "train":
+        print(json.dumps(finite_json(train_workload(args))), flush=True)
         return
     if args.workload == "surrogate":
         torch.cuda.set_device(0)

@@ -52,7 +52,8 @@ enum {
     RT_RAY_MISSED = 1,    /* never touched the cloak */
     RT_RAY_ABSORBED = 2,  /* reached the inner radius where no mirror reflects it */
     RT_RAY_MAXSTEPS = 3,  /* step budget exhausted inside the cloak */
-    RT_RAY_DIVERGED = 4,  /* non-finite state or step-size collapse */
+    RT_RAY_DIVERGED = 4,  /* non-finite state, step-size collapse, or |v^T M v - 1| > 1e-3
+                             at an outer interface (no longer a ray of the medium) */
     RT_RAY_TIR = 5,       /* more internal reflections than max_bounces */
     RT_RAY_INVALID = 6,   /* non-finite input, zero direction or origin inside the cloak */
     RT_RAY_REFLECTED = 7  /* reflected at the entry (evanescent transmission, metal end disk) */
@@ -183,8 +184,10 @@ int rt_free_cloak(rt_cloak cloak);
              surface or an end cap, times the transmission into vacuum at exit.
              Plane-wave transmittances at a locally flat interface, from
              continuity of tangential E and H (Sect. 3); the cross-polarized
-             reflected wave is dropped. 1 for a miss, 0 for a ray that did not
-             leave. Needs RT_PREC_FP64.
+             reflected wave is dropped. 1 for a miss or a reflection off the
+             metal end disk (the metal reflects every polarization), 0 for a
+             ray that did not leave or that the crystal surface reflected.
+             Needs RT_PREC_FP64.
    n = 0 is a no-op. Errors: RT_E_INVALID (NULL handle/options/required
    pointer, n < 0, r_out < r2, bad options), RT_E_UNSUPPORTED (trans with
    RT_PREC_MIXED), RT_E_NOMEM (workspace), RT_E_DEVICE (launch failure). */
@@ -355,10 +358,26 @@ int rt_surrogate_encode(const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int
    get_params) or NULL; loss: 1 float (device) or NULL. */
 int rt_surrogate_grad(rt_model model, int64_t n, int64_t ld, const float *x6, const float *t5, const float *w,
                       float huber, float *grads, float *loss, void *stream);
-/* One AdamW step on a batch (bias-corrected moments, decoupled weight
-   decay on the weights only). */
+/* One AdamW step on a batch: the gradient of rt_surrogate_grad, then, per
+   parameter p with gradient g, FP32 first and second moments
+   m <- beta1 m + (1 - beta1) g, v <- beta2 v + (1 - beta2) g^2, decoupled
+   weight decay p <- p - lr weight_decay p on the weights (not the biases),
+   and p <- p - lr (m / c1) / (sqrt(v / c2) + eps) with the bias corrections
+   c1 = 1 - beta1^t, c2 = 1 - beta2^t of step t; the BF16 copies of W2..W4
+   follow. */
 int rt_surrogate_train(rt_model model, int64_t n, int64_t ld, const float *x6, const float *t5, const float *w,
                        const rt_train_opts *opts, float *loss, void *stream);
+/* One AdamW step (as in rt_surrogate_train) with a gradient the caller
+   supplies: grads, NPARAM floats (device, the layout of get_params).
+   Errors: RT_E_INVALID for NULL grads or bad options. */
+int rt_surrogate_step(rt_model model, const float *grads, const rt_train_opts *opts, void *stream);
+/* Optimizer state in host memory: the AdamW first and second moments
+   (NPARAM floats each, the layout of get_params; either pointer may be NULL
+   in get_state) and the number of steps taken, which sets the bias
+   corrections 1 - beta^step of the next step. set_state needs finite m and
+   finite v >= 0, step >= 0. Synchronous. */
+int rt_surrogate_get_state(rt_model model, float *m_host, float *v_host, int64_t *step);
+int rt_surrogate_set_state(rt_model model, const float *m_host, const float *v_host, int64_t step);
 /* Network prediction of the targets, de-standardized: t5 SoA 5 x ld. */
 int rt_surrogate_forward(rt_model model, int64_t n, int64_t ld, const float *x6, float *t5, void *stream);
 /* Build the trust map: predicts the calibration rays x6, measures each

@@ -70,43 +70,83 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
             build()
-        L = ctypes.CDLL(_LIB_PATH)
-        L.orc_trace.argtypes = [ctypes.POINTER(_Cloak), ctypes.POINTER(_Opts), ctypes.c_int32,
-                                ctypes.c_int64, c_double_p, c_double_p, c_double_p, c_int32_p,
-                                c_double_p, c_int64_p, c_double_p]
-        L.orc_render_samples.argtypes = [ctypes.POINTER(_Cloak), ctypes.POINTER(_Opts),
-                                         ctypes.POINTER(_Room), ctypes.POINTER(_Camera),
-                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
-                                         c_int64_p, c_uint8_p, c_double_p, c_int32_p, c_double_p]
-        L.orc_eps_cyl.argtypes = [ctypes.POINTER(_Cloak), ctypes.c_double, c_double_p]
-        L.orc_metric.argtypes = [ctypes.POINTER(_Cloak), c_double_p, c_double_p]
-        L.orc_metric_det_form.argtypes = [ctypes.POINTER(_Cloak), c_double_p, c_double_p]
-        L.orc_rhs.argtypes = [ctypes.POINTER(_Cloak), ctypes.c_int32, c_double_p, c_double_p]
-        L.orc_rhs_eq8_isotropic.argtypes = [ctypes.POINTER(_Cloak), c_double_p, c_double_p]
-        L.orc_refract_in.argtypes = [ctypes.c_double, ctypes.c_double, c_double_p, c_double_p,
-                                     c_double_p, ctypes.c_int32, c_double_p, c_double_p]
-        L.orc_refract_in.restype = ctypes.c_int32
-        L.orc_refract_out.argtypes = [ctypes.c_double, ctypes.c_double, c_double_p, c_double_p,
-                                      c_double_p, ctypes.c_int32, c_double_p]
-        L.orc_refract_out.restype = ctypes.c_int32
-        L.orc_fresnel_in.argtypes = [ctypes.c_double, ctypes.c_double, c_double_p, c_double_p,
-                                     c_double_p, c_double_p, c_double_p]
-        L.orc_fresnel_in.restype = ctypes.c_int32
-        L.orc_fresnel_out.argtypes = [ctypes.c_double, ctypes.c_double, c_double_p, c_double_p,
-                                      c_double_p, ctypes.c_int32, c_double_p, c_double_p]
-        L.orc_fresnel_out.restype = ctypes.c_int32
-        L.orc_camera_ray.argtypes = [ctypes.POINTER(_Camera), ctypes.c_int32, ctypes.c_int64,
-                                     c_double_p, c_double_p]
-        L.orc_room_code.argtypes = [ctypes.POINTER(_Room), c_double_p, c_double_p, c_double_p]
-        L.orc_room_code.restype = ctypes.c_int32
-        L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
-        L.orc_splitmix64.restype = ctypes.c_uint64
-        L.orc_test_oscillator.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double,
-                                          ctypes.c_double, c_double_p, c_int64_p]
-        L.orc_test_oscillator.restype = ctypes.c_double
-        L.orc_num_threads.restype = ctypes.c_int32
-        _lib = L
+        _lib = _load(_LIB_PATH)
     return _lib
+
+
+class use_library:
+    """Context manager: route every call of this module to another build of
+    the oracle (a copy of cloak_oracle.c compiled elsewhere, e.g. with a
+    deliberate mistake planted by a test), then restore the default."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _lib
+        _lib = _load(self.path)
+        return _lib
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def build_variant(src_text: str, out_dir: str) -> str:
+    """Compile oracle source text (same flags as build()) into out_dir."""
+    src = os.path.join(out_dir, "cloak_oracle_variant.c")
+    with open(src, "w") as f:
+        f.write(src_text)
+    out = os.path.join(out_dir, "libcloak_oracle_variant.so")
+    subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-shared", "-fPIC", "-I" + _HERE,
+                    "-o", out, src, "-lm"], check=True)
+    return out
+
+
+def source_text() -> str:
+    with open(_SRC) as f:
+        return f.read()
+
+
+def _load(path):
+    L = ctypes.CDLL(path)
+    L.orc_trace.argtypes = [ctypes.POINTER(_Cloak), ctypes.POINTER(_Opts), ctypes.c_int32,
+                            ctypes.c_int64, c_double_p, c_double_p, c_double_p, c_int32_p,
+                            c_double_p, c_int64_p, c_double_p]
+    L.orc_render_samples.argtypes = [ctypes.POINTER(_Cloak), ctypes.POINTER(_Opts),
+                                     ctypes.POINTER(_Room), ctypes.POINTER(_Camera),
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                     c_int64_p, c_uint8_p, c_double_p, c_int32_p, c_double_p]
+    L.orc_eps_cyl.argtypes = [ctypes.POINTER(_Cloak), ctypes.c_double, c_double_p]
+    L.orc_metric.argtypes = [ctypes.POINTER(_Cloak), c_double_p, c_double_p]
+    L.orc_metric_det_form.argtypes = [ctypes.POINTER(_Cloak), c_double_p, c_double_p]
+    L.orc_rhs.argtypes = [ctypes.POINTER(_Cloak), ctypes.c_int32, c_double_p, c_double_p]
+    L.orc_rhs_eq8_isotropic.argtypes = [ctypes.POINTER(_Cloak), c_double_p, c_double_p]
+    L.orc_refract_in.argtypes = [ctypes.c_double, ctypes.c_double, c_double_p, c_double_p,
+                                 c_double_p, ctypes.c_int32, c_double_p, c_double_p]
+    L.orc_refract_in.restype = ctypes.c_int32
+    L.orc_refract_out.argtypes = [ctypes.c_double, ctypes.c_double, c_double_p, c_double_p,
+                                  c_double_p, ctypes.c_int32, c_double_p]
+    L.orc_refract_out.restype = ctypes.c_int32
+    L.orc_fresnel_in.argtypes = [ctypes.c_double, ctypes.c_double, c_double_p, c_double_p,
+                                 c_double_p, c_double_p, c_double_p]
+    L.orc_fresnel_in.restype = ctypes.c_int32
+    L.orc_fresnel_out.argtypes = [ctypes.c_double, ctypes.c_double, c_double_p, c_double_p,
+                                  c_double_p, ctypes.c_int32, c_double_p, c_double_p]
+    L.orc_fresnel_out.restype = ctypes.c_int32
+    L.orc_camera_ray.argtypes = [ctypes.POINTER(_Camera), ctypes.c_int32, ctypes.c_int64,
+                                 c_double_p, c_double_p]
+    L.orc_room_code.argtypes = [ctypes.POINTER(_Room), c_double_p, c_double_p, c_double_p]
+    L.orc_room_code.restype = ctypes.c_int32
+    L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    L.orc_splitmix64.restype = ctypes.c_uint64
+    L.orc_test_oscillator.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, c_double_p, c_int64_p]
+    L.orc_test_oscillator.restype = ctypes.c_double
+    L.orc_num_threads.restype = ctypes.c_int32
+    return L
 
 
 def _ptr(a, t=c_double_p):
@@ -153,7 +193,8 @@ def trace(cloak, opts, branch, rays6):
     status, hres (|H-1| at the last interface), nsteps (step attempts) and
     trans (the Eq. (12) weight of the reported ray: unpolarized entry
     transmission x same-mode internal reflectances x exit transmission; 1 for
-    a miss, 0 when the ray does not exit).
+    a miss or a reflection off the metal end disk, 0 when the ray does not
+    exit).
     """
     rays6 = np.ascontiguousarray(rays6, dtype=np.float64)
     n = rays6.shape[1]

@@ -1049,8 +1049,8 @@ static int trace_vacuum(const orc_cloak *c, int branch, const orc_opts *o,
     memcpy(dout, d_in, 3 * sizeof(double));
     *opl = 0.0;
     *hres = NAN;
-    /* Eq. (12) weight of the reported ray: 1 for a miss, the product of the
-       entry transmission, the same-mode reflectances of internal reflections
+    /* Eq. (12) weight of the reported ray: 1 for a miss or a reflection off
+       the metal end disk, the product of the entry transmission, the same-mode reflectances of internal reflections
        and the exit transmission for an exit, 0 otherwise */
     if (wt) *wt = 0.0;
     if (!c) {
@@ -1075,7 +1075,9 @@ static int trace_vacuum(const orc_cloak *c, int branch, const orc_opts *o,
         /* end disk of the inner metal cylinder */
         memcpy(p, x, sizeof(x));
         if (!c->inner_mirror) return ORC_ABSORBED;
+        /* the perfect metal reflects every polarization: all of the light */
         reflect(dout, n);
+        if (wt) *wt = 1.0;
         return ORC_REFLECTED;
     }
     double eo, ee, ch[3], k[3], v[3];
@@ -1111,6 +1113,11 @@ static int trace_vacuum(const orc_cloak *c, int branch, const orc_opts *o,
             break;
         }
         outward_normal(ev, y, nn);
+        /* a ray whose Hamiltonian v^T M v has drifted from 1 by more than
+           1e-3 at an outer interface is no longer a ray of the medium: its
+           direction there is not a solution of the dispersion relation, and
+           the refraction of Sect. 3 would act on an arbitrary vector */
+        if (!(fabs(hamiltonian(c, branch, y) - 1.0) <= 1e-3)) { status = ORC_DIVERGED; break; }
         double eo2, ee2, ch2[3], dd[3];
         material_at(c, y, &eo2, &ee2, ch2);
         double Tout = 0.0, Rref[2] = { 0.0, 0.0 };

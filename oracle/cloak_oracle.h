@@ -65,7 +65,8 @@ typedef struct {
    (NaN when the ray never entered), step attempts, and the Eq. (12) weight
    of the reported ray (unpolarized entry transmission of the branch times
    the same-mode reflectance of each internal reflection times the exit
-   transmission; 1 for a miss, 0 when the ray does not exit). Any output
+   transmission; 1 for a miss or a reflection off the metal end disk, 0 when
+   the ray does not exit). Any output
    pointer but out6 may be NULL. OpenMP over rays. */
 void orc_trace(const orc_cloak *c, const orc_opts *o, int32_t branch, int64_t n,
                const double *in6, double *out6, double *opl, int32_t *status,

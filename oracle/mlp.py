@@ -2,7 +2,8 @@
 
 TEST INFRASTRUCTURE: the GPU surrogate kernels are checked against this.
 The surrogate is not part of the paper; this module is pinned by finite
-differences (backward against forward) and by torch.nn on the CPU (forward).
+differences (backward against forward), by torch.nn on the CPU (forward)
+and by torch.optim.AdamW on the CPU (the optimizer step).
 
 Precision model of the GPU path, reproduced here when bf16=True:
   layers 1 (6 -> 256) and 5 (256 -> 5) in FP32 on the vector units: no
@@ -109,3 +110,62 @@ def loss_and_grads(params, x, t, w=None, bf16=False, huber=0.0):
             da = q(g) @ q(W).T
             g = da * silu_grad(zs[i - 1])
     return loss, grads
+
+
+def is_bias_index(nparam_layout=SIZES):
+    """Boolean mask over the flat parameter vector (W1, b1, ..., W5, b5, each
+    weight (fan_in, fan_out) row-major): True for bias entries."""
+    mask = []
+    for i in range(5):
+        mask.append(np.zeros(nparam_layout[i] * nparam_layout[i + 1], dtype=bool))
+        mask.append(np.ones(nparam_layout[i + 1], dtype=bool))
+    return np.concatenate(mask)
+
+
+def adamw_step(p, g, m, v, step, lr, beta1, beta2, eps, weight_decay, decay_mask):
+    """One AdamW step (Loshchilov & Hutter, decoupled weight decay) in FP64
+    on flat arrays; `step` is the index t >= 1 of this step. Returns
+    (p', m', v'):
+      m' = beta1 m + (1 - beta1) g,   v' = beta2 v + (1 - beta2) g^2,
+      p  <- p - lr wd p  where decay_mask (the weights, not the biases),
+      p' = p - lr (m' / (1 - beta1^t)) / (sqrt(v' / (1 - beta2^t)) + eps)."""
+    p, g, m, v = (np.asarray(a, dtype=np.float64) for a in (p, g, m, v))
+    m1 = beta1 * m + (1.0 - beta1) * g
+    v1 = beta2 * v + (1.0 - beta2) * g * g
+    pd = np.where(decay_mask, p - lr * weight_decay * p, p)
+    c1 = 1.0 - beta1 ** step
+    c2 = 1.0 - beta2 ** step
+    p1 = pd - lr * (m1 / c1) / (np.sqrt(v1 / c2) + eps)
+    return p1, m1, v1
+
+
+def grad_term_magnitudes(params, x, t, bf16=False, huber=0.0):
+    """For each gradient tensor of loss_and_grads (same order), the sum S of
+    the absolute values of the terms it adds up (over rows, and for weights
+    of the products a_rk g_rj) and the largest single term Mx. Rounding
+    error bounds of the gradient are combinations of the two: accumulation
+    in a working precision u errs by at most ~ (terms) u S, and one operand
+    rounded to the other side of a BF16 rounding boundary moves a sum by at
+    most 2^-8 Mx."""
+    n = x.shape[0]
+    y, (zs, acts) = forward(params, x, bf16)
+    d = y - t
+    big = (huber > 0) & (np.abs(d) > huber)
+    drho = np.where(big, 2.0 * huber * np.sign(d), 2.0 * d)
+    r = to_bf16 if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    S, Mx = [None] * 10, [None] * 10
+    g = drho / n
+    for i in range(4, -1, -1):
+        W = params[2 * i]
+        q = r if i in BF16_LAYERS else (lambda a: a)
+        A, G = np.abs(q(acts[i])), np.abs(q(g))
+        S[2 * i] = A.T @ G
+        mx = np.zeros((A.shape[1], G.shape[1]))
+        for row in range(n):
+            np.maximum(mx, np.outer(A[row], G[row]), out=mx)
+        Mx[2 * i] = mx
+        S[2 * i + 1] = np.abs(g).sum(axis=0)
+        Mx[2 * i + 1] = np.abs(g).max(axis=0)
+        if i > 0:
+            g = (q(g) @ q(W).T) * silu_grad(zs[i - 1])
+    return S, Mx

@@ -823,13 +823,6 @@ __device__ __forceinline__ double exit_transmission(const CloakP &c, int kind, i
   return T;
 }
 
-// outer boundary an exit point lies on (events are located to ~1e-13)
-__device__ __forceinline__ int exit_boundary(const CloakP &c, const double x[3]) {
-  if (fabs(x[2] - c.z1) <= 1e-9) return B_TOP;
-  if (fabs(x[2] - c.z0) <= 1e-9) return B_BOTTOM;
-  return B_SIDE;
-}
-
 // Entry refraction (Sect. 3) at a point of boundary `surf` with outward
 // normal along r_hat (side) or +/- z (caps). kin: unit vacuum direction.
 // Returns false if the transmitted wave is evanescent. v: ray velocity.

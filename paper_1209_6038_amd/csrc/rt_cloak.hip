@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(256) k_tb_entry(CloakP c, OptsP o, Table T, in
                                                   int *__restrict__ status, double *__restrict__ hres,
                                                   int *__restrict__ nsteps, double *__restrict__ trans) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  bool enter = false;
+  bool enter = false, disk = false;
   double x[3], v[3], s = 0.0, w_in = 0.0;
   int skey = 0;
   if (i < n) {
@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(256) k_tb_entry(CloakP c, OptsP o, Table T, in
         if (surf != B_SIDE && r2 <= c.a2) {
           p[0] = x[0]; p[1] = x[1]; p[2] = x[2];
           L = s;
-          if (c.mirror) { reflect3(d, nrm); st = RT_RAY_REFLECTED; }
+          if (c.mirror) { reflect3(d, nrm); st = RT_RAY_REFLECTED; disk = true; }
           else st = RT_RAY_ABSORBED;
         } else if (refract_in(c, kind, surf, x, d, v)) {
           enter = true;
@@ -281,7 +281,9 @@ __global__ void __launch_bounds__(256) k_tb_entry(CloakP c, OptsP o, Table T, in
       status[i] = st;
       if (hres) hres[i] = __builtin_nan("");
       if (nsteps) nsteps[i] = 0;
-      if (trans) trans[i] = st == RT_RAY_MISSED ? 1.0 : 0.0;
+      // a miss keeps all of its light, and so does a reflection off the
+      // perfect metal end disk
+      if (trans) trans[i] = (st == RT_RAY_MISSED || disk) ? 1.0 : 0.0;
     }
   }
   __shared__ unsigned int sh[16];
@@ -530,9 +532,17 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
     reflect_inside(B_INNER, L.x, L.v);
   } else {
     double d[3];
-    if (refract_out(c, KIND, rid, L.x, L.v, d, hr)) {
+    const bool leaves = refract_out(c, KIND, rid, L.x, L.v, d, hr);
+    // |v^T M v - 1| > 1e-3 at an outer interface: the state no longer
+    // satisfies the dispersion relation, so it is not a ray of the medium
+    if (!(hr <= 1e-3)) {
+      if constexpr (HAM) ham_convert<KIND>(c.a, c.kappa, L.x, L.v, true);  // the stop path converts back
+      return RT_RAY_DIVERGED;
+    }
+    if (leaves) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) L.v[i] = d[i];
+      L.rid = rid;  // the exit boundary, kept with the finished ray
       return RT_RAY_EXITED;  // the exit transmission is applied by the finish kernel
     }
     if (L.bounces >= o.max_bounces) return RT_RAY_TIR;
@@ -630,7 +640,8 @@ __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, con
           store_state(T, slot, L.x, L.v);
           T.t[slot] = L.t;
           T.nsteps[slot] = L.ns;
-          T.bounces[slot] = L.bounces;
+          // bits 8..: the boundary an exited ray left through
+          T.bounces[slot] = L.bounces | (stop == RT_RAY_EXITED ? L.rid << 8 : 0);
           T.status[slot] = stop;
           T.hres[slot] = hr;
           if constexpr (FRES) T.wt[slot] = L.wt;
@@ -698,7 +709,7 @@ __global__ void __launch_bounds__(256) k_tb_finish(CloakP c, OptsP o, Table T, l
     double L = T.opl0[s] + T.t[s];
     double hr = T.hres[s];
     double wt = 0.0;
-    if (trans && st == RT_RAY_EXITED) wt = T.wt[s] * exit_transmission(c, kind, exit_boundary(c, x), x, v);
+    if (trans && st == RT_RAY_EXITED) wt = T.wt[s] * exit_transmission(c, kind, T.bounces[s] >> 8, x, v);
     if (st == RT_RAY_EXITED) {
       double sl = leave_radius(x, v, o.r_out);
 #pragma unroll
@@ -1069,7 +1080,7 @@ __global__ void __launch_bounds__(256) k_rd_finish(CloakP c, RoomP rm, Table T, 
       for (int j = 0; j < 3; ++j) v[j] *= w;
     }
     const double wt = (R.twt && st == RT_RAY_EXITED)
-                          ? T.wt[s] * exit_transmission(c, T.kind[s], exit_boundary(c, x), x, v) : 0.0;
+                          ? T.wt[s] * exit_transmission(c, T.kind[s], T.bounces[s] >> 8, x, v) : 0.0;
     rd_write(R, q, T.key[s], code, st, x, v, L, T.nsteps[s], (float)wt);
   }
 }

@@ -1563,22 +1563,71 @@ int grad_impl(rt_model mo, int64_t n, int64_t ld, const float *x6, const float *
   return launch_err("gradient launch");
 }
 
-int rt_surrogate_train(rt_model mo, int64_t n, int64_t ld, const float *x6, const float *t5, const float *w,
-                       const rt_train_opts *opts, float *loss, void *stream) {
+int check_train_opts(const rt_train_opts *opts) {
   if (!opts) return fail(RT_E_INVALID, "opts is NULL");
   if (!(opts->lr >= 0.0f) || !(opts->beta1 >= 0.0f && opts->beta1 < 1.0f) ||
       !(opts->beta2 >= 0.0f && opts->beta2 < 1.0f) || !(opts->eps > 0.0f) || !(opts->weight_decay >= 0.0f) ||
       !(opts->huber >= 0.0f))
     return fail(RT_E_INVALID, "need lr >= 0, 0 <= beta1, beta2 < 1, eps > 0, weight_decay >= 0, huber >= 0");
-  int e = grad_impl(mo, n, ld, x6, t5, w, opts->huber, nullptr, loss, stream);
-  if (e) return e;
-  hipStream_t s = (hipStream_t)stream;
+  return RT_OK;
+}
+
+// one AdamW step with the gradient G (device, NPARAM floats); advances the
+// step count that the bias corrections use
+int adamw_step(rt_model mo, const float *G, const rt_train_opts *opts, hipStream_t s) {
   mo->step += 1;
-  const float c1 = 1.0f - (float)std::pow((double)opts->beta1, (double)mo->step);
-  const float c2 = 1.0f - (float)std::pow((double)opts->beta2, (double)mo->step);
-  hipLaunchKernelGGL(k_adamw, dim3(gblocks(NPARAM, 256)), dim3(256), 0, s, mo->P, mo->G, mo->m, mo->v, mo->Pb,
+  // bias corrections 1 - beta^t formed in FP64 and rounded once: 1 - beta2^t
+  // cancels for early steps (0.039 at beta2 = 0.995, t = 8), and rounding
+  // beta2^t to FP32 first would cost it 2^-24 / 0.039 relative
+  const float c1 = (float)(1.0 - std::pow((double)opts->beta1, (double)mo->step));
+  const float c2 = (float)(1.0 - std::pow((double)opts->beta2, (double)mo->step));
+  hipLaunchKernelGGL(k_adamw, dim3(gblocks(NPARAM, 256)), dim3(256), 0, s, mo->P, G, mo->m, mo->v, mo->Pb,
                      opts->lr, opts->weight_decay, opts->beta1, opts->beta2, c1, c2, opts->eps);
   return launch_err("optimizer launch");
+}
+
+int rt_surrogate_train(rt_model mo, int64_t n, int64_t ld, const float *x6, const float *t5, const float *w,
+                       const rt_train_opts *opts, float *loss, void *stream) {
+  int e = check_train_opts(opts);
+  if (e) return e;
+  e = grad_impl(mo, n, ld, x6, t5, w, opts->huber, nullptr, loss, stream);
+  if (e) return e;
+  return adamw_step(mo, mo->G, opts, (hipStream_t)stream);
+}
+
+int rt_surrogate_step(rt_model mo, const float *grads, const rt_train_opts *opts, void *stream) {
+  int e = check_model(mo);
+  if (!e) e = check_train_opts(opts);
+  if (e) return e;
+  if (!grads) return fail(RT_E_INVALID, "grads is NULL");
+  return adamw_step(mo, grads, opts, (hipStream_t)stream);
+}
+
+int rt_surrogate_get_state(rt_model mo, float *m_host, float *v_host, int64_t *step) {
+  int e = check_model(mo);
+  if (e) return e;
+  if (hipDeviceSynchronize() != hipSuccess) return fail(RT_E_DEVICE, "synchronize failed");
+  if ((m_host && hipMemcpy(m_host, mo->m, sizeof(float) * NPARAM, hipMemcpyDeviceToHost) != hipSuccess) ||
+      (v_host && hipMemcpy(v_host, mo->v, sizeof(float) * NPARAM, hipMemcpyDeviceToHost) != hipSuccess))
+    return fail(RT_E_DEVICE, "copy failed");
+  if (step) *step = mo->step;
+  return RT_OK;
+}
+
+int rt_surrogate_set_state(rt_model mo, const float *m_host, const float *v_host, int64_t step) {
+  int e = check_model(mo);
+  if (e) return e;
+  if (!m_host || !v_host) return fail(RT_E_INVALID, "m and v are required");
+  if (step < 0) return fail(RT_E_INVALID, "step must be >= 0");
+  for (long long i = 0; i < NPARAM; ++i)
+    if (!std::isfinite(m_host[i]) || !(v_host[i] >= 0.0f) || !std::isfinite(v_host[i]))
+      return fail(RT_E_INVALID, "moments must be finite and v >= 0 (entry %lld)", i);
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(mo->m, m_host, sizeof(float) * NPARAM, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(mo->v, v_host, sizeof(float) * NPARAM, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(RT_E_DEVICE, "copy failed");
+  mo->step = step;
+  return RT_OK;
 }
 
 int rt_surrogate_forward(rt_model mo, int64_t n, int64_t ld, const float *x6, float *t5, void *stream) {

@@ -147,6 +147,9 @@ def lib():
         L.rt_surrogate_grad.argtypes = [vp, i64, i64, vp, vp, vp, ctypes.c_float, vp, vp, vp]
         L.rt_surrogate_train.argtypes = [vp, i64, i64, vp, vp, vp, ctypes.POINTER(TrainOpts), vp, vp]
         L.rt_surrogate_forward.argtypes = [vp, i64, i64, vp, vp, vp]
+        L.rt_surrogate_step.argtypes = [vp, vp, ctypes.POINTER(TrainOpts), vp]
+        L.rt_surrogate_get_state.argtypes = [vp, vp, vp, ctypes.POINTER(i64)]
+        L.rt_surrogate_set_state.argtypes = [vp, vp, vp, i64]
         L.rt_surrogate_calibrate.argtypes = [vp, ctypes.POINTER(vp), i32, i64, i64, vp, vp, vp, vp,
                                              ctypes.POINTER(GateOpts), ctypes.POINTER(ctypes.c_double),
                                              vp]
@@ -553,6 +556,27 @@ class Surrogate:
         o = TrainOpts(lr, beta1, beta2, eps, weight_decay, huber)
         _check(lib().rt_surrogate_train(self.handle, x6.shape[1], ld, _ptr(x6), _ptr(t5), _ptr(w),
                                         ctypes.byref(o), _ptr(loss), _stream()))
+
+    def step(self, grads, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+        """One AdamW step with a caller-supplied gradient (NPARAM float32 device tensor)."""
+        import torch
+        assert grads.dtype == torch.float32 and grads.is_contiguous() and grads.numel() == self.NPARAM
+        o = TrainOpts(lr, beta1, beta2, eps, weight_decay, 0.0)
+        _check(lib().rt_surrogate_step(self.handle, _ptr(grads), ctypes.byref(o), _stream()))
+
+    def get_state(self):
+        """(m, v, step): AdamW moments (float32 host arrays) and the step count."""
+        m = np.empty(self.NPARAM, dtype=np.float32)
+        v = np.empty(self.NPARAM, dtype=np.float32)
+        k = ctypes.c_int64()
+        _check(lib().rt_surrogate_get_state(self.handle, m.ctypes.data, v.ctypes.data, ctypes.byref(k)))
+        return m, v, k.value
+
+    def set_state(self, m, v, step: int):
+        m = np.ascontiguousarray(m, dtype=np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        assert m.size == self.NPARAM and v.size == self.NPARAM
+        _check(lib().rt_surrogate_set_state(self.handle, m.ctypes.data, v.ctypes.data, int(step)))
 
     def forward(self, x6):
         import torch

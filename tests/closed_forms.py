@@ -256,3 +256,276 @@ def aimed_rays(n, seed, r_start=3.0, b=2.0, min_tangential=0.25, elev=True, min_
             continue
         out.append(np.concatenate([o, dd]))
     return np.array(out).T.copy()
+
+
+# --------------------------------------------------------------------------
+# finite cloak (end caps z = z0, z1): the two branches whose paths are
+# straight lines, in physical space (radial cloak, ordinary ray) or in the
+# virtual space (rho, theta, sqrt(kappa) z) (azimuthal cloak, extraordinary
+# ray). The caps are interfaces of Sect. 3 with normal +-z; an evanescent
+# transmitted wave means same-mode specular reflection inside (entry: the
+# ray is reflected into vacuum), and after max_bounces internal reflections
+# (caps, side or inner mirror) the ray stops.
+# --------------------------------------------------------------------------
+S_EXITED, S_MISSED, S_ABSORBED, S_TIR, S_REFLECTED = 0, 1, 2, 5, 7
+SIDE, TOP, BOTTOM = "side", "top", "bottom"
+
+
+def body_entry(o, d, b, z0, z1):
+    """First point where o + s d (s > 0) enters r <= b, z0 <= z <= z1:
+    (s, surface) or None. Written out case by case: the side (smaller root of
+    the quadratic, if its height lies between the caps) and each cap plane
+    (if the ray comes from its outside and meets it within r <= b)."""
+    best = None
+    A = d[0] ** 2 + d[1] ** 2
+    B = o[0] * d[0] + o[1] * d[1]
+    C = o[0] ** 2 + o[1] ** 2 - b * b
+    if A > 0.0 and C > 0.0 and B * B - A * C >= 0.0:
+        s = (-B - math.sqrt(B * B - A * C)) / A
+        if s > 0.0 and z0 <= o[2] + s * d[2] <= z1:
+            best = (s, SIDE)
+    for plane, surf, sign in ((z1, TOP, 1.0), (z0, BOTTOM, -1.0)):
+        if sign * d[2] < 0.0 and sign * (o[2] - plane) > 0.0:
+            s = (plane - o[2]) / d[2]
+            q = o + s * d
+            if q[0] ** 2 + q[1] ** 2 <= b * b and (best is None or s < best[0]):
+                best = (s, surf)
+    return best
+
+
+def _outward(surf, x):
+    if surf == TOP:
+        return np.array([0.0, 0.0, 1.0])
+    if surf == BOTTOM:
+        return np.array([0.0, 0.0, -1.0])
+    r = math.hypot(x[0], x[1])
+    return np.array([x[0] / r, x[1] / r, 0.0])
+
+
+def _leave_cylinder(x, d, R):
+    """Vacuum leg from x along d to the outgoing crossing of r = R."""
+    A = d[0] ** 2 + d[1] ** 2
+    if A <= 0.0:
+        return x, 0.0
+    B = x[0] * d[0] + x[1] * d[1]
+    C = x[0] ** 2 + x[1] ** 2 - R * R
+    disc = B * B - A * C
+    if disc < 0.0:
+        return x, 0.0
+    s = max((-B + math.sqrt(disc)) / A, 0.0)
+    return x + s * d, s
+
+
+def finite_radial_o(o, d, a=1.0, b=2.0, z0=0.0, z1=4.0, max_bounces=4, r_out=3.0, events=None):
+    """Radial cloak, ordinary ray, cloak of finite height (Sect. 4: n_o =
+    sqrt(kappa) constant, straight rays; metal cylinder r < a with its end
+    disks). Snell's law at every interface with n = sqrt(kappa): the wave
+    vector's tangential part is continuous and |k| = n inside, 1 outside; a
+    tangential part longer than the index of the far side reflects totally.
+    Returns (status, point on r = r_out or the last point, unit direction,
+    optical path, bounces); `events` (a list) receives (kind, surface) of
+    every interface the ray meets."""
+    ev = events if events is not None else []
+    n = math.sqrt(kappa(a, b))
+    d = np.asarray(d, float) / np.linalg.norm(d)
+    o = np.asarray(o, float)
+    hit = body_entry(o, d, b, z0, z1)
+    if hit is None:
+        p, s = _leave_cylinder(o, d, r_out)
+        return S_MISSED, p, d, s, 0
+    s_in, surf = hit
+    ev.append(("enter", surf))
+    x = o + s_in * d
+    if surf != SIDE:
+        x[2] = z1 if surf == TOP else z0
+    nrm = _outward(surf, x)
+    if surf != SIDE and x[0] ** 2 + x[1] ** 2 <= a * a:  # the metal end disk
+        dr = d - 2.0 * (d @ nrm) * nrm
+        p, s = _leave_cylinder(x, dr, r_out)
+        return S_REFLECTED, p, dr, s_in + s, 0
+    kt = d - (d @ nrm) * nrm
+    k = kt - math.sqrt(n * n - kt @ kt) * nrm      # inward normal component
+    v = k / (n * n)                                # |v| = 1/n: t is the optical path
+    t, bounces = 0.0, 0
+    while True:
+        # earliest of: inner mirror r = a (entering it), side r = b, caps
+        cands = []
+        A = v[0] ** 2 + v[1] ** 2
+        B = x[0] * v[0] + x[1] * v[1]
+        if A > 0.0:
+            Ca = x[0] ** 2 + x[1] ** 2 - a * a
+            disc = B * B - A * Ca
+            if disc > 0.0:
+                tm = (-B - math.sqrt(disc)) / A
+                if tm > 1e-12:
+                    cands.append((tm, "inner"))
+            Cb = x[0] ** 2 + x[1] ** 2 - b * b
+            tb = (-B + math.sqrt(B * B - A * Cb)) / A
+            if tb > 1e-12:
+                cands.append((tb, SIDE))
+        if v[2] > 0.0:
+            cands.append(((z1 - x[2]) / v[2], TOP))
+        elif v[2] < 0.0:
+            cands.append(((z0 - x[2]) / v[2], BOTTOM))
+        tc, surf = min(cands, key=lambda c: c[0])
+        x = x + tc * v
+        t += tc
+        if surf == "inner":
+            ev.append(("mirror", surf))
+            if bounces >= max_bounces:
+                return S_ABSORBED, x, v / np.linalg.norm(v), s_in + t, bounces
+            m = np.array([x[0], x[1], 0.0]) / math.hypot(x[0], x[1])
+            v = v - 2.0 * (v @ m) * m
+            bounces += 1
+            continue
+        nrm = _outward(surf, x)
+        k = n * n * v
+        kt = k - (k @ nrm) * nrm
+        ev.append(("exit" if kt @ kt <= 1.0 else "tir", surf))
+        if kt @ kt <= 1.0:
+            dout = kt + math.sqrt(1.0 - kt @ kt) * nrm
+            p, s = _leave_cylinder(x, dout, r_out)
+            return S_EXITED, p, dout, s_in + t + s, bounces
+        if bounces >= max_bounces:
+            return S_TIR, x, v / np.linalg.norm(v), s_in + t, bounces
+        v = v - 2.0 * (v @ nrm) * nrm
+        bounces += 1
+
+
+def finite_azimuthal_e(o, d, a=1.0, b=2.0, z0=0.0, z1=4.0, max_bounces=4, r_out=3.0, events=None):
+    """Azimuthal cloak, extraordinary ray, cloak of finite height. With
+    M = diag(kappa, kappa s, kappa) in (r, theta, z) (Eq. (15), Eq. (7)) the
+    line element is that of flat space in X = rho cos(theta),
+    Y = rho sin(theta), Z = sqrt(kappa) z, rho = sqrt(kappa) (r - a): the ray
+    is a straight line there at unit speed, its parameter the optical path.
+    The wave vector k = M v, v the physical velocity, meets each interface
+    as in Sect. 3: its tangential part is continuous, the normal part solves
+    k^T M^-1 k = 1 inside (evanescent: same-mode reflection, i.e. the
+    virtual velocity's normal component flips) or |k| = 1 outside.
+    Returns (status, point, unit direction, optical path, bounces); `events`
+    as for finite_radial_o."""
+    ev = events if events is not None else []
+    kap = kappa(a, b)
+    sk = math.sqrt(kap)
+    d = np.asarray(d, float) / np.linalg.norm(d)
+    o = np.asarray(o, float)
+    hit = body_entry(o, d, b, z0, z1)
+    if hit is None:
+        p, s = _leave_cylinder(o, d, r_out)
+        return S_MISSED, p, d, s, 0
+    s_in, surf = hit
+    ev.append(("enter", surf))
+    x = o + s_in * d
+    if surf != SIDE:
+        x[2] = z1 if surf == TOP else z0
+    r = math.hypot(x[0], x[1])
+    nrm = _outward(surf, x)
+    if surf != SIDE and r <= a:
+        dr = d - 2.0 * (d @ nrm) * nrm
+        p, s = _leave_cylinder(x, dr, r_out)
+        return S_REFLECTED, p, dr, s_in + s, 0
+    rh, th = frame_at(x)
+    sq = (r - a) / r                      # sqrt(s)
+    kr, kth, kz = d @ rh, d @ th, d[2]
+    if surf == SIDE:
+        q2 = kap - kap * kth * kth / (kap * sq * sq) - kz * kz   # m_r (1 - kt^2/m_t - kz^2/m_z)
+        if q2 < 0.0:
+            dr = d - 2.0 * (d @ nrm) * nrm
+            p, s = _leave_cylinder(x, dr, r_out)
+            return S_REFLECTED, p, dr, s_in + s, 0
+        kr = -math.sqrt(q2)
+    else:
+        q2 = kap - kr * kr - kth * kth / (sq * sq)
+        if q2 < 0.0:
+            dr = d - 2.0 * (d @ nrm) * nrm
+            p, s = _leave_cylinder(x, dr, r_out)
+            return S_REFLECTED, p, dr, s_in + s, 0
+        kz = -math.sqrt(q2) if surf == TOP else math.sqrt(q2)
+    # virtual state: position and unit velocity (V_rho, V_theta, V_Z)
+    theta = math.atan2(x[1], x[0])
+    rho = sk * (r - a)
+    X = np.array([rho * math.cos(theta), rho * math.sin(theta), sk * x[2]])
+    Vr, Vt, Vz = kr / sk, kth / (sk * sq), kz / sk
+    V = Vr * np.array([math.cos(theta), math.sin(theta), 0.0]) + \
+        Vt * np.array([-math.sin(theta), math.cos(theta), 0.0]) + np.array([0.0, 0.0, Vz])
+    t, bounces = 0.0, 0
+    Zlo, Zhi = sk * z0, sk * z1
+    while True:
+        cands = []
+        A = V[0] ** 2 + V[1] ** 2
+        if A > 0.0:
+            B = X[0] * V[0] + X[1] * V[1]
+            C = X[0] ** 2 + X[1] ** 2 - b * b
+            tb = (-B + math.sqrt(max(B * B - A * C, 0.0))) / A
+            if tb > 1e-12:
+                cands.append((tb, SIDE))
+        if V[2] > 0.0:
+            cands.append(((Zhi - X[2]) / V[2], TOP))
+        elif V[2] < 0.0:
+            cands.append(((Zlo - X[2]) / V[2], BOTTOM))
+        tc, surf = min(cands, key=lambda c: c[0])
+        X = X + tc * V
+        t += tc
+        theta = math.atan2(X[1], X[0])
+        rho = math.hypot(X[0], X[1])
+        rhv = np.array([math.cos(theta), math.sin(theta), 0.0])
+        thv = np.array([-math.sin(theta), math.cos(theta), 0.0])
+        r = a + rho / sk
+        sq = (r - a) / r
+        xp = np.array([r * math.cos(theta), r * math.sin(theta), X[2] / sk])
+        Vr, Vt, Vz = V @ rhv, V @ thv, V[2]
+        # physical velocity and k = M v
+        vr, vt, vz = Vr / sk, Vt / (sk * sq), Vz / sk
+        kr, kth, kz = kap * vr, kap * sq * sq * vt, kap * vz
+        tan2 = kth * kth + kz * kz if surf == SIDE else kr * kr + kth * kth
+        ev.append(("exit" if tan2 <= 1.0 else "tir", surf))
+        if surf == SIDE:
+            if tan2 <= 1.0:
+                dout = math.sqrt(1.0 - tan2) * rhv + kth * thv + np.array([0.0, 0.0, kz])
+                p, s = _leave_cylinder(xp, dout, r_out)
+                return S_EXITED, p, dout, s_in + t + s, bounces
+            if bounces >= max_bounces:
+                vv = vr * rhv + vt * thv + np.array([0.0, 0.0, vz])
+                return S_TIR, xp, vv / np.linalg.norm(vv), s_in + t, bounces
+            V = V - 2.0 * Vr * rhv
+        else:
+            if tan2 <= 1.0:
+                sgn = 1.0 if surf == TOP else -1.0
+                dout = kr * rhv + kth * thv + np.array([0.0, 0.0, sgn * math.sqrt(1.0 - tan2)])
+                p, s = _leave_cylinder(xp, dout, r_out)
+                return S_EXITED, p, dout, s_in + t + s, bounces
+            if bounces >= max_bounces:
+                vv = vr * rhv + vt * thv + np.array([0.0, 0.0, vz])
+                return S_TIR, xp, vv / np.linalg.norm(vv), s_in + t, bounces
+            V = V * np.array([1.0, 1.0, -1.0])
+        bounces += 1
+
+
+def cap_rays(n, seed, a=1.0, b=2.0, z0=0.0, z1=4.0, polar_max_deg=75.0, side_share=0.5):
+    """Vacuum rays that meet the finite cloak: a share through the annulus of
+    a cap (aimed at a uniform point of a < r < b on the top or bottom cap,
+    from outside, at polar angles up to polar_max_deg to the cap's normal),
+    the rest through the side at steep elevations (so that inside they reach
+    the caps). SoA (6, n), origins 6 units before the aim point."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((6, n))
+    for i in range(n):
+        if rng.uniform() >= side_share:
+            top = rng.uniform() < 0.5
+            r = math.sqrt(rng.uniform(a * a, b * b))
+            ph = rng.uniform(0, 2 * math.pi)
+            tgt = np.array([r * math.cos(ph), r * math.sin(ph), z1 if top else z0])
+            pol = math.radians(rng.uniform(0.0, polar_max_deg))
+            az = rng.uniform(0, 2 * math.pi)
+            d = np.array([math.sin(pol) * math.cos(az), math.sin(pol) * math.sin(az),
+                          -math.cos(pol) if top else math.cos(pol)])
+        else:
+            ph = rng.uniform(0, 2 * math.pi)
+            tgt = np.array([b * math.cos(ph), b * math.sin(ph), rng.uniform(z0 + 0.3, z1 - 0.3)])
+            al = rng.uniform(-1.3, 1.3)
+            be = rng.uniform(0.5, 1.3) * (1 if rng.uniform() < 0.5 else -1)
+            inward = ph + math.pi + al
+            d = np.array([math.cos(be) * math.cos(inward), math.cos(be) * math.sin(inward), math.sin(be)])
+        out[:3, i] = tgt - 6.0 * d
+        out[3:, i] = d
+    return out

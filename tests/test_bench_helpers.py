@@ -16,6 +16,10 @@ def test_finite_json_is_strict():
 
 def test_traffic_is_keyed_by_source_and_shape(monkeypatch):
     shapes = bench.TRAFFIC["bytes_per_launch"]
+    if bench.TRAFFIC["source_sha256"] != bench.integrator_source_hash():
+        # counters taken on another integrator source: no figure is reported
+        assert bench.traffic_for(256, 2) == (None, None)
+        monkeypatch.setattr(bench, "integrator_source_hash", lambda: bench.TRAFFIC["source_sha256"])
     # every measured shape reports its own figure
     for (block, refill), nbytes in shapes.items():
         assert bench.traffic_for(block, refill) == (nbytes, [block, refill])

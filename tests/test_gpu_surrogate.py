@@ -158,8 +158,25 @@ def test_forward_matches_bf16_reference():
 @pytest.mark.parametrize("masked,huber", [(False, 0.0), (True, 0.0), (False, 0.5)])
 def test_gradients_match_bf16_reference(masked, huber):
     """Gradients of the batch loss against the FP64 reference's (BF16
-    rounding at the same points), per parameter tensor, in relative
-    Frobenius norm. Masked rows (weight 0) must not contribute."""
+    rounding at the same points), element by element. Masked rows (weight
+    0) must not contribute.
+
+    Per-element bar, from the rounding the reference models. With S the sum
+    of the absolute values of the terms an entry adds up and Mx its largest
+    term (oracle.mlp.grad_term_magnitudes): the GPU's values before each
+    BF16 rounding differ from the reference's FP64 ones by FP32 accumulation
+    (~1e-7 relative); now and then such a value lies on the other side of a
+    BF16 rounding boundary, and the rounded operand differs by one BF16 unit
+    (2^-8 relative), which moves the values downstream, which flips further
+    roundings in the layers below (the backward pass crosses three BF16
+    layers). An entry then moves by a few BF16 units of its largest terms:
+    |gpu - ref| <= 2^-3 Mx + 1e-4 S, 32 units, or 1e-4 of the summed
+    magnitudes for the FP32 accumulation over up to 300 rows x 256 terms and
+    the propagated differences. A CPU simulation of this cascade (relative
+    noise up to 1e-6 before every rounding of the reference) stays within
+    0.4 of the bar. The bar still resolves single rows: the test checks that
+    dropping one row from the reference breaks it (in the simulation 40-87%
+    of each weight tensor's entries then exceed it)."""
     import torch
     from paper_1209_6038_amd import rt
     m = rt.Surrogate(seed=8)
@@ -174,22 +191,38 @@ def test_gradients_match_bf16_reference(masked, huber):
     torch.cuda.synchronize()
     g = g.cpu().numpy().astype(np.float64)
     keep = w > 0
-    lo, go = mlp.loss_and_grads(p, mlp.features(x)[keep], t.T[keep].astype(np.float64), bf16=True,
-                                huber=huber)
+    f, tt = mlp.features(x)[keep], t.T[keep].astype(np.float64)
+    lo, go = mlp.loss_and_grads(p, f, tt, bf16=True, huber=huber)
     scale = keep.sum() / n  # the GPU loss is a mean over all n rows
     lo *= scale
     go = [gg * scale for gg in go]
     say(f"loss gpu {loss.item():.6e} ref {lo:.6e}")
     assert abs(loss.item() - lo) <= 1e-5 * lo
+    S, Mx = mlp.grad_term_magnitudes(p, f, tt, bf16=True, huber=huber)
+    bars = [(1e-4 * S[i] + 2.0 ** -3 * Mx[i]) * scale for i in range(10)]
     off = 0
+    gpu_t = []
     for i, gg in enumerate(go):
         gpu = g[off:off + gg.size].reshape(gg.shape)
+        gpu_t.append(gpu)
         off += gg.size
-        rel = np.linalg.norm(gpu - gg) / np.linalg.norm(gg)
-        layer = i // 2
-        bar = 1e-2 if layer in mlp.BF16_LAYERS or layer == 0 else 1e-4
-        say(f"  tensor {i} (layer {layer + 1}) rel err {rel:.2e} (bar {bar:.0e})")
-        assert rel <= bar, (i, rel)
+        ratio = np.abs(gpu - gg) / bars[i]
+        worst = np.unravel_index(np.argmax(ratio), ratio.shape)
+        say(f"  tensor {i} (layer {i // 2 + 1}): max |gpu - ref| / bar = {ratio.max():.3f} at {worst}, "
+            f"max |gpu - ref| {np.abs(gpu - gg).max():.2e}, max |ref| {np.abs(gg).max():.2e}")
+        assert (ratio <= 1.0).all(), (i, worst, gpu[worst], gg[worst])
+    # the bar resolves one row: without the kept row with the largest loss
+    # term, the reference's weight gradients leave it in every layer
+    yk, _ = mlp.forward(p, f, bf16=True)
+    drop = int(np.argmax(((yk - tt) ** 2).sum(axis=1)))
+    sel = np.ones(len(f), bool)
+    sel[drop] = False
+    _, gd = mlp.loss_and_grads(p, f[sel], tt[sel], bf16=True, huber=huber)
+    sd = (len(f) - 1) / n
+    for i in range(0, 10, 2):
+        over = (np.abs(gpu_t[i] - gd[i] * sd) > bars[i]).mean()
+        say(f"  one row dropped: tensor {i}: {over:.1%} of the entries over the bar")
+        assert over > 0.01, i
 
 
 def test_closed_form_baselines_match_the_exact_transit():
@@ -376,3 +409,73 @@ def test_infer_rows_do_not_depend_on_the_batch():
     assert torch.equal(fb2, fb[sub])
     assert torch.equal(st2, st_s[sub])
     assert torch.equal(torch.nan_to_num(y2), torch.nan_to_num(y_s[:, sub]))
+
+
+def test_adamw_step_matches_reference():
+    """Two AdamW steps (rt_surrogate_step, the optimizer of
+    rt_surrogate_train) from a seeded state (parameters, moments, step
+    count 7) with seeded gradients, against the FP64 AdamW of the reference,
+    element by element: parameters, first and second moments. The GPU works
+    in FP32 on FP32 inputs (the reference takes the same FP32 values), a
+    handful of roundings per entry: |m - ref| <= 2^-21 (beta1 |m| +
+    (1 - beta1) |g|), likewise v, and |p - ref| <= 2^-21 (|p| + lr |m^| /
+    (sqrt(v^) + eps)). Biases are not decayed."""
+    import torch
+    from paper_1209_6038_amd import rt
+    n = rt.Surrogate.NPARAM
+    rng = np.random.default_rng(12)
+    m = rt.Surrogate(seed=13)
+    p0 = m.get_params().astype(np.float64)
+    m0 = rng.normal(scale=1e-3, size=n).astype(np.float32)
+    v0 = (rng.normal(scale=1e-3, size=n) ** 2).astype(np.float32)
+    m.set_state(m0, v0, 7)
+    hp = dict(lr=np.float32(2e-3), beta1=np.float32(0.9), beta2=np.float32(0.995), eps=np.float32(1e-8),
+              weight_decay=np.float32(0.01))
+    mask = ~mlp.is_bias_index()
+    pr, mr, vr = p0, m0.astype(np.float64), v0.astype(np.float64)
+    for k in range(2):
+        g = rng.normal(scale=1e-3, size=n).astype(np.float32)
+        g[:50] = 0.0  # zero gradients: the update is the decay and the old moments alone
+        m.step(torch.from_numpy(g).cuda(), **{a: float(b) for a, b in hp.items()})
+        torch.cuda.synchronize()
+        b1, b2 = float(hp["beta1"]), float(hp["beta2"])
+        m_prev, v_prev = mr, vr
+        pr, mr, vr = mlp.adamw_step(pr, g, mr, vr, 8 + k, float(hp["lr"]), b1, b2, float(hp["eps"]),
+                                    float(hp["weight_decay"]), mask)
+        pg = m.get_params().astype(np.float64)
+        mg, vg, step = m.get_state()
+        assert step == 8 + k
+        gg = g.astype(np.float64)
+        tol_m = 2.0 ** -21 * (b1 * np.abs(m_prev) + (1 - b1) * np.abs(gg)) + 1e-30
+        tol_v = 2.0 ** -21 * (b2 * v_prev + (1 - b2) * gg * gg) + 1e-30
+        upd = float(hp["lr"]) * np.abs(mr / (1 - b1 ** (8 + k))) / (np.sqrt(vr / (1 - b2 ** (8 + k))) +
+                                                                     float(hp["eps"]))
+        tol_p = 2.0 ** -21 * (np.abs(pr) + upd)
+        say(f"step {k}: max |dm|/tol {np.max(np.abs(mg - mr) / tol_m):.3f}, "
+            f"|dv|/tol {np.max(np.abs(vg - vr) / tol_v):.3f}, |dp|/tol {np.max(np.abs(pg - pr) / tol_p):.3f}")
+        assert (np.abs(mg - mr) <= tol_m).all()
+        assert (np.abs(vg - vr) <= tol_v).all()
+        assert (np.abs(pg - pr) <= tol_p).all()
+        # the next step starts from the GPU's FP32 state, as the GPU does
+        pr, mr, vr = pg, mg.astype(np.float64), vg.astype(np.float64)
+    m.close()
+
+
+def test_train_step_counts_steps_and_reports_the_gradient_loss():
+    """rt_surrogate_train evaluates the loss of rt_surrogate_grad (same
+    forward; the reduction order of its atomics may differ, ~1e-7) and
+    advances the step count that sets AdamW's bias corrections."""
+    import torch
+    from paper_1209_6038_amd import rt
+    rng = np.random.default_rng(14)
+    x = torch.from_numpy(rng.normal(size=(6, 700)).astype(np.float32)).cuda()
+    t = torch.from_numpy(rng.normal(size=(5, 700)).astype(np.float32)).cuda()
+    a = rt.Surrogate(seed=15)
+    _, lg = a.grad(x, t)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    a.train_step(x, t, lr=1e-3, weight_decay=0.01, loss=loss)
+    torch.cuda.synchronize()
+    assert abs(loss.item() - lg.item()) <= 1e-6 * abs(lg.item())
+    a.train_step(x, t, lr=1e-3, weight_decay=0.01)
+    assert a.get_state()[2] == 2
+    a.close()

@@ -143,7 +143,10 @@ def test_transmission_weights_full_size_sampled():
             g = {k: v.cpu().numpy() for k, v in r.items()}
             assert ((g["trans"] >= 0.0) & (g["trans"] <= 1.0 + 1e-12)).all()
             assert (g["trans"][g["status"] == 1] == 1.0).all()
-            assert (g["trans"][(g["status"] != 0) & (g["status"] != 1)] == 0.0).all()
+            # reflected at the entry: all of the light off the metal end
+            # disk, none kept by the crystal's surface reflection
+            assert np.isin(g["trans"][g["status"] == 7], (0.0, 1.0)).all()
+            assert (g["trans"][~np.isin(g["status"], (0, 1, 7))] == 0.0).all()
             idx = np.sort(rng.choice(rays.shape[1], 256, replace=False))
             o = oracle.trace(c, W.opts_dp45(), branch, rays[:, idx])
             gs = {k: v[..., idx] for k, v in g.items()}

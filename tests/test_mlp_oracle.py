@@ -105,3 +105,38 @@ def test_features_are_the_tangential_wave_numbers():
         assert f[i, 0] == pytest.approx(d @ th, abs=1e-13)
         assert f[i, 1] == pytest.approx(d @ ez, abs=1e-13)
         assert list(f[i, 2:]) == [al, be, x6[4, i], x6[5, i]]
+
+
+def test_adamw_matches_torch_cpu():
+    """Three AdamW steps of the reference against torch.optim.AdamW in
+    float64, weights decayed and biases not (two parameter groups)."""
+    import torch
+    rng = np.random.default_rng(11)
+    shapes = [(3, 4), (4,), (4, 2), (2,)]  # a small layout of the same kind: W, b, W, b
+    p0 = [rng.normal(size=s_) for s_ in shapes]
+    hp = dict(lr=3e-3, betas=(0.85, 0.99), eps=1e-7, weight_decay=0.05)
+    tw = [torch.tensor(a, dtype=torch.float64, requires_grad=True) for a in p0]
+    opt = torch.optim.AdamW([{"params": [tw[0], tw[2]], "weight_decay": hp["weight_decay"]},
+                             {"params": [tw[1], tw[3]], "weight_decay": 0.0}],
+                            lr=hp["lr"], betas=hp["betas"], eps=hp["eps"])
+    flat = np.concatenate([a.ravel() for a in p0])
+    mask = np.concatenate([np.full(a.size, len(a.shape) == 2) for a in p0])
+    m = np.zeros_like(flat)
+    v = np.zeros_like(flat)
+    for t in range(1, 4):
+        grads = [rng.normal(size=s_) for s_ in shapes]
+        for tt, gg in zip(tw, grads):
+            tt.grad = torch.tensor(gg, dtype=torch.float64)
+        opt.step()
+        gflat = np.concatenate([a.ravel() for a in grads])
+        flat, m, v = mlp.adamw_step(flat, gflat, m, v, t, hp["lr"], hp["betas"][0], hp["betas"][1],
+                                    hp["eps"], hp["weight_decay"], mask)
+        ref = np.concatenate([tt.detach().numpy().ravel() for tt in tw])
+        np.testing.assert_allclose(flat, ref, rtol=0, atol=1e-14)
+
+
+def test_bias_mask_layout():
+    mask = mlp.is_bias_index()
+    assert mask.size == 200453
+    assert mask.sum() == 256 * 4 + 5
+    assert not mask[:6 * 256].any() and mask[6 * 256:6 * 256 + 256].all()

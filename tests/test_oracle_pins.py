@@ -495,6 +495,83 @@ def test_top_disk_of_metal_cylinder_reflects():
 
 
 # --------------------------------------------------------------------------
+# end caps of the finite cloak (not in the paper: Sect. 3 interfaces with
+# normal +-z). Pinned by the two branches whose paths are straight lines:
+# the radial cloak's ordinary ray (Snell with n = sqrt(kappa) = 2 at every
+# interface, total reflection beyond 30 degrees from the normal) and the
+# azimuthal cloak's extraordinary ray (a straight line in the virtual space
+# (rho, theta, sqrt(kappa) z)), each traced in closed form through caps,
+# side, mirror and internal reflections.
+# --------------------------------------------------------------------------
+def _cap_events(fn, rays, max_bounces):
+    log = []
+    res = []
+    for i in range(rays.shape[1]):
+        ev = []
+        res.append(fn(rays[:3, i], rays[3:, i], max_bounces=max_bounces, events=ev))
+        log.append(ev)
+    return res, log
+
+
+def _check_finite(res, r, tol):
+    for i, (st, p, dd, opl, nb) in enumerate(res):
+        assert r["status"][i] == st, (i, st, r["status"][i])
+        np.testing.assert_allclose(r["out"][:3, i], p, atol=tol, err_msg=f"ray {i}")
+        np.testing.assert_allclose(r["out"][3:, i], dd, atol=tol, err_msg=f"ray {i}")
+        assert r["opl"][i] == pytest.approx(opl, abs=tol), i
+
+
+def test_finite_radial_ordinary_caps_closed_form():
+    """Radial cloak, ordinary ray, height 4: entries and exits through both
+    caps, total internal reflection at caps (side entries: horizontal wave
+    number >= sqrt(3) > 1) and at the side (cap entries), the metal mirror,
+    and the bounce limit, all against straight-line optics with n = 2."""
+    rays = CF.cap_rays(300, 31)
+    res, log = _cap_events(CF.finite_radial_o, rays, 4)
+    r = oracle.trace(W.cloak(0, height=4.0), W.opts_dp45(tol=1e-12), O, rays)
+    _check_finite(res, r, 1e-9)
+    flat = [e for ev in log for e in ev]
+    for kind, surf in (("enter", CF.TOP), ("enter", CF.BOTTOM), ("exit", CF.TOP), ("exit", CF.BOTTOM),
+                       ("tir", CF.TOP), ("tir", CF.BOTTOM), ("tir", CF.SIDE), ("mirror", "inner"),
+                       ("exit", CF.SIDE)):
+        assert flat.count((kind, surf)) >= 5, (kind, surf, flat.count((kind, surf)))
+    st = {x[0] for x in res}
+    assert {CF.S_EXITED, CF.S_TIR} <= st
+
+
+def test_finite_azimuthal_extraordinary_caps_closed_form():
+    """Azimuthal cloak, extraordinary ray, height 4: a straight line in
+    (rho cos theta, rho sin theta, sqrt(kappa) z) through caps and side, with
+    evanescent cap entries near r = a reflected into vacuum, same-mode total
+    internal reflection at caps and side, and the bounce limit."""
+    rays = CF.cap_rays(300, 32)
+    res, log = _cap_events(CF.finite_azimuthal_e, rays, 4)
+    r = oracle.trace(W.cloak(1, height=4.0), W.opts_dp45(tol=1e-12), E, rays)
+    _check_finite(res, r, 1e-7)
+    flat = [e for ev in log for e in ev]
+    for kind, surf in (("enter", CF.TOP), ("enter", CF.BOTTOM), ("exit", CF.TOP), ("exit", CF.BOTTOM),
+                       ("tir", CF.TOP), ("tir", CF.BOTTOM), ("tir", CF.SIDE), ("exit", CF.SIDE)):
+        assert flat.count((kind, surf)) >= 3, (kind, surf, flat.count((kind, surf)))
+    st = {x[0] for x in res}
+    assert {CF.S_EXITED, CF.S_REFLECTED, CF.S_TIR} <= st
+
+
+def test_diverged_rule_at_outer_interfaces():
+    """A ray whose Hamiltonian v^T M v has drifted from 1 by more than 1e-3
+    at an outer interface is reported DIVERGED (4): fixed RK4 steps far too
+    long for the curvature near r = a make in-plane extraordinary rays of
+    the radial cloak drift; rays aimed far from the axis keep |H - 1| small
+    and exit (0)."""
+    rays = W.inplane_bundle(64, 1, p_max=1.9)
+    r = oracle.trace(W.cloak(0), W.opts_rk4(h=0.2), E, rays)
+    st = r["status"]
+    assert (st == 4).any() and (st == 0).any()
+    # every exited ray passed the rule; a diverged one stopped on an interface
+    assert (r["hres"][st == 0] <= 1e-3).all()
+    assert (r["hres"][st == 4] > 1e-3).all()
+
+
+# --------------------------------------------------------------------------
 # camera, room, shading
 # --------------------------------------------------------------------------
 def test_splitmix64_published_value():
