@@ -316,7 +316,8 @@ typedef struct {
    when its (axis, branch, alpha, beta) cell of the trust map is untrusted,
    when the predicted exit violates the conservation of the tangential wave
    numbers (max(|k_theta' - k_theta|, |k_z' - k_z|)) by more than hres_max,
-   or when the predicted exit height is within cap_margin of an end cap. */
+   when the predicted exit height is within cap_margin of an end cap, or
+   when the entry lies in the near-singular band (p_min). */
 typedef struct {
     double tol;         /* calibration: largest exit error a trusted cell may show */
     double hres_max;    /* conservation residual limit */
@@ -324,6 +325,11 @@ typedef struct {
     int32_t min_count;  /* calibration rays a cell needs to be trusted */
     int32_t dilate;     /* also distrust cells within this many cells (same axis and branch) of an untrusted one */
     double unresolved;  /* calibration: exits whose exact transit drifted by |H - 1| > this are no reference */
+    double p_min;       /* near-singular band: entries whose conserved wave number (k_theta for the
+                           azimuthal cloak's extraordinary branch, |(k_theta, k_z)| for the radial
+                           extraordinary and azimuthal ordinary branches) is below p_min pass within
+                           ~p_min of r = r1, where the integrator itself does not resolve the path;
+                           they are traced exactly (0 = no band) */
 } rt_gate_opts;
 
 /* New model with weights and biases uniform in +-1/sqrt(fan_in) (seeded),
@@ -423,8 +429,13 @@ int rt_surrogate_infer(rt_model model, const rt_cloak *cloaks, int32_t n_cloaks,
    shrink, so the bucket tracks the integration cost, while the network
    costs the same for every ray. min_difficulty = 0 offers every side entry.
    The exit error of an accepted ray is what the model's calibration bounds
-   (rt_surrogate_calibrate), so a sample's colour can differ from
-   rt_render_multi's where its room point lies that close to a tile edge.
+   (tol of rt_surrogate_calibrate, in r2 units and radians); it moves the
+   room point along its face by at most tol (r2 + L) / cos(theta) for a
+   vacuum leg of length L meeting the face at angle theta to its normal. An
+   accepted prediction whose room point lies within twice that distance of
+   a tile edge or face boundary is traced by the integrator instead (tile-
+   edge gate), so every sample takes the plain render's colour wherever the
+   calibration bound holds.
      model:  a calibrated model on the current device
      min_difficulty: in [0, 16] (16 offers nothing)
      counts: host int64[2] or NULL: side entries offered to the network and

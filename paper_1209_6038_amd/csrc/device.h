@@ -995,4 +995,26 @@ __device__ __forceinline__ int room_code(const RoomP& rm, const double o[3], con
   return face * 2 + (int)par;
 }
 
+// Distance, within its face, from the room point o + s d (face `face` of
+// room_code) to the nearest tile edge or face boundary, and the cosine
+// |d . n| of the ray with the face normal. A small error in o or d moves the
+// point by (error across the ray) / cosine along the face.
+__device__ __forceinline__ double tile_edge_distance(const RoomP& rm, const double o[3], const double d[3],
+                                                     double s, int face, double& cosn) {
+  const int ax = face >> 1;
+  const int ua = ax == 0 ? 1 : 0;
+  const int va = ax == 2 ? 1 : 2;
+  double dist = __builtin_inf();
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int a = k == 0 ? ua : va;
+    const double pc = fma(s, d[a], o[a]);
+    const double f = pc / rm.tile - floor(pc / rm.tile);
+    dist = fmin(dist, fmin(f, 1.0 - f) * rm.tile);
+    dist = fmin(dist, fmin(fabs(pc - rm.lo[a]), fabs(rm.hi[a] - pc)));
+  }
+  cosn = fabs(d[ax]);
+  return dist;
+}
+
 }  // namespace rtk

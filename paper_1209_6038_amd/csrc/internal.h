@@ -18,3 +18,8 @@ __attribute__((visibility("hidden"))) int surrogate_predict_gated(rt_model model
 // RT_OK if the model lives on the current device and has a calibrated trust
 // map (what surrogate_predict_gated needs); sets the error message otherwise.
 __attribute__((visibility("hidden"))) int surrogate_check_ready(rt_model model);
+
+// The exit error that the model's calibration bounds for an accepted
+// prediction (the trust map's tolerance, in units of r2 for position and
+// radians for direction).
+__attribute__((visibility("hidden"))) double surrogate_exit_tolerance(rt_model model);

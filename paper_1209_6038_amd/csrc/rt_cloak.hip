@@ -840,6 +840,7 @@ struct RenderP {
   int pol[2];         // branch of each traced polarization
   int has_cloak, idx32;  // idx32: every flattened sample index < 2^32
   int sur_min;           // surrogate render: side entries of difficulty bucket >= sur_min are candidates
+  double edge_tol;       // surrogate render: exit-error bound of an accepted prediction (tile-edge gate)
   unsigned char *codes;  // chunk-local codes [segment][g1-g0]
   float *topl;           // chunk-local optical path to the room [segment][g1-g0] (NaN: no room point); NULL unless tof
   double *rec;           // aux (may be NULL)
@@ -1016,7 +1017,7 @@ __global__ void __launch_bounds__(256) k_rd_sur_apply(CloakP c, OptsP o, RoomP r
   const int q = (int)(key & (NSEG - 1));
   const long long gidx = key >> 2;
   static_assert(NSEG == 4, "key packing assumes 4 segments");
-  const bool rej = valid && Cd.fb[i] != 0;
+  bool rej = valid && Cd.fb[i] != 0;
   if (valid && !rej) {
     const double ph = Cd.y5[i], ze = Cd.y5[Cd.ld + i], al = Cd.y5[2 * Cd.ld + i];
     const double be = Cd.y5[3 * Cd.ld + i], Tt = Cd.y5[4 * Cd.ld + i];
@@ -1026,7 +1027,15 @@ __global__ void __launch_bounds__(256) k_rd_sur_apply(CloakP c, OptsP o, RoomP r
     double dd[3] = {cb * (ca * cp - sa * sp), cb * (ca * sp + sa * cp), sin(be)};
     double sh0;
     const int code = room_code(rm, p, dd, sh0);
-    rd_write(R, q, gidx, code, RT_RAY_EXITED, p, dd, (double)Cd.s_in[i] + Tt + sh0, 0);
+    // tile-edge gate: the accepted exit errs by at most edge_tol in
+    // position (units of r2) and direction (rad), which moves the room point
+    // along the face by at most edge_tol (r2 + distance) / cosine; a point
+    // closer than twice that to a tile edge could take the other colour, so
+    // the sample goes to the integrator
+    double cosn = 1.0;
+    const double dist = code < 12 ? tile_edge_distance(rm, p, dd, sh0, code >> 1, cosn) : 0.0;
+    if (!(dist * cosn > 2.0 * R.edge_tol * (c.b + sh0))) rej = true;
+    else rd_write(R, q, gidx, code, RT_RAY_EXITED, p, dd, (double)Cd.s_in[i] + Tt + sh0, 0);
   }
   double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, d[3] = {0, 0, 1}, s = 0.0;
   int kind = 0;
@@ -1656,6 +1665,7 @@ int render_surrogate(rt_model model, const rt_cloak_desc &desc, const RenderJob 
   const Table &T = ws.T;
   RenderP R = J.R;
   R.sur_min = min_difficulty;
+  R.edge_tol = surrogate_exit_tolerance(model);
   R.codes = ws.codes;
   R.topl = R.tof ? ws.topl : nullptr;
   for (long long g0 = 0; g0 < J.total; g0 += J.chunk) {

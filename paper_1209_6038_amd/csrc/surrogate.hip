@@ -826,7 +826,20 @@ struct GateP {
   float a, b, z0, z1;  // cloak radii r1, r2 and material height range
   float hres_max;    // conservation residual limit
   float cap_margin;  // distance of the predicted exit height from a cap
+  float p_min;       // near-singular band of the conserved wave number
 };
+
+// Outside the near-singular band: the conserved wave number that keeps the
+// path away from r = a (k_theta for the azimuthal cloak's extraordinary
+// branch, whose metric is singular in theta only; |(k_theta, k_z)| for the
+// radial extraordinary and azimuthal ordinary branches, singular in theta
+// and z; the radial cloak's ordinary branch is homogeneous) is >= p_min.
+__device__ __forceinline__ bool outside_band(int kind, float al, float be, float p_min) {
+  if (kind == 0 || !(p_min > 0.0f)) return true;
+  const float kt = cosf(be) * sinf(al), kz = sinf(be);
+  const float p = kind == 3 ? fabsf(kt) : sqrtf(fmaf(kt, kt, kz * kz));
+  return p >= p_min;
+}
 
 // Gate and write the accepted predictions. A prediction is rejected (and
 // the exact integrator traces the ray) when
@@ -851,7 +864,7 @@ __device__ __forceinline__ void gate_row(long long i, const float *__restrict__ 
   if (acc) {
     const int kind = kind_of(pol, axis);
     decode(yrow, sc, phi, z, al, be, kind, gp.a, gp.b, out);
-    acc = map[cell_of(kind, al, be)] != 0;
+    acc = map[cell_of(kind, al, be)] != 0 && outside_band(kind, al, be, gp.p_min);
     const float kt = cosf(be) * sinf(al), kz = sinf(be);
     const float kt2 = cosf(out[3]) * sinf(out[2]), kz2 = sinf(out[3]);
     const float res = fmaxf(fabsf(kt2 - kt), fabsf(kz2 - kz));
@@ -881,7 +894,7 @@ __global__ void __launch_bounds__(256) k_pregate(const float *__restrict__ x6, l
     const float phi = x6[i], z = x6[ld + i], al = x6[2 * ld + i], be = x6[3 * ld + i];
     const float pol = x6[4 * ld + i], axis = x6[5 * ld + i];
     take = entry_ok(phi, z, al, be, pol, axis) && z >= gp.z0 && z <= gp.z1 &&
-           map[cell_of(kind_of(pol, axis), al, be)] != 0;
+           map[cell_of(kind_of(pol, axis), al, be)] != 0 && outside_band(kind_of(pol, axis), al, be, gp.p_min);
     fallback[i] = take ? 0 : 1;
   }
   const unsigned long long m = __ballot(take);
@@ -1347,6 +1360,8 @@ int surrogate_check_ready(rt_model mo) {
   return RT_OK;
 }
 
+double surrogate_exit_tolerance(rt_model mo) { return mo->gate.tol; }
+
 int surrogate_predict_gated(rt_model mo, const rt_cloak_desc &d, int64_t n, int64_t ld, const float *x6, float *y5,
                             uint8_t *fallback, int32_t *status, hipStream_t s) {
   int e = surrogate_check_ready(mo);
@@ -1361,6 +1376,7 @@ int surrogate_predict_gated(rt_model mo, const rt_cloak_desc &d, int64_t n, int6
   gp.z1 = std::isfinite(d.z1) ? (float)d.z1 : INFINITY;
   gp.hres_max = (float)mo->gate.hres_max;
   gp.cap_margin = (float)mo->gate.cap_margin;
+  gp.p_min = (float)mo->gate.p_min;
   const long long batch = std::min<long long>(n, 1LL << 24);
   e = reserve_yinf(mo, batch);
   if (e) return e;
@@ -1428,6 +1444,7 @@ int rt_surrogate_create(uint64_t seed, rt_model *out) {
   mo->gate.hres_max = 1e-4;
   mo->gate.cap_margin = 1e-2;
   mo->gate.min_count = 8;
+  mo->gate.p_min = 1e-4;
   bool ok = hipMemcpy(mo->P, h.data(), sizeof(float) * NPARAM, hipMemcpyHostToDevice) == hipSuccess &&
             upload_scal(mo) == RT_OK && upload_map(mo) == RT_OK;
   if (ok) {
@@ -1670,9 +1687,10 @@ int rt_surrogate_calibrate(rt_model mo, const rt_cloak *cloaks, int32_t n_cloaks
   if (e) return e;
   if (!y5_exact || !status_exact || !gate) return fail(RT_E_INVALID, "y5_exact, status_exact and gate are required");
   if (!(gate->tol > 0.0) || !(gate->hres_max > 0.0) || !(gate->cap_margin >= 0.0) || gate->min_count < 1 ||
-      gate->dilate < 0 || gate->dilate > 8 || (hres_exact && !(gate->unresolved > 0.0)))
+      gate->dilate < 0 || gate->dilate > 8 || (hres_exact && !(gate->unresolved > 0.0)) ||
+      !(gate->p_min >= 0.0 && gate->p_min < 1.0))
     return fail(RT_E_INVALID, "gate needs tol > 0, hres_max > 0, cap_margin >= 0, min_count >= 1, "
-                              "0 <= dilate <= 8 and, with hres_exact, unresolved > 0");
+                              "0 <= dilate <= 8, 0 <= p_min < 1 and, with hres_exact, unresolved > 0");
   e = reserve_yinf(mo, n);
   if (e) return e;
   hipStream_t s = (hipStream_t)stream;
@@ -1749,7 +1767,7 @@ int rt_surrogate_save(rt_model mo, const char *path) {
     return fail(RT_E_DEVICE, "copy failed");
   FILE *f = fopen(path, "wb");
   if (!f) return fail(RT_E_INVALID, "cannot open %s", path);
-  const char magic[8] = {'R', 'T', 'M', 'L', 'P', '0', '3', '\0'};
+  const char magic[8] = {'R', 'T', 'M', 'L', 'P', '0', '4', '\0'};
   const long long np = NPARAM, nc = NCELLS;
   const int valid = mo->map_valid;
   bool ok = fwrite(magic, 1, 8, f) == 8 && fwrite(&np, sizeof(np), 1, f) == 1 &&
@@ -1773,7 +1791,7 @@ int rt_surrogate_load(const char *path, rt_model *out) {
   rt_gate_opts gate;
   std::vector<float> h(NPARAM);
   std::vector<unsigned char> map(NCELLS);
-  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "RTMLP03", 8) == 0 && fread(&np, sizeof(np), 1, f) == 1 &&
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "RTMLP04", 8) == 0 && fread(&np, sizeof(np), 1, f) == 1 &&
             np == NPARAM && fread(scal, sizeof(float), S_LOSS, f) == (size_t)S_LOSS &&
             fread(h.data(), sizeof(float), NPARAM, f) == (size_t)NPARAM && fread(&nc, sizeof(nc), 1, f) == 1 &&
             nc == NCELLS && fread(&valid, sizeof(valid), 1, f) == 1 && fread(&gate, sizeof(gate), 1, f) == 1 &&

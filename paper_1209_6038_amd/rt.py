@@ -76,7 +76,7 @@ class TrainOpts(ctypes.Structure):
 class GateOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("hres_max", ctypes.c_double),
                 ("cap_margin", ctypes.c_double), ("min_count", ctypes.c_int32),
-                ("dilate", ctypes.c_int32), ("unresolved", ctypes.c_double)]
+                ("dilate", ctypes.c_int32), ("unresolved", ctypes.c_double), ("p_min", ctypes.c_double)]
 
 
 class RenderAux(ctypes.Structure):
@@ -587,10 +587,11 @@ class Surrogate:
         return t5
 
     def calibrate(self, cloaks, x6, y5_exact, status_exact, tol=1e-3, hres_max=1e-4,
-                  cap_margin=1e-2, min_count=8, dilate=0, hres_exact=None, unresolved=1e-6) -> float:
+                  cap_margin=1e-2, min_count=8, dilate=0, hres_exact=None, unresolved=1e-6,
+                  p_min=1e-4) -> float:
         import torch
         ld = _check_soa(x6, 6, torch.float32)
-        g = GateOpts(tol, hres_max, cap_margin, min_count, dilate, unresolved)
+        g = GateOpts(tol, hres_max, cap_margin, min_count, dilate, unresolved, p_min)
         frac = ctypes.c_double()
         _check(lib().rt_surrogate_calibrate(self.handle, _handles(cloaks), len(cloaks), x6.shape[1], ld,
                                             _ptr(x6), _ptr(y5_exact), _ptr(status_exact), _ptr(hres_exact),

@@ -53,7 +53,7 @@ def test_struct_layouts_match_header():
         "rt_room": (rt.Room, ["lo", "tile", "rgb"]),
         "rt_render_aux": (rt.RenderAux, ["rec", "status", "code", "nsteps", "tof"]),
         "rt_train_opts": (rt.TrainOpts, ["lr", "eps", "weight_decay"]),
-        "rt_gate_opts": (rt.GateOpts, ["tol", "hres_max", "cap_margin", "min_count", "dilate", "unresolved"]),
+        "rt_gate_opts": (rt.GateOpts, ["tol", "hres_max", "cap_margin", "min_count", "dilate", "unresolved", "p_min"]),
     }
     lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void){"]
     for s, (_, fs) in fields.items():

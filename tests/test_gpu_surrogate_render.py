@@ -31,9 +31,30 @@ def closed_form_model(calibrate_n=3_000_000, seed=77):
     return m
 
 
+def trained_model(n_train=4_000_000, steps=1500, calibrate_n=3_000_000, seed=78):
+    """A network trained like the benchmark's (AdamW on residuals of exact
+    transits of the infinite cylinders, Huber loss, BF16 MFMA), on fewer rays
+    and steps, then calibrated at half of the 1e-3 tolerance."""
+    from paper_1209_6038_amd import rt
+    from paper_1209_6038_amd import surrogate as S
+    cl = S.make_cloaks(None)
+    x = S.features(n_train, seed)
+    _, _, t, w = S.label(cl, x)
+    m = rt.Surrogate(seed=seed)
+    m.fit_scaling(x, t, w)
+    loss = S.train(m, x, t, w, steps=steps, batch=65536, lr=2e-3, lr_end=2e-5, warmup=100, huber=0.01)
+    say(f"trained {steps} steps, loss {loss:.3e}")
+    del x, t, w
+    xc = S.features(calibrate_n, seed + 1)
+    y, st, h = rt.transit_exact(cl, S.exact_opts(), xc, hres=True)
+    frac = m.calibrate(cl, xc, y, st, tol=5e-4, min_count=16, dilate=1, hres_exact=h, unresolved=1e-6)
+    say(f"trusted cells {frac:.4f}")
+    return m
+
+
 @pytest.fixture(scope="module")
-def cf_model():
-    return closed_form_model()
+def models():
+    return {"closed_form": closed_form_model(), "trained": trained_model()}
 
 
 def both_renders(model, cams, opts, min_difficulty=0):
@@ -71,17 +92,20 @@ def test_surrogate_render_with_nothing_trusted_is_the_plain_render():
         assert torch.equal(torch.nan_to_num(aux_p["tof"]), torch.nan_to_num(aux_s["tof"]))
 
 
-@pytest.mark.parametrize("min_difficulty", [0, 2])
-def test_surrogate_render_matches_the_plain_render(cf_model, min_difficulty):
-    """With a calibrated model most offered side entries take the
-    surrogate's exit ray. Samples it does not take are the plain render's bit
-    for bit; the accepted ones leave where the integrator's rays leave (exit
-    position and direction within the calibration tolerance, p99 at float32
-    resolution), and a sample's colour differs only where its room point lies
-    within the propagated exit error of a tile edge. A difficulty threshold
-    offers fewer entries (only those whose paths pass close to r = a)."""
+@pytest.mark.parametrize("kind,min_difficulty", [("trained", 0), ("trained", 2), ("closed_form", 0)])
+def test_surrogate_render_matches_the_plain_render(models, kind, min_difficulty):
+    """With a calibrated model (the trained network, or its closed-form
+    baselines alone) most offered side entries take the surrogate's exit
+    ray. Samples it does not take are the plain render's bit for bit; the
+    accepted ones leave where the integrator's rays leave (exit position and
+    direction within the calibration tolerance, p99 at float32 resolution),
+    and, with the tile-edge gate sending every accepted sample whose room
+    point lies within twice its propagated exit-error bound of a tile edge
+    to the integrator, they see the same tile: no pixel differs by more than
+    1/255 in any channel. A difficulty threshold offers fewer entries (only
+    those whose paths pass close to r = a)."""
     import torch
-    model = cf_model
+    model = models[kind]
     cams = [W.orbit_camera(0.3, 20.0, 96, 96, spp=4, seed=11), W.orbit_camera(2.5, 45.0, 96, 96, spp=4, seed=11),
             W.orbit_camera(4.0, 0.0, 96, 96, spp=4, seed=11)]
     rgb_p, aux_p, rgb_s, aux_s, counts = both_renders(model, cams, W.render_opts(), min_difficulty)
@@ -116,17 +140,18 @@ def test_surrogate_render_matches_the_plain_render(cf_model, min_difficulty):
     err = np.maximum(dpos, ddir)
     say(f"accepted exit error: p50 {np.median(err):.2e} p99 {np.quantile(err, 0.99):.2e} max {err.max():.2e}")
     assert np.quantile(err, 0.99) <= 1e-5 and err.max() <= 1e-3
-    # colours: a differing code only near a tile edge
+    # colours: the edge gate keeps every accepted room point away from tile
+    # edges by more than the exit error can move it
     cp, cs = aux_p["code"][ok].cpu().numpy(), aux_s["code"][ok].cpu().numpy()
     diff = cp != cs
     dist, sroom = edge_distance(W.room(), rs[:6])
-    say(f"accepted samples with another colour code: {int(diff.sum())} of {diff.size}")
-    if diff.any():
-        assert (dist[diff] <= 2.0 * err[diff] * R2 * (1.0 + sroom[diff]) + 1e-6).all()
+    say(f"accepted samples with another colour code: {int(diff.sum())} of {diff.size}; "
+        f"closest accepted room point to a tile edge {dist.min():.2e}")
+    assert not diff.any()
     d = (rgb_s - rgb_p).abs().amax(dim=-1)
     over = float((d > 1.0 / 255.0).float().mean())
-    say(f"pixels differing by more than 1/255: {over:.2e} (max {float(d.max()):.3f})")
-    assert over <= 1e-3
+    say(f"pixels differing by more than 1/255: {over:.2e} (max {float(d.max()):.3e})")
+    assert float(d.max()) <= 1.0 / 255.0
 
 
 def test_surrogate_render_argument_errors():
