@@ -195,6 +195,23 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
                    const double *in6, double *out6, double *opl, int32_t *status,
                    double *hres, int32_t *nsteps, double *trans, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, serving loops, harnesses that forbid hipMalloc): rt_trace_batch
+   without any allocation. Same arguments, semantics, outputs and errors as
+   rt_trace_batch, for at most RT_NOALLOC_MAX_RAYS rays per call (more:
+   RT_E_INVALID). The work table lives in a fixed device array of the
+   library (~31.5 MB, held on each device the library runs on until the
+   process ends) instead of the growing workspace; the call itself makes no
+   hipMalloc, hipFree or other allocation and records no timing events. The
+   array is shared by every call on a device and keeps the last call's
+   contents (each call clears what it needs), so calls that overlap on one
+   device (concurrent streams or threads) race and must be serialized by
+   the caller. */
+#define RT_NOALLOC_MAX_RAYS 65536
+int rt_trace_batch_noalloc(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64_t n,
+                           const double *in6, double *out6, double *opl, int32_t *status,
+                           double *hres, int32_t *nsteps, double *trans, void *stream);
+
 /* Render n_cams views of the room with the cloak (NULL = empty room) for each
    branch in pol_mask (bit 0 ordinary, bit 1 extraordinary), tracing each
    branch separately (Sect. 4): camera rays, cloak transit as in

@@ -1223,6 +1223,41 @@ void prof_end(hipStream_t s, ProfEvent &pe, bool on) {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Work table of NSEG segments of `cap` slots at the start of a device
+// buffer: SoA doubles (x, v, t, h, opl0, hres, wt), ints (nsteps, bounces,
+// status, kind), the 64-bit sample keys, the queue and sort keys, then the
+// counters. table_bytes(cap) is its size.
+constexpr size_t table_bytes(long long cap) {
+  return ((sizeof(double) * 11 * NSEG * cap + 255) & ~(size_t)255) +
+         ((sizeof(int) * 4 * NSEG * cap + 255) & ~(size_t)255) +
+         ((sizeof(long long) * NSEG * cap + 255) & ~(size_t)255) +
+         ((sizeof(int) * 2 * NSEG * cap + 255) & ~(size_t)255) +
+         ((sizeof(unsigned int) * C_COUNT + 255) & ~(size_t)255);
+}
+
+Table table_at(char *b, long long cap) {
+  const long long ns = (long long)NSEG * cap;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  const size_t o_d = take(sizeof(double) * 11 * ns);
+  const size_t o_i = take(sizeof(int) * 4 * ns);
+  const size_t o_k = take(sizeof(long long) * ns);
+  const size_t o_q = take(sizeof(int) * 2 * ns);
+  const size_t o_c = take(sizeof(unsigned int) * C_COUNT);
+  Table T{};
+  double *D = (double *)(b + o_d);
+  T.px = D; T.py = D + ns; T.pz = D + 2 * ns; T.vx = D + 3 * ns; T.vy = D + 4 * ns; T.vz = D + 5 * ns;
+  T.t = D + 6 * ns; T.h = D + 7 * ns; T.opl0 = D + 8 * ns; T.hres = D + 9 * ns; T.wt = D + 10 * ns;
+  int *I = (int *)(b + o_i);
+  T.nsteps = I; T.bounces = I + ns; T.status = I + 2 * ns; T.kind = I + 3 * ns;
+  T.key = (long long *)(b + o_k);
+  T.order = (int *)(b + o_q);
+  T.key0 = T.order + ns;
+  T.ctr = (unsigned int *)(b + o_c);
+  T.cap = cap;
+  return T;
+}
+
 void ws_free(Workspace &ws) {
   if (ws.base) {
     (void)hipDeviceSynchronize();
@@ -1247,14 +1282,8 @@ int ws_reserve(Workspace &ws, long long cap, long long codes_len, int ncam) {
   codes_len = std::max(codes_len, 1024LL);
   ncam = std::max(ncam, 16);
   ws_free(ws);
-  long long ns = (long long)NSEG * cap;
-  size_t off = 0;
+  size_t off = table_bytes(cap);
   auto take = [&](size_t b) { size_t o = off; off = align_up(off + b); return o; };
-  size_t o_d = take(sizeof(double) * 11 * ns);
-  size_t o_i = take(sizeof(int) * 4 * ns);
-  size_t o_k = take(sizeof(long long) * ns);
-  size_t o_q = take(sizeof(int) * 2 * ns);
-  size_t o_c = take(sizeof(unsigned int) * C_COUNT);
   size_t o_codes = take((size_t)codes_len);
   size_t o_topl = take(sizeof(float) * (size_t)codes_len);
   size_t o_twt = take(sizeof(float) * (size_t)codes_len);
@@ -1266,17 +1295,7 @@ int ws_reserve(Workspace &ws, long long cap, long long codes_len, int ncam) {
     return fail(RT_E_NOMEM, "hipMalloc of %zu bytes for the workspace failed", off);
   }
   char *b = (char *)p;
-  Table &T = ws.T;
-  double *D = (double *)(b + o_d);
-  T.px = D; T.py = D + ns; T.pz = D + 2 * ns; T.vx = D + 3 * ns; T.vy = D + 4 * ns; T.vz = D + 5 * ns;
-  T.t = D + 6 * ns; T.h = D + 7 * ns; T.opl0 = D + 8 * ns; T.hres = D + 9 * ns; T.wt = D + 10 * ns;
-  int *I = (int *)(b + o_i);
-  T.nsteps = I; T.bounces = I + ns; T.status = I + 2 * ns; T.kind = I + 3 * ns;
-  T.key = (long long *)(b + o_k);
-  T.order = (int *)(b + o_q);
-  T.key0 = T.order + ns;
-  T.ctr = (unsigned int *)(b + o_c);
-  T.cap = cap;
+  ws.T = table_at(b, cap);
   ws.base = p;
   ws.bytes = off;
   ws.cap = cap;
@@ -1701,6 +1720,44 @@ int render_surrogate(rt_model model, const rt_cloak_desc &desc, const RenderJob 
   return RT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free tracing: the work table of rt_trace_batch_noalloc lives in
+// a file-scope device array instead of the library workspace. Host code may
+// not use the array's name as a device address (it is a host-side stand-in);
+// its address on each device comes from hipGetSymbolAddress, taken once per
+// device with that device current and kept here.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_BYTES = table_bytes(RT_NOALLOC_MAX_RAYS);
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[MAX_DEVICES] = {nullptr};
+
+int noalloc_scratch(char **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(RT_E_DEVICE, "hipGetDevice failed");
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(RT_E_DEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(RT_E_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = (char *)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return RT_OK;
+}
+
+int check_trace_args(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64_t n, const double *in6,
+                     const double *out6, const double *opl, const int32_t *status, const double *trans);
+int enqueue_trace(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64_t n, const double *in6,
+                  double *out6, double *opl, int32_t *status, double *hres, int32_t *nsteps, double *trans,
+                  const Table &T, hipStream_t s, bool profile);
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1777,6 +1834,36 @@ int rt_release_workspace(void) {
 int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64_t n,
                    const double *in6, double *out6, double *opl, int32_t *status, double *hres,
                    int32_t *nsteps, double *trans, void *stream) {
+  int e = check_trace_args(cloak, opts, pol, n, in6, out6, opl, status, trans);
+  if (e || n == 0) return e;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  e = ws_reserve(g_ws, n, 0, 0);
+  if (e) return e;
+  return enqueue_trace(cloak, opts, pol, n, in6, out6, opl, status, hres, nsteps, trans, g_ws.T,
+                       (hipStream_t)stream, true);
+}
+
+int rt_trace_batch_noalloc(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64_t n,
+                           const double *in6, double *out6, double *opl, int32_t *status, double *hres,
+                           int32_t *nsteps, double *trans, void *stream) {
+  int e = check_trace_args(cloak, opts, pol, n, in6, out6, opl, status, trans);
+  if (e || n == 0) return e;
+  if (n > RT_NOALLOC_MAX_RAYS)
+    return fail(RT_E_INVALID, "rt_trace_batch_noalloc takes at most %d rays per call (got %lld)",
+                RT_NOALLOC_MAX_RAYS, (long long)n);
+  char *base = nullptr;
+  e = noalloc_scratch(&base);
+  if (e) return e;
+  return enqueue_trace(cloak, opts, pol, n, in6, out6, opl, status, hres, nsteps, trans,
+                       table_at(base, RT_NOALLOC_MAX_RAYS), (hipStream_t)stream, false);
+}
+
+}  // extern "C"
+
+namespace {
+
+int check_trace_args(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64_t n, const double *in6,
+                     const double *out6, const double *opl, const int32_t *status, const double *trans) {
   if (!cloak) return fail(RT_E_INVALID, "cloak handle is NULL");
   int e = check_opts(opts, cloak->d.r2, true);
   if (e) return e;
@@ -1788,11 +1875,15 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
   if (!in6 || !out6 || !opl || !status) return fail(RT_E_INVALID, "in6, out6, opl and status are required");
   if (trans && opts->precision != RT_PREC_FP64)
     return fail(RT_E_UNSUPPORTED, "the Eq. (12) weights are computed in FP64 only");
-  hipStream_t s = (hipStream_t)stream;
-  std::lock_guard<std::mutex> lk(g_ws_mu);
-  e = ws_reserve(g_ws, n, 0, 0);
-  if (e) return e;
-  const Table &T = g_ws.T;
+  return RT_OK;
+}
+
+// the rt_trace_batch pipeline on a work table of at least n slots per
+// segment (kernel launches only: no allocation, no synchronization)
+int enqueue_trace(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64_t n, const double *in6,
+                  double *out6, double *opl, int32_t *status, double *hres, int32_t *nsteps, double *trans,
+                  const Table &T, hipStream_t s, bool profile) {
+  int e = RT_OK;
   CloakP c = make_cloak(cloak->d);
   OptsP o = make_opts(*opts);
   int block = opts->block ? opts->block : 256;
@@ -1805,13 +1896,17 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
                      in6, out6, opl, status, hres, nsteps, trans);
   e = launch_err("entry launch");
   if (e) return e;
-  run_transit(c, o, T, block, refill, grid, s, true, fres);
+  run_transit(c, o, T, block, refill, grid, s, profile, fres);
   e = launch_err("transit launch");
   if (e) return e;
   hipLaunchKernelGGL(k_tb_finish, dim3(num_cu() * 8), dim3(256), 0, s, c, o, T, (long long)n, out6,
                      opl, status, hres, nsteps, trans);
   return launch_err("finish launch");
 }
+
+}  // namespace
+
+extern "C" {
 
 int rt_transit_exact(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts, int64_t n,
                      int64_t ld, const float *x6, const uint8_t *mask, float *y5, int32_t *status,

@@ -32,7 +32,8 @@ EXPORTED = ["rt_build_cloak", "rt_free_cloak", "rt_trace_batch", "rt_render", "r
             "rt_surrogate_set_scaling", "rt_surrogate_fit_scaling", "rt_surrogate_encode",
             "rt_surrogate_grad", "rt_surrogate_train", "rt_surrogate_forward",
             "rt_surrogate_calibrate", "rt_surrogate_get_map", "rt_surrogate_infer",
-            "rt_surrogate_save", "rt_surrogate_load", "rt_render_surrogate"]
+            "rt_surrogate_save", "rt_surrogate_load", "rt_render_surrogate", "rt_surrogate_step",
+            "rt_surrogate_get_state", "rt_surrogate_set_state", "rt_trace_batch_noalloc"]
 
 
 class RtError(RuntimeError):
@@ -112,6 +113,8 @@ def lib():
         L.rt_build_cloak.argtypes = [ctypes.POINTER(CloakDesc), ctypes.POINTER(vp)]
         L.rt_free_cloak.argtypes = [vp]
         L.rt_trace_batch.argtypes = [vp, ctypes.POINTER(TraceOpts), i32, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.rt_trace_batch_noalloc.argtypes = [vp, ctypes.POINTER(TraceOpts), i32, i64, vp, vp, vp, vp, vp, vp,
+                                             vp, vp]
         L.rt_render.argtypes = [vp, ctypes.POINTER(TraceOpts), ctypes.POINTER(Room),
                                 ctypes.POINTER(Camera), i32, i32, vp, ctypes.POINTER(RenderAux), vp]
         L.rt_render_multi.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(TraceOpts),
@@ -233,27 +236,35 @@ class Cloak:
             pass
 
 
+NOALLOC_MAX_RAYS = 65536
+
+
 def trace_batch(cloak: Cloak, opts: dict, pol: int, in6, with_aux: bool = True,
-                with_trans: bool = False):
+                with_trans: bool = False, out=None, noalloc: bool = False):
     """rt_trace_batch on a float64 CUDA tensor in6 of shape (6, n).
 
     Returns dict(out=(6, n) float64, opl, status int32[, hres, nsteps][, trans])
     of device tensors (asynchronous on the current stream). `trans` is the
-    Eq. (12) intensity weight of each ray (FP64 options only)."""
+    Eq. (12) intensity weight of each ray (FP64 options only). `out`: a dict
+    of preallocated tensors of those names to write into instead.
+    noalloc=True calls rt_trace_batch_noalloc (at most NOALLOC_MAX_RAYS rays;
+    the library allocates nothing)."""
     import torch
     assert in6.is_cuda and in6.dtype == torch.float64 and in6.dim() == 2 and in6.shape[0] == 6
     in6 = in6.contiguous()
     n = in6.shape[1]
     dev = in6.device
-    out = torch.empty((6, n), dtype=torch.float64, device=dev)
-    opl = torch.empty(n, dtype=torch.float64, device=dev)
-    st = torch.empty(n, dtype=torch.int32, device=dev)
-    hres = torch.empty(n, dtype=torch.float64, device=dev) if with_aux else None
-    ns = torch.empty(n, dtype=torch.int32, device=dev) if with_aux else None
-    tr = torch.empty(n, dtype=torch.float64, device=dev) if with_trans else None
+    pre = out or {}
+    out = pre.get("out", torch.empty((6, n), dtype=torch.float64, device=dev))
+    opl = pre.get("opl", torch.empty(n, dtype=torch.float64, device=dev))
+    st = pre.get("status", torch.empty(n, dtype=torch.int32, device=dev))
+    hres = pre.get("hres", torch.empty(n, dtype=torch.float64, device=dev)) if with_aux else None
+    ns = pre.get("nsteps", torch.empty(n, dtype=torch.int32, device=dev)) if with_aux else None
+    tr = pre.get("trans", torch.empty(n, dtype=torch.float64, device=dev)) if with_trans else None
     o = trace_opts(opts)
-    _check(lib().rt_trace_batch(cloak.handle, ctypes.byref(o), int(pol), int(n), _ptr(in6), _ptr(out),
-                                _ptr(opl), _ptr(st), _ptr(hres), _ptr(ns), _ptr(tr), _stream()))
+    fn = lib().rt_trace_batch_noalloc if noalloc else lib().rt_trace_batch
+    _check(fn(cloak.handle, ctypes.byref(o), int(pol), int(n), _ptr(in6), _ptr(out),
+              _ptr(opl), _ptr(st), _ptr(hres), _ptr(ns), _ptr(tr), _stream()))
     r = {"out": out, "opl": opl, "status": st}
     if with_aux:
         r["hres"] = hres
