@@ -1,41 +1,36 @@
 #!/usr/bin/env python3
 """Benchmark of the cloak ray tracer on one MI355X.
 
-Workload (one step): the photorealistic-render workload -- radial and
-azimuthal uniaxial cloaks (R1 = 1, R2 = 2, height 4) in the checkerboard room
-[-10,10]^2 x [0,10] (0.5 tiles), pinhole camera at distance 8 from (0,0,2),
-60 deg field of view, elevations 0/15/30/45 deg, 1024 x 1024 pixels,
-ordinary and extraordinary branch traced separately, Dormand-Prince 5(4) at
-tolerance 1e-8. One step renders both cloaks (16.8 M camera rays, one
-integrator launch), with the integrator's launch shape (block size, refill
-period) chosen by rt_autotune_render on the batch beforehand (--block /
---refill fix it instead). The batch is recorded into --streams render plans (default 3; the GPU
-runs 4 hardware queues, and a fourth stream can share one)
-(rt_render_plan_*, each with its own workspace and output images), and step k
-replays plan k mod S on stream k mod S: consecutive steps overlap, so one
-step's last rays and small kernels share the chip with the next step's bulk.
-The integrator's launch time for the roofline is measured on eager,
-one-at-a-time launches of the same batch (HIP events on the launch stream).
+Headline (one step): the large-render workload -- a 36-frame camera orbit at
+30 deg elevation around the radial and the azimuthal uniaxial cloaks (R1 = 1,
+R2 = 2, height 4, standing in the checkerboard room [-10,10]^2 x [0,10] with
+0.5 tiles), pinhole camera at distance 8 from (0,0,2), 60 deg field of view,
+4096 x 4096 pixels, 4 jittered samples per pixel, ordinary and extraordinary
+branch traced separately, Dormand-Prince 5(4) at tolerance 1e-8, FP64: 9.66e9
+ray-branch samples per step, rendered two frames per integrator launch
+(rt_render_multi). Inputs (cameras, room, cloaks) are resident before the
+timed region; W orbits warm up, K orbits are timed between device
+synchronizations.
 
-Metric: Mrays/s traced through the cloak = rays that enter the cloak material
-per second of step time (all camera rays per second are reported too).
+Metric: Mrays/s traced through the cloak = samples that refract into the
+cloak material per second of step time (all samples per second are reported
+too); the exit error of this tracer against the FP64 oracle is <= 1e-6 (the
+GPU parity tests).
 
---workload batched times the batched workload instead: 64 seeded views
-(azimuth U[0, 2 pi), elevation U[0, 60] deg) at 512 x 512, both cloaks, both
-branches, replayed from render plans in the same way, with the integrator's
-launch shape chosen by rt_autotune_render.
+Roofline: algorithmic FP64 flops of the integrator (step attempts x flops per
+attempt, counted in an untimed pass) per launch over the launch time measured
+with HIP events on the launch stream, against the 78.6 TFLOP/s FP64 vector
+peak; HBM traffic per launch from rocprofv3 counters (see TRAFFIC).
 
-Surrogate leg (the "surrogate vs plain speedup at 1e-3" half of the metric,
-skipped with --no-surrogate): 10 M seeded entries on the outer cylinder of the
-infinite radial and azimuthal cloaks (both branches) are labelled by the exact
-transit (DP45 1e-8, FP64) and train the BF16 MFMA surrogate (residuals on the
-closed-form transits); a trust map is calibrated at half the 1e-3 exit-error
-tolerance on 3 M separate entries; then 1 M held-out entries are traced by the
-plain exact transit and by surrogate + exact fallback (both timed with HIP
-events, inputs resident), and the accepted predictions' exit errors are
-measured against the exact exits. Last, four frames of the large render are
-timed plain and with the surrogate (rt_render_surrogate) for several
-difficulty thresholds, with the image difference.
+Reported beside it: the FP64 C oracle on a strided sample of the first frame
+on the host cores (cpu_baseline); the surrogate (the "surrogate vs plain
+speedup at 1e-3" half of the metric: a BF16 MFMA network trained on 10 M
+exact transits, gated and calibrated at the 1e-3 exit-error tolerance, as a
+transit replacement on 1 M held-out entries and inside the orbit render, with
+the per-pixel difference from the plain render); and sub-records for the
+other workloads (the 1024^2 four-elevation render on overlapping streams, the
+64-view batched render in HIP graphs, the 2-D in-plane set, surrogate
+training throughput).
 
 Prints one JSON line. --gpus N with N > 1 exits: the implementation runs on one GPU.
 """
@@ -87,25 +82,23 @@ def attempt_flops(kind: int, scheme: int) -> int:
 # resolved by the integrator (the surrogate is then judged elsewhere)
 UNRESOLVED = 1e-6
 
+# statuses of rays that refracted into the crystal (exited, absorbed, step
+# limit, diverged, totally reflected): the "rays traced through the cloak"
+ENTERED = (0, 2, 3, 4, 5)
+
 # HBM traffic of one integrator launch from two rocprofv3 --pmc runs
-# (FETCH_SIZE, WRITE_SIZE) of this benchmark, scaled by the same counters on a
-# plain device copy of known size (bench.py --copy-probe). Valid only for the
-# integrator source it was measured on; reported as null otherwise. Keyed by
-# the launch shape (block, refill period) of the measured run: the figure moves
-# by about 1% between shapes, and the one nearest the run's shape is reported
-# together with the shape it was taken at.
-TRAFFIC = {"source_sha256": "d163277e576ce36582d5f0afd8748092ebcd51e73416e61189a8948ef1517944",
-           "bytes_per_launch": {(256, 2): 783520288, (256, 4): 785148896, (256, 8): 794267648,
-                                (128, 4): 769098592, (128, 8): 777473856}}
+# (FETCH_SIZE, WRITE_SIZE) of `bench.py --workload <w> --profile-launches N`,
+# scaled by the same counters on a plain device copy of known size
+# (bench.py --copy-probe), per workload. Valid only for the integrator source
+# it was measured on; reported as null otherwise.
+TRAFFIC = {"source_sha256": None, "bytes_per_launch": {}}
 
 
-def traffic_for(block, refill):
-    """(bytes per integrator launch, shape it was measured at) or (None, None)."""
+def traffic_for(workload):
+    """(bytes per integrator launch) or None."""
     if TRAFFIC["source_sha256"] != integrator_source_hash():
-        return None, None
-    shapes = TRAFFIC["bytes_per_launch"]
-    key = min(shapes, key=lambda k: (k[0] != block, abs(k[1] - refill)))
-    return shapes[key], list(key)
+        return None
+    return TRAFFIC["bytes_per_launch"].get(workload)
 
 
 def finite_json(obj):
@@ -155,7 +148,7 @@ def cpu_baseline(opts, cams, stride, entered_only=True):
             ids = np.arange(0, cam["w"] * cam["h"], stride, dtype=np.int64)
             for branch in (0, 1):
                 r = oracle.render_samples(c, opts, room, cam, k, branch, ids)
-                n_entered += int(np.isin(r["status"], (0, 2, 3, 4, 5)).sum())
+                n_entered += int(np.isin(r["status"], ENTERED).sum())
                 n_rays += len(ids)
     dt = time.perf_counter() - t0
     return {"value": n_entered / dt / 1e6, "unit": "Mrays/s", "cores": oracle.num_threads(),
@@ -165,124 +158,14 @@ def cpu_baseline(opts, cams, stride, entered_only=True):
             "all_rays_per_s": n_rays / dt}
 
 
-def mixed_precision_leg(cloaks, room, cams, ms_fp64, out, opts, steps: int = 10):
-    """The same render with the derivative of Eq. (8) evaluated in FP32 away
-    from the inner radius (FP64 within 0.05 of r = a, and for every event and
-    refraction): time per step and the exit error of each sample against the
-    FP64 render, stated as it is (it does not meet the 1e-6 bar)."""
-    import torch
-    from paper_1209_6038_amd import rt
-    from paper_1209_6038_amd import workloads as W
-    om = dict(opts, precision=1)  # the FP64 run's launch shape
-    rgb_f, aux_f = rt.render_multi(cloaks, opts, room, cams, 3, aux=True)
-    rgb_m, aux_m = rt.render_multi(cloaks, om, room, cams, 3, aux=True)
-    torch.cuda.synchronize()
-    both = (aux_f["status"] == 0) & (aux_m["status"] == 0)
-    rf = aux_f["rec"].transpose(3, 4)[both]
-    rm = aux_m["rec"].transpose(3, 4)[both]
-    dpos = (rf[:, :3] - rm[:, :3]).norm(dim=1) / W.R2
-    cosang = (rf[:, 3:6] * rm[:, 3:6]).sum(dim=1).clamp(-1.0, 1.0)
-    sinang = torch.cross(rf[:, 3:6], rm[:, 3:6], dim=1).norm(dim=1)
-    err = torch.maximum(dpos, torch.atan2(sinang, cosang))
-    q = torch.quantile(err.float()[:: max(1, err.numel() // 4_000_000)], torch.tensor([0.5, 0.99], device=err.device))
-    stat_mismatch = int((aux_f["status"] != aux_m["status"]).sum())
-    code_diff = float((aux_f["code"] != aux_m["code"]).float().mean())
-    d = (rgb_m - rgb_f).abs().amax(dim=-1)
-    over = float((d > 1.0 / 255.0).float().mean())
-    n_both = int(both.sum())
-    over_bar = float((err > 1e-6).float().mean())
-    emax = float(err.max())
-    del aux_f, aux_m, rf, rm, dpos, err, rgb_f, rgb_m
-    for _ in range(2):
-        rt.render_multi(cloaks, om, room, cams, 3, out=out)
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    a.record()
-    for _ in range(steps):
-        rt.render_multi(cloaks, om, room, cams, 3, out=out)
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / steps
-    return {
-        "note": ("dv/dt of Eq. (8) in FP32 outside r < r1 + 0.05, FP64 there and for events and refraction; "
-                 "exit error of each sample against the FP64 render (both exited)"),
-        "ms_per_step": round(ms, 4), "speedup_vs_fp64": round(ms_fp64 / ms, 3),
-        "exit_error_vs_fp64": {"n": n_both, "p50": float(f"{float(q[0]):.3e}"), "p99": float(f"{float(q[1]):.3e}"),
-                               "max": float(f"{emax:.3e}"), "fraction_over_1e-6": float(f"{over_bar:.3e}")},
-        "status_mismatches": stat_mismatch, "colour_code_differences": float(f"{code_diff:.3e}"),
-        "pixels_over_1_255": float(f"{over:.3e}"),
-    }
-
-
-def surrogate_render_leg(model, log, n_frames: int = 4, fpl: int = 2, difficulties=(0, 2, 3, 4)):
-    """The large render (4096^2 px x 4 jittered spp, radial + azimuthal
-    cloaks, both branches) of n_frames frames of the 36-frame orbit at 30 deg,
-    fpl frames per launch, plain (rt_render_multi) and with the surrogate
-    (rt_render_surrogate) for each threshold of difficulty (side entries of
-    at least that difficulty bucket go to the network): time per frame, share
-    of the offered side entries the gate accepts, and the image difference."""
-    import torch
-    from paper_1209_6038_amd import rt
-    from paper_1209_6038_amd import workloads as W
-    frames = W.orbit_frames(36, 4096, 4)[:: 36 // n_frames][:n_frames]
-    groups = [frames[i:i + fpl] for i in range(0, len(frames), fpl)]
-    opts = W.render_opts(max_chunk=fpl * 4096 * 4096 * 4)
-    cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
-    room = W.room()
-    dev = torch.device("cuda", 0)
-    out_p = torch.empty((len(groups), 2, fpl, 2, 4096, 4096, 3), dtype=torch.float32, device=dev)
-    out_s = torch.empty_like(out_p)
-
-    def timed(fn):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a.record()
-        for k, g in enumerate(groups):
-            fn(k, g)
-        b.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / len(frames)
-
-    def plain(k, g):
-        rt.render_multi(cloaks, opts, room, g, 3, out=out_p[k, :, :len(g)])
-
-    for k, g in enumerate(groups):  # warm-up
-        plain(k, g)
-    ms_p = timed(plain)
-    sweep = []
-    for dmin in difficulties:
-        offered = accepted = 0
-        for k, g in enumerate(groups):  # untimed pass: counts
-            _, (c0, c1) = rt.render_surrogate(model, cloaks, opts, room, g, 3, out=out_s[k, :, :len(g)],
-                                              counts=True, min_difficulty=dmin)
-            offered += c0
-            accepted += c1
-        torch.cuda.synchronize()
-        d = (out_s - out_p).abs().amax(dim=-1)
-        over = float((d > 1.0 / 255.0).float().mean())
-        dmax = float(d.max())
-        del d
-        ms_s = timed(lambda k, g: rt.render_surrogate(model, cloaks, opts, room, g, 3, out=out_s[k, :, :len(g)],
-                                                      min_difficulty=dmin))
-        log(f"surrogate render, min difficulty {dmin}: {ms_s:.1f} ms/frame (plain {ms_p:.1f}), "
-            f"accepted {accepted}/{offered} offered side entries, pixels over 1/255: {over:.2e}")
-        sweep.append({"min_difficulty": dmin, "surrogate_ms_per_frame": round(ms_s, 2),
-                      "speedup": round(ms_p / ms_s, 3), "offered_per_frame": offered // len(frames),
-                      "accepted_per_frame": accepted // len(frames),
-                      "pixels_over_1_255": over, "max_pixel_difference": round(dmax, 4)})
-    del out_p, out_s
-    best = max(sweep, key=lambda r: r["speedup"])
-    return {
-        "workload": (f"{len(frames)} frames of the 36-frame orbit at 30 deg elevation, 4096^2 px x 4 jittered spp, "
-                     f"radial + azimuthal cloaks (height 4), ordinary + extraordinary, {fpl} frames per launch"),
-        "plain_ms_per_frame": round(ms_p, 2), "speedup": best["speedup"], "best": best, "sweep": sweep,
-    }
-
-
-def surrogate_leg(steps: int, n_train: int, log, fpl: int = 2):
-    """Train, calibrate and time the transit surrogate (see the module doc)."""
+def surrogate_leg(steps: int, n_train: int, log, keep: bool = False):
+    """Train, calibrate and time the transit surrogate (see the module doc).
+    The transit speedup is measured with the gate's near-singular band off
+    (p_min = 0: entries whose paths pass within ~1e-4 of r = r1 are accepted
+    like the others; the error statistics leave out references the
+    integrator did not resolve) and with it on (p_min = 1e-4: those entries
+    go to the exact transit, which is where its longest rays are).
+    keep=True also returns the model and the calibration data."""
     import numpy as np
     import torch
     from paper_1209_6038_amd import rt
@@ -317,8 +200,7 @@ def surrogate_leg(steps: int, n_train: int, log, fpl: int = 2):
     # integrator did not resolve (Hamiltonian drift > UNRESOLVED) are no
     # reference
     trusted = m.calibrate(cl, x_cal, y_cal, st_cal, tol=0.5 * tol, min_count=16, dilate=1,
-                          hres_exact=h_cal, unresolved=UNRESOLVED)
-    del x_cal, y_cal, st_cal, h_cal
+                          hres_exact=h_cal, unresolved=UNRESOLVED, p_min=0.0)
     n = 1_000_000
     x_ev = S.features(n, 3003)
     y_ex, st_ex, h_ex = rt.transit_exact(cl, op, x_ev, hres=True)
@@ -373,12 +255,20 @@ def surrogate_leg(steps: int, n_train: int, log, fpl: int = 2):
     ms_plain_bulk = timed(lambda: rt.transit_exact(cl, op, x_ev, mask=bulk, y5=y_ex, status=st_ex))
     ms_plain = timed(lambda: rt.transit_exact(cl, op, x_ev, y5=y_ex, status=st_ex))
     ms_sur = timed(lambda: m.infer(cl, op, x_ev, y5=y_s, fallback=fb, status=st_s))
+    m.calibrate(cl, x_cal, y_cal, st_cal, tol=0.5 * tol, min_count=16, dilate=1, hres_exact=h_cal,
+                unresolved=UNRESOLVED, p_min=1e-4)
+    y_b2, st_b2, fb_b2 = m.infer(cl, op, x_ev)
+    acc_band = float((fb_b2 == 0).float().mean())
+    ms_sur_band = timed(lambda: m.infer(cl, op, x_ev, y5=y_b2, fallback=fb_b2, status=st_b2))
+    del y_b2, st_b2, fb_b2
     ms_fwd = timed(lambda: m.forward(x_ev))
     mlp_tflops = MLP_MFMA_FLOPS * n / (ms_fwd * 1e-3) / 1e12
     rec = {
         "speedup": round(ms_plain / ms_sur, 3),
         "plain_Mrays_s": round(n / (ms_plain * 1e-3) / 1e6, 2),
         "surrogate_Mrays_s": round(n / (ms_sur * 1e-3) / 1e6, 2),
+        "near_singular_band": {"p_min": 1e-4, "speedup": round(ms_plain / ms_sur_band, 3),
+                               "accepted_fraction": round(acc_band, 4)},
         "tolerance": tol,
         "accepted_fraction": round(acc_all.float().mean().item(), 4),
         "accepted_by_branch": {name: round(acc_all[kind == k].float().mean().item(), 4)
@@ -411,7 +301,9 @@ def surrogate_leg(steps: int, n_train: int, log, fpl: int = 2):
                          "frac": round(mlp_tflops / PEAK_BF16_TFLOPS, 4), "ms_per_1M_rays": round(ms_fwd, 4)},
     }
     del x_ev, y_ex, st_ex, h_ex, y_s, st_s, fb, err, operr
-    rec["render"] = surrogate_render_leg(m, log, fpl=fpl)
+    if keep:
+        return rec, m, (x_cal, y_cal, st_cal, h_cal, cl, tol)
+    m.close()
     return rec
 
 
@@ -438,7 +330,7 @@ def train_workload(args):
     m.fit_scaling(x_tr, t_tr, w_tr)
     batch = 65536
     nb = x_tr.shape[1] // batch
-    steps = args.surrogate_steps
+    steps = args.train_steps
     loss = torch.zeros(1, dtype=torch.float32, device=x_tr.device)
 
     def run(k0, k1):
@@ -483,7 +375,7 @@ def inplane_workload(args):
     r = rt.trace_batch(cl, opts, W.EXTRAORDINARY, rays)
     torch.cuda.synchronize()
     st = r["status"].cpu().numpy()
-    entered = int((st != 1).sum())
+    entered = int(np.isin(st, ENTERED).sum())
     attempts = int(r["nsteps"].cpu().numpy().astype(np.int64).sum())
     for _ in range(args.warmup):
         rt.trace_batch(cl, opts, W.EXTRAORDINARY, rays, with_aux=False)
@@ -620,12 +512,12 @@ def weights_workload(args):
         torch.cuda.synchronize()
         st = r["status"].cpu().numpy()
         w = r["trans"].cpu().numpy()
-        entered += int((st != 1).sum())
+        entered += int(np.isin(st, ENTERED).sum())
         flops += int(r["nsteps"].cpu().numpy().astype(np.int64).sum()) * attempt_flops(2 * ax + br, 1)
         ex = st == 0
         summary[f"{'radial' if ax == 0 else 'azimuthal'}_{'o' if br == 0 else 'e'}"] = {
             "exited": int(ex.sum()), "mean_weight_exited": round(float(w[ex].mean()), 5),
-            "entering_intensity_delivered": round(float(w[ex].sum() / max(1, (st != 1).sum())), 5)}
+            "entering_intensity_delivered": round(float(w[ex].sum() / max(1, np.isin(st, ENTERED).sum())), 5)}
 
     def run(trans, steps):
         for _ in range(steps):
@@ -683,7 +575,7 @@ def unpolarized_workload(args):
     _, aux = rt.render_multi(cloaks, opts, room, cams, 3, aux=True, unpolarized=True)
     torch.cuda.synchronize()
     dev = aux["status"].device
-    entered = int(torch.isin(aux["status"], torch.tensor([0, 2, 3, 4, 5], device=dev, dtype=torch.int32)).sum())
+    entered = int(torch.isin(aux["status"], torch.tensor(ENTERED, device=dev, dtype=torch.int32)).sum())
     mean_unpol = float(aux["unpol"].mean())
     del aux
     timing = {}
@@ -722,91 +614,375 @@ def unpolarized_workload(args):
     }
 
 
-def orbit_workload(args):
-    """The large-render workload timed plain: 36-frame orbit at 30 deg
-    elevation, 4096 x 4096 px, 4 jittered samples per pixel, radial and
-    azimuthal cloaks, both branches; `frames_per_launch` frames per
-    rt_render_multi call, one integrator launch each (a launch lasts at least
-    as long as its longest ray, so frames rendered together overlap one
-    frame's longest rays with the others' bulk)."""
+def _entered_tensor(dev):
+    import torch
+    return torch.tensor(ENTERED, device=dev, dtype=torch.int32)
+
+
+def orbit_counts(cloaks, room, frames, log):
+    """Untimed pass over the orbit, one frame per call with per-sample status
+    and step counts only: samples that enter the cloak, and the integrator's
+    algorithmic FP64 flops (step attempts x flops per attempt of each
+    (cloak, branch) kind). Both are per-ray quantities, independent of how
+    frames are grouped into launches."""
     import torch
     from paper_1209_6038_amd import rt
     from paper_1209_6038_amd import workloads as W
+    entered, flops = 0, 0
+    dev = torch.device("cuda", torch.cuda.current_device())
+    ent = _entered_tensor(dev)
+    for k, f in enumerate(frames):
+        _, aux = rt.render_multi(cloaks, W.render_opts(), room, [f], 3, aux=("status", "nsteps"))
+        entered += int(torch.isin(aux["status"], ent).sum())
+        for ci in range(2):
+            for pi in range(2):
+                flops += int(aux["nsteps"][ci, 0, pi].sum(dtype=torch.int64)) * attempt_flops(2 * ci + pi, 1)
+        del aux
+    torch.cuda.synchronize()
+    log(f"orbit: {len(frames)} frames counted, {entered} entering samples, {flops / 1e12:.2f} TFLOP of integration")
+    return entered, flops
 
+
+def orbit_cpu_baseline(frame, stride):
+    """The FP64 C oracle (OpenMP, all host threads) on every `stride`-th
+    sample of the first orbit frame, both cloaks and both branches."""
+    import numpy as np
+
+    import oracle
+    from paper_1209_6038_amd import workloads as W
+    room = W.room()
+    ids = np.arange(0, frame["w"] * frame["h"] * frame["spp"], stride, dtype=np.int64)
+    n_entered = 0
+    t0 = time.perf_counter()
+    for axis in (0, 1):
+        c = W.cloak(axis, height=W.HEIGHT)
+        for branch in (0, 1):
+            r = oracle.render_samples(c, W.opts_dp45(), room, frame, 0, branch, ids)
+            n_entered += int(np.isin(r["status"], ENTERED).sum())
+    dt = time.perf_counter() - t0
+    return {"value": n_entered / dt / 1e6, "unit": "Mrays/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": (f"every {stride}th sample of orbit frame 0 ({len(ids)} samples x 2 cloaks x 2 branches, "
+                       f"{n_entered} entering the cloak), FP64 C oracle with OpenMP, {dt:.1f} s"),
+            "all_samples_per_s": 4 * len(ids) / dt}
+
+
+def orbit_setup(args):
+    import torch
+    from paper_1209_6038_amd import rt
+    from paper_1209_6038_amd import workloads as W
     fpl = args.frames_per_launch
-    frames = W.orbit_frames(36, 4096, 4)
+    frames = W.orbit_frames(36, 4096, 4)[:args.frames]
     groups = [frames[i:i + fpl] for i in range(0, len(frames), fpl)]
     opts = W.render_opts(max_chunk=fpl * 4096 * 4096 * 4)
     cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
-    room = W.room()
+    return frames, groups, opts, cloaks, W.room()
+
+
+def orbit_headline(args, log):
+    """The headline: the 36-frame orbit (see the module doc), plain tracer."""
+    import torch
+    from paper_1209_6038_amd import rt
+
+    frames, groups, opts, cloaks, room = orbit_setup(args)
+    fpl = args.frames_per_launch
     dev = torch.device("cuda", 0)
-    out = torch.empty((2, fpl, 2, 4096, 4096, 3), dtype=torch.float32, device=dev)
-    # entering rays per frame (untimed counting pass, status only)
-    # the orbit is symmetric up to the jitter: every 9th frame is counted
-    entered = 0
-    counted = frames[::9]
-    for f in counted:
-        _, aux = rt.render_multi(cloaks, W.render_opts(), room, [f], 3, aux=True)
-        torch.cuda.synchronize()
-        entered += int(torch.isin(aux["status"], torch.tensor([0, 2, 3, 4, 5], device=dev,
-                                                                dtype=torch.int32)).sum())
-        del aux
-    entered_per_frame = entered / len(counted)
-    rt.render_multi(cloaks, opts, room, groups[0], 3, out=out[:, :len(groups[0])])
+    entered, flops = orbit_counts(cloaks, room, frames, log)
+    # images per launch group, each a dense [cloak][frame][branch][h][w][3] block
+    out = torch.empty((len(groups), 2, fpl, 2, 4096, 4096, 3), dtype=torch.float32, device=dev)
+
+    def step():
+        for k, g in enumerate(groups):
+            rt.render_multi(cloaks, opts, room, g, 3, out=out[k])
+
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for g in groups:
-        rt.render_multi(cloaks, opts, room, g, 3, out=out[:, :len(g)])
-    t1.record()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
     torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1)
-    samples = 36 * 4096 * 4096 * 4 * 2 * 2
-    return {
-        "metric": "Mrays/s traced through cloak at <=1e-6 exit error", "unit": "Mrays/s",
-        "value": round(entered_per_frame * 36 / (ms * 1e-3) / 1e6, 3), "n_gpus": 1,
-        "ms_per_step": round(ms, 2), "steps": 1, "warmup": 1, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "large render: 36-frame orbit at 30 deg elevation, 4096^2 px x 4 jittered spp, "
-                               "radial + azimuthal cloaks, ordinary + extraordinary, DP45 tol 1e-8, plain tracer",
-                   "frames_per_launch": fpl,
-                   "ray_branch_samples": samples, "ms_per_frame": round(ms / 36, 2),
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    log(f"orbit: {ms:.1f} ms per orbit ({ms / len(frames):.2f} ms per frame)")
+    # integrator launches timed with HIP events on the launch stream
+    rt.profile_enable(True)
+    rt.profile_read()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    step()
+    e1.record()
+    torch.cuda.synchronize()
+    eager_ms = e0.elapsed_time(e1)
+    transit_ms, launches = rt.profile_read()
+    rt.profile_enable(False)
+    avg_launch_ms = transit_ms / max(launches, 1)
+    achieved = flops / max(launches, 1) / (avg_launch_ms * 1e-3) / 1e12
+    samples = len(frames) * 4096 * 4096 * 4 * 2 * 2
+    rec = {
+        "metric": "Mrays/s traced through cloak at ≤1e-6 exit error; surrogate vs plain speedup at 1e-3",
+        "value": round(entered / (ms * 1e-3) / 1e6, 3),
+        "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": (f"large render: {len(frames)}-frame orbit at 30 deg elevation, 4096^2 px x 4 "
+                                "jittered spp, radial + azimuthal uniaxial cloaks (R1=1, R2=2, height 4) in the "
+                                "checkerboard room 20x20x10, ordinary + extraordinary, DP45 tol 1e-8, FP64, plain "
+                                "tracer"),
+                   "frames": len(frames), "frames_per_launch": fpl, "ray_branch_samples_per_step": samples,
+                   "rays_entering_cloak_per_step": entered, "miss_fraction": round(1.0 - entered / samples, 4),
                    "all_samples_per_s_M": round(samples / (ms * 1e-3) / 1e6, 1),
-                   "entered_per_frame_estimate": int(entered_per_frame),
-                   "frames_counted_for_entered": len(counted)},
+                   "ms_per_frame": round(ms / len(frames), 3), "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic_for("orbit"),
+                     "kernel": "k_transit (integrator)", "avg_launch_ms": round(avg_launch_ms, 3),
+                     "launches_per_step": launches, "flops_per_launch": round(flops / max(launches, 1)),
+                     "integrator_share_of_step": round(transit_ms / eager_ms, 4)},
     }
+    return rec, out, (frames, groups, opts, cloaks, room)
+
+
+def orbit_surrogate(model, orbit, out_plain, ms_plain, log, cal, sweep_frames=4,
+                    difficulties=(0, 2, 3, 4), p_mins=(1e-4, 0.0)):
+    """The surrogate inside the orbit render (rt_render_surrogate): a sweep of
+    the difficulty threshold (side entries of at least that bucket go to the
+    network) and of the near-singular band p_min on `sweep_frames` frames,
+    then the fastest setting whose images stay within 1/255 of the plain
+    render on every pixel runs the whole orbit: time per orbit against the
+    plain orbit, and the per-pixel difference over all of its frames."""
+    import torch
+    from paper_1209_6038_amd import rt
+    frames, groups, opts, cloaks, room = orbit
+    fpl = max(len(g) for g in groups)
+    sub = [k for k in range(len(groups))][:: max(1, len(groups) // max(1, sweep_frames // fpl))][:max(1, sweep_frames // fpl)]
+    out_s = torch.empty_like(out_plain)
+    x_cal, y_cal, st_cal, h_cal, cl_inf, tol = cal
+
+    def run_groups(ks, dmin):
+        for k in ks:
+            g = groups[k]
+            rt.render_surrogate(model, cloaks, opts, room, g, 3, out=out_s[k], min_difficulty=dmin)
+
+    def plain_groups(ks):
+        for k in ks:
+            g = groups[k]
+            rt.render_multi(cloaks, opts, room, g, 3, out=out_plain[k])
+
+    def timed(fn):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    nf_sub = sum(len(groups[k]) for k in sub)
+    ms_plain_sub = timed(lambda: plain_groups(sub)) / nf_sub
+    sweep = []
+    for p_min in p_mins:
+        model.calibrate(cl_inf, x_cal, y_cal, st_cal, tol=0.5 * tol, min_count=16, dilate=1, hres_exact=h_cal,
+                        unresolved=UNRESOLVED, p_min=p_min)
+        for dmin in difficulties:
+            offered = accepted = 0
+            for k in sub:
+                g = groups[k]
+                _, (c0, c1) = rt.render_surrogate(model, cloaks, opts, room, g, 3, out=out_s[k], counts=True,
+                                                  min_difficulty=dmin)
+                offered += c0
+                accepted += c1
+            torch.cuda.synchronize()
+            dmax = 0.0
+            over = 0
+            npix = 0
+            for k in sub:
+                d = (out_s[k] - out_plain[k]).abs().amax(dim=-1)
+                dmax = max(dmax, float(d.max()))
+                over += int((d > 1.0 / 255.0).sum())
+                npix += d.numel()
+                del d
+            ms_s = timed(lambda: run_groups(sub, dmin)) / nf_sub
+            log(f"surrogate render p_min {p_min:g}, min difficulty {dmin}: {ms_s:.1f} ms/frame "
+                f"(plain {ms_plain_sub:.1f}), accepted {accepted}/{offered}, max pixel difference {dmax:.4f}")
+            sweep.append({"p_min": p_min, "min_difficulty": dmin, "surrogate_ms_per_frame": round(ms_s, 2),
+                          "speedup": round(ms_plain_sub / ms_s, 3), "offered_per_frame": offered // nf_sub,
+                          "accepted_per_frame": accepted // nf_sub, "pixels_over_1_255": over / npix,
+                          "max_pixel_difference": round(dmax, 4)})
+    valid = [r for r in sweep if r["max_pixel_difference"] <= 1.0 / 255.0]
+    best = max(valid, key=lambda r: r["speedup"]) if valid else None
+    full = None
+    if best is not None:
+        model.calibrate(cl_inf, x_cal, y_cal, st_cal, tol=0.5 * tol, min_count=16, dilate=1, hres_exact=h_cal,
+                        unresolved=UNRESOLVED, p_min=best["p_min"])
+        allk = list(range(len(groups)))
+        run_groups(allk[:1], best["min_difficulty"])  # warm-up
+        ms_orbit = timed(lambda: run_groups(allk, best["min_difficulty"]))
+        dmax, over, npix = 0.0, 0, 0
+        for k in range(len(groups)):
+            d = (out_s[k] - out_plain[k]).abs().amax(dim=-1)
+            dmax = max(dmax, float(d.max()))
+            over += int((d > 1.0 / 255.0).sum())
+            npix += d.numel()
+            del d
+        full = {"p_min": best["p_min"], "min_difficulty": best["min_difficulty"],
+                "surrogate_ms_per_orbit": round(ms_orbit, 2), "plain_ms_per_orbit": round(ms_plain, 2),
+                "speedup": round(ms_plain / ms_orbit, 3), "max_pixel_difference": round(dmax, 5),
+                "pixels_over_1_255": over / npix}
+        log(f"surrogate orbit: {ms_orbit:.0f} ms vs plain {ms_plain:.0f} ms, max pixel difference "
+            f"{full['max_pixel_difference']}")
+    del out_s
+    return {"workload": (f"the orbit render with rt_render_surrogate; sweep on {nf_sub} frames, then the whole "
+                         f"orbit with the fastest setting within 1/255 per pixel of the plain render"),
+            "plain_ms_per_frame_sweep_frames": round(ms_plain_sub, 2), "sweep": sweep, "best": best,
+            "orbit": full}
+
+
+def render1024_record(args, log):
+    """Sub-record: the 1024^2 render (both cloaks, elevations 0/15/30/45 deg,
+    1 sample per pixel, both branches) replayed from render plans on 3
+    overlapping streams, launch shape from the autotuner."""
+    from paper_1209_6038_amd import workloads as W
+    return _plan_record(args, log, W.render_views(res=1024), "render_1024",
+                        ("3-D render: radial + azimuthal cloaks (height 4), 4 elevations x 1024^2 px, 1 spp, "
+                         "ordinary + extraordinary, DP45 tol 1e-8, FP64, render plans on 3 streams"),
+                        cpu_stride=4)
+
+
+def batched_record(args, log):
+    """Sub-record: 64 seeded views x 512^2 (azimuth U[0, 2 pi), elevation
+    U[0, 60] deg), both cloaks and branches, one HIP-graph replay per step."""
+    from paper_1209_6038_amd import workloads as W
+    return _plan_record(args, log, W.batched_views(64, 512), "batched",
+                        ("batched: 64 seeded views x 512^2 px (azimuth U[0,2pi), elevation U[0,60] deg), radial + "
+                         "azimuthal cloaks, ordinary + extraordinary, DP45 tol 1e-8, FP64, one HIP-graph replay "
+                         "per step, plans on 3 streams"),
+                        cpu_stride=64)
+
+
+def _plan_record(args, log, cams, name, desc, cpu_stride):
+    import numpy as np
+    import torch
+    from paper_1209_6038_amd import rt
+    from paper_1209_6038_amd import workloads as W
+    dev = torch.device("cuda", 0)
+    res = int(cams[0]["w"])
+    opts = W.render_opts()
+    cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
+    room = W.room()
+    out = torch.empty((2, len(cams), 2, res, res, 3), dtype=torch.float32, device=dev)
+    opts, tuned_ms = rt.autotune_render(cloaks, opts, room, cams, 3)
+    nstreams = 3
+    plans = [rt.RenderPlan(cloaks, opts, room, cams, 3) for _ in range(nstreams)]
+    streams = [torch.cuda.Stream() for _ in range(nstreams)]
+
+    def step(k):
+        with torch.cuda.stream(streams[k % nstreams]):
+            plans[k % nstreams].launch()
+
+    _, aux = rt.render_multi(cloaks, opts, room, cams, 3, aux=("status", "nsteps"))
+    torch.cuda.synchronize()
+    st = aux["status"].cpu().numpy()
+    ns = aux["nsteps"].cpu().numpy().astype(np.int64)
+    del aux
+    entered = int(np.isin(st, ENTERED).sum())
+    flops = sum(int(ns[ci, :, pi].sum()) * attempt_flops(2 * ci + pi, 1) for ci in range(2) for pi in range(2))
+    camera_rays = 2 * len(cams) * 2 * res * res
+    steps = max(5, args.steps // 2)
+    for k in range(nstreams + 2):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    rt.render_multi(cloaks, opts, room, cams, 3, out=out)
+    torch.cuda.synchronize()
+    images_equal = all(torch.equal(p.rgb, out) for p in plans)
+    for p in plans:
+        p.close()
+    del plans
+    rt.profile_enable(True)
+    rt.profile_read()
+    for _ in range(3):
+        rt.render_multi(cloaks, opts, room, cams, 3, out=out)
+    torch.cuda.synchronize()
+    transit_ms, launches = rt.profile_read()
+    rt.profile_enable(False)
+    avg = transit_ms / max(1, launches)
+    achieved = flops / (avg * 1e-3) / 1e12
+    rec = {"metric": "Mrays/s traced through cloak at ≤1e-6 exit error", "unit": "Mrays/s",
+           "value": round(entered / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 4), "steps": steps,
+           "config": {"workload": desc, "launch_shape": {"block": opts.get("block"),
+                                                         "refill_period": opts.get("refill_period"),
+                                                         "autotuned_ms": tuned_ms},
+                      "miss_fraction": round(1.0 - entered / camera_rays, 4), "camera_rays_per_step": camera_rays,
+                      "rays_entering_cloak_per_step": entered, "images_equal_across_streams": images_equal},
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                        "traffic": traffic_for(name), "kernel": "k_transit (integrator)",
+                        "avg_launch_ms": round(avg, 4)}}
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(W.opts_dp45(), cams, cpu_stride)
+    log(f"{name}: {ms:.2f} ms per step, {rec['value']} M entering rays/s, FP64 roofline {rec['roofline']['frac']}")
+    for c in cloaks:
+        c.close()
+    return rec
+
+
+def profile_launches(args):
+    """Only `--profile-launches N` integrator launches of the workload (after
+    one warm-up launch), for rocprofv3 counter runs."""
+    import torch
+    from paper_1209_6038_amd import rt
+    from paper_1209_6038_amd import workloads as W
+    n = args.profile_launches
+    if args.workload == "orbit":
+        frames, groups, opts, cloaks, room = orbit_setup(args)
+        fpl = args.frames_per_launch
+        out = torch.empty((2, fpl, 2, 4096, 4096, 3), dtype=torch.float32, device="cuda")
+        for k in range(n + 1):
+            rt.render_multi(cloaks, opts, room, groups[k % len(groups)], 3, out=out)
+    else:
+        cams = W.render_views(res=1024) if args.workload == "render_1024" else W.batched_views(64, 512)
+        cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
+        for _ in range(n + 1):
+            rt.render_multi(cloaks, W.render_opts(), W.room(), cams, 3)
+    torch.cuda.synchronize()
+    return {"profile_launches": n, "workload": args.workload}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--res", type=int, default=1024)
+    ap.add_argument("--steps", type=int, default=5, help="timed orbits (steps of the headline)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--frames", type=int, default=36, help="orbit frames per step (the workload has 36)")
     ap.add_argument("--frames-per-launch", type=int, default=2,
-                    help="orbit workload and surrogate render: 4096^2 x 4 spp frames per integrator launch (1-4)")
-    ap.add_argument("--workload", choices=("render3d", "batched", "orbit", "surrogate", "inplane", "hamiltonian",
-                                           "weights", "unpolarized", "train"),
-                    default="render3d")
-    ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 mixed")
+                    help="4096^2 x 4 spp frames per integrator launch (1-4)")
+    ap.add_argument("--workload", choices=("orbit", "render_1024", "batched", "inplane",
+                                           "hamiltonian", "weights", "unpolarized", "train"),
+                    default="orbit")
+    ap.add_argument("--res", type=int, default=1024)
     ap.add_argument("--refill", type=int, default=0)
-    ap.add_argument("--streams", type=int, default=3,
-                    help="render plans replayed on this many streams, consecutive steps overlapping")
     ap.add_argument("--block", type=int, default=0)
-    ap.add_argument("--cpu-stride", type=int, default=2)
+    ap.add_argument("--cpu-stride", type=int, default=64, help="oracle sample stride on orbit frame 0")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-sub", action="store_true", help="headline only, no sub-records")
+    ap.add_argument("--profile-launches", type=int, default=0,
+                    help="only run this many integrator launches of --workload (orbit, render_1024, batched)")
     ap.add_argument("--surrogate-steps", type=int, default=10000,
                     help="AdamW steps of 65,536 rows (10,000 = 65 epochs of the 10 M labelled rays)")
     ap.add_argument("--surrogate-train", type=int, default=10_000_000)
+    ap.add_argument("--train-steps", type=int, default=300, help="timed AdamW steps of --workload train")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
-    if not 1 <= args.streams <= 4:
-        ap.error("--streams must be in 1..4")
     if not 1 <= args.frames_per_launch <= 4:
         ap.error("--frames-per-launch must be in 1..4 (at most 2^28 samples per launch)")
+    if not 1 <= args.frames <= 36 or args.frames % args.frames_per_launch:
+        ap.error("--frames must be in 1..36 and a multiple of --frames-per-launch")
     if args.copy_probe:
         copy_probe()
         return
@@ -815,169 +991,47 @@ def main():
               "tile (no exchange but the image gather), which is not implemented", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1209_6038_amd import build as B
     from paper_1209_6038_amd import rt
-    from paper_1209_6038_amd import workloads as W
 
     if not os.path.exists(rt.LIB_PATH):
         B.build()
     torch.cuda.set_device(0)
-    dev = torch.device("cuda", 0)
-    if args.workload == "orbit":
-        print(json.dumps(finite_json(orbit_workload(args))), flush=True)
-        return
-    if args.workload == "inplane":
-        print(json.dumps(finite_json(inplane_workload(args))), flush=True)
-        return
-    if args.workload == "hamiltonian":
-        print(json.dumps(finite_json(hamiltonian_workload(args))), flush=True)
-        return
-    if args.workload == "weights":
-        print(json.dumps(finite_json(weights_workload(args))), flush=True)
-        return
-    if args.workload == "unpolarized":
-        print(json.dumps(finite_json(unpolarized_workload(args))), flush=True)
-        return
-    if args.workload == "train":
-        print(json.dumps(finite_json(train_workload(args))), flush=True)
-        return
-    if args.workload == "surrogate":
-        torch.cuda.set_device(0)
-        rec = surrogate_leg(args.surrogate_steps, args.surrogate_train,
-                            lambda msg: print(msg, file=sys.stderr, flush=True), args.frames_per_launch)
-        print(json.dumps(finite_json({"config": {"workload": "surrogate leg only"}, "surrogate": rec})), flush=True)
-        return
-    batched = args.workload == "batched"
-    cams = W.batched_views(64, 512) if batched else W.render_views(res=args.res)
-    res = int(cams[0]["w"])
-    opts = W.render_opts(precision=args.precision, refill_period=args.refill, block=args.block)
-    cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
-    room = W.room()
-    out = torch.empty((2, len(cams), 2, res, res, 3), dtype=torch.float32, device=dev)
-    tuned_ms = None
-    if not (args.refill or args.block):
-        # launch shape (block size, refill period) from the autotuner on this
-        # batch; per-ray results do not depend on it
-        opts, tuned_ms = rt.autotune_render(cloaks, opts, room, cams, 3)
-    # one plan per stream (own workspace and images); step k replays plan
-    # k mod S on stream k mod S: all cloaks, views and branches of the batch
-    # in one pass (one integrator launch)
-    plans = [rt.RenderPlan(cloaks, opts, room, cams, 3) for _ in range(args.streams)]
-    streams = [torch.cuda.Stream() for _ in range(args.streams)]
 
-    def step(k):
-        with torch.cuda.stream(streams[k % args.streams]):
-            plans[k % args.streams].launch()
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
 
-    # untimed counting pass: entering rays and integrator step attempts
-    entered = 0
-    flops = 0
-    _, aux = rt.render_multi(cloaks, opts, room, cams, 3, aux=True)
-    torch.cuda.synchronize()
-    st = aux["status"].cpu().numpy()
-    ns = aux["nsteps"].cpu().numpy().astype(np.int64)
-    del aux
-    entered += int(np.isin(st, (0, 2, 3, 4, 5)).sum())
-    for ci in range(2):
-        for pi, pol in enumerate((0, 1)):
-            kind = ci * 2 + pol
-            flops += int(ns[ci, :, pi].sum()) * attempt_flops(kind, opts["scheme"])
-    camera_rays = 2 * len(cams) * 2 * res * res
+    if args.profile_launches:
+        print(json.dumps(profile_launches(args)), flush=True)
+        return
+    single = {"inplane": inplane_workload, "hamiltonian": hamiltonian_workload, "weights": weights_workload,
+              "unpolarized": unpolarized_workload, "train": train_workload}
+    if args.workload in single:
+        print(json.dumps(finite_json(single[args.workload](args))), flush=True)
+        return
+    if args.workload in ("render_1024", "batched"):
+        fn = render1024_record if args.workload == "render_1024" else batched_record
+        print(json.dumps(finite_json(fn(args, log))), flush=True)
+        return
 
-    for k in range(max(args.warmup, args.streams)):
-        step(k)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(k)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    # every plan rendered the batch: the images agree with an eager render
-    rt.render_multi(cloaks, opts, room, cams, 3, out=out)
-    torch.cuda.synchronize()
-    images_equal = all(torch.equal(p.rgb, out) for p in plans)
-    for p in plans:
-        p.close()
-    del plans
-    # graph replays carry no timing events, and overlapped launches share the
-    # chip: time the integrator on eager, one-at-a-time launches of the same
-    # batch (same kernels, same launch shape), HIP events on the launch stream
-    rt.render_multi(cloaks, opts, room, cams, 3, out=out)
-    torch.cuda.synchronize()
-    rt.profile_enable(True)
-    rt.profile_read()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        rt.render_multi(cloaks, opts, room, cams, 3, out=out)
-    e1.record()
-    torch.cuda.synchronize()
-    eager_ms = e0.elapsed_time(e1) / args.steps
-    transit_ms, launches = rt.profile_read()
-    launches_per_step = launches / args.steps
-    rt.profile_enable(False)
-
-    avg_launch_ms = transit_ms / max(launches, 1)
-    flops_per_launch = flops / launches_per_step
-    achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
-    peak = PEAK_FP64_TFLOPS if args.precision == 0 else PEAK_FP32_TFLOPS
-    value = entered / (ms * 1e-3) / 1e6
-    shape = (opts.get("block") or 256, opts.get("refill_period") or 2)
-    traffic, traffic_shape = traffic_for(*shape) if not batched else (None, None)
-    rec = {
-        "metric": "Mrays/s traced through cloak at <=1e-6 exit error; surrogate vs plain speedup at 1e-3",
-        "value": round(value, 3),
-        "unit": "Mrays/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == 0 else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": ("batched: 64 seeded views x 512^2 px (azimuth U[0,2pi), elevation "
-                                "U[0,60] deg), radial + azimuthal cloaks, ordinary + extraordinary, "
-                                "DP45 tol 1e-8, one HIP-graph replay per step" if batched else
-                                "3-D render: radial + azimuthal uniaxial cloaks (R1=1, R2=2, "
-                                "height 4), checkerboard room 20x20x10, 4 elevations x 1024^2 px, "
-                                "ordinary + extraordinary, DP45 tol 1e-8"),
-                   "streams": args.streams,
-                   "eager_ms_per_step": round(eager_ms, 4),
-                   "images_equal_across_streams": images_equal,
-                   "launch_shape": {"block": shape[0],
-                                    "refill_period": shape[1],
-                                    "autotuned_ms": tuned_ms},
-                   "miss_fraction": round(1.0 - entered / camera_rays, 4),
-                   "camera_rays_per_step": camera_rays,
-                   "rays_entering_cloak_per_step": entered,
-                   "all_camera_rays_per_s_M": round(camera_rays / (ms * 1e-3) / 1e6, 3),
-                   "precision": "fp64" if args.precision == 0 else "mixed",
-                   "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": traffic,
-                     "traffic_launch_shape": traffic_shape,
-                     "kernel": "k_transit (integrator)",
-                     "avg_launch_ms": round(avg_launch_ms, 4),
-                     "launches_per_step": launches_per_step,
-                     "integrator_share_of_eager_step": round(transit_ms / args.steps / eager_ms, 4)},
-    }
-    if not batched and args.precision == 0:
-        rec["mixed_precision"] = mixed_precision_leg(cloaks, room, cams, eager_ms, out, opts)
-    if not args.no_cpu_baseline and not batched:
-        rec["cpu_baseline"] = cpu_baseline(W.opts_dp45(), cams, args.cpu_stride)
+    rec, out_plain, orbit = orbit_headline(args, log)
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = orbit_cpu_baseline(orbit[0][0], args.cpu_stride)
+        log(f"cpu baseline: {rec['cpu_baseline']['value']:.4f} Mrays/s on {rec['cpu_baseline']['cores']} threads")
     if not args.no_surrogate:
-        del out
-        rt.release_workspace()
-        rec["surrogate"] = surrogate_leg(args.surrogate_steps, args.surrogate_train,
-                                         lambda msg: print(msg, file=sys.stderr, flush=True),
-                                         args.frames_per_launch)
+        sur, model, cal = surrogate_leg(args.surrogate_steps, args.surrogate_train, log, keep=True)
+        sur["render"] = orbit_surrogate(model, orbit, out_plain, rec["ms_per_step"], log, cal)
+        rec["surrogate"] = sur
+        model.close()
+        del cal
+    del out_plain, orbit
+    rt.release_workspace()
+    torch.cuda.empty_cache()
+    if not args.no_sub:
+        rec["sub"] = {"render_1024": render1024_record(args, log), "batched": batched_record(args, log),
+                      "inplane": inplane_workload(args), "train": train_workload(args)}
     print(json.dumps(finite_json(rec)), flush=True)
 
 

@@ -81,12 +81,13 @@ typedef struct {
    paper compares against (Sect. 4): state (x, k), H = k^T A k - f with A = eps
    and f = eps_o eps_e (extraordinary) or A = I and f = eps_o (ordinary),
    classical RK4 with the fixed step h in the ray parameter tau
-   (dx/dtau = 2 A k, dt/dtau = 2 f); FP64 only (with RT_PREC_MIXED the call
-   returns RT_E_UNSUPPORTED). Interfaces, events and
+   (dx/dtau = 2 A k, dt/dtau = 2 f). Interfaces, events and
    outputs are those of the other schemes (k is converted to v = M^-1 k at
-   every interface). precision:
-   RT_PREC_FP64, or RT_PREC_MIXED (FP32 derivative evaluation where
-   r - r1 >= fp64_band, FP64 state and step combination everywhere).
+   every interface). precision: RT_PREC_FP64 (all arithmetic in FP64).
+   RT_PREC_MIXED (the derivative evaluated in FP32 away from r1) is rejected
+   with RT_E_UNSUPPORTED: its rounding, amplified near the singular inner
+   radius, moves exits by more than the 1e-6 bar, and on this GPU FP32 and
+   FP64 vector arithmetic issue at the same rate. fp64_band is unused.
    r_out: report radius of rt_trace_batch (>= r2). max_steps: step attempts per
    ray. max_bounces: internal reflections (inner mirror, total internal
    reflection) per ray, 0..64. block / refill_period: integrator launch shape

@@ -36,7 +36,7 @@ struct CloakP {
 };
 
 struct OptsP {
-  double h0, rtol, atol, hmax, band, r_out;
+  double h0, rtol, atol, hmax, r_out;
   long long max_steps;
   int scheme, precision, max_bounces, pad;
 };
@@ -156,69 +156,11 @@ __device__ __forceinline__ void accel64(double a, double px, double py, double v
   }
 }
 
-// Mixed precision: r^2 - a^2 is formed in FP64 (no cancellation near r = a),
-// everything else of the derivative evaluation in FP32.
+// the acceleration of branch KIND (FP64)
 template <int KIND>
-__device__ __forceinline__ void accel32(double a, double px, double py, double vx, double vy,
-                                        double vz, double& ax, double& ay, double& az) {
-  if constexpr (KIND == K_RO) {
-    ax = 0.0; ay = 0.0; az = 0.0;
-    return;
-  } else {
-    double d64 = fma(px, px, fma(py, py, -a * a));  // r^2 - a^2
-    float d = (float)d64;
-    float fa = (float)a;
-    float x = (float)px, y = (float)py;
-    float fvx = (float)vx, fvy = (float)vy, fvz = (float)vz;
-    float r2 = d + fa * fa;
-    float w = __builtin_amdgcn_rsqf(r2);
-    float r = r2 * w;
-    float w2 = w * w;
-    float q = d * w2 * __builtin_amdgcn_rcpf(1.0f + fa * w);  // (r^2-a^2)/(r (r+a)) = (r-a)/r
-    (void)r;
-    float P = fmaf(x, fvx, y * fvy);
-    float Q = fmaf(x, fvy, -y * fvx);
-    float vr = P * w, vt = Q * w;
-    float g = 2.0f * fa * w2 * __builtin_amdgcn_rcpf(q);
-    float vt2 = vt * vt;
-    float ar, at, fz;
-    if constexpr (KIND == K_RE) {
-      float s = q * q;
-      float sp = g * s;
-      ar = fmaf(0.5f * sp, fmaf(fvz, fvz, vt2), -(1.0f - s) * vt2 * w);
-      at = -g * vr * vt;
-      fz = -g * vr * fvz;
-    } else if constexpr (KIND == K_AE) {
-      float s = q * q;
-      float sp = g * s;
-      ar = fmaf(0.5f * sp, vt2, -(1.0f - s) * vt2 * w);
-      at = -g * vr * vt;
-      fz = 0.0f;
-    } else {
-      ar = 0.5f * g * fmaf(fvz, fvz, fmaf(-vr, vr, vt2));
-      at = -g * vr * vt;
-      fz = -g * vr * fvz;
-    }
-    ar *= w;
-    at *= w;
-    ax = (double)fmaf(ar, x, -at * y);
-    ay = (double)fmaf(ar, y, at * x);
-    az = (double)fz;
-  }
-}
-
-// precision dispatch: MIXED uses FP32 unless r - a < band
-template <int KIND, bool MIXED>
-__device__ __forceinline__ void accel(double a, double band2, double px, double py, double vx,
-                                      double vy, double vz, double& ax, double& ay, double& az) {
-  if constexpr (MIXED) {
-    // band2 = (a + band)^2: FP64 inside the band next to the inner radius
-    if (fma(px, px, py * py) < band2) accel64<KIND>(a, px, py, vx, vy, vz, ax, ay, az);
-    else accel32<KIND>(a, px, py, vx, vy, vz, ax, ay, az);
-  } else {
-    (void)band2;
-    accel64<KIND>(a, px, py, vx, vy, vz, ax, ay, az);
-  }
+__device__ __forceinline__ void accel(double a, double px, double py, double vx, double vy, double vz,
+                                      double& ax, double& ay, double& az) {
+  accel64<KIND>(a, px, py, vx, vy, vz, ax, ay, az);
 }
 
 // ---------------------------------------------------------------------------
@@ -263,8 +205,8 @@ constexpr double dp_ea(int l) {
 // One DP45 attempt. Inputs: state (x, v), A[0] = acceleration at the state.
 // Outputs: fifth-order state (xn, vn), A[6] = acceleration there, and the sum
 // of squared scaled errors (accept when <= 6, i.e. RMS <= 1).
-template <int KIND, bool MIXED>
-__device__ __forceinline__ double dp45_attempt(double a, double band2, const double x[3],
+template <int KIND>
+__device__ __forceinline__ double dp45_attempt(double a, const double x[3],
                                                const double v[3], double A[7][3], double h,
                                                double rtol, double atol, double xn[3],
                                                double vn[3]) {
@@ -282,7 +224,7 @@ __device__ __forceinline__ double dp45_attempt(double a, double band2, const dou
       V[i] = fma(h, av, v[i]);
       X[i] = fma(h, fma(h, ax, dp_c(s) * v[i]), x[i]);
     }
-    accel<KIND, MIXED>(a, band2, X[0], X[1], V[0], V[1], V[2], A[s][0], A[s][1], A[s][2]);
+    accel<KIND>(a, X[0], X[1], V[0], V[1], V[2], A[s][0], A[s][1], A[s][2]);
     if (s == 6) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) { xn[i] = X[i]; vn[i] = V[i]; }
@@ -348,21 +290,21 @@ __device__ __forceinline__ double dp45_factor(double sum, bool after_reject) {
 }
 
 // classical RK4 step for y = (x, v); A1 = acceleration at the state
-template <int KIND, bool MIXED>
-__device__ __forceinline__ void rk4_step(double a, double band2, const double x[3],
+template <int KIND>
+__device__ __forceinline__ void rk4_step(double a, const double x[3],
                                          const double v[3], const double A1[3], double h,
                                          double xn[3], double vn[3]) {
   double hh = 0.5 * h;
   double V2[3], V3[3], V4[3], A2[3], A3[3], A4[3], X[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) { X[i] = fma(hh, v[i], x[i]); V2[i] = fma(hh, A1[i], v[i]); }
-  accel<KIND, MIXED>(a, band2, X[0], X[1], V2[0], V2[1], V2[2], A2[0], A2[1], A2[2]);
+  accel<KIND>(a, X[0], X[1], V2[0], V2[1], V2[2], A2[0], A2[1], A2[2]);
 #pragma unroll
   for (int i = 0; i < 3; ++i) { X[i] = fma(hh, V2[i], x[i]); V3[i] = fma(hh, A2[i], v[i]); }
-  accel<KIND, MIXED>(a, band2, X[0], X[1], V3[0], V3[1], V3[2], A3[0], A3[1], A3[2]);
+  accel<KIND>(a, X[0], X[1], V3[0], V3[1], V3[2], A3[0], A3[1], A3[2]);
 #pragma unroll
   for (int i = 0; i < 3; ++i) { X[i] = fma(h, V3[i], x[i]); V4[i] = fma(h, A3[i], v[i]); }
-  accel<KIND, MIXED>(a, band2, X[0], X[1], V4[0], V4[1], V4[2], A4[0], A4[1], A4[2]);
+  accel<KIND>(a, X[0], X[1], V4[0], V4[1], V4[2], A4[0], A4[1], A4[2]);
   double h6 = h * (1.0 / 6.0);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -673,13 +615,12 @@ __device__ __forceinline__ void fresnel_out_dev(double eo, double ee, const doub
 // ---------------------------------------------------------------------------
 // kind dispatch helpers (wave-uniform in practice: slots are grouped by kind)
 // ---------------------------------------------------------------------------
-template <bool MIXED>
-__device__ __forceinline__ void accel_k(int kind, double a, double band2, const double x[3],
+__device__ __forceinline__ void accel_k(int kind, double a, const double x[3],
                                         const double v[3], double A[3]) {
   switch (kind) {
-    case K_RE: accel<K_RE, MIXED>(a, band2, x[0], x[1], v[0], v[1], v[2], A[0], A[1], A[2]); break;
-    case K_AO: accel<K_AO, MIXED>(a, band2, x[0], x[1], v[0], v[1], v[2], A[0], A[1], A[2]); break;
-    case K_AE: accel<K_AE, MIXED>(a, band2, x[0], x[1], v[0], v[1], v[2], A[0], A[1], A[2]); break;
+    case K_RE: accel<K_RE>(a, x[0], x[1], v[0], v[1], v[2], A[0], A[1], A[2]); break;
+    case K_AO: accel<K_AO>(a, x[0], x[1], v[0], v[1], v[2], A[0], A[1], A[2]); break;
+    case K_AE: accel<K_AE>(a, x[0], x[1], v[0], v[1], v[2], A[0], A[1], A[2]); break;
     default: A[0] = 0.0; A[1] = 0.0; A[2] = 0.0; break;
   }
 }

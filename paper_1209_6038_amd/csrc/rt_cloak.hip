@@ -392,8 +392,8 @@ __device__ __noinline__ double2 fresnel_event(double kappa, double a, int rid, d
   return make_double2(Tt, Rr);
 }
 
-template <int KIND, bool MIXED, bool HAM, bool FRES>
-__device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o, double band2,
+template <int KIND, bool HAM, bool FRES>
+__device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
                                        double tol, double &hr) {
   if (L.rid < 0 && L.ns >= o.max_steps) return RT_RAY_MAXSTEPS;
   const double hs = L.rid < 0 ? L.h : L.ht;
@@ -405,11 +405,11 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
     // state (x, k); the step is in the ray parameter tau
     rk4_ham_step<KIND>(c.a, c.kappa, L.x, L.v, hs, xn, vn, dts);
   } else if (o.scheme == RT_SCHEME_RK4) {
-    rk4_step<KIND, MIXED>(c.a, band2, L.x, L.v, L.A1, hs, xn, vn);
+    rk4_step<KIND>(c.a, L.x, L.v, L.A1, hs, xn, vn);
   } else {
 #pragma unroll
     for (int i = 0; i < 3; ++i) A[0][i] = L.A1[i];
-    sum = dp45_attempt<KIND, MIXED>(c.a, band2, L.x, L.v, A, hs, o.rtol, o.atol, xn, vn);
+    sum = dp45_attempt<KIND>(c.a, L.x, L.v, A, hs, o.rtol, o.atol, xn, vn);
   }
   if (L.rid < 0) {
     // ---- stepping ----
@@ -453,7 +453,7 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
       L.t += dts;
       if constexpr (!HAM) {
         if (o.scheme == RT_SCHEME_RK4) {
-          accel<KIND, MIXED>(c.a, band2, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
+          accel<KIND>(c.a, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
         } else {
 #pragma unroll
           for (int i = 0; i < 3; ++i) L.A1[i] = A[6][i];
@@ -557,7 +557,7 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
   L.h = o.h0;
   L.after_reject = false;
   if constexpr (HAM) ham_convert<KIND>(c.a, c.kappa, L.x, L.v, true);  // v -> k
-  else accel<KIND, MIXED>(c.a, band2, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
+  else accel<KIND>(c.a, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
   return -1;
 }
 
@@ -578,9 +578,9 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
 // one atomic each and refills its idle lanes every `refill` attempts. The
 // lane state lives here, specialized for the branch, so no code of another
 // branch is interleaved with the step loop.
-template <int KIND, bool MIXED, bool HAM, bool FRES>
+template <int KIND, bool HAM, bool FRES>
 __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, const Table &T, const SegMap &sm,
-                                            int seg, double band2, double tol, int refill,
+                                            int seg, double tol, int refill,
                                             unsigned int &drained) {
   int slot = -1;
   Lane L;
@@ -614,7 +614,7 @@ __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, con
         L.after_reject = false;
         L.rid = -1;
         if constexpr (HAM) ham_convert<KIND>(c.a, c.kappa, L.x, L.v, true);  // v -> k
-        else accel<KIND, MIXED>(c.a, band2, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
+        else accel<KIND>(c.a, L.x[0], L.x[1], L.v[0], L.v[1], L.v[2], L.A1[0], L.A1[1], L.A1[2]);
         if constexpr (FRES) L.wt = T.wt[slot];
       }
       cur = min(cur + (unsigned int)__popcll(m), end);
@@ -632,7 +632,7 @@ __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, con
     for (int it = 0; it < refill; ++it) {
       if (slot >= 0) {
         double hr = __builtin_nan("");
-        const int stop = iterate<KIND, MIXED, HAM, FRES>(L, c, o, band2, tol, hr);
+        const int stop = iterate<KIND, HAM, FRES>(L, c, o, tol, hr);
         if (stop >= 0) {
           // the Hamiltonian form holds k until an interface: report v
           if constexpr (HAM)
@@ -652,14 +652,13 @@ __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, con
   }
 }
 
-template <bool MIXED, bool HAM, bool FRES>
+template <bool HAM, bool FRES>
 __global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int refill) {
   // the queue holds the used parts of the segments one after the other,
   // each sorted hardest first and holding one branch (every entry kernel
   // fills segment q with one (cloak, branch) pair); a wave integrates one
   // segment at a time and moves on to the next one that still has rays
   const SegMap sm = seg_map(T);
-  const double band2 = (c.a + o.band) * (c.a + o.band);
   const double tol = 1e-13 * c.b;
   unsigned int drained = 0;  // bit q: this wave found segment q's queue exhausted
   int nused = 0;
@@ -684,10 +683,10 @@ __global__ void __launch_bounds__(256) k_transit(CloakP c, OptsP o, Table T, int
     while (drained >> seg & 1u) seg = (seg + 1) % NSEG;
     const int kind = __builtin_amdgcn_readfirstlane(T.kind[(long long)seg * T.cap]);
     switch (kind) {
-      case K_RE: run_segment<K_RE, MIXED, HAM, FRES>(c, o, T, sm, seg, band2, tol, refill, drained); break;
-      case K_AO: run_segment<K_AO, MIXED, HAM, FRES>(c, o, T, sm, seg, band2, tol, refill, drained); break;
-      case K_AE: run_segment<K_AE, MIXED, HAM, FRES>(c, o, T, sm, seg, band2, tol, refill, drained); break;
-      default: run_segment<K_RO, MIXED, HAM, FRES>(c, o, T, sm, seg, band2, tol, refill, drained); break;
+      case K_RE: run_segment<K_RE, HAM, FRES>(c, o, T, sm, seg, tol, refill, drained); break;
+      case K_AO: run_segment<K_AO, HAM, FRES>(c, o, T, sm, seg, tol, refill, drained); break;
+      case K_AE: run_segment<K_AE, HAM, FRES>(c, o, T, sm, seg, tol, refill, drained); break;
+      default: run_segment<K_RO, HAM, FRES>(c, o, T, sm, seg, tol, refill, drained); break;
     }
   }
 }
@@ -1350,15 +1349,14 @@ int check_opts(const rt_trace_opts *o, double r2, bool need_rout) {
     return fail(RT_E_INVALID, "scheme must be RT_SCHEME_RK4, RT_SCHEME_DP45 or RT_SCHEME_RK4_HAM");
   if (o->precision != RT_PREC_FP64 && o->precision != RT_PREC_MIXED)
     return fail(RT_E_INVALID, "precision must be RT_PREC_FP64 or RT_PREC_MIXED");
-  if (o->scheme == RT_SCHEME_RK4_HAM && o->precision != RT_PREC_FP64)
-    return fail(RT_E_UNSUPPORTED, "the Hamiltonian form runs in FP64 only");
+  if (o->precision == RT_PREC_MIXED)
+    return fail(RT_E_UNSUPPORTED, "RT_PREC_MIXED is not supported: an FP32 derivative misses the 1e-6 exit bar "
+                                  "and issues no faster than FP64 on this GPU; use RT_PREC_FP64");
   if (!(o->h > 0.0) || !std::isfinite(o->h)) return fail(RT_E_INVALID, "h must be > 0");
   if (o->scheme == RT_SCHEME_DP45) {
     if (!(o->rtol > 0.0) || !(o->atol > 0.0)) return fail(RT_E_INVALID, "rtol and atol must be > 0");
     if (!(o->hmax >= o->h)) return fail(RT_E_INVALID, "hmax must be >= h");
   }
-  if (o->precision == RT_PREC_MIXED && !(o->fp64_band >= 0.0))
-    return fail(RT_E_INVALID, "fp64_band must be >= 0");
   if (need_rout && !(o->r_out >= r2)) return fail(RT_E_INVALID, "r_out (%g) must be >= r2 (%g)", o->r_out, r2);
   if (o->max_steps < 1) return fail(RT_E_INVALID, "max_steps must be >= 1");
   if (o->max_bounces < 0 || o->max_bounces > MAX_BOUNCES)
@@ -1374,7 +1372,6 @@ int check_opts(const rt_trace_opts *o, double r2, bool need_rout) {
 OptsP make_opts(const rt_trace_opts &o) {
   OptsP p;
   p.h0 = o.h; p.rtol = o.rtol; p.atol = o.atol; p.hmax = o.scheme == RT_SCHEME_DP45 ? o.hmax : o.h;
-  p.band = o.precision == RT_PREC_MIXED ? o.fp64_band : 0.0;
   p.r_out = o.r_out;
   p.max_steps = o.max_steps;
   p.scheme = o.scheme; p.precision = o.precision; p.max_bounces = o.max_bounces; p.pad = 0;
@@ -1392,23 +1389,20 @@ unsigned int grid_for(long long n, int block) {
   return (unsigned int)std::max(1LL, g);
 }
 
-template <bool MIXED, bool HAM, bool FRES>
+template <bool HAM, bool FRES>
 unsigned int transit_grid_t(int block) {
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_transit<MIXED, HAM, FRES>, block, 0) != hipSuccess ||
-      occ <= 0)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_transit<HAM, FRES>, block, 0) != hipSuccess || occ <= 0)
     occ = 1;
   return (unsigned int)(num_cu() * occ);
 }
 
-// the integrator variant the options select: FP64, mixed precision or the
-// Hamiltonian form
+// the integrator variant the options select: Eq. (8) in (x, v) or the
+// Hamiltonian form, with or without the Eq. (12) weights
 unsigned int transit_grid(const OptsP &o, int block, bool fres = false) {
   if (o.scheme == RT_SCHEME_RK4_HAM)
-    return fres ? transit_grid_t<false, true, true>(block) : transit_grid_t<false, true, false>(block);
-  if (fres) return transit_grid_t<false, false, true>(block);
-  return o.precision == RT_PREC_MIXED ? transit_grid_t<true, false, false>(block)
-                                     : transit_grid_t<false, false, false>(block);
+    return fres ? transit_grid_t<true, true>(block) : transit_grid_t<true, false>(block);
+  return fres ? transit_grid_t<false, true>(block) : transit_grid_t<false, false>(block);
 }
 
 // integrate the slots already placed in the table: order them hardest
@@ -1422,15 +1416,13 @@ void run_transit(const CloakP &c, const OptsP &o, const Table &T, int block, int
   bool on = false;
   if (profile) prof_begin(s, pe, on);
   if (o.scheme == RT_SCHEME_RK4_HAM && fres)
-    hipLaunchKernelGGL((k_transit<false, true, true>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
+    hipLaunchKernelGGL((k_transit<true, true>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
   else if (o.scheme == RT_SCHEME_RK4_HAM)
-    hipLaunchKernelGGL((k_transit<false, true, false>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
+    hipLaunchKernelGGL((k_transit<true, false>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
   else if (fres)
-    hipLaunchKernelGGL((k_transit<false, false, true>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
-  else if (o.precision == RT_PREC_MIXED)
-    hipLaunchKernelGGL((k_transit<true, false, false>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
+    hipLaunchKernelGGL((k_transit<false, true>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
   else
-    hipLaunchKernelGGL((k_transit<false, false, false>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
+    hipLaunchKernelGGL((k_transit<false, false>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
   if (profile) prof_end(s, pe, on);
 }
 

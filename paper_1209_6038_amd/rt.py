@@ -85,17 +85,23 @@ class RenderAux(ctypes.Structure):
                 ("nsteps", ctypes.c_void_p), ("tof", ctypes.c_void_p), ("unpol", ctypes.c_void_p)]
 
 
-def _render_aux(lead: tuple, w: int, h: int, spp: int, dev):
+AUX_FIELDS = ("rec", "status", "code", "nsteps", "tof")
+
+
+def _render_aux(lead: tuple, w: int, h: int, spp: int, dev, fields=True):
     """Per-sample (rec, status, code, nsteps) and per-pixel (tof) render
-    outputs for images of leading shape `lead`, and their rt_render_aux."""
+    outputs for images of leading shape `lead`, and their rt_render_aux.
+    fields: True for all of them, or the names of the ones to produce."""
     import torch
     ns = w * h * spp
-    aux_t = {"rec": torch.empty(lead + (7, ns), dtype=torch.float64, device=dev),
-             "status": torch.empty(lead + (ns,), dtype=torch.int32, device=dev),
-             "code": torch.empty(lead + (ns,), dtype=torch.uint8, device=dev),
-             "nsteps": torch.empty(lead + (ns,), dtype=torch.int32, device=dev),
-             "tof": torch.empty(lead + (h, w), dtype=torch.float32, device=dev)}
-    aux_s = RenderAux(*(aux_t[k].data_ptr() for k in ("rec", "status", "code", "nsteps", "tof")))
+    want = AUX_FIELDS if fields is True else tuple(fields)
+    make = {"rec": lambda: torch.empty(lead + (7, ns), dtype=torch.float64, device=dev),
+            "status": lambda: torch.empty(lead + (ns,), dtype=torch.int32, device=dev),
+            "code": lambda: torch.empty(lead + (ns,), dtype=torch.uint8, device=dev),
+            "nsteps": lambda: torch.empty(lead + (ns,), dtype=torch.int32, device=dev),
+            "tof": lambda: torch.empty(lead + (h, w), dtype=torch.float32, device=dev)}
+    aux_t = {k: make[k]() for k in want}
+    aux_s = RenderAux(*(aux_t[k].data_ptr() if k in aux_t else None for k in AUX_FIELDS))
     return aux_t, aux_s
 
 
@@ -274,11 +280,20 @@ def trace_batch(cloak: Cloak, opts: dict, pol: int, in6, with_aux: bool = True,
     return r
 
 
+def _check_out(rgb, shape):
+    """The library writes the images densely from the tensor's first element."""
+    import torch
+    if rgb.dtype != torch.float32 or not rgb.is_cuda or not rgb.is_contiguous() or rgb.numel() != int(np.prod(shape)):
+        raise ValueError(f"out must be a contiguous float32 CUDA tensor of {int(np.prod(shape))} elements "
+                         f"({shape}); got {tuple(rgb.shape)}, contiguous={rgb.is_contiguous()}")
+
+
 def render_multi(cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: int,
                  aux: bool = False, out=None, unpolarized: bool = False):
     """rt_render_multi: the same views for several cloaks (sharing geometry) in
     one pass. Returns rgb float32 (n_cloaks, n_cams, npol, h, w, 3) and, with
-    aux=True, dict(rec, status, code, nsteps) in the same image order; with
+    aux=True, dict(rec, status, code, nsteps, tof) in the same image order
+    (aux = a tuple of those names: only these); with
     unpolarized=True (pol_mask 3, FP64) the dict also holds "unpol", the
     Eq. (12) unpolarized images, float32 (n_cloaks, n_cams, h, w, 3)."""
     import torch
@@ -289,6 +304,7 @@ def render_multi(cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: i
     dev = torch.device("cuda", torch.cuda.current_device())
     rgb = out if out is not None else torch.empty((ncl, n, npol, h, w, 3), dtype=torch.float32,
                                                   device=dev)
+    _check_out(rgb, (ncl, n, npol, h, w, 3))
     carr = (Camera * n)(*[camera(c) for c in cams])
     harr = (ctypes.c_void_p * max(len(cloaks), 1))(*[c.handle for c in cloaks])
     rm = room(room_d)
@@ -296,7 +312,7 @@ def render_multi(cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: i
     aux_s = None
     aux_t = None
     if aux:
-        aux_t, aux_s = _render_aux((ncl, n, npol,), w, h, spp, dev)
+        aux_t, aux_s = _render_aux((ncl, n, npol,), w, h, spp, dev, aux)
     if unpolarized:
         if aux_s is None:
             aux_t, aux_s = {}, RenderAux()
@@ -323,6 +339,7 @@ def render_surrogate(model, cloaks: list, opts: dict, room_d: dict, cams: list, 
     dev = torch.device("cuda", torch.cuda.current_device())
     rgb = out if out is not None else torch.empty((ncl, n, npol, h, w, 3), dtype=torch.float32,
                                                   device=dev)
+    _check_out(rgb, (ncl, n, npol, h, w, 3))
     carr = (Camera * n)(*[camera(c) for c in cams])
     harr = (ctypes.c_void_p * max(ncl, 1))(*[c.handle for c in cloaks])
     rm = room(room_d)
@@ -354,6 +371,7 @@ def render(cloak, opts: dict, room_d: dict, cams: list, pol_mask: int, aux: bool
     npol = 2 if pol_mask == 3 else 1
     dev = torch.device("cuda", torch.cuda.current_device())
     rgb = out if out is not None else torch.empty((n, npol, h, w, 3), dtype=torch.float32, device=dev)
+    _check_out(rgb, (n, npol, h, w, 3))
     carr = (Camera * n)(*[camera(c) for c in cams])
     rm = room(room_d)
     o = trace_opts(opts)
@@ -375,6 +393,7 @@ def _alloc_render_outputs(ncl, cams, pol_mask, aux, out=None):
     dev = torch.device("cuda", torch.cuda.current_device())
     rgb = out if out is not None else torch.empty((ncl, n, npol, h, w, 3), dtype=torch.float32,
                                                   device=dev)
+    _check_out(rgb, (ncl, n, npol, h, w, 3))
     aux_t = aux_s = None
     if aux:
         aux_t, aux_s = _render_aux((ncl, n, npol,), w, h, spp, dev)

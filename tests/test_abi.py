@@ -96,17 +96,22 @@ def test_argument_validation_needs_no_gpu(lib):
                               ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None, None) == rt.RT_E_INVALID
     assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 0, None, None, None, None, None, None,
                               None, None) == rt.RT_OK  # n = 0 is a no-op
-    # the Hamiltonian form (scheme 2) runs in FP64 only; scheme 3 does not exist
-    o = rt.trace_opts({"scheme": rt.RK4_HAM, "precision": rt.MIXED, "h": 1e-3, "fp64_band": 0.05})
-    assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 10, ctypes.c_void_p(8), ctypes.c_void_p(8),
-                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None, None) == rt.RT_E_UNSUPPORTED
-    assert b"FP64" in lib.rt_last_error()
-    # Eq. (12) weights are computed in FP64 only
-    o = rt.trace_opts({"scheme": rt.DP45, "precision": rt.MIXED, "h": 1e-2, "fp64_band": 0.05})
-    assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 10, ctypes.c_void_p(8), ctypes.c_void_p(8),
-                              ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, ctypes.c_void_p(8),
-                              None) == rt.RT_E_UNSUPPORTED
-    assert b"Eq. (12)" in lib.rt_last_error()
+    # an FP32 derivative (RT_PREC_MIXED) is rejected for every scheme, with
+    # or without the Eq. (12) weights, and in the allocation-free variant;
+    # scheme 3 does not exist
+    for scheme, h0 in ((rt.RK4_HAM, 1e-3), (rt.DP45, 1e-2), (rt.RK4, 1e-3)):
+        o = rt.trace_opts({"scheme": scheme, "precision": rt.MIXED, "h": h0, "fp64_band": 0.05})
+        for trans in (None, ctypes.c_void_p(8)):
+            for fn in (lib.rt_trace_batch, lib.rt_trace_batch_noalloc):
+                assert fn(h, ctypes.byref(o), 1, 10, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8),
+                          ctypes.c_void_p(8), None, None, trans, None) == rt.RT_E_UNSUPPORTED
+                assert b"RT_PREC_FP64" in lib.rt_last_error()
+    # the allocation-free variant holds at most RT_NOALLOC_MAX_RAYS rays
+    o = rt.trace_opts({"scheme": rt.DP45, "h": 1e-2})
+    assert lib.rt_trace_batch_noalloc(h, ctypes.byref(o), 1, rt.NOALLOC_MAX_RAYS + 1, ctypes.c_void_p(8),
+                                      ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8), None, None,
+                                      None, None) == rt.RT_E_INVALID
+    assert b"at most" in lib.rt_last_error()
     o = rt.trace_opts({"scheme": 3, "h": 1e-3})
     assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 10, ctypes.c_void_p(8), ctypes.c_void_p(8),
                               ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None, None) == rt.RT_E_INVALID
