@@ -91,7 +91,8 @@ ENTERED = (0, 2, 3, 4, 5)
 # scaled by the same counters on a plain device copy of known size
 # (bench.py --copy-probe), per workload. Valid only for the integrator source
 # it was measured on; reported as null otherwise.
-TRAFFIC = {"source_sha256": None, "bytes_per_launch": {}}
+TRAFFIC = {"source_sha256": "3cb87507f08a1c3acecc5e1994f621ef77a3b651225be3d0746c04c75024ef61",
+           "bytes_per_launch": {"orbit": 21_958_862_848}}
 
 
 def traffic_for(workload):
