@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -53,6 +54,7 @@ constexpr long long OFF_B4 = OFF_W4 + HID * HID;
 constexpr long long OFF_W5 = OFF_B4 + HID;
 constexpr long long OFF_B5 = OFF_W5 + HID * NOUT;
 constexpr long long NPARAM = OFF_B5 + NOUT;  // 200,453
+static_assert(OFF_B1 == OFF_W1 + NIN * HID, "W1, b1 are contiguous");
 // BF16 copies of W2, W3, W4: transposed [out][in] (forward: the 8
 // consecutive inputs an MFMA lane needs for one output are one 16-byte
 // load) and row-major [in][out] (backward through the layer); NBF per copy
@@ -94,137 +96,161 @@ __device__ __forceinline__ float dsilu_f(float z) {
 }
 
 // ---------------------------------------------------------------------------
-// Tiled GEMM on MFMA: C(M x N) = A(M x K) B(K x N) with strided operands
-// (A(i,k) = A[i*sa0 + k*sa1], B(k,j) = B[k*sb0 + j*sb1]), BF16 in, FP32
+// Tiled GEMM on MFMA: C(M x N) = A(M x K) B(K x N) with both operands
+// contiguous along K (A(i,k) = A[i*lda + k], B(k,j) = B[j*ldb + k]), BF16 in, FP32
 // accumulation. 64 x 64 tile per 256-thread block (4 waves of 32 x 32, each
-// 2 x 2 MFMA 16x16x32 tiles), K in steps of 32 staged through LDS. Split-K
-// over blockIdx.z (each z-slice covers `kchunk` of K) with atomic FP32 sums.
-// Epilogues:
-//   EPI_BIAS_SILU  z = acc + bias: Cf <- z, Cb <- bf16(silu z), Ca <- silu z
-//   EPI_DSILU      g = acc * silu'(Z): Cf <- g, Cb <- bf16(g)
-//   EPI_ATOMIC     Cf += acc
+// 2 x 2 MFMA 16x16x32 tiles), K in steps of 32 staged through LDS, optionally
+// split over K (each split covers `kchunk` of K). One-dimensional grid of
+// (column tiles) x (row tiles) x (splits) blocks, the column tile fastest.
+// Consecutive blocks go to the 8 XCDs in turn, each with its own L2, so the
+// block number is first renumbered to give each XCD a contiguous range of
+// tiles: the column tiles of a row tile (which read the same A rows), and the
+// tiles of a K split (which read the same A and B columns), then share an L2.
+// Epilogues (the backward pass of the BF16 layers):
+//   EPI_DSILU      g = acc * silu'(Z): Cf <- g, Cb <- bf16(g), its
+//                  transpose Cbt <- bf16(g)^T ([N][ldcbt]), and the
+//                  block's column sums of g to the row of colsum of its
+//                  row tile (a partial-sum array [row tiles][N], may be NULL;
+//                  with xf, [row tiles][7][N] holding xf^T g, then the sums:
+//                  the gradients of W1 and b1 when g is dz of layer 1)
+//   EPI_SPLIT      Cf + split * M * ldcf <- acc: one partial product per K
+//                  split, summed afterwards by k_sum_rows
 // (each output pointer may be NULL)
 // ---------------------------------------------------------------------------
-enum { EPI_BIAS_SILU = 0, EPI_DSILU = 1, EPI_ATOMIC = 2 };
+enum { EPI_DSILU = 1, EPI_SPLIT = 2 };
 
 struct Gemm {
   const bf16 *A;
-  long long sa0, sa1;
+  long long lda;  // A(i, k) = A[i * lda + k]
   const bf16 *B;
-  long long sb0, sb1;
+  long long ldb;  // B(k, j) = B[j * ldb + k]
+  bool veca, vecb;  // 16-byte operand loads allowed
   int M, N, K, kchunk, epi;
-  const float *bias;
+  int nct, nrt;  // column and row tiles
   const float *Z;
   long long ldz;
   float *Cf;
   long long ldcf;
   bf16 *Cb;
   long long ldcb;
-  float *Ca;
-  long long ldca;
+  float *colsum;  // EPI_DSILU: per-block column sums of g, [row tile][N] (may be NULL)
+  const float *xf;  // with colsum: the layer-1 inputs [M][6], for the sums xf^T g ([row tile][7][N])
+  bf16 *Cbt;      // EPI_DSILU: bf16(g) transposed, Cbt[col * ldcbt + row] (may be NULL)
+  long long ldcbt;
 };
 
-// Stage an R x 32 operand tile (rows r0.., k k0..) into LDS as T[row][k],
-// in passes of 64 rows. P(row, k) = P[row * s_row + k * s_k]; rows < nrow
-// and k < kend valid, zeros elsewhere. One 8-element vector per thread and
-// pass: along k when s_k == 1, along rows (stored transposed) when
-// s_row == 1, else element-wise.
-template <int R>
-__device__ __forceinline__ void stage_tile(bf16 (*T)[40], const bf16 *__restrict__ P, long long s_row, long long s_k,
-                                           int r0, int nrow, int k0, int kend, int tid) {
+// Operand tiles are staged 64 deep in K: a 64 x 64 BF16 tile (rows r0..,
+// k k0..) is two 16-byte vectors per thread, 8 consecutive threads on the 128
+// bytes of one row. P(row, k) = P[row * ld + k] (K contiguous); rows < nrow
+// and k < kend valid, zeros elsewhere (vec: ld and P allow 16-byte loads).
+constexpr int GT = 64, GK = 64, GLD = GK + 8;  // tile, K step, padded LDS row
+
+__device__ __forceinline__ void load_op(bf16x8 v[2], const bf16 *__restrict__ P, long long ld, bool vec, int r0,
+                                        int nrow, int k0, int kend, int tid) {
 #pragma unroll
-  for (int pass = 0; pass < R / 64; ++pass) {
-    const int rb = 64 * pass;
-    if (s_k == 1) {
-      const int r = rb + (tid >> 2), kk = (tid & 3) * 8;
-      const int gr = r0 + r, gk = k0 + kk;
-      const bf16 *src = P + gr * s_row + gk;
-      if (gr < nrow && gk + 8 <= kend && ((s_row & 7) == 0)) {
-        *reinterpret_cast<bf16x8 *>(&T[r][kk]) = *reinterpret_cast<const bf16x8 *>(src);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) T[r][kk + e] = (gr < nrow && gk + e < kend) ? src[e] : (bf16)0.0f;
-      }
-    } else if (s_row == 1) {
-      const int kk = tid >> 3, r = rb + (tid & 7) * 8;
-      const int gr = r0 + r, gk = k0 + kk;
-      const bf16 *src = P + gk * s_k + gr;
-      if (gk < kend && gr + 8 <= nrow && ((s_k & 7) == 0)) {
-        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(src);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) T[r + e][kk] = v[e];
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) T[r + e][kk] = (gk < kend && gr + e < nrow) ? src[e] : (bf16)0.0f;
-      }
+  for (int p = 0; p < 2; ++p) {
+    const int gr = r0 + (tid >> 3) + 32 * p, gk = k0 + 8 * (tid & 7);
+    const bf16 *src = P + (long long)gr * ld + gk;
+    if (vec && gr < nrow && gk + 8 <= kend) {
+      v[p] = *reinterpret_cast<const bf16x8 *>(src);
     } else {
-      for (int e = tid; e < 64 * 32; e += 256) {
-        const int r = rb + (e >> 5), kk = e & 31;
-        const int gr = r0 + r, gk = k0 + kk;
-        T[r][kk] = (gr < nrow && gk < kend) ? P[gr * s_row + gk * s_k] : (bf16)0.0f;
-      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[p][e] = (gr < nrow && gk + e < kend) ? src[e] : (bf16)0.0f;
     }
   }
 }
 
-// C = A B over the block's K chunk with an epilogue. 4 waves in 2 x 2, each
-// owning (16 WM) x (16 WN) outputs as WM x WN MFMA 16x16x32 tiles, so the
-// block tile is (32 WM) x (32 WN); each 32-deep K step stages both operand
-// tiles once and feeds WM * WN MFMAs per wave from 16-byte LDS reads.
-template <int WM, int WN>
+__device__ __forceinline__ void store_op(bf16 *T, const bf16x8 v[2], int tid) {
+#pragma unroll
+  for (int p = 0; p < 2; ++p) *reinterpret_cast<bf16x8 *>(&T[((tid >> 3) + 32 * p) * GLD + 8 * (tid & 7)]) = v[p];
+}
+
+// C = A B over the block's K range with an epilogue: a 64 x 64 tile, 4 waves
+// in 2 x 2, each owning 32 x 32 outputs as 2 x 2 MFMA 16x16x32 tiles. The K
+// loop is double-buffered: step i's tiles go from registers to one LDS stage
+// while step i + 1's global loads are in flight, so one barrier per 64-deep
+// step; the epilogue's inputs (the pre-activations) are loaded before the
+// loop. The FP32 output tile reuses the staging area.
 __global__ void __launch_bounds__(256) k_gemm(Gemm g) {
-  constexpr int BM = 32 * WM, BN = 32 * WN;
-  __shared__ __attribute__((aligned(16))) bf16 As[BM][40];  // [row][k], padded rows
-  __shared__ __attribute__((aligned(16))) bf16 Bs[BN][40];  // [col][k]
+  constexpr int BM = GT, BN = GT, WM = 2, WN = 2, STAGE = (BM + BN) * GLD;
+  __shared__ __attribute__((aligned(16))) bf16 sm[2 * STAGE];
+  static_assert(BM * (BN + 4) * sizeof(float) <= sizeof(sm), "the FP32 tile fits in the staging area");
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const int row0 = blockIdx.x * BM, col0 = blockIdx.y * BN;  // row tiles on x (up to 2^31 blocks)
-  const int kbeg = blockIdx.z * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned t = (nb & 7) ? b : (b & 7) * (nb >> 3) + (b >> 3);  // a bijection of [0, nb)
+  const int ct = (int)(t % (unsigned)g.nct), rt = (int)(t / (unsigned)g.nct % (unsigned)g.nrt);
+  const int split = (int)(t / (unsigned)g.nct / (unsigned)g.nrt);
+  const int row0 = rt * BM, col0 = ct * BN;
+  const int kbeg = split * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
+  // this thread's 16 epilogue entries: row lr, columns lc.. of the tile
+  const int lr = tid >> 2, lc = (tid & 3) * 16;
+  float zp[16];
+  const bool zpre = g.epi == EPI_DSILU && row0 + lr < g.M && col0 + lc + 16 <= g.N;
+  if (zpre) {
+    const float *zr = g.Z + (long long)(row0 + lr) * g.ldz + col0 + lc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 zz = *reinterpret_cast<const float4 *>(zr + 4 * q);
+      zp[4 * q] = zz.x; zp[4 * q + 1] = zz.y; zp[4 * q + 2] = zz.z; zp[4 * q + 3] = zz.w;
+    }
+  }
   f32x4 acc[WM][WN];
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
     for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kbeg; k0 < kend; k0 += 32) {
-    // A(i, k) = A[i*sa0 + k*sa1]; B staged as its transpose: B(k, j) = B[j*sb1 + k*sb0]
-    stage_tile<BM>(As, g.A, g.sa0, g.sa1, row0, g.M, k0, kend, tid);
-    stage_tile<BN>(Bs, g.B, g.sb1, g.sb0, col0, g.N, k0, kend, tid);
-    __syncthreads();
+  // A(i, k) = A[i*lda + k]; B staged as its transpose, B(k, j) = B[j*ldb + k]
+  bf16x8 ra[2], rb[2];
+  load_op(ra, g.A, g.lda, g.veca, row0, g.M, kbeg, kend, tid);
+  load_op(rb, g.B, g.ldb, g.vecb, col0, g.N, kbeg, kend, tid);
+  const int nk = (kend - kbeg + GK - 1) / GK;
+  for (int it = 0; it < nk; ++it) {
+    bf16 *As = sm + (it & 1) * STAGE, *Bs = As + BM * GLD;
+    store_op(As, ra, tid);
+    store_op(Bs, rb, tid);
+    __syncthreads();  // also: every wave is done with this stage's previous use (step it - 2)
+    if (it + 1 < nk) {
+      const int k1 = kbeg + (it + 1) * GK;
+      load_op(ra, g.A, g.lda, g.veca, row0, g.M, k1, kend, tid);
+      load_op(rb, g.B, g.ldb, g.vecb, col0, g.N, k1, kend, tid);
+    }
     // operand layout of v_mfma_f32_16x16x32_bf16: lane l holds
-    // A[l%16][8*(l/16) + j] and B[8*(l/16) + j][l%16], j = 0..7 (rows of
-    // 80 bytes keep each 8-element read 16-byte aligned)
-    bf16x8 af[WM], bfr[WN];
+    // A[l%16][8*(l/16) + j] and B[8*(l/16) + j][l%16], j = 0..7 (padded rows
+    // of 144 bytes keep each 8-element read 16-byte aligned and spread the
+    // 16 rows of a read over all banks)
 #pragma unroll
-    for (int t = 0; t < WM; ++t)
-      af[t] = *reinterpret_cast<const bf16x8 *>(&As[wm * 16 * WM + t * 16 + (lane & 15)][8 * (lane >> 4)]);
+    for (int ks = 0; ks < GK; ks += 32) {
+      bf16x8 af[WM], bfr[WN];
 #pragma unroll
-    for (int t = 0; t < WN; ++t)
-      bfr[t] = *reinterpret_cast<const bf16x8 *>(&Bs[wn * 16 * WN + t * 16 + (lane & 15)][8 * (lane >> 4)]);
+      for (int i = 0; i < WM; ++i)
+        af[i] = *reinterpret_cast<const bf16x8 *>(&As[(wm * 32 + i * 16 + (lane & 15)) * GLD + ks + 8 * (lane >> 4)]);
 #pragma unroll
-    for (int ti = 0; ti < WM; ++ti)
+      for (int j = 0; j < WN; ++j)
+        bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn * 32 + j * 16 + (lane & 15)) * GLD + ks + 8 * (lane >> 4)]);
 #pragma unroll
-      for (int tj = 0; tj < WN; ++tj)
-        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ti], bfr[tj], acc[ti][tj], 0, 0, 0);
-    __syncthreads();
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
   }
+  __syncthreads();  // every wave has read its last operands: the staging area becomes the FP32 tile
   // result layout: lane l holds D[4*(l/16) + i][l%16], i = 0..3
-  if (g.epi == EPI_ATOMIC) {
-#pragma unroll
-    for (int ti = 0; ti < WM; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < WN; ++tj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = row0 + wm * 16 * WM + ti * 16 + 4 * (lane >> 4) + r;
-          const int col = col0 + wn * 16 * WN + tj * 16 + (lane & 15);
-          if (row < g.M && col < g.N) atomicAdd(&g.Cf[row * g.ldcf + col], acc[ti][tj][r]);
-        }
-    return;
-  }
   // the elementwise epilogues read and write whole rows: the tile goes
   // through LDS, and each thread then owns 16 consecutive columns of a row
   // (64-byte FP32 and 32-byte BF16 vectors, full cache lines per row)
-  __shared__ __attribute__((aligned(16))) float Cs[BM][BN + 4];
+  float(*Cs)[BN + 4] = reinterpret_cast<float(*)[BN + 4]>(sm);
+  // beyond the FP32 tile: the layer-1 inputs of the tile's rows [64][6] and
+  // the column sums of the 4 waves [4][7][64]
+  float *const xs = &Cs[BM][0];
+  float *const red = xs + BM * NIN;
+  static_assert((BM * (BN + 4) + BM * NIN + 4 * (NIN + 1) * 64) * sizeof(float) <= sizeof(sm), "epilogue LDS");
+  if (g.epi == EPI_DSILU && g.colsum && g.xf)
+    for (int e = tid; e < BM * NIN; e += 256) {
+      const int r = e / NIN;
+      xs[e] = row0 + r < g.M ? g.xf[(long long)(row0 + r) * NIN + e % NIN] : 0.0f;
+    }
 #pragma unroll
   for (int ti = 0; ti < WM; ++ti)
 #pragma unroll
@@ -233,90 +259,145 @@ __global__ void __launch_bounds__(256) k_gemm(Gemm g) {
       for (int r = 0; r < 4; ++r)
         Cs[wm * 16 * WM + ti * 16 + 4 * (lane >> 4) + r][wn * 16 * WN + tj * 16 + (lane & 15)] = acc[ti][tj][r];
   __syncthreads();
-  static_assert(BM % 64 == 0 && BN % 64 == 0, "epilogue passes of 64 x 64");
+  static_assert(BM == 64 && BN == 64, "one epilogue pass: 16 entries per thread");
+  do {
+    const int row = row0 + lr, col = col0 + lc;
+    const bool sums = g.epi == EPI_DSILU && (g.colsum || g.Cbt);  // g stays in the tile
+    if (row >= g.M) {
+      if (sums) {
 #pragma unroll
-  for (int rb = 0; rb < BM; rb += 64)
-#pragma unroll
-    for (int cb = 0; cb < BN; cb += 64) {
-      const int lr = rb + (tid >> 2), lc = cb + (tid & 3) * 16;
-      const int row = row0 + lr, col = col0 + lc;
-      if (row >= g.M) continue;
-      float v[16];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float4 t = *reinterpret_cast<const float4 *>(&Cs[lr][lc + 4 * q]);
-        v[4 * q] = t.x; v[4 * q + 1] = t.y; v[4 * q + 2] = t.z; v[4 * q + 3] = t.w;
+        for (int e = 0; e < 16; ++e) Cs[lr][lc + e] = 0.0f;
       }
+      break;
+    }
+    float v[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 t = *reinterpret_cast<const float4 *>(&Cs[lr][lc + 4 * q]);
+      v[4 * q] = t.x; v[4 * q + 1] = t.y; v[4 * q + 2] = t.z; v[4 * q + 3] = t.w;
+    }
+    if (g.epi == EPI_SPLIT) {
+      float *o = g.Cf + (long long)split * g.M * g.ldcf + (long long)row * g.ldcf + col;
       if (col + 16 <= g.N) {
-        if (g.epi == EPI_DSILU) {
-          const float *zr = g.Z + (long long)row * g.ldz + col;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float4 zz = *reinterpret_cast<const float4 *>(zr + 4 * q);
-            v[4 * q] *= dsilu_f(zz.x); v[4 * q + 1] *= dsilu_f(zz.y);
-            v[4 * q + 2] *= dsilu_f(zz.z); v[4 * q + 3] *= dsilu_f(zz.w);
-          }
-          if (g.Cf) {
-            float *o = g.Cf + (long long)row * g.ldcf + col;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              *reinterpret_cast<float4 *>(o + 4 * q) = float4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
-          }
-          if (g.Cb) {
-            bf16x8 b0, b1;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) { b0[e] = (bf16)v[e]; b1[e] = (bf16)v[8 + e]; }
-            bf16 *o = g.Cb + (long long)row * g.ldcb + col;
-            *reinterpret_cast<bf16x8 *>(o) = b0;
-            *reinterpret_cast<bf16x8 *>(o + 8) = b1;
-          }
-        } else {
-          float a[16];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float4 bb = *reinterpret_cast<const float4 *>(g.bias + col + 4 * q);
-            v[4 * q] += bb.x; v[4 * q + 1] += bb.y; v[4 * q + 2] += bb.z; v[4 * q + 3] += bb.w;
-          }
-#pragma unroll
-          for (int e = 0; e < 16; ++e) a[e] = silu_f(v[e]);
-          if (g.Cf) {
-            float *o = g.Cf + (long long)row * g.ldcf + col;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              *reinterpret_cast<float4 *>(o + 4 * q) = float4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
-          }
-          if (g.Cb) {
-            bf16x8 b0, b1;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) { b0[e] = (bf16)a[e]; b1[e] = (bf16)a[8 + e]; }
-            bf16 *o = g.Cb + (long long)row * g.ldcb + col;
-            *reinterpret_cast<bf16x8 *>(o) = b0;
-            *reinterpret_cast<bf16x8 *>(o + 8) = b1;
-          }
-          if (g.Ca) {
-            float *o = g.Ca + (long long)row * g.ldca + col;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              *reinterpret_cast<float4 *>(o + 4 * q) = float4{a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]};
-          }
-        }
+        for (int q = 0; q < 4; ++q)
+          *reinterpret_cast<float4 *>(o + 4 * q) = float4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
       } else {
-        for (int e = 0; e < 16 && col + e < g.N; ++e) {
-          const long long c = col + e;
-          if (g.epi == EPI_DSILU) {
-            const float d = v[e] * dsilu_f(g.Z[row * g.ldz + c]);
-            if (g.Cf) g.Cf[row * g.ldcf + c] = d;
-            if (g.Cb) g.Cb[row * g.ldcb + c] = (bf16)d;
-          } else {
-            const float z = v[e] + g.bias[c];
-            const float a = silu_f(z);
-            if (g.Cf) g.Cf[row * g.ldcf + c] = z;
-            if (g.Cb) g.Cb[row * g.ldcb + c] = (bf16)a;
-            if (g.Ca) g.Ca[row * g.ldca + c] = a;
-          }
-        }
+        for (int e = 0; e < 16 && col + e < g.N; ++e) o[e] = v[e];
+      }
+      break;
+    }
+    if (col + 16 <= g.N) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] *= dsilu_f(zp[e]);  // zpre holds here
+      if (g.Cf) {
+        float *o = g.Cf + (long long)row * g.ldcf + col;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          *reinterpret_cast<float4 *>(o + 4 * q) = float4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+      }
+      if (g.Cb) {
+        bf16x8 b0, b1;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) { b0[e] = (bf16)v[e]; b1[e] = (bf16)v[8 + e]; }
+        bf16 *o = g.Cb + (long long)row * g.ldcb + col;
+        *reinterpret_cast<bf16x8 *>(o) = b0;
+        *reinterpret_cast<bf16x8 *>(o + 8) = b1;
+      }
+      if (sums) {
+        // this thread's own 16 entries of the staged tile, now holding g
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          *reinterpret_cast<float4 *>(&Cs[lr][lc + 4 * q]) = float4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+      }
+    } else {
+      for (int e = 0; e < 16; ++e) {
+        const long long c = col + e;
+        const float d = c < g.N ? v[e] * dsilu_f(g.Z[row * g.ldz + c]) : 0.0f;
+        if (sums) Cs[lr][lc + e] = d;
+        if (c >= g.N) continue;
+        if (g.Cf) g.Cf[row * g.ldcf + c] = d;
+        if (g.Cb) g.Cb[row * g.ldcb + c] = (bf16)d;
       }
     }
+  } while (false);
+  if (g.epi == EPI_DSILU && (g.colsum || g.Cbt)) __syncthreads();
+  if (g.epi == EPI_DSILU && g.Cbt) {
+    // every thread has left g (zeros outside the matrix) in its entries of
+    // the staged tile: the transpose, 8 consecutive rows of one column per
+    // 16-byte store
+    // (BM / 8 consecutive threads on the consecutive pieces of one column)
+    static_assert(BM % 8 == 0 && (BM / 8) * BN % 256 == 0, "transposed pieces per thread");
+    for (int e = tid; e < (BM / 8) * BN; e += 256) {
+      const int c = e / (BM / 8), r8 = (e % (BM / 8)) * 8;
+      const int col = col0 + c, row = row0 + r8;
+      if (col >= g.N || row >= g.M) continue;
+      bf16 *o = g.Cbt + (long long)col * g.ldcbt + row;
+      if (row + 8 <= g.M) {
+        bf16x8 pk;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pk[k] = (bf16)Cs[r8 + k][c];
+        *reinterpret_cast<bf16x8 *>(o) = pk;
+      } else {
+        for (int k = 0; row + k < g.M; ++k) o[k] = (bf16)Cs[r8 + k][c];
+      }
+    }
+  }
+  if (g.epi == EPI_DSILU && g.colsum) {
+    // the tile's column sums of g and, with xf, before them the sums of
+    // xf[row][k] g[row][col], k < 6: one row of partial sums per row tile,
+    // [row tile][7][N] (or [row tile][N]), added up by k_sum_rows (no
+    // atomics). Wave w sums rows 16 w .. 16 w + 15 for column `lane`, then
+    // the 4 waves' sums are added through LDS.
+    static_assert(BN == 64, "one column per lane");
+    constexpr int NS = NIN + 1;
+    float sk[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) sk[k] = 0.0f;
+#pragma unroll 4
+    for (int r = 16 * w; r < 16 * w + 16; ++r) {
+      const float gv = Cs[r][lane];
+      sk[NIN] += gv;
+      if (g.xf) {
+#pragma unroll
+        for (int k = 0; k < NIN; ++k) sk[k] = fmaf(xs[r * NIN + k], gv, sk[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) red[(w * NS + k) * 64 + lane] = sk[k];
+    __syncthreads();
+    const int nsum = g.xf ? NS : 1;
+    for (int e = tid; e < nsum * BN; e += 256) {
+      const int k = e / BN, c = e % BN, src = g.xf ? k : NIN;
+      const float v = (red[src * 64 + c] + red[(NS + src) * 64 + c]) +
+                      (red[(2 * NS + src) * 64 + c] + red[(3 * NS + src) * 64 + c]);
+      if (col0 + c < g.N) g.colsum[((long long)rt * nsum + k) * g.N + col0 + c] = v;
+    }
+  }
+}
+
+// dst[c] += sum over r < rows of part[r * ld + c], c < ncols. Block (x, y):
+// 64 consecutive columns x 4 groups of rows y*4+q, y*4+q+4Y, ... (Y =
+// gridDim.y) summed in registers, then over the 4 groups in LDS, one atomic
+// per column and block row (gridDim.y = 1: a single writer per column).
+__global__ void __launch_bounds__(256) k_sum_rows(const float *__restrict__ part, int rows, long long ld,
+                                                  int ncols, float *__restrict__ dst) {
+  __shared__ float sh[4][64];
+  const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const long long col = (long long)blockIdx.x * 64 + c;
+  float s0 = 0.f, s1 = 0.f;
+  if (col < ncols) {
+    const int step = 4 * gridDim.y;
+    int r = blockIdx.y * 4 + q;
+    for (; r + step < rows; r += 2 * step) {
+      s0 += part[(long long)r * ld + col];
+      s1 += part[(long long)(r + step) * ld + col];
+    }
+    if (r < rows) s0 += part[(long long)r * ld + col];
+  }
+  sh[q][c] = s0 + s1;
+  __syncthreads();
+  if (q == 0 && col < ncols) atomicAdd(&dst[col], (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]));
 }
 
 // Network input features of entry i. The transit of the infinite cylinder
@@ -335,80 +416,6 @@ __device__ __forceinline__ void features(const float *__restrict__ x6, long long
   f[5] = x6[5 * ld + i];
 }
 
-// layer 1 in FP32: xn = (f - in_off) * in_scale, z1 = xn W1 + b1,
-// a1 = bf16(silu z1). One block per row, thread j = hidden unit j.
-__global__ void __launch_bounds__(256) k_layer1(const float *__restrict__ x, long long ld, int n,
-                                                const float *__restrict__ P, const float *__restrict__ sc,
-                                                float *__restrict__ z1, bf16 *__restrict__ a1,
-                                                float *__restrict__ xf) {
-  // features of a tile of 64 rows, computed once per row
-  __shared__ float xs[64][NIN];
-  const int j = threadIdx.x;
-  float w[NIN];
-#pragma unroll
-  for (int k = 0; k < NIN; ++k) w[k] = P[OFF_W1 + k * HID + j];
-  const float b = P[OFF_B1 + j];
-  for (int r0 = blockIdx.x * 64; r0 < n; r0 += gridDim.x * 64) {
-    if (j < 64) {
-      const int row = r0 + j;
-      float f[NIN] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      if (row < n) {
-        features(x, ld, row, f);
-#pragma unroll
-        for (int k = 0; k < NIN; ++k) f[k] = (f[k] - sc[S_INOFF + k]) * sc[S_INSCALE + k];
-        if (xf) {
-#pragma unroll
-          for (int k = 0; k < NIN; ++k) xf[(long long)row * NIN + k] = f[k];
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < NIN; ++k) xs[j][k] = f[k];
-    }
-    __syncthreads();
-    const int rn = min(64, n - r0);
-    for (int r = 0; r < rn; ++r) {
-      float z = b;
-#pragma unroll
-      for (int k = 0; k < NIN; ++k) z = fmaf(xs[r][k], w[k], z);
-      const long long row = r0 + r;
-      if (z1) z1[row * HID + j] = z;
-      a1[row * HID + j] = (bf16)silu_f(z);
-    }
-    __syncthreads();
-  }
-}
-
-// layer 5 in FP32: y = a4 W5 + b5 (standardized outputs, n x 5 row-major).
-// One wave per row: lane l holds W5 rows 4l..4l+3 in registers and reads
-// a4[row][4l..4l+3]; the 5 dot products are reduced across the wave.
-__global__ void __launch_bounds__(256) k_layer5(const float *__restrict__ a4, int n, const float *__restrict__ P,
-                                                float *__restrict__ y) {
-  const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int nwave = (gridDim.x * blockDim.x) >> 6;
-  float w[4][NOUT];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int o = 0; o < NOUT; ++o) w[q][o] = P[OFF_W5 + (4 * lane + q) * NOUT + o];
-  for (int row = wave; row < n; row += nwave) {
-    const float4 a = *reinterpret_cast<const float4 *>(a4 + (long long)row * HID + 4 * lane);
-    float s[NOUT];
-#pragma unroll
-    for (int o = 0; o < NOUT; ++o) s[o] = a.x * w[0][o] + a.y * w[1][o] + a.z * w[2][o] + a.w * w[3][o];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-      for (int o = 0; o < NOUT; ++o) s[o] += __shfl_xor(s[o], off);
-    if (lane < NOUT) {
-      float v = s[0];
-#pragma unroll
-      for (int o = 1; o < NOUT; ++o) v = lane == o ? s[o] : v;
-      y[(long long)row * NOUT + lane] = v + P[OFF_B5 + lane];
-    }
-  }
-}
-
 // standardized outputs (n x 5) -> SoA targets (5 x ld)
 __global__ void k_destd(const float *__restrict__ y, int n, long long ld, const float *__restrict__ sc,
                         float *__restrict__ t) {
@@ -418,142 +425,126 @@ __global__ void k_destd(const float *__restrict__ y, int n, long long ld, const 
   t[o * ld + row] = fmaf(y[i], sc[S_OSTD + o], sc[S_OMEAN + o]);
 }
 
-// loss on the standardized targets and its gradient; t is SoA (5 x ld),
-// w (n) the per-row weight (NULL = 1). Per element d = y - t:
-// huber = 0: d^2 (gradient 2 d); huber = delta > 0: d^2 for |d| <= delta,
-// 2 delta |d| - delta^2 beyond (gradient clipped to 2 delta sign(d)).
-// Loss and gradient are divided by n.
-__global__ void __launch_bounds__(256) k_loss(const float *__restrict__ y, const float *__restrict__ t, long long ld,
-                                              const float *__restrict__ wrow, int n, const float *__restrict__ sc,
-                                              float huber, float *__restrict__ dy, float *__restrict__ loss) {
-  __shared__ float part[256];
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  float l = 0.f;
-  if (i < (long long)n * NOUT) {
-    const int row = (int)(i / NOUT), o = (int)(i - (long long)row * NOUT);
-    const float wr = wrow ? wrow[row] : 1.0f;
-    float g = 0.f;
-    if (wr != 0.0f) {
-      const float tn = (t[o * ld + row] - sc[S_OMEAN + o]) / sc[S_OSTD + o];
-      const float d = y[i] - tn;
-      if (huber > 0.0f && fabsf(d) > huber) {
-        l = wr * (2.0f * huber * fabsf(d) - huber * huber);
-        g = 2.0f * wr * copysignf(huber, d);
-      } else {
-        l = wr * d * d;
-        g = 2.0f * wr * d;
-      }
-    }
-    dy[i] = g / (float)n;
-  }
-  part[threadIdx.x] = l;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) atomicAdd(loss, part[0] / (float)n);
-}
+// backward of layer 5 (FP32): dW5 = a4^T dy, db5 = sum dy, with a4 =
+// silu(z4) recomputed from the saved pre-activation (the same FP32 function
+// as the forward's), dz4 = (dy W5^T) * silu'(z4) -> BF16 for the next
+// product (row-major and transposed), and db4 = sum dz4 (FP32). A block
+// takes a run of rows in chunks of 64, wave w rows 16 w .. 16 w + 15 of a
+// chunk, lane l units 4 l .. 4 l + 3 (one 16-byte load per lane covers a
+// row's 256 units); the transposed copy goes through LDS and out in whole
+// 128-byte lines. Each block writes its partial sums of the 1,541 gradient
+// entries b4 [256], W5 [256][5], b5 [5] (contiguous in the parameter vector
+// from OFF_B4) to a row of `part`.
+constexpr int L5_N = HID + HID * NOUT + NOUT, L5_LD = 1544, L5_MAXB = 1024;
+static_assert(OFF_W5 == OFF_B4 + HID && OFF_B5 == OFF_W5 + HID * NOUT, "b4, W5, b5 are contiguous");
 
-// backward of layer 5 (FP32): dW5 += a4^T dy, db5 += sum dy,
-// dz4 = (dy W5^T) * silu'(z4) -> FP32 and BF16 copies. Thread j = unit j.
-// partial sums of the layer-5 gradient (W5 [256][5] then b5 [5]) of each
-// block of k_layer5_back, summed over the blocks by k_layer5_reduce
-constexpr int L5_N = HID * NOUT + NOUT, L5_LD = 1288, L5_MAXB = 1024;
-
-__global__ void __launch_bounds__(256) k_layer5_back(const float *__restrict__ dy, const float *__restrict__ a4,
-                                                     const float *__restrict__ z4, int n,
-                                                     const float *__restrict__ P, float *__restrict__ part,
-                                                     float *__restrict__ dzf, bf16 *__restrict__ dzb) {
-  const int j = threadIdx.x;
-  float w[NOUT], gw[NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f}, gb = 0.f;
+__global__ void __launch_bounds__(256) k_layer5_back(const float *__restrict__ dy, const float *__restrict__ z4,
+                                                     int n, const float *__restrict__ P, float *__restrict__ part,
+                                                     bf16 *__restrict__ dzb, bf16 *__restrict__ dzT, long long ldT) {
+  // unit u's 8 pieces of 8 rows of a chunk at tp[9 u + p]; afterwards the
+  // same memory holds the 4 waves' partial sums
+  __shared__ bf16x8 tp[HID * 9];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int u0 = 4 * lane;
+  float w5[4][NOUT], gw[4][NOUT], gz[4] = {0.f, 0.f, 0.f, 0.f}, gb[NOUT];
 #pragma unroll
-  for (int o = 0; o < NOUT; ++o) w[o] = P[OFF_W5 + j * NOUT + o];
-  const int per = (n + gridDim.x - 1) / gridDim.x;
-  const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
-#pragma unroll 4
-  for (int row = r0; row < r1; ++row) {
-    const long long e = (long long)row * HID + j;
-    const float a = a4[e], zz = z4[e];
-    float da = 0.f;
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
-      const float d = dy[(long long)row * NOUT + o];
-      da = fmaf(d, w[o], da);
-      gw[o] = fmaf(a, d, gw[o]);
+      w5[i][o] = P[OFF_W5 + (u0 + i) * NOUT + o];
+      gw[i][o] = 0.0f;
     }
-    if (j < NOUT) gb += dy[(long long)row * NOUT + j];
-    const float g = da * dsilu_f(zz);
-    dzf[e] = g;
-    dzb[e] = (bf16)g;
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) gb[o] = 0.0f;
+  const int per = (((n + gridDim.x - 1) / gridDim.x) + 63) & ~63;
+  const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+  for (int c0 = r0; c0 < r1; c0 += 64) {
+    const int c1 = min(r1, c0 + 64);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int rb = c0 + 16 * w + 8 * p;
+      // the 8 rows' loads together (rows past the chunk repeat its last
+      // row and are not used)
+      float4 zz[8];
+      float d[8][NOUT];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const long long row = min(rb + k, c1 - 1);
+        zz[k] = *reinterpret_cast<const float4 *>(&z4[row * HID + u0]);
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) d[k][o] = dy[row * NOUT + o];
+      }
+      bf16x8 pk[4];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const float zk[4] = {zz[k].x, zz[k].y, zz[k].z, zz[k].w};
+        bf16x4 out;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float a = silu_f(zk[i]);
+          float da = 0.f;
+#pragma unroll
+          for (int o = 0; o < NOUT; ++o) da = fmaf(d[k][o], w5[i][o], da);
+          const float g = da * dsilu_f(zk[i]);
+          out[i] = (bf16)g;
+          pk[i][k] = out[i];
+          if (rb + k < c1) {
+            gz[i] += g;
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) gw[i][o] = fmaf(a, d[k][o], gw[i][o]);
+          }
+        }
+        if (rb + k < c1) {
+#pragma unroll
+          for (int o = 0; o < NOUT; ++o) gb[o] += d[k][o];
+          *reinterpret_cast<bf16x4 *>(&dzb[(long long)(rb + k) * HID + u0]) = out;
+        }
+      }
+      if (rb < c1) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tp[9 * (u0 + i) + ((rb - c0) >> 3)] = pk[i];
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < 8 * HID; e += 256) {
+      const int u = e >> 3, p = e & 7, row = c0 + 8 * p;
+      if (row >= c1) continue;
+      const bf16x8 v = tp[9 * u + p];
+      bf16 *o = dzT + (long long)u * ldT + row;
+      if (row + 8 <= c1) {
+        *reinterpret_cast<bf16x8 *>(o) = v;
+      } else {
+        for (int k = 0; row + k < c1; ++k) o[k] = v[k];
+      }
+    }
+    __syncthreads();
   }
+  // the 4 waves' sums: [wave][unit][W5 row (5), b4], then db5 [wave][5]
+  float *red = reinterpret_cast<float *>(tp);
+  static_assert((4 * HID * (NOUT + 1) + 4 * NOUT) * sizeof(float) <= sizeof(tp), "reduction fits");
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) red[(w * HID + u0 + i) * (NOUT + 1) + o] = gw[i][o];
+    red[(w * HID + u0 + i) * (NOUT + 1) + NOUT] = gz[i];
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) red[4 * HID * (NOUT + 1) + w * NOUT + o] = gb[o];
+  }
+  __syncthreads();
   float *pb = part + (long long)blockIdx.x * L5_LD;
-#pragma unroll
-  for (int o = 0; o < NOUT; ++o) pb[j * NOUT + o] = gw[o];
-  if (j < NOUT) pb[HID * NOUT + j] = gb;
-}
-
-// G[W5], G[b5] = sums of the blocks' partials (the only contributions)
-__global__ void __launch_bounds__(256) k_layer5_reduce(const float *__restrict__ part, int nblocks,
-                                                       float *__restrict__ G) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= L5_N) return;
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-  int b = 0;
-  for (; b + 4 <= nblocks; b += 4) {
-    s0 += part[(long long)b * L5_LD + t];
-    s1 += part[(long long)(b + 1) * L5_LD + t];
-    s2 += part[(long long)(b + 2) * L5_LD + t];
-    s3 += part[(long long)(b + 3) * L5_LD + t];
+  for (int e = tid; e < HID * (NOUT + 1); e += 256) {
+    const int u = e / (NOUT + 1), k = e % (NOUT + 1);
+    constexpr int WS = HID * (NOUT + 1);
+    const float v = (red[e] + red[WS + e]) + (red[2 * WS + e] + red[3 * WS + e]);
+    pb[k == NOUT ? u : HID + u * NOUT + k] = v;
   }
-  for (; b < nblocks; ++b) s0 += part[(long long)b * L5_LD + t];
-  G[t < HID * NOUT ? OFF_W5 + t : OFF_B5 + (t - HID * NOUT)] = (s0 + s1) + (s2 + s3);
-}
-
-// column sums of an (n x 256) FP32 matrix, accumulated into out[0..255];
-// each block sums a contiguous run of rows, 8 loads in flight per thread
-__global__ void __launch_bounds__(256) k_colsum(const float *__restrict__ d, int n, float *__restrict__ out) {
-  const int j = threadIdx.x;
-  const int per = (n + gridDim.x - 1) / gridDim.x;
-  const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
-  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  int row = r0;
-  for (; row + 8 <= r1; row += 8)
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] += d[(long long)(row + u) * HID + j];
-  for (; row < r1; ++row) s[0] += d[(long long)row * HID + j];
-  atomicAdd(&out[j], ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
-}
-
-// backward of layer 1 (FP32): dW1 += xn^T dz1, db1 += sum dz1, with the
-// standardized features xn saved by the forward; contiguous rows per block
-__global__ void __launch_bounds__(256) k_layer1_back(const float *__restrict__ xf, int n,
-                                                     const float *__restrict__ dz1, float *__restrict__ G) {
-  const int j = threadIdx.x;
-  const int per = (n + gridDim.x - 1) / gridDim.x;
-  const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
-  float gw[NIN] = {0, 0, 0, 0, 0, 0}, gb = 0.f;
-  int row = r0;
-  for (; row + 4 <= r1; row += 4) {
-    float d[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) d[u] = dz1[(long long)(row + u) * HID + j];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      gb += d[u];
-#pragma unroll
-      for (int k = 0; k < NIN; ++k) gw[k] = fmaf(xf[(long long)(row + u) * NIN + k], d[u], gw[k]);
-    }
+  if (tid < NOUT) {
+    const float *rb = red + 4 * HID * (NOUT + 1);
+    pb[HID + HID * NOUT + tid] = (rb[tid] + rb[NOUT + tid]) + (rb[2 * NOUT + tid] + rb[3 * NOUT + tid]);
   }
-  for (; row < r1; ++row) {
-    const float d = dz1[(long long)row * HID + j];
-    gb += d;
-#pragma unroll
-    for (int k = 0; k < NIN; ++k) gw[k] = fmaf(xf[(long long)row * NIN + k], d, gw[k]);
-  }
-#pragma unroll
-  for (int k = 0; k < NIN; ++k) atomicAdd(&G[OFF_W1 + k * HID + j], gw[k]);
-  atomicAdd(&G[OFF_B1 + j], gb);
 }
 
 __global__ void k_fill(float *p, long long n, float v) {
@@ -937,6 +928,53 @@ __global__ void __launch_bounds__(256) k_gate_idx(const float *__restrict__ x6, 
 // ---------------------------------------------------------------------------
 constexpr int FR = 128, ALD = HID + 8;
 
+// copy the block's BF16 activation tile (R rows of ALD, padded)
+// transposed to dst[unit * ldT + row0 + r]: 8 consecutive rows of one unit
+// per 16-byte store, R / 8 consecutive threads on the consecutive pieces of
+// one unit (whole 128-byte lines per group of 8 lanes at R = 64)
+template <int R>
+__device__ __forceinline__ void store_act_tile_t(const bf16 *act, bf16 *__restrict__ dst, long long ldT,
+                                                 long long row0, int n, int tid) {
+  constexpr int P8 = R / 8;
+#pragma unroll 2
+  for (int e = tid; e < P8 * HID; e += 256) {
+    const int u = e / P8, r8 = (e % P8) * 8;
+    bf16 *o = dst + (long long)u * ldT + row0 + r8;
+    if (row0 + r8 + 8 <= n) {
+      bf16x8 pk;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) pk[k] = act[(r8 + k) * ALD + u];
+      *reinterpret_cast<bf16x8 *>(o) = pk;
+    } else {
+      for (int k = 0; row0 + r8 + k < n; ++k) o[k] = act[(r8 + k) * ALD + u];
+    }
+  }
+}
+
+// What the training forward keeps for the backward pass, per row of the
+// batch (row-major [n][256] unless noted): the standardized features xf
+// [n][6], the pre-activations z1..z4 (FP32), the BF16 activations a1..a3
+// (the inputs of the BF16 layers) transposed, aT[l][unit * ldT + row] (the
+// weight-gradient products read them along the batch), and, instead of the
+// standardized outputs,
+// the loss term and its gradient dy [n][5] against the targets t (SoA 5 x
+// ld) with the row weights w (NULL = 1): per element d = y - (t - out_mean)
+// / out_std, the loss d^2, or for huber = delta > 0 the Huber function (d^2
+// up to |d| = delta, then 2 delta |d| - delta^2, gradient clipped to
+// 2 delta sign(d)), times the row weight; loss and gradient divided by n.
+struct TrainSink {
+  float *xf;
+  float *z[4];
+  bf16 *aT[3];
+  long long ldT;
+  const float *t;
+  long long ldt;
+  const float *w;
+  float huber;
+  float *dy;
+  float *loss;
+};
+
 // With idx != NULL, row r of the network is entry idx[r] for r < *count
 // (a compacted subset); otherwise row r is entry r, r < n.
 __global__ void __launch_bounds__(256, 2) k_mlp_fused(const float *__restrict__ x6, long long ld, int n,
@@ -1079,6 +1117,209 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fused(const float *__restrict__ 
   }
 }
 
+// The training forward: the network of k_mlp_fused on a batch of n rows,
+// R rows per block, keeping what the backward pass reads (TrainSink), with
+// the loss and its output gradient in place of the outputs.
+constexpr int TR = 64;  // rows per block
+__global__ void __launch_bounds__(256, 2) k_mlp_train_fwd(const float *__restrict__ x6, long long ld, int n,
+                                                          const float *__restrict__ P, const bf16 *__restrict__ Wt,
+                                                          const float *__restrict__ sc, TrainSink ts) {
+  constexpr int R = TR;
+  constexpr int NT = R / 16;  // row tiles of 16
+  constexpr int ZLD = 64 + 4;  // padded rows of the pre-activation staging tiles
+  __shared__ __attribute__((aligned(16))) bf16 act[R * ALD];
+  __shared__ float xn[R * NIN];
+  __shared__ __attribute__((aligned(16))) float zs[4 * 16 * ZLD];  // one 16 x 64 tile per wave
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const long long row0 = (long long)blockIdx.x * R;
+  if (row0 >= n) return;
+  // standardized input features of the tile (rows past n read as zeros)
+  if (tid < R) {
+    const long long i = row0 + tid;
+    float f[NIN] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (i < n) {
+      features(x6, ld, i, f);
+#pragma unroll
+      for (int k = 0; k < NIN; ++k) f[k] = (f[k] - sc[S_INOFF + k]) * sc[S_INSCALE + k];
+#pragma unroll
+      for (int k = 0; k < NIN; ++k) ts.xf[i * NIN + k] = f[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) xn[tid * NIN + k] = f[k];
+  }
+  __syncthreads();
+  {  // layer 1 (FP32): thread = pair of hidden units x half of the rows
+    const int u = 2 * (tid & 127), rb = (tid >> 7) * (R / 2);
+    float w0[NIN], w1[NIN];
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) {
+      w0[k] = P[OFF_W1 + k * HID + u];
+      w1[k] = P[OFF_W1 + k * HID + u + 1];
+    }
+    const float b0 = P[OFF_B1 + u], b1 = P[OFF_B1 + u + 1];
+    for (int r = rb; r < rb + R / 2; ++r) {
+      float z0 = b0, z1 = b1;
+#pragma unroll
+      for (int k = 0; k < NIN; ++k) {
+        z0 = fmaf(xn[r * NIN + k], w0[k], z0);
+        z1 = fmaf(xn[r * NIN + k], w1[k], z1);
+      }
+      bf16x2 pr;
+      pr[0] = (bf16)silu_f(z0);
+      pr[1] = (bf16)silu_f(z1);
+      *reinterpret_cast<bf16x2 *>(&act[r * ALD + u]) = pr;
+      if (row0 + r < n) *reinterpret_cast<float2 *>(&ts.z[0][(row0 + r) * HID + u]) = float2{z0, z1};
+    }
+  }
+  __syncthreads();
+  store_act_tile_t<R>(act, ts.aT[0], ts.ldT, row0, n, tid);
+  const int q = lane >> 4, c16 = lane & 15, ub = 64 * w;
+  const long long offb[3] = {OFF_B2, OFF_B3, OFF_B4};
+  f32x4 acc[4][NT];  // [unit tile][row tile]
+  for (int l = 0; l < 3; ++l) {
+    const bf16 *W = Wt + (long long)l * HID * HID;
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) acc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int k0 = 0; k0 < HID; k0 += 32) {
+      bf16x8 aop[4];
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti)
+        aop[ti] = *reinterpret_cast<const bf16x8 *>(W + (ub + 16 * ti + c16) * HID + k0 + 8 * q);
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+        const bf16x8 bop = *reinterpret_cast<const bf16x8 *>(&act[(16 * tj + c16) * ALD + k0 + 8 * q]);
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop[ti], bop, acc[ti][tj], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // every wave has read the layer's input tile
+    {
+      // the pre-activations z = acc + bias of this layer: each 16-row tile
+      // of the wave's 64 units goes through the wave's own LDS tile, so
+      // that a store instruction writes 4 rows x 256 contiguous bytes
+      // (whole lines) instead of 16 rows x 64 bytes. One wave writes and
+      // reads its tile; its LDS operations complete in order, and the wave
+      // barrier keeps the compiler from moving them across each other.
+      float *zl = ts.z[l + 1] + row0 * HID;  // the block's rows (32-bit offsets from here)
+      float *zw = zs + w * 16 * ZLD;
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti) {
+          const float4 bb = *reinterpret_cast<const float4 *>(&P[offb[l] + ub + 16 * ti + 4 * q]);
+          *reinterpret_cast<float4 *>(&zw[c16 * ZLD + 16 * ti + 4 * q]) =
+              float4{acc[ti][tj][0] + bb.x, acc[ti][tj][1] + bb.y, acc[ti][tj][2] + bb.z, acc[ti][tj][3] + bb.w};
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int rl = 4 * rr + (lane >> 4), r = 16 * tj + rl;
+          const float4 v = *reinterpret_cast<const float4 *>(&zw[rl * ZLD + 4 * c16]);
+          if (row0 + r < n) *reinterpret_cast<float4 *>(&zl[r * HID + ub + 4 * c16]) = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    if (l < 2) {
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti) {
+        const int u0 = ub + 16 * ti + 4 * q;  // this lane's 4 consecutive units
+        float bias[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bias[r] = P[offb[l] + u0 + r];
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) {
+          bf16x4 pk;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) pk[r] = (bf16)silu_f(acc[ti][tj][r] + bias[r]);
+          *reinterpret_cast<bf16x4 *>(&act[(16 * tj + c16) * ALD + u0]) = pk;
+        }
+      }
+      __syncthreads();
+      store_act_tile_t<R>(act, ts.aT[l + 1], ts.ldT, row0, n, tid);
+    } else {
+      // layer 5 (FP32) on a4 = silu(z4): partial sums over this lane's 16
+      // units for each of its 8 rows, then over the 4 lane groups
+      float s5[NT][NOUT];
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) s5[tj][o] = 0.0f;
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti) {
+        const int u0 = ub + 16 * ti + 4 * q;
+        float bias[4], w5[4][NOUT];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          bias[r] = P[offb[l] + u0 + r];
+#pragma unroll
+          for (int o = 0; o < NOUT; ++o) w5[r][o] = P[OFF_W5 + (u0 + r) * NOUT + o];
+        }
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float a4 = silu_f(acc[ti][tj][r] + bias[r]);
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) s5[tj][o] = fmaf(a4, w5[r][o], s5[tj][o]);
+          }
+      }
+      float *red = reinterpret_cast<float *>(act);  // [4 waves][R][NOUT]
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) {
+          s5[tj][o] += __shfl_xor(s5[tj][o], 16);
+          s5[tj][o] += __shfl_xor(s5[tj][o], 32);
+        }
+        if (q == 0) {
+#pragma unroll
+          for (int o = 0; o < NOUT; ++o) red[(w * R + 16 * tj + c16) * NOUT + o] = s5[tj][o];
+        }
+      }
+      __syncthreads();
+      float lrow = 0.0f;
+      if (tid < R) {
+        const long long i = row0 + tid;
+        if (i < n) {
+#pragma unroll
+          for (int o = 0; o < NOUT; ++o) {
+            const float y = P[OFF_B5 + o] + ((red[(0 * R + tid) * NOUT + o] + red[(1 * R + tid) * NOUT + o]) +
+                                             (red[(2 * R + tid) * NOUT + o] + red[(3 * R + tid) * NOUT + o]));
+            {
+              // the loss term and its gradient (see TrainSink)
+              const float wr = ts.w ? ts.w[i] : 1.0f;
+              float g = 0.f;
+              if (wr != 0.0f) {
+                const float tn = (ts.t[o * ts.ldt + i] - sc[S_OMEAN + o]) / sc[S_OSTD + o];
+                const float d = y - tn;
+                if (ts.huber > 0.0f && fabsf(d) > ts.huber) {
+                  lrow += wr * (2.0f * ts.huber * fabsf(d) - ts.huber * ts.huber);
+                  g = 2.0f * wr * copysignf(ts.huber, d);
+                } else {
+                  lrow += wr * d * d;
+                  g = 2.0f * wr * d;
+                }
+              }
+              ts.dy[i * NOUT + o] = g / (float)n;
+            }
+          }
+        }
+      }
+      {
+        // block sum of the loss terms (rows of the first R / 64 waves)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) lrow += __shfl_xor(lrow, off);
+        if (lane == 0 && w < R / 64) atomicAdd(ts.loss, lrow / (float)n);
+      }
+    }
+  }
+}
+
 // exit point and unit direction from exit parameters
 __device__ __forceinline__ void exit_ray(const float *p, float b, float x[3], float d[3]) {
   float sp, cp, sa, ca, sb, cbt;
@@ -1162,14 +1403,15 @@ struct rt_model_s {
   long long cap = 0;
   void *act = nullptr;
   float *z[4] = {nullptr, nullptr, nullptr, nullptr};  // hidden pre-activations (FP32)
-  bf16 *a[3] = {nullptr, nullptr, nullptr};            // a1..a3 (BF16)
-  float *a4 = nullptr;                                 // a4 (FP32)
+  bf16 *aT[3] = {nullptr, nullptr, nullptr};           // a1..a3 (BF16), transposed [256][ldT]
+  long long ldT = 0;                                   // row stride of the transposed arrays
   float *p5 = nullptr;                                 // layer-5 gradient partials [L5_MAXB][L5_LD]
-  float *y = nullptr;                                  // standardized outputs [cap][5]
   float *dy = nullptr;                                 // [cap][5]
-  float *dzf = nullptr;                                // [cap][256]
-  bf16 *dzb[2] = {nullptr, nullptr};
+  bf16 *dzb[2] = {nullptr, nullptr};                   // BF16 dz [cap][256], ping-pong
+  bf16 *dzT[2] = {nullptr, nullptr};                   // their transposes [256][ldT]
   float *xf = nullptr;                                 // standardized input features [cap][6]
+  float *wpart = nullptr;                              // split-K partial weight gradients [64][256 * 256]
+  float *cpart = nullptr;                              // per-row-tile column-sum partials [cap / 64][7][256]
   // standardized outputs of the fused inference kernel, and the compacted
   // entry list of the gated inference
   long long ycap = 0;
@@ -1190,10 +1432,12 @@ int reserve_acts(rt_model mo, long long n) {
   }
   const long long cap = std::max(n, 4096LL);
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t zb = al(sizeof(float) * cap * HID), ab = al(sizeof(bf16) * cap * HID);
+  const long long ldT = (cap + 63) & ~63LL;
+  const size_t zb = al(sizeof(float) * cap * HID), ab = al(sizeof(bf16) * ldT * HID);
   const size_t yb = al(sizeof(float) * cap * NOUT), fb = al(sizeof(float) * cap * NIN);
   const size_t pb = al(sizeof(float) * L5_MAXB * L5_LD);
-  const size_t bytes = 4 * zb + 3 * ab + zb + 2 * yb + zb + 2 * ab + fb + pb;
+  const size_t wb = al(sizeof(float) * 64 * HID * HID), cb = al(sizeof(float) * ((cap + 63) / 64) * (NIN + 1) * HID);
+  const size_t bytes = 4 * zb + 3 * ab + yb + 4 * ab + fb + pb + wb + cb;
   void *p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
@@ -1202,15 +1446,17 @@ int reserve_acts(rt_model mo, long long n) {
   char *c = (char *)p;
   size_t off = 0;
   for (int l = 0; l < 4; ++l) { mo->z[l] = (float *)(c + off); off += zb; }
-  for (int l = 0; l < 3; ++l) { mo->a[l] = (bf16 *)(c + off); off += ab; }
-  mo->a4 = (float *)(c + off); off += zb;
-  mo->y = (float *)(c + off); off += yb;
+  for (int l = 0; l < 3; ++l) { mo->aT[l] = (bf16 *)(c + off); off += ab; }
+  mo->ldT = ldT;
   mo->dy = (float *)(c + off); off += yb;
-  mo->dzf = (float *)(c + off); off += zb;
   mo->dzb[0] = (bf16 *)(c + off); off += ab;
   mo->dzb[1] = (bf16 *)(c + off); off += ab;
+  mo->dzT[0] = (bf16 *)(c + off); off += ab;
+  mo->dzT[1] = (bf16 *)(c + off); off += ab;
   mo->xf = (float *)(c + off); off += fb;
   mo->p5 = (float *)(c + off); off += pb;
+  mo->wpart = (float *)(c + off); off += wb;
+  mo->cpart = (float *)(c + off); off += cb;
   mo->act = p;
   mo->cap = cap;
   return RT_OK;
@@ -1242,74 +1488,76 @@ void infer_outputs(rt_model mo, const float *x, long long ld, int n, hipStream_t
                      mo->scal, mo->yinf);
 }
 
-void gemm(hipStream_t s, const bf16 *A, long long sa0, long long sa1, const bf16 *B, long long sb0, long long sb1,
-          int M, int N, int K, int epi, const float *bias, const float *Z, long long ldz, float *Cf, long long ldcf,
-          bf16 *Cb, long long ldcb, float *Ca, long long ldca, int splits = 1) {
+// returns the number of K splits used (EPI_SPLIT writes that many partials)
+int gemm(hipStream_t s, const bf16 *A, long long lda, const bf16 *B, long long ldb, int M, int N, int K, int epi,
+         const float *Z, long long ldz, float *Cf, long long ldcf, bf16 *Cb, long long ldcb, int splits = 1,
+         float *colsum = nullptr, bf16 *Cbt = nullptr, long long ldcbt = 0, const float *xf = nullptr) {
   int kchunk = (K + splits - 1) / splits;
-  kchunk = (kchunk + 31) & ~31;
+  kchunk = (kchunk + GK - 1) / GK * GK;  // splits start on a K step
   splits = (K + kchunk - 1) / kchunk;
-  Gemm g{A, sa0, sa1, B, sb0, sb1, M, N, K, kchunk, epi, bias, Z, ldz, Cf, ldcf, Cb, ldcb, Ca, ldca};
-  // 64 x 64 block tiles: 128 x 128 ones (k_gemm<4, 4>) measured slower on
-  // the training shapes, whose time goes to the epilogue's activation
-  // traffic rather than to the MFMAs
-  hipLaunchKernelGGL((k_gemm<2, 2>), dim3(gblocks(M, 64), gblocks(N, 64), splits), dim3(256), 0, s, g);
+  const int nct = (int)gblocks(N, GT), nrt = (int)gblocks(M, GT);
+  const bool veca = lda % 8 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0;
+  const bool vecb = ldb % 8 == 0 && reinterpret_cast<uintptr_t>(B) % 16 == 0;
+  Gemm g{A, lda, B, ldb, veca, vecb, M, N, K, kchunk, epi, nct, nrt, Z, ldz, Cf, ldcf, Cb, ldcb, colsum, xf, Cbt, ldcbt};
+  // 64 x 64 block tiles: 128 x 128 ones measured slower on the training
+  // shapes, whose time goes to the epilogue's activation traffic rather than
+  // to the MFMAs
+  hipLaunchKernelGGL(k_gemm, dim3((unsigned)((long long)nct * nrt * splits)), dim3(256), 0, s, g);
+  return splits;
 }
 
 // BF16 weights of W2 (l = 0), W3 (1), W4 (2): transposed [out][in] and row-major [in][out]
 const bf16 *wb(rt_model mo, int l) { return mo->Pb + (long long)l * HID * HID; }
 const bf16 *wr(rt_model mo, int l) { return mo->Pb + NBF + (long long)l * HID * HID; }
 
-// layered forward of n rows for training: keeps every activation and the
-// pre-activations for backward (inference uses the fused kernel)
-void forward(rt_model mo, const float *x, long long ld, int n, bool train, hipStream_t s) {
-  hipLaunchKernelGGL(k_layer1, dim3(std::min(gblocks(n, 64), 4096u)), dim3(HID), 0, s, x, ld, n, mo->P, mo->scal,
-                     train ? mo->z[0] : nullptr, mo->a[0], train ? mo->xf : nullptr);
-  const long long offb[3] = {OFF_B2, OFF_B3, OFF_B4};
-  for (int l = 1; l <= 3; ++l) {
-    const bool last = l == 3;
-    gemm(s, mo->a[l - 1], HID, 1, wb(mo, l - 1), 1, HID, n, HID, HID, EPI_BIAS_SILU, mo->P + offb[l - 1], nullptr,
-         0, train ? mo->z[l] : nullptr, HID, last ? nullptr : mo->a[l], HID, last ? mo->a4 : nullptr, HID);
-  }
-  hipLaunchKernelGGL(k_layer5, dim3(std::min(gblocks(n, 4), 4096u)), dim3(256), 0, s, mo->a4, n, mo->P, mo->y);
-}
-
 int split_for(int n) { return std::min(64, std::max(1, n / 512)); }
 
-// gradients of the loss of the last forward into mo->G; loss into scal[S_LOSS]
-void backward(rt_model mo, const float *x, const float *t, long long ld, const float *wrow, int n, float huber,
-              hipStream_t s) {
+// training forward of n rows (the fused network, keeping xf, z1..z4 and
+// a1..a3 for the backward pass) with the loss and its output gradient dy;
+// then the gradients of that loss into mo->G, the loss into scal[S_LOSS]
+void forward_backward(rt_model mo, const float *x, const float *t, long long ld, const float *wrow, int n,
+                      float huber, hipStream_t s) {
   float *loss = mo->scal + S_LOSS;
-  // reductions over rows: each block sums a contiguous run of >= 32 rows
-  // (loads in flight per thread), and at most 256 partial sums per
-  // parameter meet in atomics
-  const unsigned int rows_grid = (unsigned int)std::min(256, std::max(1, n / 32));
   hipLaunchKernelGGL(k_fill, dim3(gblocks(NPARAM, 256)), dim3(256), 0, s, mo->G, NPARAM, 0.0f);
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, loss, 1LL, 0.0f);
-  hipLaunchKernelGGL(k_loss, dim3(gblocks((long long)n * NOUT, 256)), dim3(256), 0, s, mo->y, t, ld, wrow, n,
-                     mo->scal, huber, mo->dy, loss);
-  // layer 5: its per-element work (dz of layer 4) is as large as a
-  // hidden layer's and parallel over rows, so it gets blocks of >= 16 rows
-  // (up to 1024 blocks, ~16 waves per CU); the blocks' partial sums of the
-  // 1285 layer-5 gradient entries are then added in a second pass (atomics
-  // from every block would serialize on the entries' few cache lines)
-  const int l5_grid = std::min(L5_MAXB, std::max(1, n / 16));
-  hipLaunchKernelGGL(k_layer5_back, dim3(l5_grid), dim3(HID), 0, s, mo->dy, mo->a4, mo->z[3], n, mo->P, mo->p5,
-                     mo->dzf, mo->dzb[1]);
-  hipLaunchKernelGGL(k_layer5_reduce, dim3((L5_N + 255) / 256), dim3(256), 0, s, mo->p5, l5_grid, mo->G);
-  // hidden layers from the top: dz of layer l (FP32 in dzf, BF16 in dzb[cur])
+  const long long ldT = mo->ldT;
+  TrainSink ts{mo->xf, {mo->z[0], mo->z[1], mo->z[2], mo->z[3]}, {mo->aT[0], mo->aT[1], mo->aT[2]}, ldT, t, ld,
+               wrow, huber, mo->dy, loss};
+  hipLaunchKernelGGL(k_mlp_train_fwd, dim3(gblocks(n, TR)), dim3(256), 0, s, x, ld, n, mo->P, mo->Pb, mo->scal, ts);
+  // layer 5: its per-element work (dz of layer 4) is as large as a hidden
+  // layer's and parallel over rows: one block per 64 rows, up to 1024
+  // blocks; the blocks' partial sums of the layer-5 weights and biases and
+  // of b4 are added in a second pass
+  const int l5_grid = std::min(L5_MAXB, (int)gblocks(n, 64));
+  hipLaunchKernelGGL(k_layer5_back, dim3(l5_grid), dim3(HID), 0, s, mo->dy, mo->z[3], n, mo->P, mo->p5, mo->dzb[1],
+                     mo->dzT[1], ldT);
+  hipLaunchKernelGGL(k_sum_rows, dim3((L5_N + 63) / 64, std::max(1, std::min(16, l5_grid / 4))), dim3(256), 0, s,
+                     mo->p5, l5_grid, (long long)L5_LD, L5_N, mo->G + OFF_B4);
+  // hidden layers from the top: dz of layer l + 1 in dzb[cur] (BF16,
+  // row-major) and dzT[cur] (its transpose)
   const long long offw[3] = {OFF_W2, OFF_W3, OFF_W4}, offb[3] = {OFF_B2, OFF_B3, OFF_B4};
   int cur = 1;
   for (int l = 3; l >= 1; --l) {
-    // dW_{l+1} += a_l^T dz (a_l: BF16 [n][256] read transposed), db_{l+1} += sum dz
-    gemm(s, mo->a[l - 1], 1, HID, mo->dzb[cur], HID, 1, HID, HID, n, EPI_ATOMIC, nullptr, nullptr, 0,
-         mo->G + offw[l - 1], HID, nullptr, 0, nullptr, 0, split_for(n));
-    hipLaunchKernelGGL(k_colsum, dim3(rows_grid), dim3(HID), 0, s, mo->dzf, n, mo->G + offb[l - 1]);
-    // dz_{l-1} = (dz W_{l+1}^T) * silu'(z_{l-1}); B(k, j) = W(in=j, out=k), row-major copy
-    gemm(s, mo->dzb[cur], HID, 1, wr(mo, l - 1), 1, HID, n, HID, HID, EPI_DSILU, nullptr, mo->z[l - 1], HID,
-         mo->dzf, HID, mo->dzb[cur ^ 1], HID, nullptr, 0);
+    // dW_{l+1} = a_l^T dz: both operands transposed so that the batch (the
+    // sum) is their contiguous index, split over the rows into partial
+    // products, then summed
+    const int splits = gemm(s, mo->aT[l - 1], ldT, mo->dzT[cur], ldT, HID, HID, n, EPI_SPLIT, nullptr, 0,
+                            mo->wpart, HID, nullptr, 0, split_for(n));
+    hipLaunchKernelGGL(k_sum_rows, dim3(HID * HID / 64, 1), dim3(256), 0, s, mo->wpart, splits,
+                       (long long)HID * HID, HID * HID, mo->G + offw[l - 1]);
+    // dz_l = (dz W_{l+1}^T) * silu'(z_l) (B(k, j) = W(in=j, out=k), row-major
+    // copy) with its per-row-tile column sums: for l >= 2 dz_l goes out in
+    // BF16 (both layouts) and the sums make db_l; dz_1 (FP32) never leaves
+    // the tile: its sums xf^T dz_1 and sum dz_1 are the gradients of W1 and
+    // b1 (contiguous in the parameter vector)
+    const int nrt = (int)gblocks(n, 64), ns = l >= 2 ? 1 : NIN + 1;
+    gemm(s, mo->dzb[cur], HID, wr(mo, l - 1), HID, n, HID, HID, EPI_DSILU, mo->z[l - 1], HID, nullptr, 0,
+         l >= 2 ? mo->dzb[cur ^ 1] : nullptr, HID, 1, mo->cpart, l >= 2 ? mo->dzT[cur ^ 1] : nullptr, ldT,
+         l >= 2 ? nullptr : mo->xf);
+    hipLaunchKernelGGL(k_sum_rows, dim3(ns * HID / 64, std::max(1, std::min(16, nrt / 4))), dim3(256), 0, s,
+                       mo->cpart, nrt, (long long)ns * HID, ns * HID, mo->G + (l >= 2 ? offb[l - 2] : OFF_W1));
     cur ^= 1;
   }
-  hipLaunchKernelGGL(k_layer1_back, dim3(rows_grid), dim3(HID), 0, s, mo->xf, n, mo->dzf, mo->G);
 }
 
 int check_model(rt_model mo) {
@@ -1573,8 +1821,7 @@ int grad_impl(rt_model mo, int64_t n, int64_t ld, const float *x6, const float *
   e = reserve_acts(mo, n);
   if (e) return e;
   hipStream_t s = (hipStream_t)stream;
-  forward(mo, x6, ld, (int)n, true, s);
-  backward(mo, x6, t5, ld, w, (int)n, huber, s);
+  forward_backward(mo, x6, t5, ld, w, (int)n, huber, s);
   if (grads) (void)hipMemcpyAsync(grads, mo->G, sizeof(float) * NPARAM, hipMemcpyDeviceToDevice, s);
   if (loss) (void)hipMemcpyAsync(loss, mo->scal + S_LOSS, sizeof(float), hipMemcpyDeviceToDevice, s);
   return launch_err("gradient launch");
