@@ -223,34 +223,41 @@ def test_render_in_small_chunks_equals_one_launch():
     assert torch.equal(torch.nan_to_num(aux_a["tof"]), torch.nan_to_num(aux_b["tof"]))
 
 
-def test_orbit_frame_full_size_sampled():
-    """One frame of the large-render workload at full size (4096^2 x 4
-    jittered spp, both cloaks, both branches, one launch): sampled pixels,
-    half of them where the cloak is, re-rendered by the oracle. Pixel means
-    of the 4 samples must agree; a sample whose wall hit lies on a tile edge
-    to rounding may flip parity, so one differing pixel per image is
-    allowed."""
+def test_orbit_frames_full_size_sampled():
+    """Two frames of the large-render workload at full size (4096^2 x 4
+    jittered spp, both cloaks, both branches) in the launch configuration
+    the benchmark times (two frames per integrator launch): per image, 256
+    random samples and 256 samples that enter the cloak re-traced by the
+    oracle, compared sample by sample as the 1024^2 render is: equal
+    statuses, exit rays within the 1e-6 bar (position / R2 and direction),
+    colour codes equal except within the propagated error of a tile edge."""
     import torch
     from paper_1209_6038_amd import rt
-    frame = W.orbit_frames(36, 4096, 4)[5]
+    frames = W.orbit_frames(36, 4096, 4)[5:7]
     descs = [W.cloak(a, height=W.HEIGHT) for a in (0, 1)]
     cls = [rt.Cloak(d) for d in descs]
-    say("case orbit frame 5: 4096^2 x 4 spp, 2 cloaks x 2 branches")
-    rgb = rt.render_multi(cls, W.render_opts(), W.room(), [frame], 3)
+    say("case orbit frames 5-6: 4096^2 x 4 spp, 2 cloaks x 2 branches, one launch")
+    opts = W.render_opts(max_chunk=2 * 4096 * 4096 * 4)
+    _, aux = rt.render_multi(cls, opts, W.room(), frames, 3, aux=("rec", "status", "code"))
     torch.cuda.synchronize()
-    rng = np.random.default_rng(5)
-    rows = np.concatenate([rng.integers(0, 4096, 24), rng.integers(1400, 2800, 24)])
-    cols = np.concatenate([rng.integers(0, 4096, 24), rng.integers(1600, 2500, 24)])
-    pix = rows * 4096 + cols
-    rt_, ct_ = torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()
-    g = rgb[:, 0][:, :, rt_, ct_].cpu().numpy()  # (cloak, branch, pixel, rgb)
+    room = W.room()
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    ns = 4096 * 4096 * 4
     for ci, c in enumerate(descs):
-        for pi in range(2):
-            o, _ = oracle.render_pixels(c, W.opts_dp45(), W.room(), frame, 0, pi, pix)
-            d = np.abs(g[ci, pi] - o).max(axis=1)
-            bad = int((d > 1e-6).sum())
-            say(f"  cloak axis {c['axis']} branch {pi}: {bad} of {len(pix)} pixels differ")
-            assert bad <= 1
+        for k, frame in enumerate(frames):
+            for pi in range(2):
+                st = aux["status"][ci, k, pi]
+                hits = torch.nonzero(st != 1).flatten().cpu()
+                ids = torch.cat([torch.randint(0, ns, (256,), generator=gen),
+                                 hits[torch.randint(0, hits.numel(), (256,), generator=gen)]])
+                ids = torch.unique(ids).numpy().astype(np.int64)
+                it = torch.from_numpy(ids).cuda()
+                g_code = aux["code"][ci, k, pi][it].cpu().numpy()
+                g_rec = aux["rec"][ci, k, pi][:, it].cpu().numpy()
+                g_st = st[it].cpu().numpy()
+                # camera index k within the launch: the jitter is keyed by it
+                o = oracle.render_samples(c, W.opts_dp45(), room, frame, k, pi, ids)
+                compare_samples(g_code, g_rec, g_st, o, room, f"orbit a{c['axis']} frame{5 + k} b{pi}")
 
 
 def test_two_large_frames_in_one_launch_equal_one_launch_each():
