@@ -136,6 +136,14 @@ def _load(path):
     L.orc_fresnel_out.argtypes = [ctypes.c_double, ctypes.c_double, c_double_p, c_double_p,
                                   c_double_p, ctypes.c_int32, c_double_p, c_double_p]
     L.orc_fresnel_out.restype = ctypes.c_int32
+    L.orc_fresnel_in_pol.argtypes = [ctypes.c_double, ctypes.c_double, c_double_p, c_double_p,
+                                     c_double_p, c_double_p, c_double_p, c_double_p]
+    L.orc_fresnel_in_pol.restype = ctypes.c_int32
+    L.orc_goggle_axis.argtypes = [ctypes.POINTER(_Camera), c_double_p, ctypes.c_int32, c_double_p]
+    L.orc_goggle_axis.restype = ctypes.c_int32
+    L.orc_render_goggle.argtypes = [ctypes.POINTER(_Cloak), ctypes.POINTER(_Opts), ctypes.POINTER(_Camera),
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                    c_int64_p, c_double_p]
     L.orc_camera_ray.argtypes = [ctypes.POINTER(_Camera), ctypes.c_int32, ctypes.c_int64,
                                  c_double_p, c_double_p]
     L.orc_room_code.argtypes = [ctypes.POINTER(_Room), c_double_p, c_double_p, c_double_p]
@@ -262,6 +270,24 @@ def render_unpolarized_pixels(cloak, opts, room, camera, cam_index, pixels):
     return col.reshape(len(pixels), spp, 3).mean(axis=1)
 
 
+def render_goggle_pixels(cloak, opts, room, camera, cam_index, pixels, goggle):
+    """RGB (float64, n x 3) of the given pixels seen through goggle `goggle`
+    (0 in-plane, 1 axial; Figs. 1d,e and 2d,e): per sample, the sum over the
+    two branches of its goggle weight times the colour it sees, averaged
+    over the pixel's samples."""
+    pixels = np.asarray(pixels, dtype=np.int64)
+    spp = int(camera.get("spp", 1))
+    ids = (pixels[:, None] * spp + np.arange(spp)[None, :]).reshape(-1)
+    table = np.zeros((13, 3))
+    table[:12] = np.asarray(room["rgb"], dtype=np.float32).reshape(12, 3)
+    col = np.zeros((len(ids), 3))
+    for branch in (0, 1):
+        r = render_samples(cloak, opts, room, camera, cam_index, branch, ids)
+        wg = render_goggle_weights(cloak, opts, camera, cam_index, branch, goggle, ids)
+        col += wg[:, None] * table[r["code"]]
+    return col.reshape(len(pixels), spp, 3).mean(axis=1)
+
+
 def eps_cyl(cloak, r):
     out = np.empty(3)
     c = _cloak(cloak)
@@ -328,6 +354,41 @@ def fresnel_out(eps_o, eps_e, chat, nhat, k_in, branch):
                                _ptr(T), _ptr(R))
     assert st == 0
     return float(T[0]), R
+
+
+def fresnel_in_pol(eps_o, eps_e, chat, nhat, kin, e_in):
+    """Eq. (12) at the entry for the incident vacuum field along e_in:
+    ((T_o, T_e), R)."""
+    chat, nhat, kin, e_in = (np.ascontiguousarray(a, dtype=np.float64) for a in (chat, nhat, kin, e_in))
+    T = np.empty(2)
+    R = np.empty(1)
+    st = lib().orc_fresnel_in_pol(float(eps_o), float(eps_e), _ptr(chat), _ptr(nhat), _ptr(kin), _ptr(e_in),
+                                  _ptr(T), _ptr(R))
+    assert st == 0
+    return T, float(R[0])
+
+
+def goggle_axis(camera, d, goggle):
+    """Transmission axis of goggle 0 (in-plane) or 1 (axial) for the unit ray
+    direction d of `camera`."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    e = np.empty(3)
+    cm = _camera(camera)
+    assert lib().orc_goggle_axis(ctypes.byref(cm), _ptr(d), int(goggle), _ptr(e)) == 0
+    return e
+
+
+def render_goggle_weights(cloak, opts, camera, cam_index, branch, goggle, ids):
+    """Per sample, the share of its light that reaches the camera through
+    goggle `goggle` (0 in-plane, 1 axial) by way of `branch`."""
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    n = ids.shape[0]
+    wg = np.empty(n)
+    c = _cloak(cloak)
+    o, cm = _opts(opts), _camera(camera)
+    lib().orc_render_goggle(ctypes.byref(c) if c is not None else None, ctypes.byref(o), ctypes.byref(cm),
+                            int(cam_index), int(branch), int(goggle), n, _ptr(ids, c_int64_p), _ptr(wg))
+    return wg
 
 
 def camera_ray(camera, cam_index, sample_id):

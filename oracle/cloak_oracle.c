@@ -875,64 +875,107 @@ static void tangential(const zc E[3], const zc H[3], const double t1[3], const d
     col[3] = H[0] * t2[0] + H[1] * t2[1] + H[2] * t2[2];
 }
 
-int32_t orc_fresnel_in(double eps_o, double eps_e, const double chat[3], const double nhat[3],
-                       const double kin[3], double T[2], double *R) {
-    double kn = dot3(kin, nhat), kt[3], t1[3], t2[3];
+/* the waves of an entry: the two reflected vacuum polarizations (s along
+   t2, perpendicular to the plane of incidence, and p) and the two
+   refracted crystal waves, as field pairs */
+typedef struct {
+    double t1[3], t2[3];
+    zc s[3], ki[3];
+    zc Es[3], Hs[3], Ep[3], Hp[3], Eo[3], Ho[3], Ee[3], He[3];
+} entry_waves;
+
+static void entry_setup(double eps_o, double eps_e, const double chat[3], const double nhat[3],
+                        const double kin[3], entry_waves *w) {
+    double kn = dot3(kin, nhat), kt[3];
     for (int i = 0; i < 3; i++) kt[i] = kin[i] - kn * nhat[i];
-    tangent_basis(nhat, kt, t1, t2);
+    tangent_basis(nhat, kt, w->t1, w->t2);
     double ktt = dot3(kt, kt);
     zc qr = q_iso(1.0, ktt, +1), qo = q_iso(eps_o, ktt, -1), qe = q_extra(eps_o, eps_e, chat, nhat, kt, -1);
-    zc kr[3], ko[3], ke[3], ki[3];
+    zc kr[3], ko[3], ke[3];
     for (int i = 0; i < 3; i++) {
         kr[i] = kt[i] + qr * nhat[i];
         ko[i] = kt[i] + qo * nhat[i];
         ke[i] = kt[i] + qe * nhat[i];
-        ki[i] = kin[i];
+        w->ki[i] = kin[i];
+        w->s[i] = w->t2[i];
     }
-    /* vacuum polarizations: s along t2 (perpendicular to the plane of incidence) */
-    zc s[3] = { t2[0], t2[1], t2[2] }, Es[3], Hs[3], Ep[3], Hp[3], Eo[3], Ho[3], Ee[3], He[3];
-    for (int i = 0; i < 3; i++) Es[i] = s[i];
-    zcross(kr, Es, Hs);
-    zcross(kr, Es, Ep);
-    zcross(kr, Ep, Hp);
-    crystal_mode(eps_o, eps_e, chat, 1, ko, t1, Eo, Ho);
-    crystal_mode(eps_o, eps_e, chat, 0, ke, t1, Ee, He);
+    for (int i = 0; i < 3; i++) w->Es[i] = w->s[i];
+    zcross(kr, w->Es, w->Hs);
+    zcross(kr, w->Es, w->Ep);
+    zcross(kr, w->Ep, w->Hp);
+    crystal_mode(eps_o, eps_e, chat, 1, ko, w->t1, w->Eo, w->Ho);
+    crystal_mode(eps_o, eps_e, chat, 0, ke, w->t1, w->Ee, w->He);
+}
+
+/* continuity of tangential E and H for the incident field Ei (transverse to
+   kin): the flux into each wave over the incident flux */
+static int entry_solve(const entry_waves *w, const double nhat[3], const zc Ei[3], double *To, double *Te,
+                       double *Rr) {
+    zc Hi[3];
+    zcross(w->ki, Ei, Hi);
+    zc cols[4][4], A[4][4], b[4], x[4];
+    tangential(w->Es, w->Hs, w->t1, w->t2, cols[0]);
+    tangential(w->Ep, w->Hp, w->t1, w->t2, cols[1]);
+    tangential(w->Eo, w->Ho, w->t1, w->t2, cols[2]);
+    tangential(w->Ee, w->He, w->t1, w->t2, cols[3]);
+    zc inc[4];
+    tangential(Ei, Hi, w->t1, w->t2, inc);
+    for (int r = 0; r < 4; r++) {
+        A[r][0] = cols[0][r];
+        A[r][1] = cols[1][r];
+        A[r][2] = -cols[2][r];
+        A[r][3] = -cols[3][r];
+        b[r] = -inc[r];
+    }
+    if (zsolve4(A, b, x)) return 1;
+    double si = fabs(zflux(Ei, Hi, nhat));
+    zc E1[3], H1[3];
+    for (int i = 0; i < 3; i++) { E1[i] = x[2] * w->Eo[i]; H1[i] = x[2] * w->Ho[i]; }
+    *To = fabs(zflux(E1, H1, nhat)) / si;
+    for (int i = 0; i < 3; i++) { E1[i] = x[3] * w->Ee[i]; H1[i] = x[3] * w->He[i]; }
+    *Te = fabs(zflux(E1, H1, nhat)) / si;
+    for (int i = 0; i < 3; i++) { E1[i] = x[0] * w->Es[i] + x[1] * w->Ep[i]; H1[i] = x[0] * w->Hs[i] + x[1] * w->Hp[i]; }
+    *Rr = fabs(zflux(E1, H1, nhat)) / si;
+    return 0;
+}
+
+int32_t orc_fresnel_in(double eps_o, double eps_e, const double chat[3], const double nhat[3],
+                       const double kin[3], double T[2], double *R) {
+    entry_waves w;
+    entry_setup(eps_o, eps_e, chat, nhat, kin, &w);
     double To = 0.0, Te = 0.0, Rr = 0.0;
     for (int pol = 0; pol < 2; pol++) {
-        zc Ei[3], Hi[3];
+        zc Ei[3];
         if (pol == 0) {
-            for (int i = 0; i < 3; i++) Ei[i] = s[i];
+            for (int i = 0; i < 3; i++) Ei[i] = w.s[i];
         } else {
-            zcross(ki, s, Ei);
+            zcross(w.ki, w.s, Ei);
         }
-        zcross(ki, Ei, Hi);
-        zc cols[4][4], A[4][4], b[4], x[4];
-        tangential(Es, Hs, t1, t2, cols[0]);
-        tangential(Ep, Hp, t1, t2, cols[1]);
-        tangential(Eo, Ho, t1, t2, cols[2]);
-        tangential(Ee, He, t1, t2, cols[3]);
-        zc inc[4];
-        tangential(Ei, Hi, t1, t2, inc);
-        for (int r = 0; r < 4; r++) {
-            A[r][0] = cols[0][r];
-            A[r][1] = cols[1][r];
-            A[r][2] = -cols[2][r];
-            A[r][3] = -cols[3][r];
-            b[r] = -inc[r];
-        }
-        if (zsolve4(A, b, x)) return 1;
-        double si = fabs(zflux(Ei, Hi, nhat));
-        zc E1[3], H1[3];
-        for (int i = 0; i < 3; i++) { E1[i] = x[2] * Eo[i]; H1[i] = x[2] * Ho[i]; }
-        To += fabs(zflux(E1, H1, nhat)) / si;
-        for (int i = 0; i < 3; i++) { E1[i] = x[3] * Ee[i]; H1[i] = x[3] * He[i]; }
-        Te += fabs(zflux(E1, H1, nhat)) / si;
-        for (int i = 0; i < 3; i++) { E1[i] = x[0] * Es[i] + x[1] * Ep[i]; H1[i] = x[0] * Hs[i] + x[1] * Hp[i]; }
-        Rr += fabs(zflux(E1, H1, nhat)) / si;
+        double to, te, rr;
+        if (entry_solve(&w, nhat, Ei, &to, &te, &rr)) return 1;
+        To += to;
+        Te += te;
+        Rr += rr;
     }
     T[0] = 0.5 * To;
     T[1] = 0.5 * Te;
     if (R) *R = 0.5 * Rr;
+    return 0;
+}
+
+int32_t orc_fresnel_in_pol(double eps_o, double eps_e, const double chat[3], const double nhat[3],
+                           const double kin[3], const double e_in[3], double T[2], double *R) {
+    /* the transverse part of e_in, normalized */
+    double ek = dot3(e_in, kin), e[3];
+    for (int i = 0; i < 3; i++) e[i] = e_in[i] - ek * kin[i];
+    double l = norm3(e);
+    if (!(l > 1e-12)) return 1;
+    entry_waves w;
+    entry_setup(eps_o, eps_e, chat, nhat, kin, &w);
+    zc Ei[3] = { e[0] / l, e[1] / l, e[2] / l };
+    double rr;
+    if (entry_solve(&w, nhat, Ei, &T[0], &T[1], &rr)) return 1;
+    if (R) *R = rr;
     return 0;
 }
 
@@ -1044,14 +1087,15 @@ static void reflect(double *v, const double *n) {
    vacuum ray (for MISSED the input ray), opl the optical path up to p. */
 static int trace_vacuum(const orc_cloak *c, int branch, const orc_opts *o,
                         const double *o_in, const double *d_in, double *p, double *dout,
-                        double *opl, double *hres, int64_t *nsteps, double *wt) {
+                        double *opl, double *hres, int64_t *nsteps, double *wt, const double *e_pol) {
     memcpy(p, o_in, 3 * sizeof(double));
     memcpy(dout, d_in, 3 * sizeof(double));
     *opl = 0.0;
     *hres = NAN;
     /* Eq. (12) weight of the reported ray: 1 for a miss or a reflection off
        the metal end disk, the product of the entry transmission, the same-mode reflectances of internal reflections
-       and the exit transmission for an exit, 0 otherwise */
+       and the exit transmission for an exit, 0 otherwise. The entry takes
+       unpolarized light, or with e_pol the vacuum field along e_pol. */
     if (wt) *wt = 0.0;
     if (!c) {
         if (wt) *wt = 1.0;
@@ -1092,7 +1136,9 @@ static int trace_vacuum(const orc_cloak *c, int branch, const orc_opts *o,
     int bounces = 0, status;
     if (wt) {
         double Tin[2];
-        if (orc_fresnel_in(eo, ee, ch, n, d_in, Tin, NULL) == 0) w = Tin[branch];
+        int bad = e_pol ? orc_fresnel_in_pol(eo, ee, ch, n, d_in, e_pol, Tin, NULL)
+                        : orc_fresnel_in(eo, ee, ch, n, d_in, Tin, NULL);
+        if (!bad) w = Tin[branch];
     }
     for (;;) {
         int ev = o->scheme == ORC_RK4_HAM ? integrate_ham(c, branch, o, y, &t, nsteps)
@@ -1195,7 +1241,7 @@ void orc_trace(const orc_cloak *c, const orc_opts *o, int32_t branch, int64_t n,
             memcpy(p, org, sizeof(p));
             memcpy(dout, d, sizeof(dout));
         } else {
-            st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, trans ? &w : NULL);
+            st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, trans ? &w : NULL, NULL);
             if (st == ORC_EXITED || st == ORC_MISSED || st == ORC_REFLECTED) {
                 double s = leave_radius(p, dout, o->r_out);
                 for (int j = 0; j < 3; j++) p[j] += s * dout[j];
@@ -1303,7 +1349,7 @@ void orc_render_samples(const orc_cloak *c, const orc_opts *o, const orc_room *r
         double org[3], d[3], p[3], dout[3], L = 0.0, hr, w = 0.0;
         int64_t ns = 0;
         orc_camera_ray(cam, cam_index, ids[i], org, d);
-        int st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, wimg ? &w : NULL);
+        int st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, wimg ? &w : NULL, NULL);
         if (wimg) {
             /* share of the sample's unpolarized light that this branch carries
                to the room (Eq. (12)): a ray that stays in vacuum (a miss, or
@@ -1329,6 +1375,63 @@ void orc_render_samples(const orc_cloak *c, const orc_opts *o, const orc_room *r
             for (int j = 0; j < 3; j++) { rec[j * n + i] = p[j]; rec[(3 + j) * n + i] = dout[j]; }
             rec[6 * n + i] = L;
         }
+    }
+}
+
+/* Polarizer goggles in front of the camera (Sect. 4, Figs. 1d,e and 2d,e).
+   The in-plane goggle transmits the field along the camera's horizontal axis
+   R = F x up / |F x up| (at elevation 0 the horizontal is the cross-section
+   plane of the upright cylinder, the cloaking plane), the axial goggle the
+   orthogonal one; for a ray of unit direction d the axes are the projection
+   of R on the plane normal to d and d x that projection, an orthonormal pair
+   transverse to d. */
+int32_t orc_goggle_axis(const orc_camera *cam, const double d[3], int32_t goggle, double e[3]) {
+    double F[3], R[3];
+    for (int i = 0; i < 3; i++) F[i] = cam->look[i] - cam->eye[i];
+    normalize3(F);
+    cross3(F, cam->up, R);
+    normalize3(R);
+    double rd = dot3(R, d), a[3];
+    for (int i = 0; i < 3; i++) a[i] = R[i] - rd * d[i];
+    double l = norm3(a);
+    if (!(l > 1e-12)) return 1;
+    for (int i = 0; i < 3; i++) a[i] /= l;
+    if (goggle == 0) {
+        memcpy(e, a, sizeof(a));
+    } else {
+        cross3(d, a, e);
+    }
+    return 0;
+}
+
+/* Share of each sample's light that reaches the camera through goggle
+   `goggle` (0 in-plane, 1 axial) by way of this branch. Unpolarized light
+   from the room behind a polarizer keeps half its intensity: a ray that stays
+   in vacuum (a miss, or the metal end disk, which reflects every
+   polarization) gives each of the two branch images 1/4. For a ray through
+   the crystal, reciprocity turns the polarizer into the polarization of the
+   camera ray: the light of the room enters the crystal unpolarized at the
+   far side and leaves towards the camera, and the flux it carries into the
+   goggle's polarization equals 1/2 (the unpolarized room light's share of
+   one polarization) times the transmission of the reversed path, which
+   enters with the goggle's field: 1/2 x (entry transmission of the goggle's
+   field into the branch) x (internal reflectances) x (exit transmission).
+   The two goggles' weights add up to the unpolarized image weight. */
+void orc_render_goggle(const orc_cloak *c, const orc_opts *o, const orc_camera *cam, int32_t cam_index,
+                       int32_t branch, int32_t goggle, int64_t n, const int64_t *ids, double *wg) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+        double org[3], d[3], p[3], dout[3], L = 0.0, hr, w = 0.0, e[3];
+        int64_t ns = 0;
+        orc_camera_ray(cam, cam_index, ids[i], org, d);
+        double wi = 0.0;
+        if (orc_goggle_axis(cam, d, goggle, e) == 0) {
+            int st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, &w, e);
+            if (st == ORC_MISSED) wi = 0.25;
+            else if (st == ORC_EXITED) wi = 0.5 * w;
+            else if (st == ORC_REFLECTED && c && sqrt(p[0] * p[0] + p[1] * p[1]) <= c->a) wi = 0.25;
+        }
+        wg[i] = wi;
     }
 }
 

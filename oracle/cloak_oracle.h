@@ -90,12 +90,34 @@ void orc_render_samples(const orc_cloak *c, const orc_opts *o, const orc_room *r
 int32_t orc_fresnel_in(double eps_o, double eps_e, const double chat[3], const double nhat[3],
                        const double kin[3], double T[2], double *R);
 
+/* Eq. (12) at the entry for one linear polarization: the incident vacuum
+   field along e_in (its part transverse to kin is used, normalized); T[0],
+   T[1] the fluxes into the ordinary and extraordinary waves and R the
+   reflected flux, over the incident flux. The mean over any two orthogonal
+   e_in is orc_fresnel_in. Returns nonzero if e_in has no transverse part or
+   the continuity system is singular. */
+int32_t orc_fresnel_in_pol(double eps_o, double eps_e, const double chat[3], const double nhat[3],
+                           const double kin[3], const double e_in[3], double T[2], double *R);
+
 /* Eq. (12) at the exit: an ordinary or extraordinary wave with wave vector
    k_in (power towards +nhat) meets the crystal/vacuum interface; T is the
    transmitted fraction (0 under total internal reflection), R[0] and R[1]
    the fractions reflected into the ordinary and extraordinary waves. */
 int32_t orc_fresnel_out(double eps_o, double eps_e, const double chat[3], const double nhat[3],
                         const double k_in[3], int32_t branch, double *T, double R[2]);
+
+/* Polarizer goggles (Sect. 4, Figs. 1d,e and 2d,e): e = the transmission
+   axis of goggle 0 (in-plane: the camera's horizontal axis projected on the
+   plane normal to the unit ray direction d) or 1 (axial: d x that
+   projection). Returns nonzero if the projection vanishes. */
+int32_t orc_goggle_axis(const orc_camera *cam, const double d[3], int32_t goggle, double e[3]);
+
+/* Per camera sample (ids as orc_render_samples), the share of its light that
+   reaches the camera through goggle `goggle` by way of branch `branch`: 1/4
+   for a ray that stays in vacuum, 1/2 x the trace weight with the goggle's
+   field at the entry for a ray through the crystal, 0 otherwise. */
+void orc_render_goggle(const orc_cloak *c, const orc_opts *o, const orc_camera *cam, int32_t cam_index,
+                       int32_t branch, int32_t goggle, int64_t n, const int64_t *ids, double *wg);
 
 /* Pieces exposed for the pin tests. */
 void orc_eps_cyl(const orc_cloak *c, double r, double out3[3]);

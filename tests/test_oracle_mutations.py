@@ -29,6 +29,21 @@ MUTATIONS = [
      "if (!(fabs(hamiltonian(c, branch, y) - 1.0) <= 1e-3)) { status = ORC_DIVERGED; break; }",
      "",
      (P.test_diverged_rule_at_outer_interfaces,)),
+    ("goggle axes swapped",
+     "    if (goggle == 0) {\n        memcpy(e, a, sizeof(a));",
+     "    if (goggle != 0) {\n        memcpy(e, a, sizeof(a));",
+     (P.test_goggle_axes_are_an_orthonormal_pair_along_the_camera_frame,
+      P.test_inplane_goggle_passes_the_design_polarization_on_the_centre_row)),
+    ("polarized entry always takes the s wave",
+     "    zc Ei[3] = { e[0] / l, e[1] / l, e[2] / l };",
+     "    zc Ei[3] = { w.s[0], w.s[1], w.s[2] };",
+     (P.test_polarized_entry_is_textbook_fresnel_with_the_mixing_angle,
+      P.test_polarized_entry_conserves_energy_and_averages_to_unpolarized)),
+    ("goggle weight of a crystal path without the polarizer's half",
+     "            else if (st == ORC_EXITED) wi = 0.5 * w;",
+     "            else if (st == ORC_EXITED) wi = w;",
+     (P.test_goggle_images_split_the_unpolarized_image,
+      P.test_inplane_goggle_passes_the_design_polarization_on_the_centre_row)),
 ]
 
 

@@ -819,6 +819,146 @@ def test_fresnel_conserves_energy_and_reflects_totally():
         assert Tt == pytest.approx(0.0, abs=1e-12) and Rr.sum() == pytest.approx(1.0, abs=1e-11)
 
 
+def _rp_axis_in_plane(eps_par, eps_perp_n, ci, si):
+    """TM reflection amplitude for an optic axis in the plane of incidence,
+    eps_par the permittivity along the surface in that plane and eps_perp_n
+    along the normal: k_n = sqrt(eps_par (1 - sin^2 / eps_perp_n)), and
+    r_p = (eps_par cos - k_n) / (eps_par cos + k_n)."""
+    kn = math.sqrt(eps_par * (1.0 - si * si / eps_perp_n))
+    return (eps_par * ci - kn) / (eps_par * ci + kn)
+
+
+def test_polarized_entry_is_textbook_fresnel_with_the_mixing_angle():
+    """A linear polarization at angle chi to s splits by the squares of
+    cos chi and sin chi when the two crystal waves are the s and the p wave:
+    isotropic (any axis along the normal), the uniaxial axis along the normal
+    (the radial cloak's side) and the axis in the surface within the plane
+    of incidence (the azimuthal cloak's side, in-plane rays): T_o = cos^2 chi
+    (1 - r_s^2), T_e = sin^2 chi (1 - r_p^2), R = cos^2 chi r_s^2 +
+    sin^2 chi r_p^2."""
+    nz = np.array([0.0, 0.0, 1.0])
+    cases = []
+    for nn in (1.3, 2.0):  # isotropic: r_p of the textbook
+        cases.append((nn * nn, nn * nn, nz, lambda ci, si, e=nn * nn: _rp_axis_in_plane(e, e, ci, si)))
+    for eo, ee in ((4.0, 1.0), (2.25, 3.0)):  # axis along the normal: eps_par = eo, normal ee
+        cases.append((eo, ee, nz, lambda ci, si, eo=eo, ee=ee: _rp_axis_in_plane(eo, ee, ci, si)))
+    for eo, ee in ((1.0, 4.0), (2.0, 3.5)):  # axis along x (in the surface and the plane of incidence)
+        cases.append((eo, ee, np.array([1.0, 0.0, 0.0]), lambda ci, si, eo=eo, ee=ee: _rp_axis_in_plane(ee, eo, ci, si)))
+    for eo, ee, c, rp_of in cases:
+        # at normal incidence along the axis the two crystal waves are one
+        # degenerate wave, and which polarization is "ordinary" is a convention
+        for th in ((0.4, 1.0, 1.4) if c[2] == 1.0 else (0.0, 0.4, 1.0, 1.4)):
+            ci, si = math.cos(th), math.sin(th)
+            kin = np.array([si, 0.0, -ci])
+            s_hat = np.array([0.0, 1.0, 0.0])
+            p_hat = np.cross(kin, s_hat)
+            rs = (ci - math.sqrt(eo - si * si)) / (ci + math.sqrt(eo - si * si))
+            rp = rp_of(ci, si)
+            for chi in (0.0, 0.3, 0.9, math.pi / 2):
+                e_in = math.cos(chi) * s_hat + math.sin(chi) * p_hat
+                T, R = oracle.fresnel_in_pol(eo, ee, c, nz, kin, e_in)
+                c2, s2 = math.cos(chi) ** 2, math.sin(chi) ** 2
+                assert T[0] == pytest.approx(c2 * (1.0 - rs * rs), abs=1e-12)
+                assert T[1] == pytest.approx(s2 * (1.0 - rp * rp), abs=1e-12)
+                assert R == pytest.approx(c2 * rs * rs + s2 * rp * rp, abs=1e-12)
+
+
+def test_polarized_entry_conserves_energy_and_averages_to_unpolarized():
+    """Random axes, directions and polarizations: T_o + T_e + R = 1; and
+    unpolarized light is the incoherent mean of any two orthogonal linear
+    polarizations, so the mean over a random orthonormal pair transverse to
+    the ray is the unpolarized transmission (the oracle's unpolarized entry
+    uses the fixed s and p pair)."""
+    rng = np.random.default_rng(23)
+    nz = np.array([0.0, 0.0, 1.0])
+    for _ in range(40):
+        eo, ee = rng.uniform(0.5, 5.0, 2)
+        c = _unit(rng.normal(size=3))
+        kin = _unit(rng.normal(size=3))
+        kin[2] = -abs(kin[2]) - 0.05
+        kin = _unit(kin)
+        a = rng.normal(size=3)
+        e1 = _unit(a - a.dot(kin) * kin)
+        e2 = np.cross(kin, e1)
+        T1, R1 = oracle.fresnel_in_pol(eo, ee, c, nz, kin, e1)
+        T2, R2 = oracle.fresnel_in_pol(eo, ee, c, nz, kin, e2)
+        for T, R in ((T1, R1), (T2, R2)):
+            assert (T >= 0).all() and R >= 0 and T.sum() + R == pytest.approx(1.0, abs=1e-11)
+        Tu, Ru = oracle.fresnel_in(eo, ee, c, nz, kin)
+        assert 0.5 * (T1 + T2) == pytest.approx(Tu, abs=1e-12)
+        assert 0.5 * (R1 + R2) == pytest.approx(Ru, abs=1e-12)
+
+
+def test_goggle_axes_are_an_orthonormal_pair_along_the_camera_frame():
+    """The in-plane goggle's axis is the camera's horizontal R projected
+    transverse to the ray, the axial one completes the pair; on the optical
+    axis they are R and the camera's up vector (up to sign)."""
+    cam = W.orbit_camera(0.7, 20.0, 33, 33)
+    F = np.array(cam["look"]) - np.array(cam["eye"])
+    F /= np.linalg.norm(F)
+    Rv = _unit(np.cross(F, cam["up"]))
+    U = np.cross(Rv, F)
+    e0, e1 = oracle.goggle_axis(cam, F, 0), oracle.goggle_axis(cam, F, 1)
+    assert e0 == pytest.approx(Rv, abs=1e-15)
+    assert abs(e1.dot(U)) == pytest.approx(1.0, abs=1e-15)
+    for sid in (0, 100, 545, 1088):
+        _, d = oracle.camera_ray(cam, 0, sid)
+        e0, e1 = oracle.goggle_axis(cam, d, 0), oracle.goggle_axis(cam, d, 1)
+        for a, b in ((e0, d), (e1, d), (e0, e1)):
+            assert abs(a.dot(b)) < 1e-15
+        assert np.linalg.norm(e0) == pytest.approx(1.0, abs=1e-15)
+        assert np.linalg.norm(e1) == pytest.approx(1.0, abs=1e-15)
+        # e0 lies in the plane of R and the ray, on R's side
+        assert abs(e0.dot(np.cross(Rv, d))) < 1e-15 and e0.dot(Rv) > 0.5
+
+
+def test_goggle_images_split_the_unpolarized_image():
+    """Per sample and branch, the two goggles' weights add up to the
+    unpolarized image weight (misses, the metal end disk, crystal paths),
+    and a ray that stays in vacuum gives each goggle and branch 1/4."""
+    cam = W.orbit_camera(0.4, 25.0, 24, 24, spp=1)
+    ids = np.arange(24 * 24)
+    for axis in (0, 1):
+        cl = W.cloak(axis, height=W.HEIGHT)
+        for br in (O, E):
+            r = oracle.render_samples(cl, W.render_opts(), W.room(), cam, 0, br, ids, weights=True)
+            g0 = oracle.render_goggle_weights(cl, W.render_opts(), cam, 0, br, 0, ids)
+            g1 = oracle.render_goggle_weights(cl, W.render_opts(), cam, 0, br, 1, ids)
+            assert g0 + g1 == pytest.approx(r["wimg"], abs=1e-12)
+            miss = r["status"] == 1
+            assert miss.sum() > 50 and (g0[miss] == 0.25).all() and (g1[miss] == 0.25).all()
+            cross = r["status"] == 0
+            assert cross.sum() > 50 and (np.abs(g0[cross] - g1[cross]) > 1e-3).any()
+
+
+def test_inplane_goggle_passes_the_design_polarization_on_the_centre_row():
+    """At elevation 0 the centre row's rays lie in the cross-section plane,
+    the plane in which both cloaks are designed to cloak light polarized in
+    that plane (Sect. 4, Sect. 5 / Fig. 3). There the in-plane goggle's
+    field lies in that plane: in the radial cloak (axis along the normal)
+    and in the azimuthal cloak (axis along theta, in the plane) such a field
+    excites only the extraordinary wave, so through the in-plane goggle the
+    extraordinary branch carries its whole unpolarized share (twice half of
+    it) and the ordinary branch nothing, and through the axial goggle the
+    reverse."""
+    h = 41
+    cam = W.orbit_camera(0.3, 0.0, 64, h, spp=1)
+    ids = (h // 2) * 64 + np.arange(64)
+    for axis in (0, 1):
+        cl = W.cloak(axis, height=W.HEIGHT)
+        for br in (O, E):
+            r = oracle.render_samples(cl, W.render_opts(), W.room(), cam, 0, br, ids, weights=True)
+            cross = r["status"] == 0
+            assert cross.sum() > 8
+            g0 = oracle.render_goggle_weights(cl, W.render_opts(), cam, 0, br, 0, ids)[cross]
+            g1 = oracle.render_goggle_weights(cl, W.render_opts(), cam, 0, br, 1, ids)[cross]
+            w = r["wimg"][cross]
+            assert (w > 0.01).all()
+            on, off = (g0, g1) if br == E else (g1, g0)
+            assert on == pytest.approx(w, rel=1e-10, abs=1e-14)
+            assert np.abs(off).max() < 1e-12
+
+
 def test_trace_weights():
     """The Eq. (12) weight of a traced ray: 1 for a miss, in (0, 1] for an
     exit, 0 otherwise; the azimuthal cloak's ordinary index is 1 at r = b, so
