@@ -149,7 +149,22 @@ typedef struct {
    branch 1/2; one that crosses the crystal gives its branch the weight
    rt_trace_batch reports as trans; light reflected at the crystal surface
    is not imaged. Needs pol_mask = 3 and RT_PREC_FP64, else RT_E_UNSUPPORTED
-   (and always in rt_render_surrogate). */
+   (and always in rt_render_surrogate).
+   goggle_inplane, goggle_axial: the images through a linear polarizer in
+   front of the camera (Sect. 4, Figs. 1d,e and 2d,e), laid out as unpol.
+   The in-plane goggle transmits the field along the camera's horizontal
+   axis (F x up), which at elevation 0 lies in the cylinder's cross-section,
+   the plane the cloaks are designed for: the paper's cylinder lies
+   horizontally, so this is its "vertical" goggle (Fig. 1d, 2d), and the
+   axial goggle its "horizontal" one (Fig. 1e, 2e). For a sample of unit
+   direction d the axes are the horizontal axis projected transverse to d
+   and d x that projection. Room light is unpolarized: a sample that stays
+   in vacuum gives each goggle half its light (1/4 per branch); for one
+   through the crystal, by reciprocity, the goggle's share is half its trace
+   weight with the entry taking the goggle's field instead of unpolarized
+   light (entry transmission of that field into the branch x internal
+   reflectances x exit transmission). The two goggle images add up to the
+   unpolarized one. Same requirements as unpol. */
 typedef struct {
     double *rec;
     int32_t *status;
@@ -157,6 +172,8 @@ typedef struct {
     int32_t *nsteps;
     float *tof;
     float *unpol;
+    float *goggle_inplane;
+    float *goggle_axial;
 } rt_render_aux;
 
 /* Build a cloak handle (host-side constants; no device memory).

@@ -577,6 +577,42 @@ __device__ __forceinline__ double fresnel_in_dev(double eo, double ee, const dou
   return 0.5 * T;
 }
 
+// Transmission from vacuum into the crystal wave of `extra` for the
+// incident field along the unit vector e (transverse to d), and (Tun) for
+// unpolarized light as fresnel_in_dev computes it. With s along t2 (normal
+// to the plane of incidence) and p = d x s, e = alpha s + beta p, and by
+// linearity the crystal amplitude is alpha a_s + beta a_p.
+__device__ __forceinline__ double fresnel_in_pol_dev(double eo, double ee, const double cax[3], const double n[3],
+                                                     const double d[3], int extra, const double e[3], double &Tun) {
+  double t1[3], t2[3], k1;
+  interface_basis(n, d, t1, t2, k1);
+  const double c[3] = {cax[0] * t1[0] + cax[1] * t1[1] + cax[2] * t1[2],
+                       cax[0] * t2[0] + cax[1] * t2[1] + cax[2] * t2[2],
+                       cax[0] * n[0] + cax[1] * n[1] + cax[2] * n[2]};
+  const double qi = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];  // < 0
+  const cplx qr = q_iso_dev(1.0, k1, +1);
+  const cplx qo = q_iso_dev(eo, k1, -1), qe = q_extra_dev(eo, ee, c, k1, -1);
+  cplx fo[4], fe[4];
+  crystal_tangential(eo, ee, c, true, k1, qo, fo);
+  crystal_tangential(eo, ee, c, false, k1, qe, fe);
+  const cplx y22 = cdiv(cx(k1 * k1) + qr * qr, qr);
+  const cplx A[2] = {fo[2] - (cx(0.0) - qr * fo[1]), fo[3] - y22 * fo[0]};
+  const cplx B[2] = {fe[2] - (cx(0.0) - qr * fe[1]), fe[3] - y22 * fe[0]};
+  // s and p as in fresnel_in_dev, one incident flux |qi| / 2 for both
+  const cplx rs[2] = {cx(-qi) - (cx(0.0) - qr * cx(1.0)), cx(0.0)};
+  const cplx rp[2] = {cx(0.0), cx(-qi * qi - k1 * k1) - y22 * cx(-qi)};
+  cplx aos, aes, aop, aep;
+  solve2(A, B, rs, aos, aes);
+  solve2(A, B, rp, aop, aep);
+  const double si = 0.5 * fabs(qi);
+  const double f = extra ? fabs(flux_t(fe)) : fabs(flux_t(fo));
+  const cplx as = extra ? aes : aos, ap = extra ? aep : aop;
+  Tun = 0.5 * (cabs2(as) * f / si + cabs2(ap) * f / si);
+  const double al = e[0] * t2[0] + e[1] * t2[1] + e[2] * t2[2];
+  const double be = -qi * (e[0] * t1[0] + e[1] * t1[1] + e[2] * t1[2]) + k1 * (e[0] * n[0] + e[1] * n[1] + e[2] * n[2]);
+  return cabs2(al * as + be * ap) * f / si;
+}
+
 // A crystal wave of `extra` with wave vector k (power towards +n) meets the
 // interface: transmitted fraction T and the fraction R reflected into the
 // same wave type.

@@ -847,8 +847,13 @@ struct RenderP {
   unsigned char *code;
   int *nsteps;
   float *tof;            // aux per-pixel time of flight (may be NULL)
-  float *twt;            // chunk-local Eq. (12) image weight [segment][g1-g0]; NULL unless unpol
+  float *twt;            // chunk-local Eq. (12) image weight [segment][g1-g0]; NULL unless unpol or goggles
   float *unpol;          // aux per-pixel unpolarized image, per (cloak, camera) (may be NULL)
+  // chunk-local [segment][g1-g0]: the entry transmission of the in-plane
+  // goggle's field over the unpolarized one (1 for a sample that stays in
+  // vacuum); NULL unless goggle images
+  float *grho;
+  float *gog[2];         // aux per-pixel goggle images (in-plane, axial), per (cloak, camera) (may be NULL)
 };
 
 // Surrogate render: the side entries of a chunk that go to the network
@@ -919,6 +924,36 @@ __device__ __forceinline__ void put_candidate(const CandP &C, unsigned int i, co
   C.s_in[i] = (float)s;
 }
 
+// Eq. (12) at a camera sample's entry into branch `kind` through boundary
+// surf at x, direction d: the unpolarized transmission (.x) and, with
+// goggle, the ratio to it of the transmission of the in-plane goggle's
+// field (.y, else 1). That field is the camera's horizontal axis r made
+// transverse to the ray (Figs. 1d and 2d); the axial goggle's is d x it,
+// and the two transmissions add up to twice the unpolarized one. Out of
+// line with scalar arguments, like fresnel_event: the complex solve would
+// otherwise set the register allocation of the whole generation kernel.
+__device__ __noinline__ double2 entry_weight(double kappa, double a, int kind, int surf, double x0, double x1,
+                                             double x2, double d0, double d1, double d2, double r0, double r1,
+                                             double r2, int goggle) {
+  CloakP c{};
+  c.kappa = kappa;
+  c.a = a;
+  const double x[3] = {x0, x1, x2}, d[3] = {d0, d1, d2};
+  double eo, ee, cax[3], nrm[3];
+  boundary_normal(surf, x, nrm);
+  material_axis(c, kind >> 1, x, eo, ee, cax);
+  // the unpolarized weight is the same with or without goggles
+  const double w = fresnel_in_dev(eo, ee, cax, nrm, d, kind & 1);
+  if (!goggle) return make_double2(w, 1.0);
+  const double rd = r0 * d0 + r1 * d1 + r2 * d2;
+  double e[3] = {r0 - rd * d0, r1 - rd * d1, r2 - rd * d2};
+  const double ie = 1.0 / sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+  e[0] *= ie; e[1] *= ie; e[2] *= ie;
+  double tun;
+  const double tg = fresnel_in_pol_dev(eo, ee, cax, nrm, d, kind & 1, e, tun);
+  return make_double2(w, tun > 0.0 ? tg / tun : 1.0);
+}
+
 // camera rays of a chunk; one thread per sample, every (cloak, branch).
 // SUR: side entries become surrogate candidates instead of work-table slots
 template <bool SUR>
@@ -926,7 +961,7 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
                                                 const CamP *__restrict__ cams, Table T, RenderP R, CandP Cd) {
   long long gidx = R.g0 + (long long)blockIdx.x * blockDim.x + threadIdx.x;
   bool valid = gidx < R.g1;
-  double org[3] = {0, 0, 0}, d[3] = {0, 0, 1}, x[3] = {0, 0, 0}, s = 0.0;
+  double org[3] = {0, 0, 0}, d[3] = {0, 0, 1}, x[3] = {0, 0, 0}, s = 0.0, cr[3] = {1, 0, 0};
   int surf = 0;
   bool hitc = false, disk = false;
   if (valid) {
@@ -937,6 +972,7 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
     const int smp = (int)(l32 - (unsigned int)pix * sp);
     const CamP &C = cams[cam];
     org[0] = C.eye[0]; org[1] = C.eye[1]; org[2] = C.eye[2];
+    cr[0] = C.R[0]; cr[1] = C.R[1]; cr[2] = C.R[2];
     camera_ray(C, (int)cam, pix, smp, d);
     if (R.has_cloak) hitc = vacuum_entry(c, org, d, s, surf);
     if (hitc) {
@@ -972,6 +1008,8 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
     int kind = (ci == 0 ? R.axis[0] : R.axis[1]) * 2 + (pi == 0 ? R.pol[0] : R.pol[1]);
     bool enter = false, cand = false;
     double v[3] = {0, 0, 0}, w_in = 0.0;
+    // goggle ratio 1 unless the sample enters the crystal (set below)
+    if (valid && R.grho) R.grho[(long long)q * (R.g1 - R.g0) + (gidx - R.g0)] = 1.0f;
     if (valid) {
       if (!hitc || disk) {
         rd_write(R, q, gidx, vcode, vst, vp, vd, vL, 0, 0.5f);  // vacuum light splits evenly
@@ -980,10 +1018,10 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
         if (SUR && surf == B_SIDE && NBUCKET - 1 - skey >= R.sur_min) cand = true;
         else enter = true;
         if (!SUR && R.twt) {
-          double nrm[3], eo, ee, cax[3];
-          boundary_normal(surf, x, nrm);
-          material_axis(c, kind >> 1, x, eo, ee, cax);
-          w_in = fresnel_in_dev(eo, ee, cax, nrm, d, kind & 1);
+          const double2 ew = entry_weight(c.kappa, c.a, kind, surf, x[0], x[1], x[2], d[0], d[1], d[2], cr[0],
+                                          cr[1], cr[2], R.grho != nullptr);
+          w_in = ew.x;
+          if (R.grho) R.grho[(long long)q * (R.g1 - R.g0) + (gidx - R.g0)] = (float)ew.y;
         }
       } else {
         // evanescent transmission into this branch: reflected at the entry
@@ -1166,6 +1204,34 @@ __global__ void __launch_bounds__(256) k_rd_resolve(RenderP R, const float *__re
     u[1] = ug * inv;
     u[2] = ub * inv;
   }
+  if (R.grho && pi == 0) {
+    // the goggles: half of each branch's unpolarized share (its image weight)
+    // times the ratio of the goggle field's entry transmission to the
+    // unpolarized one, rho for the in-plane goggle and 2 - rho for the axial
+    float gr[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    for (int b = 0; b < 2; ++b) {
+      const unsigned char *cb = R.codes + (q + b) * chunk + lp * R.spp;
+      const float *wb = R.twt + (q + b) * chunk + lp * R.spp;
+      const float *rb = R.grho + (q + b) * chunk + lp * R.spp;
+      for (int k = 0; k < R.spp; ++k) {
+        const int cc = cb[k];
+        const float w0 = 0.5f * wb[k] * rb[k], w1 = wb[k] - w0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          gr[0][j] = fmaf(w0, tab[3 * cc + j], gr[0][j]);
+          gr[1][j] = fmaf(w1, tab[3 * cc + j], gr[1][j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      if (!R.gog[g]) continue;
+      float *u = R.gog[g] + (((long long)ci * R.n_cams + cam) * npix + pix) * 3;
+      u[0] = gr[g][0] * inv;
+      u[1] = gr[g][1] * inv;
+      u[2] = gr[g][2] * inv;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1185,7 +1251,8 @@ struct Workspace {
   Table T{};
   unsigned char *codes = nullptr;
   float *topl = nullptr;  // per-sample optical path of a chunk (time-of-flight images)
-  float *twt = nullptr;   // per-sample Eq. (12) image weight of a chunk (unpolarized images)
+  float *twt = nullptr;   // per-sample Eq. (12) image weight of a chunk (unpolarized and goggle images)
+  float *grho = nullptr;  // per-sample goggle ratio of a chunk (goggle images)
   CamP *cams = nullptr;
   float *table = nullptr;
 };
@@ -1286,6 +1353,7 @@ int ws_reserve(Workspace &ws, long long cap, long long codes_len, int ncam) {
   size_t o_codes = take((size_t)codes_len);
   size_t o_topl = take(sizeof(float) * (size_t)codes_len);
   size_t o_twt = take(sizeof(float) * (size_t)codes_len);
+  size_t o_grho = take(sizeof(float) * (size_t)codes_len);
   size_t o_cams = take(sizeof(CamP) * ncam);
   size_t o_tab = take(sizeof(float) * 64);
   void *p = nullptr;
@@ -1301,6 +1369,7 @@ int ws_reserve(Workspace &ws, long long cap, long long codes_len, int ncam) {
   ws.codes = (unsigned char *)(b + o_codes);
   ws.topl = (float *)(b + o_topl);
   ws.twt = (float *)(b + o_twt);
+  ws.grho = (float *)(b + o_grho);
   ws.codes_len = codes_len;
   ws.cams = (CamP *)(b + o_cams);
   ws.cams_cap = ncam;
@@ -1558,7 +1627,9 @@ int prepare_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts
     if (it != g_tuned.end()) { J.block = it->second.first; J.refill = it->second.second; }
   }
   const bool unpol = aux && aux->unpol;
-  J.grid = transit_grid(J.o, J.block, unpol);
+  const bool goggles = aux && (aux->goggle_inplane || aux->goggle_axial);
+  const bool weights = unpol || goggles;  // the Eq. (12) weights ride in the integrator
+  J.grid = transit_grid(J.o, J.block, weights);
   RenderP &R = J.R;
   R.ns_img = ns_img; R.n_cams = n_cams; R.ncl = ncl; R.npol = npol; R.spp = spp;
   R.axis[0] = n_cloaks > 0 ? cloaks[0]->d.axis : 0;
@@ -1575,10 +1646,13 @@ int prepare_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts
   R.tof = aux ? aux->tof : nullptr;
   R.topl = nullptr;
   R.unpol = unpol ? aux->unpol : nullptr;
+  R.gog[0] = goggles ? aux->goggle_inplane : nullptr;
+  R.gog[1] = goggles ? aux->goggle_axial : nullptr;
   R.twt = nullptr;
-  if (unpol && npol != 2)
-    return fail(RT_E_UNSUPPORTED, "the unpolarized image needs both branches (pol_mask = 3)");
-  if (unpol && opts->precision != RT_PREC_FP64)
+  R.grho = nullptr;
+  if (weights && npol != 2)
+    return fail(RT_E_UNSUPPORTED, "the unpolarized and goggle images need both branches (pol_mask = 3)");
+  if (weights && opts->precision != RT_PREC_FP64)
     return fail(RT_E_UNSUPPORTED, "the Eq. (12) weights are computed in FP64 only");
   return RT_OK;
 }
@@ -1603,7 +1677,9 @@ void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStre
   RenderP R = J.R;
   R.codes = ws.codes;
   R.topl = R.tof ? ws.topl : nullptr;
-  R.twt = R.unpol ? ws.twt : nullptr;
+  const bool goggles = R.gog[0] || R.gog[1];
+  R.twt = R.unpol || goggles ? ws.twt : nullptr;
+  R.grho = goggles ? ws.grho : nullptr;
   for (long long g0 = 0; g0 < J.total; g0 += J.chunk) {
     R.g0 = g0;
     R.g1 = std::min(J.total, g0 + J.chunk);
@@ -1611,7 +1687,7 @@ void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStre
     hipLaunchKernelGGL(k_rd_gen<false>, dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
                        ws.cams, T, R, CandP{});
     if (J.n_cloaks) {
-      run_transit(J.c, J.o, T, J.block, J.refill, J.grid, s, profile, R.unpol != nullptr);
+      run_transit(J.c, J.o, T, J.block, J.refill, J.grid, s, profile, R.twt != nullptr);
       hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, J.c, J.rm, T, R);
     }
     long long nres = (R.g1 - R.g0) / R.spp * R.ncl * R.npol;
@@ -1672,7 +1748,8 @@ int cws_reserve(CandWs &w, long long cap) {
 // accepted.
 int render_surrogate(rt_model model, const rt_cloak_desc &desc, const RenderJob &J, const Workspace &ws,
                      const CandWs &cw, int min_difficulty, float *rgb, hipStream_t s, long long counts[2]) {
-  if (J.R.unpol) return fail(RT_E_UNSUPPORTED, "the surrogate render makes no unpolarized image");
+  if (J.R.unpol || J.R.gog[0] || J.R.gog[1])
+    return fail(RT_E_UNSUPPORTED, "the surrogate render makes no unpolarized or goggle image");
   const Table &T = ws.T;
   RenderP R = J.R;
   R.sur_min = min_difficulty;

@@ -51,7 +51,8 @@ def test_struct_layouts_match_header():
                                          "max_bounces", "refill_period", "max_chunk"]),
         "rt_camera": (rt.Camera, ["eye", "fov_deg", "w", "spp", "seed"]),
         "rt_room": (rt.Room, ["lo", "tile", "rgb"]),
-        "rt_render_aux": (rt.RenderAux, ["rec", "status", "code", "nsteps", "tof"]),
+        "rt_render_aux": (rt.RenderAux, ["rec", "status", "code", "nsteps", "tof", "unpol", "goggle_inplane",
+                                         "goggle_axial"]),
         "rt_train_opts": (rt.TrainOpts, ["lr", "eps", "weight_decay"]),
         "rt_gate_opts": (rt.GateOpts, ["tol", "hres_max", "cap_margin", "min_count", "dilate", "unresolved", "p_min"]),
     }

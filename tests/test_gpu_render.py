@@ -310,12 +310,51 @@ def test_unpolarized_image_parity(spp):
         c.close()
 
 
+@pytest.mark.parametrize("spp", [1, 4])
+def test_goggle_image_parity(spp):
+    """The images through the in-plane and the axial polarizer
+    (rt_render_aux.goggle_inplane / goggle_axial, Figs. 1d,e and 2d,e) of both
+    cloaks in one call against the oracle's per-sample goggle weights; the
+    branch images and the unpolarized image are those of the call without
+    goggles, the two goggles add up to the unpolarized image, and without a
+    cloak each goggle sees half of the room."""
+    import torch
+    from paper_1209_6038_amd import rt
+    n = 32
+    cams = [W.orbit_camera(az, el, n, n, spp=spp, seed=7) for az, el in ((0.2, 0.0), (1.1, 35.0))]
+    room = W.room()
+    ds = [W.cloak(0, height=W.HEIGHT), W.cloak(1, height=W.HEIGHT)]
+    cls = [rt.Cloak(d) for d in ds]
+    say(f"case goggles spp={spp}")
+    rgb, aux = rt.render_multi(cls, W.opts_dp45(), room, cams, 3, unpolarized=True, goggles=True)
+    rgb0, aux0 = rt.render_multi(cls, W.opts_dp45(), room, cams, 3, unpolarized=True)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb, rgb0)
+    assert torch.equal(aux["unpol"], aux0["unpol"])
+    g_in, g_ax = aux["goggle_inplane"], aux["goggle_axial"]
+    assert float((g_in + g_ax - aux["unpol"]).abs().max()) <= 1e-6
+    for gi, img in enumerate((g_in.cpu().numpy(), g_ax.cpu().numpy())):
+        for ci, d in enumerate(ds):
+            for k, cam in enumerate(cams):
+                o = oracle.render_goggle_pixels(d, W.opts_dp45(), room, cam, k, np.arange(n * n), gi)
+                err = np.abs(img[ci, k].reshape(-1, 3) - o).max()
+                say(f"  goggle {gi} cloak {ci} cam {k}: max |image - oracle| = {err:.3e}, mean {img[ci, k].mean():.4f}")
+                assert err <= 1e-5
+    e_rgb, e_aux = rt.render_multi([], W.opts_dp45(), room, cams, 3, goggles=True)
+    torch.cuda.synchronize()
+    for name in ("goggle_inplane", "goggle_axial"):
+        assert torch.allclose(e_aux[name][0], 0.5 * e_rgb[0, :, 1], rtol=0, atol=1e-6)
+    for c in cls:
+        c.close()
+
+
 def test_unpolarized_image_needs_both_branches_and_fp64():
     from paper_1209_6038_amd import rt
     cam = W.orbit_camera(0.0, 0.0, 8, 8)
     cl = rt.Cloak(W.cloak(0, height=W.HEIGHT))
     for pol_mask, op in ((1, W.opts_dp45()),):
-        with pytest.raises(rt.RtError) as e:
-            rt.render_multi([cl], op, W.room(), [cam], pol_mask, unpolarized=True)
-        assert e.value.code == rt.RT_E_UNSUPPORTED
+        for kw in ({"unpolarized": True}, {"goggles": True}):
+            with pytest.raises(rt.RtError) as e:
+                rt.render_multi([cl], op, W.room(), [cam], pol_mask, **kw)
+            assert e.value.code == rt.RT_E_UNSUPPORTED
     cl.close()
