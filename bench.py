@@ -563,8 +563,9 @@ def weights_workload(args):
 
 def unpolarized_workload(args):
     """The headline render (both cloaks, 4 views of 1024^2, both branches,
-    DP45 1e-8, FP64) with the Eq. (12) unpolarized images, timed beside the
-    same render without them; one step = one rt_render_multi call."""
+    DP45 1e-8, FP64) with the Eq. (12) unpolarized images and the two
+    polarizer-goggle images, timed beside the same render without images and
+    with the unpolarized images only; one step = one rt_render_multi call."""
     import torch
     from paper_1209_6038_amd import rt
     from paper_1209_6038_amd import workloads as W
@@ -573,16 +574,17 @@ def unpolarized_workload(args):
     opts = W.render_opts(block=args.block, refill_period=args.refill)
     cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
     room = W.room()
-    _, aux = rt.render_multi(cloaks, opts, room, cams, 3, aux=True, unpolarized=True)
+    _, aux = rt.render_multi(cloaks, opts, room, cams, 3, aux=True, unpolarized=True, goggles=True)
     torch.cuda.synchronize()
     dev = aux["status"].device
     entered = int(torch.isin(aux["status"], torch.tensor(ENTERED, device=dev, dtype=torch.int32)).sum())
-    mean_unpol = float(aux["unpol"].mean())
+    means = {k: round(float(aux[k].mean()), 5) for k in ("unpol", "goggle_inplane", "goggle_axial")}
     del aux
+    modes = {"none": {}, "unpolarized": {"unpolarized": True}, "goggles": {"unpolarized": True, "goggles": True}}
     timing = {}
-    for unpol in (False, True):
+    for mode, kw in modes.items():
         for _ in range(args.warmup):
-            rt.render_multi(cloaks, opts, room, cams, 3, unpolarized=unpol)
+            rt.render_multi(cloaks, opts, room, cams, 3, **kw)
         torch.cuda.synchronize()
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
@@ -590,28 +592,31 @@ def unpolarized_workload(args):
         rt.profile_read()
         a.record()
         for _ in range(args.steps):
-            rt.render_multi(cloaks, opts, room, cams, 3, unpolarized=unpol)
+            rt.render_multi(cloaks, opts, room, cams, 3, **kw)
         b.record()
         torch.cuda.synchronize()
         transit_ms, launches = rt.profile_read()
         rt.profile_enable(False)
-        timing[unpol] = (a.elapsed_time(b) / args.steps, transit_ms / max(1, launches))
-    ms, launch_ms = timing[True]
+        timing[mode] = (a.elapsed_time(b) / args.steps, transit_ms / max(1, launches))
+    ms, launch_ms = timing["goggles"]
     return {
-        "metric": "Mrays/s traced through cloak at <=1e-6 exit error, with Eq. (12) unpolarized images",
+        "metric": "Mrays/s traced through cloak at <=1e-6 exit error, with Eq. (12) unpolarized and goggle images",
         "unit": "Mrays/s", "value": round(entered / (ms * 1e-3) / 1e6, 3), "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "3-D render with unpolarized images: radial + azimuthal cloaks (height 4), "
-                               "4 elevations x 1024^2 px, ordinary + extraordinary, DP45 tol 1e-8, FP64, "
-                               "eager calls",
-                   "entering_per_step": entered, "ms_per_step_without_images": round(timing[False][0], 4),
-                   "images_cost": round(ms / timing[False][0], 4), "mean_unpolarized_value": round(mean_unpol, 5)},
+        "config": {"workload": "3-D render with unpolarized and in-plane / axial goggle images: radial + "
+                               "azimuthal cloaks (height 4), 4 elevations x 1024^2 px, ordinary + extraordinary, "
+                               "DP45 tol 1e-8, FP64, eager calls",
+                   "entering_per_step": entered, "ms_per_step_without_images": round(timing["none"][0], 4),
+                   "ms_per_step_unpolarized_only": round(timing["unpolarized"][0], 4),
+                   "images_cost": round(ms / timing["none"][0], 4),
+                   "goggles_cost_over_unpolarized": round(ms / timing["unpolarized"][0], 4),
+                   "mean_image_values": means},
         "roofline": {"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": None, "traffic": None, "kernel": "k_transit (integrator, weighted)",
                      "avg_launch_ms": round(launch_ms, 4),
-                     "avg_launch_ms_without_images": round(timing[False][1], 4)},
+                     "avg_launch_ms_without_images": round(timing["none"][1], 4)},
     }
 
 
