@@ -144,6 +144,11 @@ def _load(path):
     L.orc_render_goggle.argtypes = [ctypes.POINTER(_Cloak), ctypes.POINTER(_Opts), ctypes.POINTER(_Camera),
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                     c_int64_p, c_double_p]
+    L.orc_trace_reflections.argtypes = [ctypes.POINTER(_Cloak), ctypes.POINTER(_Opts), ctypes.c_int32,
+                                        ctypes.c_int64, c_double_p, c_double_p, c_double_p]
+    L.orc_render_reflections.argtypes = [ctypes.POINTER(_Cloak), ctypes.POINTER(_Opts), ctypes.POINTER(_Room),
+                                         ctypes.POINTER(_Camera), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int64, c_int64_p, c_double_p, c_uint8_p]
     L.orc_camera_ray.argtypes = [ctypes.POINTER(_Camera), ctypes.c_int32, ctypes.c_int64,
                                  c_double_p, c_double_p]
     L.orc_room_code.argtypes = [ctypes.POINTER(_Room), c_double_p, c_double_p, c_double_p]
@@ -285,6 +290,56 @@ def render_goggle_pixels(cloak, opts, room, camera, cam_index, pixels, goggle):
         r = render_samples(cloak, opts, room, camera, cam_index, branch, ids)
         wg = render_goggle_weights(cloak, opts, camera, cam_index, branch, goggle, ids)
         col += wg[:, None] * table[r["code"]]
+    return col.reshape(len(pixels), spp, 3).mean(axis=1)
+
+
+def trace_reflections(cloak, opts, branch, rays):
+    """First-order reflections of vacuum rays (6 x n) through `branch`:
+    weights (3, n) and vacuum rays (3, 6, n) of the entry's reflected ray
+    (row 0) and the ordinary (1) and extraordinary (2) waves reflected at the
+    exit, each where it leaves the crystal."""
+    rays = np.ascontiguousarray(rays, dtype=np.float64)
+    n = rays.shape[1]
+    w = np.empty((3, n))
+    ray = np.empty((3, 6, n))
+    c = _cloak(cloak)
+    o = _opts(opts)
+    lib().orc_trace_reflections(ctypes.byref(c), ctypes.byref(o), int(branch), n, _ptr(rays), _ptr(w), _ptr(ray))
+    return w, ray
+
+
+def render_reflections(cloak, opts, room, camera, cam_index, branch, ids, goggle=-1):
+    """First-order reflections of samples through `branch`: weights (3, n)
+    and room codes (3, n) of the entry's reflected vacuum ray (row 0) and the
+    ordinary (1) and extraordinary (2) waves reflected at the exit; goggle -1
+    for the unpolarized image, 0 / 1 for the in-plane / axial goggle."""
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    n = ids.shape[0]
+    w = np.empty((3, n))
+    code = np.empty((3, n), dtype=np.uint8)
+    c = _cloak(cloak)
+    o, rm, cm = _opts(opts), _room(room), _camera(camera)
+    lib().orc_render_reflections(ctypes.byref(c) if c is not None else None, ctypes.byref(o), ctypes.byref(rm),
+                                 ctypes.byref(cm), int(cam_index), int(branch), int(goggle), n,
+                                 _ptr(ids, c_int64_p), _ptr(w), _ptr(code, c_uint8_p))
+    return w, code
+
+
+def render_reflection_pixels(cloak, opts, room, camera, cam_index, pixels, goggle=-1):
+    """RGB (float64, n x 3) that first-order reflections add to the given
+    pixels of the unpolarized image (goggle -1) or a goggle image (0 / 1):
+    per sample, the sum over both branches and the three contributions of
+    weight times colour, averaged over the pixel's samples."""
+    pixels = np.asarray(pixels, dtype=np.int64)
+    spp = int(camera.get("spp", 1))
+    ids = (pixels[:, None] * spp + np.arange(spp)[None, :]).reshape(-1)
+    table = np.zeros((13, 3))
+    table[:12] = np.asarray(room["rgb"], dtype=np.float32).reshape(12, 3)
+    col = np.zeros((len(ids), 3))
+    for branch in (0, 1):
+        w, code = render_reflections(cloak, opts, room, camera, cam_index, branch, ids, goggle)
+        for j in range(3):
+            col += w[j][:, None] * table[code[j]]
     return col.reshape(len(pixels), spp, 3).mean(axis=1)
 
 

@@ -1083,15 +1083,120 @@ static void reflect(double *v, const double *n) {
     for (int i = 0; i < 3; i++) v[i] -= 2.0 * d * n[i];
 }
 
+/* A crystal ray where it leaves: the wave met at the exit and what the
+   interface reflects of it (Sect. 3: two reflected waves in the crystal,
+   one refracted into vacuum). */
+typedef struct {
+    double x[3], n[3], k[3];  /* exit point, outward normal, wave vector k = M v met */
+    double eo, ee, ch[3];     /* material at the exit */
+    double Rref[2];           /* fractions reflected into the ordinary and extraordinary waves */
+    double w_pre;             /* the ray's weight before the exit transmission */
+} exit_state;
+
+/* Follow a crystal ray of `branch` from y = (x, v) (inside the cloak or on
+   its boundary heading in) until it leaves: specular reflection at the inner
+   metal cylinder (radial cloak), same-mode specular reflection under total
+   internal reflection (weight x that mode's reflectance), refraction into
+   vacuum at the exit (Sect. 3). Returns the status; p/dout get the exit ray
+   (or the last state), *t the optical path. With w, *w is multiplied by the
+   reflectances and the exit transmission (0 unless the ray exits); with ex,
+   an exit fills it. */
+static int crystal_walk(const orc_cloak *c, int branch, const orc_opts *o, double *y, double *t,
+                        int64_t *nsteps, double *w, exit_state *ex, double *p, double *dout, double *hres) {
+    int bounces = 0, status;
+    for (;;) {
+        int ev = o->scheme == ORC_RK4_HAM ? integrate_ham(c, branch, o, y, t, nsteps)
+                                          : integrate(c, branch, o, y, t, nsteps);
+        if (ev == EV_MAXSTEPS) { status = ORC_MAXSTEPS; break; }
+        if (ev == EV_DIVERGED) { status = ORC_DIVERGED; break; }
+        double nn[3];
+        if (ev == EV_INNER) {
+            if (c->inner_mirror && c->axis == ORC_AXIS_RADIAL && bounces < o->max_bounces) {
+                /* optic axis along the mirror normal: one specular reflection
+                   for either ray (Sect. 4) */
+                outward_normal(SURF_SIDE, y, nn);
+                reflect(y + 3, nn);
+                bounces++;
+                continue;
+            }
+            status = ORC_ABSORBED;
+            break;
+        }
+        outward_normal(ev, y, nn);
+        /* a ray whose Hamiltonian v^T M v has drifted from 1 by more than
+           1e-3 at an outer interface is no longer a ray of the medium: its
+           direction there is not a solution of the dispersion relation, and
+           the refraction of Sect. 3 would act on an arbitrary vector */
+        if (!(fabs(hamiltonian(c, branch, y) - 1.0) <= 1e-3)) { status = ORC_DIVERGED; break; }
+        double eo2, ee2, ch2[3], dd[3], k[3];
+        material_at(c, y, &eo2, &ee2, ch2);
+        double Tout = 0.0, Rref[2] = { 0.0, 0.0 };
+        if (w || ex) {
+            /* k = M v of the wave meeting the interface */
+            double M[3][3];
+            if (branch == ORC_ORDINARY) {
+                for (int i = 0; i < 3; i++) k[i] = eo2 * y[3 + i];
+            } else {
+                metric_from_axis(eo2, ee2, ch2, M);
+                for (int i = 0; i < 3; i++) k[i] = M[i][0] * y[3] + M[i][1] * y[4] + M[i][2] * y[5];
+            }
+            if (orc_fresnel_out(eo2, ee2, ch2, nn, k, branch, &Tout, Rref) != 0) Tout = Rref[0] = Rref[1] = 0.0;
+        }
+        if (orc_refract_out(eo2, ee2, ch2, nn, y + 3, branch, dd) == 0) {
+            *hres = fabs(hamiltonian(c, branch, y) - 1.0);
+            memcpy(p, y, 3 * sizeof(double));
+            memcpy(dout, dd, sizeof(dd));
+            status = ORC_EXITED;
+            if (ex) {
+                memcpy(ex->x, y, 3 * sizeof(double));
+                memcpy(ex->n, nn, sizeof(nn));
+                memcpy(ex->k, k, sizeof(k));
+                ex->eo = eo2;
+                ex->ee = ee2;
+                memcpy(ex->ch, ch2, sizeof(ch2));
+                ex->Rref[0] = Rref[0];
+                ex->Rref[1] = Rref[1];
+                ex->w_pre = w ? *w : 0.0;
+            }
+            if (w) *w *= Tout;
+            break;
+        }
+        /* total internal reflection: same-mode specular reflection */
+        if (bounces >= o->max_bounces) { status = ORC_TIR; break; }
+        if (w) *w *= Rref[branch];
+        reflect(y + 3, nn);
+        bounces++;
+    }
+    if (status != ORC_EXITED) {
+        *hres = fabs(hamiltonian(c, branch, y) - 1.0);
+        memcpy(p, y, 3 * sizeof(double));
+        double l = norm3(y + 3);
+        for (int i = 0; i < 3; i++) dout[i] = y[3 + i] / l;
+        if (w) *w = 0.0;
+    }
+    return status;
+}
+
+/* First-order reflections of one camera ray through one branch (R27):
+   the vacuum ray reflected at its first crystal interface, and the two
+   waves the branch's ray reflects into at its exit, each followed to its
+   own exit (their own reflections are of second order and not followed). */
+typedef struct {
+    double w_ext, p_ext[3], d_ext[3];          /* reflected flux fraction R at the entry (0: none) */
+    double w_child[2], p_child[2][3], d_child[2][3];  /* weight and exit ray of the ordinary / extraordinary child */
+} orc_refl;
+
 /* Trace one vacuum ray through the cloak. On return p/dout hold the last
    vacuum ray (for MISSED the input ray), opl the optical path up to p. */
 static int trace_vacuum(const orc_cloak *c, int branch, const orc_opts *o,
                         const double *o_in, const double *d_in, double *p, double *dout,
-                        double *opl, double *hres, int64_t *nsteps, double *wt, const double *e_pol) {
+                        double *opl, double *hres, int64_t *nsteps, double *wt, const double *e_pol,
+                        orc_refl *rf) {
     memcpy(p, o_in, 3 * sizeof(double));
     memcpy(dout, d_in, 3 * sizeof(double));
     *opl = 0.0;
     *hres = NAN;
+    if (rf) memset(rf, 0, sizeof(*rf));
     /* Eq. (12) weight of the reported ray: 1 for a miss or a reflection off
        the metal end disk, the product of the entry transmission, the same-mode reflectances of internal reflections
        and the exit transmission for an exit, 0 otherwise. The entry takes
@@ -1126,80 +1231,51 @@ static int trace_vacuum(const orc_cloak *c, int branch, const orc_opts *o,
     }
     double eo, ee, ch[3], k[3], v[3];
     material_at(c, x, &eo, &ee, ch);
+    double w = 0.0;
+    if (wt || rf) {
+        double Tin[2], Rin = 0.0;
+        int bad = e_pol ? orc_fresnel_in_pol(eo, ee, ch, n, d_in, e_pol, Tin, &Rin)
+                        : orc_fresnel_in(eo, ee, ch, n, d_in, Tin, &Rin);
+        if (!bad) w = Tin[branch];
+        if (rf && !bad) {
+            rf->w_ext = Rin;
+            memcpy(rf->p_ext, x, sizeof(x));
+            memcpy(rf->d_ext, d_in, 3 * sizeof(double));
+            reflect(rf->d_ext, n);
+        }
+    }
     if (orc_refract_in(eo, ee, ch, n, d_in, branch, k, v)) {
         memcpy(p, x, sizeof(x));
         reflect(dout, n);
+        if (wt) *wt = 0.0;
         return ORC_REFLECTED;
     }
     double y[6] = { x[0], x[1], x[2], v[0], v[1], v[2] };
-    double t = 0.0, w = 0.0;
-    int bounces = 0, status;
-    if (wt) {
-        double Tin[2];
-        int bad = e_pol ? orc_fresnel_in_pol(eo, ee, ch, n, d_in, e_pol, Tin, NULL)
-                        : orc_fresnel_in(eo, ee, ch, n, d_in, Tin, NULL);
-        if (!bad) w = Tin[branch];
-    }
-    for (;;) {
-        int ev = o->scheme == ORC_RK4_HAM ? integrate_ham(c, branch, o, y, &t, nsteps)
-                                          : integrate(c, branch, o, y, &t, nsteps);
-        if (ev == EV_MAXSTEPS) { status = ORC_MAXSTEPS; break; }
-        if (ev == EV_DIVERGED) { status = ORC_DIVERGED; break; }
-        double nn[3];
-        if (ev == EV_INNER) {
-            if (c->inner_mirror && c->axis == ORC_AXIS_RADIAL && bounces < o->max_bounces) {
-                /* optic axis along the mirror normal: one specular reflection
-                   for either ray (Sect. 4) */
-                outward_normal(SURF_SIDE, y, nn);
-                reflect(y + 3, nn);
-                bounces++;
-                continue;
-            }
-            status = ORC_ABSORBED;
-            break;
-        }
-        outward_normal(ev, y, nn);
-        /* a ray whose Hamiltonian v^T M v has drifted from 1 by more than
-           1e-3 at an outer interface is no longer a ray of the medium: its
-           direction there is not a solution of the dispersion relation, and
-           the refraction of Sect. 3 would act on an arbitrary vector */
-        if (!(fabs(hamiltonian(c, branch, y) - 1.0) <= 1e-3)) { status = ORC_DIVERGED; break; }
-        double eo2, ee2, ch2[3], dd[3];
-        material_at(c, y, &eo2, &ee2, ch2);
-        double Tout = 0.0, Rref[2] = { 0.0, 0.0 };
-        if (wt) {
-            /* k = M v of the wave meeting the interface */
-            double k[3], M[3][3];
-            if (branch == ORC_ORDINARY) {
-                for (int i = 0; i < 3; i++) k[i] = eo2 * y[3 + i];
-            } else {
-                metric_from_axis(eo2, ee2, ch2, M);
-                for (int i = 0; i < 3; i++) k[i] = M[i][0] * y[3] + M[i][1] * y[4] + M[i][2] * y[5];
-            }
-            if (orc_fresnel_out(eo2, ee2, ch2, nn, k, branch, &Tout, Rref) != 0) Tout = Rref[0] = Rref[1] = 0.0;
-        }
-        if (orc_refract_out(eo2, ee2, ch2, nn, y + 3, branch, dd) == 0) {
-            *hres = fabs(hamiltonian(c, branch, y) - 1.0);
-            memcpy(p, y, 3 * sizeof(double));
-            memcpy(dout, dd, sizeof(dd));
-            status = ORC_EXITED;
-            w *= Tout;
-            break;
-        }
-        /* total internal reflection: same-mode specular reflection */
-        if (bounces >= o->max_bounces) { status = ORC_TIR; break; }
-        w *= Rref[branch];
-        reflect(y + 3, nn);
-        bounces++;
-    }
-    if (status != ORC_EXITED) {
-        *hres = fabs(hamiltonian(c, branch, y) - 1.0);
-        memcpy(p, y, 3 * sizeof(double));
-        double l = norm3(y + 3);
-        for (int i = 0; i < 3; i++) dout[i] = y[3 + i] / l;
-    }
+    double t = 0.0;
+    exit_state ex;
+    int status = crystal_walk(c, branch, o, y, &t, nsteps, &w, rf ? &ex : NULL, p, dout, hres);
     *opl += t;
-    if (wt) *wt = status == ORC_EXITED ? w : 0.0;
+    if (wt) *wt = w;
+    if (rf && status == ORC_EXITED) {
+        /* the two reflected waves: the tangential wave vector of the wave met
+           and each mode's dispersion relation, the root that carries power
+           back into the crystal (the refraction of Sect. 3 read with the
+           reflected wave vectors) */
+        double kt[3], kn = dot3(ex.k, ex.n), kin[3];
+        for (int i = 0; i < 3; i++) {
+            kt[i] = ex.k[i] - kn * ex.n[i];
+            kin[i] = kt[i] - ex.n[i];
+        }
+        for (int bp = 0; bp < 2; bp++) {
+            double kc[3], vc[3];
+            if (!(ex.Rref[bp] > 0.0) || orc_refract_in(ex.eo, ex.ee, ex.ch, ex.n, kin, bp, kc, vc)) continue;
+            double yc[6] = { ex.x[0], ex.x[1], ex.x[2], vc[0], vc[1], vc[2] };
+            double tc = 0.0, hc, wc = ex.w_pre * ex.Rref[bp];
+            int64_t nc = 0;
+            int sc = crystal_walk(c, bp, o, yc, &tc, &nc, &wc, NULL, rf->p_child[bp], rf->d_child[bp], &hc);
+            rf->w_child[bp] = sc == ORC_EXITED ? wc : 0.0;
+        }
+    }
     return status;
 }
 
@@ -1241,7 +1317,7 @@ void orc_trace(const orc_cloak *c, const orc_opts *o, int32_t branch, int64_t n,
             memcpy(p, org, sizeof(p));
             memcpy(dout, d, sizeof(dout));
         } else {
-            st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, trans ? &w : NULL, NULL);
+            st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, trans ? &w : NULL, NULL, NULL);
             if (st == ORC_EXITED || st == ORC_MISSED || st == ORC_REFLECTED) {
                 double s = leave_radius(p, dout, o->r_out);
                 for (int j = 0; j < 3; j++) p[j] += s * dout[j];
@@ -1349,7 +1425,7 @@ void orc_render_samples(const orc_cloak *c, const orc_opts *o, const orc_room *r
         double org[3], d[3], p[3], dout[3], L = 0.0, hr, w = 0.0;
         int64_t ns = 0;
         orc_camera_ray(cam, cam_index, ids[i], org, d);
-        int st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, wimg ? &w : NULL, NULL);
+        int st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, wimg ? &w : NULL, NULL, NULL);
         if (wimg) {
             /* share of the sample's unpolarized light that this branch carries
                to the room (Eq. (12)): a ray that stays in vacuum (a miss, or
@@ -1374,6 +1450,73 @@ void orc_render_samples(const orc_cloak *c, const orc_opts *o, const orc_room *r
         if (rec) {
             for (int j = 0; j < 3; j++) { rec[j * n + i] = p[j]; rec[(3 + j) * n + i] = dout[j]; }
             rec[6 * n + i] = L;
+        }
+    }
+}
+
+/* First-order reflections of arbitrary vacuum rays (in6 as orc_trace)
+   through branch `branch`, unpolarized: w[j * n + i] the flux fraction of
+   contribution j (0 the entry's reflected vacuum ray, 1 / 2 the ordinary /
+   extraordinary wave reflected at the exit and followed to its own exit;
+   0 if absent) and ray[(j * 6 + q) * n + i] its vacuum ray where it leaves
+   the interface (point q < 3, unit direction q >= 3). */
+void orc_trace_reflections(const orc_cloak *c, const orc_opts *o, int32_t branch, int64_t n, const double *in6,
+                           double *w, double *ray) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+        double org[3], d[3], p[3], dout[3], L = 0.0, hr, wt = 0.0;
+        int64_t ns = 0;
+        orc_refl rf;
+        memset(&rf, 0, sizeof(rf));
+        for (int j = 0; j < 3; j++) { org[j] = in6[j * n + i]; d[j] = in6[(3 + j) * n + i]; }
+        double dl = norm3(d);
+        for (int j = 0; j < 3; j++) d[j] /= dl;
+        trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, &wt, NULL, &rf);
+        const double wj[3] = { rf.w_ext, rf.w_child[0], rf.w_child[1] };
+        const double *pj[3] = { rf.p_ext, rf.p_child[0], rf.p_child[1] };
+        const double *dj[3] = { rf.d_ext, rf.d_child[0], rf.d_child[1] };
+        for (int j = 0; j < 3; j++) {
+            w[j * n + i] = wj[j];
+            for (int q = 0; q < 3; q++) {
+                ray[(j * 6 + q) * n + i] = pj[j][q];
+                ray[(j * 6 + 3 + q) * n + i] = dj[j][q];
+            }
+        }
+    }
+}
+
+/* First-order reflections of camera samples through branch `branch`
+   (R27). For each sample three contributions j: 0 the vacuum ray reflected
+   at its first crystal interface, 1 and 2 the ordinary and extraordinary
+   waves the branch's ray reflects into at its exit, each followed to its
+   own exit. w[j * n + i] is the contribution's image weight and
+   code[j * n + i] the room code it sees (12: no light, weight 0). goggle
+   -1: the unpolarized image (the reflected fraction R of the entry split
+   evenly over the two branches, R / 2 each; a child carries the trace
+   weight of its path); 0, 1: that goggle's image (entry with the goggle's
+   field, and half of it, as orc_render_goggle). */
+void orc_render_reflections(const orc_cloak *c, const orc_opts *o, const orc_room *room, const orc_camera *cam,
+                            int32_t cam_index, int32_t branch, int32_t goggle, int64_t n, const int64_t *ids,
+                            double *w, uint8_t *code) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+        double org[3], d[3], p[3], dout[3], L = 0.0, hr, wt = 0.0, e[3];
+        int64_t ns = 0;
+        orc_refl rf;
+        memset(&rf, 0, sizeof(rf));
+        orc_camera_ray(cam, cam_index, ids[i], org, d);
+        int ok = goggle < 0 || orc_goggle_axis(cam, d, goggle, e) == 0;
+        if (ok) trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, &wt, goggle < 0 ? NULL : e, &rf);
+        double half = goggle < 0 ? 1.0 : 0.5, s;
+        double wj[3] = { ok ? 0.5 * half * rf.w_ext : 0.0, ok ? half * rf.w_child[0] : 0.0,
+                         ok ? half * rf.w_child[1] : 0.0 };
+        const double *pj[3] = { rf.p_ext, rf.p_child[0], rf.p_child[1] };
+        const double *dj[3] = { rf.d_ext, rf.d_child[0], rf.d_child[1] };
+        for (int j = 0; j < 3; j++) {
+            int cd = 12;
+            if (wj[j] > 0.0) cd = orc_room_code(room, pj[j], dj[j], &s);
+            w[j * n + i] = cd < 12 ? wj[j] : 0.0;
+            code[j * n + i] = (uint8_t)cd;
         }
     }
 }
@@ -1426,7 +1569,7 @@ void orc_render_goggle(const orc_cloak *c, const orc_opts *o, const orc_camera *
         orc_camera_ray(cam, cam_index, ids[i], org, d);
         double wi = 0.0;
         if (orc_goggle_axis(cam, d, goggle, e) == 0) {
-            int st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, &w, e);
+            int st = trace_vacuum(c, branch, o, org, d, p, dout, &L, &hr, &ns, &w, e, NULL);
             if (st == ORC_MISSED) wi = 0.25;
             else if (st == ORC_EXITED) wi = 0.5 * w;
             else if (st == ORC_REFLECTED && c && sqrt(p[0] * p[0] + p[1] * p[1]) <= c->a) wi = 0.25;

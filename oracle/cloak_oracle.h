@@ -119,7 +119,29 @@ int32_t orc_goggle_axis(const orc_camera *cam, const double d[3], int32_t goggle
 void orc_render_goggle(const orc_cloak *c, const orc_opts *o, const orc_camera *cam, int32_t cam_index,
                        int32_t branch, int32_t goggle, int64_t n, const int64_t *ids, double *wg);
 
-/* Pieces exposed for the pin tests. */
+/* First-order reflections of vacuum rays (in6 as orc_trace) through branch
+   `branch`, unpolarized light: w[j * n + i] the flux fraction of
+   contribution j (0: the entry's reflected vacuum ray, 1 / 2: the ordinary
+   / extraordinary wave reflected at the exit, followed to its own exit; 0
+   if absent) and ray[(j * 6 + q) * n + i] that contribution's vacuum ray
+   at the interface it leaves (point, then unit direction). */
+void orc_trace_reflections(const orc_cloak *c, const orc_opts *o, int32_t branch, int64_t n, const double *in6,
+                           double *w, double *ray);
+
+/* First-order reflections (Sect. 4; Sect. 3 for the two reflected waves in
+   the crystal): per camera sample (ids as orc_render_samples) and branch,
+   three contributions j (0: the vacuum ray reflected at the first crystal
+   interface, 1 / 2: the ordinary / extraordinary wave the branch's ray
+   reflects into at its exit, followed to its own exit without further
+   partial reflections), their image weights w[j * n + i] and room codes
+   code[j * n + i] (12: none). goggle -1: unpolarized image (the entry's
+   reflected fraction split evenly over the two branches); 0, 1: that
+   goggle's image. */
+void orc_render_reflections(const orc_cloak *c, const orc_opts *o, const orc_room *room, const orc_camera *cam,
+                            int32_t cam_index, int32_t branch, int32_t goggle, int64_t n, const int64_t *ids,
+                            double *w, uint8_t *code);
+
+/* Pieces exposed for the pin tests. *//* Pieces exposed for the pin tests. */
 void orc_eps_cyl(const orc_cloak *c, double r, double out3[3]);
 void orc_metric(const orc_cloak *c, const double x[3], double M[9]);
 void orc_metric_det_form(const orc_cloak *c, const double x[3], double M[9]);

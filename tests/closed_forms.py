@@ -529,3 +529,91 @@ def cap_rays(n, seed, a=1.0, b=2.0, z0=0.0, z1=4.0, polar_max_deg=75.0, side_sha
         out[:3, i] = tgt - 6.0 * d
         out[3:, i] = d
     return out
+
+
+def _fresnel_s(kt2, n):
+    """Intensity reflectance of the s wave (field across the plane of
+    incidence) between vacuum and index n for the tangential wave number^2
+    kt2 (the same from either side); 1 beyond the critical angle."""
+    if kt2 >= 1.0:
+        return 1.0
+    cv, cn = math.sqrt(1.0 - kt2), math.sqrt(n * n - kt2)
+    r = (cv - cn) / (cv + cn)
+    return r * r
+
+
+def radial_o_first_reflection(o, d, a=1.0, b=2.0, max_bounces=4):
+    """Radial cloak, ordinary ray, side surface only (an infinitely long
+    cylinder): the primary ray and the ordinary wave it reflects into at its
+    exit (R27). At the side the optic axis is the normal, so the ordinary
+    wave is the s wave of index n = sqrt(kappa) on both sides of every
+    interface: the entry takes (1 - R_s)/2 of unpolarized light, total
+    internal reflection keeps all of it, the exit reflects R_s back into the
+    ordinary wave, and the child leaves with 1 - R_s, each R_s at that
+    interface's tangential wave number. Rays are straight inside and reflect
+    specularly off the metal at r = a. Returns None if the ray misses, else
+    (primary exit point, primary vacuum direction, child status, child exit
+    point, child vacuum direction, child weight)."""
+    n = math.sqrt(kappa(a, b))
+    d = np.asarray(d, float) / np.linalg.norm(d)
+    o = np.asarray(o, float)
+    A = d[0] ** 2 + d[1] ** 2
+    B = o[0] * d[0] + o[1] * d[1]
+    if A <= 0.0 or B * B - A * (o[0] ** 2 + o[1] ** 2 - b * b) <= 0.0:
+        return None
+    _, x, nrm, _, _ = side_entry(o, d, b)
+    kt = d - (d @ nrm) * nrm
+    w = 0.5 * (1.0 - _fresnel_s(kt @ kt, n))
+    v = (kt - math.sqrt(n * n - kt @ kt) * nrm) / (n * n)
+
+    def walk(x, v, w):
+        """straight legs to the next side exit; returns (status, x, v, kt2, w)"""
+        bounces = 0
+        while True:
+            A = v[0] ** 2 + v[1] ** 2
+            B = x[0] * v[0] + x[1] * v[1]
+            cands = []
+            Ca = x[0] ** 2 + x[1] ** 2 - a * a
+            disc = B * B - A * Ca
+            if disc > 0.0:
+                tm = (-B - math.sqrt(disc)) / A
+                if tm > 1e-12:
+                    cands.append((tm, "inner"))
+            Cb = x[0] ** 2 + x[1] ** 2 - b * b
+            tb = (-B + math.sqrt(B * B - A * Cb)) / A
+            cands.append((tb, "side"))
+            tc, surf = min(cands, key=lambda c: c[0])
+            x = x + tc * v
+            m = np.array([x[0], x[1], 0.0]) / math.hypot(x[0], x[1])
+            if surf == "inner":
+                if bounces >= max_bounces:
+                    return S_ABSORBED, x, v, 0.0, 0.0
+                v = v - 2.0 * (v @ m) * m
+                bounces += 1
+                continue
+            k = n * n * v
+            ktt = k - (k @ m) * m
+            if ktt @ ktt <= 1.0:
+                return S_EXITED, x, v, ktt @ ktt, w
+            if bounces >= max_bounces:
+                return S_TIR, x, v, 0.0, 0.0
+            v = v - 2.0 * (v @ m) * m
+            bounces += 1
+
+    st, xe, ve, kt2, w = walk(x, v, w)
+    if st != S_EXITED:
+        return None
+    m = np.array([xe[0], xe[1], 0.0]) / math.hypot(xe[0], xe[1])
+    k = n * n * ve
+    ktt = k - (k @ m) * m
+    dout = ktt + math.sqrt(1.0 - kt2) * m
+    wc = w * _fresnel_s(kt2, n)
+    vc = ve - 2.0 * (ve @ m) * m  # the same-mode reflected wave: the mirror image
+    stc, xc, vcc, kt2c, wc = walk(xe, vc, wc)
+    if stc != S_EXITED:
+        return xe, dout, stc, xc, None, 0.0
+    mc = np.array([xc[0], xc[1], 0.0]) / math.hypot(xc[0], xc[1])
+    kc = n * n * vcc
+    kttc = kc - (kc @ mc) * mc
+    doutc = kttc + math.sqrt(1.0 - kt2c) * mc
+    return xe, dout, S_EXITED, xc, doutc, wc * (1.0 - _fresnel_s(kt2c, n))

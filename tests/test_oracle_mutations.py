@@ -18,8 +18,8 @@ MUTATIONS = [
      "if (surf == SURF_BOTTOM || surf == EV_BOTTOM) { n[0] = 0; n[1] = 0; n[2] = 1; return; }",
      (P.test_finite_radial_ordinary_caps_closed_form, P.test_finite_azimuthal_extraordinary_caps_closed_form)),
     ("total internal reflection about the radial normal on every surface",
-     "        w *= Rref[branch];\n        reflect(y + 3, nn);",
-     "        w *= Rref[branch];\n        outward_normal(SURF_SIDE, y, nn);\n        reflect(y + 3, nn);",
+     "        if (w) *w *= Rref[branch];\n        reflect(y + 3, nn);",
+     "        if (w) *w *= Rref[branch];\n        outward_normal(SURF_SIDE, y, nn);\n        reflect(y + 3, nn);",
      (P.test_finite_radial_ordinary_caps_closed_form, P.test_finite_azimuthal_extraordinary_caps_closed_form)),
     ("entry through the top cap accepted only over the metal disk's radius",
      "        if (s > 0.0 && x * x + y * y <= c->b * c->b && s < best) {\n            best = s; *surf = SURF_TOP;",
@@ -44,6 +44,18 @@ MUTATIONS = [
      "            else if (st == ORC_EXITED) wi = w;",
      (P.test_goggle_images_split_the_unpolarized_image,
       P.test_inplane_goggle_passes_the_design_polarization_on_the_centre_row)),
+    ("reflected child followed in the other mode's medium",
+     "            int sc = crystal_walk(c, bp, o, yc, &tc, &nc, &wc, NULL, rf->p_child[bp], rf->d_child[bp], &hc);",
+     "            int sc = crystal_walk(c, 1 - bp, o, yc, &tc, &nc, &wc, NULL, rf->p_child[bp], rf->d_child[bp], &hc);",
+     (P.test_first_order_reflection_of_the_radial_ordinary_ray_closed_form,)),
+    ("reflected child without its exit transmission",
+     "            int sc = crystal_walk(c, bp, o, yc, &tc, &nc, &wc, NULL, rf->p_child[bp], rf->d_child[bp], &hc);",
+     "            int sc = crystal_walk(c, bp, o, yc, &tc, &nc, NULL, NULL, rf->p_child[bp], rf->d_child[bp], &hc);",
+     (P.test_first_order_reflection_of_the_radial_ordinary_ray_closed_form,)),
+    ("entry reflection weighted by the transmitted fraction",
+     "            rf->w_ext = Rin;",
+     "            rf->w_ext = Tin[branch];",
+     (P.test_entry_reflection_is_the_fresnel_remainder,)),
 ]
 
 

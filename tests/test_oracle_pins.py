@@ -959,6 +959,94 @@ def test_inplane_goggle_passes_the_design_polarization_on_the_centre_row():
             assert np.abs(off).max() < 1e-12
 
 
+def _radial_o_rays(n_try, seed):
+    rng = np.random.default_rng(seed)
+    rays, cfs = [], []
+    for _ in range(n_try):
+        org = np.array([5.0, rng.uniform(-2.2, 2.2), rng.uniform(-0.5, 0.5)])
+        d = _unit([-1.0, rng.uniform(-0.1, 0.1), rng.uniform(-0.3, 0.3)])
+        r = CF.radial_o_first_reflection(org, d)
+        if r is None or r[2] != CF.S_EXITED:
+            continue
+        rays.append(np.concatenate([org, d]))
+        cfs.append(r)
+    return np.array(rays).T, cfs
+
+
+def test_first_order_reflection_of_the_radial_ordinary_ray_closed_form():
+    """Radial cloak, ordinary rays through the side (infinite cylinder,
+    Sect. 4): the wave the exit reflects back into the ordinary mode, followed
+    to its own exit, leaves where the closed form's straight chords (with the
+    metal mirror) leave, and carries (1 - R_s)/2 x R_s x (1 - R_s) of
+    unpolarized light (the ordinary wave is the s wave at the side, where
+    the optic axis is the normal); the axis along the normal couples nothing
+    into the extraordinary mode."""
+    rays, cfs = _radial_o_rays(200, 3)
+    assert len(cfs) > 100
+    w, ray = oracle.trace_reflections(W.cloak(0), W.opts_dp45(), O, rays)
+    wc = np.array([c[5] for c in cfs])
+    pc = np.array([c[3] for c in cfs]).T
+    dc = np.array([c[4] for c in cfs]).T
+    assert wc.min() > 0.03
+    assert np.abs(w[1] - wc).max() < 1e-12
+    assert np.abs(ray[1, :3] - pc).max() < 1e-9
+    assert np.abs(ray[1, 3:] - dc).max() < 1e-9
+    assert np.abs(w[2]).max() < 1e-20
+
+
+def test_entry_reflection_is_the_fresnel_remainder():
+    """The light reflected at the first crystal interface is what the two
+    refracted waves do not take, R = 1 - T_o - T_e (Sect. 3), leaving along
+    the mirror image of the incident direction about the outward normal;
+    both branches report it."""
+    rays = W.random_rays(128, seed=8, z_range=(-1.0, 5.0))
+    for axis in (0, 1):
+        cl = W.cloak(axis, height=W.HEIGHT)
+        k = CF.kappa(1.0, 2.0)
+        ws = []
+        for br in (O, E):
+            w, ray = oracle.trace_reflections(cl, W.opts_dp45(), br, rays)
+            ws.append(w[0])
+            for i in range(rays.shape[1]):
+                o, d = rays[:3, i], _unit(rays[3:, i])
+                hit = CF.body_entry(o, d, 2.0, 0.0, W.HEIGHT)
+                if hit is None:
+                    assert w[0, i] == 0.0
+                    continue
+                s, surf = hit
+                x = o + s * d
+                r = math.hypot(x[0], x[1])
+                if surf != CF.SIDE and r <= 1.0:   # the metal end disk
+                    assert w[0, i] == 0.0
+                    continue
+                nrm = CF._outward(surf, x)
+                q = k * (1.0 - 1.0 / r) ** 2
+                eo, ee = (k, q) if axis == 0 else (q, k)
+                c = np.array([x[0] / r, x[1] / r, 0.0]) if axis == 0 else np.array([-x[1] / r, x[0] / r, 0.0])
+                T, _ = oracle.fresnel_in(eo, ee, c, nrm, d)
+                assert w[0, i] == pytest.approx(1.0 - T.sum(), abs=1e-12)
+                assert ray[0, :3, i] == pytest.approx(x, abs=1e-12)
+                assert ray[0, 3:, i] == pytest.approx(d - 2.0 * (d @ nrm) * nrm, abs=1e-12)
+        assert np.array_equal(ws[0], ws[1])
+        assert (ws[0] > 0).sum() > 20
+
+
+def test_reflections_split_between_the_goggles():
+    """Each first-order contribution's goggle weights add up to its
+    unpolarized weight (the entry's reflected ray included), for both cloaks
+    and branches."""
+    cam = W.orbit_camera(0.4, 20.0, 20, 20, spp=1)
+    ids = np.arange(400)
+    for axis in (0, 1):
+        cl = W.cloak(axis, height=W.HEIGHT)
+        for br in (O, E):
+            wu, cu = oracle.render_reflections(cl, W.render_opts(), W.room(), cam, 0, br, ids, -1)
+            w0, c0 = oracle.render_reflections(cl, W.render_opts(), W.room(), cam, 0, br, ids, 0)
+            w1, c1 = oracle.render_reflections(cl, W.render_opts(), W.room(), cam, 0, br, ids, 1)
+            assert (wu > 0).sum(axis=1)[0] > 50
+            assert w0 + w1 == pytest.approx(wu, abs=1e-12)
+
+
 def test_trace_weights():
     """The Eq. (12) weight of a traced ray: 1 for a miss, in (0, 1] for an
     exit, 0 otherwise; the azimuthal cloak's ordinary index is 1 at r = b, so
