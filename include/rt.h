@@ -164,7 +164,20 @@ typedef struct {
    weight with the entry taking the goggle's field instead of unpolarized
    light (entry transmission of that field into the branch x internal
    reflectances x exit transmission). The two goggle images add up to the
-   unpolarized one. Same requirements as unpol. */
+   unpolarized one. Same requirements as unpol.
+   reflections: nonzero adds first-order reflections (Sect. 4: reflections
+   of the first order are kept, higher orders dropped) to unpol and the
+   goggle images: the vacuum ray reflected where the sample first meets the
+   crystal (fraction 1 - T_o - T_e of its light, half per branch), and at
+   each branch's exit the waves reflected into the ordinary and the
+   extraordinary mode (Sect. 3: two reflections in the crystal, one
+   refraction), each followed through the cloak to its own exit, where it
+   refracts out with its transmission; their own partial reflections are
+   not followed. The branch images and the per-sample outputs are those of
+   the primary rays alone. Needs unpol or a goggle image (RT_E_INVALID
+   otherwise); renders in chunks of at most 2^22 samples and needs a second
+   work table (about 1 KB per sample of a chunk); not taken by render plans
+   or rt_render_surrogate (RT_E_UNSUPPORTED). */
 typedef struct {
     double *rec;
     int32_t *status;
@@ -174,6 +187,7 @@ typedef struct {
     float *unpol;
     float *goggle_inplane;
     float *goggle_axial;
+    int32_t reflections;
 } rt_render_aux;
 
 /* Build a cloak handle (host-side constants; no device memory).

@@ -536,9 +536,9 @@ __device__ __forceinline__ void solve2(const cplx a[2], const cplx b[2], const c
 }
 
 // Unpolarized transmission from vacuum (unit direction d, n outward) into
-// the crystal wave of `extra` (0 ordinary, 1 extraordinary).
-__device__ __forceinline__ double fresnel_in_dev(double eo, double ee, const double cax[3], const double n[3],
-                                                 const double d[3], int extra) {
+// the ordinary (To) and the extraordinary (Te) crystal wave.
+__device__ __forceinline__ void fresnel_in2_dev(double eo, double ee, const double cax[3], const double n[3],
+                                                const double d[3], double &To, double &Te) {
   double t1[3], t2[3], k1;
   interface_basis(n, d, t1, t2, k1);
   const double c[3] = {cax[0] * t1[0] + cax[1] * t1[1] + cax[2] * t1[2],
@@ -555,7 +555,8 @@ __device__ __forceinline__ double fresnel_in_dev(double eo, double ee, const dou
   // columns h - Y e of the two crystal waves
   const cplx A[2] = {fo[2] - (cx(0.0) - qr * fo[1]), fo[3] - y22 * fo[0]};
   const cplx B[2] = {fe[2] - (cx(0.0) - qr * fe[1]), fe[3] - y22 * fe[0]};
-  double T = 0.0;
+  To = 0.0;
+  Te = 0.0;
   for (int pol = 0; pol < 2; ++pol) {
     // s: E = (0, 1, 0); p: E = k x (0, 1, 0) = (-qi, 0, k1)
     cplx fi[4];
@@ -571,19 +572,59 @@ __device__ __forceinline__ double fresnel_in_dev(double eo, double ee, const dou
     cplx ao, ae;
     solve2(A, B, r, ao, ae);
     const double si = fabs(flux_t(fi));
-    const double fm = extra ? cabs2(ae) * fabs(flux_t(fe)) : cabs2(ao) * fabs(flux_t(fo));
-    T += fm / si;
+    To += cabs2(ao) * fabs(flux_t(fo)) / si;
+    Te += cabs2(ae) * fabs(flux_t(fe)) / si;
+  }
+  To *= 0.5;
+  Te *= 0.5;
+}
+
+// Unpolarized transmission from vacuum into the crystal wave of `extra`
+// (0 ordinary, 1 extraordinary): fresnel_in2_dev for one wave (the same
+// arithmetic), so that callers that need one carry one.
+__device__ __forceinline__ double fresnel_in_dev(double eo, double ee, const double cax[3], const double n[3],
+                                                 const double d[3], int extra) {
+  double t1[3], t2[3], k1;
+  interface_basis(n, d, t1, t2, k1);
+  const double c[3] = {cax[0] * t1[0] + cax[1] * t1[1] + cax[2] * t1[2],
+                       cax[0] * t2[0] + cax[1] * t2[1] + cax[2] * t2[2],
+                       cax[0] * n[0] + cax[1] * n[1] + cax[2] * n[2]};
+  const double qi = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
+  const cplx qr = q_iso_dev(1.0, k1, +1);
+  const cplx qo = q_iso_dev(eo, k1, -1), qe = q_extra_dev(eo, ee, c, k1, -1);
+  cplx fo[4], fe[4];
+  crystal_tangential(eo, ee, c, true, k1, qo, fo);
+  crystal_tangential(eo, ee, c, false, k1, qe, fe);
+  const cplx y22 = cdiv(cx(k1 * k1) + qr * qr, qr);
+  const cplx A[2] = {fo[2] - (cx(0.0) - qr * fo[1]), fo[3] - y22 * fo[0]};
+  const cplx B[2] = {fe[2] - (cx(0.0) - qr * fe[1]), fe[3] - y22 * fe[0]};
+  double T = 0.0;
+  for (int pol = 0; pol < 2; ++pol) {
+    cplx fi[4];
+    if (pol == 0) {
+      fi[0] = cx(0.0); fi[1] = cx(1.0);
+      fi[2] = cx(-qi); fi[3] = cx(0.0);
+    } else {
+      fi[0] = cx(-qi); fi[1] = cx(0.0);
+      fi[2] = cx(0.0); fi[3] = cx(-qi * qi - k1 * k1);
+    }
+    const cplx r[2] = {fi[2] - (cx(0.0) - qr * fi[1]), fi[3] - y22 * fi[0]};
+    cplx ao, ae;
+    solve2(A, B, r, ao, ae);
+    const double si = fabs(flux_t(fi));
+    T += (extra ? cabs2(ae) * fabs(flux_t(fe)) : cabs2(ao) * fabs(flux_t(fo))) / si;
   }
   return 0.5 * T;
 }
 
-// Transmission from vacuum into the crystal wave of `extra` for the
-// incident field along the unit vector e (transverse to d), and (Tun) for
-// unpolarized light as fresnel_in_dev computes it. With s along t2 (normal
-// to the plane of incidence) and p = d x s, e = alpha s + beta p, and by
-// linearity the crystal amplitude is alpha a_s + beta a_p.
-__device__ __forceinline__ double fresnel_in_pol_dev(double eo, double ee, const double cax[3], const double n[3],
-                                                     const double d[3], int extra, const double e[3], double &Tun) {
+// Transmission from vacuum into the ordinary (Go) and extraordinary (Ge)
+// crystal wave for the incident field along the unit vector e (transverse
+// to d), and the unpolarized ones (Uo, Ue, as fresnel_in2_dev). With s
+// along t2 (normal to the plane of incidence) and p = d x s, e = alpha s +
+// beta p, and by linearity each crystal amplitude is alpha a_s + beta a_p.
+__device__ __forceinline__ void fresnel_in_pol_dev(double eo, double ee, const double cax[3], const double n[3],
+                                                   const double d[3], const double e[3], double &Go, double &Ge,
+                                                   double &Uo, double &Ue) {
   double t1[3], t2[3], k1;
   interface_basis(n, d, t1, t2, k1);
   const double c[3] = {cax[0] * t1[0] + cax[1] * t1[1] + cax[2] * t1[2],
@@ -598,26 +639,28 @@ __device__ __forceinline__ double fresnel_in_pol_dev(double eo, double ee, const
   const cplx y22 = cdiv(cx(k1 * k1) + qr * qr, qr);
   const cplx A[2] = {fo[2] - (cx(0.0) - qr * fo[1]), fo[3] - y22 * fo[0]};
   const cplx B[2] = {fe[2] - (cx(0.0) - qr * fe[1]), fe[3] - y22 * fe[0]};
-  // s and p as in fresnel_in_dev, one incident flux |qi| / 2 for both
+  // s and p as in fresnel_in2_dev, one incident flux |qi| / 2 for both
   const cplx rs[2] = {cx(-qi) - (cx(0.0) - qr * cx(1.0)), cx(0.0)};
   const cplx rp[2] = {cx(0.0), cx(-qi * qi - k1 * k1) - y22 * cx(-qi)};
   cplx aos, aes, aop, aep;
   solve2(A, B, rs, aos, aes);
   solve2(A, B, rp, aop, aep);
   const double si = 0.5 * fabs(qi);
-  const double f = extra ? fabs(flux_t(fe)) : fabs(flux_t(fo));
-  const cplx as = extra ? aes : aos, ap = extra ? aep : aop;
-  Tun = 0.5 * (cabs2(as) * f / si + cabs2(ap) * f / si);
+  const double fo_ = fabs(flux_t(fo)) / si, fe_ = fabs(flux_t(fe)) / si;
+  Uo = 0.5 * (cabs2(aos) + cabs2(aop)) * fo_;
+  Ue = 0.5 * (cabs2(aes) + cabs2(aep)) * fe_;
   const double al = e[0] * t2[0] + e[1] * t2[1] + e[2] * t2[2];
   const double be = -qi * (e[0] * t1[0] + e[1] * t1[1] + e[2] * t1[2]) + k1 * (e[0] * n[0] + e[1] * n[1] + e[2] * n[2]);
-  return cabs2(al * as + be * ap) * f / si;
+  Go = cabs2(al * aos + be * aop) * fo_;
+  Ge = cabs2(al * aes + be * aep) * fe_;
 }
 
 // A crystal wave of `extra` with wave vector k (power towards +n) meets the
-// interface: transmitted fraction T and the fraction R reflected into the
-// same wave type.
-__device__ __forceinline__ void fresnel_out_dev(double eo, double ee, const double cax[3], const double n[3],
-                                                const double k[3], int extra, double &T, double &R) {
+// interface: transmitted fraction T and the fractions Ro, Re reflected into
+// the ordinary and the extraordinary wave (Sect. 3: two reflections in the
+// crystal, one refraction into vacuum).
+__device__ __forceinline__ void fresnel_out2_dev(double eo, double ee, const double cax[3], const double n[3],
+                                                 const double k[3], int extra, double &T, double &Ro, double &Re) {
   double t1[3], t2[3], k1;
   interface_basis(n, k, t1, t2, k1);
   const double c[3] = {cax[0] * t1[0] + cax[1] * t1[1] + cax[2] * t1[2],
@@ -645,7 +688,16 @@ __device__ __forceinline__ void fresnel_out_dev(double eo, double ee, const doub
   ft[2] = cx(0.0) - qv * ft[1];
   ft[3] = y22 * ft[0];
   T = fabs(flux_t(ft)) / si;
-  R = extra ? cabs2(be) * fabs(flux_t(fe)) / si : cabs2(bo) * fabs(flux_t(fo)) / si;
+  Ro = cabs2(bo) * fabs(flux_t(fo)) / si;
+  Re = cabs2(be) * fabs(flux_t(fe)) / si;
+}
+
+// as fresnel_out2_dev, R the fraction reflected into the same wave type
+__device__ __forceinline__ void fresnel_out_dev(double eo, double ee, const double cax[3], const double n[3],
+                                                const double k[3], int extra, double &T, double &R) {
+  double Ro, Re;
+  fresnel_out2_dev(eo, ee, cax, n, k, extra, T, Ro, Re);
+  R = extra ? Re : Ro;
 }
 
 // ---------------------------------------------------------------------------
@@ -775,9 +827,10 @@ __device__ __forceinline__ void local_frame(const double x[3], double rh[2], dou
 // outgoing vacuum direction d. Its tangential k equals d's (Eq. (11)); its
 // normal component is the outward root of the branch's dispersion
 // k^T M^-1 k = 1, with M diagonal in (r, theta, z) and the normal one of
-// those axes.
-__device__ __forceinline__ double exit_transmission(const CloakP &c, int kind, int rid, const double x[3],
-                                                    const double d[3]) {
+// those axes. T transmitted, Ro / Re reflected into the ordinary /
+// extraordinary wave; exit_transmission returns T alone.
+__device__ __forceinline__ void exit_fresnel(const CloakP &c, int kind, int rid, const double x[3],
+                                             const double d[3], double &T, double &Ro, double &Re) {
   double rh[2], th[2], w;
   local_frame(x, rh, th, w);
   double mr, mt, mz;
@@ -793,10 +846,16 @@ __device__ __forceinline__ double exit_transmission(const CloakP &c, int kind, i
     kz = rid == B_TOP ? q : -q;
   }
   const double k[3] = {kr * rh[0] + kt * th[0], kr * rh[1] + kt * th[1], kz};
-  double eo, ee, cax[3], nrm[3], T, R;
+  double eo, ee, cax[3], nrm[3];
   material_axis(c, kind >> 1, x, eo, ee, cax);
   boundary_normal(rid, x, nrm);
-  fresnel_out_dev(eo, ee, cax, nrm, k, kind & 1, T, R);
+  fresnel_out2_dev(eo, ee, cax, nrm, k, kind & 1, T, Ro, Re);
+}
+
+__device__ __forceinline__ double exit_transmission(const CloakP &c, int kind, int rid, const double x[3],
+                                                    const double d[3]) {
+  double T, Ro, Re;
+  exit_fresnel(c, kind, rid, x, d, T, Ro, Re);
   return T;
 }
 

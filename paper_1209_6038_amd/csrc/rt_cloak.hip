@@ -59,6 +59,7 @@ enum {
   C_COUNT = C_ACC + C_LINE
 };
 constexpr int MAX_BOUNCES = 64;
+constexpr long long REFL_CHUNK = 1LL << 22;  // samples per chunk with first-order reflections
 constexpr unsigned int FETCH_CHUNK = 64;  // rays claimed per wave per atomic
 constexpr int LONG_RAY_ATTEMPTS = 64;      // see the issue priority in k_transit
 constexpr int NBUCKET = 16;               // difficulty buckets
@@ -854,6 +855,14 @@ struct RenderP {
   // vacuum); NULL unless goggle images
   float *grho;
   float *gog[2];         // aux per-pixel goggle images (in-plane, axial), per (cloak, camera) (may be NULL)
+  // first-order reflections (with refl set), chunk-local: per [segment][g1-g0]
+  // the entry's reflected vacuum ray, its unpolarized image weight (R / 2),
+  // the in-plane goggle's weight (R_in / 4; NULL without goggles) and its
+  // room code; per [segment][child mode][g1-g0] the weight and room code of
+  // the wave reflected at the exit into that mode, followed to its own exit
+  int refl;
+  float *rext, *rgin, *cw;
+  unsigned char *rcode, *ccode;
 };
 
 // Surrogate render: the side entries of a chunk that go to the network
@@ -924,15 +933,18 @@ __device__ __forceinline__ void put_candidate(const CandP &C, unsigned int i, co
   C.s_in[i] = (float)s;
 }
 
-// Eq. (12) at a camera sample's entry into branch `kind` through boundary
-// surf at x, direction d: the unpolarized transmission (.x) and, with
-// goggle, the ratio to it of the transmission of the in-plane goggle's
-// field (.y, else 1). That field is the camera's horizontal axis r made
-// transverse to the ray (Figs. 1d and 2d); the axial goggle's is d x it,
-// and the two transmissions add up to twice the unpolarized one. Out of
-// line with scalar arguments, like fresnel_event: the complex solve would
-// otherwise set the register allocation of the whole generation kernel.
-__device__ __noinline__ double2 entry_weight(double kappa, double a, int kind, int surf, double x0, double x1,
+// Eq. (12) at a camera sample's entry into the cloak of axis kind >> 1
+// through boundary surf at x, direction d: the unpolarized transmission
+// into branch kind & 1 (.x), with goggle the ratio to it of the
+// transmission of the in-plane goggle's field (.y, else 1), and the
+// reflected fractions of unpolarized light (.z) and of the goggle's field
+// (.w, with goggle), 1 - T_o - T_e. The goggle's field is the camera's
+// horizontal axis r made transverse to the ray (Figs. 1d and 2d); the axial
+// goggle's is d x it, and the two transmissions add up to twice the
+// unpolarized one. Out of line with scalar arguments, like fresnel_event:
+// the complex solves would otherwise set the register allocation of the
+// whole generation kernel.
+__device__ __noinline__ double4 entry_weight(double kappa, double a, int kind, int surf, double x0, double x1,
                                              double x2, double d0, double d1, double d2, double r0, double r1,
                                              double r2, int goggle) {
   CloakP c{};
@@ -942,21 +954,26 @@ __device__ __noinline__ double2 entry_weight(double kappa, double a, int kind, i
   double eo, ee, cax[3], nrm[3];
   boundary_normal(surf, x, nrm);
   material_axis(c, kind >> 1, x, eo, ee, cax);
-  // the unpolarized weight is the same with or without goggles
-  const double w = fresnel_in_dev(eo, ee, cax, nrm, d, kind & 1);
-  if (!goggle) return make_double2(w, 1.0);
+  double To, Te;
+  fresnel_in2_dev(eo, ee, cax, nrm, d, To, Te);
+  const double w = (kind & 1) ? Te : To;
+  if (!goggle) return make_double4(w, 1.0, 1.0 - To - Te, 0.0);
   const double rd = r0 * d0 + r1 * d1 + r2 * d2;
   double e[3] = {r0 - rd * d0, r1 - rd * d1, r2 - rd * d2};
   const double ie = 1.0 / sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
   e[0] *= ie; e[1] *= ie; e[2] *= ie;
-  double tun;
-  const double tg = fresnel_in_pol_dev(eo, ee, cax, nrm, d, kind & 1, e, tun);
-  return make_double2(w, tun > 0.0 ? tg / tun : 1.0);
+  double go, ge, uo, ue;
+  fresnel_in_pol_dev(eo, ee, cax, nrm, d, e, go, ge, uo, ue);
+  const double tg = (kind & 1) ? ge : go, tun = (kind & 1) ? ue : uo;
+  return make_double4(w, tun > 0.0 ? tg / tun : 1.0, 1.0 - To - Te, 1.0 - go - ge);
 }
 
 // camera rays of a chunk; one thread per sample, every (cloak, branch).
-// SUR: side entries become surrogate candidates instead of work-table slots
-template <bool SUR>
+// SUR: side entries become surrogate candidates instead of work-table slots.
+// WM: Eq. (12) weights at the entry, 0 none, 1 unpolarized, 2 with the
+// goggle ratio (separate instantiations: the entry solves are large, and a
+// render without weights should not carry their registers)
+template <bool SUR, int WM>
 __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
                                                 const CamP *__restrict__ cams, Table T, RenderP R, CandP Cd) {
   long long gidx = R.g0 + (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1008,8 +1025,36 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
     int kind = (ci == 0 ? R.axis[0] : R.axis[1]) * 2 + (pi == 0 ? R.pol[0] : R.pol[1]);
     bool enter = false, cand = false;
     double v[3] = {0, 0, 0}, w_in = 0.0;
-    // goggle ratio 1 unless the sample enters the crystal (set below)
-    if (valid && R.grho) R.grho[(long long)q * (R.g1 - R.g0) + (gidx - R.g0)] = 1.0f;
+    const long long li = (long long)q * (R.g1 - R.g0) + (gidx - R.g0);  // chunk-local index
+    if (valid) {
+      // goggle ratio 1 and no reflected light unless the sample meets the
+      // crystal (set below)
+      if (R.grho) R.grho[li] = 1.0f;
+      if (R.refl) {
+        R.rext[li] = 0.0f;
+        if (R.rgin) R.rgin[li] = 0.0f;
+        R.rcode[li] = 12;
+#pragma unroll
+        for (int bp = 0; bp < 2; ++bp) {
+          R.cw[(2 * q + bp) * (R.g1 - R.g0) + (gidx - R.g0)] = 0.0f;
+          R.ccode[(2 * q + bp) * (R.g1 - R.g0) + (gidx - R.g0)] = 12;
+        }
+      }
+    }
+    double4 ew = make_double4(0.0, 1.0, 0.0, 0.0);
+    if (WM > 0 && valid && hitc && !disk) {
+      ew = entry_weight(c.kappa, c.a, kind, surf, x[0], x[1], x[2], d[0], d[1], d[2], cr[0], cr[1], cr[2],
+                        WM == 2);
+      if (R.refl) {
+        // the vacuum ray reflected at the entry (a convex body: it leaves)
+        double nrm[3], dd[3] = {d[0], d[1], d[2]}, sh;
+        boundary_normal(surf, x, nrm);
+        reflect3(dd, nrm);
+        R.rext[li] = (float)(0.5 * ew.z);
+        if (R.rgin) R.rgin[li] = (float)(0.25 * ew.w);
+        R.rcode[li] = (unsigned char)room_code(rm, x, dd, sh);
+      }
+    }
     if (valid) {
       if (!hitc || disk) {
         rd_write(R, q, gidx, vcode, vst, vp, vd, vL, 0, 0.5f);  // vacuum light splits evenly
@@ -1017,11 +1062,9 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
         const int skey = sort_key(c, kind, x, d);
         if (SUR && surf == B_SIDE && NBUCKET - 1 - skey >= R.sur_min) cand = true;
         else enter = true;
-        if (!SUR && R.twt) {
-          const double2 ew = entry_weight(c.kappa, c.a, kind, surf, x[0], x[1], x[2], d[0], d[1], d[2], cr[0],
-                                          cr[1], cr[2], R.grho != nullptr);
+        if (WM > 0) {
           w_in = ew.x;
-          if (R.grho) R.grho[(long long)q * (R.g1 - R.g0) + (gidx - R.g0)] = (float)ew.y;
+          if (WM == 2) R.grho[li] = (float)ew.y;
         }
       } else {
         // evanescent transmission into this branch: reflected at the entry
@@ -1034,7 +1077,7 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
     }
     unsigned int sl = block_append(T.ctr + C_N(q), enter, sh);
     if (enter) put_slot(T, (int)(q * T.cap + sl), x, v, kind, gidx, s, o.h0, sort_key(c, kind, x, d));
-    if (!SUR && enter && R.twt) T.wt[q * T.cap + sl] = w_in;
+    if (WM > 0 && enter) T.wt[q * T.cap + sl] = w_in;
     if constexpr (SUR) {
       const unsigned int ci2 = block_append(T.ctr + C_SUR, cand, sh);
       if (cand) put_candidate(Cd, ci2, x, d, kind, gidx, q, s);
@@ -1131,6 +1174,90 @@ __global__ void __launch_bounds__(256) k_rd_finish(CloakP c, RoomP rm, Table T, 
   }
 }
 
+// First-order reflections, after k_rd_finish: every primary that left the
+// crystal spawns the two waves its exit reflects into the ordinary and the
+// extraordinary mode (fractions Ro, Re of the exit solve) as slots of the
+// child table Tc, in the segment of that mode. A reflected wave has the
+// tangential wave vector of the wave met and the normal component of its
+// own mode's dispersion relation, pointing back in: that is the refraction
+// of the vacuum ray mirrored about the surface, whose tangential part is
+// the exit ray's. A child carries the primary's weight before the exit
+// transmission times its reflectance, and its key the sample and the
+// primary's branch (bits 56+). The loop runs in whole blocks, so that
+// every thread of a block takes part in each append.
+constexpr int CHILD_SHIFT = 56;
+__global__ void __launch_bounds__(256) k_rd_spawn(CloakP c, OptsP o, Table T, Table Tc, RenderP R) {
+  const SegMap m = seg_map(T);
+  const unsigned int n = m.off[NSEG];
+  __shared__ unsigned int sh[16];
+  for (unsigned int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const unsigned int idx = base + threadIdx.x;
+    bool have = false;
+    int q = 0, kind = 0, rid = 0;
+    double x[3] = {0, 0, 0}, d[3] = {0, 0, 1}, wpre = 0.0, Rr[2] = {0.0, 0.0};
+    long long key = 0;
+    if (idx < n) {
+      const int sl = slot_at(T, m, idx, q);
+      if (T.status[sl] == RT_RAY_EXITED) {
+        load_state(T, sl, x, d);
+        kind = T.kind[sl];
+        rid = T.bounces[sl] >> 8;
+        double Tt;
+        exit_fresnel(c, kind, rid, x, d, Tt, Rr[0], Rr[1]);
+        wpre = T.wt[sl];
+        key = T.key[sl] | ((long long)(q % R.npol) << CHILD_SHIFT);
+        have = true;
+      }
+    }
+#pragma unroll
+    for (int bp = 0; bp < 2; ++bp) {
+      double vc[3], dm[3] = {d[0], d[1], d[2]};
+      const int kc = (kind & ~1) | bp, qc = (q / R.npol) * R.npol + bp;
+      bool put = false;
+      if (have && Rr[bp] > 0.0) {
+        double nrm[3];
+        boundary_normal(rid, x, nrm);
+        reflect3(dm, nrm);
+        put = refract_in(c, kc, rid, x, dm, vc);
+      }
+      for (int qq = 0; qq < R.ncl * R.npol; ++qq) {
+        const bool p2 = put && qc == qq;
+        const unsigned int cs = block_append(Tc.ctr + C_N(qq), p2, sh);
+        if (p2) {
+          const int slot = (int)(qq * Tc.cap + cs);
+          put_slot(Tc, slot, x, vc, kc, key, 0.0, o.h0, sort_key(c, kc, x, dm));
+          Tc.wt[slot] = wpre * Rr[bp];
+        }
+      }
+    }
+  }
+}
+
+// The children's exits: room code and weight (x the exit transmission) into
+// the chunk-local arrays of their primary's segment and their mode; a child
+// that does not leave keeps weight 0.
+__global__ void __launch_bounds__(256) k_rd_cfinish(CloakP c, RoomP rm, Table Tc, RenderP R) {
+  const SegMap m = seg_map(Tc);
+  const unsigned int n = m.off[NSEG];
+  const long long chunk = R.g1 - R.g0;
+  for (unsigned int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += gridDim.x * blockDim.x) {
+    int qc;
+    const int s = slot_at(Tc, m, idx, qc);
+    if (Tc.status[s] != RT_RAY_EXITED) continue;
+    double x[3], d[3], sh;
+    load_state(Tc, s, x, d);
+    const int code = room_code(rm, x, d, sh);
+    const double w = Tc.wt[s] * exit_transmission(c, Tc.kind[s], Tc.bounces[s] >> 8, x, d);
+    const long long key = Tc.key[s];
+    const int pi = (int)(key >> CHILD_SHIFT), bp = qc % R.npol;
+    const long long gidx = key & ((1LL << CHILD_SHIFT) - 1);
+    const int qp = (qc / R.npol) * R.npol + pi;
+    const long long o = (2LL * qp + bp) * chunk + (gidx - R.g0);
+    R.cw[o] = (float)w;
+    R.ccode[o] = (unsigned char)code;
+  }
+}
+
 // per-pixel mean colour; the 13-entry colour table is staged in LDS
 __global__ void __launch_bounds__(256) k_rd_resolve(RenderP R, const float *__restrict__ table39,
                                                     float *__restrict__ rgb, long long npix) {
@@ -1184,52 +1311,63 @@ __global__ void __launch_bounds__(256) k_rd_resolve(RenderP R, const float *__re
   o[1] = g * inv;
   o[2] = b * inv;
   if (R.tof) R.tof[img * npix + pix] = tn ? (float)(tsum / tn) : __builtin_nanf("");
-  if (R.unpol && pi == 0) {
+  if ((R.unpol || R.grho) && pi == 0) {
     // both branches of this cloak (segments q, q + 1), each sample's colour
-    // times the share of its light the branch carries
-    float ur = 0.f, ug = 0.f, ub = 0.f;
+    // times the share of its light the branch carries; the goggles take half
+    // of that share times the ratio of the goggle field's entry transmission
+    // to the unpolarized one, rho for the in-plane goggle and 2 - rho for
+    // the axial; with first-order reflections, the entry's reflected ray
+    // (R / 2 per branch, R_in / 4 through the in-plane goggle) and the two
+    // reflected waves of each branch's exit (entry shared with the branch)
+    float u[3] = {0.f, 0.f, 0.f}, gr[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
     for (int b = 0; b < 2; ++b) {
-      const unsigned char *cb = R.codes + (q + b) * chunk + lp * R.spp;
-      const float *wb = R.twt + (q + b) * chunk + lp * R.spp;
+      const long long o = (q + b) * chunk + lp * R.spp;
+      const unsigned char *cb = R.codes + o;
+      const float *wb = R.twt + o;
       for (int k = 0; k < R.spp; ++k) {
         const int cc = cb[k];
-        const float wk = wb[k];
-        ur = fmaf(wk, tab[3 * cc], ur);
-        ug = fmaf(wk, tab[3 * cc + 1], ug);
-        ub = fmaf(wk, tab[3 * cc + 2], ub);
-      }
-    }
-    float *u = R.unpol + (((long long)ci * R.n_cams + cam) * npix + pix) * 3;
-    u[0] = ur * inv;
-    u[1] = ug * inv;
-    u[2] = ub * inv;
-  }
-  if (R.grho && pi == 0) {
-    // the goggles: half of each branch's unpolarized share (its image weight)
-    // times the ratio of the goggle field's entry transmission to the
-    // unpolarized one, rho for the in-plane goggle and 2 - rho for the axial
-    float gr[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
-    for (int b = 0; b < 2; ++b) {
-      const unsigned char *cb = R.codes + (q + b) * chunk + lp * R.spp;
-      const float *wb = R.twt + (q + b) * chunk + lp * R.spp;
-      const float *rb = R.grho + (q + b) * chunk + lp * R.spp;
-      for (int k = 0; k < R.spp; ++k) {
-        const int cc = cb[k];
-        const float w0 = 0.5f * wb[k] * rb[k], w1 = wb[k] - w0;
+        const float wk = wb[k], rk = R.grho ? R.grho[o + k] : 1.0f;
+        const float w0 = 0.5f * wk * rk, w1 = wk - w0;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
+          u[j] = fmaf(wk, tab[3 * cc + j], u[j]);
           gr[0][j] = fmaf(w0, tab[3 * cc + j], gr[0][j]);
           gr[1][j] = fmaf(w1, tab[3 * cc + j], gr[1][j]);
         }
+        if (R.refl) {
+          const int ce = R.rcode[o + k];
+          const float we = R.rext[o + k], wi = R.rgin ? R.rgin[o + k] : 0.f;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            u[j] = fmaf(we, tab[3 * ce + j], u[j]);
+            gr[0][j] = fmaf(wi, tab[3 * ce + j], gr[0][j]);
+            gr[1][j] = fmaf(we - wi, tab[3 * ce + j], gr[1][j]);
+          }
+#pragma unroll
+          for (int bp = 0; bp < 2; ++bp) {
+            const long long oc = (2 * (q + b) + bp) * chunk + lp * R.spp + k;
+            const int c2 = R.ccode[oc];
+            const float wc = R.cw[oc], c0 = 0.5f * wc * rk, c1 = wc - c0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              u[j] = fmaf(wc, tab[3 * c2 + j], u[j]);
+              gr[0][j] = fmaf(c0, tab[3 * c2 + j], gr[0][j]);
+              gr[1][j] = fmaf(c1, tab[3 * c2 + j], gr[1][j]);
+            }
+          }
+        }
       }
+    }
+    const long long po = (((long long)ci * R.n_cams + cam) * npix + pix) * 3;
+    if (R.unpol) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) R.unpol[po + j] = u[j] * inv;
     }
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
       if (!R.gog[g]) continue;
-      float *u = R.gog[g] + (((long long)ci * R.n_cams + cam) * npix + pix) * 3;
-      u[0] = gr[g][0] * inv;
-      u[1] = gr[g][1] * inv;
-      u[2] = gr[g][2] * inv;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) R.gog[g][po + j] = gr[g][j] * inv;
     }
   }
 }
@@ -1654,6 +1792,14 @@ int prepare_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts
     return fail(RT_E_UNSUPPORTED, "the unpolarized and goggle images need both branches (pol_mask = 3)");
   if (weights && opts->precision != RT_PREC_FP64)
     return fail(RT_E_UNSUPPORTED, "the Eq. (12) weights are computed in FP64 only");
+  R.refl = aux && aux->reflections ? 1 : 0;
+  R.rext = R.rgin = R.cw = nullptr;
+  R.rcode = R.ccode = nullptr;
+  if (R.refl && !weights)
+    return fail(RT_E_INVALID, "first-order reflections need the unpolarized or a goggle image");
+  // the reflected waves' table holds up to two children per primary and
+  // segment: chunks of at most 2^22 samples keep it near 4 GB
+  if (R.refl) J.chunk = std::min(J.chunk, std::max((long long)spp, REFL_CHUNK / spp * spp));
   return RT_OK;
 }
 
@@ -1672,7 +1818,53 @@ int upload_job(const RenderJob &J, const Workspace &ws, hipStream_t s) {
   return RT_OK;
 }
 
-void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStream_t s, bool profile) {
+// First-order reflections: the child table (two children per primary and
+// segment at most) and the chunk-local reflection arrays (grows, never
+// shrinks)
+struct ReflWs {
+  void *base = nullptr;
+  long long chunk = 0, len = 0;
+  int device = -1;
+  Table Tc{};
+  float *rext = nullptr, *rgin = nullptr, *cw = nullptr;
+  unsigned char *rcode = nullptr, *ccode = nullptr;
+};
+ReflWs g_rws;
+
+int rws_reserve(ReflWs &w, long long chunk, long long len) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(RT_E_DEVICE, "hipGetDevice failed");
+  if (w.base && w.device == dev && w.chunk >= chunk && w.len >= len) return RT_OK;
+  if (w.base) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(w.base);
+    w = ReflWs{};
+  }
+  size_t off = table_bytes(2 * chunk);
+  auto take = [&](size_t b) { size_t o = off; off = align_up(off + b); return o; };
+  const size_t o_re = take(sizeof(float) * len), o_ri = take(sizeof(float) * len);
+  const size_t o_cw = take(sizeof(float) * 2 * len), o_rc = take((size_t)len), o_cc = take((size_t)(2 * len));
+  void *p = nullptr;
+  if (hipMalloc(&p, off) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(RT_E_NOMEM, "hipMalloc of %zu bytes for the reflected waves failed", off);
+  }
+  char *b = (char *)p;
+  w.base = p;
+  w.chunk = chunk;
+  w.len = len;
+  w.device = dev;
+  w.Tc = table_at(b, 2 * chunk);
+  w.rext = (float *)(b + o_re);
+  w.rgin = (float *)(b + o_ri);
+  w.cw = (float *)(b + o_cw);
+  w.rcode = (unsigned char *)(b + o_rc);
+  w.ccode = (unsigned char *)(b + o_cc);
+  return RT_OK;
+}
+
+void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStream_t s, bool profile,
+                    const ReflWs *rw = nullptr) {
   const Table &T = ws.T;
   RenderP R = J.R;
   R.codes = ws.codes;
@@ -1680,15 +1872,38 @@ void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStre
   const bool goggles = R.gog[0] || R.gog[1];
   R.twt = R.unpol || goggles ? ws.twt : nullptr;
   R.grho = goggles ? ws.grho : nullptr;
+  R.refl = R.refl && rw ? 1 : 0;
+  if (R.refl) {
+    R.rext = rw->rext;
+    R.rgin = goggles ? rw->rgin : nullptr;
+    R.cw = rw->cw;
+    R.rcode = rw->rcode;
+    R.ccode = rw->ccode;
+  }
   for (long long g0 = 0; g0 < J.total; g0 += J.chunk) {
     R.g0 = g0;
     R.g1 = std::min(J.total, g0 + J.chunk);
     hipLaunchKernelGGL(k_zero, dim3((C_COUNT + 255) / 256), dim3(256), 0, s, T.ctr, (int)C_COUNT);
-    hipLaunchKernelGGL(k_rd_gen<false>, dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
-                       ws.cams, T, R, CandP{});
+    if (R.grho)
+      hipLaunchKernelGGL((k_rd_gen<false, 2>), dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
+                         ws.cams, T, R, CandP{});
+    else if (R.twt)
+      hipLaunchKernelGGL((k_rd_gen<false, 1>), dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
+                         ws.cams, T, R, CandP{});
+    else
+      hipLaunchKernelGGL((k_rd_gen<false, 0>), dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
+                         ws.cams, T, R, CandP{});
     if (J.n_cloaks) {
       run_transit(J.c, J.o, T, J.block, J.refill, J.grid, s, profile, R.twt != nullptr);
       hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, J.c, J.rm, T, R);
+      if (R.refl) {
+        // the waves reflected at the exits, integrated as a second batch
+        const Table &Tc = rw->Tc;
+        hipLaunchKernelGGL(k_zero, dim3((C_COUNT + 255) / 256), dim3(256), 0, s, Tc.ctr, (int)C_COUNT);
+        hipLaunchKernelGGL(k_rd_spawn, dim3(num_cu() * 8), dim3(256), 0, s, J.c, J.o, T, Tc, R);
+        run_transit(J.c, J.o, Tc, J.block, J.refill, J.grid, s, profile, true);
+        hipLaunchKernelGGL(k_rd_cfinish, dim3(num_cu() * 8), dim3(256), 0, s, J.c, J.rm, Tc, R);
+      }
     }
     long long nres = (R.g1 - R.g0) / R.spp * R.ncl * R.npol;
     hipLaunchKernelGGL(k_rd_resolve, dim3(grid_for(nres, 256)), dim3(256), 0, s, R, ws.table, rgb,
@@ -1760,7 +1975,7 @@ int render_surrogate(rt_model model, const rt_cloak_desc &desc, const RenderJob 
     R.g0 = g0;
     R.g1 = std::min(J.total, g0 + J.chunk);
     hipLaunchKernelGGL(k_zero, dim3((C_COUNT + 255) / 256), dim3(256), 0, s, T.ctr, (int)C_COUNT);
-    hipLaunchKernelGGL(k_rd_gen<true>, dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
+    hipLaunchKernelGGL((k_rd_gen<true, 0>), dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
                        ws.cams, T, R, cw.P);
     unsigned int nc = 0;
     if (hipMemcpyAsync(&nc, T.ctr + C_SUR, sizeof(nc), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -2031,10 +2246,11 @@ int rt_render_multi(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opt
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_ws_mu);
   e = ws_reserve_for(g_ws, J);
+  if (!e && J.R.refl) e = rws_reserve(g_rws, J.chunk, J.chunk * J.R.ncl * J.R.npol);
   if (e) return e;
   e = upload_job(J, g_ws, s);
   if (e) return e;
-  enqueue_render(J, g_ws, rgb, s, true);
+  enqueue_render(J, g_ws, rgb, s, true, J.R.refl ? &g_rws : nullptr);
   return launch_err("render launch");
 }
 
@@ -2081,6 +2297,7 @@ int rt_render_plan_create(const rt_cloak *cloaks, int32_t n_cloaks, const rt_tra
   rt_plan p = new (std::nothrow) rt_plan_s;
   if (!p) return fail(RT_E_NOMEM, "host allocation failed");
   int e = prepare_render(cloaks, n_cloaks, opts, room, cams, n_cams, pol_mask, aux, p->J);
+  if (!e && p->J.R.refl) e = fail(RT_E_UNSUPPORTED, "render plans do not take first-order reflections");
   if (!e) e = ws_reserve_for(p->ws, p->J);
   hipStream_t cs = nullptr;
   if (!e && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)

@@ -83,7 +83,8 @@ class GateOpts(ctypes.Structure):
 class RenderAux(ctypes.Structure):
     _fields_ = [("rec", ctypes.c_void_p), ("status", ctypes.c_void_p), ("code", ctypes.c_void_p),
                 ("nsteps", ctypes.c_void_p), ("tof", ctypes.c_void_p), ("unpol", ctypes.c_void_p),
-                ("goggle_inplane", ctypes.c_void_p), ("goggle_axial", ctypes.c_void_p)]
+                ("goggle_inplane", ctypes.c_void_p), ("goggle_axial", ctypes.c_void_p),
+                ("reflections", ctypes.c_int32)]
 
 
 AUX_FIELDS = ("rec", "status", "code", "nsteps", "tof")
@@ -290,7 +291,8 @@ def _check_out(rgb, shape):
 
 
 def render_multi(cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: int,
-                 aux: bool = False, out=None, unpolarized: bool = False, goggles: bool = False):
+                 aux: bool = False, out=None, unpolarized: bool = False, goggles: bool = False,
+                 reflections: bool = False):
     """rt_render_multi: the same views for several cloaks (sharing geometry) in
     one pass. Returns rgb float32 (n_cloaks, n_cams, npol, h, w, 3) and, with
     aux=True, dict(rec, status, code, nsteps, tof) in the same image order
@@ -298,7 +300,8 @@ def render_multi(cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: i
     unpolarized=True (pol_mask 3, FP64) the dict also holds "unpol", the
     Eq. (12) unpolarized images, float32 (n_cloaks, n_cams, h, w, 3), and
     with goggles=True "goggle_inplane" and "goggle_axial", the images through
-    the in-plane and the axial polarizer (same shape)."""
+    the in-plane and the axial polarizer (same shape); reflections=True adds
+    first-order reflections to those images."""
     import torch
     n = len(cams)
     ncl = max(len(cloaks), 1)
@@ -324,10 +327,14 @@ def render_multi(cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: i
         for name in names:
             aux_t[name] = torch.empty((ncl, n, h, w, 3), dtype=torch.float32, device=dev)
             setattr(aux_s, name, aux_t[name].data_ptr())
+    if reflections:
+        if aux_s is None:
+            aux_t, aux_s = {}, RenderAux()
+        aux_s.reflections = 1
     _check(lib().rt_render_multi(harr, len(cloaks), ctypes.byref(o), ctypes.byref(rm), carr, n,
                                  int(pol_mask), _ptr(rgb),
                                  ctypes.byref(aux_s) if aux_s is not None else None, _stream()))
-    return (rgb, aux_t) if (aux or unpolarized or goggles) else rgb
+    return (rgb, aux_t) if (aux or unpolarized or goggles or reflections) else rgb
 
 
 def render_surrogate(model, cloaks: list, opts: dict, room_d: dict, cams: list, pol_mask: int,

@@ -52,7 +52,7 @@ def test_struct_layouts_match_header():
         "rt_camera": (rt.Camera, ["eye", "fov_deg", "w", "spp", "seed"]),
         "rt_room": (rt.Room, ["lo", "tile", "rgb"]),
         "rt_render_aux": (rt.RenderAux, ["rec", "status", "code", "nsteps", "tof", "unpol", "goggle_inplane",
-                                         "goggle_axial"]),
+                                         "goggle_axial", "reflections"]),
         "rt_train_opts": (rt.TrainOpts, ["lr", "eps", "weight_decay"]),
         "rt_gate_opts": (rt.GateOpts, ["tol", "hres_max", "cap_margin", "min_count", "dilate", "unresolved", "p_min"]),
     }
@@ -156,6 +156,18 @@ def test_render_argument_validation_needs_no_gpu(lib):
     assert b"max_chunk" in lib.rt_last_error()
     cams = (rt.Camera * 1)(rt.camera(W.orbit_camera(0.3, 20.0, 8, 8)))
     o = rt.trace_opts(W.render_opts())
+    # first-order reflections need an image they add to, and render plans
+    # do not take them
+    aux = rt.RenderAux()
+    aux.reflections = 1
+    assert lib.rt_render_multi(harr, 1, ctypes.byref(o), ctypes.byref(room), cams, 1, 3, fake_rgb,
+                               ctypes.byref(aux), None) == rt.RT_E_INVALID
+    assert b"reflections" in lib.rt_last_error()
+    aux.unpol = 8
+    plan = ctypes.c_void_p()
+    assert lib.rt_render_plan_create(harr, 1, ctypes.byref(o), ctypes.byref(room), cams, 1, 3, fake_rgb,
+                                     ctypes.byref(aux), ctypes.byref(plan)) == rt.RT_E_UNSUPPORTED
+    assert b"reflections" in lib.rt_last_error()
     assert lib.rt_render_surrogate(None, harr, 1, ctypes.byref(o), ctypes.byref(room), cams, 1, 3, 0, fake_rgb,
                                    None, None, None, None) == rt.RT_E_INVALID
     assert b"model" in lib.rt_last_error()

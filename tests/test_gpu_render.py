@@ -348,6 +348,50 @@ def test_goggle_image_parity(spp):
         c.close()
 
 
+@pytest.mark.parametrize("spp", [1, 4])
+def test_first_order_reflection_parity(spp):
+    """First-order reflections (rt_render_aux.reflections, Sect. 4) in the
+    unpolarized and both goggle images of both cloaks, against the oracle's
+    primary images plus its reflection contributions (the entry's reflected
+    ray and the two waves reflected at each branch's exit, followed to their
+    own exits); the branch images stay as without; the goggles still add up
+    to the unpolarized image; chunking does not change the images."""
+    import torch
+    from paper_1209_6038_amd import rt
+    n = 24
+    cams = [W.orbit_camera(az, el, n, n, spp=spp, seed=9) for az, el in ((0.2, 0.0), (1.1, 35.0))]
+    room = W.room()
+    ds = [W.cloak(0, height=W.HEIGHT), W.cloak(1, height=W.HEIGHT)]
+    cls = [rt.Cloak(d) for d in ds]
+    say(f"case reflections spp={spp}")
+    kw = {"unpolarized": True, "goggles": True}
+    rgb, aux = rt.render_multi(cls, W.opts_dp45(), room, cams, 3, reflections=True, **kw)
+    rgb0, aux0 = rt.render_multi(cls, W.opts_dp45(), room, cams, 3, **kw)
+    rgb1, aux1 = rt.render_multi(cls, W.opts_dp45(max_chunk=n * n * spp // 3 // spp * spp), room, cams, 3,
+                                 reflections=True, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb, rgb0)
+    added = aux["unpol"] - aux0["unpol"]
+    say(f"  reflections add mean {float(added.mean()):.4e}, max {float(added.max()):.4e}")
+    assert float(added.min()) >= -1e-6 and float(added.max()) > 1e-3
+    for name in ("unpol", "goggle_inplane", "goggle_axial"):
+        assert torch.equal(aux[name], aux1[name]), name
+    assert float((aux["goggle_inplane"] + aux["goggle_axial"] - aux["unpol"]).abs().max()) <= 1e-6
+    for gi, name in ((-1, "unpol"), (0, "goggle_inplane"), (1, "goggle_axial")):
+        img = aux[name].cpu().numpy()
+        for ci, d in enumerate(ds):
+            for k, cam in enumerate(cams):
+                px = np.arange(n * n)
+                base = (oracle.render_unpolarized_pixels(d, W.opts_dp45(), room, cam, k, px) if gi < 0 else
+                        oracle.render_goggle_pixels(d, W.opts_dp45(), room, cam, k, px, gi))
+                ref = base + oracle.render_reflection_pixels(d, W.opts_dp45(), room, cam, k, px, gi)
+                err = np.abs(img[ci, k].reshape(-1, 3) - ref).max()
+                say(f"  {name} cloak {ci} cam {k}: max |image - oracle| = {err:.3e}")
+                assert err <= 1e-5
+    for c in cls:
+        c.close()
+
+
 def test_unpolarized_image_needs_both_branches_and_fp64():
     from paper_1209_6038_amd import rt
     cam = W.orbit_camera(0.0, 0.0, 8, 8)
