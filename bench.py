@@ -91,8 +91,8 @@ ENTERED = (0, 2, 3, 4, 5)
 # scaled by the same counters on a plain device copy of known size
 # (bench.py --copy-probe), per workload. Valid only for the integrator source
 # it was measured on; reported as null otherwise.
-TRAFFIC = {"source_sha256": "3cb87507f08a1c3acecc5e1994f621ef77a3b651225be3d0746c04c75024ef61",
-           "bytes_per_launch": {"orbit": 21_958_862_848}}
+TRAFFIC = {"source_sha256": "5ca49f20cf53588491f194a0c1fe90e775ad5d54d3929ef743a3c4aeaca7750e",
+           "bytes_per_launch": {"orbit": 21_940_867_546}}
 
 
 def traffic_for(workload):
@@ -564,8 +564,9 @@ def weights_workload(args):
 def unpolarized_workload(args):
     """The headline render (both cloaks, 4 views of 1024^2, both branches,
     DP45 1e-8, FP64) with the Eq. (12) unpolarized images and the two
-    polarizer-goggle images, timed beside the same render without images and
-    with the unpolarized images only; one step = one rt_render_multi call."""
+    polarizer-goggle images, timed beside the same render without images,
+    with the unpolarized images only, and with first-order reflections added
+    to the images; one step = one rt_render_multi call."""
     import torch
     from paper_1209_6038_amd import rt
     from paper_1209_6038_amd import workloads as W
@@ -575,12 +576,15 @@ def unpolarized_workload(args):
     cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
     room = W.room()
     _, aux = rt.render_multi(cloaks, opts, room, cams, 3, aux=True, unpolarized=True, goggles=True)
+    _, aux_r = rt.render_multi(cloaks, opts, room, cams, 3, unpolarized=True, goggles=True, reflections=True)
     torch.cuda.synchronize()
     dev = aux["status"].device
     entered = int(torch.isin(aux["status"], torch.tensor(ENTERED, device=dev, dtype=torch.int32)).sum())
     means = {k: round(float(aux[k].mean()), 5) for k in ("unpol", "goggle_inplane", "goggle_axial")}
-    del aux
-    modes = {"none": {}, "unpolarized": {"unpolarized": True}, "goggles": {"unpolarized": True, "goggles": True}}
+    means["unpol_with_reflections"] = round(float(aux_r["unpol"].mean()), 5)
+    del aux, aux_r
+    modes = {"none": {}, "unpolarized": {"unpolarized": True}, "goggles": {"unpolarized": True, "goggles": True},
+             "reflections": {"unpolarized": True, "goggles": True, "reflections": True}}
     timing = {}
     for mode, kw in modes.items():
         for _ in range(args.warmup):
@@ -612,6 +616,8 @@ def unpolarized_workload(args):
                    "ms_per_step_unpolarized_only": round(timing["unpolarized"][0], 4),
                    "images_cost": round(ms / timing["none"][0], 4),
                    "goggles_cost_over_unpolarized": round(ms / timing["unpolarized"][0], 4),
+                   "ms_per_step_with_first_order_reflections": round(timing["reflections"][0], 4),
+                   "reflections_cost_over_goggles": round(timing["reflections"][0] / ms, 4),
                    "mean_image_values": means},
         "roofline": {"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": None, "traffic": None, "kernel": "k_transit (integrator, weighted)",
