@@ -502,24 +502,32 @@ static int integrate(const orc_cloak *c, int branch, const orc_opts *o, double *
    dispersion relation (Eq. (6) with M = eps_o eps_e eps^-1, Eq. (7)).
    Ordinary wave: A = I, f = eps_o. With the ray parameter tau,
    dx/dtau = dH/dk = 2 A k and dk/dtau = -dH/dx; because the ray velocity is
-   v = dx/dt = M^-1 k = A k / f, the optical path advances as dt/dtau = 2 f. */
-static void ham_parts(const orc_cloak *c, int branch, const dual x[3], dual A[3][3], dual *f) {
+   v = dx/dt = M^-1 k = A k / f, the optical path advances as dt/dtau = 2 f.
+   The canonical normalization (canon) is H' = H / f = k^T M^-1 k - 1, the
+   same form with A / f in place of A and 1 in place of f: the same rays, the
+   ray parameter proportional to the optical path (dt/dtau = 2). */
+static void ham_parts(const orc_cloak *c, int branch, const dual x[3], dual A[3][3], dual *f, int canon) {
     dual E[3][3], eo, ee;
     eps_cart(c, x, E, &eo, &ee);
     for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++)
             A[i][j] = branch == ORC_EXTRAORDINARY ? E[i][j] : dk(i == j ? 1.0 : 0.0);
     *f = branch == ORC_EXTRAORDINARY ? dmul(eo, ee) : eo;
+    if (canon) {
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) A[i][j] = ddiv(A[i][j], *f);
+        *f = dk(1.0);
+    }
 }
 
 /* y = (x, k, t): dy/dtau, the gradient of H by forward-mode duals */
-static void rhs_ham(const orc_cloak *c, int branch, const double *y, double *dy) {
+static void rhs_ham(const orc_cloak *c, int branch, const double *y, double *dy, int canon) {
     const double *k = y + 3;
     double A[3][3], dH[3], f = 0.0;
     for (int m = 0; m < 3; m++) {
         dual x[3], Ad[3][3], fd;
         for (int i = 0; i < 3; i++) x[i] = mkd(y[i], i == m ? 1.0 : 0.0);
-        ham_parts(c, branch, x, Ad, &fd);
+        ham_parts(c, branch, x, Ad, &fd, canon);
         double s = 0.0;
         for (int i = 0; i < 3; i++)
             for (int j = 0; j < 3; j++) {
@@ -539,15 +547,15 @@ static void rhs_ham(const orc_cloak *c, int branch, const double *y, double *dy)
 }
 
 /* classical RK4 in tau on the 7-component state (x, k, t) */
-static void rk4_ham(const orc_cloak *c, int branch, const double *y, double h, double *out) {
+static void rk4_ham(const orc_cloak *c, int branch, const double *y, double h, double *out, int canon) {
     double k1[7], k2[7], k3[7], k4[7], t[7];
-    rhs_ham(c, branch, y, k1);
+    rhs_ham(c, branch, y, k1, canon);
     for (int i = 0; i < 7; i++) t[i] = y[i] + 0.5 * h * k1[i];
-    rhs_ham(c, branch, t, k2);
+    rhs_ham(c, branch, t, k2, canon);
     for (int i = 0; i < 7; i++) t[i] = y[i] + 0.5 * h * k2[i];
-    rhs_ham(c, branch, t, k3);
+    rhs_ham(c, branch, t, k3, canon);
     for (int i = 0; i < 7; i++) t[i] = y[i] + h * k3[i];
-    rhs_ham(c, branch, t, k4);
+    rhs_ham(c, branch, t, k4, canon);
     for (int i = 0; i < 7; i++)
         out[i] = y[i] + h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
 }
@@ -555,7 +563,7 @@ static void rk4_ham(const orc_cloak *c, int branch, const double *y, double h, d
 /* k = M v = f A^-1 v, and back v = A k / f, at the point x */
 static void ham_v_to_k(const orc_cloak *c, int branch, const double *x, const double *v, double *k) {
     dual xd[3] = { dk(x[0]), dk(x[1]), dk(x[2]) }, Ad[3][3], fd;
-    ham_parts(c, branch, xd, Ad, &fd);
+    ham_parts(c, branch, xd, Ad, &fd, 0);
     double A[3][3], Ai[3][3];
     for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++) A[i][j] = Ad[i][j].v;
@@ -565,26 +573,26 @@ static void ham_v_to_k(const orc_cloak *c, int branch, const double *x, const do
 
 static void ham_k_to_v(const orc_cloak *c, int branch, const double *x, const double *k, double *v) {
     dual xd[3] = { dk(x[0]), dk(x[1]), dk(x[2]) }, Ad[3][3], fd;
-    ham_parts(c, branch, xd, Ad, &fd);
+    ham_parts(c, branch, xd, Ad, &fd, 0);
     for (int i = 0; i < 3; i++)
         v[i] = (Ad[i][0].v * k[0] + Ad[i][1].v * k[1] + Ad[i][2].v * k[2]) / fd.v;
 }
 
 /* bisection on the tau step for boundary `id`, as crossing() */
 static double crossing_ham(const orc_cloak *c, int branch, const double *y, double h, int id,
-                           double *yout) {
+                           double *yout, int canon) {
     double lo = 0.0, hi = h, mid = h, tol = 1e-13 * c->b;
     double ym[7];
     for (int it = 0; it < 400; it++) {
         double m = 0.5 * (lo + hi);
         if (!(m > lo && m < hi)) break;
         mid = m;
-        rk4_ham(c, branch, y, mid, ym);
+        rk4_ham(c, branch, y, mid, ym, canon);
         double g = gfun(c, id, ym);
         if (fabs(g) <= tol) break;
         if (g < 0.0) lo = mid; else hi = mid;
     }
-    rk4_ham(c, branch, y, mid, yout);
+    rk4_ham(c, branch, y, mid, yout, canon);
     return mid;
 }
 
@@ -593,6 +601,7 @@ static double crossing_ham(const orc_cloak *c, int branch, const double *y, doub
    advances by the optical path. */
 static int integrate_ham(const orc_cloak *c, int branch, const orc_opts *o, double *y,
                          double *t, int64_t *nsteps) {
+    const int canon = o->scheme == ORC_RK4_HAMC;
     double z[7], zn[7], h = o->h;
     memcpy(z, y, 3 * sizeof(double));
     ham_v_to_k(c, branch, y, y + 3, z + 3);
@@ -601,7 +610,7 @@ static int integrate_ham(const orc_cloak *c, int branch, const orc_opts *o, doub
     for (;;) {
         if (*nsteps >= o->max_steps) { ev = EV_MAXSTEPS; break; }
         (*nsteps)++;
-        rk4_ham(c, branch, z, h, zn);
+        rk4_ham(c, branch, z, h, zn, canon);
         int fin = 1;
         for (int i = 0; i < 7; i++) fin &= isfinite(zn[i]) ? 1 : 0;
         if (!fin) { ev = EV_DIVERGED; break; }
@@ -610,7 +619,7 @@ static int integrate_ham(const orc_cloak *c, int branch, const orc_opts *o, doub
         for (int id = 0; id < 4; id++) {
             if (gfun(c, id, zn) >= 0.0) {
                 double zc[7];
-                double hc = crossing_ham(c, branch, z, h, id, zc);
+                double hc = crossing_ham(c, branch, z, h, id, zc, canon);
                 if (first < 0 || hc < hfirst) {
                     first = id; hfirst = hc;
                     memcpy(zfirst, zc, sizeof(zc));
@@ -626,7 +635,7 @@ static int integrate_ham(const orc_cloak *c, int branch, const orc_opts *o, doub
                 double f = -(z[0] * dx + z[1] * dy) / dd;
                 double px = z[0] + f * dx, py = z[1] + f * dy;
                 if (f > 0.0 && f < 1.0 && px * px + py * py < c->a * c->a) {
-                    crossing_ham(c, branch, z, f * h, EV_INNER, zfirst);
+                    crossing_ham(c, branch, z, f * h, EV_INNER, zfirst, canon);
                     first = EV_INNER;
                 }
             }
@@ -1105,8 +1114,8 @@ static int crystal_walk(const orc_cloak *c, int branch, const orc_opts *o, doubl
                         int64_t *nsteps, double *w, exit_state *ex, double *p, double *dout, double *hres) {
     int bounces = 0, status;
     for (;;) {
-        int ev = o->scheme == ORC_RK4_HAM ? integrate_ham(c, branch, o, y, t, nsteps)
-                                          : integrate(c, branch, o, y, t, nsteps);
+        int ev = o->scheme == ORC_RK4_HAM || o->scheme == ORC_RK4_HAMC ? integrate_ham(c, branch, o, y, t, nsteps)
+                                                                       : integrate(c, branch, o, y, t, nsteps);
         if (ev == EV_MAXSTEPS) { status = ORC_MAXSTEPS; break; }
         if (ev == EV_DIVERGED) { status = ORC_DIVERGED; break; }
         double nn[3];

@@ -25,8 +25,10 @@ enum { ORC_ORDINARY = 0, ORC_EXTRAORDINARY = 1 };
 /* ORC_RK4_HAM: classical RK4 with a fixed step in the ray parameter tau of
    the Hamiltonian H(x, k) = k^T A k - f (A = eps, f = eps_o eps_e for the
    extraordinary wave; A = I, f = eps_o for the ordinary one), the form the
-   paper compares its Eq. (8) tracer against (Sect. 4). */
-enum { ORC_RK4 = 0, ORC_DP45 = 1, ORC_RK4_HAM = 2 };
+   paper compares its Eq. (8) tracer against (Sect. 4). ORC_RK4_HAMC: the same
+   with the canonical normalization H / f = k^T M^-1 k - 1 (the same rays,
+   tau proportional to the optical path). */
+enum { ORC_RK4 = 0, ORC_DP45 = 1, ORC_RK4_HAM = 2, ORC_RK4_HAMC = 3 };
 enum {
     ORC_EXITED = 0, ORC_MISSED = 1, ORC_ABSORBED = 2, ORC_MAXSTEPS = 3,
     ORC_DIVERGED = 4, ORC_TIR = 5, ORC_INVALID = 6, ORC_REFLECTED = 7
@@ -40,7 +42,7 @@ typedef struct {
 } orc_cloak;
 
 typedef struct {
-    int32_t scheme;       /* ORC_RK4, ORC_DP45 or ORC_RK4_HAM */
+    int32_t scheme;       /* ORC_RK4, ORC_DP45, ORC_RK4_HAM or ORC_RK4_HAMC */
     int32_t max_bounces;  /* internal reflections before status TIR */
     double h;             /* RK4 step in t, RK4_HAM step in tau, DP45 initial step */
     double rtol, atol, hmax;

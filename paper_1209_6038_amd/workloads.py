@@ -39,6 +39,15 @@ def opts_rk4(h: float = 1e-3, r_out: float = 3.0, **kw) -> dict:
     return d
 
 
+def opts_rk4_hamc(h: float = 1e-3, r_out: float = 3.0, **kw) -> dict:
+    """Classical RK4 with the fixed step h in the ray parameter of the
+    canonically normalized Hamiltonian k^T M^-1 k - 1 (scheme 3); dt/dtau = 2
+    everywhere, so h = 1e-3 is a step of 0.002 in optical path."""
+    d = opts_rk4_ham(h, r_out, **kw)
+    d["scheme"] = 3
+    return d
+
+
 def opts_rk4_ham(h: float = 3e-3, r_out: float = 3.0, **kw) -> dict:
     """Classical RK4 with the fixed step h in the ray parameter tau of the
     Hamiltonian form (scheme 2); dt/dtau = 2 eps_o eps_e = 8 at r = 2 of the

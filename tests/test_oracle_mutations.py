@@ -52,6 +52,10 @@ MUTATIONS = [
      "            int sc = crystal_walk(c, bp, o, yc, &tc, &nc, &wc, NULL, rf->p_child[bp], rf->d_child[bp], &hc);",
      "            int sc = crystal_walk(c, bp, o, yc, &tc, &nc, NULL, NULL, rf->p_child[bp], rf->d_child[bp], &hc);",
      (P.test_first_order_reflection_of_the_radial_ordinary_ray_closed_form,)),
+    ("canonical Hamiltonian keeps the polynomial form's f",
+     "        *f = dk(1.0);\n",
+     "",
+     (lambda: P.test_canonical_hamiltonian_cloaks_inplane_rays_and_is_singular_at_the_axis(0),)),
     ("entry reflection weighted by the transmitted fraction",
      "            rf->w_ext = Rin;",
      "            rf->w_ext = Tin[branch];",

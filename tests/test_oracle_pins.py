@@ -728,6 +728,58 @@ def test_hamiltonian_form_resolves_rays_aimed_near_the_axis():
 
 
 # --------------------------------------------------------------------------
+# the canonically normalized Hamiltonian k^T M^-1 k - 1 (the other reading of
+# the Sect. 4 comparison): the same rays, tau proportional to the optical path
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("axis", [0, 1])
+def test_canonical_hamiltonian_cloaks_inplane_rays_and_is_singular_at_the_axis(axis):
+    """CF1 through the canonical form: in-plane extraordinary rays with
+    |p| >= 0.3 leave along their incident line with the vacuum time of
+    flight (the optical path is twice the ray parameter); fourth order in the
+    step; and, with dt/dtau = 2 everywhere, its right-hand side carries
+    Eq. (8)'s 1/f singularity at r = a: rays aimed within 0.3 of the axis miss
+    the 1e-6 bar at a step where the wide ones meet 1e-8."""
+    rays = W.inplane_bundle(48, 2)
+    pe, de, s, p = _exact_inplane(rays)
+    hit = np.abs(p) < 2.0
+    wide = (np.abs(p) >= 0.3) & hit
+    errs = []
+    for h in (2e-3, 1e-3, 5e-4):
+        r = oracle.trace(W.cloak(axis), W.opts_rk4_hamc(h=h), E, rays)
+        ep = np.linalg.norm(r["out"][:3] - pe, axis=0)
+        errs.append(ep[wide].max())
+        if h == 5e-4:
+            assert (r["status"][wide] == 0).all() and errs[-1] < 1e-9
+            assert np.linalg.norm(r["out"][3:] - de, axis=0)[wide].max() < 1e-9
+            assert np.abs(r["opl"] - s)[wide].max() < 1e-9
+        if h == 1e-3:
+            assert errs[-1] < 2e-8
+            near = np.where(r["status"] == 0, ep, np.inf)[np.abs(p) < 0.3]
+            assert near.max() > 1e-6
+    assert 10.0 < errs[0] / errs[1] < 24.0
+
+
+@pytest.mark.parametrize("case", ["cf2_azimuthal_e", "cf3_radial_o", "cf4_radial_e", "cf4_azimuthal_o"])
+def test_canonical_hamiltonian_matches_the_3d_closed_forms(case):
+    axis, branch = {"cf2_azimuthal_e": (1, E), "cf3_radial_o": (0, O), "cf4_radial_e": (0, E),
+                    "cf4_azimuthal_o": (1, O)}[case]
+    rays = CF.aimed_rays(24, 11, min_ktheta=0.2) if case == "cf2_azimuthal_e" else CF.aimed_rays(12, 13 + axis)
+    r = oracle.trace(W.cloak(axis), W.opts_rk4_hamc(h=5e-4, r_out=2.0), branch, rays)
+    assert (r["status"] == 0).all()
+    for i in range(rays.shape[1]):
+        o, d = rays[:3, i], rays[3:, i]
+        if case == "cf2_azimuthal_e":
+            pe, de, opl = CF.cf2_azimuthal_e(o, d)
+        elif case == "cf3_radial_o":
+            pe, de, opl = CF.cf3_radial_o(o, d)
+        else:
+            pe, de, opl = CF.cf4_quadrature(axis, branch, o, d)
+        np.testing.assert_allclose(r["out"][:3, i], pe, atol=1e-9)
+        np.testing.assert_allclose(r["out"][3:, i], de, atol=1e-9)
+        assert r["opl"][i] == pytest.approx(opl, abs=1e-9)
+
+
+# --------------------------------------------------------------------------
 # Eq. (12): intensity transmission at the interfaces (Sect. 3)
 # --------------------------------------------------------------------------
 def _unit(v):
