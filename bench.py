@@ -430,12 +430,21 @@ def hamiltonian_workload(args):
 
     bundle = W.inplane_bundle(16384, 8)
     pb = bundle[0] * (-bundle[4]) + bundle[1] * bundle[3]
-    sets = {"wide": (np.abs(pb) >= 0.3) & (np.abs(pb) < 1.999),
-            "near_axis": (np.abs(pb) >= 1e-3) & (np.abs(pb) < 0.3)}
+    # the same impact parameters 16 times denser: the "wide" rays fill the
+    # chip's resident lanes several times over, so the comparison is one of
+    # throughput rather than of the longest ray's latency
+    big = W.inplane_bundle(16384 * 16, 8)
+    pbig = big[0] * (-big[4]) + big[1] * big[3]
+    sets = {"wide": (bundle, pb, (np.abs(pb) >= 0.3) & (np.abs(pb) < 1.999)),
+            "near_axis": (bundle, pb, (np.abs(pb) >= 1e-3) & (np.abs(pb) < 0.3)),
+            "wide_full_chip": (big, pbig, (np.abs(pbig) >= 0.3) & (np.abs(pbig) < 1.999))}
+    steps = {"wide": ((4e-3, 2e-3, 1e-3, 5e-4, 2.5e-4), (1.6e-2, 8e-3, 4e-3, 2e-3, 1e-3)),
+             "near_axis": ((4e-3, 2e-3, 1e-3, 5e-4, 2.5e-4), (1.6e-2, 8e-3, 4e-3, 2e-3, 1e-3)),
+             "wide_full_chip": ((2e-3, 1e-3), (4e-3, 2e-3))}
     cl = rt.Cloak(W.cloak(W.RADIAL))
     target = 1e-8
 
-    def sweep(make, steps, sel):
+    def sweep(make, steps, bundle, pb, sel):
         rays_np = np.ascontiguousarray(bundle[:, sel])
         rays = torch.from_numpy(rays_np).cuda()
         o, d, p = rays_np[:3], rays_np[3:], pb[sel]
@@ -462,7 +471,7 @@ def hamiltonian_workload(args):
             transit_ms, launches = rt.profile_read()
             rt.profile_enable(False)
             launch_ms = transit_ms / max(1, launches)
-            per_step = (HAM_COMBINE_FLOPS + 4 * HAM_RHS_FLOPS[1] if opts["scheme"] == 2
+            per_step = (HAM_COMBINE_FLOPS + 4 * HAM_RHS_FLOPS[1] if opts["scheme"] in (2, 3)
                         else attempt_flops(1, 0))
             tflops = float(ns.sum()) * per_step / (launch_ms * 1e-3) / 1e12
             rows.append({"step": h, "ms_per_call": round(a.elapsed_time(b) / 3, 4),
@@ -473,18 +482,28 @@ def hamiltonian_workload(args):
         return rows
 
     res = {}
-    for name, sel in sets.items():
-        eq8 = sweep(lambda h: W.opts_rk4(h, max_steps=200_000), (4e-3, 2e-3, 1e-3, 5e-4, 2.5e-4), sel)
-        ham = sweep(lambda h: W.opts_rk4_ham(h, max_steps=200_000), (1.6e-2, 8e-3, 4e-3, 2e-3, 1e-3), sel)
+    for name, (bnd, pbb, sel) in sets.items():
+        eq8 = sweep(lambda h: W.opts_rk4(h, max_steps=200_000), steps[name][0], bnd, pbb, sel)
+        ham = sweep(lambda h: W.opts_rk4_ham(h, max_steps=200_000), steps[name][1], bnd, pbb, sel)
+        # the canonical normalization: tau steps of h are optical-path steps of 2 h
+        hamc = sweep(lambda h: W.opts_rk4_hamc(h, max_steps=200_000), tuple(0.5 * h for h in steps[name][0]),
+                     bnd, pbb, sel)
         ok_e = [r for r in eq8 if r["max_exit_err"] <= target]
         ok_h = [r for r in ham if r["max_exit_err"] <= target]
+        ok_c = [r for r in hamc if r["max_exit_err"] <= target]
         e = max(ok_e, key=lambda r: r["step"]) if ok_e else None
         h = max(ok_h, key=lambda r: r["step"]) if ok_h else None
+        cc = max(ok_c, key=lambda r: r["step"]) if ok_c else None
         res[name] = {"rays": int(sel.sum()), "eq8_rk4_in_t": eq8, "hamiltonian_rk4_in_tau": ham,
+                     "canonical_hamiltonian_rk4_in_tau": hamc,
                      "at_target": {"eq8": e and {"step": e["step"], "ms_per_call": e["ms_per_call"]},
                                    "hamiltonian": h and {"step": h["step"], "ms_per_call": h["ms_per_call"]},
+                                   "canonical_hamiltonian": cc and {"step": cc["step"],
+                                                                    "ms_per_call": cc["ms_per_call"]},
                                    "time_ratio_hamiltonian_over_eq8": (round(h["ms_per_call"] / e["ms_per_call"], 3)
-                                                                       if e and h else None)}}
+                                                                       if e and h else None),
+                                   "time_ratio_canonical_over_eq8": (round(cc["ms_per_call"] / e["ms_per_call"], 3)
+                                                                     if e and cc else None)}}
     return {"config": {"workload": "Sect. 4 comparison: Eq. (8) vs the Hamiltonian form, fixed-step RK4, "
                                    "in-plane radial cloak, extraordinary rays, exact exit = incident line (CF1), "
                                    "FP64", "target_exit_error": target, "max_steps": 200_000},

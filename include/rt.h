@@ -43,7 +43,7 @@ enum { RT_AXIS_RADIAL = 0, RT_AXIS_AZIMUTHAL = 1 };
 /* Ray branch inside the cloak (Sect. 2): ordinary (Eq. (2)) or extraordinary (Eq. (8)). */
 enum { RT_POL_ORDINARY = 0, RT_POL_EXTRAORDINARY = 1 };
 
-enum { RT_SCHEME_RK4 = 0, RT_SCHEME_DP45 = 1, RT_SCHEME_RK4_HAM = 2 };
+enum { RT_SCHEME_RK4 = 0, RT_SCHEME_DP45 = 1, RT_SCHEME_RK4_HAM = 2, RT_SCHEME_RK4_HAMC = 3 };
 enum { RT_PREC_FP64 = 0, RT_PREC_MIXED = 1 };
 
 /* Per-ray outcome. */
@@ -81,7 +81,10 @@ typedef struct {
    paper compares against (Sect. 4): state (x, k), H = k^T A k - f with A = eps
    and f = eps_o eps_e (extraordinary) or A = I and f = eps_o (ordinary),
    classical RK4 with the fixed step h in the ray parameter tau
-   (dx/dtau = 2 A k, dt/dtau = 2 f). Interfaces, events and
+   (dx/dtau = 2 A k, dt/dtau = 2 f). RT_SCHEME_RK4_HAMC: the same with the
+   canonical normalization H / f = k^T M^-1 k - 1 (the same rays; the ray
+   parameter advances with the optical path, dt/dtau = 2, and the right-hand
+   side is singular at r1 as Eq. (8)'s is). Interfaces, events and
    outputs are those of the other schemes (k is converted to v = M^-1 k at
    every interface). precision: RT_PREC_FP64 (all arithmetic in FP64).
    RT_PREC_MIXED (the derivative evaluated in FP32 away from r1) is rejected

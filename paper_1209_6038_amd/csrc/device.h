@@ -372,23 +372,79 @@ __device__ __forceinline__ void ham_rhs(double a, double kappa, const double x[3
   }
 }
 
-// classical RK4 with step h in tau on (x, k); dt = optical path of the step
+// The canonically normalized Hamiltonian H' = H / f = k^T M^-1 k - 1 with
+// M^-1 = A / f = diag(a_r, a_t, a_z) in (r_hat, theta_hat, z_hat):
+// dx/dtau = 2 (a_r k_r r_hat + a_t k_t theta_hat + a_z k_z z_hat),
+// dk/dtau = -(a_r' k_r^2 + a_t' k_t^2 + a_z' k_z^2) r_hat
+//           - 2 (a_r - a_t) k_r k_t / r theta_hat,
+// dt/dtau = 2. Per branch (s = (1 - a/r)^2, f = kappa^2 s or eps_o):
+// radial-o a = 1/kappa; azimuthal-o a = 1/(kappa s); radial-e (a_r, a_t,
+// a_z) = (1/kappa, 1/(kappa s), 1/(kappa s)); azimuthal-e (1/kappa,
+// 1/(kappa s), 1/kappa). The derivative of 1/(kappa s) is -s'/(kappa s^2).
 template <int KIND>
+__device__ __forceinline__ void ham_rhs_canon(double a, double kappa, const double x[3], const double k[3],
+                                              double dx[3], double dk[3], double& dt) {
+  dt = 2.0;
+  const double ik = 1.0 / kappa;
+  if constexpr (KIND == K_RO) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { dx[i] = 2.0 * ik * k[i]; dk[i] = 0.0; }
+  } else {
+    const double r2 = fma(x[0], x[0], x[1] * x[1]);
+    const double w = rsq64_1(r2);
+    const double q = fma(-a, w, 1.0);
+    const double s = q * q;
+    const double sp = 2.0 * a * q * w * w;  // ds/dr
+    const double is = rcp64(s);
+    const double g = ik * is;              // 1 / (kappa s)
+    const double gp = -g * sp * is;        // its r-derivative
+    const double kr = fma(x[0], k[0], x[1] * k[1]) * w;
+    const double kt = fma(x[0], k[1], -x[1] * k[0]) * w;
+    double ar, at, az, arp, atp, azp;
+    if constexpr (KIND == K_AO) {
+      ar = at = az = g; arp = atp = azp = gp;
+    } else if constexpr (KIND == K_RE) {
+      ar = ik; at = az = g; arp = 0.0; atp = azp = gp;
+    } else {  // K_AE
+      ar = az = ik; at = g; arp = azp = 0.0; atp = gp;
+    }
+    const double ur = 2.0 * ar * kr * w, ut = 2.0 * at * kt * w;
+    dx[0] = fma(ur, x[0], -ut * x[1]);
+    dx[1] = fma(ur, x[1], ut * x[0]);
+    dx[2] = 2.0 * az * k[2];
+    const double P = -(arp * kr * kr + atp * kt * kt + azp * k[2] * k[2]);
+    const double Qt = -2.0 * (ar - at) * kr * kt * w;
+    dk[0] = fma(P * w, x[0], -Qt * w * x[1]);
+    dk[1] = fma(P * w, x[1], Qt * w * x[0]);
+    dk[2] = 0.0;
+  }
+}
+
+template <int KIND, bool CANON>
+__device__ __forceinline__ void ham_rhs_any(double a, double kappa, const double x[3], const double k[3],
+                                            double dx[3], double dk[3], double& dt) {
+  if constexpr (CANON) ham_rhs_canon<KIND>(a, kappa, x, k, dx, dk, dt);
+  else ham_rhs<KIND>(a, kappa, x, k, dx, dk, dt);
+}
+
+// classical RK4 with step h in tau on (x, k); dt = optical path of the step
+// (CANON: the canonically normalized Hamiltonian)
+template <int KIND, bool CANON = false>
 __device__ __forceinline__ void rk4_ham_step(double a, double kappa, const double x[3], const double k[3],
                                              double h, double xn[3], double kn[3], double& dt) {
   double d1x[3], d1k[3], d2x[3], d2k[3], d3x[3], d3k[3], d4x[3], d4k[3], X[3], K[3];
   double t1, t2, t3, t4;
   const double hh = 0.5 * h;
-  ham_rhs<KIND>(a, kappa, x, k, d1x, d1k, t1);
+  ham_rhs_any<KIND, CANON>(a, kappa, x, k, d1x, d1k, t1);
 #pragma unroll
   for (int i = 0; i < 3; ++i) { X[i] = fma(hh, d1x[i], x[i]); K[i] = fma(hh, d1k[i], k[i]); }
-  ham_rhs<KIND>(a, kappa, X, K, d2x, d2k, t2);
+  ham_rhs_any<KIND, CANON>(a, kappa, X, K, d2x, d2k, t2);
 #pragma unroll
   for (int i = 0; i < 3; ++i) { X[i] = fma(hh, d2x[i], x[i]); K[i] = fma(hh, d2k[i], k[i]); }
-  ham_rhs<KIND>(a, kappa, X, K, d3x, d3k, t3);
+  ham_rhs_any<KIND, CANON>(a, kappa, X, K, d3x, d3k, t3);
 #pragma unroll
   for (int i = 0; i < 3; ++i) { X[i] = fma(h, d3x[i], x[i]); K[i] = fma(h, d3k[i], k[i]); }
-  ham_rhs<KIND>(a, kappa, X, K, d4x, d4k, t4);
+  ham_rhs_any<KIND, CANON>(a, kappa, X, K, d4x, d4k, t4);
   const double h6 = h * (1.0 / 6.0);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {

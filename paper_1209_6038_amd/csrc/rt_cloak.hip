@@ -403,8 +403,10 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
   double sum = 0.0;
   double dts = hs;  // optical path of the attempt: its length but in the Hamiltonian form
   if constexpr (HAM) {
-    // state (x, k); the step is in the ray parameter tau
-    rk4_ham_step<KIND>(c.a, c.kappa, L.x, L.v, hs, xn, vn, dts);
+    // state (x, k); the step is in the ray parameter tau of the polynomial
+    // or (RT_SCHEME_RK4_HAMC) the canonically normalized Hamiltonian
+    if (o.scheme == RT_SCHEME_RK4_HAMC) rk4_ham_step<KIND, true>(c.a, c.kappa, L.x, L.v, hs, xn, vn, dts);
+    else rk4_ham_step<KIND, false>(c.a, c.kappa, L.x, L.v, hs, xn, vn, dts);
   } else if (o.scheme == RT_SCHEME_RK4) {
     rk4_step<KIND>(c.a, L.x, L.v, L.A1, hs, xn, vn);
   } else {
@@ -496,7 +498,8 @@ __device__ __forceinline__ int iterate(Lane &L, const CloakP &c, const OptsP &o,
     if constexpr (HAM) {
       // dg/dtau along dx/dtau at the trial point
       double dx[3], dk[3], dt_;
-      ham_rhs<KIND>(c.a, c.kappa, xn, vn, dx, dk, dt_);
+      if (o.scheme == RT_SCHEME_RK4_HAMC) ham_rhs_canon<KIND>(c.a, c.kappa, xn, vn, dx, dk, dt_);
+      else ham_rhs<KIND>(c.a, c.kappa, xn, vn, dx, dk, dt_);
       slope = gsq_slope(c, L.rid, xn, dx);
     } else {
       slope = gsq_slope(c, L.rid, xn, vn);
@@ -1552,8 +1555,9 @@ CloakP make_cloak(const rt_cloak_desc &d) {
 
 int check_opts(const rt_trace_opts *o, double r2, bool need_rout) {
   if (!o) return fail(RT_E_INVALID, "options are NULL");
-  if (o->scheme != RT_SCHEME_RK4 && o->scheme != RT_SCHEME_DP45 && o->scheme != RT_SCHEME_RK4_HAM)
-    return fail(RT_E_INVALID, "scheme must be RT_SCHEME_RK4, RT_SCHEME_DP45 or RT_SCHEME_RK4_HAM");
+  if (o->scheme != RT_SCHEME_RK4 && o->scheme != RT_SCHEME_DP45 && o->scheme != RT_SCHEME_RK4_HAM &&
+      o->scheme != RT_SCHEME_RK4_HAMC)
+    return fail(RT_E_INVALID, "scheme must be RT_SCHEME_RK4, RT_SCHEME_DP45, RT_SCHEME_RK4_HAM or RT_SCHEME_RK4_HAMC");
   if (o->precision != RT_PREC_FP64 && o->precision != RT_PREC_MIXED)
     return fail(RT_E_INVALID, "precision must be RT_PREC_FP64 or RT_PREC_MIXED");
   if (o->precision == RT_PREC_MIXED)
@@ -1607,7 +1611,7 @@ unsigned int transit_grid_t(int block) {
 // the integrator variant the options select: Eq. (8) in (x, v) or the
 // Hamiltonian form, with or without the Eq. (12) weights
 unsigned int transit_grid(const OptsP &o, int block, bool fres = false) {
-  if (o.scheme == RT_SCHEME_RK4_HAM)
+  if (o.scheme == RT_SCHEME_RK4_HAM || o.scheme == RT_SCHEME_RK4_HAMC)
     return fres ? transit_grid_t<true, true>(block) : transit_grid_t<true, false>(block);
   return fres ? transit_grid_t<false, true>(block) : transit_grid_t<false, false>(block);
 }
@@ -1622,9 +1626,10 @@ void run_transit(const CloakP &c, const OptsP &o, const Table &T, int block, int
   ProfEvent pe;
   bool on = false;
   if (profile) prof_begin(s, pe, on);
-  if (o.scheme == RT_SCHEME_RK4_HAM && fres)
+  const bool ham = o.scheme == RT_SCHEME_RK4_HAM || o.scheme == RT_SCHEME_RK4_HAMC;
+  if (ham && fres)
     hipLaunchKernelGGL((k_transit<true, true>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
-  else if (o.scheme == RT_SCHEME_RK4_HAM)
+  else if (ham)
     hipLaunchKernelGGL((k_transit<true, false>), dim3(grid), dim3(block), 0, s, c, o, T, refill);
   else if (fres)
     hipLaunchKernelGGL((k_transit<false, true>), dim3(grid), dim3(block), 0, s, c, o, T, refill);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librt_cloak.so")
 RT_OK, RT_E_INVALID, RT_E_NOMEM, RT_E_DEVICE, RT_E_UNSUPPORTED = range(5)
 RADIAL, AZIMUTHAL = 0, 1
 ORDINARY, EXTRAORDINARY = 0, 1
-RK4, DP45, RK4_HAM = 0, 1, 2
+RK4, DP45, RK4_HAM, RK4_HAMC = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 STATUS_NAMES = ["EXITED", "MISSED", "ABSORBED", "MAXSTEPS", "DIVERGED", "TIR", "INVALID", "REFLECTED"]
 

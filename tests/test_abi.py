@@ -99,7 +99,7 @@ def test_argument_validation_needs_no_gpu(lib):
                               None, None) == rt.RT_OK  # n = 0 is a no-op
     # an FP32 derivative (RT_PREC_MIXED) is rejected for every scheme, with
     # or without the Eq. (12) weights, and in the allocation-free variant;
-    # scheme 3 does not exist
+    # scheme 4 does not exist
     for scheme, h0 in ((rt.RK4_HAM, 1e-3), (rt.DP45, 1e-2), (rt.RK4, 1e-3)):
         o = rt.trace_opts({"scheme": scheme, "precision": rt.MIXED, "h": h0, "fp64_band": 0.05})
         for trans in (None, ctypes.c_void_p(8)):
@@ -113,7 +113,7 @@ def test_argument_validation_needs_no_gpu(lib):
                                       ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8), None, None,
                                       None, None) == rt.RT_E_INVALID
     assert b"at most" in lib.rt_last_error()
-    o = rt.trace_opts({"scheme": 3, "h": 1e-3})
+    o = rt.trace_opts({"scheme": 4, "h": 1e-3})
     assert lib.rt_trace_batch(h, ctypes.byref(o), 1, 10, ctypes.c_void_p(8), ctypes.c_void_p(8),
                               ctypes.c_void_p(8), ctypes.c_void_p(8), None, None, None, None) == rt.RT_E_INVALID
     assert lib.rt_free_cloak(h) == rt.RT_OK

@@ -239,6 +239,36 @@ def test_3d_hamiltonian_form_parity(axis, branch):
     assert (g["nsteps"][ok] == o["nsteps"][ok]).all()
 
 
+@pytest.mark.parametrize("axis,branch", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_3d_canonical_hamiltonian_parity(axis, branch):
+    """The canonically normalized Hamiltonian k^T M^-1 k - 1 (the same rays,
+    tau proportional to the optical path) on random 3-D rays against the
+    finite cloak, against the oracle's dual-number implementation of that
+    Hamiltonian: exits within the 1e-6 bar, same statuses and step counts.
+    Its right-hand side is singular at r = a, and fixed steps fail on the
+    rays that pass next to it (the extraordinary rays of the azimuthal cloak
+    aimed at the axis): there the scheme's answer is a failure either way,
+    and rounding decides which one (drift past the DIVERGED bar, a step into
+    the metal, the step limit). Where the oracle's ray fails, the GPU's must
+    fail too (any failure status); everywhere else the statuses are equal."""
+    rays = W.random_rays(1024, seed=400 + 10 * axis + branch, z_range=(-1.0, 5.0))
+    c = W.cloak(axis, height=W.HEIGHT)
+    op = W.opts_rk4_hamc(h=1e-3)
+    say(f"case 3d canonical hamiltonian axis={axis} branch={branch}")
+    g = gpu_trace(c, op, branch, rays)
+    o = oracle.trace(c, op, branch, rays)
+    say(f"  status counts oracle {np.bincount(o['status'], minlength=8)}")
+    fails = (2, 3, 4)  # ABSORBED, MAXSTEPS, DIVERGED
+    failed = np.isin(o["status"], fails)
+    say(f"  oracle failures {int(failed.sum())}, of which the GPU reports another failure status "
+        f"{int((failed & (g['status'] != o['status'])).sum())}")
+    assert failed.sum() <= 32  # 14 of the 1,024 at this seed
+    assert np.isin(g["status"][failed], fails).all()
+    check_trace(g, o, mask=~failed, opl_tol=2e-6, label=f"3d hamc a{axis} b{branch}")
+    ok = o["status"] == 0
+    assert (g["nsteps"][ok] == o["nsteps"][ok]).all()
+
+
 def test_hamiltonian_form_inplane_full_size():
     """The in-plane workload through the Hamiltonian form (radial cloak,
     extraordinary rays, tau step 2e-3). Every entering ray aimed at least
