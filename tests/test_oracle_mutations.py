@@ -56,6 +56,14 @@ MUTATIONS = [
      "        *f = dk(1.0);\n",
      "",
      (lambda: P.test_canonical_hamiltonian_cloaks_inplane_rays_and_is_singular_at_the_axis(0),)),
+    ("step growth capped at 4 instead of 5",
+     "    else fac = fmin(5.0, fmax(0.2, 0.9 * pow(err, -0.2)));",
+     "    else fac = fmin(4.0, fmax(0.2, 0.9 * pow(err, -0.2)));",
+     (P.test_dp45_controller_on_straight_chords,)),
+    ("hmax ignored by the step controller",
+     "            h_next = fmin(h * dp45_factor(err, after_reject), o->hmax);",
+     "            h_next = h * dp45_factor(err, after_reject);",
+     (P.test_dp45_controller_on_straight_chords,)),
     ("entry reflection weighted by the transmitted fraction",
      "            rf->w_ext = Rin;",
      "            rf->w_ext = Tin[branch];",

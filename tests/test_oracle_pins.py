@@ -697,6 +697,41 @@ def test_hamiltonian_form_matches_the_3d_closed_forms(case):
         assert r["opl"][i] == pytest.approx(opl, abs=3e-9)
 
 
+def test_dp45_controller_on_straight_chords():
+    """The radial cloak's ordinary rays travel straight (eps_o = kappa is
+    constant, Sect. 4), so every DP45 attempt is exact and its error
+    estimate zero: the controller grows the step by its largest factor, 5,
+    up to hmax, and a reflection at the metal restarts it at h. A chord of
+    optical length L then takes the smallest n attempts whose steps
+    min(h 5^k, hmax), k < n, add up to at least L. In-plane rays (infinite
+    cylinder), chord lengths from Snell's law at n = sqrt(kappa) = 2: one
+    chord from r = b to r = b, or two equal ones to the mirror and back."""
+    rays = W.inplane_bundle(40, 2)
+    p = rays[0] * (-rays[4]) + rays[1] * rays[3]
+    nidx, a, b = 2.0, 1.0, 2.0
+
+    def attempts(L, h0, hmax):
+        s, k, h = 0.0, 0, h0
+        while True:
+            s += h
+            k += 1
+            if s >= L:
+                return k
+            h = min(5.0 * h, hmax)
+
+    for h0, hmax in ((1e-2, 0.5), (3e-3, 0.13)):
+        r = oracle.trace(W.cloak(0), W.opts_dp45(h=h0, hmax=hmax), O, rays)
+        hit = np.abs(p) < b
+        assert hit.sum() > 40 and (r["status"][hit] == 0).all()
+        for i in np.flatnonzero(hit):
+            pin = abs(p[i]) / nidx
+            if pin < a:
+                want = 2 * attempts(nidx * (math.sqrt(b * b - pin * pin) - math.sqrt(a * a - pin * pin)), h0, hmax)
+            else:
+                want = attempts(nidx * 2.0 * math.sqrt(b * b - pin * pin), h0, hmax)
+            assert r["nsteps"][i] == want, (p[i], r["nsteps"][i], want)
+
+
 def test_hamiltonian_form_is_fourth_order_in_tau():
     rays = W.inplane_bundle(32, 2)
     pe, de, s, p = _exact_inplane(rays)
