@@ -720,10 +720,15 @@ def orbit_headline(args, log):
     entered, flops = orbit_counts(cloaks, room, frames, log)
     # images per launch group, each a dense [cloak][frame][branch][h][w][3] block
     out = torch.empty((len(groups), 2, fpl, 2, 4096, 4096, 3), dtype=torch.float32, device=dev)
+    # consecutive launch groups alternate between streams: the library keeps
+    # a workspace per stream, so one group's camera rays, sort and finish run
+    # beside the previous group's integrator and its drain
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(args.orbit_streams - 1)]
 
-    def step():
+    def step(overlap=True):
         for k, g in enumerate(groups):
-            rt.render_multi(cloaks, opts, room, g, 3, out=out[k])
+            with torch.cuda.stream(streams[k % len(streams)] if overlap else streams[0]):
+                rt.render_multi(cloaks, opts, room, g, 3, out=out[k])
 
     for _ in range(args.warmup):
         step()
@@ -734,13 +739,14 @@ def orbit_headline(args, log):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     log(f"orbit: {ms:.1f} ms per orbit ({ms / len(frames):.2f} ms per frame)")
-    # integrator launches timed with HIP events on the launch stream
+    # integrator launches timed with HIP events on the launch stream, one
+    # stream (overlapped launches would share the chip)
     rt.profile_enable(True)
     rt.profile_read()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
-    step()
+    step(overlap=False)
     e1.record()
     torch.cuda.synchronize()
     eager_ms = e0.elapsed_time(e1)
@@ -762,13 +768,16 @@ def orbit_headline(args, log):
                    "frames": len(frames), "frames_per_launch": fpl, "ray_branch_samples_per_step": samples,
                    "rays_entering_cloak_per_step": entered, "miss_fraction": round(1.0 - entered / samples, 4),
                    "all_samples_per_s_M": round(samples / (ms * 1e-3) / 1e6, 1),
-                   "ms_per_frame": round(ms / len(frames), 3), "parallelism": "single GPU"},
+                   "ms_per_frame": round(ms / len(frames), 3), "parallelism": "single GPU",
+                   "streams": len(streams), "ms_per_step_one_stream": round(eager_ms, 3)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic_for("orbit"),
                      "kernel": "k_transit (integrator)", "avg_launch_ms": round(avg_launch_ms, 3),
                      "launches_per_step": launches, "flops_per_launch": round(flops / max(launches, 1)),
                      "integrator_share_of_step": round(transit_ms / eager_ms, 4)},
     }
+    torch.cuda.synchronize()
+    rt.release_workspace()  # the second stream's workspace (~70 GB) is not needed further on
     return rec, out, (frames, groups, opts, cloaks, room)
 
 
@@ -989,6 +998,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5, help="timed orbits (steps of the headline)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--frames", type=int, default=36, help="orbit frames per step (the workload has 36)")
+    ap.add_argument("--orbit-streams", type=int, default=2, choices=(1, 2),
+                    help="streams the orbit's launch groups alternate between (the library keeps a workspace "
+                         "for each of two)")
     ap.add_argument("--frames-per-launch", type=int, default=2,
                     help="4096^2 x 4 spp frames per integrator launch (1-4)")
     ap.add_argument("--workload", choices=("orbit", "render_1024", "batched", "inplane",

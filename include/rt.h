@@ -21,7 +21,13 @@
  *    output buffers.
  *  - The library allocates a device workspace on first use and grows it when
  *    a larger call needs it (hipMalloc, synchronous); it is released by
- *    rt_release_workspace() or at process exit. Renders are processed in
+ *    rt_release_workspace() or at process exit. Calls that use it on
+ *    different streams are ordered on the device: each waits for the
+ *    previous use (an event), so their work does not overlap, except that
+ *    rt_render and rt_render_multi keep a second workspace for a second
+ *    stream: renders issued alternately on two streams run side by side
+ *    (twice the workspace memory). A call waits on the host for its
+ *    workspace's previous use before it copies its camera records. Renders are processed in
  *    chunks of camera samples (2^26 unless max_chunk says otherwise, at most
  *    2^28), with a workspace of ~0.5 KB per sample of a chunk (~31 GB for a
  *    4096 x 4096 x 4 spp view).

@@ -1400,6 +1400,40 @@ struct Workspace {
 
 std::mutex g_ws_mu;
 Workspace g_ws;
+// The direct calls' shared workspaces. Every call waits on its stream for
+// the previous use of the workspace it takes (which may have been enqueued
+// on another stream) and marks its own use with an event, so calls on
+// several streams are ordered where they share memory. rt_render_multi
+// keeps a second workspace for a second stream: consecutive renders on two
+// streams then run side by side, one's camera rays and sort next to the
+// other's integrator and its drain. The other direct calls, the surrogate
+// and reflection buffers use the first.
+Workspace g_ws2;
+hipEvent_t g_ws_ev[2] = {nullptr, nullptr};
+int g_ws_evdev[2] = {-1, -1};
+hipStream_t g_ws_stream[2] = {nullptr, nullptr};
+unsigned int g_ws_turn = 0;
+
+int ws_order(int k, hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(RT_E_DEVICE, "hipGetDevice failed");
+  if (g_ws_ev[k] && g_ws_evdev[k] != dev) {
+    // the previous use was on another device: a workspace is reallocated on
+    // the device of its next use, which synchronizes first
+    (void)hipEventDestroy(g_ws_ev[k]);
+    g_ws_ev[k] = nullptr;
+  }
+  if (!g_ws_ev[k]) {
+    if (hipEventCreateWithFlags(&g_ws_ev[k], hipEventDisableTiming) != hipSuccess)
+      return fail(RT_E_DEVICE, "event creation failed");
+    g_ws_evdev[k] = dev;
+    return RT_OK;
+  }
+  if (hipStreamWaitEvent(s, g_ws_ev[k], 0) != hipSuccess) return fail(RT_E_DEVICE, "stream wait failed");
+  return RT_OK;
+}
+
+void ws_done(int k, hipStream_t s) { (void)hipEventRecord(g_ws_ev[k], s); }
 int g_num_cu = 0;
 
 // integrator timing (rt_profile_*): event pairs around every transit launch
@@ -2112,6 +2146,12 @@ int rt_profile_read(double *transit_ms, int64_t *launches) {
 int rt_release_workspace(void) {
   std::lock_guard<std::mutex> lk(g_ws_mu);
   ws_free(g_ws);
+  ws_free(g_ws2);
+  if (g_rws.base) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g_rws.base);
+    g_rws = ReflWs{};
+  }
   if (g_cws.base) {
     (void)hipDeviceSynchronize();
     (void)hipFree(g_cws.base);
@@ -2126,10 +2166,13 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
   int e = check_trace_args(cloak, opts, pol, n, in6, out6, opl, status, trans);
   if (e || n == 0) return e;
   std::lock_guard<std::mutex> lk(g_ws_mu);
-  e = ws_reserve(g_ws, n, 0, 0);
+  e = ws_order(0, (hipStream_t)stream);
+  if (!e) e = ws_reserve(g_ws, n, 0, 0);
   if (e) return e;
-  return enqueue_trace(cloak, opts, pol, n, in6, out6, opl, status, hres, nsteps, trans, g_ws.T,
-                       (hipStream_t)stream, true);
+  e = enqueue_trace(cloak, opts, pol, n, in6, out6, opl, status, hres, nsteps, trans, g_ws.T,
+                    (hipStream_t)stream, true);
+  ws_done(0, (hipStream_t)stream);
+  return e;
 }
 
 int rt_trace_batch_noalloc(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64_t n,
@@ -2220,7 +2263,8 @@ int rt_transit_exact(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_op
   if (!x6 || !y5 || !status) return fail(RT_E_INVALID, "x6, y5 and status are required");
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_ws_mu);
-  e = ws_reserve(g_ws, n, 0, 0);
+  e = ws_order(0, s);
+  if (!e) e = ws_reserve(g_ws, n, 0, 0);
   if (e) return e;
   const Table &T = g_ws.T;
   CloakP c = make_cloak(cloaks[0]->d);
@@ -2232,13 +2276,17 @@ int rt_transit_exact(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_op
   hipLaunchKernelGGL(k_sx_entry, dim3(grid_for(n, 256)), dim3(256), 0, s, c, o, T, (long long)n,
                      (long long)ld, x6, mask, have_axes, y5, status, hres, nsteps);
   e = launch_err("entry launch");
-  if (e) return e;
-  run_transit(c, o, T, block, refill, grid, s, true);
-  e = launch_err("transit launch");
-  if (e) return e;
-  hipLaunchKernelGGL(k_sx_finish, dim3(num_cu() * 8), dim3(256), 0, s, c, T, (long long)ld, y5, status,
-                     hres, nsteps);
-  return launch_err("finish launch");
+  if (!e) {
+    run_transit(c, o, T, block, refill, grid, s, true);
+    e = launch_err("transit launch");
+  }
+  if (!e) {
+    hipLaunchKernelGGL(k_sx_finish, dim3(num_cu() * 8), dim3(256), 0, s, c, T, (long long)ld, y5, status,
+                       hres, nsteps);
+    e = launch_err("finish launch");
+  }
+  ws_done(0, s);
+  return e;
 }
 
 int rt_render_multi(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opts *opts,
@@ -2250,12 +2298,23 @@ int rt_render_multi(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opt
   if (e) return e;
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_ws_mu);
-  e = ws_reserve_for(g_ws, J);
+  // the workspace this stream used last, else the one used longer ago
+  // (renders with reflections stay on the first, beside their buffers)
+  int k = 0;
+  if (!J.R.refl) {
+    if (s == g_ws_stream[0]) k = 0;
+    else if (s == g_ws_stream[1]) k = 1;
+    else k = (int)(g_ws_turn++ & 1u);
+    g_ws_stream[k] = s;
+  }
+  Workspace &ws = k ? g_ws2 : g_ws;
+  e = ws_order(k, s);
+  if (!e) e = ws_reserve_for(ws, J);
   if (!e && J.R.refl) e = rws_reserve(g_rws, J.chunk, J.chunk * J.R.ncl * J.R.npol);
+  if (!e) e = upload_job(J, ws, s);
   if (e) return e;
-  e = upload_job(J, g_ws, s);
-  if (e) return e;
-  enqueue_render(J, g_ws, rgb, s, true, J.R.refl ? &g_rws : nullptr);
+  enqueue_render(J, ws, rgb, s, true, J.R.refl ? &g_rws : nullptr);
+  ws_done(k, s);
   return launch_err("render launch");
 }
 
@@ -2275,13 +2334,14 @@ int rt_render_surrogate(rt_model model, const rt_cloak *cloaks, int32_t n_cloaks
   if (e) return e;
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_ws_mu);
-  e = ws_reserve_for(g_ws, J);
+  e = ws_order(0, s);
+  if (!e) e = ws_reserve_for(g_ws, J);
   if (!e) e = cws_reserve(g_cws, J.chunk * J.R.ncl * J.R.npol);
-  if (e) return e;
-  e = upload_job(J, g_ws, s);
+  if (!e) e = upload_job(J, g_ws, s);
   if (e) return e;
   long long c2[2] = {0, 0};
   e = render_surrogate(model, cloaks[0]->d, J, g_ws, g_cws, min_difficulty, rgb, s, counts ? c2 : nullptr);
+  ws_done(0, s);
   if (e) return e;
   if (counts) { counts[0] = c2[0]; counts[1] = c2[1]; }
   return launch_err("surrogate render launch");
@@ -2368,7 +2428,8 @@ int rt_autotune_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_
   int bb = J.block, br = J.refill;
   {
     std::lock_guard<std::mutex> lk(g_ws_mu);
-    e = ws_reserve_for(g_ws, J);
+    e = ws_order(0, s);
+    if (!e) e = ws_reserve_for(g_ws, J);
     if (!e) e = upload_job(J, g_ws, s);
     for (int bi = 0; !e && bi < 3; ++bi)
       for (int ri = 0; !e && ri < 4; ++ri) {
@@ -2386,6 +2447,7 @@ int rt_autotune_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_
         }
         if (ms * 0.5 < best) { best = ms * 0.5; bb = J.block; br = J.refill; }
       }
+    ws_done(0, s);
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);

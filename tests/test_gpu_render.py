@@ -310,6 +310,44 @@ def test_unpolarized_image_parity(spp):
         c.close()
 
 
+def test_renders_on_two_streams_equal_renders_on_one():
+    """Direct render calls alternating between two streams (the library then
+    uses a workspace per stream and lets them overlap), with traces on a third
+    stream in between (ordered after the renders that share their workspace),
+    give the images and exits of the same calls issued one after another on
+    one stream, bit for bit."""
+    import torch
+    from paper_1209_6038_amd import rt
+    cls = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
+    room = W.room()
+    groups = [[W.orbit_camera(0.4 * k + 0.1 * j, 10.0 * k, 96, 64, spp=4, seed=k) for j in range(2)]
+              for k in range(6)]
+    rays = torch.from_numpy(W.random_rays(4096, seed=21, z_range=(-1.0, 5.0))).cuda()
+    say("case two streams")
+
+    def run(streams):
+        imgs, exits = [], []
+        for k, g in enumerate(groups):
+            with torch.cuda.stream(streams[k % len(streams)]):
+                imgs.append(rt.render_multi(cls, W.render_opts(), room, g, 3))
+            if k % 2 == 1:
+                with torch.cuda.stream(streams[-1]):
+                    exits.append(rt.trace_batch(cls[k % 2], W.opts_dp45(), 1, rays)["out"])
+        torch.cuda.synchronize()
+        return imgs, exits
+
+    one = torch.cuda.current_stream()
+    ref_i, ref_e = run([one])
+    alt_i, alt_e = run([one, torch.cuda.Stream(), torch.cuda.Stream()])
+    for a, b in zip(ref_i, alt_i):
+        assert torch.equal(a, b)
+    for a, b in zip(ref_e, alt_e):
+        assert torch.equal(a, b)
+    for c in cls:
+        c.close()
+    rt.release_workspace()
+
+
 @pytest.mark.parametrize("spp", [1, 4])
 def test_goggle_image_parity(spp):
     """The images through the in-plane and the axial polarizer
