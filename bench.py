@@ -777,7 +777,7 @@ def orbit_headline(args, log):
                      "integrator_share_of_step": round(transit_ms / eager_ms, 4)},
     }
     torch.cuda.synchronize()
-    rt.release_workspace()  # the second stream's workspace (~70 GB) is not needed further on
+    rt.release_workspace()  # the other streams' workspaces (~70 GB each) are not needed further on
     return rec, out, (frames, groups, opts, cloaks, room)
 
 
@@ -998,9 +998,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5, help="timed orbits (steps of the headline)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--frames", type=int, default=36, help="orbit frames per step (the workload has 36)")
-    ap.add_argument("--orbit-streams", type=int, default=2, choices=(1, 2),
-                    help="streams the orbit's launch groups alternate between (the library keeps a workspace "
-                         "for each of two)")
+    ap.add_argument("--orbit-streams", type=int, default=2, choices=(1, 2, 3, 4),
+                    help="streams the orbit's launch groups rotate over (the library keeps a workspace for each "
+                         "of up to four)")
     ap.add_argument("--frames-per-launch", type=int, default=2,
                     help="4096^2 x 4 spp frames per integrator launch (1-4)")
     ap.add_argument("--workload", choices=("orbit", "render_1024", "batched", "inplane",
@@ -1026,6 +1026,9 @@ def main():
         ap.error("--frames-per-launch must be in 1..4 (at most 2^28 samples per launch)")
     if not 1 <= args.frames <= 36 or args.frames % args.frames_per_launch:
         ap.error("--frames must be in 1..36 and a multiple of --frames-per-launch")
+    if args.orbit_streams * args.frames_per_launch > 6:
+        ap.error("--orbit-streams x --frames-per-launch must be at most 6: each stream's workspace takes "
+                 "~35 GB per frame of a launch, and the orbit's pixels another ~29 GB of the 288 GB")
     if args.copy_probe:
         copy_probe()
         return

@@ -24,9 +24,10 @@
  *    rt_release_workspace() or at process exit. Calls that use it on
  *    different streams are ordered on the device: each waits for the
  *    previous use (an event), so their work does not overlap, except that
- *    rt_render and rt_render_multi keep a second workspace for a second
- *    stream: renders issued alternately on two streams run side by side
- *    (twice the workspace memory). A call waits on the host for its
+ *    rt_render and rt_render_multi keep up to four workspaces, one per
+ *    stream they are called on (a fifth stream takes the one used longest
+ *    ago): renders issued on several streams run side by side, at one
+ *    workspace's memory per stream. A call waits on the host for its
  *    workspace's previous use before it copies its camera records. Renders are processed in
  *    chunks of camera samples (2^26 unless max_chunk says otherwise, at most
  *    2^28), with a workspace of ~0.5 KB per sample of a chunk (~31 GB for a

@@ -1404,15 +1404,20 @@ Workspace g_ws;
 // the previous use of the workspace it takes (which may have been enqueued
 // on another stream) and marks its own use with an event, so calls on
 // several streams are ordered where they share memory. rt_render_multi
-// keeps a second workspace for a second stream: consecutive renders on two
-// streams then run side by side, one's camera rays and sort next to the
-// other's integrator and its drain. The other direct calls, the surrogate
-// and reflection buffers use the first.
-Workspace g_ws2;
-hipEvent_t g_ws_ev[2] = {nullptr, nullptr};
-int g_ws_evdev[2] = {-1, -1};
-hipStream_t g_ws_stream[2] = {nullptr, nullptr};
-unsigned int g_ws_turn = 0;
+// keeps up to NWS workspaces, one per stream it sees (a new stream takes the
+// workspace used longest ago): renders on several streams then run side by
+// side, one's camera rays and sort next to another's integrator and its
+// drain. The other direct calls, the surrogate and reflection buffers use
+// the first.
+constexpr int NWS = 4;
+Workspace g_wsx[NWS - 1];  // workspaces 1..NWS-1 (workspace 0 is g_ws)
+hipEvent_t g_ws_ev[NWS] = {nullptr, nullptr, nullptr, nullptr};
+int g_ws_evdev[NWS] = {-1, -1, -1, -1};
+hipStream_t g_ws_stream[NWS] = {nullptr, nullptr, nullptr, nullptr};
+unsigned long long g_ws_last[NWS] = {0, 0, 0, 0};  // call counter at the last use
+unsigned long long g_ws_calls = 0;
+
+Workspace &ws_at(int k) { return k ? g_wsx[k - 1] : g_ws; }
 
 int ws_order(int k, hipStream_t s) {
   int dev = 0;
@@ -2146,7 +2151,7 @@ int rt_profile_read(double *transit_ms, int64_t *launches) {
 int rt_release_workspace(void) {
   std::lock_guard<std::mutex> lk(g_ws_mu);
   ws_free(g_ws);
-  ws_free(g_ws2);
+  for (int j = 0; j < NWS - 1; ++j) ws_free(g_wsx[j]);
   if (g_rws.base) {
     (void)hipDeviceSynchronize();
     (void)hipFree(g_rws.base);
@@ -2298,16 +2303,22 @@ int rt_render_multi(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_opt
   if (e) return e;
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_ws_mu);
-  // the workspace this stream used last, else the one used longer ago
+  // the workspace this stream used last, else the one used longest ago
   // (renders with reflections stay on the first, beside their buffers)
   int k = 0;
   if (!J.R.refl) {
-    if (s == g_ws_stream[0]) k = 0;
-    else if (s == g_ws_stream[1]) k = 1;
-    else k = (int)(g_ws_turn++ & 1u);
-    g_ws_stream[k] = s;
+    k = -1;
+    for (int j = 0; j < NWS && k < 0; ++j)
+      if (g_ws_last[j] && g_ws_stream[j] == s) k = j;
+    if (k < 0) {
+      k = 0;
+      for (int j = 1; j < NWS; ++j)
+        if (g_ws_last[j] < g_ws_last[k]) k = j;
+    }
   }
-  Workspace &ws = k ? g_ws2 : g_ws;
+  g_ws_stream[k] = s;
+  g_ws_last[k] = ++g_ws_calls;
+  Workspace &ws = ws_at(k);
   e = ws_order(k, s);
   if (!e) e = ws_reserve_for(ws, J);
   if (!e && J.R.refl) e = rws_reserve(g_rws, J.chunk, J.chunk * J.R.ncl * J.R.npol);
