@@ -91,8 +91,8 @@ ENTERED = (0, 2, 3, 4, 5)
 # scaled by the same counters on a plain device copy of known size
 # (bench.py --copy-probe), per workload. Valid only for the integrator source
 # it was measured on; reported as null otherwise.
-TRAFFIC = {"source_sha256": "5ca49f20cf53588491f194a0c1fe90e775ad5d54d3929ef743a3c4aeaca7750e",
-           "bytes_per_launch": {"orbit": 21_940_867_546}}
+TRAFFIC = {"source_sha256": "3e7abe4cd643f0461a338ffbc0f325e3eac713306c36663ca1b059a8deeb8f11",
+           "bytes_per_launch": {"orbit": 22_100_462_547}}
 
 
 def traffic_for(workload):
