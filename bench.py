@@ -308,6 +308,134 @@ def surrogate_leg(steps: int, n_train: int, log, keep: bool = False):
     return rec
 
 
+def cap_leg(side_model, log, steps: int = 60000, n_train: int = 8_000_000, n_cal: int = 16_000_000):
+    """The surrogate's cap job: a second model learns the side entries of the
+    height-4 cloaks whose path leaves through an end cap (the closed-form
+    transits are those of the infinite cylinder, and the side job's gate
+    rejects every entry that meets a cap). Trained on the cap exits of
+    n_train uniform side entries, calibrated on n_cal others, measured on
+    1 M held-out entries against the exact transit: the share of cap exits
+    accepted with the network and with the closed forms alone (a side model
+    whose network output is zeroed, every cell trusted), the accepted exit
+    errors, and the side model alone against the side model chained to the
+    cap model (rows the first rejects go to the second), with times."""
+    import numpy as np
+    import torch
+    from paper_1209_6038_amd import rt
+    from paper_1209_6038_amd import surrogate as S
+    from paper_1209_6038_amd import workloads as W
+
+    def sync():
+        torch.cuda.synchronize()
+
+    def timed(fn, reps=3):
+        fn()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        sync()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        sync()
+        return a.elapsed_time(b) / reps
+
+    tol = 1e-3
+    cl = S.make_cloaks(W.HEIGHT)
+    op = S.exact_opts()
+    sync()
+    t0 = time.perf_counter()
+    x_tr, t_tr, w_tr = S.cap_training_set(n_train, 1101, op)
+    sync()
+    t_label = time.perf_counter() - t0
+    rows = x_tr.shape[1]
+    m = rt.Surrogate(seed=0)
+    m.set_job(rt.CAP, cl[0])
+    m.fit_scaling(x_tr, t_tr, w_tr)
+    batch = 16384
+    t0 = time.perf_counter()
+    loss = S.train(m, x_tr, t_tr, w_tr, steps=steps, batch=batch, lr=1e-3, lr_end=1e-5, huber=0.01)
+    sync()
+    t_train = time.perf_counter() - t0
+    del x_tr, t_tr, w_tr
+    log(f"cap model: {rows} cap exits of {n_train} entries labelled in {t_label:.2f} s, trained {steps} steps in "
+        f"{t_train:.1f} s (loss {loss:.2e})")
+    x_cal = S.features(n_cal, 1102)
+    y_cal, st_cal, h_cal = rt.transit_exact(cl, op, x_cal, hres=True)
+    trusted = m.calibrate(cl, x_cal, y_cal, st_cal, tol=0.5 * tol, min_count=CAP_MIN_COUNT, dilate=CAP_DILATE,
+                          hres_exact=h_cal, unresolved=UNRESOLVED, p_min=0.0)
+    del x_cal, y_cal, st_cal, h_cal
+    n = 1_000_000
+    x_ev = S.features(n, 1103)
+    y_ex, st_ex, h_ex = rt.transit_exact(cl, op, x_ev, hres=True)
+    up = x_ev[3] >= 0
+    cap = (st_ex == 0) & (((y_ex[1] > W.HEIGHT) & up) | ((y_ex[1] < 0.0) & ~up))
+    # references the integrator resolves: drift below UNRESOLVED and below
+    # the squared normal wave number (cos alpha cos beta)^2 that the exit
+    # keeps (a grazing side entry's drift above it turns the side exit into
+    # a total reflection, and the ray runs on to a cap)
+    kn = torch.cos(x_ev[2]) * torch.cos(x_ev[3])
+    resolved = (h_ex <= UNRESOLVED) & (h_ex < kn * kn)
+    cap = cap & resolved
+    y_c, _, fb_c = m.infer(cl, op, x_ev)
+    acc_c = fb_c == 0
+    err, operr = S.exit_error(y_c, y_ex)
+    a = acc_c & cap
+    e = S.summarize_errors(err, a)
+    base = rt.Surrogate(seed=0)
+    base.set_params(np.zeros(rt.Surrogate.NPARAM, np.float32))
+    sc = base.get_scaling()
+    sc[12:22] = np.concatenate([np.zeros(5, np.float32), np.ones(5, np.float32)])
+    base.set_scaling(sc)
+    base.calibrate(cl, x_ev, y_ex, st_ex, tol=1e30, min_count=1, p_min=0.0)
+    _, _, fb_b = base.infer(cl, op, x_ev)
+    base.close()
+    _, _, fb_s = side_model.infer(cl, op, x_ev)
+    side_model.chain(m)
+    try:
+        _, _, fb_k = side_model.infer(cl, op, x_ev)
+        ms_chain = timed(lambda: side_model.infer(cl, op, x_ev))
+    finally:
+        side_model.chain(None)
+    ms_side = timed(lambda: side_model.infer(cl, op, x_ev))
+    ms_plain = timed(lambda: rt.transit_exact(cl, op, x_ev))
+    ncap = int(cap.sum())
+
+    def share(mask):
+        return round(float(mask.float().mean()), 4)
+
+    rec = {
+        "workload": ("1 M held-out uniform side entries (phi, z in [0, 4], alpha, beta, branch and axis bits as the "
+                     "side job's) of the height-4 radial and azimuthal cloaks, DP45 1e-8 FP64 exact transit"),
+        "cap_exits": ncap,
+        "accepted_of_cap_exits": {"with_network": share(acc_c[cap]), "closed_forms_only": share(fb_b[cap] == 0)},
+        "accepted_exit_error": {k: (float(f"{v:.3e}") if isinstance(v, float) else v) for k, v in e.items()},
+        "accepted_over_tolerance": int((err[a] > tol).sum()),
+        "accepted_not_cap_exits": int((acc_c & ~cap & resolved).sum()),
+        "reference": ("cap exits of the exact transit where it resolves the path: |H - 1| <= 1e-6 at the exit and "
+                      "below the entry's squared normal wave number"),
+        "accepted_opl_rel_error_p99": float(f"{S.summarize_errors(operr, a).get('p99', 0.0):.3e}"),
+        "tolerance": tol,
+        "trusted_cells": round(trusted, 4),
+        "calibration": {"entries": n_cal, "tol": 0.5 * tol, "min_count": CAP_MIN_COUNT, "dilate": CAP_DILATE},
+        "side_entries_accepted": {"side_model": share(fb_s == 0), "side_then_cap_model": share(fb_k == 0)},
+        "ms_per_1M_entries": {"plain": round(ms_plain, 3), "side_model": round(ms_side, 3),
+                              "side_then_cap_model": round(ms_chain, 3)},
+        "train": {"entries": n_train, "cap_exit_rows": rows, "steps": steps, "batch": batch,
+                  "seconds": round(t_train, 2), "final_loss": float(f"{loss:.3e}")},
+    }
+    log(f"cap model: accepts {rec['accepted_of_cap_exits']['with_network']} of the cap exits (closed forms "
+        f"{rec['accepted_of_cap_exits']['closed_forms_only']}), exit error p50 {e.get('p50', 0):.2e} max "
+        f"{e.get('max', 0):.2e}, over tol {rec['accepted_over_tolerance']}")
+    del x_ev, y_ex, st_ex, h_ex, y_c, fb_c, err, operr
+    return rec, m
+
+
+# calibration of the cap model's trust map (cells of (axis, branch) x alpha x
+# |beta| x u, 32 x 16 x 32)
+CAP_MIN_COUNT, CAP_DILATE = 8, 1
+
+
 # MFMA flops of one training sample: the forward products of the three
 # 256 x 256 layers, and in backward the data gradient through them and the
 # weight gradient of each (the 6 -> 256 and 256 -> 5 layers run in FP32 on
@@ -782,13 +910,17 @@ def orbit_headline(args, log):
 
 
 def orbit_surrogate(model, orbit, out_plain, ms_plain, log, cal, sweep_frames=4,
-                    difficulties=(0, 2, 3, 4), p_mins=(1e-4, 0.0)):
+                    difficulties=(0, 2, 3, 4), p_mins=(1e-4, 0.0), cap_model=None):
     """The surrogate inside the orbit render (rt_render_surrogate): a sweep of
     the difficulty threshold (side entries of at least that bucket go to the
     network) and of the near-singular band p_min on `sweep_frames` frames,
     then the fastest setting whose images stay within 1/255 of the plain
     render on every pixel runs the whole orbit: time per orbit against the
-    plain orbit, and the per-pixel difference over all of its frames."""
+    plain orbit, and the per-pixel difference over all of its frames. With
+    cap_model, the same setting also runs with the side model chained to the
+    cap model (side entries the first rejects that meet a cap go to the
+    second): accepted entries, time and pixel difference with and without it,
+    on the sweep frames (every side entry offered) and on the whole orbit."""
     import torch
     from paper_1209_6038_amd import rt
     frames, groups, opts, cloaks, room = orbit
@@ -870,11 +1002,51 @@ def orbit_surrogate(model, orbit, out_plain, ms_plain, log, cal, sweep_frames=4,
                 "pixels_over_1_255": over / npix}
         log(f"surrogate orbit: {ms_orbit:.0f} ms vs plain {ms_plain:.0f} ms, max pixel difference "
             f"{full['max_pixel_difference']}")
+    chained = None
+    if best is not None and cap_model is not None:
+        def frames_rec(ks, dmin, chain):
+            model.chain(cap_model if chain else None)
+            try:
+                offered = accepted = 0
+                for k in ks:
+                    _, (c0, c1) = rt.render_surrogate(model, cloaks, opts, room, groups[k], 3, out=out_s[k],
+                                                      counts=True, min_difficulty=dmin)
+                    offered += c0
+                    accepted += c1
+                torch.cuda.synchronize()
+                dmax = max(float((out_s[k] - out_plain[k]).abs().max()) for k in ks)
+                ms = timed(lambda: run_groups(ks, dmin))
+            finally:
+                model.chain(None)
+            nf = sum(len(groups[k]) for k in ks)
+            return {"ms_per_frame": round(ms / nf, 2), "offered_per_frame": offered // nf,
+                    "accepted_per_frame": accepted // nf, "max_pixel_difference": round(dmax, 5)}
+
+        chained = {"note": ("side model alone vs chained to the cap model, same calibration; min_difficulty 0 offers "
+                            "every side entry, the best setting only the hard ones"),
+                   "every_side_entry": {"without_cap_model": frames_rec(sub, 0, False),
+                                        "with_cap_model": frames_rec(sub, 0, True)},
+                   "best_setting": {"without_cap_model": frames_rec(sub, best["min_difficulty"], False),
+                                    "with_cap_model": frames_rec(sub, best["min_difficulty"], True)}}
+        allk = list(range(len(groups)))
+        model.chain(cap_model)
+        try:
+            ms_orbit_c = timed(lambda: run_groups(allk, best["min_difficulty"]))
+            dmax = max(float((out_s[k] - out_plain[k]).abs().max()) for k in allk)
+        finally:
+            model.chain(None)
+        chained["orbit_with_cap_model"] = {"surrogate_ms_per_orbit": round(ms_orbit_c, 2),
+                                           "speedup": round(ms_plain / ms_orbit_c, 3),
+                                           "max_pixel_difference": round(dmax, 5)}
+        e0, e1 = chained["every_side_entry"]["without_cap_model"], chained["every_side_entry"]["with_cap_model"]
+        log(f"surrogate render with the cap model (every side entry offered): accepted {e1['accepted_per_frame']} "
+            f"vs {e0['accepted_per_frame']} per frame, {e1['ms_per_frame']} vs {e0['ms_per_frame']} ms/frame; "
+            f"orbit at the best setting {ms_orbit_c:.0f} ms, max pixel difference {dmax:.5f}")
     del out_s
     return {"workload": (f"the orbit render with rt_render_surrogate; sweep on {nf_sub} frames, then the whole "
                          f"orbit with the fastest setting within 1/255 per pixel of the plain render"),
             "plain_ms_per_frame_sweep_frames": round(ms_plain_sub, 2), "sweep": sweep, "best": best,
-            "orbit": full}
+            "orbit": full, "chained_cap_model": chained}
 
 
 def render1024_record(args, log):
@@ -1068,8 +1240,10 @@ def main():
         log(f"cpu baseline: {rec['cpu_baseline']['value']:.4f} Mrays/s on {rec['cpu_baseline']['cores']} threads")
     if not args.no_surrogate:
         sur, model, cal = surrogate_leg(args.surrogate_steps, args.surrogate_train, log, keep=True)
-        sur["render"] = orbit_surrogate(model, orbit, out_plain, rec["ms_per_step"], log, cal)
+        sur["cap_job"], cap_model = cap_leg(model, log)
+        sur["render"] = orbit_surrogate(model, orbit, out_plain, rec["ms_per_step"], log, cal, cap_model=cap_model)
         rec["surrogate"] = sur
+        cap_model.close()
         model.close()
         del cal
     del out_plain, orbit

@@ -361,9 +361,26 @@ int rt_transit_exact(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_op
    (axis, branch) pairs of Eqs. (14)/(15):
      t0 = dtheta - dtheta_0, t1 = (z' - z) - dz_0, t2 = alpha' - alpha,
      t3 = beta' - beta,      t4 = T - T_0,
-   where dtheta is the signed azimuth the ray sweeps (sign of alpha). A model
-   belongs to the device current at its creation; calls on one model must
-   not overlap (they share its activation buffers). Arrays are device
+   where dtheta is the signed azimuth the ray sweeps (sign of alpha). That
+   is the side job (RT_SUR_SIDE). A model set to the cap job (RT_SUR_CAP,
+   rt_surrogate_set_job) learns instead the side entries of a cloak of
+   finite height whose path meets an end cap, for which no closed form is
+   built here: with h the entry's distance to the cap it heads for (sign of
+   beta) and u = h / |dz_0| (< 1 exactly when the infinite-cylinder path
+   rises past that cap), inputs (k_theta, |k_z|, u, alpha, branch, axis)
+   and targets the state where the ray leaves the cap plane: the cap
+   point's swept azimuth and radius, the radial component of the vacuum
+   direction, the optical path to the cap point and the vertical component
+   (d_theta = r2 k_theta / r_c follows from the conserved angular momentum),
+   as residuals against a chord model of the path (the straight chord with
+   the path's turning radius, traversed to rise fraction u, its radial wave
+   number from the dispersion relation; exact for the azimuthal cloak's
+   extraordinary branch):
+     t0 = dtheta_c - frac dtheta_0, t1 = r_c - r_c^chord,
+     t2 = d_r - d_r^chord, t3 = T_c - u T_0, t4 = |d_z| - |d_z|^chord;
+   the exit on r = r2 is that state plus its straight vacuum leg.
+   A model belongs to the device current at its creation; calls on one model
+   must not overlap (they share its activation buffers). Arrays are device
    pointers unless stated; n <= 2^24, ld >= n.
    --------------------------------------------------------------------------- */
 typedef struct {
@@ -371,12 +388,21 @@ typedef struct {
     float huber;  /* loss per element: 0 = squared error; delta > 0 = Huber (quadratic to delta) */
 } rt_train_opts;
 
+#define RT_SUR_SIDE 0  /* side-to-side transits, residuals against the closed forms */
+#define RT_SUR_CAP 1   /* side entries whose path meets an end cap */
+
 /* Gate of rt_surrogate_infer: a prediction is replaced by the exact transit
-   when its (axis, branch, alpha, beta) cell of the trust map is untrusted,
-   when the predicted exit violates the conservation of the tangential wave
-   numbers (max(|k_theta' - k_theta|, |k_z' - k_z|)) by more than hres_max,
-   when the predicted exit height is within cap_margin of an end cap, or
-   when the entry lies in the near-singular band (p_min). */
+   when the entry lies in the near-singular band (p_min) or its cell of the
+   trust map is untrusted, and
+   side job: when the predicted exit violates the conservation of the
+   tangential wave numbers (max(|k_theta' - k_theta|, |k_z' - k_z|)) by more
+   than hres_max or the predicted exit height is within cap_margin of an
+   end cap;
+   cap job: when the entry heads for no cap (u >= 1), the predicted cap
+   point lies within cap_margin of the cap's rims r1, r2, the vacuum
+   direction has |d_z| < 0.05 (next to total reflection) or a horizontal
+   speed below 0.05, or the two estimates of |d_z| (t4, and the
+   normalization of (d_r, d_theta)) differ by more than 0.01. */
 typedef struct {
     double tol;         /* calibration: largest exit error a trusted cell may show */
     double hres_max;    /* conservation residual limit */
@@ -416,6 +442,28 @@ int rt_surrogate_fit_scaling(rt_model model, int64_t n, int64_t ld, const float 
    side-to-side transit, 0 otherwise (its t5 entries are 0). */
 int rt_surrogate_encode(const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int64_t ld, const float *x6,
                         const float *y5, const int32_t *status, float *t5, float *w, void *stream);
+/* Targets of either job (job RT_SUR_SIDE is rt_surrogate_encode). Cap job:
+   w[i] = 1 for an entry inside the material's height range that leaves
+   through the cap it heads for (u < 1), 0 otherwise; the cloaks must have
+   finite height (RT_E_INVALID). */
+int rt_surrogate_encode_job(int32_t job, const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int64_t ld,
+                            const float *x6, const float *y5, const int32_t *status, float *t5, float *w,
+                            void *stream);
+/* Set a model's job (RT_SUR_SIDE or RT_SUR_CAP); the cap job takes the
+   geometry (r1, r2, z0, z1, finite height) of `cloak` (ignored for the side
+   job, may be NULL), and calibration and inference then need cloaks of that
+   geometry (RT_E_INVALID otherwise). Clears the trust map. New models have
+   the side job. */
+int rt_surrogate_set_job(rt_model model, int32_t job, rt_cloak cloak);
+int rt_surrogate_get_job(rt_model model, int32_t *job);
+/* Chain two models: rt_surrogate_infer and rt_render_surrogate with `first`
+   offer the rows that first's gate rejects to `next` (its own gate and
+   trust map), and the exact integrator traces what both reject. A chain
+   holds two models; next = NULL unchains. Neither owns the other:
+   rt_surrogate_free of either unchains them. Both must be calibrated before
+   inference. The chain's exit tolerance (the tile-edge gate) is the larger
+   of the two calibrations' tol. */
+int rt_surrogate_chain(rt_model first, rt_model next);
 /* Loss L = (1/n) sum_i w_i sum_o rho(y_io - (t_io - out_mean_o)/out_std_o)
    of one batch (w NULL = all ones) and its gradient, rho(d) = d^2, or for
    huber = delta > 0 the Huber function (d^2 up to |d| = delta, then
@@ -448,24 +496,30 @@ int rt_surrogate_forward(rt_model model, int64_t n, int64_t ld, const float *x6,
 /* Build the trust map: predicts the calibration rays x6, measures each
    one's exit error max(|x - x_exact| / r2, angle(d, d_exact)) against the
    exact exits, and trusts a cell when it holds >= min_count rays, all of
-   them side-to-side transits with error <= tol, and no cell within
-   `dilate` cells of it (in alpha and beta) fails that test (discontinuities
-   of the transit run along thin curves that a cell's calibration rays can
-   miss). hres_exact (n floats from rt_transit_exact, or NULL): exits with
+   them finished transits with error <= tol, and no cell within `dilate`
+   cells of it (in alpha and beta, and u for the cap job) fails that test
+   (discontinuities of the transit run along thin curves that a cell's
+   calibration rays can miss). The cap job counts only the rays its gate
+   would predict (heading for a cap, a usable cap exit; see rt_gate_opts).
+   hres_exact (n floats from rt_transit_exact, or NULL): exits with
    hres_exact > gate->unresolved (> 0) are left out, neither counted nor
    failing, since the integrator did not resolve them; with hres_exact and
    cloaks of infinite height, so are totally reflected exits (a side entry
    of the infinite cylinder conserves its tangential wave numbers and always
    transmits at its exit; the status only arises from the integrator's
-   drift at grazing entries). Stores `gate` in the model. trusted_fraction (host, may be NULL): share of trusted cells.
+   drift at grazing entries). Stores `gate` in the model.
+   trusted_fraction (host, may be NULL): share of trusted cells.
    Synchronous. */
 int rt_surrogate_calibrate(rt_model model, const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int64_t ld,
                            const float *x6, const float *y5_exact, const int32_t *status_exact,
                            const float *hres_exact, const rt_gate_opts *gate, double *trusted_fraction,
                            void *stream);
-/* Trust map (host, 4 x cells_alpha x cells_beta bytes, (axis*2+branch)
-   major, uniform cells over (-pi/2, pi/2)^2); host may be NULL. */
-int rt_surrogate_get_map(rt_model model, uint8_t *host, int32_t *cells_alpha, int32_t *cells_beta);
+/* Trust map (host, 4 x cells_alpha x cells_beta x cells_u bytes,
+   (axis*2+branch) major): side job uniform cells over (alpha, beta) in
+   (-pi/2, pi/2)^2 (cells_u = 1), cap job over alpha in (-pi/2, pi/2),
+   |beta| in [0, pi/2) and u in [0, 1). host and the counts may be NULL. */
+int rt_surrogate_get_map(rt_model model, uint8_t *host, int32_t *cells_alpha, int32_t *cells_beta,
+                         int32_t *cells_u);
 /* Surrogate transit with exact fallback: y5/status as rt_transit_exact.
    fallback[i] (n bytes) = 1 where the gate rejected the prediction and the
    exact integrator traced the ray, 0 where y5 is the network's. Needs a
@@ -510,7 +564,7 @@ int rt_render_surrogate(rt_model model, const rt_cloak *cloaks, int32_t n_cloaks
                         int32_t min_difficulty, float *rgb, const rt_render_aux *aux, int64_t *counts,
                         void *stream);
 
-/* Model file: parameters, scaling, gate and trust map. */
+/* Model file: parameters, scaling, gate, trust map, job and geometry. */
 int rt_surrogate_save(rt_model model, const char *path);
 int rt_surrogate_load(const char *path, rt_model *out);
 

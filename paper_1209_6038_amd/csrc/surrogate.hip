@@ -61,9 +61,13 @@ static_assert(OFF_B1 == OFF_W1 + NIN * HID, "W1, b1 are contiguous");
 constexpr long long NBF = 3LL * HID * HID;
 // scaling block: in_off[6], in_scale[6], out_mean[5], out_std[5], then the loss
 constexpr int S_INOFF = 0, S_INSCALE = 6, S_OMEAN = 12, S_OSTD = 17, S_LOSS = 22, NSCAL = 24;
-// trust map: (axis, branch) x alpha cells x beta cells
+// trust map of the side job: (axis, branch) x alpha cells x beta cells
 constexpr int NCELL_A = 128, NCELL_B = 128, NCOMBO = 4;
 constexpr int NCELLS = NCOMBO * NCELL_A * NCELL_B;
+// trust map of the cap job: (axis, branch) x alpha x |beta| x cap-fraction
+// cells, as many as the side job's
+constexpr int CAP_A = 32, CAP_B = 16, CAP_U = 32;
+static_assert(NCOMBO * CAP_A * CAP_B * CAP_U == NCELLS, "both jobs' trust maps have NCELLS cells");
 constexpr float OUT_STD_FLOOR = 1e-3f;
 constexpr float PI_F = 3.14159265358979f;
 
@@ -400,13 +404,215 @@ __global__ void __launch_bounds__(256) k_sum_rows(const float *__restrict__ part
   if (q == 0 && col < ncols) atomicAdd(&dst[col], (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]));
 }
 
+// ---------------------------------------------------------------------------
+// Target encoding. Entry (phi, z, alpha, beta) on r = b, exit (phi', z',
+// alpha', beta') on r = b, optical path T between them:
+//   t0 = dtheta - dtheta_0,  t1 = dz - dz_0,  t2 = alpha' - alpha,
+//   t3 = beta' - beta,       t4 = T - T_0,
+// with dz = z' - z and dtheta the signed azimuth swept by the ray. The
+// conserved angular momentum p_theta keeps its sign along the path (the
+// inner mirror reflects radially), so theta is monotonic with the sign s of
+// alpha, and dtheta = s * ((s (phi' - phi)) mod 2 pi) unwraps exactly for
+// transits of less than a full turn. All five residuals are bounded: the
+// refraction into the cloak keeps the rise and the path inside finite even
+// for entries at grazing elevation, so they enter unscaled (a residual
+// divided by cos(beta) would multiply the network's error by 1 / cos(beta)).
+//
+// (dtheta_0, dz_0, T_0) is the closed-form transit where one exists (zero
+// otherwise), so that the network learns a residual:
+//  - radial cloak, ordinary branch: M = kappa I (Eq. (14): eps_o = kappa),
+//    a homogeneous medium of index n = sqrt(kappa) = b / (b - a); the ray is
+//    straight inside, with horizontal wave number k_h = sqrt(n^2 - k_z^2)
+//    and horizontal impact parameter p = b |k_theta| / k_h, and reflects
+//    specularly off the metal cylinder when p <= a (Sect. 4);
+//  - azimuthal cloak, extraordinary branch: M = diag(kappa, kappa s, kappa)
+//    (Eq. (15)) makes the line element drho^2 + rho^2 dtheta^2 + dzeta^2 with
+//    rho = sqrt(kappa) (r - a), zeta = sqrt(kappa) z: a straight line in
+//    (rho, theta, zeta) at unit speed, entering at rho = b with tangential
+//    speed k_theta and axial speed k_z / sqrt(kappa).
+//  - radial cloak, extraordinary branch, and azimuthal cloak, ordinary
+//    branch: both have m_theta = m_z = kappa s, so with p = b k_theta the
+//    Hamiltonian constraint gives m_r rdot^2 = Q(r) / (kappa (r - a)^2) for
+//    the quadratic Q(r) = kappa (r - a)^2 - p^2 - k_z^2 r^2, which equals
+//    (b k_n)^2 at r = b; the turning point is its larger root. The sweep,
+//    the rise and the optical path per unit r are
+//      radial e (m_r = kappa):      p / (u sqrt Q), k_z r^2 / (u sqrt Q),
+//                                   kappa u / sqrt Q            (u = r - a),
+//      azimuthal o (m_r = kappa s): p / (r sqrt Q), k_z r / sqrt Q,
+//                                   kappa u^2 / (r sqrt Q),
+//    sums of 1 / sqrt Q, x / sqrt Q and 1 / (x sqrt Q) for Q quadratic in x,
+//    integrated in closed form from the root to r = b (asinh, atan2 and
+//    asinh(sqrt y) / sqrt y, the last continued through y = 0 as
+//    asin(sqrt -y) / sqrt -y).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float wrap2pi(float a) {
+  a = fmodf(a, 2.0f * PI_F);
+  return a < 0.0f ? a + 2.0f * PI_F : a;
+}
+
+// half the azimuth swept along a chord of a circle of radius 1 with impact
+// parameter u in [0, 1]: acos(u), in a form accurate near u = 1
+__device__ __forceinline__ float half_sweep(float u) { return atan2f(sqrtf(fmaxf(0.f, (1.f - u) * (1.f + u))), u); }
+
+__device__ __forceinline__ void baseline(int kind, float al, float be, float a, float b, float &dth, float &dz,
+                                         float &T) {
+  dth = 0.f; dz = 0.f; T = 0.f;
+  const float s = al < 0.0f ? -1.0f : 1.0f;
+  const float kt = fabsf(cosf(be) * sinf(al)), kz = sinf(be);
+  const float n = b / (b - a), kap = n * n;
+  if (kind == 0) {
+    const float kh = sqrtf(kap - kz * kz);
+    const float u = kt / kh;  // p / b
+    float sweep = half_sweep(u), lh = b * sqrtf(fmaxf(0.f, (1.f - u) * (1.f + u)));
+    const float ua = u * (b / a);  // p / a
+    if (ua <= 1.0f) {
+      sweep -= half_sweep(ua);
+      lh -= a * sqrtf(fmaxf(0.f, (1.f - ua) * (1.f + ua)));
+    }
+    dth = 2.0f * s * sweep;
+    dz = 2.0f * lh * kz / kh;
+    T = 2.0f * lh * kap / kh;
+  } else if (kind == 3) {
+    const float h = sqrtf(1.0f - kz * kz / kap);
+    const float u = kt / h;
+    dth = 2.0f * s * half_sweep(u);
+    T = 2.0f * b * sqrtf(fmaxf(0.f, (1.f - u) * (1.f + u))) / h;
+    dz = T * kz / kap;
+  } else {
+    const float p = b * kt, A = kap - kz * kz, kza2 = kz * kz * a * a;
+    const float S = sqrtf(fmaf(A, p * p, kap * kza2));  // half the root of the discriminant of Q
+    const float sq = b * cosf(al) * cosf(be);           // sqrt Q(b)
+    const float sA = sqrtf(A);
+    const float J0 = asinhf(sA * sq / S) / sA;          // int dx / sqrt Q from the root
+    if (kind == 1) {                                    // x = u: Q = A u^2 - 2 a k_z^2 u - (p^2 + k_z^2 a^2)
+      const float mC = fmaf(p, p, kza2), rm = sqrtf(mC);
+      const float J1 = fmaf(a * kz * kz, J0, sq) / A;   // int u du / sqrt Q
+      const float Jm = atan2f(rm * sq, fmaf(a * kz * kz, b - a, mC)) / rm;  // int du / (u sqrt Q)
+      dth = 2.0f * s * p * Jm;
+      dz = 2.0f * kz * (J1 + 2.0f * a * J0 + a * a * Jm);
+      T = 2.0f * kap * J1;
+    } else {                                            // x = r: Q = A r^2 - 2 kappa a r + kappa a^2 - p^2
+      const float C = fmaf(kap * a, a, -p * p);
+      const float y = C * sq * sq / (b * b * S * S);
+      float g;                                          // asinh(sqrt y) / sqrt y
+      if (fabsf(y) < 1e-3f) g = fmaf(y, fmaf(y, 0.075f, -1.0f / 6.0f), 1.0f);
+      else if (y > 0.0f) g = asinhf(sqrtf(y)) / sqrtf(y);
+      else g = asinf(sqrtf(-y)) / sqrtf(-y);
+      const float Jm = sq / (b * S) * g;                // int dr / (r sqrt Q)
+      const float J1 = fmaf(kap * a, J0, sq) / A;       // int r dr / sqrt Q
+      dth = 2.0f * s * p * Jm;
+      dz = 2.0f * kz * J1;
+      T = 2.0f * kap * (J1 - 2.0f * a * J0 + a * a * Jm);
+    }
+  }
+}
+
+__device__ __forceinline__ int kind_of(float pol, float axis) {
+  return (axis == 0.0f ? 0 : 2) + (pol == 0.0f ? 0 : 1);
+}
+
+__device__ __forceinline__ bool entry_ok(float phi, float z, float al, float be, float pol, float axis) {
+  return isfinite(phi) && isfinite(z) && fabsf(al) < 0.5f * PI_F && fabsf(be) < 0.5f * PI_F &&
+         (pol == 0.0f || pol == 1.0f) && (axis == 0.0f || axis == 1.0f);
+}
+
+// A model's job and the geometry it needs besides an entry: RT_SUR_SIDE
+// (side-to-side transits of the infinite cylinder, no geometry) or
+// RT_SUR_CAP (side entries whose path meets an end cap of the cloak with
+// radii a < b and material height [z0, z1]).
+struct JobP {
+  int job;
+  float a, b, z0, z1;
+};
+
+// Fraction u of the closed-form infinite-cylinder transit's rise that the
+// entry's headroom allows: h / |dz_0| with h the distance from the entry
+// height to the cap the ray climbs (or sinks) towards. z is monotonic along
+// a transit (p_z keeps its sign), so the path meets that cap exactly when
+// u < 1. Clamped to [0, 2] (u >= 1 never meets a cap).
+__device__ __forceinline__ float cap_fraction(float z, float al, float be, int kind, const JobP &jp) {
+  float dth0, dz0, T0;
+  baseline(kind, al, be, jp.a, jp.b, dth0, dz0, T0);
+  const float h = be >= 0.0f ? jp.z1 - z : z - jp.z0;
+  const float u = h / fabsf(dz0);
+  return u < 2.0f ? fmaxf(u, 0.0f) : 2.0f;  // NaN (dz_0 = 0 = h) -> 2
+}
+
+// Chord model of the path up to the cap, at rise fraction u, for the cap
+// job's baselines. The infinite-cylinder path is symmetric about its
+// turning point, which it reaches at u = 1/2, so it is modelled by the
+// straight chord through the entry with the path's impact parameter w, the
+// radius traversed at fraction u being sqrt(w^2 + (b^2 - w^2)(1 - 2u)^2):
+//  - radial extraordinary and azimuthal ordinary branches: w the turning
+//    radius, the larger root (kappa a + S) / (kappa - k_z^2) of the
+//    quadratic Q of the closed-form transit (S as there);
+//  - azimuthal extraordinary branch: the path is a straight line in
+//    (rho = sqrt(kappa) (r - a), theta, zeta = sqrt(kappa) z) at unit speed
+//    (Eq. (15)), so the chord in rho, with w = b k_theta / sqrt(1 - k_z^2 /
+//    kappa) and rho_b = b, is exact, as are the sweep fraction and the
+//    optical-path fraction u;
+//  - radial ordinary branch: the straight chord (its paths never leave
+//    through a cap: with n = 2 it is totally reflected at every cap).
+// The swept azimuth is the chord's share frac of the whole sweep, the radial
+// wave number at the modelled radius r_c comes from the dispersion relation
+// k_r^2 / m_r + k_theta^2 / m_theta + k_z^2 / m_z = 1 (k_theta = p_theta /
+// r_c, k_z conserved; the metric of Eqs. (14)/(15): m = kappa (1, 1, 1),
+// kappa (1, s, s), kappa s (1, 1, 1), kappa (1, s, 1) for the radial o, e
+// and azimuthal o, e branches, s = ((r - a) / r)^2) with the sign of the leg
+// (inwards before the turning point), and it is the vacuum direction's d_r
+// after the cap (tangential continuity, Sect. 3), with |d_z| from
+// normalization.
+__device__ __forceinline__ void cap_chord(int kind, float al, float be, float u, float a, float b, float &frac,
+                                          float &rc, float &dr, float &adz) {
+  const float kap = (b / (b - a)) * (b / (b - a)), skap = b / (b - a);
+  const float kt = fabsf(cosf(be) * sinf(al)), kz = sinf(be), p = b * kt;
+  const float A = kap - kz * kz;
+  float w;
+  if (kind == 3) {
+    w = b * kt / sqrtf(1.0f - kz * kz / kap);
+  } else if (kind == 0) {
+    w = p / sqrtf(A);
+  } else {
+    w = (kap * a + sqrtf(fmaf(A, p * p, kap * kz * kz * a * a))) / A;
+  }
+  w = fminf(w, b);
+  const float v = 1.0f - 2.0f * u;
+  const float wb = sqrtf(fmaxf(0.0f, (b - w) * (b + w)));
+  const float rr = sqrtf(fmaf(wb * wb, v * v, w * w));
+  rc = kind == 3 ? a + rr / skap : rr;
+  const float half = atan2f(wb, w);
+  frac = half > 1e-6f ? 0.5f * (1.0f - atan2f(wb * v, w) / half) : u;
+  // k_r^2 vanishes at the turning point, where its terms cancel; written
+  // with the factor rr - w = wb^2 v^2 / (rr + w) taken out it is v^2 times a
+  // smooth positive function, so d_r = -v (...) runs linearly through it:
+  //  - radial ordinary, azimuthal extraordinary (straight in r or rho):
+  //    k_r^2 = (kappa - k_z^2)(rr^2 - w^2) / rr^2;
+  //  - radial extraordinary, azimuthal ordinary: k_r^2 = m_r Q(r) /
+  //    (kappa (r - a)^2) with Q = (kappa - k_z^2)(r - w)(r - r_s), r_s the
+  //    smaller root (kappa a^2 - p^2) / ((kappa - k_z^2) w).
+  if (kind == 0 || kind == 3) {
+    dr = -v * wb * sqrtf(A) / rr;
+  } else {
+    const float rs = (kap * a * a - p * p) / (A * w);
+    const float g = sqrtf(fmaxf(0.0f, A * (rc - rs) / (rc + w)));
+    dr = -v * wb * g / (kind == 1 ? rc - a : rc);
+  }
+  const float kth = p / rc;
+  adz = sqrtf(fmaxf(0.0f, 1.0f - dr * dr - kth * kth));
+}
+
 // Network input features of entry i. The transit of the infinite cylinder
 // is invariant under rotation about and translation along its axis, so the
 // exit offsets do not depend on phi or z; those two slots carry instead the
 // entry's tangential wave numbers k_theta = cos(beta) sin(alpha) and
 // k_z = sin(beta), the invariants p_theta / r2 and p_z of the transit:
-//   f = (k_theta, k_z, alpha, beta, branch bit, axis bit).
-__device__ __forceinline__ void features(const float *__restrict__ x6, long long ld, long long i, float f[NIN]) {
+//   side job: f = (k_theta, k_z, alpha, beta, branch bit, axis bit).
+// A path that meets a cap depends on the height as well; the cloak is also
+// symmetric under the mirror z -> z0 + z1 - z, which flips beta, so the cap
+// job takes |k_z| and the cap fraction u (cap_fraction) instead:
+//   cap job:  f = (k_theta, |k_z|, u, alpha, branch bit, axis bit).
+__device__ __forceinline__ void features(const float *__restrict__ x6, long long ld, long long i, const JobP &jp,
+                                         float f[NIN]) {
   const float al = x6[2 * ld + i], be = x6[3 * ld + i];
   f[0] = cosf(be) * sinf(al);
   f[1] = sinf(be);
@@ -414,6 +620,11 @@ __device__ __forceinline__ void features(const float *__restrict__ x6, long long
   f[3] = be;
   f[4] = x6[4 * ld + i];
   f[5] = x6[5 * ld + i];
+  if (jp.job == RT_SUR_CAP) {
+    f[1] = fabsf(f[1]);
+    f[2] = cap_fraction(x6[ld + i], al, be, kind_of(f[4], f[5]), jp);
+    f[3] = al;
+  }
 }
 
 // standardized outputs (n x 5) -> SoA targets (5 x ld)
@@ -613,7 +824,8 @@ __global__ void k_refresh_bf16(const float *__restrict__ P, bf16 *__restrict__ P
 // masked first and second moments of the 6 input features and 5 targets (FP64 sums)
 constexpr int NMOM = 2 * (NIN + NOUT) + 1;
 __global__ void __launch_bounds__(256) k_moments(const float *__restrict__ x, const float *__restrict__ t, long long ld,
-                                                 const float *__restrict__ wrow, int n, double *__restrict__ acc) {
+                                                 const float *__restrict__ wrow, int n, JobP jp,
+                                                 double *__restrict__ acc) {
   double s[NMOM];
 #pragma unroll
   for (int k = 0; k < NMOM; ++k) s[k] = 0.0;
@@ -622,7 +834,7 @@ __global__ void __launch_bounds__(256) k_moments(const float *__restrict__ x, co
     if (wr == 0.0) continue;
     s[NMOM - 1] += wr;
     float f[NIN];
-    features(x, ld, i, f);
+    features(x, ld, i, jp, f);
 #pragma unroll
     for (int k = 0; k < NIN; ++k) {
       const double v = f[k];
@@ -650,116 +862,16 @@ __global__ void k_fill_f64(double *p, int n) {
   if (i < n) p[i] = 0.0;
 }
 
-// ---------------------------------------------------------------------------
-// Target encoding. Entry (phi, z, alpha, beta) on r = b, exit (phi', z',
-// alpha', beta') on r = b, optical path T between them:
-//   t0 = dtheta - dtheta_0,  t1 = dz - dz_0,  t2 = alpha' - alpha,
-//   t3 = beta' - beta,       t4 = T - T_0,
-// with dz = z' - z and dtheta the signed azimuth swept by the ray. The
-// conserved angular momentum p_theta keeps its sign along the path (the
-// inner mirror reflects radially), so theta is monotonic with the sign s of
-// alpha, and dtheta = s * ((s (phi' - phi)) mod 2 pi) unwraps exactly for
-// transits of less than a full turn. All five residuals are bounded: the
-// refraction into the cloak keeps the rise and the path inside finite even
-// for entries at grazing elevation, so they enter unscaled (a residual
-// divided by cos(beta) would multiply the network's error by 1 / cos(beta)).
-//
-// (dtheta_0, dz_0, T_0) is the closed-form transit where one exists (zero
-// otherwise), so that the network learns a residual:
-//  - radial cloak, ordinary branch: M = kappa I (Eq. (14): eps_o = kappa),
-//    a homogeneous medium of index n = sqrt(kappa) = b / (b - a); the ray is
-//    straight inside, with horizontal wave number k_h = sqrt(n^2 - k_z^2)
-//    and horizontal impact parameter p = b |k_theta| / k_h, and reflects
-//    specularly off the metal cylinder when p <= a (Sect. 4);
-//  - azimuthal cloak, extraordinary branch: M = diag(kappa, kappa s, kappa)
-//    (Eq. (15)) makes the line element drho^2 + rho^2 dtheta^2 + dzeta^2 with
-//    rho = sqrt(kappa) (r - a), zeta = sqrt(kappa) z: a straight line in
-//    (rho, theta, zeta) at unit speed, entering at rho = b with tangential
-//    speed k_theta and axial speed k_z / sqrt(kappa).
-//  - radial cloak, extraordinary branch, and azimuthal cloak, ordinary
-//    branch: both have m_theta = m_z = kappa s, so with p = b k_theta the
-//    Hamiltonian constraint gives m_r rdot^2 = Q(r) / (kappa (r - a)^2) for
-//    the quadratic Q(r) = kappa (r - a)^2 - p^2 - k_z^2 r^2, which equals
-//    (b k_n)^2 at r = b; the turning point is its larger root. The sweep,
-//    the rise and the optical path per unit r are
-//      radial e (m_r = kappa):      p / (u sqrt Q), k_z r^2 / (u sqrt Q),
-//                                   kappa u / sqrt Q            (u = r - a),
-//      azimuthal o (m_r = kappa s): p / (r sqrt Q), k_z r / sqrt Q,
-//                                   kappa u^2 / (r sqrt Q),
-//    sums of 1 / sqrt Q, x / sqrt Q and 1 / (x sqrt Q) for Q quadratic in x,
-//    integrated in closed form from the root to r = b (asinh, atan2 and
-//    asinh(sqrt y) / sqrt y, the last continued through y = 0 as
-//    asin(sqrt -y) / sqrt -y).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float wrap2pi(float a) {
-  a = fmodf(a, 2.0f * PI_F);
-  return a < 0.0f ? a + 2.0f * PI_F : a;
-}
-
-// half the azimuth swept along a chord of a circle of radius 1 with impact
-// parameter u in [0, 1]: acos(u), in a form accurate near u = 1
-__device__ __forceinline__ float half_sweep(float u) { return atan2f(sqrtf(fmaxf(0.f, (1.f - u) * (1.f + u))), u); }
-
-__device__ __forceinline__ void baseline(int kind, float al, float be, float a, float b, float &dth, float &dz,
-                                         float &T) {
-  dth = 0.f; dz = 0.f; T = 0.f;
-  const float s = al < 0.0f ? -1.0f : 1.0f;
-  const float kt = fabsf(cosf(be) * sinf(al)), kz = sinf(be);
-  const float n = b / (b - a), kap = n * n;
-  if (kind == 0) {
-    const float kh = sqrtf(kap - kz * kz);
-    const float u = kt / kh;  // p / b
-    float sweep = half_sweep(u), lh = b * sqrtf(fmaxf(0.f, (1.f - u) * (1.f + u)));
-    const float ua = u * (b / a);  // p / a
-    if (ua <= 1.0f) {
-      sweep -= half_sweep(ua);
-      lh -= a * sqrtf(fmaxf(0.f, (1.f - ua) * (1.f + ua)));
-    }
-    dth = 2.0f * s * sweep;
-    dz = 2.0f * lh * kz / kh;
-    T = 2.0f * lh * kap / kh;
-  } else if (kind == 3) {
-    const float h = sqrtf(1.0f - kz * kz / kap);
-    const float u = kt / h;
-    dth = 2.0f * s * half_sweep(u);
-    T = 2.0f * b * sqrtf(fmaxf(0.f, (1.f - u) * (1.f + u))) / h;
-    dz = T * kz / kap;
-  } else {
-    const float p = b * kt, A = kap - kz * kz, kza2 = kz * kz * a * a;
-    const float S = sqrtf(fmaf(A, p * p, kap * kza2));  // half the root of the discriminant of Q
-    const float sq = b * cosf(al) * cosf(be);           // sqrt Q(b)
-    const float sA = sqrtf(A);
-    const float J0 = asinhf(sA * sq / S) / sA;          // int dx / sqrt Q from the root
-    if (kind == 1) {                                    // x = u: Q = A u^2 - 2 a k_z^2 u - (p^2 + k_z^2 a^2)
-      const float mC = fmaf(p, p, kza2), rm = sqrtf(mC);
-      const float J1 = fmaf(a * kz * kz, J0, sq) / A;   // int u du / sqrt Q
-      const float Jm = atan2f(rm * sq, fmaf(a * kz * kz, b - a, mC)) / rm;  // int du / (u sqrt Q)
-      dth = 2.0f * s * p * Jm;
-      dz = 2.0f * kz * (J1 + 2.0f * a * J0 + a * a * Jm);
-      T = 2.0f * kap * J1;
-    } else {                                            // x = r: Q = A r^2 - 2 kappa a r + kappa a^2 - p^2
-      const float C = fmaf(kap * a, a, -p * p);
-      const float y = C * sq * sq / (b * b * S * S);
-      float g;                                          // asinh(sqrt y) / sqrt y
-      if (fabsf(y) < 1e-3f) g = fmaf(y, fmaf(y, 0.075f, -1.0f / 6.0f), 1.0f);
-      else if (y > 0.0f) g = asinhf(sqrtf(y)) / sqrtf(y);
-      else g = asinf(sqrtf(-y)) / sqrtf(-y);
-      const float Jm = sq / (b * S) * g;                // int dr / (r sqrt Q)
-      const float J1 = fmaf(kap * a, J0, sq) / A;       // int r dr / sqrt Q
-      dth = 2.0f * s * p * Jm;
-      dz = 2.0f * kz * J1;
-      T = 2.0f * kap * (J1 - 2.0f * a * J0 + a * a * Jm);
-    }
-  }
-}
-
-__device__ __forceinline__ int kind_of(float pol, float axis) {
-  return (axis == 0.0f ? 0 : 2) + (pol == 0.0f ? 0 : 1);
-}
-
-__device__ __forceinline__ bool entry_ok(float phi, float z, float al, float be, float pol, float axis) {
-  return isfinite(phi) && isfinite(z) && fabsf(al) < 0.5f * PI_F && fabsf(be) < 0.5f * PI_F &&
-         (pol == 0.0f || pol == 1.0f) && (axis == 0.0f || axis == 1.0f);
+// exit point and unit direction from exit parameters
+__device__ __forceinline__ void exit_ray(const float *p, float b, float x[3], float d[3]) {
+  float sp, cp, sa, ca, sb, cbt;
+  sincosf(p[0], &sp, &cp);
+  sincosf(p[2], &sa, &ca);
+  sincosf(p[3], &sb, &cbt);
+  x[0] = b * cp; x[1] = b * sp; x[2] = p[1];
+  d[0] = cbt * (ca * cp - sa * sp);
+  d[1] = cbt * (ca * sp + sa * cp);
+  d[2] = sb;
 }
 
 __global__ void __launch_bounds__(256) k_encode(const float *__restrict__ x6, const float *__restrict__ y5,
@@ -789,6 +901,67 @@ __global__ void __launch_bounds__(256) k_encode(const float *__restrict__ x6, co
   wrow[i] = ok ? 1.0f : 0.0f;
 }
 
+// Cap-job targets. A side entry whose path leaves through an end cap exits
+// as the vacuum ray from its cap point, given where that ray crosses r = b;
+// the straight vacuum leg back to the cap plane recovers the cap point
+// (r_c, theta_c) and the optical path T_c up to it. The cap's refraction
+// keeps the tangential wave vector (k_r, k_theta), so the vacuum direction
+// there has d_theta = b k_theta / r_c (the conserved angular momentum) and
+// |d_z| from normalization: the exit is fixed by (theta_c, r_c, d_r, T_c).
+// With u the cap fraction (cap_fraction) and (dtheta_0, T_0) the closed-form
+// transit of the infinite cylinder, whose share u the path covers before the
+// cap in rise, the state (dtheta_c, r_c, d_r, T_c) and |d_z| (a second
+// estimate, checked against the normalization by the gate) enter as
+// residuals,
+// dtheta_c the signed azimuth swept from the entry to the cap point (sign of
+// alpha), each against the chord model of the path (cap_chord):
+//   t0 = dtheta_c - frac dtheta_0,  t1 = r_c - r_c^chord,
+//   t2 = d_r - d_r^chord,           t3 = T_c - u T_0,
+//   t4 = |d_z| - |d_z|^chord.
+// Rows that do not leave through the cap they head for get w = 0.
+__global__ void __launch_bounds__(256) k_encode_cap(const float *__restrict__ x6, const float *__restrict__ y5,
+                                                    const int *__restrict__ status, long long ld, long long n,
+                                                    JobP jp, float *__restrict__ t5, float *__restrict__ wrow) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float phi = x6[i], z = x6[ld + i], al = x6[2 * ld + i], be = x6[3 * ld + i];
+  const float pol = x6[4 * ld + i], axis = x6[5 * ld + i];
+  float t[NOUT] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  const float ze = y5[ld + i];
+  const bool up = be >= 0.0f;
+  bool ok = status[i] == RT_RAY_EXITED && entry_ok(phi, z, al, be, pol, axis) && z >= jp.z0 && z <= jp.z1 &&
+            (up ? ze > jp.z1 : ze < jp.z0);
+  if (ok) {
+    float ex[NOUT], xe[3], de[3];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) ex[o] = y5[o * ld + i];
+    exit_ray(ex, jp.b, xe, de);
+    const float tb = (xe[2] - (up ? jp.z1 : jp.z0)) / de[2];  // vacuum leg back to the cap plane
+    const float cx = fmaf(-tb, de[0], xe[0]), cy = fmaf(-tb, de[1], xe[1]);
+    const float rc = sqrtf(fmaf(cx, cx, cy * cy));
+    const float s = al < 0.0f ? -1.0f : 1.0f;
+    float dth = s * wrap2pi(s * (atan2f(cy, cx) - phi));
+    if (s * dth > 2.0f * PI_F - 1e-3f) dth -= s * 2.0f * PI_F;  // a sweep rounded to just below zero
+    const int kind = kind_of(pol, axis);
+    float dth0, dz0, T0;
+    baseline(kind, al, be, jp.a, jp.b, dth0, dz0, T0);
+    const float u = cap_fraction(z, al, be, kind, jp);
+    float frac, rcb, drb, adzb;
+    cap_chord(kind, al, be, u, jp.a, jp.b, frac, rcb, drb, adzb);
+    t[0] = fmaf(-frac, dth0, dth);
+    t[1] = rc - rcb;
+    t[2] = fmaf(cx, de[0], cy * de[1]) / rc - drb;
+    t[3] = fmaf(-u, T0, ex[4] - tb);
+    t[4] = fabsf(de[2]) - adzb;
+    ok = tb >= 0.0f && u < 1.0f;
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) ok = ok && isfinite(t[o]);
+  }
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) t5[o * ld + i] = ok ? t[o] : 0.0f;
+  wrow[i] = ok ? 1.0f : 0.0f;
+}
+
 // standardized network outputs -> exit parameters (phi', z', alpha', beta', T)
 __device__ __forceinline__ void decode(const float *yrow, const float *sc, float phi, float z, float al, float be,
                                        int kind, float a, float b, float out[NOUT]) {
@@ -804,7 +977,55 @@ __device__ __forceinline__ void decode(const float *yrow, const float *sc, float
   out[4] = T0 + t[4];
 }
 
-// cell of the trust map
+// Cap-job prediction -> exit parameters: the cap point and the vacuum
+// direction from the targets of k_encode_cap, then the straight vacuum leg
+// to r = b. Returns false where the prediction is no usable cap exit: a cap
+// point within `margin` of the rims r = a, r = b of the cap, a vacuum
+// direction within |d_z| < 0.05 of grazing the cap (the refraction is
+// ill-conditioned next to total reflection) or with a horizontal speed
+// below 0.05 (a vacuum leg longer than ~2 b / 0.05), or the two estimates
+// of |d_z| (normalization, output t4) apart by more than CAP_DZ_CHECK: a
+// network that contradicts itself that much is outside what it learned.
+constexpr float CAP_DZ_CHECK = 1e-2f;
+__device__ __forceinline__ bool decode_cap(const float *yrow, const float *sc, float phi, float z, float al,
+                                           float be, int kind, const JobP &jp, float margin, float out[NOUT]) {
+  float t[NOUT];
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) t[o] = fmaf(yrow[o], sc[S_OSTD + o], sc[S_OMEAN + o]);
+  float dth0, dz0, T0;
+  baseline(kind, al, be, jp.a, jp.b, dth0, dz0, T0);
+  const float u = cap_fraction(z, al, be, kind, jp);
+  float frac, rcb, drb, adzb;
+  cap_chord(kind, al, be, u, jp.a, jp.b, frac, rcb, drb, adzb);
+  const bool up = be >= 0.0f;
+  const float thc = phi + fmaf(frac, dth0, t[0]);
+  const float rc = rcb + t[1], dr = drb + t[2];
+  const float dt = jp.b * cosf(be) * sinf(al) / rc;
+  const float q = fmaf(dr, dr, dt * dt);  // horizontal speed squared
+  const float adz = sqrtf(fmaxf(0.0f, 1.0f - q));
+  float st, ct;
+  sincosf(thc, &st, &ct);
+  const float cx = rc * ct, cy = rc * st;
+  const float dx = dr * ct - dt * st, dy = dr * st + dt * ct;
+  // vacuum leg: |(c + s d)_xy| = b with s > 0 from a cap point inside
+  // (r_c < b), in the form without cancellation for either sign of d_r
+  const float qb = rc * dr, qc = (rc - jp.b) * (rc + jp.b);
+  const float disc = sqrtf(fmaxf(0.0f, fmaf(qb, qb, -q * qc)));
+  const float s = qb >= 0.0f ? -qc / (qb + disc) : (disc - qb) / q;
+  const float px = fmaf(s, dx, cx), py = fmaf(s, dy, cy);
+  const float ph = wrap2pi(atan2f(py, px));
+  float sph, cph;
+  sincosf(ph, &sph, &cph);
+  out[0] = ph;
+  out[1] = fmaf(s, up ? adz : -adz, up ? jp.z1 : jp.z0);
+  out[2] = atan2f(dy * cph - dx * sph, fmaf(dx, cph, dy * sph));
+  out[3] = up ? asinf(fminf(1.0f, adz)) : -asinf(fminf(1.0f, adz));
+  out[4] = fmaf(u, T0, t[3]) + s;
+  return rc > jp.a + margin && rc < jp.b - margin && adz >= 0.05f && q >= 0.0025f &&
+         fabsf(adzb + t[4] - adz) <= CAP_DZ_CHECK;
+}
+
+// cell of the side job's trust map: (axis, branch) x alpha x beta
 __device__ __forceinline__ int cell_of(int kind, float al, float be) {
   int ia = (int)floorf((al + 0.5f * PI_F) * (NCELL_A / PI_F));
   int ib = (int)floorf((be + 0.5f * PI_F) * (NCELL_B / PI_F));
@@ -813,10 +1034,21 @@ __device__ __forceinline__ int cell_of(int kind, float al, float be) {
   return (kind * NCELL_A + ia) * NCELL_B + ib;
 }
 
+// cell of the cap job's trust map: (axis, branch) x alpha x |beta| x u
+__device__ __forceinline__ int cell_cap(int kind, float al, float be, float u) {
+  int ia = (int)floorf((al + 0.5f * PI_F) * (CAP_A / PI_F));
+  int ib = (int)floorf(fabsf(be) * (2.0f * CAP_B / PI_F));
+  int iu = (int)floorf(u * (float)CAP_U);
+  ia = min(max(ia, 0), CAP_A - 1);
+  ib = min(max(ib, 0), CAP_B - 1);
+  iu = min(max(iu, 0), CAP_U - 1);
+  return ((kind * CAP_A + ia) * CAP_B + ib) * CAP_U + iu;
+}
+
 struct GateP {
   float a, b, z0, z1;  // cloak radii r1, r2 and material height range
   float hres_max;    // conservation residual limit
-  float cap_margin;  // distance of the predicted exit height from a cap
+  float cap_margin;  // distance of the predicted exit height from a cap (side job), of the cap point from the rims (cap job)
   float p_min;       // near-singular band of the conserved wave number
 };
 
@@ -832,35 +1064,51 @@ __device__ __forceinline__ bool outside_band(int kind, float al, float be, float
   return p >= p_min;
 }
 
+// The input half of the gate: a valid entry inside the material's height
+// range, outside the near-singular band, in a trusted cell of the model's
+// trust map and, for the cap job, heading for a cap (u < 1).
+__device__ __forceinline__ bool gate_inputs(float phi, float z, float al, float be, float pol, float axis,
+                                            const unsigned char *__restrict__ map, const GateP &gp, const JobP &jp) {
+  if (!(entry_ok(phi, z, al, be, pol, axis) && z >= gp.z0 && z <= gp.z1)) return false;
+  const int kind = kind_of(pol, axis);
+  if (!outside_band(kind, al, be, gp.p_min)) return false;
+  if (jp.job == RT_SUR_CAP) {
+    const float u = cap_fraction(z, al, be, kind, jp);
+    return u < 1.0f && map[cell_cap(kind, al, be, u)] != 0;
+  }
+  return map[cell_of(kind, al, be)] != 0;
+}
+
 // Gate and write the accepted predictions. A prediction is rejected (and
-// the exact integrator traces the ray) when
-//  - the entry is not a valid side entry,
-//  - its trust-map cell is not trusted,
-//  - the predicted exit ray violates the conservation of the tangential
-//    wave numbers (p_theta / b and p_z, equal at entry and exit on r = b
-//    for every side-to-side transit) by more than hres_max, or
-//  - the predicted exit height lies within cap_margin of an end cap or
-//    beyond it (z is monotonic along a transit since p_z keeps its sign,
-//    so an exit height inside the material with margin means the whole
-//    path stayed inside).
+// the exact integrator traces the ray) when its input fails gate_inputs or
+//  - side job: the predicted exit ray violates the conservation of the
+//    tangential wave numbers (p_theta / b and p_z, equal at entry and exit
+//    on r = b for every side-to-side transit) by more than hres_max, or the
+//    predicted exit height lies within cap_margin of an end cap or beyond
+//    it (z is monotonic along a transit since p_z keeps its sign, so an exit
+//    height inside the material with margin means the whole path stayed
+//    inside);
+//  - cap job: the prediction is no usable cap exit (decode_cap).
 __device__ __forceinline__ void gate_row(long long i, const float *__restrict__ x6, long long ld,
                                          const float *yrow, const float *__restrict__ sc,
-                                         const unsigned char *__restrict__ map, const GateP &gp,
+                                         const unsigned char *__restrict__ map, const GateP &gp, const JobP &jp,
                                          float *__restrict__ y5, unsigned char *__restrict__ fallback,
                                          int *__restrict__ status) {
   const float phi = x6[i], z = x6[ld + i], al = x6[2 * ld + i], be = x6[3 * ld + i];
   const float pol = x6[4 * ld + i], axis = x6[5 * ld + i];
-  bool acc = entry_ok(phi, z, al, be, pol, axis) && z >= gp.z0 && z <= gp.z1;
+  bool acc = gate_inputs(phi, z, al, be, pol, axis, map, gp, jp);
   float out[NOUT];
   if (acc) {
     const int kind = kind_of(pol, axis);
-    decode(yrow, sc, phi, z, al, be, kind, gp.a, gp.b, out);
-    acc = map[cell_of(kind, al, be)] != 0 && outside_band(kind, al, be, gp.p_min);
-    const float kt = cosf(be) * sinf(al), kz = sinf(be);
-    const float kt2 = cosf(out[3]) * sinf(out[2]), kz2 = sinf(out[3]);
-    const float res = fmaxf(fabsf(kt2 - kt), fabsf(kz2 - kz));
-    acc = acc && res <= gp.hres_max;
-    acc = acc && out[1] >= gp.z0 + gp.cap_margin && out[1] <= gp.z1 - gp.cap_margin;
+    if (jp.job == RT_SUR_CAP) {
+      acc = decode_cap(yrow, sc, phi, z, al, be, kind, jp, gp.cap_margin, out);
+    } else {
+      decode(yrow, sc, phi, z, al, be, kind, gp.a, gp.b, out);
+      const float kt = cosf(be) * sinf(al), kz = sinf(be);
+      const float kt2 = cosf(out[3]) * sinf(out[2]), kz2 = sinf(out[3]);
+      const float res = fmaxf(fabsf(kt2 - kt), fabsf(kz2 - kz));
+      acc = res <= gp.hres_max && out[1] >= gp.z0 + gp.cap_margin && out[1] <= gp.z1 - gp.cap_margin;
+    }
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) acc = acc && isfinite(out[o]);
   }
@@ -872,20 +1120,19 @@ __device__ __forceinline__ void gate_row(long long i, const float *__restrict__ 
   }
 }
 
-// First half of the gate, on the inputs alone: entries whose trust-map cell
-// is trusted (and that are valid side entries) are appended to idx for the
-// network; the others go to the exact transit (fallback = 1).
+// First half of the gate, on the inputs alone: entries that pass
+// gate_inputs are appended to idx for the network; the others go to the
+// exact transit (fallback = 1). With `chained`, only the rows an earlier
+// model rejected (fallback != 0) are considered; the others keep fallback 0.
 __global__ void __launch_bounds__(256) k_pregate(const float *__restrict__ x6, long long ld, int n,
-                                                 const unsigned char *__restrict__ map, GateP gp,
-                                                 unsigned char *__restrict__ fallback, int *__restrict__ idx,
-                                                 unsigned int *__restrict__ count) {
+                                                 const unsigned char *__restrict__ map, GateP gp, JobP jp,
+                                                 int chained, unsigned char *__restrict__ fallback,
+                                                 int *__restrict__ idx, unsigned int *__restrict__ count) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   bool take = false;
-  if (i < n) {
-    const float phi = x6[i], z = x6[ld + i], al = x6[2 * ld + i], be = x6[3 * ld + i];
-    const float pol = x6[4 * ld + i], axis = x6[5 * ld + i];
-    take = entry_ok(phi, z, al, be, pol, axis) && z >= gp.z0 && z <= gp.z1 &&
-           map[cell_of(kind_of(pol, axis), al, be)] != 0 && outside_band(kind_of(pol, axis), al, be, gp.p_min);
+  if (i < n && (!chained || fallback[i] != 0)) {
+    take = gate_inputs(x6[i], x6[ld + i], x6[2 * ld + i], x6[3 * ld + i], x6[4 * ld + i], x6[5 * ld + i], map, gp,
+                       jp);
     fallback[i] = take ? 0 : 1;
   }
   const unsigned long long m = __ballot(take);
@@ -904,11 +1151,11 @@ __global__ void __launch_bounds__(256) k_pregate(const float *__restrict__ x6, l
 __global__ void __launch_bounds__(256) k_gate_idx(const float *__restrict__ x6, long long ld,
                                                   const int *__restrict__ idx, const unsigned int *count,
                                                   const float *__restrict__ y, const float *__restrict__ sc,
-                                                  const unsigned char *__restrict__ map, GateP gp,
+                                                  const unsigned char *__restrict__ map, GateP gp, JobP jp,
                                                   float *__restrict__ y5, unsigned char *__restrict__ fallback,
                                                   int *__restrict__ status) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < (long long)*count) gate_row(idx[p], x6, ld, y + p * NOUT, sc, map, gp, y5, fallback, status);
+  if (p < (long long)*count) gate_row(idx[p], x6, ld, y + p * NOUT, sc, map, gp, jp, y5, fallback, status);
 }
 
 // ---------------------------------------------------------------------------
@@ -980,7 +1227,8 @@ struct TrainSink {
 __global__ void __launch_bounds__(256, 2) k_mlp_fused(const float *__restrict__ x6, long long ld, int n,
                                                       const int *__restrict__ idx, const unsigned int *count,
                                                       const float *__restrict__ P, const bf16 *__restrict__ Wt,
-                                                      const float *__restrict__ sc, float *__restrict__ yout) {
+                                                      const float *__restrict__ sc, JobP jp,
+                                                      float *__restrict__ yout) {
   __shared__ __attribute__((aligned(16))) bf16 act[FR * ALD];
   __shared__ float xn[FR * NIN];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -992,7 +1240,7 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fused(const float *__restrict__ 
     const long long i = row0 + tid;
     float f[NIN] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (i < n) {
-      features(x6, ld, idx ? (long long)idx[i] : i, f);
+      features(x6, ld, idx ? (long long)idx[i] : i, jp, f);
 #pragma unroll
       for (int k = 0; k < NIN; ++k) f[k] = (f[k] - sc[S_INOFF + k]) * sc[S_INSCALE + k];
     }
@@ -1123,7 +1371,7 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fused(const float *__restrict__ 
 constexpr int TR = 64;  // rows per block
 __global__ void __launch_bounds__(256, 2) k_mlp_train_fwd(const float *__restrict__ x6, long long ld, int n,
                                                           const float *__restrict__ P, const bf16 *__restrict__ Wt,
-                                                          const float *__restrict__ sc, TrainSink ts) {
+                                                          const float *__restrict__ sc, JobP jp, TrainSink ts) {
   constexpr int R = TR;
   constexpr int NT = R / 16;  // row tiles of 16
   constexpr int ZLD = 64 + 4;  // padded rows of the pre-activation staging tiles
@@ -1138,7 +1386,7 @@ __global__ void __launch_bounds__(256, 2) k_mlp_train_fwd(const float *__restric
     const long long i = row0 + tid;
     float f[NIN] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (i < n) {
-      features(x6, ld, i, f);
+      features(x6, ld, i, jp, f);
 #pragma unroll
       for (int k = 0; k < NIN; ++k) f[k] = (f[k] - sc[S_INOFF + k]) * sc[S_INSCALE + k];
 #pragma unroll
@@ -1320,27 +1568,18 @@ __global__ void __launch_bounds__(256, 2) k_mlp_train_fwd(const float *__restric
   }
 }
 
-// exit point and unit direction from exit parameters
-__device__ __forceinline__ void exit_ray(const float *p, float b, float x[3], float d[3]) {
-  float sp, cp, sa, ca, sb, cbt;
-  sincosf(p[0], &sp, &cp);
-  sincosf(p[2], &sa, &ca);
-  sincosf(p[3], &sb, &cbt);
-  x[0] = b * cp; x[1] = b * sp; x[2] = p[1];
-  d[0] = cbt * (ca * cp - sa * sp);
-  d[1] = cbt * (ca * sp + sa * cp);
-  d[2] = sb;
-}
-
 // error of the decoded prediction against the exact exit, per trust-map cell:
 // err = max(|x - x_exact| / b, angle(d, d_exact)); a ray the exact
-// integrator did not carry from side to side (absorbed, reflected, ...)
-// makes its cell untrusted
+// integrator did not carry to an exit (absorbed, reflected, ...) makes its
+// cell untrusted. The cap job counts only the rows its gate would offer the
+// network (heading for a cap, u < 1) and whose prediction is a usable cap
+// exit (decode_cap with the gate's margin): the gate rejects the
+// others whatever their cell, so they neither count towards nor fail it.
 __global__ void __launch_bounds__(256) k_calib(const float *__restrict__ x6, long long ld, int n,
                                                const float *__restrict__ y, const float *__restrict__ sc,
                                                const float *__restrict__ ye, const int *__restrict__ st,
                                                const float *__restrict__ hres, float unresolved, bool infinite,
-                                               float a, float b, unsigned int *__restrict__ cmax,
+                                               JobP jp, float margin, unsigned int *__restrict__ cmax,
                                                unsigned int *__restrict__ ccnt) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -1356,11 +1595,24 @@ __global__ void __launch_bounds__(256) k_calib(const float *__restrict__ x6, lon
   if (hres && st[i] == RT_RAY_EXITED && !(hres[i] <= unresolved)) return;
   if (hres && infinite && st[i] == RT_RAY_TIR) return;
   const int kind = kind_of(pol, axis);
-  const int cell = cell_of(kind, al, be);
+  const float b = jp.b;
+  int cell;
+  float out[NOUT];
+  bool usable = true;
+  if (jp.job == RT_SUR_CAP) {
+    if (!(z >= jp.z0 && z <= jp.z1)) return;
+    const float u = cap_fraction(z, al, be, kind, jp);
+    if (!(u < 1.0f)) return;
+    cell = cell_cap(kind, al, be, u);
+    usable = decode_cap(y + i * NOUT, sc, phi, z, al, be, kind, jp, margin, out);
+  } else {
+    cell = cell_of(kind, al, be);
+    decode(y + i * NOUT, sc, phi, z, al, be, kind, jp.a, b, out);
+  }
   float err = INFINITY;
   if (st[i] == RT_RAY_EXITED) {
-    float out[NOUT], ex[NOUT], xp[3], dp[3], xe[3], de[3];
-    decode(y + i * NOUT, sc, phi, z, al, be, kind, a, b, out);
+    if (!usable) return;
+    float ex[NOUT], xp[3], dp[3], xe[3], de[3];
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) ex[o] = ye[o * ld + i];
     exit_ray(out, b, xp, dp);
@@ -1397,6 +1649,10 @@ struct rt_model_s {
   float h_scal[NSCAL] = {0};
   std::vector<unsigned char> h_map;
   int map_valid = 0;
+  int job = RT_SUR_SIDE;
+  float geo[4] = {0.f, 0.f, 0.f, 0.f};  // cap job: r1, r2, z0, z1 of the cloak it was set up for
+  rt_model next = nullptr;              // rt_surrogate_chain: rows this model rejects go to next
+  rt_model prev = nullptr;              // the model whose rejected rows come here
   rt_gate_opts gate{};
   long long step = 0;
   // activations for up to `cap` rows
@@ -1482,10 +1738,20 @@ int reserve_yinf(rt_model mo, long long n) {
   return RT_OK;
 }
 
+// The job parameters of a model's kernels: the cap job carries the
+// geometry it was set up for; the side job's features need none, and its
+// decoding takes the radii of the cloak description d (if given).
+JobP job_for(rt_model mo, const rt_cloak_desc *d) {
+  if (mo->job == RT_SUR_CAP) return JobP{RT_SUR_CAP, mo->geo[0], mo->geo[1], mo->geo[2], mo->geo[3]};
+  if (!d) return JobP{RT_SUR_SIDE, 0.0f, 0.0f, 0.0f, 0.0f};
+  return JobP{RT_SUR_SIDE, (float)d->r1, (float)d->r2, std::isfinite(d->z0) ? (float)d->z0 : -INFINITY,
+              std::isfinite(d->z1) ? (float)d->z1 : INFINITY};
+}
+
 // standardized outputs of n rows into mo->yinf (fused kernel)
 void infer_outputs(rt_model mo, const float *x, long long ld, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_mlp_fused, dim3(gblocks(n, FR)), dim3(256), 0, s, x, ld, n, nullptr, nullptr, mo->P, mo->Pb,
-                     mo->scal, mo->yinf);
+                     mo->scal, job_for(mo, nullptr), mo->yinf);
 }
 
 // returns the number of K splits used (EPI_SPLIT writes that many partials)
@@ -1523,7 +1789,8 @@ void forward_backward(rt_model mo, const float *x, const float *t, long long ld,
   const long long ldT = mo->ldT;
   TrainSink ts{mo->xf, {mo->z[0], mo->z[1], mo->z[2], mo->z[3]}, {mo->aT[0], mo->aT[1], mo->aT[2]}, ldT, t, ld,
                wrow, huber, mo->dy, loss};
-  hipLaunchKernelGGL(k_mlp_train_fwd, dim3(gblocks(n, TR)), dim3(256), 0, s, x, ld, n, mo->P, mo->Pb, mo->scal, ts);
+  hipLaunchKernelGGL(k_mlp_train_fwd, dim3(gblocks(n, TR)), dim3(256), 0, s, x, ld, n, mo->P, mo->Pb, mo->scal,
+                     job_for(mo, nullptr), ts);
   // layer 5: its per-element work (dz of layer 4) is as large as a hidden
   // layer's and parallel over rows: one block per 64 rows, up to 1024
   // blocks; the blocks' partial sums of the layer-5 weights and biases and
@@ -1599,47 +1866,70 @@ int launch_err(const char *what) {
   return RT_OK;
 }
 
-}  // namespace
-
-int surrogate_check_ready(rt_model mo) {
-  int e = check_model(mo);
-  if (e) return e;
-  if (!mo->map_valid) return fail(RT_E_INVALID, "the model has no calibrated trust map (rt_surrogate_calibrate)");
+// A cap model works on cloaks of the geometry it was set up for.
+int check_geometry(rt_model mo, const rt_cloak_desc &d) {
+  if (mo->job != RT_SUR_CAP) return RT_OK;
+  if ((float)d.r1 != mo->geo[0] || (float)d.r2 != mo->geo[1] || (float)d.z0 != mo->geo[2] ||
+      (float)d.z1 != mo->geo[3])
+    return fail(RT_E_INVALID, "the cloaks' geometry (r1 %g, r2 %g, z %g..%g) is not the one the cap model was set "
+                              "up for (r1 %g, r2 %g, z %g..%g)", d.r1, d.r2, d.z0, d.z1, mo->geo[0], mo->geo[1],
+                mo->geo[2], mo->geo[3]);
   return RT_OK;
 }
 
-double surrogate_exit_tolerance(rt_model mo) { return mo->gate.tol; }
+}  // namespace
+
+int surrogate_check_ready(rt_model mo) {
+  for (rt_model m = mo; m; m = m == mo ? mo->next : nullptr) {
+    int e = check_model(m);
+    if (e) return e;
+    if (!m->map_valid)
+      return fail(RT_E_INVALID, "the %smodel has no calibrated trust map (rt_surrogate_calibrate)",
+                  m == mo ? "" : "chained ");
+  }
+  return RT_OK;
+}
+
+double surrogate_exit_tolerance(rt_model mo) {
+  return mo->next ? std::max(mo->gate.tol, mo->next->gate.tol) : mo->gate.tol;
+}
 
 int surrogate_predict_gated(rt_model mo, const rt_cloak_desc &d, int64_t n, int64_t ld, const float *x6, float *y5,
                             uint8_t *fallback, int32_t *status, hipStream_t s) {
   int e = surrogate_check_ready(mo);
+  if (!e) e = check_geometry(mo, d);
+  if (!e && mo->next) e = check_geometry(mo->next, d);
   if (e) return e;
   if (n == 0) return RT_OK;
   if (n < 0 || ld < n || !x6 || !y5 || !fallback || !status)
     return fail(RT_E_INVALID, "bad rows for the surrogate (n, ld or a NULL array)");
-  GateP gp;
-  gp.a = (float)d.r1;
-  gp.b = (float)d.r2;
-  gp.z0 = std::isfinite(d.z0) ? (float)d.z0 : -INFINITY;
-  gp.z1 = std::isfinite(d.z1) ? (float)d.z1 : INFINITY;
-  gp.hres_max = (float)mo->gate.hres_max;
-  gp.cap_margin = (float)mo->gate.cap_margin;
-  gp.p_min = (float)mo->gate.p_min;
   const long long batch = std::min<long long>(n, 1LL << 24);
-  e = reserve_yinf(mo, batch);
-  if (e) return e;
-  for (long long off = 0; off < n; off += batch) {
-    const int m = (int)std::min<long long>(batch, n - off);
-    const float *x = x6 + off;
-    // trusted entries only go through the network (compacted), then the
-    // output half of the gate
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, mo->count, 1LL);
-    hipLaunchKernelGGL(k_pregate, dim3(gblocks(m, 256)), dim3(256), 0, s, x, (long long)ld, m, mo->map, gp,
-                       fallback + off, mo->idx, mo->count);
-    hipLaunchKernelGGL(k_mlp_fused, dim3(gblocks(m, FR)), dim3(256), 0, s, x, (long long)ld, m, mo->idx, mo->count,
-                       mo->P, mo->Pb, mo->scal, mo->yinf);
-    hipLaunchKernelGGL(k_gate_idx, dim3(gblocks(m, 256)), dim3(256), 0, s, x, (long long)ld, mo->idx, mo->count,
-                       mo->yinf, mo->scal, mo->map, gp, y5 + off, fallback + off, status + off);
+  // the model, then the chained one on the rows the first rejected
+  for (rt_model m = mo; m; m = m == mo ? mo->next : nullptr) {
+    GateP gp;
+    gp.a = (float)d.r1;
+    gp.b = (float)d.r2;
+    gp.z0 = std::isfinite(d.z0) ? (float)d.z0 : -INFINITY;
+    gp.z1 = std::isfinite(d.z1) ? (float)d.z1 : INFINITY;
+    gp.hres_max = (float)m->gate.hres_max;
+    gp.cap_margin = (float)m->gate.cap_margin;
+    gp.p_min = (float)m->gate.p_min;
+    const JobP jp = job_for(m, &d);
+    e = reserve_yinf(m, batch);
+    if (e) return e;
+    for (long long off = 0; off < n; off += batch) {
+      const int rows = (int)std::min<long long>(batch, n - off);
+      const float *x = x6 + off;
+      // entries that pass the input gate only go through the network
+      // (compacted), then the output half of the gate
+      hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, m->count, 1LL);
+      hipLaunchKernelGGL(k_pregate, dim3(gblocks(rows, 256)), dim3(256), 0, s, x, (long long)ld, rows, m->map, gp, jp,
+                         m == mo ? 0 : 1, fallback + off, m->idx, m->count);
+      hipLaunchKernelGGL(k_mlp_fused, dim3(gblocks(rows, FR)), dim3(256), 0, s, x, (long long)ld, rows, m->idx,
+                         m->count, m->P, m->Pb, m->scal, jp, m->yinf);
+      hipLaunchKernelGGL(k_gate_idx, dim3(gblocks(rows, 256)), dim3(256), 0, s, x, (long long)ld, m->idx, m->count,
+                         m->yinf, m->scal, m->map, gp, jp, y5 + off, fallback + off, status + off);
+    }
   }
   return launch_err("surrogate launch");
 }
@@ -1713,6 +2003,8 @@ int rt_surrogate_create(uint64_t seed, rt_model *out) {
 int rt_surrogate_free(rt_model mo) {
   if (!mo) return RT_OK;
   (void)hipDeviceSynchronize();
+  if (mo->prev) mo->prev->next = nullptr;
+  if (mo->next) mo->next->prev = nullptr;
   if (mo->act) (void)hipFree(mo->act);
   if (mo->yinf) (void)hipFree(mo->yinf);
   if (mo->base) (void)hipFree(mo->base);
@@ -1782,7 +2074,7 @@ int rt_surrogate_fit_scaling(rt_model mo, int64_t n, int64_t ld, const float *x6
   double h[NMOM];
   hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, mo->mom, NMOM);
   hipLaunchKernelGGL(k_moments, dim3(std::min(gblocks(n, 256), 1024u)), dim3(256), 0, s, x6, t5, (long long)ld, w,
-                     (int)n, mo->mom);
+                     (int)n, job_for(mo, nullptr), mo->mom);
   if (hipMemcpyAsync(h, mo->mom, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(RT_E_DEVICE, "moments failed");
@@ -1908,18 +2200,33 @@ int rt_surrogate_forward(rt_model mo, int64_t n, int64_t ld, const float *x6, fl
   return launch_err("forward launch");
 }
 
-int rt_surrogate_encode(const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int64_t ld, const float *x6,
-                        const float *y5, const int32_t *status, float *t5, float *w, void *stream) {
+int rt_surrogate_encode_job(int32_t job, const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int64_t ld,
+                            const float *x6, const float *y5, const int32_t *status, float *t5, float *w,
+                            void *stream) {
   rt_cloak_desc d;
   int e = cloak_geometry(cloaks, n_cloaks, d);
   if (e) return e;
+  if (job != RT_SUR_SIDE && job != RT_SUR_CAP) return fail(RT_E_INVALID, "job must be RT_SUR_SIDE or RT_SUR_CAP");
+  if (job == RT_SUR_CAP && (!std::isfinite(d.z0) || !std::isfinite(d.z1) || !(d.z1 > d.z0)))
+    return fail(RT_E_INVALID, "the cap job needs cloaks of finite height");
   if (n == 0) return RT_OK;
   e = check_rows(n, ld, x6);
   if (e) return e;
   if (!y5 || !status || !t5 || !w) return fail(RT_E_INVALID, "y5, status, t5 and w are required");
-  hipLaunchKernelGGL(k_encode, dim3(gblocks(n, 256)), dim3(256), 0, (hipStream_t)stream, x6, y5, status,
-                     (long long)ld, (long long)n, (float)d.r1, (float)d.r2, t5, w);
+  if (job == RT_SUR_CAP) {
+    const JobP jp{RT_SUR_CAP, (float)d.r1, (float)d.r2, (float)d.z0, (float)d.z1};
+    hipLaunchKernelGGL(k_encode_cap, dim3(gblocks(n, 256)), dim3(256), 0, (hipStream_t)stream, x6, y5, status,
+                       (long long)ld, (long long)n, jp, t5, w);
+  } else {
+    hipLaunchKernelGGL(k_encode, dim3(gblocks(n, 256)), dim3(256), 0, (hipStream_t)stream, x6, y5, status,
+                       (long long)ld, (long long)n, (float)d.r1, (float)d.r2, t5, w);
+  }
   return launch_err("encode launch");
+}
+
+int rt_surrogate_encode(const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int64_t ld, const float *x6,
+                        const float *y5, const int32_t *status, float *t5, float *w, void *stream) {
+  return rt_surrogate_encode_job(RT_SUR_SIDE, cloaks, n_cloaks, n, ld, x6, y5, status, t5, w, stream);
 }
 
 int rt_surrogate_calibrate(rt_model mo, const rt_cloak *cloaks, int32_t n_cloaks, int64_t n, int64_t ld,
@@ -1930,6 +2237,7 @@ int rt_surrogate_calibrate(rt_model mo, const rt_cloak *cloaks, int32_t n_cloaks
   if (e) return e;
   rt_cloak_desc d;
   e = cloak_geometry(cloaks, n_cloaks, d);
+  if (!e) e = check_geometry(mo, d);
   if (!e) e = check_rows(n, ld, x6);
   if (e) return e;
   if (!y5_exact || !status_exact || !gate) return fail(RT_E_INVALID, "y5_exact, status_exact and gate are required");
@@ -1945,7 +2253,8 @@ int rt_surrogate_calibrate(rt_model mo, const rt_cloak *cloaks, int32_t n_cloaks
   hipLaunchKernelGGL(k_fill_u32, dim3(gblocks(2LL * NCELLS, 256)), dim3(256), 0, s, mo->cal, 2LL * NCELLS);
   hipLaunchKernelGGL(k_calib, dim3(gblocks(n, 256)), dim3(256), 0, s, x6, (long long)ld, (int)n, mo->yinf, mo->scal,
                      y5_exact, status_exact, hres_exact, (float)gate->unresolved,
-                     !std::isfinite(d.z0) && !std::isfinite(d.z1), (float)d.r1, (float)d.r2, mo->cal, mo->cal + NCELLS);
+                     !std::isfinite(d.z0) && !std::isfinite(d.z1), job_for(mo, &d), (float)gate->cap_margin, mo->cal,
+                     mo->cal + NCELLS);
   std::vector<unsigned int> h(2 * NCELLS);
   if (hipMemcpyAsync(h.data(), mo->cal, sizeof(unsigned int) * 2 * NCELLS, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
@@ -1956,33 +2265,90 @@ int rt_surrogate_calibrate(rt_model mo, const rt_cloak *cloaks, int32_t n_cloaks
     memcpy(&mx, &h[c], sizeof(float));
     good[c] = h[NCELLS + c] >= (unsigned int)gate->min_count && mx <= (float)gate->tol;
   }
+  // dilation within each (axis, branch) block over the cell grid's
+  // dimensions: (alpha, beta) for the side job, (alpha, |beta|, u) for the
+  // cap job
   const int dl = gate->dilate;
+  const bool capj = mo->job == RT_SUR_CAP;
+  const int na = capj ? CAP_A : NCELL_A, nb = capj ? CAP_B : NCELL_B, nu = capj ? CAP_U : 1;
+  const int du = capj ? dl : 0;
   long long trusted = 0;
   for (int k = 0; k < NCOMBO; ++k)
-    for (int ia = 0; ia < NCELL_A; ++ia)
-      for (int ib = 0; ib < NCELL_B; ++ib) {
-        bool ok = true;
-        for (int da = -dl; da <= dl && ok; ++da)
-          for (int db = -dl; db <= dl && ok; ++db) {
-            const int ja = ia + da, jb = ib + db;
-            if (ja < 0 || ja >= NCELL_A || jb < 0 || jb >= NCELL_B) continue;
-            ok = good[(k * NCELL_A + ja) * NCELL_B + jb] != 0;
-          }
-        mo->h_map[(k * NCELL_A + ia) * NCELL_B + ib] = ok ? 1 : 0;
-        trusted += ok;
-      }
+    for (int ia = 0; ia < na; ++ia)
+      for (int ib = 0; ib < nb; ++ib)
+        for (int iu = 0; iu < nu; ++iu) {
+          bool ok = true;
+          for (int da = -dl; da <= dl && ok; ++da)
+            for (int db = -dl; db <= dl && ok; ++db)
+              for (int dv = -du; dv <= du && ok; ++dv) {
+                const int ja = ia + da, jb = ib + db, ju = iu + dv;
+                if (ja < 0 || ja >= na || jb < 0 || jb >= nb || ju < 0 || ju >= nu) continue;
+                ok = good[((k * na + ja) * nb + jb) * nu + ju] != 0;
+              }
+          mo->h_map[((k * na + ia) * nb + ib) * nu + iu] = ok ? 1 : 0;
+          trusted += ok;
+        }
   mo->gate = *gate;
   mo->map_valid = 1;
   if (trusted_fraction) *trusted_fraction = (double)trusted / NCELLS;
   return upload_map(mo);
 }
 
-int rt_surrogate_get_map(rt_model mo, uint8_t *host, int32_t *cells_alpha, int32_t *cells_beta) {
+int rt_surrogate_get_map(rt_model mo, uint8_t *host, int32_t *cells_alpha, int32_t *cells_beta, int32_t *cells_u) {
   int e = check_model(mo);
   if (e) return e;
-  if (cells_alpha) *cells_alpha = NCELL_A;
-  if (cells_beta) *cells_beta = NCELL_B;
+  const bool capj = mo->job == RT_SUR_CAP;
+  if (cells_alpha) *cells_alpha = capj ? CAP_A : NCELL_A;
+  if (cells_beta) *cells_beta = capj ? CAP_B : NCELL_B;
+  if (cells_u) *cells_u = capj ? CAP_U : 1;
   if (host) memcpy(host, mo->h_map.data(), NCELLS);
+  return RT_OK;
+}
+
+int rt_surrogate_set_job(rt_model mo, int32_t job, rt_cloak cloak) {
+  int e = check_model(mo);
+  if (e) return e;
+  if (job != RT_SUR_SIDE && job != RT_SUR_CAP) return fail(RT_E_INVALID, "job must be RT_SUR_SIDE or RT_SUR_CAP");
+  float geo[4] = {0.f, 0.f, 0.f, 0.f};
+  if (job == RT_SUR_CAP) {
+    rt_cloak_desc d;
+    if (!cloak || rt_cloak_get_desc(cloak, &d) != RT_OK) return fail(RT_E_INVALID, "the cap job needs a cloak handle");
+    if (!std::isfinite(d.z0) || !std::isfinite(d.z1) || !(d.z1 > d.z0))
+      return fail(RT_E_INVALID, "the cap job needs a cloak of finite height");
+    geo[0] = (float)d.r1;
+    geo[1] = (float)d.r2;
+    geo[2] = (float)d.z0;
+    geo[3] = (float)d.z1;
+  }
+  mo->job = job;
+  memcpy(mo->geo, geo, sizeof(geo));
+  // the cells of the trust map change meaning
+  std::fill(mo->h_map.begin(), mo->h_map.end(), 0);
+  mo->map_valid = 0;
+  return upload_map(mo);
+}
+
+int rt_surrogate_get_job(rt_model mo, int32_t *job) {
+  int e = check_model(mo);
+  if (e) return e;
+  if (!job) return fail(RT_E_INVALID, "job is NULL");
+  *job = mo->job;
+  return RT_OK;
+}
+
+int rt_surrogate_chain(rt_model first, rt_model next) {
+  int e = check_model(first);
+  if (e) return e;
+  if (next) {
+    e = check_model(next);
+    if (e) return e;
+    if (next == first) return fail(RT_E_INVALID, "a model cannot follow itself");
+    if (next->next || first->prev) return fail(RT_E_INVALID, "chains hold two models");
+    if (next->prev && next->prev != first) return fail(RT_E_INVALID, "next already follows another model");
+  }
+  if (first->next) first->next->prev = nullptr;
+  first->next = next;
+  if (next) next->prev = first;
   return RT_OK;
 }
 
@@ -2014,14 +2380,15 @@ int rt_surrogate_save(rt_model mo, const char *path) {
     return fail(RT_E_DEVICE, "copy failed");
   FILE *f = fopen(path, "wb");
   if (!f) return fail(RT_E_INVALID, "cannot open %s", path);
-  const char magic[8] = {'R', 'T', 'M', 'L', 'P', '0', '4', '\0'};
+  const char magic[8] = {'R', 'T', 'M', 'L', 'P', '0', '5', '\0'};
   const long long np = NPARAM, nc = NCELLS;
   const int valid = mo->map_valid;
   bool ok = fwrite(magic, 1, 8, f) == 8 && fwrite(&np, sizeof(np), 1, f) == 1 &&
             fwrite(mo->h_scal, sizeof(float), S_LOSS, f) == (size_t)S_LOSS &&
             fwrite(h.data(), sizeof(float), NPARAM, f) == (size_t)NPARAM && fwrite(&nc, sizeof(nc), 1, f) == 1 &&
             fwrite(&valid, sizeof(valid), 1, f) == 1 && fwrite(&mo->gate, sizeof(mo->gate), 1, f) == 1 &&
-            fwrite(mo->h_map.data(), 1, NCELLS, f) == (size_t)NCELLS;
+            fwrite(mo->h_map.data(), 1, NCELLS, f) == (size_t)NCELLS && fwrite(&mo->job, sizeof(int), 1, f) == 1 &&
+            fwrite(mo->geo, sizeof(float), 4, f) == 4;
   ok = (fclose(f) == 0) && ok;
   return ok ? RT_OK : fail(RT_E_INVALID, "write to %s failed", path);
 }
@@ -2033,16 +2400,17 @@ int rt_surrogate_load(const char *path, rt_model *out) {
   if (!f) return fail(RT_E_INVALID, "cannot open %s", path);
   char magic[8];
   long long np = 0, nc = 0;
-  int valid = 0;
-  float scal[S_LOSS];
+  int valid = 0, job = RT_SUR_SIDE;
+  float scal[S_LOSS], geo[4];
   rt_gate_opts gate;
   std::vector<float> h(NPARAM);
   std::vector<unsigned char> map(NCELLS);
-  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "RTMLP04", 8) == 0 && fread(&np, sizeof(np), 1, f) == 1 &&
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "RTMLP05", 8) == 0 && fread(&np, sizeof(np), 1, f) == 1 &&
             np == NPARAM && fread(scal, sizeof(float), S_LOSS, f) == (size_t)S_LOSS &&
             fread(h.data(), sizeof(float), NPARAM, f) == (size_t)NPARAM && fread(&nc, sizeof(nc), 1, f) == 1 &&
             nc == NCELLS && fread(&valid, sizeof(valid), 1, f) == 1 && fread(&gate, sizeof(gate), 1, f) == 1 &&
-            fread(map.data(), 1, NCELLS, f) == (size_t)NCELLS;
+            fread(map.data(), 1, NCELLS, f) == (size_t)NCELLS && fread(&job, sizeof(int), 1, f) == 1 &&
+            fread(geo, sizeof(float), 4, f) == 4 && (job == RT_SUR_SIDE || job == RT_SUR_CAP);
   fclose(f);
   if (!ok) return fail(RT_E_INVALID, "%s is not a surrogate file of this layout", path);
   rt_model mo = nullptr;
@@ -2054,6 +2422,8 @@ int rt_surrogate_load(const char *path, rt_model *out) {
     mo->h_map = map;
     mo->map_valid = valid;
     mo->gate = gate;
+    mo->job = job;
+    memcpy(mo->geo, geo, sizeof(geo));
     e = upload_map(mo);
   }
   if (e) {

@@ -33,7 +33,8 @@ EXPORTED = ["rt_build_cloak", "rt_free_cloak", "rt_trace_batch", "rt_render", "r
             "rt_surrogate_grad", "rt_surrogate_train", "rt_surrogate_forward",
             "rt_surrogate_calibrate", "rt_surrogate_get_map", "rt_surrogate_infer",
             "rt_surrogate_save", "rt_surrogate_load", "rt_render_surrogate", "rt_surrogate_step",
-            "rt_surrogate_get_state", "rt_surrogate_set_state", "rt_trace_batch_noalloc"]
+            "rt_surrogate_get_state", "rt_surrogate_set_state", "rt_trace_batch_noalloc",
+            "rt_surrogate_encode_job", "rt_surrogate_set_job", "rt_surrogate_get_job", "rt_surrogate_chain"]
 
 
 class RtError(RuntimeError):
@@ -164,7 +165,11 @@ def lib():
         L.rt_surrogate_calibrate.argtypes = [vp, ctypes.POINTER(vp), i32, i64, i64, vp, vp, vp, vp,
                                              ctypes.POINTER(GateOpts), ctypes.POINTER(ctypes.c_double),
                                              vp]
-        L.rt_surrogate_get_map.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.rt_surrogate_get_map.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.rt_surrogate_encode_job.argtypes = [i32, ctypes.POINTER(vp), i32, i64, i64, vp, vp, vp, vp, vp, vp]
+        L.rt_surrogate_set_job.argtypes = [vp, i32, vp]
+        L.rt_surrogate_get_job.argtypes = [vp, ctypes.POINTER(i32)]
+        L.rt_surrogate_chain.argtypes = [vp, vp]
         L.rt_surrogate_infer.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(TraceOpts), i64,
                                          i64, vp, vp, vp, vp, vp]
         L.rt_surrogate_save.argtypes = [vp, ctypes.c_char_p]
@@ -520,16 +525,20 @@ def transit_exact(cloaks: list, opts: dict, x6, mask=None, y5=None, status=None,
     return out
 
 
-def surrogate_encode(cloaks: list, x6, y5, status):
-    """Training targets t5 (5, n) and row weights w (n) of exact transits."""
+SIDE, CAP = 0, 1  # surrogate jobs (RT_SUR_SIDE, RT_SUR_CAP)
+
+
+def surrogate_encode(cloaks: list, x6, y5, status, job: int = SIDE):
+    """Training targets t5 (5, n) and row weights w (n) of exact transits
+    for the side or the cap job."""
     import torch
     ld = _check_soa(x6, 6, torch.float32)
     assert y5.stride(0) == ld
     n = x6.shape[1]
     t5 = torch.empty((5, ld), dtype=torch.float32, device=x6.device)[:, :n]
     w = torch.empty(n, dtype=torch.float32, device=x6.device)
-    _check(lib().rt_surrogate_encode(_handles(cloaks), len(cloaks), n, ld, _ptr(x6), _ptr(y5),
-                                     _ptr(status), _ptr(t5), _ptr(w), _stream()))
+    _check(lib().rt_surrogate_encode_job(int(job), _handles(cloaks), len(cloaks), n, ld, _ptr(x6), _ptr(y5),
+                                         _ptr(status), _ptr(t5), _ptr(w), _stream()))
     return t5, w
 
 
@@ -642,11 +651,30 @@ class Surrogate:
         return frac.value
 
     def trust_map(self) -> np.ndarray:
-        na, nb = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().rt_surrogate_get_map(self.handle, None, ctypes.byref(na), ctypes.byref(nb)))
-        out = np.empty((4, na.value, nb.value), dtype=np.uint8)
-        _check(lib().rt_surrogate_get_map(self.handle, out.ctypes.data, None, None))
-        return out
+        """(4, alpha cells, beta cells) for the side job, (4, alpha, |beta|, u
+        cells) for the cap job."""
+        na, nb, nu = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().rt_surrogate_get_map(self.handle, None, ctypes.byref(na), ctypes.byref(nb), ctypes.byref(nu)))
+        out = np.empty((4, na.value, nb.value, nu.value), dtype=np.uint8)
+        _check(lib().rt_surrogate_get_map(self.handle, out.ctypes.data, None, None, None))
+        return out if nu.value > 1 else out[..., 0]
+
+    def set_job(self, job: int, cloak=None):
+        """Side job (SIDE) or cap job (CAP, with the geometry of `cloak`);
+        clears the trust map."""
+        _check(lib().rt_surrogate_set_job(self.handle, int(job), cloak.handle if cloak is not None else None))
+
+    @property
+    def job(self) -> int:
+        j = ctypes.c_int32()
+        _check(lib().rt_surrogate_get_job(self.handle, ctypes.byref(j)))
+        return j.value
+
+    def chain(self, nxt: "Surrogate | None"):
+        """Offer the rows this model's gate rejects to `nxt` (None unchains).
+        Keeps a reference so that `nxt` lives as long as the chain."""
+        _check(lib().rt_surrogate_chain(self.handle, nxt.handle if nxt is not None else None))
+        self._next = nxt
 
     def infer(self, cloaks, opts: dict, x6, y5=None, fallback=None, status=None):
         """Surrogate transit with exact fallback: (y5, status, fallback)."""

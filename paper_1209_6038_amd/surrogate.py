@@ -32,11 +32,32 @@ def features(n: int, seed: int, device="cuda"):
     return torch.from_numpy(W.surrogate_features(n, seed)).to(device)
 
 
-def label(cloaks, x6, opts=None):
-    """Exact transits and training targets of entries x6: (y5, status, t5, w)."""
+def label(cloaks, x6, opts=None, job=rt.SIDE):
+    """Exact transits and training targets of entries x6 for the side or the
+    cap job: (y5, status, t5, w)."""
     y5, st = rt.transit_exact(cloaks, opts or exact_opts(), x6)
-    t5, w = rt.surrogate_encode(cloaks, x6, y5, st)
+    t5, w = rt.surrogate_encode(cloaks, x6, y5, st, job=job)
     return y5, st, t5, w
+
+
+def compact(x6, t5, w):
+    """The rows with w > 0 (contiguous SoA copies) and unit weights: for a
+    job whose targets exist on few rows (the cap job's side entries that
+    leave through a cap), so that every training batch is full."""
+    import torch
+    idx = torch.nonzero(w > 0).flatten()
+    ones = torch.ones(idx.numel(), dtype=torch.float32, device=w.device)
+    return x6[:, idx].contiguous(), t5[:, idx].contiguous(), ones
+
+
+def cap_training_set(n: int, seed: int, opts=None):
+    """Cap-job training rows from n side entries (uniform, as features) of
+    the radial and azimuthal cloaks of height W.HEIGHT: (x6, t5, w) of the
+    entries that leave through the cap they head for, compacted."""
+    cl = make_cloaks(W.HEIGHT)
+    x6 = features(n, seed)
+    _, _, t5, w = label(cl, x6, opts, job=rt.CAP)
+    return compact(x6, t5, w)
 
 
 def exit_points(y5, b: float):

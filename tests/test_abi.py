@@ -1,5 +1,6 @@
 """Host-side checks of the C ABI (no GPU needed, no compute calls)."""
 import ctypes
+import math
 import os
 import re
 import subprocess
@@ -172,3 +173,23 @@ def test_render_argument_validation_needs_no_gpu(lib):
                                    None, None, None, None) == rt.RT_E_INVALID
     assert b"model" in lib.rt_last_error()
     assert lib.rt_free_cloak(h) == rt.RT_OK
+
+
+def test_cap_job_argument_validation_needs_no_gpu(lib):
+    """The cap job's encoding is checked on the host: a job that does not
+    exist, and cloaks of infinite height (the cap job needs end caps), are
+    rejected before any device use; chaining and job changes need a model."""
+    h_inf, h_fin = ctypes.c_void_p(), ctypes.c_void_p()
+    assert lib.rt_build_cloak(ctypes.byref(rt.CloakDesc(1.0, 2.0, -math.inf, math.inf, 0, 1)),
+                              ctypes.byref(h_inf)) == rt.RT_OK
+    assert lib.rt_build_cloak(ctypes.byref(rt.CloakDesc(1.0, 2.0, 0.0, 4.0, 0, 1)), ctypes.byref(h_fin)) == rt.RT_OK
+    fake = ctypes.c_void_p(8)  # never dereferenced on these paths
+    for h, job, msg in ((h_fin, 2, b"RT_SUR_SIDE or RT_SUR_CAP"), (h_inf, rt.CAP, b"finite height")):
+        arr = (ctypes.c_void_p * 1)(h)
+        assert lib.rt_surrogate_encode_job(job, arr, 1, 10, 10, fake, fake, fake, fake, fake, None) == rt.RT_E_INVALID
+        assert msg in lib.rt_last_error()
+    arr = (ctypes.c_void_p * 1)(h_fin)
+    assert lib.rt_surrogate_encode_job(rt.CAP, arr, 1, 0, 0, None, None, None, None, None, None) == rt.RT_OK
+    assert lib.rt_surrogate_chain(None, None) == rt.RT_E_INVALID
+    assert lib.rt_surrogate_set_job(None, rt.CAP, h_fin) == rt.RT_E_INVALID
+    assert lib.rt_free_cloak(h_inf) == rt.RT_OK and lib.rt_free_cloak(h_fin) == rt.RT_OK

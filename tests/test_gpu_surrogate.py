@@ -11,29 +11,9 @@ import oracle
 from oracle import mlp
 from paper_1209_6038_amd import workloads as W
 from tests.gpu_helpers import say
+from tests.oracle_transit import oracle_exit_params
 
 pytestmark = pytest.mark.gpu
-
-
-def oracle_exit_params(cloak_d, opts, x6):
-    """Oracle transit of entries x6 (float32 (6, n), one (axis, branch) pair
-    per call): vacuum rays starting one unit outside the entry point, traced
-    to r = r2, converted to exit parameters (phi', z', alpha', beta', T)."""
-    b = cloak_d["r2"]
-    phi, z, al, be = (x6[k].astype(np.float64) for k in range(4))
-    cp, sp = np.cos(phi), np.sin(phi)
-    d = np.stack([np.cos(be) * (-np.cos(al) * cp - np.sin(al) * sp),
-                  np.cos(be) * (-np.cos(al) * sp + np.sin(al) * cp), np.sin(be)])
-    p = np.stack([b * cp, b * sp, z])
-    rays = np.concatenate([p - d, d])
-    o = oracle.trace(cloak_d, dict(opts, r_out=b), int(x6[4, 0]), rays)
-    out = o["out"]
-    ph = np.mod(np.arctan2(out[1], out[0]), 2 * math.pi)
-    rl = np.hypot(out[0], out[1])
-    vr = (out[0] * out[3] + out[1] * out[4]) / rl
-    vt = (out[0] * out[4] - out[1] * out[3]) / rl
-    y5 = np.stack([ph, out[2], np.arctan2(vt, vr), np.arcsin(np.clip(out[5], -1, 1)), o["opl"] - 1.0])
-    return y5, o["status"], o["hres"]
 
 
 def _angle_diff(a, b):
