@@ -1090,8 +1090,9 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
 
 // Surrogate render, after the gate: an accepted candidate's predicted exit
 // ray (on r = b, alpha' to the outward normal) takes its vacuum leg to the
-// room; a rejected one is generated again from its camera sample exactly as
-// k_rd_gen does and queued for the integrator in its segment.
+// room (its record: that point, or for an exit beyond a cap the cap point on
+// the same line); a rejected one is generated again from its camera sample
+// exactly as k_rd_gen does and queued for the integrator in its segment.
 __global__ void __launch_bounds__(256) k_rd_sur_apply(CloakP c, OptsP o, RoomP rm, const CamP *__restrict__ cams,
                                                       Table T, RenderP R, CandP Cd, unsigned int n) {
   const unsigned int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1108,17 +1109,27 @@ __global__ void __launch_bounds__(256) k_rd_sur_apply(CloakP c, OptsP o, RoomP r
     const double ca = cos(al), sa = sin(al);
     double p[3] = {c.b * cp, c.b * sp, ze};
     double dd[3] = {cb * (ca * cp - sa * sp), cb * (ca * sp + sa * cp), sin(be)};
+    // an exit beyond a cap (a chained cap model's prediction) left the
+    // crystal at its cap point, on the same line, where the vacuum leg to
+    // the room starts (the point on r = b can lie above the room)
+    double tb = 0.0;
+    if (ze > c.z1 || ze < c.z0) {
+      tb = (ze - (ze > c.z1 ? c.z1 : c.z0)) / dd[2];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) p[j] = fma(-tb, dd[j], p[j]);
+    }
     double sh0;
     const int code = room_code(rm, p, dd, sh0);
     // tile-edge gate: the accepted exit errs by at most edge_tol in
-    // position (units of r2) and direction (rad), which moves the room point
-    // along the face by at most edge_tol (r2 + distance) / cosine; a point
-    // closer than twice that to a tile edge could take the other colour, so
-    // the sample goes to the integrator
+    // position (units of r2) and direction (rad) on r = b, which moves the
+    // room point along the face by at most edge_tol (r2 + distance) /
+    // cosine, the distance counted from r = b (the vacuum leg back to a cap
+    // point included); a point closer than twice that to a tile edge could
+    // take the other colour, so the sample goes to the integrator
     double cosn = 1.0;
     const double dist = code < 12 ? tile_edge_distance(rm, p, dd, sh0, code >> 1, cosn) : 0.0;
-    if (!(dist * cosn > 2.0 * R.edge_tol * (c.b + sh0))) rej = true;
-    else rd_write(R, q, gidx, code, RT_RAY_EXITED, p, dd, (double)Cd.s_in[i] + Tt + sh0, 0);
+    if (!(dist * cosn > 2.0 * R.edge_tol * (c.b + tb + sh0))) rej = true;
+    else rd_write(R, q, gidx, code, RT_RAY_EXITED, p, dd, (double)Cd.s_in[i] + (Tt - tb) + sh0, 0);
   }
   double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, d[3] = {0, 0, 1}, s = 0.0;
   int kind = 0;

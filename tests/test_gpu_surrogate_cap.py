@@ -235,3 +235,66 @@ def test_cap_model_save_load_and_job_errors(cap_setup, tmp_path):
     m2.set_job(rt.SIDE)
     assert m2.job == rt.SIDE and m2.trust_map().shape == (4, 128, 128)
     m2.close()
+
+
+def _forward_to_r2(rec):
+    """Exit points (records (7, n): point, direction, ...) moved along their
+    direction to r = R2 where they lie inside it (cap points)."""
+    x, d = rec[:3], rec[3:6]
+    qa = d[0] ** 2 + d[1] ** 2
+    qb = x[0] * d[0] + x[1] * d[1]
+    qc = x[0] ** 2 + x[1] ** 2 - B * B
+    s = np.where(qc < -1e-9, (-qb + np.sqrt(np.maximum(qb * qb - qa * qc, 0.0))) / np.maximum(qa, 1e-30), 0.0)
+    return x + s * d
+
+
+def test_chained_render_matches_the_plain_render(cap_setup):
+    """rt_render_surrogate with the closed-form side model (calibrated as in
+    the side job's render tests) chained to the cap model: the same side
+    entries are offered, more of them are accepted than by the side model
+    alone (cap exits), accepted samples leave where the integrator's rays
+    leave (within TOL), the others are the plain render's bit for bit, and no
+    pixel differs from the plain render by more than 1/255 (tile-edge gate
+    with the chain's tolerance)."""
+    import torch
+    from paper_1209_6038_amd import rt
+    from tests.gpu_helpers import R2, angle_between
+    from tests.test_gpu_surrogate_render import closed_form_model
+    m = cap_setup[0]
+    side = closed_form_model()
+    cls = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
+    cams = [W.orbit_camera(0.3, 20.0, 96, 96, spp=4, seed=11), W.orbit_camera(2.5, 45.0, 96, 96, spp=4, seed=11),
+            W.orbit_camera(4.0, 60.0, 96, 96, spp=4, seed=11)]
+    opts = W.render_opts()
+    say("case chained render: 3 views 96 x 96 x 4 spp")
+    rgb_p, aux_p = rt.render_multi(cls, opts, W.room(), cams, 3, aux=True)
+    _, _, c_side = rt.render_surrogate(side, cls, opts, W.room(), cams, 3, aux=True, counts=True)
+    side.chain(m)
+    try:
+        rgb_s, aux_s, c_chain = rt.render_surrogate(side, cls, opts, W.room(), cams, 3, aux=True, counts=True)
+    finally:
+        side.chain(None)
+    torch.cuda.synchronize()
+    say(f"offered {c_side[0]}, accepted by the side model {c_side[1]}, chained {c_chain[1]}")
+    assert c_chain[0] == c_side[0] and c_chain[1] > c_side[1]
+    st_p, st_s = aux_p["status"], aux_s["status"]
+    acc = (st_s == 0) & (aux_s["nsteps"] == 0) & (aux_p["nsteps"] > 0)
+    assert int(acc.sum()) == c_chain[1]
+    same = ~acc
+    assert torch.equal(st_p[same], st_s[same]) and torch.equal(aux_p["code"][same], aux_s["code"][same])
+    assert torch.equal(torch.nan_to_num(aux_p["rec"].transpose(3, 4)[same]),
+                       torch.nan_to_num(aux_s["rec"].transpose(3, 4)[same]))
+    ok = acc & (st_p == 0)
+    assert int((acc & (st_p != 0)).sum()) <= max(1, int(1e-4 * c_chain[1]))
+    rp = aux_p["rec"].transpose(3, 4)[ok].cpu().numpy().T.astype(np.float64)
+    rs = aux_s["rec"].transpose(3, 4)[ok].cpu().numpy().T.astype(np.float64)
+    # both record where the ray left the crystal (a cap point for a cap
+    # exit); the calibration bounds the exit ray where it crosses r = r2
+    err = np.maximum(np.linalg.norm(_forward_to_r2(rs) - _forward_to_r2(rp), axis=0) / R2,
+                     angle_between(rs[3:6], rp[3:6]))
+    say(f"accepted exit error: p50 {np.median(err):.2e} max {err.max():.2e}")
+    assert err.max() <= TOL
+    d = (rgb_s - rgb_p).abs().amax(dim=-1)
+    say(f"max pixel difference {float(d.max()):.3e}")
+    assert float(d.max()) <= 1.0 / 255.0
+    side.close()
