@@ -91,8 +91,8 @@ ENTERED = (0, 2, 3, 4, 5)
 # scaled by the same counters on a plain device copy of known size
 # (bench.py --copy-probe), per workload. Valid only for the integrator source
 # it was measured on; reported as null otherwise.
-TRAFFIC = {"source_sha256": "3e7abe4cd643f0461a338ffbc0f325e3eac713306c36663ca1b059a8deeb8f11",
-           "bytes_per_launch": {"orbit": 22_100_462_547}}
+TRAFFIC = {"source_sha256": "41806cd201b023de5c106b2e825bd491bd7028e590822d1a5502b59ba762a132",
+           "bytes_per_launch": {"orbit": 21_960_563_378}}
 
 
 def traffic_for(workload):
