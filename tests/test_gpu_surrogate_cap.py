@@ -298,3 +298,39 @@ def test_chained_render_matches_the_plain_render(cap_setup):
     say(f"max pixel difference {float(d.max()):.3e}")
     assert float(d.max()) <= 1.0 / 255.0
     side.close()
+
+
+def test_chain_rules_and_freeing_a_chained_model():
+    """A chain holds two models: a model cannot follow itself, a chained
+    model cannot start or extend another chain, and freeing either model
+    unchains the other (its next calls work alone, with no reference to the
+    freed one)."""
+    import torch
+    from paper_1209_6038_amd import rt
+    from paper_1209_6038_amd import surrogate as S
+    a, b, c = rt.Surrogate(seed=1), rt.Surrogate(seed=2), rt.Surrogate(seed=3)
+    cl = S.make_cloaks(None)
+    x = S.features(4096, seed=9)
+    y, st = rt.transit_exact(cl, S.exact_opts(), x)
+    for m in (a, b, c):
+        m.calibrate(cl, x, y, st, tol=1e-30)
+    with pytest.raises(rt.RtError):
+        a.chain(a)
+    a.chain(b)
+    with pytest.raises(rt.RtError):
+        b.chain(c)  # b follows a: it cannot start a chain
+    with pytest.raises(rt.RtError):
+        c.chain(a)  # a leads a chain: it cannot follow
+    with pytest.raises(rt.RtError):
+        c.chain(b)  # b already follows a
+    y1, st1, fb1 = a.infer(cl, S.exact_opts(), x)
+    b.close()  # unchains a
+    y2, st2, fb2 = a.infer(cl, S.exact_opts(), x)
+    torch.cuda.synchronize()
+    assert bool((fb1 == 1).all()) and bool((fb2 == 1).all())
+    assert torch.equal(torch.nan_to_num(y1), torch.nan_to_num(y2)) and torch.equal(st1, st2)
+    a.chain(c)
+    a.close()  # unchains c, which can now lead a chain of its own
+    c.chain(rt.Surrogate(seed=4))
+    c.chain(None)
+    c.close()
