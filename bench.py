@@ -87,19 +87,38 @@ UNRESOLVED = 1e-6
 ENTERED = (0, 2, 3, 4, 5)
 
 # HBM traffic of one integrator launch from two rocprofv3 --pmc runs
-# (FETCH_SIZE, WRITE_SIZE) of `bench.py --workload <w> --profile-launches N`,
-# scaled by the same counters on a plain device copy of known size
-# (bench.py --copy-probe), per workload. Valid only for the integrator source
-# it was measured on; reported as null otherwise.
-TRAFFIC = {"source_sha256": "41806cd201b023de5c106b2e825bd491bd7028e590822d1a5502b59ba762a132",
-           "bytes_per_launch": {"orbit": 21_960_563_378}}
+# (FETCH_SIZE, WRITE_SIZE) of `bench.py --workload <w> --block B --refill R
+# --profile-launches N`, scaled by the same counters on a plain device copy of
+# known size (bench.py --copy-probe), per workload and launch shape (block,
+# refill period). Valid only for the integrator source it was measured on;
+# reported as null otherwise, or for a shape that was not measured.
+TRAFFIC = {"source_sha256": "26de92922eff0b53ebd9c8369696c5d476aff461363baef10462050dcf05b55d",
+           "bytes_per_launch": {
+               "orbit": {(64, 4): 21_807_399_654, (64, 8): 22_284_645_326, (64, 12): 22_352_131_291,
+                         (64, 16): 22_334_976_683, (128, 4): 22_085_481_439, (128, 8): 22_412_452_461,
+                         (128, 12): 22_488_136_569, (128, 16): 22_492_880_824, (256, 4): 22_216_580_207,
+                         (256, 8): 22_547_835_686, (256, 12): 22_658_142_431, (256, 16): 22_684_391_350},
+               "render_1024": {(64, 1): 755_922_255, (64, 2): 758_353_385, (64, 4): 762_684_613,
+                               (64, 8): 771_392_662, (64, 12): 772_537_392, (64, 16): 764_400_133,
+                               (128, 1): 758_306_500, (128, 2): 761_929_578, (128, 4): 766_535_048,
+                               (128, 8): 774_532_467, (128, 12): 778_403_382, (128, 16): 772_008_277,
+                               (256, 1): 770_978_009, (256, 2): 776_455_865, (256, 4): 782_310_354,
+                               (256, 8): 790_268_186, (256, 12): 792_796_686, (256, 16): 786_774_521},
+               "batched": {(64, 1): 3_485_168_937, (64, 2): 3_495_385_322, (64, 4): 3_502_225_383,
+                           (64, 8): 3_493_725_971, (64, 12): 3_489_913_246, (64, 16): 3_458_330_866,
+                           (128, 1): 3_506_725_636, (128, 2): 3_526_375_807, (128, 4): 3_532_065_392,
+                           (128, 8): 3_523_447_967, (128, 12): 3_512_456_185, (128, 16): 3_486_331_450,
+                           (256, 1): 3_542_281_163, (256, 2): 3_560_162_298, (256, 4): 3_560_978_112,
+                           (256, 8): 3_550_184_168, (256, 12): 3_540_013_629, (256, 16): 3_514_386_684}}}
 
 
-def traffic_for(workload):
-    """(bytes per integrator launch) or None."""
+def traffic_for(workload, shape=None):
+    """(bytes per integrator launch) of the workload at launch shape
+    (block, refill_period), or None where it was not measured."""
     if TRAFFIC["source_sha256"] != integrator_source_hash():
         return None
-    return TRAFFIC["bytes_per_launch"].get(workload)
+    v = TRAFFIC["bytes_per_launch"].get(workload)
+    return v.get(tuple(shape)) if isinstance(v, dict) and shape is not None else None
 
 
 def finite_json(obj):
@@ -832,7 +851,7 @@ def orbit_setup(args):
     fpl = args.frames_per_launch
     frames = W.orbit_frames(36, 4096, 4)[:args.frames]
     groups = [frames[i:i + fpl] for i in range(0, len(frames), fpl)]
-    opts = W.render_opts(max_chunk=fpl * 4096 * 4096 * 4)
+    opts = W.render_opts(max_chunk=fpl * 4096 * 4096 * 4, block=args.block, refill_period=args.refill)
     cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
     return frames, groups, opts, cloaks, W.room()
 
@@ -846,6 +865,15 @@ def orbit_headline(args, log):
     fpl = args.frames_per_launch
     dev = torch.device("cuda", 0)
     entered, flops = orbit_counts(cloaks, room, frames, log)
+    # launch shape (block size, refill period) from the autotuner on the first
+    # launch group, unless given; untimed
+    tuned_ms = None
+    if not (args.block or args.refill):
+        opts, tuned_ms = rt.autotune_render(cloaks, opts, room, groups[0], 3)
+        torch.cuda.synchronize()
+        log(f"orbit launch shape: block {opts['block']}, refill period {opts['refill_period']} "
+            f"({tuned_ms:.1f} ms per launch group)")
+    shape = (opts.get("block") or 256, opts.get("refill_period") or 2)
     # images per launch group, each a dense [cloak][frame][branch][h][w][3] block
     out = torch.empty((len(groups), 2, fpl, 2, 4096, 4096, 3), dtype=torch.float32, device=dev)
     # consecutive launch groups alternate between streams: the library keeps
@@ -897,9 +925,10 @@ def orbit_headline(args, log):
                    "rays_entering_cloak_per_step": entered, "miss_fraction": round(1.0 - entered / samples, 4),
                    "all_samples_per_s_M": round(samples / (ms * 1e-3) / 1e6, 1),
                    "ms_per_frame": round(ms / len(frames), 3), "parallelism": "single GPU",
-                   "streams": len(streams), "ms_per_step_one_stream": round(eager_ms, 3)},
+                   "streams": len(streams), "ms_per_step_one_stream": round(eager_ms, 3),
+                   "launch_shape": {"block": shape[0], "refill_period": shape[1], "autotuned_ms": tuned_ms}},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic_for("orbit"),
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic_for("orbit", shape),
                      "kernel": "k_transit (integrator)", "avg_launch_ms": round(avg_launch_ms, 3),
                      "launches_per_step": launches, "flops_per_launch": round(flops / max(launches, 1)),
                      "integrator_share_of_step": round(transit_ms / eager_ms, 4)},
@@ -1132,7 +1161,8 @@ def _plan_record(args, log, cams, name, desc, cpu_stride):
                       "rays_entering_cloak_per_step": entered, "images_equal_across_streams": images_equal},
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                        "traffic": traffic_for(name), "kernel": "k_transit (integrator)",
+                        "traffic": traffic_for(name, (opts.get("block"), opts.get("refill_period"))),
+                        "kernel": "k_transit (integrator)",
                         "avg_launch_ms": round(avg, 4)}}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(W.opts_dp45(), cams, cpu_stride)
@@ -1158,8 +1188,9 @@ def profile_launches(args):
     else:
         cams = W.render_views(res=1024) if args.workload == "render_1024" else W.batched_views(64, 512)
         cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
+        opts = W.render_opts(block=args.block, refill_period=args.refill)
         for _ in range(n + 1):
-            rt.render_multi(cloaks, W.render_opts(), W.room(), cams, 3)
+            rt.render_multi(cloaks, opts, W.room(), cams, 3)
     torch.cuda.synchronize()
     return {"profile_launches": n, "workload": args.workload}
 

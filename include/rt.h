@@ -304,7 +304,7 @@ int rt_render_plan_launch(rt_plan plan, void *stream);
 int rt_render_plan_destroy(rt_plan plan);
 
 /* Autotuner of the integrator's launch shape for a batch: times every block
-   size in {64, 128, 256} x refill period in {1, 2, 4, 8} on the batch itself
+   size in {64, 128, 256} x refill period in {1, 2, 4, 8, 12, 16} on the batch itself
    (one warm-up and two timed renders each, into `rgb`, which is overwritten),
    writes opts with the fastest shape into `tuned` and its time per render
    into `best_ms` (may be NULL), and remembers the choice for later calls of

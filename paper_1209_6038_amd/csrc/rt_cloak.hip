@@ -2440,7 +2440,7 @@ int rt_autotune_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_
   int e = prepare_render(cloaks, n_cloaks, opts, room, cams, n_cams, pol_mask, nullptr, J);
   if (e) return e;
   static const int blocks[] = {64, 128, 256};
-  static const int refills[] = {1, 2, 4, 8};
+  static const int refills[] = {1, 2, 4, 8, 12, 16};
   hipStream_t s = nullptr;
   hipEvent_t a = nullptr, b = nullptr;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&a) != hipSuccess ||
@@ -2454,7 +2454,7 @@ int rt_autotune_render(const rt_cloak *cloaks, int32_t n_cloaks, const rt_trace_
     if (!e) e = ws_reserve_for(g_ws, J);
     if (!e) e = upload_job(J, g_ws, s);
     for (int bi = 0; !e && bi < 3; ++bi)
-      for (int ri = 0; !e && ri < 4; ++ri) {
+      for (int ri = 0; !e && ri < 6; ++ri) {
         J.block = blocks[bi];
         J.refill = refills[ri];
         J.grid = transit_grid(J.o, J.block);

@@ -14,19 +14,24 @@ def test_finite_json_is_strict():
     json.loads(json.dumps(out, allow_nan=False))
 
 
-def test_traffic_is_keyed_by_source_and_workload(monkeypatch):
+def test_traffic_is_keyed_by_source_workload_and_shape(monkeypatch):
     """A figure is reported only for the integrator source its counters were
-    taken on, and only for its own workload."""
+    taken on, and only for its own workload and launch shape."""
     table = bench.TRAFFIC["bytes_per_launch"]
-    monkeypatch.setattr(bench, "TRAFFIC", {"source_sha256": "a" * 64, "bytes_per_launch": {"orbit": 123}})
+    monkeypatch.setattr(bench, "TRAFFIC", {"source_sha256": "a" * 64,
+                                           "bytes_per_launch": {"orbit": {(256, 8): 123}}})
     monkeypatch.setattr(bench, "integrator_source_hash", lambda: "a" * 64)
-    assert bench.traffic_for("orbit") == 123
-    assert bench.traffic_for("batched") is None
-    monkeypatch.setattr(bench, "integrator_source_hash", lambda: "b" * 64)
+    assert bench.traffic_for("orbit", (256, 8)) == 123
+    assert bench.traffic_for("orbit", [256, 8]) == 123
+    assert bench.traffic_for("orbit", (128, 8)) is None
     assert bench.traffic_for("orbit") is None
+    assert bench.traffic_for("batched", (256, 8)) is None
+    monkeypatch.setattr(bench, "integrator_source_hash", lambda: "b" * 64)
+    assert bench.traffic_for("orbit", (256, 8)) is None
     # the committed figures, if any, are per-launch byte counts of plausible size
-    for nbytes in table.values():
-        assert 1e6 < nbytes < 1e11
+    for per_shape in table.values():
+        for shape, nbytes in per_shape.items():
+            assert len(shape) == 2 and 1e6 < nbytes < 1e11
 
 
 def test_flop_counts():
