@@ -1107,11 +1107,15 @@ def _plan_record(args, log, cams, name, desc, cpu_stride):
     from paper_1209_6038_amd import workloads as W
     dev = torch.device("cuda", 0)
     res = int(cams[0]["w"])
-    opts = W.render_opts()
+    opts = W.render_opts(block=args.block, refill_period=args.refill)
     cloaks = [rt.Cloak(W.cloak(a, height=W.HEIGHT)) for a in (0, 1)]
     room = W.room()
     out = torch.empty((2, len(cams), 2, res, res, 3), dtype=torch.float32, device=dev)
-    opts, tuned_ms = rt.autotune_render(cloaks, opts, room, cams, 3)
+    # launch shape from the autotuner, unless given
+    tuned_ms = None
+    if not (args.block or args.refill):
+        opts, tuned_ms = rt.autotune_render(cloaks, opts, room, cams, 3)
+    opts["block"], opts["refill_period"] = opts.get("block") or 256, opts.get("refill_period") or 2
     nstreams = 3
     plans = [rt.RenderPlan(cloaks, opts, room, cams, 3) for _ in range(nstreams)]
     streams = [torch.cuda.Stream() for _ in range(nstreams)]
@@ -1207,7 +1211,7 @@ def main():
     ap.add_argument("--frames-per-launch", type=int, default=2,
                     help="4096^2 x 4 spp frames per integrator launch (1-4)")
     ap.add_argument("--workload", choices=("orbit", "render_1024", "batched", "inplane",
-                                           "hamiltonian", "weights", "unpolarized", "train"),
+                                           "hamiltonian", "weights", "unpolarized", "train", "surrogate"),
                     default="orbit")
     ap.add_argument("--res", type=int, default=1024)
     ap.add_argument("--refill", type=int, default=0)
@@ -1256,7 +1260,8 @@ def main():
         print(json.dumps(profile_launches(args)), flush=True)
         return
     single = {"inplane": inplane_workload, "hamiltonian": hamiltonian_workload, "weights": weights_workload,
-              "unpolarized": unpolarized_workload, "train": train_workload}
+              "unpolarized": unpolarized_workload, "train": train_workload,
+              "surrogate": lambda a: surrogate_leg(a.surrogate_steps, a.surrogate_train, log)}
     if args.workload in single:
         print(json.dumps(finite_json(single[args.workload](args))), flush=True)
         return
