@@ -82,7 +82,7 @@ def test_autotuner_choice_does_not_change_results():
     cls = _cloaks()
     tuned, ms = rt.autotune_render(cls, W.render_opts(), W.room(), cams, 3)
     say(f"autotuned block {tuned['block']} refill {tuned['refill_period']}: {ms:.3f} ms")
-    assert tuned["block"] in (64, 128, 256) and tuned["refill_period"] in (1, 2, 4, 8)
+    assert tuned["block"] in (64, 128, 256) and tuned["refill_period"] in (1, 2, 4, 8, 12, 16)
     assert ms > 0
     a = rt.render_multi(cls, W.render_opts(), W.room(), cams, 3)
     b = rt.render_multi(cls, tuned, W.room(), cams, 3)
