@@ -226,7 +226,8 @@ def test_render_in_small_chunks_equals_one_launch():
 def test_orbit_frames_full_size_sampled():
     """Two frames of the large-render workload at full size (4096^2 x 4
     jittered spp, both cloaks, both branches) in the launch configuration
-    the benchmark times (two frames per integrator launch): per image, 256
+    the benchmark times (two frames per integrator launch, the launch shape
+    from the autotuner on these frames): per image, 256
     random samples and 256 samples that enter the cloak re-traced by the
     oracle, compared sample by sample as the 1024^2 render is: equal
     statuses, exit rays within the 1e-6 bar (position / R2 and direction),
@@ -237,7 +238,8 @@ def test_orbit_frames_full_size_sampled():
     descs = [W.cloak(a, height=W.HEIGHT) for a in (0, 1)]
     cls = [rt.Cloak(d) for d in descs]
     say("case orbit frames 5-6: 4096^2 x 4 spp, 2 cloaks x 2 branches, one launch")
-    opts = W.render_opts(max_chunk=2 * 4096 * 4096 * 4)
+    opts, _ = rt.autotune_render(cls, W.render_opts(max_chunk=2 * 4096 * 4096 * 4), W.room(), frames, 3)
+    say(f"launch shape: block {opts['block']}, refill period {opts['refill_period']}")
     _, aux = rt.render_multi(cls, opts, W.room(), frames, 3, aux=("rec", "status", "code"))
     torch.cuda.synchronize()
     room = W.room()
