@@ -242,7 +242,7 @@ int rt_trace_batch(rt_cloak cloak, const rt_trace_opts *opts, int32_t pol, int64
    without any allocation. Same arguments, semantics, outputs and errors as
    rt_trace_batch, for at most RT_NOALLOC_MAX_RAYS rays per call (more:
    RT_E_INVALID). The work table lives in a fixed device array of the
-   library (~31.5 MB, held on each device the library runs on until the
+   library (~29.6 MB, held on each device the library runs on until the
    process ends) instead of the growing workspace; the call itself makes no
    hipMalloc, hipFree or other allocation and records no timing events. The
    array is shared by every call on a device and keeps the last call's

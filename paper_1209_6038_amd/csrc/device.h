@@ -44,9 +44,6 @@ struct OptsP {
 // branch kind = axis * 2 + pol
 enum { K_RO = 0, K_RE = 1, K_AO = 2, K_AE = 3 };
 
-// internal slot states (final states are the RT_RAY_* codes 0..7)
-enum { ST_ACTIVE = 100, ST_EVENT = 101 };
-
 // boundary ids
 enum { B_SIDE = 0, B_INNER = 1, B_TOP = 2, B_BOTTOM = 3 };
 

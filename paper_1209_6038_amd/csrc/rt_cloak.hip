@@ -52,9 +52,7 @@ enum {
   C_LINE = 32,
   C_NBASE = 0,               // C_N(s): slots used in segment s
   C_FBASE = NSEG * C_LINE,   // C_FETCH(s): integrator work counter of segment s
-  C_HBASE = 2 * NSEG * C_LINE,       // C_HIST(bin): slots per (segment, difficulty) key
-  C_OBASE = C_HBASE + 64 * C_LINE,   // C_OFF(bin): scatter offset of the key
-  C_SUR = C_OBASE + 64 * C_LINE,     // surrogate render: side entries offered to the network
+  C_SUR = 2 * NSEG * C_LINE,        // surrogate render: side entries offered to the network
   C_ACC = C_SUR + C_LINE,            // surrogate render: entries whose prediction was accepted
   C_COUNT = C_ACC + C_LINE
 };
@@ -63,22 +61,26 @@ constexpr long long REFL_CHUNK = 1LL << 22;  // samples per chunk with first-ord
 constexpr unsigned int FETCH_CHUNK = 64;  // rays claimed per wave per atomic
 constexpr int LONG_RAY_ATTEMPTS = 64;      // see the issue priority in k_transit
 constexpr int NBUCKET = 16;               // difficulty buckets
-constexpr int NBIN = NBUCKET * NSEG;
-static_assert(NBIN <= 64, "counter layout holds 64 bins");
+constexpr int NBIN = NBUCKET * NSEG;       // sort keys: (segment, difficulty bucket)
+// the counting sort runs a fixed grid; each block owns one contiguous range of
+// the queue, and the table keeps one count (then one offset) per (key, block)
+constexpr int SORT_BLOCKS = 1024;
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ITEMS = 8;              // keys per thread per tile
+static_assert(NBIN <= SORT_THREADS, "the scatter gives one thread to each key");
 __host__ __device__ constexpr int C_N(int s) { return C_NBASE + s * C_LINE; }
 __host__ __device__ constexpr int C_FETCH(int s) { return C_FBASE + s * C_LINE; }
-__host__ __device__ constexpr int C_HIST(int b) { return C_HBASE + b * C_LINE; }
-__host__ __device__ constexpr int C_OFF(int b) { return C_OBASE + b * C_LINE; }
 
 struct Table {
   double *px, *py, *pz, *vx, *vy, *vz;
-  double *t, *h, *opl0, *hres;
+  double *t, *opl0, *hres;  // t and hres, like nsteps, bounces and status, are written when the ray stops
   double *wt;  // Eq. (12) weight carried along the ray (rt_trace_batch with trans)
   int *nsteps, *bounces, *status, *kind;
   long long *key;
   int *order;   // integrator queue: slots sorted hardest first
   int *key0;    // sort key of each slot
   unsigned int *ctr;
+  unsigned int *bh;  // sort: NBIN x SORT_BLOCKS counts, key-major, then their offsets
   long long cap;  // capacity of one segment; segment s starts at s * cap
 };
 
@@ -190,17 +192,14 @@ __device__ __forceinline__ void store_state(const Table &T, int s, const double 
   T.vx[s] = v[0]; T.vy[s] = v[1]; T.vz[s] = v[2];
 }
 
+// a new slot: entry state, sort key, vacuum path so far, branch and output
+// index. The integrator starts every slot with t = 0, step h0, no steps and
+// no bounces, and writes the rest when the ray stops.
 __device__ __forceinline__ void put_slot(const Table &T, int s, const double x[3], const double v[3],
-                                         int kind, long long key, double opl0, double h0, int skey) {
+                                         int kind, long long key, double opl0, int skey) {
   store_state(T, s, x, v);
   T.key0[s] = skey;
-  T.t[s] = 0.0;
-  T.h[s] = h0;
   T.opl0[s] = opl0;
-  T.hres[s] = __builtin_nan("");
-  T.nsteps[s] = 0;
-  T.bounces[s] = 0;
-  T.status[s] = ST_ACTIVE;
   T.kind[s] = kind;
   T.key[s] = key;
 }
@@ -290,64 +289,160 @@ __global__ void __launch_bounds__(256) k_tb_entry(CloakP c, OptsP o, Table T, in
   __shared__ unsigned int sh[16];
   unsigned int sl = block_append(T.ctr + C_N(0), enter, sh);
   if (enter) {
-    put_slot(T, (int)sl, x, v, kind, i, s, o.h0, skey);
+    put_slot(T, (int)sl, x, v, kind, i, s, skey);
     if (trans) T.wt[sl] = w_in;
   }
 }
 
-// counting sort of the entered slots by key (LDS-privatized histogram,
-// single-wave scan, block-reserved scatter)
-__global__ void __launch_bounds__(256) k_sort_hist(Table T) {
+// Counting sort of the entered slots by key, stable in queue order. The
+// queue is cut into SORT_BLOCKS contiguous ranges, one per block of the
+// histogram and scatter passes (both launched with SORT_BLOCKS x
+// SORT_THREADS), so no pass needs a global atomic.
+
+// queue range [lo, hi) of sort block b
+__device__ __forceinline__ void sort_range(unsigned int n, unsigned int b, unsigned int &lo, unsigned int &hi) {
+  const unsigned int chunk = (n + SORT_BLOCKS - 1) / SORT_BLOCKS;
+  lo = min(n, b * chunk);
+  hi = min(n, lo + chunk);
+}
+
+// lanes of the wave whose key equals this lane's (0 where !active); every
+// lane of the wave must call it
+__device__ __forceinline__ unsigned long long same_key_lanes(int key, bool active) {
+  unsigned long long left = __ballot(active), mine = 0;
+  while (left) {
+    const int k = __shfl(key, __ffsll((long long)left) - 1);
+    const unsigned long long m = __ballot(active && key == k);
+    if (active && key == k) mine = m;
+    left &= ~m;
+  }
+  return mine;
+}
+
+// pass 1: the block's count of each key, into bh[key * SORT_BLOCKS + block]
+__global__ void __launch_bounds__(SORT_THREADS) k_sort_hist(Table T) {
   __shared__ unsigned int lh[NBIN];
   for (int i = threadIdx.x; i < NBIN; i += blockDim.x) lh[i] = 0;
   __syncthreads();
   const SegMap m = seg_map(T);
-  const unsigned int n = m.off[NSEG];
-  unsigned int stride = gridDim.x * blockDim.x;
-  for (unsigned int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
-    int seg;
-    int slot = slot_at(T, m, idx, seg);
-    atomicAdd(&lh[seg * NBUCKET + T.key0[slot]], 1u);
+  unsigned int lo, hi;
+  sort_range(m.off[NSEG], blockIdx.x, lo, hi);
+  for (unsigned int base = lo; base < hi; base += SORT_ITEMS * SORT_THREADS) {
+    int key[SORT_ITEMS];
+    bool active[SORT_ITEMS];
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j) {
+      const unsigned int idx = base + j * SORT_THREADS + threadIdx.x;
+      active[j] = idx < hi;
+      key[j] = 0;
+      if (active[j]) {
+        int seg;
+        const int slot = slot_at(T, m, idx, seg);
+        key[j] = seg * NBUCKET + T.key0[slot];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j) {
+      const unsigned long long same = same_key_lanes(key[j], active[j]);
+      if (active[j] && (same & lanemask_lt()) == 0) atomicAdd(&lh[key[j]], (unsigned int)__popcll(same));
+    }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < NBIN; i += blockDim.x)
-    if (lh[i]) atomicAdd(&T.ctr[C_HIST(i)], lh[i]);
+  for (int i = threadIdx.x; i < NBIN; i += blockDim.x) T.bh[i * SORT_BLOCKS + blockIdx.x] = lh[i];
 }
 
-__global__ void k_sort_scan(Table T) {
-  if (threadIdx.x == 0) {
+// pass 2: exclusive scan of bh in place by one block of SORT_THREADS threads,
+// each summing a run of E consecutive entries. A small block: it starts on a
+// CU that integrator waves of another stream still occupy, instead of waiting
+// for a whole CU to drain.
+__global__ void __launch_bounds__(SORT_THREADS) k_sort_scan(Table T) {
+  constexpr int E = NBIN * SORT_BLOCKS / SORT_THREADS, NW = SORT_THREADS / 64;
+  static_assert(E % 4 == 0, "runs are read as uint4");
+  __shared__ unsigned int ws[NW];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  uint4 *p = (uint4 *)(T.bh + t * E);  // the table is 256-byte aligned
+  unsigned int sum = 0;
+#pragma unroll 8
+  for (int i = 0; i < E / 4; ++i) { const uint4 c = p[i]; sum += c.x + c.y + c.z + c.w; }
+  // inclusive scan of the 64 lane sums, then across the waves
+  unsigned int inc = sum;
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned int u = __shfl_up(inc, d);
+    if (lane >= d) inc += u;
+  }
+  if (lane == 63) ws[w] = inc;
+  __syncthreads();
+  if (t == 0) {
     unsigned int acc = 0;
-    for (int i = 0; i < NBIN; ++i) {
-      T.ctr[C_OFF(i)] = acc;
-      acc += T.ctr[C_HIST(i)];
-    }
+    for (int k = 0; k < NW; ++k) { const unsigned int c = ws[k]; ws[k] = acc; acc += c; }
+  }
+  __syncthreads();
+  unsigned int acc = ws[w] + inc - sum;
+#pragma unroll 8
+  for (int i = 0; i < E / 4; ++i) {
+    const uint4 c = p[i];
+    uint4 o;
+    o.x = acc; acc += c.x;
+    o.y = acc; acc += c.y;
+    o.z = acc; acc += c.z;
+    o.w = acc; acc += c.w;
+    p[i] = o;
   }
 }
 
-__global__ void __launch_bounds__(256) k_sort_scatter(Table T) {
-  __shared__ unsigned int lc[NBIN], lb[NBIN];
+// pass 3: place the block's range tile by tile. The keys of one tile are
+// ranked among equal keys of their wave with ballots; a per-key scan over the
+// tile's (item, wave) groups, added to the block's running offset of the
+// key, orders the groups. Every slot lands after the slots of its key that
+// precede it in the queue.
+__global__ void __launch_bounds__(SORT_THREADS) k_sort_scatter(Table T) {
+  constexpr int NW = SORT_THREADS / 64, NG = SORT_ITEMS * NW;
+  __shared__ unsigned int run[NBIN];
+  __shared__ unsigned int gc[NG * NBIN];  // per (group, key): count, then offset
   const SegMap m = seg_map(T);
-  const unsigned int n = m.off[NSEG];
-  unsigned int stride = gridDim.x * blockDim.x;
-  unsigned int rounds = (n + stride - 1) / stride;
-  for (unsigned int r = 0; r < rounds; ++r) {
-    for (int i = threadIdx.x; i < NBIN; i += blockDim.x) lc[i] = 0;
-    __syncthreads();
-    unsigned int idx = r * stride + blockIdx.x * blockDim.x + threadIdx.x;
-    int slot = -1, key = 0;
-    unsigned int local = 0;
-    if (idx < n) {
-      int seg;
-      slot = slot_at(T, m, idx, seg);
-      key = seg * NBUCKET + T.key0[slot];
-      local = atomicAdd(&lc[key], 1u);
+  unsigned int lo, hi;
+  sort_range(m.off[NSEG], blockIdx.x, lo, hi);
+  for (int i = threadIdx.x; i < NBIN; i += blockDim.x) run[i] = T.bh[i * SORT_BLOCKS + blockIdx.x];
+  const int w = threadIdx.x >> 6;
+  const unsigned long long lt = lanemask_lt();
+  for (unsigned int base = lo; base < hi; base += SORT_ITEMS * SORT_THREADS) {
+    for (int i = threadIdx.x; i < NG * NBIN; i += blockDim.x) gc[i] = 0;
+    int key[SORT_ITEMS], slot[SORT_ITEMS];
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j) {
+      const unsigned int idx = base + j * SORT_THREADS + threadIdx.x;
+      slot[j] = -1;
+      key[j] = 0;
+      if (idx < hi) {
+        int seg;
+        slot[j] = slot_at(T, m, idx, seg);
+        key[j] = seg * NBUCKET + T.key0[slot[j]];
+      }
+    }
+    __syncthreads();  // gc cleared (and the previous tile's reads done)
+    unsigned int rank[SORT_ITEMS];
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j) {
+      const bool active = slot[j] >= 0;
+      const unsigned long long same = same_key_lanes(key[j], active);
+      rank[j] = (unsigned int)__popcll(same & lt);
+      if (active && rank[j] == 0) gc[(j * NW + w) * NBIN + key[j]] = (unsigned int)__popcll(same);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < NBIN; i += blockDim.x)
-      lb[i] = lc[i] ? atomicAdd(&T.ctr[C_OFF(i)], lc[i]) : 0u;
+    if (threadIdx.x < NBIN) {
+      unsigned int acc = run[threadIdx.x];
+      for (int g = 0; g < NG; ++g) {
+        const unsigned int c = gc[g * NBIN + threadIdx.x];
+        gc[g * NBIN + threadIdx.x] = acc;
+        acc += c;
+      }
+      run[threadIdx.x] = acc;
+    }
     __syncthreads();
-    if (slot >= 0) T.order[lb[key] + local] = slot;
-    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j)
+      if (slot[j] >= 0) T.order[gc[(j * NW + w) * NBIN + key[j]] + rank[j]] = slot[j];
+    __syncthreads();  // gc read before the next tile clears it
   }
 }
 
@@ -611,10 +706,10 @@ __device__ __forceinline__ void run_segment(const CloakP &c, const OptsP &o, con
       if (slot < 0 && idx < end) {
         slot = T.order[idx];
         load_state(T, slot, L.x, L.v);
-        L.t = T.t[slot];
-        L.h = T.h[slot];
-        L.ns = T.nsteps[slot];
-        L.bounces = T.bounces[slot];
+        L.t = 0.0;
+        L.h = o.h0;
+        L.ns = 0;
+        L.bounces = 0;
         L.after_reject = false;
         L.rid = -1;
         if constexpr (HAM) ham_convert<KIND>(c.a, c.kappa, L.x, L.v, true);  // v -> k
@@ -784,7 +879,7 @@ __global__ void __launch_bounds__(256) k_sx_entry(CloakP c, OptsP o, Table T, lo
   for (int q = 0; q < 4; ++q) {
     const bool want = entered && kind == q;
     unsigned int sl = block_append(T.ctr + C_N(q), want, sh);
-    if (want) put_slot(T, (int)(q * T.cap + sl), x, v, q, i, 0.0, o.h0, skey);
+    if (want) put_slot(T, (int)(q * T.cap + sl), x, v, q, i, 0.0, skey);
   }
 }
 
@@ -975,9 +1070,12 @@ __device__ __noinline__ double4 entry_weight(double kappa, double a, int kind, i
 // SUR: side entries become surrogate candidates instead of work-table slots.
 // WM: Eq. (12) weights at the entry, 0 none, 1 unpolarized, 2 with the
 // goggle ratio (separate instantiations: the entry solves are large, and a
-// render without weights should not carry their registers)
+// render without weights should not carry their registers). Without weights
+// the kernel is held to 128 VGPRs (4 waves per SIMD instead of 3, a few
+// registers spilled): its barriers and table stores then hide better, and
+// the orbit's camera-ray launches take 5.5 ms instead of 6.6 ms.
 template <bool SUR, int WM>
-__global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WM == 0 ? 4 : 1))) k_rd_gen(CloakP c, OptsP o, RoomP rm,
                                                 const CamP *__restrict__ cams, Table T, RenderP R, CandP Cd) {
   long long gidx = R.g0 + (long long)blockIdx.x * blockDim.x + threadIdx.x;
   bool valid = gidx < R.g1;
@@ -1079,7 +1177,7 @@ __global__ void __launch_bounds__(256) k_rd_gen(CloakP c, OptsP o, RoomP rm,
       }
     }
     unsigned int sl = block_append(T.ctr + C_N(q), enter, sh);
-    if (enter) put_slot(T, (int)(q * T.cap + sl), x, v, kind, gidx, s, o.h0, sort_key(c, kind, x, d));
+    if (enter) put_slot(T, (int)(q * T.cap + sl), x, v, kind, gidx, s, sort_key(c, kind, x, d));
     if (WM > 0 && enter) T.wt[q * T.cap + sl] = w_in;
     if constexpr (SUR) {
       const unsigned int ci2 = block_append(T.ctr + C_SUR, cand, sh);
@@ -1156,7 +1254,7 @@ __global__ void __launch_bounds__(256) k_rd_sur_apply(CloakP c, OptsP o, RoomP r
   for (int qq = 0; qq < R.ncl * R.npol; ++qq) {
     const bool put = enter && q == qq;
     const unsigned int sl = block_append(T.ctr + C_N(qq), put, sh);
-    if (put) put_slot(T, (int)(qq * T.cap + sl), x, v, kind, gidx, s, o.h0, sort_key(c, kind, x, d));
+    if (put) put_slot(T, (int)(qq * T.cap + sl), x, v, kind, gidx, s, sort_key(c, kind, x, d));
   }
   (void)block_append(T.ctr + C_ACC, valid && !rej, sh);
 }
@@ -1239,7 +1337,7 @@ __global__ void __launch_bounds__(256) k_rd_spawn(CloakP c, OptsP o, Table T, Ta
         const unsigned int cs = block_append(Tc.ctr + C_N(qq), p2, sh);
         if (p2) {
           const int slot = (int)(qq * Tc.cap + cs);
-          put_slot(Tc, slot, x, vc, kc, key, 0.0, o.h0, sort_key(c, kc, x, dm));
+          put_slot(Tc, slot, x, vc, kc, key, 0.0, sort_key(c, kc, x, dm));
           Tc.wt[slot] = wpre * Rr[bp];
         }
       }
@@ -1485,32 +1583,35 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // status, kind), the 64-bit sample keys, the queue and sort keys, then the
 // counters. table_bytes(cap) is its size.
 constexpr size_t table_bytes(long long cap) {
-  return ((sizeof(double) * 11 * NSEG * cap + 255) & ~(size_t)255) +
+  return ((sizeof(double) * 10 * NSEG * cap + 255) & ~(size_t)255) +
          ((sizeof(int) * 4 * NSEG * cap + 255) & ~(size_t)255) +
          ((sizeof(long long) * NSEG * cap + 255) & ~(size_t)255) +
          ((sizeof(int) * 2 * NSEG * cap + 255) & ~(size_t)255) +
-         ((sizeof(unsigned int) * C_COUNT + 255) & ~(size_t)255);
+         ((sizeof(unsigned int) * C_COUNT + 255) & ~(size_t)255) +
+         ((sizeof(unsigned int) * NBIN * SORT_BLOCKS + 255) & ~(size_t)255);
 }
 
 Table table_at(char *b, long long cap) {
   const long long ns = (long long)NSEG * cap;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
-  const size_t o_d = take(sizeof(double) * 11 * ns);
+  const size_t o_d = take(sizeof(double) * 10 * ns);
   const size_t o_i = take(sizeof(int) * 4 * ns);
   const size_t o_k = take(sizeof(long long) * ns);
   const size_t o_q = take(sizeof(int) * 2 * ns);
   const size_t o_c = take(sizeof(unsigned int) * C_COUNT);
+  const size_t o_b = take(sizeof(unsigned int) * NBIN * SORT_BLOCKS);
   Table T{};
   double *D = (double *)(b + o_d);
   T.px = D; T.py = D + ns; T.pz = D + 2 * ns; T.vx = D + 3 * ns; T.vy = D + 4 * ns; T.vz = D + 5 * ns;
-  T.t = D + 6 * ns; T.h = D + 7 * ns; T.opl0 = D + 8 * ns; T.hres = D + 9 * ns; T.wt = D + 10 * ns;
+  T.t = D + 6 * ns; T.opl0 = D + 7 * ns; T.hres = D + 8 * ns; T.wt = D + 9 * ns;
   int *I = (int *)(b + o_i);
   T.nsteps = I; T.bounces = I + ns; T.status = I + 2 * ns; T.kind = I + 3 * ns;
   T.key = (long long *)(b + o_k);
   T.order = (int *)(b + o_q);
   T.key0 = T.order + ns;
   T.ctr = (unsigned int *)(b + o_c);
+  T.bh = (unsigned int *)(b + o_b);
   T.cap = cap;
   return T;
 }
@@ -1670,9 +1771,9 @@ unsigned int transit_grid(const OptsP &o, int block, bool fres = false) {
 // first, then one persistent integrator launch (kernel launches only)
 void run_transit(const CloakP &c, const OptsP &o, const Table &T, int block, int refill,
                  unsigned int grid, hipStream_t s, bool profile, bool fres = false) {
-  hipLaunchKernelGGL(k_sort_hist, dim3(num_cu() * 4), dim3(256), 0, s, T);
-  hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(64), 0, s, T);
-  hipLaunchKernelGGL(k_sort_scatter, dim3(num_cu() * 4), dim3(256), 0, s, T);
+  hipLaunchKernelGGL(k_sort_hist, dim3(SORT_BLOCKS), dim3(SORT_THREADS), 0, s, T);
+  hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(SORT_THREADS), 0, s, T);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(SORT_BLOCKS), dim3(SORT_THREADS), 0, s, T);
   ProfEvent pe;
   bool on = false;
   if (profile) prof_begin(s, pe, on);
