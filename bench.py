@@ -92,24 +92,24 @@ ENTERED = (0, 2, 3, 4, 5)
 # known size (bench.py --copy-probe), per workload and launch shape (block,
 # refill period). Valid only for the integrator source it was measured on;
 # reported as null otherwise, or for a shape that was not measured.
-TRAFFIC = {"source_sha256": "26de92922eff0b53ebd9c8369696c5d476aff461363baef10462050dcf05b55d",
+TRAFFIC = {"source_sha256": "3923198717bc1ecf97bd2dca77c74055844315a3c1525353aa8f9ebf2534c6e0",
            "bytes_per_launch": {
-               "orbit": {(64, 4): 21_807_399_654, (64, 8): 22_284_645_326, (64, 12): 22_352_131_291,
-                         (64, 16): 22_334_976_683, (128, 4): 22_085_481_439, (128, 8): 22_412_452_461,
-                         (128, 12): 22_488_136_569, (128, 16): 22_492_880_824, (256, 4): 22_216_580_207,
-                         (256, 8): 22_547_835_686, (256, 12): 22_658_142_431, (256, 16): 22_684_391_350},
-               "render_1024": {(64, 1): 755_922_255, (64, 2): 758_353_385, (64, 4): 762_684_613,
-                               (64, 8): 771_392_662, (64, 12): 772_537_392, (64, 16): 764_400_133,
-                               (128, 1): 758_306_500, (128, 2): 761_929_578, (128, 4): 766_535_048,
-                               (128, 8): 774_532_467, (128, 12): 778_403_382, (128, 16): 772_008_277,
-                               (256, 1): 770_978_009, (256, 2): 776_455_865, (256, 4): 782_310_354,
-                               (256, 8): 790_268_186, (256, 12): 792_796_686, (256, 16): 786_774_521},
-               "batched": {(64, 1): 3_485_168_937, (64, 2): 3_495_385_322, (64, 4): 3_502_225_383,
-                           (64, 8): 3_493_725_971, (64, 12): 3_489_913_246, (64, 16): 3_458_330_866,
-                           (128, 1): 3_506_725_636, (128, 2): 3_526_375_807, (128, 4): 3_532_065_392,
-                           (128, 8): 3_523_447_967, (128, 12): 3_512_456_185, (128, 16): 3_486_331_450,
-                           (256, 1): 3_542_281_163, (256, 2): 3_560_162_298, (256, 4): 3_560_978_112,
-                           (256, 8): 3_550_184_168, (256, 12): 3_540_013_629, (256, 16): 3_514_386_684}}}
+               "orbit": {(64, 4): 16_349_745_696, (64, 8): 16_591_656_203, (64, 12): 16_717_345_408,
+                         (64, 16): 16_729_416_597, (128, 4): 16_474_282_891, (128, 8): 16_712_886_293,
+                         (128, 12): 16_824_902_944, (128, 16): 16_858_630_496, (256, 4): 16_515_145_963,
+                         (256, 8): 16_747_886_528, (256, 12): 16_861_369_568, (256, 16): 16_907_402_101},
+               "render_1024": {(64, 1): 576_186_232, (64, 2): 578_004_080, (64, 4): 580_807_824,
+                               (64, 8): 585_966_752, (64, 12): 589_518_056, (64, 16): 584_963_656,
+                               (128, 1): 576_963_560, (128, 2): 578_812_968, (128, 4): 581_950_304,
+                               (128, 8): 586_780_872, (128, 12): 590_212_496, (128, 16): 586_975_056,
+                               (256, 1): 581_403_552, (256, 2): 584_845_272, (256, 4): 588_742_960,
+                               (256, 8): 595_124_496, (256, 12): 598_794_840, (256, 16): 594_593_752},
+               "batched": {(64, 1): 2_581_217_952, (64, 2): 2_593_213_216, (64, 4): 2_607_467_104,
+                           (64, 8): 2_617_559_808, (64, 12): 2_620_236_336, (64, 16): 2_605_379_728,
+                           (128, 1): 2_586_021_160, (128, 2): 2_604_985_848, (128, 4): 2_618_550_168,
+                           (128, 8): 2_629_807_648, (128, 12): 2_630_624_792, (128, 16): 2_616_886_264,
+                           (256, 1): 2_598_221_368, (256, 2): 2_619_333_216, (256, 4): 2_640_786_704,
+                           (256, 8): 2_647_265_840, (256, 12): 2_646_335_144, (256, 16): 2_630_171_456}}}
 
 
 def traffic_for(workload, shape=None):
