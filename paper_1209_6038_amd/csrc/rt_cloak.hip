@@ -989,11 +989,15 @@ __device__ __forceinline__ void split_index(const RenderP &R, long long gidx, lo
 }
 
 // segment q = cloak * npol + polarization; images are laid out
-// [cloak][camera][polarization]
+// [cloak][camera][polarization]. OUT = false: the caller guarantees that no
+// optional output (weights, optical paths, per-sample records) is asked
+// for, and only the colour code is written.
+template <bool OUT = true>
 __device__ __forceinline__ void rd_write(const RenderP &R, int q, long long gidx, int code,
                                          int st, const double p[3], const double d[3], double L,
                                          int nsteps, float wt = 0.f) {
   R.codes[(long long)q * (R.g1 - R.g0) + (gidx - R.g0)] = (unsigned char)code;
+  if constexpr (!OUT) return;
   if (R.twt) R.twt[(long long)q * (R.g1 - R.g0) + (gidx - R.g0)] = wt;
   if (R.topl) R.topl[(long long)q * (R.g1 - R.g0) + (gidx - R.g0)] = code < 12 ? (float)L : __builtin_nanf("");
   long long cam, loc;
@@ -1071,10 +1075,12 @@ __device__ __noinline__ double4 entry_weight(double kappa, double a, int kind, i
 // WM: Eq. (12) weights at the entry, 0 none, 1 unpolarized, 2 with the
 // goggle ratio (separate instantiations: the entry solves are large, and a
 // render without weights should not carry their registers). Without weights
-// the kernel is held to 128 VGPRs (4 waves per SIMD instead of 3, a few
-// registers spilled): its barriers and table stores then hide better, and
-// the orbit's camera-ray launches take 5.5 ms instead of 6.6 ms.
-template <bool SUR, int WM>
+// the kernel is held to 128 VGPRs (4 waves per SIMD instead of 3): its
+// barriers and table stores then hide better. OUT: per-sample outputs
+// (records, optical paths) are asked for; without them and without weights
+// the kernel writes colour codes and work-table slots only, and holds fewer
+// uniform pointers.
+template <bool SUR, int WM, bool OUT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WM == 0 ? 4 : 1))) k_rd_gen(CloakP c, OptsP o, RoomP rm,
                                                 const CamP *__restrict__ cams, Table T, RenderP R, CandP Cd) {
   long long gidx = R.g0 + (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1127,7 +1133,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WM == 
     bool enter = false, cand = false;
     double v[3] = {0, 0, 0}, w_in = 0.0;
     const long long li = (long long)q * (R.g1 - R.g0) + (gidx - R.g0);  // chunk-local index
-    if (valid) {
+    int skey = 0;
+    // goggles and reflections need the Eq. (12) weights (WM > 0)
+    if (WM > 0 && valid) {
       // goggle ratio 1 and no reflected light unless the sample meets the
       // crystal (set below)
       if (R.grho) R.grho[li] = 1.0f;
@@ -1158,9 +1166,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WM == 
     }
     if (valid) {
       if (!hitc || disk) {
-        rd_write(R, q, gidx, vcode, vst, vp, vd, vL, 0, 0.5f);  // vacuum light splits evenly
+        rd_write<(OUT || WM > 0)>(R, q, gidx, vcode, vst, vp, vd, vL, 0, 0.5f);  // vacuum light splits evenly
       } else if (refract_in(c, kind, surf, x, d, v)) {
-        const int skey = sort_key(c, kind, x, d);
+        skey = sort_key(c, kind, x, d);
         if (SUR && surf == B_SIDE && NBUCKET - 1 - skey >= R.sur_min) cand = true;
         else enter = true;
         if (WM > 0) {
@@ -1173,11 +1181,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WM == 
         boundary_normal(surf, x, nrm);
         reflect3(dd, nrm);
         int code = room_code(rm, x, dd, sh);
-        rd_write(R, q, gidx, code, RT_RAY_REFLECTED, x, dd, s + sh, 0);
+        rd_write<(OUT || WM > 0)>(R, q, gidx, code, RT_RAY_REFLECTED, x, dd, s + sh, 0);
       }
     }
     unsigned int sl = block_append(T.ctr + C_N(q), enter, sh);
-    if (enter) put_slot(T, (int)(q * T.cap + sl), x, v, kind, gidx, s, sort_key(c, kind, x, d));
+    if (enter) put_slot(T, (int)(q * T.cap + sl), x, v, kind, gidx, s, skey);
     if (WM > 0 && enter) T.wt[q * T.cap + sl] = w_in;
     if constexpr (SUR) {
       const unsigned int ci2 = block_append(T.ctr + C_SUR, cand, sh);
@@ -1259,6 +1267,9 @@ __global__ void __launch_bounds__(256) k_rd_sur_apply(CloakP c, OptsP o, RoomP r
   (void)block_append(T.ctr + C_ACC, valid && !rej, sh);
 }
 
+// OUT: per-sample outputs are asked for (sample_outputs); without them a
+// ray's colour code needs only its status and, if it exited, its exit ray
+template <bool OUT>
 __global__ void __launch_bounds__(256) k_rd_finish(CloakP c, RoomP rm, Table T, RenderP R) {
   const SegMap m = seg_map(T);
   const unsigned int n = m.off[NSEG];
@@ -1266,6 +1277,16 @@ __global__ void __launch_bounds__(256) k_rd_finish(CloakP c, RoomP rm, Table T, 
   for (unsigned int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
     int q;
     int s = slot_at(T, m, idx, q);
+    if constexpr (!OUT) {
+      int code = 12;
+      if (T.status[s] == RT_RAY_EXITED) {
+        double x[3], v[3], sh;
+        load_state(T, s, x, v);
+        code = room_code(rm, x, v, sh);
+      }
+      rd_write<false>(R, q, T.key[s], code, 0, nullptr, nullptr, 0.0, 0);
+      continue;
+    }
     double x[3], v[3];
     load_state(T, s, x, v);
     int st = T.status[s];
@@ -2019,6 +2040,12 @@ int rws_reserve(ReflWs &w, long long chunk, long long len) {
   return RT_OK;
 }
 
+// any per-sample output of the camera-ray and finish kernels besides the
+// colour codes (selects the instantiations that write them)
+bool sample_outputs(const RenderP &R) {
+  return R.twt || R.topl || R.st || R.code || R.nsteps || R.rec;
+}
+
 void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStream_t s, bool profile,
                     const ReflWs *rw = nullptr) {
   const Table &T = ws.T;
@@ -2041,17 +2068,23 @@ void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStre
     R.g1 = std::min(J.total, g0 + J.chunk);
     hipLaunchKernelGGL(k_zero, dim3((C_COUNT + 255) / 256), dim3(256), 0, s, T.ctr, (int)C_COUNT);
     if (R.grho)
-      hipLaunchKernelGGL((k_rd_gen<false, 2>), dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
-                         ws.cams, T, R, CandP{});
-    else if (R.twt)
-      hipLaunchKernelGGL((k_rd_gen<false, 1>), dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
-                         ws.cams, T, R, CandP{});
+      hipLaunchKernelGGL((k_rd_gen<false, 2, true>), dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o,
+                         J.rm, ws.cams, T, R, CandP{});
+    else if (R.twt || R.refl)
+      hipLaunchKernelGGL((k_rd_gen<false, 1, true>), dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o,
+                         J.rm, ws.cams, T, R, CandP{});
+    else if (sample_outputs(R))
+      hipLaunchKernelGGL((k_rd_gen<false, 0, true>), dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o,
+                         J.rm, ws.cams, T, R, CandP{});
     else
-      hipLaunchKernelGGL((k_rd_gen<false, 0>), dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
-                         ws.cams, T, R, CandP{});
+      hipLaunchKernelGGL((k_rd_gen<false, 0, false>), dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o,
+                         J.rm, ws.cams, T, R, CandP{});
     if (J.n_cloaks) {
       run_transit(J.c, J.o, T, J.block, J.refill, J.grid, s, profile, R.twt != nullptr);
-      hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, J.c, J.rm, T, R);
+      if (sample_outputs(R))
+        hipLaunchKernelGGL(k_rd_finish<true>, dim3(num_cu() * 8), dim3(256), 0, s, J.c, J.rm, T, R);
+      else
+        hipLaunchKernelGGL(k_rd_finish<false>, dim3(num_cu() * 8), dim3(256), 0, s, J.c, J.rm, T, R);
       if (R.refl) {
         // the waves reflected at the exits, integrated as a second batch
         const Table &Tc = rw->Tc;
@@ -2131,8 +2164,12 @@ int render_surrogate(rt_model model, const rt_cloak_desc &desc, const RenderJob 
     R.g0 = g0;
     R.g1 = std::min(J.total, g0 + J.chunk);
     hipLaunchKernelGGL(k_zero, dim3((C_COUNT + 255) / 256), dim3(256), 0, s, T.ctr, (int)C_COUNT);
-    hipLaunchKernelGGL((k_rd_gen<true, 0>), dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o, J.rm,
-                       ws.cams, T, R, cw.P);
+    if (sample_outputs(R))
+      hipLaunchKernelGGL((k_rd_gen<true, 0, true>), dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o,
+                         J.rm, ws.cams, T, R, cw.P);
+    else
+      hipLaunchKernelGGL((k_rd_gen<true, 0, false>), dim3(grid_for(R.g1 - R.g0, 256)), dim3(256), 0, s, J.c, J.o,
+                         J.rm, ws.cams, T, R, cw.P);
     unsigned int nc = 0;
     if (hipMemcpyAsync(&nc, T.ctr + C_SUR, sizeof(nc), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -2145,7 +2182,10 @@ int render_surrogate(rt_model model, const rt_cloak_desc &desc, const RenderJob 
                          cw.P, nc);
     }
     run_transit(J.c, J.o, T, J.block, J.refill, J.grid, s, true);
-    hipLaunchKernelGGL(k_rd_finish, dim3(num_cu() * 8), dim3(256), 0, s, J.c, J.rm, T, R);
+    if (sample_outputs(R))
+      hipLaunchKernelGGL(k_rd_finish<true>, dim3(num_cu() * 8), dim3(256), 0, s, J.c, J.rm, T, R);
+    else
+      hipLaunchKernelGGL(k_rd_finish<false>, dim3(num_cu() * 8), dim3(256), 0, s, J.c, J.rm, T, R);
     long long nres = (R.g1 - R.g0) / R.spp * R.ncl * R.npol;
     hipLaunchKernelGGL(k_rd_resolve, dim3(grid_for(nres, 256)), dim3(256), 0, s, R, ws.table, rgb, J.npix);
     if (counts) {
