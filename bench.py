@@ -92,24 +92,24 @@ ENTERED = (0, 2, 3, 4, 5)
 # known size (bench.py --copy-probe), per workload and launch shape (block,
 # refill period). Valid only for the integrator source it was measured on;
 # reported as null otherwise, or for a shape that was not measured.
-TRAFFIC = {"source_sha256": "3923198717bc1ecf97bd2dca77c74055844315a3c1525353aa8f9ebf2534c6e0",
+TRAFFIC = {"source_sha256": "d6b342b372ee7eb1ee8a2fe99d5a43fdb9f023738e6ce182d6f6e6c4db9d0cbd",
            "bytes_per_launch": {
-               "orbit": {(64, 4): 16_349_745_696, (64, 8): 16_591_656_203, (64, 12): 16_717_345_408,
-                         (64, 16): 16_729_416_597, (128, 4): 16_474_282_891, (128, 8): 16_712_886_293,
-                         (128, 12): 16_824_902_944, (128, 16): 16_858_630_496, (256, 4): 16_515_145_963,
-                         (256, 8): 16_747_886_528, (256, 12): 16_861_369_568, (256, 16): 16_907_402_101},
-               "render_1024": {(64, 1): 576_186_232, (64, 2): 578_004_080, (64, 4): 580_807_824,
-                               (64, 8): 585_966_752, (64, 12): 589_518_056, (64, 16): 584_963_656,
-                               (128, 1): 576_963_560, (128, 2): 578_812_968, (128, 4): 581_950_304,
-                               (128, 8): 586_780_872, (128, 12): 590_212_496, (128, 16): 586_975_056,
-                               (256, 1): 581_403_552, (256, 2): 584_845_272, (256, 4): 588_742_960,
-                               (256, 8): 595_124_496, (256, 12): 598_794_840, (256, 16): 594_593_752},
-               "batched": {(64, 1): 2_581_217_952, (64, 2): 2_593_213_216, (64, 4): 2_607_467_104,
-                           (64, 8): 2_617_559_808, (64, 12): 2_620_236_336, (64, 16): 2_605_379_728,
-                           (128, 1): 2_586_021_160, (128, 2): 2_604_985_848, (128, 4): 2_618_550_168,
-                           (128, 8): 2_629_807_648, (128, 12): 2_630_624_792, (128, 16): 2_616_886_264,
-                           (256, 1): 2_598_221_368, (256, 2): 2_619_333_216, (256, 4): 2_640_786_704,
-                           (256, 8): 2_647_265_840, (256, 12): 2_646_335_144, (256, 16): 2_630_171_456}}}
+               "orbit": {(64, 4): 16_349_053_867, (64, 8): 16_594_036_693, (64, 12): 16_719_543_925,
+                         (64, 16): 16_731_669_611, (128, 4): 16_481_970_037, (128, 8): 16_717_948_949,
+                         (128, 12): 16_820_200_864, (128, 16): 16_864_336_832, (256, 4): 16_516_240_107,
+                         (256, 8): 16_749_765_696, (256, 12): 16_856_543_627, (256, 16): 16_909_143_765},
+               "render_1024": {(64, 1): 576_061_048, (64, 2): 577_933_984, (64, 4): 580_871_976,
+                               (64, 8): 586_283_704, (64, 12): 589_868_728, (64, 16): 584_778_736,
+                               (128, 1): 577_123_808, (128, 2): 579_013_008, (128, 4): 582_736_248,
+                               (128, 8): 588_080_688, (128, 12): 591_001_832, (128, 16): 588_068_400,
+                               (256, 1): 581_910_840, (256, 2): 584_831_152, (256, 4): 588_918_144,
+                               (256, 8): 595_861_144, (256, 12): 598_591_288, (256, 16): 595_080_232},
+               "batched": {(64, 1): 2_577_534_496, (64, 2): 2_590_757_304, (64, 4): 2_603_469_192,
+                           (64, 8): 2_614_178_192, (64, 12): 2_616_816_168, (64, 16): 2_603_781_592,
+                           (128, 1): 2_584_552_800, (128, 2): 2_601_029_552, (128, 4): 2_616_992_512,
+                           (128, 8): 2_626_535_080, (128, 12): 2_626_543_496, (128, 16): 2_613_480_944,
+                           (256, 1): 2_595_263_168, (256, 2): 2_617_165_744, (256, 4): 2_636_943_744,
+                           (256, 8): 2_644_768_912, (256, 12): 2_643_750_992, (256, 16): 2_628_188_416}}}
 
 
 def traffic_for(workload, shape=None):
