@@ -1392,6 +1392,103 @@ __global__ void __launch_bounds__(256) k_rd_cfinish(CloakP c, RoomP rm, Table Tc
 }
 
 // per-pixel mean colour; the 13-entry colour table is staged in LDS
+// (segment, pixel) entry i of a chunk -> segment q, chunk-local pixel lp,
+// camera and the float index of the pixel's RGB in the [cloak][camera]
+// [branch][pixel][3] images
+__device__ __forceinline__ long long resolve_index(const RenderP &R, long long npix, long long pix_in_chunk,
+                                                   long long i, int &q, long long &lp, long long &cam) {
+  if (R.idx32) {  // every index below fits 32 bits
+    const unsigned int i32 = (unsigned int)i, pc = (unsigned int)pix_in_chunk;
+    q = (int)(i32 / pc);
+    lp = i32 - (unsigned int)q * pc;
+  } else {
+    q = (int)(i / pix_in_chunk);
+    lp = i - q * pix_in_chunk;
+  }
+  const long long gpix = R.g0 / R.spp + lp;  // flattened (camera, pixel)
+  long long pix;
+  if (R.idx32) {
+    const unsigned int g32 = (unsigned int)gpix, np = (unsigned int)npix, c32 = g32 / np;
+    cam = c32;
+    pix = g32 - c32 * np;
+  } else {
+    cam = gpix / npix;
+    pix = gpix - cam * npix;
+  }
+  const int ci = q / R.npol, pi = q - ci * R.npol;
+  return ((((long long)ci * R.n_cams + cam) * R.npol + pi) * npix + pix) * 3;
+}
+
+// Pixel means of a render that asks for no other per-pixel image (no time of
+// flight, unpolarized or goggle image): tiles of 256 entries, in the order of
+// k_rd_resolve, taken by a fixed grid of blocks in turn. A tile whose entries
+// form one run of the output (one segment and camera, 16-byte aligned) is
+// staged in LDS and stored as 192 float4; any other tile stores each pixel's
+// three floats.
+__global__ void __launch_bounds__(256) k_rd_resolve_plain(RenderP R, const float *__restrict__ table39,
+                                                          float *__restrict__ rgb, long long npix) {
+  __shared__ float tab[39];
+  __shared__ float4 buf4[192];
+  __shared__ long long run0;
+  if (threadIdx.x < 39) tab[threadIdx.x] = table39[threadIdx.x];
+  const long long chunk = R.g1 - R.g0, pix_in_chunk = chunk / R.spp;
+  const long long total = pix_in_chunk * R.ncl * R.npol;
+  const long long ntiles = (total + 255) / 256;
+  const float inv = 1.0f / (float)R.spp;
+  for (long long t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const long long i0 = t * 256, i = i0 + threadIdx.x;
+    const bool valid = i < total;
+    if (threadIdx.x == 0) {
+      long long r = -1;
+      if (i0 + 255 < total) {
+        int qa, qb;
+        long long la, lb, ca, cb;
+        const long long oa = resolve_index(R, npix, pix_in_chunk, i0, qa, la, ca);
+        (void)resolve_index(R, npix, pix_in_chunk, i0 + 255, qb, lb, cb);
+        if (qa == qb && ca == cb && ((uintptr_t)(rgb + oa) & 15) == 0) r = oa;
+      }
+      run0 = r;
+    }
+    __syncthreads();  // tab (first tile) and run0 set; the previous tile's buf4 read
+    float c[3] = {0.f, 0.f, 0.f};
+    long long o = 0;
+    if (valid) {
+      int q;
+      long long lp, cam;
+      o = resolve_index(R, npix, pix_in_chunk, i, q, lp, cam);
+      const unsigned char *cd = R.codes + q * chunk + lp * R.spp;
+      if (R.spp == 4) {  // chunk and codes are 4-byte aligned
+        const unsigned int c4 = *(const unsigned int *)cd;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int cc = (c4 >> (8 * k)) & 0xff;
+          c[0] += tab[3 * cc]; c[1] += tab[3 * cc + 1]; c[2] += tab[3 * cc + 2];
+        }
+      } else {
+        for (int k = 0; k < R.spp; ++k) {
+          const int cc = cd[k];
+          c[0] += tab[3 * cc]; c[1] += tab[3 * cc + 1]; c[2] += tab[3 * cc + 2];
+        }
+      }
+      c[0] *= inv; c[1] *= inv; c[2] *= inv;
+    }
+    const long long base = run0;
+    if (base >= 0) {  // block-uniform
+      float *b = (float *)buf4;
+      b[3 * threadIdx.x] = c[0];
+      b[3 * threadIdx.x + 1] = c[1];
+      b[3 * threadIdx.x + 2] = c[2];
+      __syncthreads();
+      if (threadIdx.x < 192) ((float4 *)(rgb + base))[threadIdx.x] = buf4[threadIdx.x];
+    } else if (valid) {
+      rgb[o] = c[0];
+      rgb[o + 1] = c[1];
+      rgb[o + 2] = c[2];
+    }
+    __syncthreads();  // run0 and buf4 read before the next tile writes them
+  }
+}
+
 __global__ void __launch_bounds__(256) k_rd_resolve(RenderP R, const float *__restrict__ table39,
                                                     float *__restrict__ rgb, long long npix) {
   __shared__ float tab[39];
@@ -1600,9 +1697,10 @@ void prof_end(hipStream_t s, ProfEvent &pe, bool on) {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Work table of NSEG segments of `cap` slots at the start of a device
-// buffer: SoA doubles (x, v, t, h, opl0, hres, wt), ints (nsteps, bounces,
-// status, kind), the 64-bit sample keys, the queue and sort keys, then the
-// counters. table_bytes(cap) is its size.
+// buffer: SoA doubles (x, v, t, opl0, hres, wt), ints (nsteps, bounces,
+// status, kind), the 64-bit sample keys, the queue and sort keys, the
+// counters and the sort's per-(key, block) counts. table_bytes(cap) is its
+// size.
 constexpr size_t table_bytes(long long cap) {
   return ((sizeof(double) * 10 * NSEG * cap + 255) & ~(size_t)255) +
          ((sizeof(int) * 4 * NSEG * cap + 255) & ~(size_t)255) +
@@ -2046,6 +2144,18 @@ bool sample_outputs(const RenderP &R) {
   return R.twt || R.topl || R.st || R.code || R.nsteps || R.rec;
 }
 
+// fixed grid of the grid-stride plain resolve kernel: a few times the
+// blocks the chip holds at once, fewer when the chunk is small
+unsigned int resolve_grid(long long nres) {
+  return std::min(grid_for(nres, 256), (unsigned int)num_cu() * 16);
+}
+
+// any per-pixel image besides the colour image (time of flight,
+// unpolarized, goggles): the general resolve kernel makes them
+bool pixel_images(const RenderP &R) {
+  return R.tof || R.unpol || R.grho || R.gog[0] || R.gog[1];
+}
+
 void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStream_t s, bool profile,
                     const ReflWs *rw = nullptr) {
   const Table &T = ws.T;
@@ -2095,8 +2205,12 @@ void enqueue_render(const RenderJob &J, const Workspace &ws, float *rgb, hipStre
       }
     }
     long long nres = (R.g1 - R.g0) / R.spp * R.ncl * R.npol;
-    hipLaunchKernelGGL(k_rd_resolve, dim3(grid_for(nres, 256)), dim3(256), 0, s, R, ws.table, rgb,
-                       J.npix);
+    if (pixel_images(R))
+      hipLaunchKernelGGL(k_rd_resolve, dim3(grid_for(nres, 256)), dim3(256), 0, s, R, ws.table, rgb,
+                         J.npix);
+    else
+      hipLaunchKernelGGL(k_rd_resolve_plain, dim3(resolve_grid(nres)), dim3(256), 0, s, R, ws.table, rgb,
+                         J.npix);
   }
 }
 
@@ -2187,7 +2301,11 @@ int render_surrogate(rt_model model, const rt_cloak_desc &desc, const RenderJob 
     else
       hipLaunchKernelGGL(k_rd_finish<false>, dim3(num_cu() * 8), dim3(256), 0, s, J.c, J.rm, T, R);
     long long nres = (R.g1 - R.g0) / R.spp * R.ncl * R.npol;
-    hipLaunchKernelGGL(k_rd_resolve, dim3(grid_for(nres, 256)), dim3(256), 0, s, R, ws.table, rgb, J.npix);
+    if (pixel_images(R))
+      hipLaunchKernelGGL(k_rd_resolve, dim3(grid_for(nres, 256)), dim3(256), 0, s, R, ws.table, rgb, J.npix);
+    else
+      hipLaunchKernelGGL(k_rd_resolve_plain, dim3(resolve_grid(nres)), dim3(256), 0, s, R, ws.table, rgb,
+                         J.npix);
     if (counts) {
       unsigned int na = 0;
       if (hipMemcpyAsync(&na, T.ctr + C_ACC, sizeof(na), hipMemcpyDeviceToHost, s) != hipSuccess ||
