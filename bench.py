@@ -92,24 +92,24 @@ ENTERED = (0, 2, 3, 4, 5)
 # known size (bench.py --copy-probe), per workload and launch shape (block,
 # refill period). Valid only for the integrator source it was measured on;
 # reported as null otherwise, or for a shape that was not measured.
-TRAFFIC = {"source_sha256": "d6b342b372ee7eb1ee8a2fe99d5a43fdb9f023738e6ce182d6f6e6c4db9d0cbd",
+TRAFFIC = {"source_sha256": "a9a9495366d70c26cce4b56bb0ce7d971ef1e55ade0358be616ac5afc396e310",
            "bytes_per_launch": {
-               "orbit": {(64, 4): 16_349_053_867, (64, 8): 16_594_036_693, (64, 12): 16_719_543_925,
-                         (64, 16): 16_731_669_611, (128, 4): 16_481_970_037, (128, 8): 16_717_948_949,
-                         (128, 12): 16_820_200_864, (128, 16): 16_864_336_832, (256, 4): 16_516_240_107,
-                         (256, 8): 16_749_765_696, (256, 12): 16_856_543_627, (256, 16): 16_909_143_765},
-               "render_1024": {(64, 1): 576_061_048, (64, 2): 577_933_984, (64, 4): 580_871_976,
-                               (64, 8): 586_283_704, (64, 12): 589_868_728, (64, 16): 584_778_736,
-                               (128, 1): 577_123_808, (128, 2): 579_013_008, (128, 4): 582_736_248,
-                               (128, 8): 588_080_688, (128, 12): 591_001_832, (128, 16): 588_068_400,
-                               (256, 1): 581_910_840, (256, 2): 584_831_152, (256, 4): 588_918_144,
-                               (256, 8): 595_861_144, (256, 12): 598_591_288, (256, 16): 595_080_232},
-               "batched": {(64, 1): 2_577_534_496, (64, 2): 2_590_757_304, (64, 4): 2_603_469_192,
-                           (64, 8): 2_614_178_192, (64, 12): 2_616_816_168, (64, 16): 2_603_781_592,
-                           (128, 1): 2_584_552_800, (128, 2): 2_601_029_552, (128, 4): 2_616_992_512,
-                           (128, 8): 2_626_535_080, (128, 12): 2_626_543_496, (128, 16): 2_613_480_944,
-                           (256, 1): 2_595_263_168, (256, 2): 2_617_165_744, (256, 4): 2_636_943_744,
-                           (256, 8): 2_644_768_912, (256, 12): 2_643_750_992, (256, 16): 2_628_188_416}}}
+               "orbit": {(64, 4): 16_367_264_853, (64, 8): 16_602_244_747, (64, 12): 16_738_936_565,
+                         (64, 16): 16_740_058_976, (128, 4): 16_492_896_405, (128, 8): 16_727_920_267,
+                         (128, 12): 16_840_027_520, (128, 16): 16_883_521_525, (256, 4): 16_535_520_341,
+                         (256, 8): 16_765_989_120, (256, 12): 16_876_966_368, (256, 16): 16_928_693_867},
+               "render_1024": {(64, 1): 576_314_856, (64, 2): 578_478_216, (64, 4): 581_150_584,
+                               (64, 8): 585_980_760, (64, 12): 589_803_952, (64, 16): 585_261_208,
+                               (128, 1): 577_334_288, (128, 2): 579_538_424, (128, 4): 582_954_576,
+                               (128, 8): 587_826_800, (128, 12): 591_496_336, (128, 16): 588_082_776,
+                               (256, 1): 582_124_096, (256, 2): 585_049_584, (256, 4): 589_310_288,
+                               (256, 8): 595_968_472, (256, 12): 598_821_816, (256, 16): 594_912_168},
+               "batched": {(64, 1): 2_575_599_168, (64, 2): 2_588_529_816, (64, 4): 2_599_886_416,
+                           (64, 8): 2_611_125_984, (64, 12): 2_614_895_840, (64, 16): 2_602_135_272,
+                           (128, 1): 2_580_383_632, (128, 2): 2_599_642_352, (128, 4): 2_614_251_952,
+                           (128, 8): 2_624_741_968, (128, 12): 2_625_039_016, (128, 16): 2_610_439_112,
+                           (256, 1): 2_593_232_352, (256, 2): 2_614_858_856, (256, 4): 2_633_913_808,
+                           (256, 8): 2_642_026_480, (256, 12): 2_640_291_072, (256, 16): 2_626_358_272}}}
 
 
 def traffic_for(workload, shape=None):
